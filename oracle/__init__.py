@@ -1,0 +1,266 @@
+"""Python view of the plain FP64 CPU oracle (oracle/stencil_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark, never by the product package. It shares no
+code with the GPU path.
+
+Arrays are NumPy float64, C-contiguous, padded by r cells on every active axis
+(paper Eq. 2, Fig. 1) and indexed [z, y, x] in NumPy order so that x is the
+fastest axis (row-wise scan order, Sec. 4.4). ``n`` tuples are (nx, ny, nz).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MODEL_MHD8 = 0
+MODEL_ADVDIFF = 1
+# field order of the 8-field system (Table A1)
+LNRHO, UX, UY, UZ, SS, AX, AY, AZ = range(8)
+# derivative operator codes
+OP_X, OP_Y, OP_Z, OP_XX, OP_YY, OP_ZZ, OP_XY, OP_XZ, OP_YZ = range(9)
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_lp = ctypes.POINTER(ctypes.c_long)
+
+
+def lib():
+    """Load liboracle.so, building it with gcc first if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.oracle_fill_periodic.argtypes = [_dp, ctypes.c_int, _lp, ctypes.c_int]
+        L.oracle_xcorr.argtypes = [_dp, _dp, ctypes.c_int, _lp, ctypes.c_int, _dp]
+        L.oracle_xcorr_at.argtypes = [_dp, ctypes.c_int, _lp, ctypes.c_int, _dp, _lp,
+                                      ctypes.c_long, _dp]
+        L.oracle_fd_weights.argtypes = [_dp, _dp]
+        L.oracle_deriv.argtypes = [_dp, _dp, ctypes.c_int, _lp, _dp, ctypes.c_int]
+        L.oracle_deriv.restype = ctypes.c_int
+        L.oracle_rhs.argtypes = [ctypes.c_int, ctypes.POINTER(_dp), ctypes.POINTER(_dp),
+                                 ctypes.c_int, _lp, _dp, _dp]
+        L.oracle_rhs.restype = ctypes.c_int
+        L.oracle_rk3_coeffs.argtypes = [_dp, _dp]
+        L.oracle_rk3_substep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_dp),
+                                         ctypes.POINTER(_dp), ctypes.POINTER(_dp),
+                                         ctypes.c_int, _lp, _dp, _dp, ctypes.c_double]
+        L.oracle_rk3_substep.restype = ctypes.c_int
+        L.oracle_rk3_substep_at.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_dp),
+                                            _dp, ctypes.c_int, _lp, _dp, _dp,
+                                            ctypes.c_double, _lp, ctypes.c_long, _dp, _dp]
+        L.oracle_rk3_substep_at.restype = ctypes.c_int
+        L.oracle_reduce.argtypes = [_dp, ctypes.c_int, _lp, ctypes.c_int, _dp]
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+def _ptr(a):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "need C-contiguous float64"
+    return a.ctypes.data_as(_dp)
+
+
+def _dims(a, r):
+    """(ndim, n as ctypes long[3]) from a padded array."""
+    nd = a.ndim
+    n = [a.shape[nd - 1 - k] - 2 * r for k in range(nd)] + [1] * (3 - nd)
+    if min(n[:nd]) < 1:
+        raise ValueError("array smaller than its padding")
+    return nd, (ctypes.c_long * 3)(*n)
+
+
+def _ptrs(arrs):
+    if any(a.shape != arrs[0].shape for a in arrs):
+        raise ValueError("all fields must have the same padded shape")
+    return (_dp * len(arrs))(*[_ptr(a) for a in arrs])
+
+
+def _d3(v):
+    v = list(v) + [0.0] * (3 - len(v))
+    return (ctypes.c_double * 3)(*v)
+
+
+# --------------------------------------------------------------------------
+# padding psi (Eq. 2)
+# --------------------------------------------------------------------------
+
+def padded_shape(n, r):
+    """NumPy shape of a field with interior n = (nx[, ny[, nz]]) padded by r."""
+    return tuple(int(n[k]) + 2 * r for k in reversed(range(len(n))))
+
+
+def interior(a, r):
+    return a[tuple(slice(r, s - r) for s in a.shape)]
+
+
+def fill_periodic(a, r):
+    """Periodic boundary function: fill the halo of padded array a in place."""
+    nd, n = _dims(a, r)
+    lib().oracle_fill_periodic(_ptr(a), nd, n, r)
+    return a
+
+
+def pad_periodic(inner, r):
+    """New padded array whose interior is ``inner`` and halo is periodic."""
+    inner = np.asarray(inner, dtype=np.float64)
+    a = np.zeros(tuple(s + 2 * r for s in inner.shape))
+    interior(a, r)[...] = inner
+    return fill_periodic(a, r)
+
+
+# --------------------------------------------------------------------------
+# linear cross-correlation (Eq. 3, Eq. 6-7)
+# --------------------------------------------------------------------------
+
+def xcorr(a, r, g):
+    """Cross-correlation of padded a with the dense (2r+1)^ndim tensor g
+    (NumPy order [sz, sy, sx]). Returns a padded array, halo zero."""
+    nd, n = _dims(a, r)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    assert g.shape == (2 * r + 1,) * nd
+    out = np.zeros_like(a)
+    lib().oracle_xcorr(_ptr(a), _ptr(out), nd, n, r, _ptr(g))
+    return out
+
+
+def xcorr_periodic_iterate(a, r, g, iters):
+    """``iters`` chained applications with a periodic halo refresh before
+    each one; the input is not modified. Returns the padded result."""
+    cur = fill_periodic(a.copy(), r)
+    for _ in range(iters):
+        cur = fill_periodic(xcorr(cur, r, g), r)
+    return cur
+
+
+def xcorr_at(a, r, g, pts):
+    """Cross-correlation at interior points pts (array of (x, y, z) rows)."""
+    nd, n = _dims(a, r)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    assert g.shape == (2 * r + 1,) * nd
+    pts = np.ascontiguousarray(pts, dtype=np.int64).reshape(-1, 3)
+    nn = [n[0], n[1], n[2]]
+    if len(pts) and (pts.min() < 0 or any(pts[:, a].max() >= nn[a] for a in range(3))):
+        raise ValueError("point outside the interior")
+    out = np.zeros(len(pts))
+    lib().oracle_xcorr_at(_ptr(a), nd, n, r, _ptr(g), pts.ctypes.data_as(_lp), len(pts),
+                          _ptr(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# sixth-order derivatives, right-hand sides, RK3
+# --------------------------------------------------------------------------
+
+def fd_weights():
+    c1 = np.zeros(7)
+    c2 = np.zeros(7)
+    lib().oracle_fd_weights(_ptr(c1), _ptr(c2))
+    return c1, c2
+
+
+def rk3_coeffs():
+    a = np.zeros(3)
+    b = np.zeros(3)
+    lib().oracle_rk3_coeffs(_ptr(a), _ptr(b))
+    return a, b
+
+
+def deriv(f, ds, op):
+    """Apply derivative operator ``op`` to radius-3 padded field f."""
+    nd, n = _dims(f, 3)
+    out = np.zeros_like(f)
+    if lib().oracle_deriv(_ptr(f), _ptr(out), nd, n, _d3(ds), op) != 0:
+        raise ValueError("operator not defined in %d dimensions" % nd)
+    return out
+
+
+def _model_prm(model, nu, eta, cs2, c):
+    if model == MODEL_MHD8:
+        return (ctypes.c_double * 4)(nu, eta, cs2, 0.0)
+    c = list(c) + [0.0] * (3 - len(c))
+    return (ctypes.c_double * 4)(nu, *c)
+
+
+def rhs(model, fields, ds, nu=1e-3, eta=1e-3, cs2=1.0, c=(0.0, 0.0, 0.0)):
+    """Right-hand side R of the model over the interior; returns padded arrays
+    (halo zero), one per field."""
+    nd, n = _dims(fields[0], 3)
+    if len(fields) != (8 if model == MODEL_MHD8 else 1):
+        raise ValueError("wrong number of fields for the model")
+    R = [np.zeros_like(fields[0]) for _ in fields]
+    rc = lib().oracle_rhs(model, _ptrs(fields), _ptrs(R), nd, n, _d3(ds),
+                          _model_prm(model, nu, eta, cs2, c))
+    if rc != 0:
+        raise ValueError("bad model/dimension")
+    return R
+
+
+def rk3_substep(model, stage, fin, w, ds, dt, nu=1e-3, eta=1e-3, cs2=1.0,
+                c=(0.0, 0.0, 0.0)):
+    """One Williamson substep: updates the arrays in w in place and returns
+    new padded f arrays with a periodic halo."""
+    nd, n = _dims(fin[0], 3)
+    if len(fin) != len(w) or len(fin) != (8 if model == MODEL_MHD8 else 1):
+        raise ValueError("wrong number of fields for the model")
+    if any(a.shape != fin[0].shape for a in w):
+        raise ValueError("w must match the fields' padded shape")
+    fout = [np.zeros_like(a) for a in fin]
+    rc = lib().oracle_rk3_substep(model, stage, _ptrs(fin), _ptrs(w), _ptrs(fout), nd, n,
+                                  _d3(ds), _model_prm(model, nu, eta, cs2, c), dt)
+    if rc != 0:
+        raise ValueError("bad model/dimension/stage")
+    return fout
+
+
+def rk3_steps(model, f, ds, dt, steps, **kw):
+    """``steps`` full RK3 steps from padded f (halo refreshed first); returns
+    the final padded fields. The inputs are not modified."""
+    cur = [fill_periodic(a.copy(), 3) for a in f]
+    w = [np.zeros_like(a) for a in f]
+    for _ in range(steps):
+        for stage in range(3):
+            cur = rk3_substep(model, stage, cur, w, ds, dt, **kw)
+    return cur
+
+
+def rk3_substep_at(model, stage, fin, w_in, ds, dt, pts, nu=1e-3, eta=1e-3, cs2=1.0,
+                   c=(0.0, 0.0, 0.0)):
+    """Substep at listed interior points. w_in: (nf, count) old w (ignored at
+    stage 0). Returns (w_out, f_out), each (nf, count)."""
+    nd, n = _dims(fin[0], 3)
+    pts = np.ascontiguousarray(pts, dtype=np.int64).reshape(-1, 3)
+    nf = len(fin)
+    if nf != (8 if model == MODEL_MHD8 else 1):
+        raise ValueError("wrong number of fields for the model")
+    nn = [n[0], n[1], n[2]]
+    if len(pts) and (pts.min() < 0 or any(pts[:, a].max() >= nn[a] for a in range(3))):
+        raise ValueError("point outside the interior")
+    cnt = len(pts)
+    w_in = np.ascontiguousarray(np.zeros((nf, cnt)) if w_in is None else w_in,
+                                dtype=np.float64)
+    w_out = np.zeros((nf, cnt))
+    f_out = np.zeros((nf, cnt))
+    rc = lib().oracle_rk3_substep_at(model, stage, _ptrs(fin), _ptr(w_in), nd, n, _d3(ds),
+                                     _model_prm(model, nu, eta, cs2, c), dt,
+                                     pts.ctypes.data_as(_lp), cnt, _ptr(w_out), _ptr(f_out))
+    if rc != 0:
+        raise ValueError("bad model/dimension/stage")
+    return w_out, f_out
+
+
+def reduce(f, r):
+    """(sum, sum of squares, max |f|) over the interior, sequential FP64."""
+    nd, n = _dims(f, r)
+    out = np.zeros(3)
+    lib().oracle_reduce(_ptr(f), nd, n, r, _ptr(out))
+    return out
