@@ -1,0 +1,152 @@
+/*
+ * stencil.h -- C ABI of the MI355X (gfx950) stencil library, libstencil.so.
+ *
+ * Plain C types only: device pointers are void*, HIP streams are passed as
+ * void* (a hipStream_t, or NULL for the default stream). Every entry point
+ * returns a stencil_status; nothing throws or aborts across the ABI. On
+ * failure stencil_last_error() returns a thread-local message.
+ *
+ * Array layout (paper Sec. 2.4, Eq. 2 and Fig. 1; row-wise scan order of
+ * Sec. 4.4): a field with interior dims[0] x dims[1] x dims[2] (x fastest) is
+ * stored padded by r cells on both sides of every active axis. Axis a < ndim
+ * has extent dims[a] + 2r, unused axes have extent 1; the linear index of
+ * padded cell (x, y, z) is x + Px*(y + Py*z), and padded coordinate q holds
+ * interior point q - r. Buffers are caller-owned and must be aligned to their
+ * element size; stencil_padded_elems() gives the element count.
+ *
+ * Asynchrony: apply/step calls enqueue work on the given stream and return;
+ * errors detected at enqueue time are returned, device faults surface at the
+ * next synchronising call. Plans are immutable after creation and may be used
+ * from several host threads and streams at once (the caller keeps buffers in
+ * flight on different streams disjoint).
+ */
+#ifndef STENCIL_H
+#define STENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int stencil_status;
+#define STENCIL_OK 0
+#define STENCIL_EINVAL (-1)       /* bad descriptor, pointer, size or aliasing */
+#define STENCIL_ENOMEM (-2)       /* device or host allocation failed */
+#define STENCIL_EUNSUPPORTED (-3) /* valid request this build does not implement */
+#define STENCIL_EDEVICE (-4)      /* HIP runtime error (sticky for the plan) */
+#define STENCIL_EAGAIN (-5)       /* server queue full */
+#define STENCIL_ESTATE (-6)       /* call not valid in the object's state */
+#define STENCIL_ETIMEOUT (-7)     /* wait timed out */
+
+/* Storage types. Arithmetic is FP64 for F64 storage and FP32 for F32 and BF16
+ * storage (BF16 values are widened exactly and results rounded to nearest
+ * even). */
+typedef enum { STENCIL_F64 = 0, STENCIL_F32 = 1, STENCIL_BF16 = 2 } stencil_dtype;
+
+/* Boundary function beta of Eq. 2. PERIODIC: the library keeps halos periodic.
+ * USER_HALO: the caller fills the input halo; only the interior is written. */
+typedef enum { STENCIL_BC_PERIODIC = 0, STENCIL_BC_USER_HALO = 1 } stencil_bc;
+
+/* Kernel variants of the linear cross-correlation (STENCIL_VARIANT_AUTO lets
+ * the plan choose, with timing when STENCIL_FLAG_AUTOTUNE is set).
+ *  GENERIC : one lane per output, every tap read through the hardware caches
+ *            (any ndim, radius and tap pattern).
+ *  STAR3D  : 3-D axis-aligned stencils (radius 1..4): x-y plane tile staged in
+ *            LDS, z taps from a per-lane register window marching along z.
+ *  LINE1D  : 1-D stencils: block working set staged in LDS, several outputs
+ *            per lane. */
+#define STENCIL_VARIANT_AUTO (-1)
+#define STENCIL_VARIANT_GENERIC 0
+#define STENCIL_VARIANT_STAR3D 1
+#define STENCIL_VARIANT_LINE1D 2
+
+#define STENCIL_FLAG_AUTOTUNE 1u /* time the candidate variants at plan time */
+
+/* Linear stencil descriptor (Eq. 3 generalised by Eq. 6-7):
+ *   out_p = sum over s in [-r, r]^ndim of coeffs_s * in_{p+s}.
+ * coeffs: host pointer to the dense (2r+1)^ndim tensor, x fastest, copied by
+ * stencil_plan; zero taps are pruned. radius 0..8 (r = 0 is a copy).
+ * Periodic planes need dims[a] >= r on every active axis. */
+typedef struct stencil_desc {
+    int ndim;             /* 1, 2 or 3 */
+    int dims[3];          /* interior extents (unused axes ignored) */
+    int radius;
+    const double *coeffs; /* host, (2r+1)^ndim doubles */
+    int dtype;            /* stencil_dtype */
+    int bc;               /* stencil_bc */
+    unsigned flags;       /* STENCIL_FLAG_* */
+    int variant;          /* STENCIL_VARIANT_* */
+    /* launch overrides (all zero = the plan's choice), per variant:
+     *   STAR3D : {lanes along y, rows per lane (1, 2, 4 or 8), z planes per
+     *             workgroup, flags: bit 0 XCD-aware workgroup order, bit 1
+     *             separate halo pass instead of writing periodic images}
+     *   GENERIC: {block x, block y} (a multiple of 64 lanes, at most 1024)
+     *   LINE1D : {outputs per lane: 1, 2, 4 or 8} */
+    int tile[4];
+} stencil_desc;
+
+typedef struct stencil_plan_s *stencil_plan_t;
+
+/* Thread-local description of the last failure in this thread. */
+const char *stencil_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int stencil_version(void);
+
+/* Number of elements of a field with interior dims padded by r. */
+size_t stencil_padded_elems(int ndim, const int dims[3], int radius);
+
+/* Create a linear plan on the current HIP device. The plan owns a device copy
+ * of the pruned taps. With STENCIL_FLAG_AUTOTUNE the candidate variants are
+ * timed once on scratch buffers (synchronous) and the choice is cached per
+ * process for the same shape class. */
+stencil_status stencil_plan(const stencil_desc *desc, stencil_plan_t *out);
+
+/* Release a plan (waits for nothing: the caller must not destroy a plan with
+ * work in flight). NULL is accepted. */
+stencil_status stencil_plan_destroy(stencil_plan_t plan);
+
+/* Variant the plan will launch (after tuning), or a negative status. */
+int stencil_plan_variant(stencil_plan_t plan);
+
+/* iters chained applications on stream. d_a and d_b are caller-owned padded
+ * device buffers of the plan's dtype and may not overlap. Iteration k reads
+ * one and writes the other, starting d_a -> d_b, so the result is in d_b when
+ * iters is odd and in d_a when even (iters = 0 does nothing).
+ * PERIODIC: the halo of d_a is refreshed before the first iteration (d_a's
+ * halo cells are written) and every result carries a valid periodic halo.
+ * USER_HALO: iters must be 1; the caller's halo of d_a is read and only the
+ * interior of d_b is written. */
+stencil_status stencil_apply(stencil_plan_t plan, void *d_a, void *d_b, int iters,
+                             void *stream);
+
+/* stencil_apply with flags. STENCIL_APPLY_HALO_VALID: the caller guarantees
+ * d_a's periodic halo is already valid (e.g. it is the result of an earlier
+ * apply), so no refresh is launched and d_a is not written; each iteration is
+ * then exactly one kernel launch. Other bits must be zero. */
+#define STENCIL_APPLY_HALO_VALID 1u
+stencil_status stencil_apply_ex(stencil_plan_t plan, void *d_a, void *d_b, int iters,
+                                unsigned flags, void *stream);
+
+/* Refresh the periodic halo of one padded buffer laid out as in a plan of
+ * (ndim, dims, radius, dtype): every halo cell takes the value of the interior
+ * cell congruent to it modulo dims (Eq. 2 with a periodic beta). */
+stencil_status stencil_halo_periodic(int ndim, const int dims[3], int radius, int dtype,
+                                     void *d_buf, void *stream);
+
+/* Streaming copy of nbytes (multiple of 16, both pointers 16-byte aligned):
+ * the r = 0 case used to measure achievable HBM bandwidth (Sec. 5.2). */
+stencil_status stencil_copy(const void *d_src, void *d_dst, size_t nbytes, void *stream);
+
+/* Central finite-difference weights on offsets -r..r for the derivative of
+ * the given order (1 or 2), of accuracy order 2r, for unit spacing, computed
+ * by solving the moment conditions. out receives 2r+1 doubles. */
+stencil_status stencil_fd_weights(int order, int radius, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STENCIL_H */

@@ -1,0 +1,191 @@
+"""Python binding of libstencil.so (MI355X / gfx950 stencil library).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/stencil.h. PyTorch supplies the
+device memory (tensors) and streams; tensors are passed as raw pointers.
+
+The library is loaded lazily on first use, after ``import torch`` so that the
+process has a single HIP runtime. There is no fallback: if libstencil.so is
+missing or fails to load, the call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstencil.so")
+
+# storage types, boundary modes, variants (include/stencil.h)
+F64, F32, BF16 = 0, 1, 2
+PERIODIC, USER_HALO = 0, 1
+VARIANT_AUTO, GENERIC, STAR3D, LINE1D = -1, 0, 1, 2
+FLAG_AUTOTUNE = 1
+APPLY_HALO_VALID = 1
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSUPPORTED", -4: "EDEVICE",
+           -5: "EAGAIN", -6: "ESTATE", -7: "ETIMEOUT"}
+
+
+class StencilError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int * 3), ("radius", ctypes.c_int),
+                ("coeffs", ctypes.POINTER(ctypes.c_double)), ("dtype", ctypes.c_int),
+                ("bc", ctypes.c_int), ("flags", ctypes.c_uint), ("variant", ctypes.c_int),
+                ("tile", ctypes.c_int * 4)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """The loaded libstencil.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (one HIP runtime per process: torch's)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libstencil.so is not built: run __graft_entry__.build() "
+                               "or python paper_2406_08923_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _declare(L):
+    c_int, c_size = ctypes.c_int, ctypes.c_size_t
+    L.stencil_last_error.restype = ctypes.c_char_p
+    L.stencil_version.restype = c_int
+    L.stencil_padded_elems.argtypes = [c_int, ctypes.POINTER(c_int), c_int]
+    L.stencil_padded_elems.restype = c_size
+    L.stencil_plan.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_vp)]
+    L.stencil_plan_destroy.argtypes = [_vp]
+    L.stencil_plan_variant.argtypes = [_vp]
+    L.stencil_apply.argtypes = [_vp, _vp, _vp, c_int, _vp]
+    L.stencil_apply_ex.argtypes = [_vp, _vp, _vp, c_int, ctypes.c_uint, _vp]
+    L.stencil_halo_periodic.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, _vp, _vp]
+    L.stencil_copy.argtypes = [_vp, _vp, c_size, _vp]
+    L.stencil_fd_weights.argtypes = [c_int, c_int, ctypes.POINTER(ctypes.c_double)]
+
+
+def check(rc):
+    if rc != 0:
+        msg = lib().stencil_last_error()
+        raise StencilError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def stream_ptr(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _vp(s.cuda_stream)
+
+
+def ptr(t):
+    return _vp(t.data_ptr())
+
+
+def torch_dtype(dtype):
+    import torch
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[dtype]
+
+
+def _dims3(dims):
+    d = list(dims) + [1] * (3 - len(dims))
+    return (ctypes.c_int * 3)(*d)
+
+
+def padded_elems(dims, radius):
+    return int(lib().stencil_padded_elems(len(dims), _dims3(dims), radius))
+
+
+def padded_shape(dims, radius):
+    """Tensor shape [z, y, x] (slowest first) of a padded field."""
+    return tuple(int(dims[k]) + 2 * radius for k in reversed(range(len(dims))))
+
+
+def fd_weights(order, radius):
+    out = (ctypes.c_double * (2 * radius + 1))()
+    check(lib().stencil_fd_weights(order, radius, out))
+    return np.array(out[:])
+
+
+def halo_periodic(buf, dims, radius, dtype, stream=None):
+    check(lib().stencil_halo_periodic(len(dims), _dims3(dims), radius, dtype, ptr(buf),
+                                      stream_ptr(stream)))
+
+
+def copy(src, dst, nbytes=None, stream=None):
+    n = src.numel() * src.element_size() if nbytes is None else nbytes
+    check(lib().stencil_copy(ptr(src), ptr(dst), n, stream_ptr(stream)))
+
+
+class LinearPlan:
+    """Plan of a linear stencil (Eq. 3 / Eq. 6-7): ``coeffs`` is the dense
+    (2r+1)^ndim tensor in NumPy order [s_z, s_y, s_x] (x fastest)."""
+
+    def __init__(self, dims, radius, coeffs, dtype=F64, bc=PERIODIC, autotune=False,
+                 variant=VARIANT_AUTO, tile=None):
+        self.dims = tuple(int(v) for v in dims)
+        self.ndim = len(self.dims)
+        self.radius = int(radius)
+        self.dtype = dtype
+        c = np.ascontiguousarray(coeffs, dtype=np.float64).reshape(-1)
+        if c.size != (2 * radius + 1) ** self.ndim:
+            raise ValueError("coeffs must hold (2r+1)^ndim values")
+        self._coeffs = c
+        d = _Desc()
+        d.ndim = self.ndim
+        d.dims = _dims3(self.dims)
+        d.radius = self.radius
+        d.coeffs = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.dtype = dtype
+        d.bc = bc
+        d.flags = FLAG_AUTOTUNE if autotune else 0
+        d.variant = variant
+        d.tile = (ctypes.c_int * 4)(*(list(tile or []) + [0] * 4)[:4])
+        h = _vp()
+        check(lib().stencil_plan(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def variant(self):
+        v = lib().stencil_plan_variant(self._h)
+        return check(v) if v < 0 else v
+
+    def empty(self, fill=None):
+        """A padded device tensor of the plan's shape and dtype."""
+        import torch
+        t = torch.empty(padded_shape(self.dims, self.radius), dtype=torch_dtype(self.dtype),
+                        device="cuda")
+        if fill is not None:
+            t.fill_(fill)
+        return t
+
+    def apply(self, a, b, iters=1, stream=None, halo_valid=False):
+        """Chained application; the result is in b for odd iters, else in a.
+        halo_valid: a's periodic halo is already valid (no refresh launch)."""
+        n = padded_elems(self.dims, self.radius)
+        for t in (a, b):
+            if t.numel() != n or not t.is_contiguous() or t.dtype != torch_dtype(self.dtype):
+                raise ValueError("buffer must be a contiguous padded tensor of the plan dtype")
+        check(lib().stencil_apply_ex(self._h, ptr(a), ptr(b), int(iters),
+                                     APPLY_HALO_VALID if halo_valid else 0, stream_ptr(stream)))
+        return b if iters % 2 else a
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().stencil_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

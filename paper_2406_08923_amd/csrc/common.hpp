@@ -1,0 +1,160 @@
+// common.hpp -- internals shared by the translation units of libstencil.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/stencil.h"
+
+namespace stn {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+// Record a printf-style message as this thread's last error; returns code.
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define STN_HIP(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::stn::fail(STENCIL_EDEVICE, "%s failed: %s", #expr,                 \
+                               hipGetErrorString(e_));                                  \
+    } while (0)
+
+// Status of the launches just enqueued (hipGetLastError).
+int check_launch(const char *what);
+
+// ---------------------------------------------------------------------------
+// storage types
+// ---------------------------------------------------------------------------
+
+struct bf16 {
+    uint16_t bits;
+};
+
+// Storage type S with its arithmetic type C, a widening load and a rounding
+// store. BF16 is widened exactly (the 16 stored bits are the high half of the
+// FP32 pattern) and narrowed with round-to-nearest-even.
+template <typename S> struct Store;
+
+template <> struct Store<double> {
+    using C = double;
+    static __device__ __forceinline__ double ld(const double *p) { return *p; }
+    static __device__ __forceinline__ void st(double *p, double v) { *p = v; }
+};
+
+template <> struct Store<float> {
+    using C = float;
+    static __device__ __forceinline__ float ld(const float *p) { return *p; }
+    static __device__ __forceinline__ void st(float *p, float v) { *p = v; }
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b)
+{
+    return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float v)
+{
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) // NaN: keep sign, force a quiet NaN
+        return static_cast<uint16_t>(((u >> 16) & 0x8000u) | 0x7fc0u);
+    // round to nearest, ties to even: add 0x7fff plus the lsb of the kept half
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+template <> struct Store<bf16> {
+    using C = float;
+    static __device__ __forceinline__ float ld(const bf16 *p) { return bf16_to_f32(p->bits); }
+    static __device__ __forceinline__ void st(bf16 *p, float v) { p->bits = f32_to_bf16(v); }
+};
+
+inline size_t dtype_size(int dtype)
+{
+    return dtype == STENCIL_F64 ? 8 : dtype == STENCIL_F32 ? 4 : dtype == STENCIL_BF16 ? 2 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// padded geometry
+// ---------------------------------------------------------------------------
+
+// Interior extents n, radius r, padded strides. Unused axes have n = 1 and no
+// padding. Interior point (x, y, z) lives at padded cell (x+r, y+ry, z+rz).
+struct Geo {
+    int ndim;
+    int nx, ny, nz;
+    int r, ry, rz;
+    int64_t sy, sz; // element strides of y and z in the padded array
+
+    __host__ __device__ int64_t at(int x, int y, int z) const
+    {
+        return static_cast<int64_t>(x + r) + sy * (y + ry) + sz * (z + rz);
+    }
+};
+
+inline Geo make_geo(int ndim, const int *dims, int r)
+{
+    Geo g;
+    g.ndim = ndim;
+    g.nx = dims[0];
+    g.ny = ndim > 1 ? dims[1] : 1;
+    g.nz = ndim > 2 ? dims[2] : 1;
+    g.r = r;
+    g.ry = ndim > 1 ? r : 0;
+    g.rz = ndim > 2 ? r : 0;
+    g.sy = g.nx + 2 * r;
+    g.sz = g.sy * (g.ny + 2 * g.ry);
+    return g;
+}
+
+inline int64_t padded_elems(const Geo &g)
+{
+    return g.sz * (g.nz + 2 * g.rz);
+}
+
+// Store v at interior point (x, y, z) and, when fuse is set, at every periodic
+// image of the point that falls inside the halo, so the output's halo is valid
+// without a separate pass (Eq. 2 with a periodic beta). Images along an axis:
+// x + n when x < r, x - n when x >= n - r (both when n < 2r).
+template <typename S>
+__device__ __forceinline__ void store_periodic(S *out, const Geo &g, int x, int y, int z,
+                                               typename Store<S>::C v, bool fuse)
+{
+    Store<S>::st(out + g.at(x, y, z), v);
+    if (!fuse)
+        return;
+    const int r = g.r;
+    bool nx_ = x < r || x >= g.nx - r;
+    bool ny_ = g.ry && (y < r || y >= g.ny - r);
+    bool nz_ = g.rz && (z < r || z >= g.nz - r);
+    if (!(nx_ || ny_ || nz_))
+        return;
+    int xs[3], ys[3], zs[3];
+    int cx = 0, cy = 0, cz = 0;
+    xs[cx++] = x;
+    if (x < r) xs[cx++] = x + g.nx;
+    if (x >= g.nx - r) xs[cx++] = x - g.nx;
+    ys[cy++] = y;
+    if (g.ry) {
+        if (y < r) ys[cy++] = y + g.ny;
+        if (y >= g.ny - r) ys[cy++] = y - g.ny;
+    }
+    zs[cz++] = z;
+    if (g.rz) {
+        if (z < r) zs[cz++] = z + g.nz;
+        if (z >= g.nz - r) zs[cz++] = z - g.nz;
+    }
+    for (int iz = 0; iz < cz; ++iz)
+        for (int iy = 0; iy < cy; ++iy)
+            for (int ix = 0; ix < cx; ++ix)
+                if (ix | iy | iz)
+                    Store<S>::st(out + g.at(xs[ix], ys[iy], zs[iz]), v);
+}
+
+} // namespace stn

@@ -1,0 +1,579 @@
+// linear_api.hip -- C ABI of the linear path: plans, variant choice and
+// autotuning, chained application with periodic halos, finite-difference
+// weights, copy.
+#include "linear_kernels.hpp"
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace stn {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local char g_err[1024] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(STENCIL_EDEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+    return STENCIL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation helpers
+// ---------------------------------------------------------------------------
+
+int check_dims(int ndim, const int *dims, int r, int bc)
+{
+    if (ndim < 1 || ndim > 3)
+        return fail(STENCIL_EINVAL, "ndim must be 1, 2 or 3 (got %d)", ndim);
+    if (!dims)
+        return fail(STENCIL_EINVAL, "dims is NULL");
+    int64_t cells = 1;
+    for (int a = 0; a < ndim; ++a) {
+        if (dims[a] < 1)
+            return fail(STENCIL_EINVAL, "dims[%d] = %d must be >= 1", a, dims[a]);
+        if (bc == STENCIL_BC_PERIODIC && dims[a] < r)
+            return fail(STENCIL_EINVAL, "periodic padding needs dims[%d] = %d >= radius %d", a,
+                        dims[a], r);
+        cells *= (int64_t)dims[a] + 2 * r;
+    }
+    if (cells > (int64_t(1) << 40))
+        return fail(STENCIL_EINVAL, "padded array too large");
+    return STENCIL_OK;
+}
+
+int check_buffers(const void *a, const void *b, size_t bytes, size_t align)
+{
+    if (!a || !b)
+        return fail(STENCIL_EINVAL, "NULL device buffer");
+    auto ua = reinterpret_cast<uintptr_t>(a), ub = reinterpret_cast<uintptr_t>(b);
+    if (ua % align || ub % align)
+        return fail(STENCIL_EINVAL, "device buffer not aligned to %zu bytes", align);
+    if (ua < ub + bytes && ub < ua + bytes)
+        return fail(STENCIL_EINVAL, "input and output buffers overlap");
+    return STENCIL_OK;
+}
+
+int check_device(int plan_device)
+{
+    int dev = -1;
+    STN_HIP(hipGetDevice(&dev));
+    if (dev != plan_device)
+        return fail(STENCIL_EINVAL, "plan was created on device %d but device %d is current",
+                    plan_device, dev);
+    return STENCIL_OK;
+}
+
+} // namespace stn
+
+using namespace stn;
+
+// ---------------------------------------------------------------------------
+// plan internals
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct TuneChoice {
+    int variant, p0, p1, p2, p3;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune_cache;
+
+template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out, hipStream_t s)
+{
+    using C = typename Store<S>::C;
+    const bool periodic = p->lin.bc == STENCIL_BC_PERIODIC;
+    int rc;
+    switch (p->lin.variant) {
+    case STENCIL_VARIANT_STAR3D: {
+        int fl = p->lin.sflags | (periodic ? 0 : STAR_FLAG_NOFUSE);
+        rc = launch_star3d<S>(in, out, p->lin.g, p->lin.star, p->lin.reff, p->lin.ty,
+                              p->lin.ny, p->lin.lz, fl, s);
+        if (rc == STENCIL_OK && periodic && (p->lin.sflags & STAR_FLAG_NOFUSE))
+            rc = launch_halo<S>(out, p->lin.g, s);
+        return rc;
+    }
+    case STENCIL_VARIANT_LINE1D:
+        return launch_line1d<S>(in, out, p->lin.g, static_cast<const C *>(p->lin.d_dense),
+                                periodic, p->lin.e1d, s);
+    default:
+        return launch_generic<S>(in, out, p->lin.g, static_cast<const int *>(p->lin.d_offs),
+                                 static_cast<const C *>(p->lin.d_taps), p->lin.ntaps, periodic,
+                                 p->lin.gbx, p->lin.gby, s);
+    }
+}
+
+template <typename S>
+int apply_t(stencil_plan_s *p, void *da, void *db, int iters, hipStream_t s, bool halo_valid)
+{
+    S *a = static_cast<S *>(da), *b = static_cast<S *>(db);
+    int rc = STENCIL_OK;
+    if (p->lin.bc == STENCIL_BC_PERIODIC && !halo_valid)
+        rc = launch_halo<S>(a, p->lin.g, s);
+    for (int k = 0; k < iters && rc == STENCIL_OK; ++k) {
+        rc = run_linear_once<S>(p, a, b, s);
+        std::swap(a, b);
+    }
+    return rc;
+}
+
+int apply_any(stencil_plan_s *p, void *a, void *b, int iters, hipStream_t s,
+              bool halo_valid = false)
+{
+    switch (p->lin.dtype) {
+    case STENCIL_F64: return apply_t<double>(p, a, b, iters, s, halo_valid);
+    case STENCIL_F32: return apply_t<float>(p, a, b, iters, s, halo_valid);
+    default: return apply_t<bf16>(p, a, b, iters, s, halo_valid);
+    }
+}
+
+std::string tune_key(const stencil_plan_s *p)
+{
+    char buf[256];
+    snprintf(buf, sizeof(buf), "lin|dt%d|nd%d|%dx%dx%d|r%d|reff%d|star%d|bc%d|nt%d", p->lin.dtype,
+             p->lin.g.ndim, p->lin.g.nx, p->lin.g.ny, p->lin.g.nz, p->lin.g.r, p->lin.reff,
+             p->lin.is_star ? 1 : 0, p->lin.bc, p->lin.ntaps);
+    return buf;
+}
+
+void set_choice(stencil_plan_s *p, const TuneChoice &c)
+{
+    p->lin.variant = c.variant;
+    if (c.variant == STENCIL_VARIANT_STAR3D) {
+        p->lin.ty = c.p0;
+        p->lin.ny = c.p1;
+        p->lin.lz = c.p2;
+        p->lin.sflags = c.p3;
+    } else if (c.variant == STENCIL_VARIANT_LINE1D) {
+        p->lin.e1d = c.p0;
+    } else {
+        p->lin.gbx = c.p0;
+        p->lin.gby = c.p1;
+    }
+}
+
+std::vector<TuneChoice> candidates(const stencil_plan_s *p)
+{
+    std::vector<TuneChoice> c;
+    const Geo &g = p->lin.g;
+    if (p->lin.is_star) {
+        const int shapes[][2] = {{4, 1}, {4, 2}, {4, 4}, {8, 2}, {2, 4}, {8, 1}, {2, 8}};
+        const int lzs[] = {32, 64, 128, 256};
+        for (auto &sh : shapes)
+            for (int lz : lzs) {
+                if (lz > 2 * g.nz && lz != 32)
+                    continue;
+                c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, STAR_FLAG_XCD});
+                c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, 0});
+            }
+    }
+    if (g.ndim == 1)
+        for (int e : {1, 2, 4, 8})
+            c.push_back({STENCIL_VARIANT_LINE1D, e, 0, 0, 0});
+    if (g.ndim == 1) {
+        c.push_back({STENCIL_VARIANT_GENERIC, 256, 1, 0, 0});
+    } else {
+        c.push_back({STENCIL_VARIANT_GENERIC, 64, 4, 0, 0});
+        c.push_back({STENCIL_VARIANT_GENERIC, 64, 8, 0, 0});
+        c.push_back({STENCIL_VARIANT_GENERIC, 128, 2, 0, 0});
+    }
+    return c;
+}
+
+TuneChoice default_choice(const stencil_plan_s *p)
+{
+    if (p->lin.is_star)
+        return {STENCIL_VARIANT_STAR3D, 4, 4, 64, STAR_FLAG_XCD};
+    if (p->lin.g.ndim == 1)
+        return {STENCIL_VARIANT_LINE1D, 4, 0, 0, 0};
+    return {STENCIL_VARIANT_GENERIC, 64, 4, 0, 0};
+}
+
+// Time every candidate on scratch buffers (3 launches after one warm-up;
+// launches that fail are dropped, as in the paper's heuristic search of
+// Sec. 5.1) and keep the fastest.
+int autotune(stencil_plan_s *p)
+{
+    std::string key = tune_key(p);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            set_choice(p, it->second);
+            return STENCIL_OK;
+        }
+    }
+    const size_t bytes = (size_t)padded_elems(p->lin.g) * dtype_size(p->lin.dtype);
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        if (a) (void)hipFree(a);
+        return fail(STENCIL_ENOMEM, "autotune: cannot allocate 2 x %zu bytes of scratch", bytes);
+    }
+    STN_HIP(hipMemset(a, 0, bytes));
+    STN_HIP(hipMemset(b, 0, bytes));
+    hipEvent_t e0, e1;
+    STN_HIP(hipEventCreate(&e0));
+    STN_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    TuneChoice best_c = default_choice(p);
+    for (const TuneChoice &c : candidates(p)) {
+        set_choice(p, c);
+        if (apply_any(p, a, b, 1, nullptr) != STENCIL_OK) {
+            (void)hipGetLastError();
+            continue;
+        }
+        if (hipEventRecord(e0, nullptr) != hipSuccess) break;
+        int rc = apply_any(p, a, b, 3, nullptr);
+        if (hipEventRecord(e1, nullptr) != hipSuccess) break;
+        if (hipEventSynchronize(e1) != hipSuccess || rc != STENCIL_OK) {
+            (void)hipGetLastError();
+            continue;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    set_choice(p, best_c);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best_c;
+    return STENCIL_OK;
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *stencil_last_error(void) { return g_err; }
+
+int stencil_version(void) { return 10000; }
+
+size_t stencil_padded_elems(int ndim, const int dims[3], int radius)
+{
+    if (ndim < 1 || ndim > 3 || !dims || radius < 0)
+        return 0;
+    size_t n = 1;
+    for (int a = 0; a < ndim; ++a) {
+        if (dims[a] < 1)
+            return 0;
+        n *= (size_t)dims[a] + 2 * (size_t)radius;
+    }
+    return n;
+}
+
+stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
+{
+    if (!d || !out)
+        return fail(STENCIL_EINVAL, "NULL descriptor or output");
+    *out = nullptr;
+    if (d->radius < 0 || d->radius > 8)
+        return fail(STENCIL_EINVAL, "radius %d not in 0..8", d->radius);
+    if (d->dtype < STENCIL_F64 || d->dtype > STENCIL_BF16)
+        return fail(STENCIL_EINVAL, "unknown dtype %d", d->dtype);
+    if (d->bc != STENCIL_BC_PERIODIC && d->bc != STENCIL_BC_USER_HALO)
+        return fail(STENCIL_EINVAL, "unknown boundary mode %d", d->bc);
+    if (!d->coeffs)
+        return fail(STENCIL_EINVAL, "coeffs is NULL");
+    int rc = check_dims(d->ndim, d->dims, d->radius, d->bc);
+    if (rc) return rc;
+    if (d->variant < STENCIL_VARIANT_AUTO || d->variant > STENCIL_VARIANT_LINE1D)
+        return fail(STENCIL_EINVAL, "unknown variant %d", d->variant);
+    {
+        const size_t K = 2 * (size_t)d->radius + 1;
+        size_t nc = K;
+        for (int a = 1; a < d->ndim; ++a) nc *= K;
+        for (size_t i = 0; i < nc; ++i)
+            if (!std::isfinite(d->coeffs[i]))
+                return fail(STENCIL_EINVAL, "non-finite coefficient at index %zu", i);
+    }
+
+    auto *p = new (std::nothrow) stencil_plan_s();
+    if (!p)
+        return fail(STENCIL_ENOMEM, "out of host memory");
+    p->kind = PLAN_LINEAR;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return fail(STENCIL_EDEVICE, "no HIP device");
+    }
+    LinearPlan &L = p->lin;
+    const int r = d->radius, nd = d->ndim, K = 2 * r + 1;
+    L.dtype = d->dtype;
+    L.bc = d->bc;
+    L.g = make_geo(nd, d->dims, r);
+    const int Ky = nd > 1 ? K : 1, Kz = nd > 2 ? K : 1;
+    L.dense.assign(d->coeffs, d->coeffs + (size_t)K * Ky * Kz);
+
+    // prune zero taps (lexicographic s_z, s_y, s_x); classify the pattern
+    std::vector<int> offs;
+    std::vector<double> taps;
+    int reff = 0;
+    bool star = nd == 3;
+    for (int sz = -(Kz / 2); sz <= Kz / 2; ++sz)
+        for (int sy = -(Ky / 2); sy <= Ky / 2; ++sy)
+            for (int sx = -r; sx <= r; ++sx) {
+                double c = L.dense[(size_t)(sx + r) + (size_t)K * ((sy + Ky / 2) + (size_t)Ky * (sz + Kz / 2))];
+                if (c == 0.0)
+                    continue;
+                offs.push_back((int)(sx + L.g.sy * sy + L.g.sz * sz));
+                taps.push_back(c);
+                reff = std::max(reff, std::max(std::abs(sx), std::max(std::abs(sy), std::abs(sz))));
+                if ((sx != 0) + (sy != 0) + (sz != 0) > 1)
+                    star = false;
+            }
+    L.reff = reff;
+    L.ntaps = (int)taps.size();
+    L.is_star = star && reff >= 1 && reff <= STAR_MAX_R;
+    if (L.is_star) {
+        std::memset(&L.star, 0, sizeof(L.star));
+        for (int sz = -reff; sz <= reff; ++sz)
+            for (int sy = -reff; sy <= reff; ++sy)
+                for (int sx = -reff; sx <= reff; ++sx) {
+                    if ((sx != 0) + (sy != 0) + (sz != 0) > 1)
+                        continue;
+                    double c = L.dense[(size_t)(sx + r) + (size_t)K * ((sy + r) + (size_t)K * (sz + r))];
+                    if (!sx && !sy && !sz) L.star.c0 = c;
+                    else if (sx < 0) L.star.xm[-sx - 1] = c;
+                    else if (sx > 0) L.star.xp[sx - 1] = c;
+                    else if (sy < 0) L.star.ym[-sy - 1] = c;
+                    else if (sy > 0) L.star.yp[sy - 1] = c;
+                    else if (sz < 0) L.star.zm[-sz - 1] = c;
+                    else L.star.zp[sz - 1] = c;
+                }
+    }
+
+    // device copies of the taps in the arithmetic type
+    const bool f64 = L.dtype == STENCIL_F64;
+    const size_t csz = f64 ? 8 : 4;
+    std::vector<unsigned char> tbuf(std::max<size_t>(1, taps.size()) * csz);
+    std::vector<unsigned char> dbuf((size_t)K * csz);
+    for (size_t i = 0; i < taps.size(); ++i) {
+        if (f64) reinterpret_cast<double *>(tbuf.data())[i] = taps[i];
+        else reinterpret_cast<float *>(tbuf.data())[i] = (float)taps[i];
+    }
+    if (nd == 1)
+        for (int i = 0; i < K; ++i) {
+            if (f64) reinterpret_cast<double *>(dbuf.data())[i] = L.dense[i];
+            else reinterpret_cast<float *>(dbuf.data())[i] = (float)L.dense[i];
+        }
+    if (offs.empty()) offs.push_back(0);
+    if (hipMalloc(&L.d_offs, offs.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc(&L.d_taps, tbuf.size()) != hipSuccess ||
+        hipMalloc(&L.d_dense, dbuf.size()) != hipSuccess) {
+        (void)hipGetLastError();
+        stencil_plan_destroy(p);
+        return fail(STENCIL_ENOMEM, "cannot allocate plan coefficients on the device");
+    }
+    if (hipMemcpy(L.d_offs, offs.data(), offs.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L.d_taps, tbuf.data(), tbuf.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L.d_dense, dbuf.data(), dbuf.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        stencil_plan_destroy(p);
+        return fail(STENCIL_EDEVICE, "cannot upload plan coefficients");
+    }
+
+    // variant choice
+    if (d->variant == STENCIL_VARIANT_STAR3D && !L.is_star) {
+        stencil_plan_destroy(p);
+        return fail(STENCIL_EUNSUPPORTED, "STAR3D needs a 3-D axis-aligned stencil of radius 1..4");
+    }
+    if (d->variant == STENCIL_VARIANT_LINE1D && nd != 1) {
+        stencil_plan_destroy(p);
+        return fail(STENCIL_EUNSUPPORTED, "LINE1D needs ndim = 1");
+    }
+    TuneChoice c = default_choice(p);
+    if (d->variant != STENCIL_VARIANT_AUTO) {
+        c.variant = d->variant;
+        if (c.variant != default_choice(p).variant) {
+            if (c.variant == STENCIL_VARIANT_GENERIC) c = {c.variant, nd == 1 ? 256 : 64, nd == 1 ? 1 : 4, 0, 0};
+            else if (c.variant == STENCIL_VARIANT_LINE1D) c = {c.variant, 4, 0, 0, 0};
+        }
+        const int *t = d->tile;
+        if (c.variant == STENCIL_VARIANT_STAR3D && (t[0] || t[1] || t[2] || t[3])) {
+            if (t[0]) c.p0 = t[0];
+            if (t[1]) c.p1 = t[1];
+            if (t[2]) c.p2 = t[2];
+            c.p3 = t[3] & 3; // explicit tiles set the flag word exactly
+        } else if (c.variant == STENCIL_VARIANT_LINE1D) {
+            if (t[0]) c.p0 = t[0];
+        } else {
+            if (t[0]) c.p0 = t[0];
+            if (t[1]) c.p1 = t[1];
+            if (c.p0 < 1 || c.p1 < 1 || c.p0 * c.p1 > 1024 || (c.p0 * c.p1) % 64) {
+                stencil_plan_destroy(p);
+                return fail(STENCIL_EINVAL, "generic block %dx%d must be a multiple of 64 lanes <= 1024",
+                            c.p0, c.p1);
+            }
+        }
+        if (c.variant == STENCIL_VARIANT_STAR3D && c.p2 < 1) {
+            stencil_plan_destroy(p);
+            return fail(STENCIL_EINVAL, "star z chunk must be >= 1");
+        }
+        set_choice(p, c);
+    } else if (d->flags & STENCIL_FLAG_AUTOTUNE) {
+        rc = autotune(p);
+        if (rc) {
+            stencil_plan_destroy(p);
+            return rc;
+        }
+    } else {
+        set_choice(p, c);
+    }
+    *out = p;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_plan_destroy(stencil_plan_t p)
+{
+    if (!p)
+        return STENCIL_OK;
+    plan_release_device(p);
+    delete p;
+    return STENCIL_OK;
+}
+
+int stencil_plan_variant(stencil_plan_t p)
+{
+    if (!p || p->kind != PLAN_LINEAR)
+        return fail(STENCIL_EINVAL, "not a linear plan");
+    return p->lin.variant;
+}
+
+stencil_status stencil_apply(stencil_plan_t p, void *a, void *b, int iters, void *stream)
+{
+    return stencil_apply_ex(p, a, b, iters, 0u, stream);
+}
+
+stencil_status stencil_apply_ex(stencil_plan_t p, void *a, void *b, int iters, unsigned flags,
+                                void *stream)
+{
+    if (flags & ~STENCIL_APPLY_HALO_VALID)
+        return fail(STENCIL_EINVAL, "unknown apply flags 0x%x", flags);
+    if (!p || p->kind != PLAN_LINEAR)
+        return fail(STENCIL_EINVAL, "not a linear plan");
+    if (p->sticky)
+        return fail(p->sticky, "plan is in an error state from an earlier device failure");
+    if (iters < 0)
+        return fail(STENCIL_EINVAL, "iters must be >= 0");
+    if (p->lin.bc == STENCIL_BC_USER_HALO && iters > 1)
+        return fail(STENCIL_EINVAL, "USER_HALO plans apply one iteration at a time");
+    const size_t es = dtype_size(p->lin.dtype);
+    int rc = check_buffers(a, b, (size_t)padded_elems(p->lin.g) * es, es);
+    if (rc) return rc;
+    rc = check_device(p->device);
+    if (rc) return rc;
+    if (iters == 0)
+        return STENCIL_OK;
+    rc = apply_any(p, a, b, iters, static_cast<hipStream_t>(stream),
+                   (flags & STENCIL_APPLY_HALO_VALID) != 0);
+    if (rc == STENCIL_EDEVICE)
+        p->sticky = rc;
+    return rc;
+}
+
+stencil_status stencil_halo_periodic(int ndim, const int dims[3], int radius, int dtype,
+                                     void *buf, void *stream)
+{
+    int rc = check_dims(ndim, dims, radius, STENCIL_BC_PERIODIC);
+    if (rc) return rc;
+    if (radius < 0 || radius > 8)
+        return fail(STENCIL_EINVAL, "radius %d not in 0..8", radius);
+    const size_t es = dtype_size(dtype);
+    if (!es)
+        return fail(STENCIL_EINVAL, "unknown dtype %d", dtype);
+    if (!buf || reinterpret_cast<uintptr_t>(buf) % es)
+        return fail(STENCIL_EINVAL, "NULL or misaligned buffer");
+    Geo g = make_geo(ndim, dims, radius);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (dtype) {
+    case STENCIL_F64: return launch_halo<double>(static_cast<double *>(buf), g, s);
+    case STENCIL_F32: return launch_halo<float>(static_cast<float *>(buf), g, s);
+    default: return launch_halo<bf16>(static_cast<bf16 *>(buf), g, s);
+    }
+}
+
+stencil_status stencil_copy(const void *src, void *dst, size_t nbytes, void *stream)
+{
+    if (nbytes % 16)
+        return fail(STENCIL_EINVAL, "copy size must be a multiple of 16 bytes");
+    int rc = check_buffers(src, dst, nbytes, 16);
+    if (rc) return rc;
+    if (!nbytes) return STENCIL_OK;
+    return launch_copy(src, dst, nbytes, static_cast<hipStream_t>(stream));
+}
+
+// Fornberg's recurrence (Math. Comp. 51, 1988) for the weights of the
+// derivatives of order 0..m at 0 on the nodes -r..r; we keep order m.
+stencil_status stencil_fd_weights(int order, int radius, double *out)
+{
+    if (!out || radius < 1 || radius > 8 || order < 1 || order > 2 || order > 2 * radius)
+        return fail(STENCIL_EINVAL, "need order 1 or 2, radius 1..8, non-NULL out");
+    const int n = 2 * radius + 1, m = order;
+    std::vector<long double> x(n);
+    for (int i = 0; i < n; ++i) x[i] = i - radius;
+    // w[j][k]: weight of node j for derivative k
+    std::vector<std::vector<long double>> w(n, std::vector<long double>(m + 1, 0.0L));
+    long double c1 = 1.0L, c4 = x[0];
+    w[0][0] = 1.0L;
+    for (int i = 1; i < n; ++i) {
+        int mn = std::min(i, m);
+        long double c2 = 1.0L, c5 = c4;
+        c4 = x[i];
+        for (int j = 0; j < i; ++j) {
+            long double c3 = x[i] - x[j];
+            c2 *= c3;
+            if (j == i - 1) {
+                for (int k = mn; k >= 1; --k)
+                    w[i][k] = c1 * (k * w[i - 1][k - 1] - c5 * w[i - 1][k]) / c2;
+                w[i][0] = -c1 * c5 * w[i - 1][0] / c2;
+            }
+            for (int k = mn; k >= 1; --k)
+                w[j][k] = (c4 * w[j][k] - k * w[j][k - 1]) / c3;
+            w[j][0] = c4 * w[j][0] / c3;
+        }
+        c1 = c2;
+    }
+    // centred nodes: odd orders are exactly antisymmetric, even orders
+    // symmetric; average the two halves so rounding cannot break that
+    const long double sgn = (m % 2) ? -1.0L : 1.0L;
+    for (int i = 0; i < radius; ++i) {
+        long double v = 0.5L * (w[n - 1 - i][m] + sgn * w[i][m]);
+        out[n - 1 - i] = (double)v;
+        out[i] = (double)(sgn * v);
+    }
+    out[radius] = (m % 2) ? 0.0 : (double)w[radius][m];
+    return STENCIL_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,60 @@
+// linear_kernels.hpp -- launchers of the linear-path kernels (internal).
+#pragma once
+
+#include "common.hpp"
+
+namespace stn {
+
+// Axis-aligned (star) coefficients of radius R: centre, and per axis the taps
+// at -m (xm[m-1]) and +m (xp[m-1]), m = 1..R. Passed by value as kernel
+// arguments, so they sit in scalar registers.
+template <typename C, int R> struct StarCoef {
+    C c0;
+    C xm[R], xp[R], ym[R], yp[R], zm[R], zp[R];
+};
+
+constexpr int STAR_MAX_R = 4;
+
+struct StarCoefAny {
+    double c0;
+    double xm[STAR_MAX_R], xp[STAR_MAX_R], ym[STAR_MAX_R], yp[STAR_MAX_R];
+    double zm[STAR_MAX_R], zp[STAR_MAX_R];
+
+    template <typename C, int R> StarCoef<C, R> get() const
+    {
+        StarCoef<C, R> o;
+        o.c0 = static_cast<C>(c0);
+        for (int m = 0; m < R; ++m) {
+            o.xm[m] = static_cast<C>(xm[m]);
+            o.xp[m] = static_cast<C>(xp[m]);
+            o.ym[m] = static_cast<C>(ym[m]);
+            o.yp[m] = static_cast<C>(yp[m]);
+            o.zm[m] = static_cast<C>(zm[m]);
+            o.zp[m] = static_cast<C>(zp[m]);
+        }
+        return o;
+    }
+};
+
+// star kernel flags
+constexpr int STAR_FLAG_XCD = 1;    // XCD-aware workgroup order
+constexpr int STAR_FLAG_NOFUSE = 2; // do not write periodic images
+
+template <typename S> int launch_halo(S *a, const Geo &g, hipStream_t s);
+
+template <typename S>
+int launch_generic(const S *in, S *out, const Geo &g, const int *offs,
+                   const typename Store<S>::C *cs, int ntaps, bool fuse, int bx, int by,
+                   hipStream_t s);
+
+template <typename S>
+int launch_star3d(const S *in, S *out, const Geo &g, const StarCoefAny &cf, int R, int ty,
+                  int ny, int lz, int flags, hipStream_t s);
+
+template <typename S>
+int launch_line1d(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs, bool fuse,
+                  int e, hipStream_t s);
+
+int launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t s);
+
+} // namespace stn

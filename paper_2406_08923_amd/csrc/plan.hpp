@@ -1,0 +1,51 @@
+// plan.hpp -- the opaque plan object behind stencil_plan_t (internal).
+#pragma once
+
+#include "linear_kernels.hpp"
+
+#include <vector>
+
+namespace stn {
+
+enum PlanKind { PLAN_LINEAR = 1, PLAN_RK = 2 };
+
+struct LinearPlan {
+    int dtype = 0, bc = 0;
+    Geo g{};
+    std::vector<double> dense; // (2r+1)^ndim coefficients, x fastest
+    int ntaps = 0, reff = 0;   // pruned taps and their radius
+    bool is_star = false;
+    StarCoefAny star{};
+    void *d_offs = nullptr;  // int32 tap offsets in the padded array
+    void *d_taps = nullptr;  // tap coefficients, arithmetic type
+    void *d_dense = nullptr; // 1-D dense coefficients, arithmetic type
+    // chosen variant and its launch parameters
+    int variant = STENCIL_VARIANT_GENERIC;
+    int ty = 4, ny = 4, lz = 64, sflags = 0; // STAR3D
+    int gbx = 64, gby = 4;                   // GENERIC
+    int e1d = 4;                             // LINE1D
+};
+
+// validation helpers shared by the C-ABI translation units
+int check_dims(int ndim, const int *dims, int r, int bc);
+int check_buffers(const void *a, const void *b, size_t bytes, size_t align);
+int check_device(int plan_device);
+
+} // namespace stn
+
+struct stencil_plan_s {
+    int kind = 0;
+    int device = 0;
+    int sticky = 0; // device error latched by an earlier call
+    stn::LinearPlan lin;
+};
+
+namespace stn {
+inline void plan_release_device(stencil_plan_s *p)
+{
+    void *bufs[] = {p->lin.d_offs, p->lin.d_taps, p->lin.d_dense};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    p->lin.d_offs = p->lin.d_taps = p->lin.d_dense = nullptr;
+}
+} // namespace stn

@@ -80,3 +80,29 @@ def rk3_stability(z):
     """Amplification factor of any 3-stage third-order explicit RK method on
     y' = lambda y with z = dt lambda."""
     return 1 + z + z * z / 2 + z ** 3 / 6
+
+
+def laplacian_star_exact(ndim, r):
+    """Star Laplacian (grid units) from the exact rational weights."""
+    c = [float(v) for v in central_weights(2, r)]
+    g = np.zeros((2 * r + 1,) * ndim)
+    for a in range(ndim):
+        idx = [r] * ndim
+        for m in range(-r, r + 1):
+            idx[a] = r + m
+            g[tuple(idx)] += c[m + r]
+    return g
+
+
+def diffusion_star_exact(ndim, r, s):
+    g = s * laplacian_star_exact(ndim, r)
+    g[(r,) * ndim] += 1.0
+    return g
+
+
+def laplacian_symbol_grid(k, n, r):
+    """Symbol of the 1-D (2r)-th order second difference in grid units on the
+    mode exp(2 pi i k x / n)."""
+    c = [float(v) for v in central_weights(2, r)]
+    th = 2 * math.pi * k / n
+    return sum(c[m + r] * math.cos(m * th) for m in range(-r, r + 1))

@@ -1,0 +1,110 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, and its host-only paths (validation, sizes, finite-difference
+weights) behave as documented. No kernel is launched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2406_08923_amd as S
+from closed_forms import central_weights
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(stencil_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("stencil_plan", "stencil_apply", "stencil_plan_destroy", "stencil_last_error",
+                 "stencil_halo_periodic", "stencil_padded_elems"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = S.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_padded_elems():
+    L = S.lib()
+    assert L.stencil_version() >= 10000
+    assert S.padded_elems((512, 512, 512), 3) == 518 ** 3
+    assert S.padded_elems((2 ** 20,), 1) == 2 ** 20 + 2
+    assert S.padded_elems((7, 5), 2) == 11 * 9
+    dims = (ctypes.c_int * 3)(4, 4, 4)
+    assert L.stencil_padded_elems(4, dims, 1) == 0
+    assert L.stencil_padded_elems(3, dims, -1) == 0
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_fd_weights_match_exact_rationals(order, r):
+    w = S.fd_weights(order, r)
+    exact = np.array([float(v) for v in central_weights(order, r)])
+    assert np.max(np.abs(w - exact)) <= 4e-16 * np.max(np.abs(exact))
+    if order == 1:
+        assert w[r] == 0.0 and np.array_equal(w, -w[::-1])
+    else:
+        assert np.array_equal(w, w[::-1])
+
+
+def _plan_rc(**kw):
+    d = S._Desc()
+    d.ndim = kw.get("ndim", 3)
+    dims = kw.get("dims", (8, 8, 8))
+    d.dims = (ctypes.c_int * 3)(*dims)
+    d.radius = kw.get("radius", 1)
+    coeffs = kw.get("coeffs", np.ones(27))
+    d.coeffs = None if coeffs is None else coeffs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.dtype = kw.get("dtype", S.F64)
+    d.bc = kw.get("bc", S.PERIODIC)
+    d.variant = kw.get("variant", S.VARIANT_AUTO)
+    h = ctypes.c_void_p()
+    return S.lib().stencil_plan(ctypes.byref(d), ctypes.byref(h))
+
+
+@pytest.mark.parametrize("kw", [dict(ndim=4), dict(ndim=0), dict(radius=9), dict(radius=-1),
+                                dict(coeffs=None), dict(dtype=7), dict(bc=3),
+                                dict(dims=(2, 8, 8), radius=3, coeffs=np.ones(343)),
+                                dict(dims=(0, 8, 8)), dict(variant=9)])
+def test_plan_rejects_bad_descriptors_without_a_device(kw):
+    assert _plan_rc(**kw) == -1
+    assert S.lib().stencil_last_error()
+
+
+def test_plan_rejects_nonfinite_coefficients_before_the_device():
+    c = np.ones(27)
+    c[3] = np.nan
+    assert _plan_rc(coeffs=c) == -1
+    c[3] = np.inf
+    assert _plan_rc(coeffs=c) == -1
+
+
+def test_copy_and_halo_validate_before_launch():
+    L = S.lib()
+    assert L.stencil_copy(ctypes.c_void_p(4096), ctypes.c_void_p(8192), 24, None) == -1
+    assert L.stencil_copy(ctypes.c_void_p(4096), ctypes.c_void_p(4096 + 16), 64, None) == -1
+    assert L.stencil_copy(ctypes.c_void_p(4104), ctypes.c_void_p(1 << 20), 64, None) == -1
+    dims = (ctypes.c_int * 3)(8, 8, 8)
+    assert L.stencil_halo_periodic(3, dims, 1, 9, ctypes.c_void_p(4096), None) == -1
+    assert L.stencil_halo_periodic(3, dims, 1, 0, None, None) == -1
+    assert L.stencil_halo_periodic(3, dims, 9, 0, ctypes.c_void_p(4096), None) == -1
+
+
+def test_apply_rejects_null_plan():
+    assert S.lib().stencil_apply(None, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 1,
+                                 None) == -1

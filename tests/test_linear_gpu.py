@@ -1,0 +1,299 @@
+"""GPU parity of the linear path (halo, cross-correlation variants, copy)
+against the CPU oracle, through the C ABI.
+
+FP64 bar: normwise max relative error <= 1e-12 per output. FP32 / BF16 bar:
+the rounding bound of the arithmetic, per point,
+    |gpu - oracle| <= 2 (ntaps + 1) u32 sum_s |g_s| |f_{p+s}| + u_out |oracle|,
+with u32 = 2^-24 (FP32 accumulation), u_out = 2^-24 (FP32) or 2^-8 (BF16
+result rounding); inputs are exactly representable in the storage type.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from closed_forms import diffusion_star_exact, laplacian_symbol_grid
+from paper_2406_08923_amd import inputs
+
+torch = pytest.importorskip("torch")
+import paper_2406_08923_amd as S  # noqa: E402
+from paper_2406_08923_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def to_storage_values(a, dtype):
+    if dtype == S.F32:
+        return a.astype(np.float32).astype(np.float64)
+    if dtype == S.BF16:
+        return inputs.to_bf16_values(a)
+    return a
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(S.torch_dtype(dtype))
+
+
+def host(t):
+    return t.to(torch.float64).cpu().numpy()
+
+
+def u_out(dtype):
+    return {S.F64: 2.0 ** -53, S.F32: 2.0 ** -24, S.BF16: 2.0 ** -8}[dtype]
+
+
+def assert_close(gpu, ref, dtype, absconv=None, ntaps=1, what=""):
+    if dtype == S.F64:
+        err = np.max(np.abs(gpu - ref)) / max(np.max(np.abs(ref)), 1e-300)
+        assert err <= 1e-12, "%s: normwise rel err %.3e" % (what, err)
+    else:
+        bound = 2 * (ntaps + 1) * 2.0 ** -24 * absconv + u_out(dtype) * np.abs(ref)
+        bad = np.abs(gpu - ref) > bound
+        assert not bad.any(), "%s: %d points over the bound, worst %.3e" % (
+            what, int(bad.sum()), float(np.max(np.abs(gpu - ref) - bound)))
+
+
+def oracle_apply(inner, r, g, iters, bc=S.PERIODIC, padded_in=None):
+    if bc == S.PERIODIC:
+        return O.xcorr_periodic_iterate(O.pad_periodic(inner, r), r, g, iters)
+    return O.xcorr(padded_in, r, g)
+
+
+def run_case(dims, r, g, dtype, variant, tile=None, iters=1, seed=1, autotune=False):
+    inner = to_storage_values(inputs.uniform_field(dims, seed), dtype)
+    plan = S.LinearPlan(dims, r, g, dtype=dtype, variant=variant, tile=tile, autotune=autotune)
+    a_host = np.full(O.padded_shape(dims, r), 7.0)  # halo garbage: the library fills it
+    O.interior(a_host, r)[...] = inner
+    a = dev(a_host, dtype)
+    b = plan.empty(fill=-3.0)
+    res = host(plan.apply(a, b, iters))
+    torch.cuda.synchronize()
+    ref = oracle_apply(inner, r, g, iters)
+    ntaps = int(np.count_nonzero(g))
+    absconv = None
+    if dtype != S.F64:
+        assert iters == 1
+        absconv = O.xcorr(np.abs(O.pad_periodic(inner, r)), r, np.abs(g))
+    assert_close(res, ref, dtype, absconv, ntaps, what="%s r=%d var=%d tile=%s" % (dims, r, variant, tile))
+    return plan
+
+
+# ---------------------------------------------------------------------------
+# periodic halo and copy: exact
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims,r", [((1000,), 1), ((77,), 8), ((40, 33), 3), ((5, 4), 3),
+                                    ((37, 29, 23), 3), ((6, 5, 4), 4), ((64, 64, 64), 1)])
+@pytest.mark.parametrize("dtype", [S.F64, S.F32, S.BF16])
+def test_halo_periodic_exact(dims, r, dtype):
+    inner = to_storage_values(inputs.uniform_field(dims, 3), dtype)
+    pad = np.full(O.padded_shape(dims, r), np.nan)
+    O.interior(pad, r)[...] = inner
+    t = dev(pad, dtype)
+    S.halo_periodic(t, dims, r, dtype)
+    got = host(t)
+    ref = O.fill_periodic(pad.copy(), r)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16, 1 << 24])
+def test_copy_exact(nbytes):
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros_like(src)
+    S.copy(src, dst)
+    assert torch.equal(src, dst)
+
+
+# ---------------------------------------------------------------------------
+# cross-correlation, small grids spanning several tiles with ragged tails
+# ---------------------------------------------------------------------------
+
+DTYPES = [S.F64, S.F32, S.BF16]
+
+
+def rand_star(r, seed):
+    rng = np.random.default_rng(seed)
+    g = np.zeros((2 * r + 1,) * 3)
+    for a in range(3):
+        for m in range(-r, r + 1):
+            idx = [r, r, r]
+            idx[a] = r + m
+            g[tuple(idx)] = rng.uniform(-1, 1)
+    return g
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("tile", [(4, 1, 64), (4, 4, 64), (2, 8, 8), (8, 2, 13), (4, 2, 5, 1),
+                                  (8, 1, 64, 2), (2, 4, 7, 3)])
+def test_star3d_tiles_diffusion(dtype, tile):
+    g = diffusion_star_exact(3, 3, 0.0815)
+    run_case((70, 37, 29), 3, g, dtype, S.STAR3D, tile=tile)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("dtype", [S.F64, S.F32])
+def test_star3d_asymmetric_random_taps(r, dtype):
+    # asymmetric coefficients: a swapped side or axis would show
+    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(4, 2, 8))
+
+
+def test_star3d_tap_radius_below_padding():
+    # radius-4 padding, radius-2 taps: the plan runs a radius-2 kernel
+    g = np.zeros((9, 9, 9))
+    g[2:7, 2:7, 2:7] = rand_star(2, 5)
+    p = run_case((40, 20, 12), 4, g, S.F64, S.STAR3D, tile=(4, 2, 8))
+    assert p.variant == S.STAR3D
+
+
+@pytest.mark.parametrize("dims,r", [((3, 3, 3), 3), ((5, 4, 7), 3), ((4, 5, 6), 4), ((1, 1, 1), 1)])
+def test_star3d_tiny_periodic_grids(dims, r):
+    # n < 2r: a point has periodic images on both sides
+    run_case(dims, r, rand_star(r, 2), S.F64, S.STAR3D, tile=(4, 1, 2))
+    run_case(dims, r, rand_star(r, 2), S.F64, S.GENERIC)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("dims,r", [((1000,), 1), ((1000,), 3), ((333,), 8), ((50, 37), 2),
+                                    ((23, 17, 11), 2), ((30, 20, 10), 3)])
+def test_generic_dense(dtype, dims, r):
+    g = np.random.default_rng(7).uniform(-1, 1, (2 * r + 1,) * len(dims))
+    run_case(dims, r, g, dtype, S.GENERIC)
+
+
+@pytest.mark.parametrize("e", [1, 2, 4, 8])
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,r", [(5000, 1), (777, 4), (3, 3)])
+def test_line1d(e, dtype, n, r):
+    g = np.random.default_rng(8).uniform(-1, 1, 2 * r + 1)
+    run_case((n,), r, g, dtype, S.LINE1D, tile=(e,))
+
+
+def test_sparse_box_is_not_a_star():
+    g = np.zeros((3, 3, 3))
+    g[1, 1, 1] = 1.0
+    g[0, 0, 1] = 0.5  # an off-axis tap
+    with pytest.raises(S.StencilError):
+        S.LinearPlan((8, 8, 8), 1, g, variant=S.STAR3D)
+    run_case((19, 13, 11), 1, g, S.F64, S.VARIANT_AUTO)
+
+
+def test_r0_copy_stencil():
+    run_case((33, 17, 9), 0, np.array([[[2.0]]]), S.F64, S.GENERIC)
+
+
+@pytest.mark.parametrize("variant,tile", [(S.STAR3D, (4, 4, 16)), (S.GENERIC, None)])
+@pytest.mark.parametrize("iters", [6, 7])
+def test_chained_iterations_ping_pong(variant, tile, iters):
+    g = diffusion_star_exact(3, 3, 0.2)
+    run_case((40, 33, 21), 3, g, S.F64, variant, tile=tile, iters=iters)
+
+
+@pytest.mark.parametrize("variant", [S.STAR3D, S.GENERIC])
+def test_user_halo_reads_caller_halo_and_writes_interior_only(variant):
+    dims, r = (45, 26, 17), 3
+    g = rand_star(3, 4)
+    rng = np.random.default_rng(12)
+    a_host = rng.uniform(-1, 1, O.padded_shape(dims, r))  # non-periodic halo
+    plan = S.LinearPlan(dims, r, g, bc=S.USER_HALO, variant=variant,
+                        tile=(4, 2, 8) if variant == S.STAR3D else None)
+    a = dev(a_host, S.F64)
+    b = plan.empty(fill=123.0)
+    plan.apply(a, b, 1)
+    got = host(b)
+    ref = O.xcorr(a_host, r, g)
+    assert_close(O.interior(got, r), O.interior(ref, r), S.F64)
+    mask = np.ones(got.shape, bool)
+    O.interior(mask, r)[...] = False
+    assert np.all(got[mask] == 123.0)
+    assert np.array_equal(host(a), a_host)  # input untouched
+    with pytest.raises(S.StencilError):
+        plan.apply(a, b, 2)
+
+
+def test_autotuned_plan_matches_oracle():
+    g = diffusion_star_exact(3, 3, 0.0815)
+    p = run_case((96, 48, 40), 3, g, S.F64, S.VARIANT_AUTO, autotune=True)
+    assert p.variant in (S.STAR3D, S.GENERIC)
+
+
+def test_apply_validation_on_device():
+    plan = S.LinearPlan((16, 16, 16), 1, np.ones((3, 3, 3)))
+    a = plan.empty(0.0)
+    with pytest.raises(S.StencilError):
+        S.check(S.lib().stencil_apply(plan._h, S.ptr(a), S.ptr(a), 1, None))  # aliasing
+    assert plan.apply(a, plan.empty(0.0), 0) is a  # iters = 0 is a no-op
+
+
+# ---------------------------------------------------------------------------
+# full sizes of the benchmark workloads
+# ---------------------------------------------------------------------------
+
+def test_smoother_2pow20_ten_iterations():
+    n = 2 ** 20
+    g = W.smoother3()
+    assert np.array_equal(g, np.array([0.25, 0.5, 0.25]))
+    run_case((n,), 1, g, S.F64, S.VARIANT_AUTO, iters=10, autotune=True)
+
+
+def sample_points(dims, count, seed):
+    rng = np.random.default_rng(seed)
+    pts = np.stack([rng.integers(0, d, count) for d in dims], axis=1)
+    corners = np.array([[x, y, z] for x in (0, dims[0] - 1) for y in (0, dims[1] - 1)
+                        for z in (0, dims[2] - 1)])
+    return np.concatenate([pts, corners])
+
+
+@pytest.mark.parametrize("dtype", [S.F64, S.F32])
+def test_star_512_cubed_sampled_points(dtype):
+    dims, r = (512, 512, 512), 3
+    s = W.diffusion_number(512)
+    g_prod = W.diffusion_star(3, 3, s)
+    g_ref = diffusion_star_exact(3, 3, s)
+    assert np.max(np.abs(g_prod - g_ref)) < 1e-15
+    inner = to_storage_values(inputs.uniform_field(dims, 1), dtype)
+    plan = S.LinearPlan(dims, r, g_prod, dtype=dtype, autotune=True)
+    a_host = np.zeros(O.padded_shape(dims, r))
+    O.interior(a_host, r)[...] = inner
+    del inner
+    a = dev(a_host, dtype)
+    b = plan.empty(0.0)
+    plan.apply(a, b, 1)
+    got = host(b)
+    O.fill_periodic(a_host, r)
+    pts = sample_points(dims, 4000, 2)
+    ref = O.xcorr_at(a_host, r, g_ref, pts)
+    vals = got[pts[:, 2] + r, pts[:, 1] + r, pts[:, 0] + r]
+    if dtype == S.F64:
+        assert np.max(np.abs(vals - ref)) <= 1e-12 * np.max(np.abs(ref))
+    else:
+        absconv = O.xcorr_at(np.abs(a_host), r, np.abs(g_ref), pts)
+        assert np.all(np.abs(vals - ref) <= 2 * 20 * 2.0 ** -24 * absconv + 2.0 ** -24 * np.abs(ref))
+    # the output halo is the periodic image of its interior
+    assert np.array_equal(got[:r], got[512:512 + r]) and np.array_equal(got[:, :, -r:], got[:, :, r:2 * r])
+
+
+def test_star_512_cubed_hundred_iterations_fourier_mode():
+    # a single Fourier mode is an eigenvector: after N iterations it is scaled
+    # by the symbol to the N-th power (closed form, any size)
+    dims, r, N = (512, 512, 512), 3, 100
+    s = W.diffusion_number(512)
+    k = (3, -5, 7)
+    X = inputs.grid_coords(dims)
+    inner = np.cos(sum(k[a] * X[a] for a in range(3)) + 0.25)
+    lam = 1.0 + s * sum(laplacian_symbol_grid(k[a], 512, r) for a in range(3))
+    plan = S.LinearPlan(dims, r, W.diffusion_star(3, 3, s), autotune=True)
+    a_host = np.zeros(O.padded_shape(dims, r))
+    O.interior(a_host, r)[...] = inner
+    a = dev(a_host, S.F64)
+    b = plan.empty(0.0)
+    res = plan.apply(a, b, N)
+    got = O.interior(host(res), r)
+    err = np.max(np.abs(got - lam ** N * inner))
+    assert err <= 1e-12, err
