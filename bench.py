@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the stencil hot path on one MI355X.
 
-Default workload: the 3-D linear cross-correlation with the 19-point radius-3
+Headline workload: the 3-D linear cross-correlation with the 19-point radius-3
 star (one forward-Euler step of the sixth-order diffusion operator, Eq. 5/7),
 512^3 FP64, periodic halo, 100 chained iterations. One step = one iteration =
 one kernel launch (periodic images written by the kernel itself). Input: seeded
@@ -9,11 +9,14 @@ uniform [-1, 1), resident in HBM before timing starts.
 
 Prints one JSON line: grid-point updates/s, the HBM roofline of the dominant
 kernel (algorithmic bytes per launch / average launch duration from HIP events
-recorded on the launch stream) and the CPU oracle timed on a bounded sample.
+recorded on the launch stream), the CPU oracle timed on a bounded sample, and
+secondary lines for the other workloads (FP32 star, 1-D radius-1 smoother,
+fused 8-field RK3 step in FP64 and with FP32/BF16 storage).
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -34,22 +37,25 @@ def parse():
     ap.add_argument("--dtype", choices=sorted(DTYPES), default="f64")
     ap.add_argument("--n", type=int, default=512, help="grid edge")
     ap.add_argument("--radius", type=int, default=3)
+    ap.add_argument("--tile", default=None,
+                    help="star3d launch shape TY,NY,LZ,FLAGS (skips autotuning)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth probe")
+    ap.add_argument("--no-secondary", action="store_true", help="headline workload only")
     return ap.parse_args()
 
 
-def kernel_source_hash():
+def source_hash(files):
     h = hashlib.sha256()
-    for f in ("linear_kernels.hip", "common.hpp", "linear_kernels.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2406_08923_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(name, bytes_per_launch):
+def load_traffic(name, files):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", name)
@@ -57,23 +63,30 @@ def load_traffic(name, bytes_per_launch):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != source_hash(files):
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def timed(torch, fn, reps, warm=2):
+    """Average ms per call of fn over reps calls (HIP events on the current
+    stream)."""
+    for _ in range(warm):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
 def copy_bandwidth(torch, S, nbytes=2 << 30, reps=20):
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(3):
-        S.copy(src, dst)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        S.copy(src, dst)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    ms = timed(torch, lambda: S.copy(src, dst), reps, warm=3)
     del src, dst
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
@@ -82,7 +95,6 @@ def cpu_baseline(n, r, g, seconds):
     """The oracle as it stands (dense (2r+1)^3 tap loop, OpenMP over z) on an
     n x n x nz slab of the same workload; nz grown until the run takes about
     `seconds`."""
-    import numpy as np
     import oracle as O
     from paper_2406_08923_amd import inputs
     nz, t = 2, 0.0
@@ -107,6 +119,86 @@ def cpu_baseline(n, r, g, seconds):
                       % ((2 * r + 1) ** 3, n, n, nz, t)}
 
 
+def star_run(torch, S, W, inputs, n, r, dtype, steps, warmup, tile=None):
+    """Chained iterations of the star workload, one launch per step with an
+    event after each; returns (plan, total ms, per-launch ms list)."""
+    import numpy as np
+    dims = (n, n, n)
+    g = W.diffusion_star(3, r, W.diffusion_number(n))
+    if tile:
+        plan = S.LinearPlan(dims, r, g, dtype=dtype, variant=S.STAR3D, tile=tile)
+    else:
+        plan = S.LinearPlan(dims, r, g, dtype=dtype, autotune=True)
+    a = plan.empty(0.0)
+    a[r:r + n, r:r + n, r:r + n] = torch.from_numpy(inputs.uniform_field(dims, 1)).to(
+        "cuda").to(a.dtype)
+    b = plan.empty(0.0)
+    S.halo_periodic(a, dims, r, dtype)
+    cur, nxt = a, b
+    for _ in range(warmup):
+        plan.apply(cur, nxt, 1, halo_valid=True)
+        cur, nxt = nxt, cur
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for k in range(steps):
+        plan.apply(cur, nxt, 1, halo_valid=True)
+        cur, nxt = nxt, cur
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    total = ev[0].elapsed_time(ev[steps])
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    del a, b
+    return plan, g, total, float(np.mean(per))
+
+
+def secondary(torch, S, W, inputs, args):
+    out = {}
+    # FP32 storage of the same star workload
+    n, r = args.n, args.radius
+    _, _, tot, per = star_run(torch, S, W, inputs, n, r, S.F32, 50, 5)
+    out["star_%d_f32" % n] = {"updates_per_s": n ** 3 / (tot / 50 * 1e-3),
+                              "hbm_frac": 8 * n ** 3 / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "avg_launch_ms": per}
+    # 1-D radius-1 smoother, 2^20 points, 10 chained iterations per call
+    N = 1 << 20
+    p1 = S.LinearPlan((N,), 1, W.smoother3(), autotune=True)
+    a = p1.empty(0.0)
+    a[1:N + 1] = torch.from_numpy(inputs.uniform_field((N,), 1)).cuda()
+    b = p1.empty(0.0)
+    ms = timed(torch, lambda: p1.apply(a, b, 10), 50)
+    out["line_2^20_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
+                                   "us_per_iteration": ms * 100.0,
+                                   "variant": p1.variant, "tile": list(p1.tile)}
+    del a, b
+    # fused 8-field RK3 step, 256^3
+    nm = 256
+    f, _ = inputs.fourier_fields((nm, nm, nm), 1, nf=8, modes=8, kmax=8, amp=0.01)
+    ds = 2 * math.pi / nm
+    dt = 0.1 * ds
+    bytes_step = {S.PREC_F64: 640, S.PREC_F32_MASTER64: 480, S.PREC_BF16_MASTER64: 384}
+    for prec, name in ((S.PREC_F64, "f64"), (S.PREC_F32_MASTER64, "f32_master64"),
+                       (S.PREC_BF16_MASTER64, "bf16_master64")):
+        plan = S.RkPlan(S.MODEL_MHD8, (nm, nm, nm), prec)
+        bufs = plan.alloc()
+        for k in range(8):
+            bufs["f_a"][k][3:nm + 3, 3:nm + 3, 3:nm + 3] = torch.from_numpy(f[k]).cuda().to(
+                bufs["f_a"][k].dtype)
+            if plan.master:
+                bufs["f64"][k][3:nm + 3, 3:nm + 3, 3:nm + 3] = torch.from_numpy(f[k]).cuda()
+        steps = 5
+        ms = timed(torch, lambda: plan.run(bufs["f_a"], bufs["f_b"], bufs["w"], steps, dt,
+                                           w2=bufs["w2"], f64=bufs["f64"]), 2, warm=1) / steps
+        pts = nm ** 3
+        out["mhd8_%d_%s" % (nm, name)] = {
+            "point_steps_per_s": pts / (ms * 1e-3),
+            "point_substeps_per_s": 3 * pts / (ms * 1e-3),
+            "ms_per_step": ms,
+            "hbm_frac": bytes_step[prec] * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del bufs, plan
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -115,7 +207,7 @@ def main():
               "(--gpus %d requested)" % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
 
     import paper_2406_08923_amd as S
@@ -125,45 +217,19 @@ def main():
     torch.cuda.set_device(0)
     n, r = args.n, args.radius
     dtype, esize = DTYPES[args.dtype]
-    dims = (n, n, n)
-    s = W.diffusion_number(n)
-    g = W.diffusion_star(3, r, s)
-
-    # input resident in HBM before timing
-    inner = inputs.uniform_field(dims, 1)
-    plan = S.LinearPlan(dims, r, g, dtype=dtype, autotune=True)
-    a = plan.empty(0.0)
-    a[r:r + n, r:r + n, r:r + n] = torch.from_numpy(inner).to("cuda").to(a.dtype)
-    del inner
-    b = plan.empty(0.0)
-    S.halo_periodic(a, dims, r, dtype)
-
-    cur, nxt = a, b
-    for _ in range(args.warmup):
-        plan.apply(cur, nxt, 1, halo_valid=True)
-        cur, nxt = nxt, cur
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     K = args.steps
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev[0].record()
-    for k in range(K):
-        plan.apply(cur, nxt, 1, halo_valid=True)
-        cur, nxt = nxt, cur
-        ev[k + 1].record()
-    torch.cuda.synchronize()
+    plan, g, total_ms, avg_launch_ms = star_run(torch, S, W, inputs, n, r, dtype, K,
+                                                args.warmup, tile)
     wall = time.perf_counter() - t0
-    total_ms = ev[0].elapsed_time(ev[K])
-    launch_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(K)]
-    avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     ms_per_step = total_ms / K
     points = n ** 3
     value = points / (ms_per_step * 1e-3)
-
     alg_bytes = 2 * esize * points  # read f once, write f' once per point
-    achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = load_traffic("traffic_star3d_%d_%s.json" % (n, args.dtype), alg_bytes)
-
+    achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
+    kern_files = ("linear_kernels.hip", "common.hpp", "linear_kernels.hpp")
+    traffic = load_traffic("traffic_star3d_%d_%s.json" % (n, args.dtype), kern_files)
     copy_gbs = None if args.no_copy else copy_bandwidth(torch, S)
 
     out = {
@@ -182,9 +248,10 @@ def main():
         "config": {
             "workload": "3-D linear cross-correlation, 19-point radius-%d star (6th-order "
                         "diffusion step, s=%.4f), %d^3 %s, periodic halo, %d chained iterations"
-                        % (r, s, n, args.dtype.upper(), K),
-            "grid": list(dims), "radius": r, "taps": int(np.count_nonzero(g)),
+                        % (r, W.diffusion_number(n), n, args.dtype.upper(), K),
+            "grid": [n, n, n], "radius": r, "taps": int((g != 0).sum()),
             "kernel_variant": {0: "generic", 1: "star3d", 2: "line1d"}[plan.variant],
+            "tile": list(plan.tile),
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -195,13 +262,15 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": alg_bytes,
-            "avg_launch_ms": avg_launch_s * 1e3,
+            "avg_launch_ms": avg_launch_ms,
         },
         "hbm_roofline_pct": 100.0 * achieved / HBM_PEAK_GBS,
         "copy_bandwidth_gbs": copy_gbs,
         "pct_of_copy_bandwidth": (100.0 * achieved / copy_gbs) if copy_gbs else None,
-        "wall_s_timed": wall,
+        "wall_s_star_phase": wall,
     }
+    if not args.no_secondary:
+        out["secondary"] = secondary(torch, S, W, inputs, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, r, g, args.cpu_seconds)
     print(json.dumps(out), flush=True)

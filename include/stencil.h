@@ -111,6 +111,10 @@ stencil_status stencil_plan_destroy(stencil_plan_t plan);
 /* Variant the plan will launch (after tuning), or a negative status. */
 int stencil_plan_variant(stencil_plan_t plan);
 
+/* Launch parameters the plan will use, in the layout of stencil_desc.tile for
+ * its variant (passing them back in a descriptor reproduces the choice). */
+stencil_status stencil_plan_tile(stencil_plan_t plan, int tile[4]);
+
 /* iters chained applications on stream. d_a and d_b are caller-owned padded
  * device buffers of the plan's dtype and may not overlap. Iteration k reads
  * one and writes the other, starting d_a -> d_b, so the result is in d_b when
@@ -144,6 +148,95 @@ stencil_status stencil_copy(const void *d_src, void *d_dst, size_t nbytes, void 
  * the given order (1 or 2), of accuracy order 2r, for unit spacing, computed
  * by solving the moment conditions. out receives 2r+1 doubles. */
 stencil_status stencil_fd_weights(int order, int radius, double *out);
+
+
+/* ------------------------------------------------------------------------ */
+/* Fused nonlinear substep: derivative bank + right-hand side + RK3 update  */
+/* ------------------------------------------------------------------------ */
+
+/* Models (the nonlinear stencil function phi of Eq. 9 on the sixth-order,
+ * radius-3 derivative bank gamma = AB of Eq. 8, Sec. 3.3):
+ *  MHD8   : 8 fields (lnrho, u_x, u_y, u_z, s, A_x, A_y, A_z; Table A1), 3-D:
+ *           R_lnrho = -u.grad lnrho - div u + nu lap lnrho
+ *           R_u     = -(u.grad)u - cs2 grad(s + lnrho) + j x B
+ *                     + nu [lap u + grad(div u)/3 + 2 S.grad lnrho]
+ *           R_s     = -u.grad s + nu lap s + eta |j|^2 + 2 nu S:S
+ *           R_A     = u x B + eta lap A
+ *           with B = curl A, j = grad(div A) - lap A, S the traceless rate
+ *           of shear: Eq. A1-A4 with rho, T, c_p, mu_0 = 1 and no heating,
+ *           cooling, conduction or bulk viscosity.
+ *  ADVDIFF: 1 field, 2-D or 3-D: R = -c.grad f + nu lap f.
+ * Mixed derivatives are tensor products of the first-derivative stencil. */
+#define STENCIL_MODEL_MHD8 0
+#define STENCIL_MODEL_ADVDIFF 1
+
+/* Precision policies. F64: FP64 everywhere. F32_MASTER64 / BF16_MASTER64:
+ * fields stored in FP32 / BF16, derivatives and RK registers in FP32, and an
+ * FP64 master state that the last substep of every step recomputes as
+ * master + b0 w1 + b1 w2 + b2 w3 in FP64 (so rounding does not accumulate in
+ * the state across steps). F32_ONLY / BF16_ONLY: no master (ablation). */
+#define STENCIL_PREC_F64 0
+#define STENCIL_PREC_F32_MASTER64 1
+#define STENCIL_PREC_BF16_MASTER64 2
+#define STENCIL_PREC_F32_ONLY 3
+#define STENCIL_PREC_BF16_ONLY 4
+
+typedef struct stencil_rk_desc {
+    int model;      /* STENCIL_MODEL_* */
+    int ndim;       /* 3 for MHD8, 2 or 3 for ADVDIFF */
+    int dims[3];    /* interior extents, each >= 3 (periodic, radius 3) */
+    int precision;  /* STENCIL_PREC_* */
+    double ds[3];   /* grid spacing per axis (> 0) */
+    double nu, eta, cs2;
+    double adv[3];  /* ADVDIFF velocity */
+    int block[2];   /* launch override (x, y lanes); 0 = plan's choice */
+} stencil_rk_desc;
+
+/* Buffers of one substep; all are caller-owned padded (radius 3) device
+ * arrays of the plan's dims, one per field (entries beyond the model's field
+ * count are ignored).
+ *  f_in  : substep input (storage type; halo must be periodic-valid)
+ *  f_out : substep output (storage type; interior and periodic halo written)
+ *  w     : RK register, FP64 for PREC_F64, FP32 otherwise. Non-master
+ *          policies update it in place (not read at substep 0, not written at
+ *          substep 2). Master policies: written at substep 0, read at 1 and 2.
+ *  w2    : master policies only: written at substep 1, read at substep 2.
+ *  f64   : master policies only: FP64 state, read and written at substep 2
+ *          (interior only). */
+typedef struct stencil_fields {
+    void *f_in[8];
+    void *f_out[8];
+    void *w[8];
+    void *w2[8];
+    double *f64[8];
+} stencil_fields;
+
+/* Plan of the fused substep of a model; RK coefficients are Williamson's
+ * 2N-storage third-order scheme: alpha = (0, -5/9, -153/128), beta = (1/3,
+ * 15/16, 8/15), substep i: w = alpha_i w + dt R(f), f = f + beta_i w. */
+stencil_status stencil_plan_rk(const stencil_rk_desc *desc, stencil_plan_t *out);
+
+/* Number of fields of the plan's model (8 or 1), or a negative status. */
+int stencil_plan_nfields(stencil_plan_t plan);
+
+/* One fused substep (substep = 0, 1, 2) as one kernel launch on stream. */
+stencil_status stencil_step(stencil_plan_t plan, const stencil_fields *fields, int substep,
+                            double dt, void *stream);
+
+/* nsteps full RK3 steps (3 substeps each). f_in holds the initial state (its
+ * halo is refreshed first) and f_in / f_out are used in ping-pong, so the
+ * result is in f_out when nsteps is odd and in f_in when even. Registers and
+ * the master (master policies: f64 must hold the FP64 copy of f_in) as in
+ * stencil_step. */
+stencil_status stencil_rk_run(stencil_plan_t plan, const stencil_fields *fields, int nsteps,
+                              double dt, void *stream);
+
+/* Global diagnostics in FP64 over the interior of nfields padded buffers of
+ * the plan's geometry stored as dtype: host_out[3k..3k+2] = (sum, sum of
+ * squares, max |f|) of field k. Deterministic (fixed two-level tree, no
+ * floating-point atomics). Synchronises the stream. */
+stencil_status stencil_reduce(stencil_plan_t plan, const void *const *fields, int nfields,
+                              int dtype, double *host_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -67,11 +67,13 @@ def _declare(L):
     L.stencil_plan.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_vp)]
     L.stencil_plan_destroy.argtypes = [_vp]
     L.stencil_plan_variant.argtypes = [_vp]
+    L.stencil_plan_tile.argtypes = [_vp, ctypes.POINTER(c_int)]
     L.stencil_apply.argtypes = [_vp, _vp, _vp, c_int, _vp]
     L.stencil_apply_ex.argtypes = [_vp, _vp, _vp, c_int, ctypes.c_uint, _vp]
     L.stencil_halo_periodic.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, _vp, _vp]
     L.stencil_copy.argtypes = [_vp, _vp, c_size, _vp]
     L.stencil_fd_weights.argtypes = [c_int, c_int, ctypes.POINTER(ctypes.c_double)]
+    _declare_rk(L)
 
 
 def check(rc):
@@ -159,6 +161,20 @@ class LinearPlan:
         v = lib().stencil_plan_variant(self._h)
         return check(v) if v < 0 else v
 
+    @property
+    def tile(self):
+        t = (ctypes.c_int * 4)()
+        check(lib().stencil_plan_tile(self._h, t))
+        return tuple(t)
+
+    def reduce(self, fields, dtype=None, stream=None):
+        """(sum, sum of squares, max |f|) per buffer, FP64, deterministic."""
+        dtype = self.dtype if dtype is None else dtype
+        ptrs = (_vp * len(fields))(*[t.data_ptr() for t in fields])
+        out = (ctypes.c_double * (3 * len(fields)))()
+        check(lib().stencil_reduce(self._h, ptrs, len(fields), dtype, out, stream_ptr(stream)))
+        return np.array(out[:]).reshape(len(fields), 3)
+
     def empty(self, fill=None):
         """A padded device tensor of the plan's shape and dtype."""
         import torch
@@ -178,6 +194,128 @@ class LinearPlan:
         check(lib().stencil_apply_ex(self._h, ptr(a), ptr(b), int(iters),
                                      APPLY_HALO_VALID if halo_valid else 0, stream_ptr(stream)))
         return b if iters % 2 else a
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().stencil_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# fused nonlinear substep (derivative bank + phi + low-storage RK3)
+# ---------------------------------------------------------------------------
+
+MODEL_MHD8, MODEL_ADVDIFF = 0, 1
+PREC_F64, PREC_F32_MASTER64, PREC_BF16_MASTER64, PREC_F32_ONLY, PREC_BF16_ONLY = range(5)
+_PREC_STORE = {PREC_F64: F64, PREC_F32_MASTER64: F32, PREC_BF16_MASTER64: BF16,
+               PREC_F32_ONLY: F32, PREC_BF16_ONLY: BF16}
+
+
+class _RkDesc(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int), ("ndim", ctypes.c_int), ("dims", ctypes.c_int * 3),
+                ("precision", ctypes.c_int), ("ds", ctypes.c_double * 3),
+                ("nu", ctypes.c_double), ("eta", ctypes.c_double), ("cs2", ctypes.c_double),
+                ("adv", ctypes.c_double * 3), ("block", ctypes.c_int * 2)]
+
+
+class _Fields(ctypes.Structure):
+    _fields_ = [("f_in", _vp * 8), ("f_out", _vp * 8), ("w", _vp * 8), ("w2", _vp * 8),
+                ("f64", _vp * 8)]
+
+
+def _declare_rk(L):
+    c_int = ctypes.c_int
+    L.stencil_plan_rk.argtypes = [ctypes.POINTER(_RkDesc), ctypes.POINTER(_vp)]
+    L.stencil_plan_nfields.argtypes = [_vp]
+    L.stencil_step.argtypes = [_vp, ctypes.POINTER(_Fields), c_int, ctypes.c_double, _vp]
+    L.stencil_rk_run.argtypes = [_vp, ctypes.POINTER(_Fields), c_int, ctypes.c_double, _vp]
+    L.stencil_reduce.argtypes = [_vp, ctypes.POINTER(_vp), c_int, c_int,
+                                 ctypes.POINTER(ctypes.c_double), _vp]
+
+
+def _fields_struct(f_in, f_out, w, w2=None, f64=None):
+    fs = _Fields()
+    for name, lst in (("f_in", f_in), ("f_out", f_out), ("w", w), ("w2", w2), ("f64", f64)):
+        if lst is None:
+            continue
+        arr = getattr(fs, name)
+        for k, t in enumerate(lst):
+            arr[k] = t.data_ptr() if t is not None else None
+    return fs
+
+
+class RkPlan:
+    """Plan of the fused substep of a model (MODEL_MHD8: 8 fields, 3-D;
+    MODEL_ADVDIFF: 1 field, 2-D or 3-D), radius-3 periodic padding."""
+
+    def __init__(self, model, dims, precision=PREC_F64, ds=None, nu=1e-3, eta=1e-3, cs2=1.0,
+                 adv=(0.0, 0.0, 0.0), block=None):
+        import math
+        self.model = model
+        self.dims = tuple(int(v) for v in dims)
+        self.ndim = len(self.dims)
+        self.precision = precision
+        self.dtype = _PREC_STORE[precision]
+        self.master = precision in (PREC_F32_MASTER64, PREC_BF16_MASTER64)
+        if ds is None:
+            ds = [2 * math.pi / v for v in self.dims]
+        d = _RkDesc()
+        d.model = model
+        d.ndim = self.ndim
+        d.dims = _dims3(self.dims)
+        d.precision = precision
+        d.ds = (ctypes.c_double * 3)(*(list(ds) + [1.0] * (3 - len(ds))))
+        d.nu, d.eta, d.cs2 = nu, eta, cs2
+        d.adv = (ctypes.c_double * 3)(*(list(adv) + [0.0] * (3 - len(adv))))
+        d.block = (ctypes.c_int * 2)(*(list(block or []) + [0, 0])[:2])
+        L = lib()
+        h = _vp()
+        check(L.stencil_plan_rk(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.nfields = L.stencil_plan_nfields(h)
+
+    @property
+    def reg_dtype(self):
+        import torch
+        return torch.float64 if self.precision == PREC_F64 else torch.float32
+
+    def alloc(self):
+        """Device buffers of one integration: f_a, f_b (storage), w, w2
+        (registers) and f64 (master), as lists of padded tensors."""
+        import torch
+        shp = padded_shape(self.dims, 3)
+        sd = torch_dtype(self.dtype)
+        mk = lambda dt: [torch.zeros(shp, dtype=dt, device="cuda") for _ in range(self.nfields)]
+        bufs = {"f_a": mk(sd), "f_b": mk(sd), "w": mk(self.reg_dtype)}
+        bufs["w2"] = mk(self.reg_dtype) if self.master else None
+        bufs["f64"] = mk(torch.float64) if self.master else None
+        return bufs
+
+    def step(self, f_in, f_out, w, substep, dt, w2=None, f64=None, stream=None):
+        fs = _fields_struct(f_in, f_out, w, w2, f64)
+        check(lib().stencil_step(self._h, ctypes.byref(fs), int(substep), float(dt),
+                                 stream_ptr(stream)))
+
+    def run(self, f_a, f_b, w, nsteps, dt, w2=None, f64=None, stream=None):
+        """nsteps full steps; returns the list holding the result."""
+        fs = _fields_struct(f_a, f_b, w, w2, f64)
+        check(lib().stencil_rk_run(self._h, ctypes.byref(fs), int(nsteps), float(dt),
+                                   stream_ptr(stream)))
+        return f_b if nsteps % 2 else f_a
+
+    def reduce(self, fields, dtype=None, stream=None):
+        """(sum, sum of squares, max |f|) per field, FP64, deterministic."""
+        dtype = self.dtype if dtype is None else dtype
+        ptrs = (_vp * len(fields))(*[t.data_ptr() for t in fields])
+        out = (ctypes.c_double * (3 * len(fields)))()
+        check(lib().stencil_reduce(self._h, ptrs, len(fields), dtype, out, stream_ptr(stream)))
+        return np.array(out[:]).reshape(len(fields), 3)
 
     def close(self):
         if getattr(self, "_h", None):

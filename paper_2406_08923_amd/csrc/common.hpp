@@ -75,6 +75,53 @@ template <> struct Store<bf16> {
     static __device__ __forceinline__ void st(bf16 *p, float v) { p->bits = f32_to_bf16(v); }
 };
 
+// ---------------------------------------------------------------------------
+// buffer loads
+// ---------------------------------------------------------------------------
+//
+// A raw buffer load takes a per-lane 32-bit byte offset (VGPR) plus a
+// wave-uniform byte offset (SGPR): a stencil tap whose offset is the same for
+// every lane then costs one load instruction and no address arithmetic.
+// Offsets are unsigned, so callers index from the lowest address a lane can
+// touch. Loads past num_records bytes return zero (no fault). Usable for
+// arrays below 4 GiB.
+
+constexpr int BUF_DWORD3 = 0x00020000; // raw 32-bit data format, gfx9 family
+
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ __forceinline__ Buf make_buf(const void *base, uint64_t bytes)
+{
+    const uint32_t n = bytes > 0xffffffffull ? 0xffffffffu : static_cast<uint32_t>(bytes);
+    return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0,
+                                                 static_cast<int>(n), BUF_DWORD3)};
+}
+
+template <typename S> struct BufLd;
+
+template <> struct BufLd<double> {
+    static __device__ __forceinline__ double ld(const Buf &b, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, voff, soff, 0));
+    }
+};
+
+template <> struct BufLd<float> {
+    static __device__ __forceinline__ float ld(const Buf &b, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, voff, soff, 0));
+    }
+};
+
+template <> struct BufLd<bf16> {
+    static __device__ __forceinline__ float ld(const Buf &b, uint32_t voff, uint32_t soff)
+    {
+        return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(b.r, voff, soff, 0));
+    }
+};
+
 inline size_t dtype_size(int dtype)
 {
     return dtype == STENCIL_F64 ? 8 : dtype == STENCIL_F32 ? 4 : dtype == STENCIL_BF16 ? 2 : 0;
@@ -113,7 +160,7 @@ inline Geo make_geo(int ndim, const int *dims, int r)
     return g;
 }
 
-inline int64_t padded_elems(const Geo &g)
+__host__ __device__ inline int64_t padded_elems(const Geo &g)
 {
     return g.sz * (g.nz + 2 * g.rz);
 }

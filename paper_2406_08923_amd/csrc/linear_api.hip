@@ -470,6 +470,26 @@ int stencil_plan_variant(stencil_plan_t p)
     return p->lin.variant;
 }
 
+stencil_status stencil_plan_tile(stencil_plan_t p, int tile[4])
+{
+    if (!p || p->kind != PLAN_LINEAR || !tile)
+        return fail(STENCIL_EINVAL, "not a linear plan or NULL output");
+    const LinearPlan &L = p->lin;
+    tile[0] = tile[1] = tile[2] = tile[3] = 0;
+    if (L.variant == STENCIL_VARIANT_STAR3D) {
+        tile[0] = L.ty;
+        tile[1] = L.ny;
+        tile[2] = L.lz;
+        tile[3] = L.sflags;
+    } else if (L.variant == STENCIL_VARIANT_LINE1D) {
+        tile[0] = L.e1d;
+    } else {
+        tile[0] = L.gbx;
+        tile[1] = L.gby;
+    }
+    return STENCIL_OK;
+}
+
 stencil_status stencil_apply(stencil_plan_t p, void *a, void *b, int iters, void *stream)
 {
     return stencil_apply_ex(p, a, b, iters, 0u, stream);

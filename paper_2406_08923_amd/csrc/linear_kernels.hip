@@ -401,22 +401,37 @@ int launch_line1d(const S *in, S *out, const Geo &g, const typename Store<S>::C 
 // r = 0 streaming copy (effective-bandwidth measurement, Sec. 5.2)
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+// Four 16-byte loads in flight per lane before the stores, non-temporal so the
+// stream does not evict useful cache lines.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_copy16(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
                                                 int64_t n)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        u32x4 v0 = __builtin_nontemporal_load(src + i);
+        u32x4 v1 = __builtin_nontemporal_load(src + i + stride);
+        u32x4 v2 = __builtin_nontemporal_load(src + i + 2 * stride);
+        u32x4 v3 = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(v0, dst + i);
+        __builtin_nontemporal_store(v1, dst + i + stride);
+        __builtin_nontemporal_store(v2, dst + i + 2 * stride);
+        __builtin_nontemporal_store(v3, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 int launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t s)
 {
     int64_t n = (int64_t)(nbytes / 16);
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;
+    int64_t blocks = (n + 4 * 256 - 1) / (4 * 256);
+    if (blocks > 256 * 32) blocks = 256 * 32;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s,
-                       static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n);
+                       static_cast<const u32x4 *>(src), static_cast<u32x4 *>(dst), n);
     return check_launch("copy");
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "linear_kernels.hpp"
+#include "rk_kernels.hpp"
 
 #include <vector>
 
@@ -26,6 +27,16 @@ struct LinearPlan {
     int e1d = 4;                             // LINE1D
 };
 
+struct RkPlan {
+    int model = 0, policy = 0, nf = 0;
+    Geo g{};
+    FdWeights fd{};
+    double inv_ds[3] = {1, 1, 1};
+    double nu = 0, eta = 0, cs2 = 0, adv[3] = {0, 0, 0};
+    int bx = 64, by = 4;
+    size_t store_size = 8, reg_size = 8; // bytes per element of f and of w
+};
+
 // validation helpers shared by the C-ABI translation units
 int check_dims(int ndim, const int *dims, int r, int bc);
 int check_buffers(const void *a, const void *b, size_t bytes, size_t align);
@@ -38,6 +49,7 @@ struct stencil_plan_s {
     int device = 0;
     int sticky = 0; // device error latched by an earlier call
     stn::LinearPlan lin;
+    stn::RkPlan rk;
 };
 
 namespace stn {

@@ -1,0 +1,116 @@
+// reduce_kernels.hip -- deterministic FP64 field diagnostics: sum, sum of
+// squares and maximum magnitude over the interior of a padded field.
+//
+// Two fixed levels, no floating-point atomics: pass 1 gives every workgroup a
+// fixed contiguous range of interior rows and reduces it (lane-strided
+// sequential sums, then a fixed tree in LDS) to one partial triple; pass 2
+// reduces the partials of each field in one workgroup with the same fixed
+// tree. The result depends only on the grid shape, never on timing.
+#include "reduce_kernels.hpp"
+
+namespace stn {
+
+namespace {
+constexpr int RT = 256;
+
+__device__ __forceinline__ void tree3(double *s0, double *s1, double *s2, double &a, double &b,
+                                      double &c)
+{
+    const int t = threadIdx.x;
+    s0[t] = a;
+    s1[t] = b;
+    s2[t] = c;
+    __syncthreads();
+    for (int h = RT / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            s0[t] += s0[t + h];
+            s1[t] += s1[t + h];
+            s2[t] = fmax(s2[t], s2[t + h]);
+        }
+        __syncthreads();
+    }
+    a = s0[0];
+    b = s1[0];
+    c = s2[0];
+}
+} // namespace
+
+template <typename S>
+__global__ void __launch_bounds__(RT) k_reduce_pass1(FieldPtrs fields, Geo g,
+                                                     int64_t rows_per_block, double *partial,
+                                                     int nblocks)
+{
+    __shared__ double s0[RT], s1[RT], s2[RT];
+    const S *f = static_cast<const S *>(fields.p[blockIdx.y]);
+    const int64_t nrows = (int64_t)g.ny * g.nz;
+    const int64_t r0 = blockIdx.x * rows_per_block;
+    const int64_t r1 = min(nrows, r0 + rows_per_block);
+    const int64_t len = (r1 > r0 ? r1 - r0 : 0) * g.nx;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t i = threadIdx.x; i < len; i += RT) {
+        int64_t row = r0 + i / g.nx;
+        int x = static_cast<int>(i % g.nx);
+        int y = static_cast<int>(row % g.ny), z = static_cast<int>(row / g.ny);
+        double v = static_cast<double>(Store<S>::ld(f + g.at(x, y, z)));
+        a += v;
+        b = fma(v, v, b);
+        c = fmax(c, fabs(v));
+    }
+    tree3(s0, s1, s2, a, b, c);
+    if (threadIdx.x == 0) {
+        double *o = partial + 3 * ((int64_t)blockIdx.y * nblocks + blockIdx.x);
+        o[0] = a;
+        o[1] = b;
+        o[2] = c;
+    }
+}
+
+__global__ void __launch_bounds__(RT) k_reduce_pass2(const double *partial, int nblocks,
+                                                     double *out)
+{
+    __shared__ double s0[RT], s1[RT], s2[RT];
+    const double *p = partial + 3 * (int64_t)blockIdx.x * nblocks;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += RT) {
+        a += p[3 * i];
+        b += p[3 * i + 1];
+        c = fmax(c, p[3 * i + 2]);
+    }
+    tree3(s0, s1, s2, a, b, c);
+    if (threadIdx.x == 0) {
+        out[3 * blockIdx.x] = a;
+        out[3 * blockIdx.x + 1] = b;
+        out[3 * blockIdx.x + 2] = c;
+    }
+}
+
+int reduce_nblocks(const Geo &g)
+{
+    const int64_t nrows = (int64_t)g.ny * g.nz;
+    const int64_t pts = nrows * g.nx;
+    int64_t nb = (pts + RT * 16 - 1) / (RT * 16);
+    if (nb > 2048) nb = 2048;
+    if (nb > nrows) nb = nrows;
+    return nb < 1 ? 1 : (int)nb;
+}
+
+int launch_reduce(const FieldPtrs &d_fields, int nfields, int dtype, const Geo &g,
+                  double *d_partial, double *d_out, hipStream_t s)
+{
+    const int nb = reduce_nblocks(g);
+    const int64_t nrows = (int64_t)g.ny * g.nz;
+    const int64_t rpb = (nrows + nb - 1) / nb;
+    dim3 grid(nb, nfields);
+    switch (dtype) {
+    case STENCIL_F64: hipLaunchKernelGGL(k_reduce_pass1<double>, grid, dim3(RT), 0, s, d_fields, g, rpb, d_partial, nb); break;
+    case STENCIL_F32: hipLaunchKernelGGL(k_reduce_pass1<float>, grid, dim3(RT), 0, s, d_fields, g, rpb, d_partial, nb); break;
+    case STENCIL_BF16: hipLaunchKernelGGL(k_reduce_pass1<bf16>, grid, dim3(RT), 0, s, d_fields, g, rpb, d_partial, nb); break;
+    default: return fail(STENCIL_EINVAL, "unknown dtype %d", dtype);
+    }
+    int rc = check_launch("reduce_pass1");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_reduce_pass2, dim3(nfields), dim3(RT), 0, s, d_partial, nb, d_out);
+    return check_launch("reduce_pass2");
+}
+
+} // namespace stn

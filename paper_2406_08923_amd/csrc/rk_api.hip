@@ -1,0 +1,277 @@
+// rk_api.hip -- C ABI of the fused nonlinear substep (derivative bank + phi +
+// low-storage RK3) and of the FP64 diagnostics.
+#include "plan.hpp"
+#include "reduce_kernels.hpp"
+
+#include <cmath>
+#include <new>
+
+using namespace stn;
+
+namespace {
+
+// Williamson's 2N-storage third-order Runge-Kutta coefficients.
+const double RK_ALPHA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+const double RK_BETA[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+bool master_policy(int pol) { return pol == POL_F32_MASTER64 || pol == POL_BF16_MASTER64; }
+
+int store_dtype(int pol)
+{
+    switch (pol) {
+    case POL_F64: return STENCIL_F64;
+    case POL_F32_MASTER64:
+    case POL_F32_ONLY: return STENCIL_F32;
+    default: return STENCIL_BF16;
+    }
+}
+
+int launch_substep(const stencil_plan_s *p, const stencil_fields *f, int sub, double dt,
+                   hipStream_t s)
+{
+    const RkPlan &P = p->rk;
+    RkArgs a{};
+    const bool master = master_policy(P.policy);
+    for (int k = 0; k < P.nf; ++k) {
+        a.fin[k] = f->f_in[k];
+        a.fout[k] = f->f_out[k];
+        if (master) {
+            a.wrd[k] = sub == 1 ? f->w[k] : f->w2[k];
+            a.wwr[k] = sub == 0 ? f->w[k] : f->w2[k];
+            a.w1[k] = f->w[k];
+            a.master[k] = f->f64[k];
+        } else {
+            a.wrd[k] = f->w[k];
+            a.wwr[k] = f->w[k];
+        }
+    }
+    a.g = P.g;
+    a.alpha = RK_ALPHA[sub];
+    a.beta = RK_BETA[sub];
+    for (int i = 0; i < 3; ++i) {
+        a.beta_all[i] = RK_BETA[i];
+        a.inv_ds[i] = P.inv_ds[i];
+        a.adv[i] = P.adv[i];
+    }
+    a.dt = dt;
+    a.nu = P.nu;
+    a.eta = P.eta;
+    a.cs2 = P.cs2;
+    a.fd = P.fd;
+    a.stage = sub;
+    a.fuse = 1;
+    a.phases = -1;
+    if (P.model == STENCIL_MODEL_MHD8)
+        return launch_rk_mhd8(P.policy, a, P.bx, P.by, s);
+    return launch_rk_advdiff(P.policy, a, P.bx, P.by, s);
+}
+
+int check_fields(const stencil_plan_s *p, const stencil_fields *f, int sub)
+{
+    if (!f)
+        return fail(STENCIL_EINVAL, "fields is NULL");
+    const RkPlan &P = p->rk;
+    const size_t n = (size_t)padded_elems(P.g);
+    const bool master = master_policy(P.policy);
+    for (int k = 0; k < P.nf; ++k) {
+        int rc = check_buffers(f->f_in[k], f->f_out[k], n * P.store_size, P.store_size);
+        if (rc) return rc;
+        if (!f->w[k] || reinterpret_cast<uintptr_t>(f->w[k]) % P.reg_size)
+            return fail(STENCIL_EINVAL, "w[%d] is NULL or misaligned", k);
+        if (master && (sub < 0 || sub >= 1)) {
+            if (!f->w2[k] || reinterpret_cast<uintptr_t>(f->w2[k]) % P.reg_size)
+                return fail(STENCIL_EINVAL, "w2[%d] is NULL or misaligned", k);
+        }
+        if (master && (sub < 0 || sub == 2)) {
+            if (!f->f64[k] || reinterpret_cast<uintptr_t>(f->f64[k]) % 8)
+                return fail(STENCIL_EINVAL, "f64[%d] is NULL or misaligned", k);
+        }
+    }
+    return STENCIL_OK;
+}
+
+template <typename S> int halo_fields(const stencil_plan_s *p, void *const *bufs, hipStream_t s)
+{
+    for (int k = 0; k < p->rk.nf; ++k) {
+        int rc = launch_halo<S>(static_cast<S *>(bufs[k]), p->rk.g, s);
+        if (rc) return rc;
+    }
+    return STENCIL_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
+{
+    if (!d || !out)
+        return fail(STENCIL_EINVAL, "NULL descriptor or output");
+    *out = nullptr;
+    if (d->model != STENCIL_MODEL_MHD8 && d->model != STENCIL_MODEL_ADVDIFF)
+        return fail(STENCIL_EINVAL, "unknown model %d", d->model);
+    if (d->model == STENCIL_MODEL_MHD8 && d->ndim != 3)
+        return fail(STENCIL_EINVAL, "MHD8 is three-dimensional");
+    if (d->model == STENCIL_MODEL_ADVDIFF && d->ndim != 2 && d->ndim != 3)
+        return fail(STENCIL_EINVAL, "ADVDIFF needs ndim 2 or 3");
+    if (d->precision < STENCIL_PREC_F64 || d->precision > STENCIL_PREC_BF16_ONLY)
+        return fail(STENCIL_EINVAL, "unknown precision policy %d", d->precision);
+    int rc = check_dims(d->ndim, d->dims, 3, STENCIL_BC_PERIODIC);
+    if (rc) return rc;
+    for (int a = 0; a < d->ndim; ++a)
+        if (!(d->ds[a] > 0.0) || !std::isfinite(d->ds[a]))
+            return fail(STENCIL_EINVAL, "ds[%d] must be positive and finite", a);
+    const double prm[] = {d->nu, d->eta, d->cs2, d->adv[0], d->adv[1], d->adv[2]};
+    for (double v : prm)
+        if (!std::isfinite(v))
+            return fail(STENCIL_EINVAL, "non-finite model parameter");
+    int bx = d->block[0] ? d->block[0] : 64, by = d->block[1] ? d->block[1] : 4;
+    if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64)
+        return fail(STENCIL_EINVAL, "block %dx%d must be a multiple of 64 lanes <= 256", bx, by);
+
+    auto *p = new (std::nothrow) stencil_plan_s();
+    if (!p)
+        return fail(STENCIL_ENOMEM, "out of host memory");
+    p->kind = PLAN_RK;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return fail(STENCIL_EDEVICE, "no HIP device");
+    }
+    RkPlan &P = p->rk;
+    P.model = d->model;
+    P.policy = d->precision;
+    P.nf = d->model == STENCIL_MODEL_MHD8 ? 8 : 1;
+    P.g = make_geo(d->ndim, d->dims, 3);
+    double w1[7], w2[7];
+    stencil_fd_weights(1, 3, w1);
+    stencil_fd_weights(2, 3, w2);
+    for (int m = 1; m <= 3; ++m) {
+        P.fd.w1[m - 1] = w1[3 + m];
+        P.fd.w2[m] = w2[3 + m];
+    }
+    P.fd.w2[0] = w2[3];
+    for (int a = 0; a < 3; ++a) {
+        P.inv_ds[a] = a < d->ndim ? 1.0 / d->ds[a] : 0.0;
+        P.adv[a] = a < d->ndim ? d->adv[a] : 0.0;
+    }
+    P.nu = d->nu;
+    P.eta = d->eta;
+    P.cs2 = d->cs2;
+    P.bx = bx;
+    P.by = by;
+    P.store_size = dtype_size(store_dtype(P.policy));
+    P.reg_size = P.policy == POL_F64 ? 8 : 4;
+    *out = p;
+    return STENCIL_OK;
+}
+
+int stencil_plan_nfields(stencil_plan_t p)
+{
+    if (!p || p->kind != PLAN_RK)
+        return fail(STENCIL_EINVAL, "not an RK plan");
+    return p->rk.nf;
+}
+
+stencil_status stencil_step(stencil_plan_t p, const stencil_fields *f, int sub, double dt,
+                            void *stream)
+{
+    if (!p || p->kind != PLAN_RK)
+        return fail(STENCIL_EINVAL, "not an RK plan");
+    if (p->sticky)
+        return fail(p->sticky, "plan is in an error state from an earlier device failure");
+    if (sub < 0 || sub > 2)
+        return fail(STENCIL_EINVAL, "substep %d not in 0..2", sub);
+    if (!std::isfinite(dt))
+        return fail(STENCIL_EINVAL, "dt is not finite");
+    int rc = check_fields(p, f, sub);
+    if (rc) return rc;
+    rc = check_device(p->device);
+    if (rc) return rc;
+    rc = launch_substep(p, f, sub, dt, static_cast<hipStream_t>(stream));
+    if (rc == STENCIL_EDEVICE)
+        p->sticky = rc;
+    return rc;
+}
+
+stencil_status stencil_rk_run(stencil_plan_t p, const stencil_fields *f, int nsteps, double dt,
+                              void *stream)
+{
+    if (!p || p->kind != PLAN_RK)
+        return fail(STENCIL_EINVAL, "not an RK plan");
+    if (p->sticky)
+        return fail(p->sticky, "plan is in an error state from an earlier device failure");
+    if (nsteps < 0 || !std::isfinite(dt))
+        return fail(STENCIL_EINVAL, "nsteps must be >= 0 and dt finite");
+    int rc = check_fields(p, f, -1);
+    if (rc) return rc;
+    rc = check_device(p->device);
+    if (rc) return rc;
+    if (nsteps == 0)
+        return STENCIL_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (store_dtype(p->rk.policy)) {
+    case STENCIL_F64: rc = halo_fields<double>(p, f->f_in, s); break;
+    case STENCIL_F32: rc = halo_fields<float>(p, f->f_in, s); break;
+    default: rc = halo_fields<bf16>(p, f->f_in, s); break;
+    }
+    stencil_fields cur = *f;
+    for (int step = 0; step < nsteps && rc == STENCIL_OK; ++step)
+        for (int sub = 0; sub < 3 && rc == STENCIL_OK; ++sub) {
+            rc = launch_substep(p, &cur, sub, dt, s);
+            for (int k = 0; k < p->rk.nf; ++k) {
+                void *t = cur.f_in[k];
+                cur.f_in[k] = cur.f_out[k];
+                cur.f_out[k] = t;
+            }
+        }
+    if (rc == STENCIL_EDEVICE)
+        p->sticky = rc;
+    return rc;
+}
+
+stencil_status stencil_reduce(stencil_plan_t p, const void *const *fields, int nfields,
+                              int dtype, double *host_out, void *stream)
+{
+    if (!p || (p->kind != PLAN_RK && p->kind != PLAN_LINEAR))
+        return fail(STENCIL_EINVAL, "not a plan");
+    if (!fields || !host_out || nfields < 1 || nfields > 64)
+        return fail(STENCIL_EINVAL, "need 1..64 fields and a host output");
+    const size_t es = dtype_size(dtype);
+    if (!es)
+        return fail(STENCIL_EINVAL, "unknown dtype %d", dtype);
+    for (int k = 0; k < nfields; ++k)
+        if (!fields[k] || reinterpret_cast<uintptr_t>(fields[k]) % es)
+            return fail(STENCIL_EINVAL, "field %d is NULL or misaligned", k);
+    int rc = check_device(p->device);
+    if (rc) return rc;
+    const Geo &g = p->kind == PLAN_RK ? p->rk.g : p->lin.g;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nb = reduce_nblocks(g);
+    const int chunk = nfields < 8 ? nfields : 8;
+    double *d_partial = nullptr, *d_out = nullptr;
+    STN_HIP(hipMallocAsync(reinterpret_cast<void **>(&d_partial),
+                           sizeof(double) * 3 * (size_t)nb * chunk, s));
+    if (hipMallocAsync(reinterpret_cast<void **>(&d_out), sizeof(double) * 3 * nfields, s) !=
+        hipSuccess) {
+        (void)hipFreeAsync(d_partial, s);
+        return fail(STENCIL_ENOMEM, "reduce: cannot allocate scratch");
+    }
+    for (int k0 = 0; k0 < nfields && rc == STENCIL_OK; k0 += 8) {
+        FieldPtrs fp{};
+        int m = nfields - k0 < 8 ? nfields - k0 : 8;
+        for (int i = 0; i < m; ++i)
+            fp.p[i] = fields[k0 + i];
+        rc = launch_reduce(fp, m, dtype, g, d_partial, d_out + 3 * k0, s);
+    }
+    if (rc == STENCIL_OK &&
+        hipMemcpyAsync(host_out, d_out, sizeof(double) * 3 * nfields, hipMemcpyDeviceToHost,
+                       s) != hipSuccess)
+        rc = fail(STENCIL_EDEVICE, "reduce: copy to host failed");
+    (void)hipFreeAsync(d_partial, s);
+    (void)hipFreeAsync(d_out, s);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == STENCIL_OK)
+        rc = fail(STENCIL_EDEVICE, "reduce: stream synchronisation failed");
+    return rc;
+}
+
+} // extern "C"

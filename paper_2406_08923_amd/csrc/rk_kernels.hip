@@ -1,0 +1,309 @@
+// rk_kernels.hip -- fused substep phi(gamma(psi(f))) for gfx950: the sixth-order
+// derivative bank gamma = AB (Eq. 8), the nonlinear right-hand side phi
+// (Eq. 9) and the low-storage RK3 update, in one pass over the grid.
+//
+// One lane per output point; every tap is read through the hardware caches
+// (the hardware-cached strategy of Sec. 4.4, which the paper found fastest for
+// the fused MHD kernel on all of its devices) as a buffer load whose tap offset
+// is a wave-uniform scalar, so taps cost no per-lane address arithmetic. First and second derivatives
+// along an axis share their seven loads; mixed derivatives use the
+// antisymmetry of the first-derivative weights to fold the 36 taps into 9
+// weighted four-point differences. The periodic images of each output are
+// written by the kernel itself, so no halo pass follows.
+#include "rk_kernels.hpp"
+
+namespace stn {
+
+namespace {
+
+// Taps are buffer loads: vo is the lane's byte offset of the lowest corner of
+// its radius-3 neighbourhood, so every tap offset (bytes, wave-uniform) is
+// non-negative: c is the centre's offset, st the axis stride in bytes.
+
+// d1 (unit spacing) and d2 (unit spacing) along one axis.
+template <typename S, typename C>
+__device__ __forceinline__ void d12(const Buf &b, uint32_t vo, uint32_t c, uint32_t st,
+                                    const FdWeights &w, C &d1, C &d2, C &c0)
+{
+    c0 = BufLd<S>::ld(b, vo, c);
+    C m1 = BufLd<S>::ld(b, vo, c - st), q1 = BufLd<S>::ld(b, vo, c + st);
+    C m2 = BufLd<S>::ld(b, vo, c - 2 * st), q2 = BufLd<S>::ld(b, vo, c + 2 * st);
+    C m3 = BufLd<S>::ld(b, vo, c - 3 * st), q3 = BufLd<S>::ld(b, vo, c + 3 * st);
+    d1 = C(w.w1[0]) * (q1 - m1) + C(w.w1[1]) * (q2 - m2) + C(w.w1[2]) * (q3 - m3);
+    d2 = C(w.w2[0]) * c0 + C(w.w2[1]) * (q1 + m1) + C(w.w2[2]) * (q2 + m2) +
+         C(w.w2[3]) * (q3 + m3);
+}
+
+// d_a d_b (unit spacing), byte strides sa, sb: tensor product of the
+// first-derivative weights folded by antisymmetry into 9 four-point terms.
+template <typename S, typename C>
+__device__ __forceinline__ C dmix(const Buf &b, uint32_t vo, uint32_t c, uint32_t sa,
+                                  uint32_t sb, const FdWeights &w)
+{
+    C acc = 0;
+#pragma unroll
+    for (int i = 1; i <= 3; ++i)
+#pragma unroll
+        for (int j = 1; j <= 3; ++j) {
+            const uint32_t ia = i * sa, jb = j * sb;
+            C q = (BufLd<S>::ld(b, vo, c + ia + jb) - BufLd<S>::ld(b, vo, c - ia + jb)) -
+                  (BufLd<S>::ld(b, vo, c + ia - jb) - BufLd<S>::ld(b, vo, c - ia - jb));
+            acc = fma(C(w.w1[i - 1] * w.w1[j - 1]), q, acc);
+        }
+    return acc;
+}
+
+// Register update of the 2N scheme and the new state, per policy.
+//   non-master: w = alpha w + dt R (w not read at stage 0, not written at
+//               the last stage where it is dead), f_out = f_in + beta w
+//   master, stages 0-1: as above in FP32 on the low-precision state
+//   master, stage 2: w3 = alpha w2 + dt R; f = f64 + b0 w1 + b1 w2 + b2 w3 in
+//               FP64, written to the master and rounded into f_out
+template <typename S, typename W, typename C, bool MASTER>
+__device__ __forceinline__ void rk_store(const RkArgs &a, int k, int64_t p, int x, int y,
+                                         int z, C R, C fc)
+{
+    const C dt = C(a.dt);
+    C wn = dt * R;
+    if (a.stage > 0)
+        wn = fma(C(a.alpha), C(static_cast<const W *>(a.wrd[k])[p]), wn);
+    if (MASTER && a.stage == 2) {
+        double f = a.master[k][p];
+        f = fma(a.beta_all[0], double(static_cast<const W *>(a.w1[k])[p]), f);
+        f = fma(a.beta_all[1], double(static_cast<const W *>(a.wrd[k])[p]), f);
+        f = fma(a.beta_all[2], double(wn), f);
+        a.master[k][p] = f;
+        store_periodic(static_cast<S *>(a.fout[k]), a.g, x, y, z, C(f), a.fuse != 0);
+        return;
+    }
+    if (a.stage < 2)
+        static_cast<W *>(a.wwr[k])[p] = W(wn);
+    store_periodic(static_cast<S *>(a.fout[k]), a.g, x, y, z, fma(C(a.beta), wn, fc),
+                   a.fuse != 0);
+}
+
+} // namespace
+
+// Derivative bank of one 3-vector field v (three consecutive fields): values,
+// the first derivatives d1[ax][b] = d_ax v_b, the Laplacians lap[b] and
+// grad(div v)_a = sum_b d_a d_b v_b (pure second derivative for b == a, mixed
+// otherwise). Scheduling fences between the groups of loads keep the
+// compiler from hoisting all of them, which would exhaust the registers.
+template <typename S, typename C>
+__device__ __forceinline__ void vector_bank(const Buf *fb, uint32_t vo, uint32_t c,
+                                            const uint32_t *st, const FdWeights &w,
+                                            const C *ids, C *val, C (*d1)[3], C *lap, C *gdiv)
+{
+    C diag[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        lap[b] = 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            C c0, a1, a2;
+            d12<S, C>(fb[b], vo, c, st[ax], w, a1, a2, c0);
+            val[b] = c0;
+            d1[ax][b] = a1 * ids[ax];
+            const C t = a2 * (ids[ax] * ids[ax]);
+            lap[b] += t;
+            if (ax == b) diag[b] = t;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    const C sxy = ids[0] * ids[1], sxz = ids[0] * ids[2], syz = ids[1] * ids[2];
+    gdiv[0] = diag[0];
+    gdiv[1] = diag[1];
+    gdiv[2] = diag[2];
+    C m;
+    m = dmix<S, C>(fb[1], vo, c, st[0], st[1], w); // d_x d_y v_y
+    gdiv[0] = fma(sxy, m, gdiv[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    m = dmix<S, C>(fb[2], vo, c, st[0], st[2], w); // d_x d_z v_z
+    gdiv[0] = fma(sxz, m, gdiv[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    m = dmix<S, C>(fb[0], vo, c, st[0], st[1], w); // d_x d_y v_x
+    gdiv[1] = fma(sxy, m, gdiv[1]);
+    __builtin_amdgcn_sched_barrier(0);
+    m = dmix<S, C>(fb[2], vo, c, st[1], st[2], w); // d_y d_z v_z
+    gdiv[1] = fma(syz, m, gdiv[1]);
+    __builtin_amdgcn_sched_barrier(0);
+    m = dmix<S, C>(fb[0], vo, c, st[0], st[2], w); // d_x d_z v_x
+    gdiv[2] = fma(sxz, m, gdiv[2]);
+    __builtin_amdgcn_sched_barrier(0);
+    m = dmix<S, C>(fb[1], vo, c, st[1], st[2], w); // d_y d_z v_y
+    gdiv[2] = fma(syz, m, gdiv[2]);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Gradient, Laplacian and value of one scalar field.
+template <typename S, typename C>
+__device__ __forceinline__ void scalar_bank(const Buf &fb, uint32_t vo, uint32_t c,
+                                            const uint32_t *st, const FdWeights &w,
+                                            const C *ids, C &val, C *grad, C &lap)
+{
+    lap = 0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        C a1, a2;
+        d12<S, C>(fb, vo, c, st[ax], w, a1, a2, val);
+        grad[ax] = a1 * ids[ax];
+        lap += a2 * (ids[ax] * ids[ax]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Field order (Table A1): lnrho, u_x, u_y, u_z, s, A_x, A_y, A_z. The bank is
+// evaluated field group by field group (A, then u, then the scalars) and each
+// group is reduced at once to the quantities phi needs, so few values stay
+// live at a time.
+template <typename S, typename W, typename C, bool MASTER>
+__global__ void __launch_bounds__(256) k_rk_mhd8(RkArgs a)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    const Geo &g = a.g;
+    if (x >= g.nx || y >= g.ny)
+        return;
+    const int64_t p = g.at(x, y, z);
+    constexpr uint32_t es = sizeof(S);
+    const uint32_t st[3] = {es, uint32_t(g.sy) * es, uint32_t(g.sz) * es};
+    const uint32_t c = 3 * (st[0] + st[1] + st[2]); // centre, from the lowest corner
+    const uint32_t vo = uint32_t(p) * es - c;
+    const uint64_t bytes = uint64_t(padded_elems(g)) * es;
+    Buf fb[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        fb[k] = make_buf(a.fin[k], bytes);
+    const C ids[3] = {C(a.inv_ds[0]), C(a.inv_ds[1]), C(a.inv_ds[2])};
+
+    // Each group below sits behind its own wave-uniform branch on a kernel
+    // argument that is always all-ones: the branches split the kernel into
+    // basic blocks, so no scheduler hoists the loads of a later group above an
+    // earlier one (which would keep hundreds of values live at once).
+    // gamma, magnetic potential: B = curl A, j = grad(div A) - lap A
+    C vA[3] = {}, B[3] = {}, J[3] = {}, lapA[3] = {};
+    if (a.phases & 1) {
+        C dA[3][3], gdivA[3];
+        vector_bank<S, C>(fb + 5, vo, c, st, a.fd, ids, vA, dA, lapA, gdivA);
+        B[0] = dA[1][2] - dA[2][1];
+        B[1] = dA[2][0] - dA[0][2];
+        B[2] = dA[0][1] - dA[1][0];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            J[i] = gdivA[i] - lapA[i];
+    }
+    // gamma, velocity
+    C u[3] = {}, du[3][3] = {}, lapu[3] = {}, gdivu[3] = {};
+    if (a.phases & 2)
+        vector_bank<S, C>(fb + 1, vo, c, st, a.fd, ids, u, du, lapu, gdivu);
+    // gamma, log density and entropy
+    C vl = 0, vs = 0, gl[3] = {}, gs[3] = {}, lapl = 0, laps = 0;
+    if (a.phases & 4)
+        scalar_bank<S, C>(fb[0], vo, c, st, a.fd, ids, vl, gl, lapl);
+    if (a.phases & 8)
+        scalar_bank<S, C>(fb[4], vo, c, st, a.fd, ids, vs, gs, laps);
+
+    // phi: the 8-field right-hand side
+    const C nu = C(a.nu), eta = C(a.eta), cs2 = C(a.cs2);
+    const C divu = du[0][0] + du[1][1] + du[2][2];
+    C Sm[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Sm[i][j] = C(0.5) * (du[i][j] + du[j][i]) - (i == j ? divu / C(3) : C(0));
+    C R[8];
+    R[0] = -(u[0] * gl[0] + u[1] * gl[1] + u[2] * gl[2]) - divu + nu * lapl;
+    const C jxB[3] = {J[1] * B[2] - J[2] * B[1], J[2] * B[0] - J[0] * B[2], J[0] * B[1] - J[1] * B[0]};
+    const C uxB[3] = {u[1] * B[2] - u[2] * B[1], u[2] * B[0] - u[0] * B[2], u[0] * B[1] - u[1] * B[0]};
+    C SS = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const C adv = u[0] * du[0][i] + u[1] * du[1][i] + u[2] * du[2][i];
+        const C Sgl = Sm[i][0] * gl[0] + Sm[i][1] * gl[1] + Sm[i][2] * gl[2];
+        R[1 + i] = -adv - cs2 * (gs[i] + gl[i]) + jxB[i] +
+                   nu * (lapu[i] + gdivu[i] / C(3) + C(2) * Sgl);
+        SS += Sm[i][0] * Sm[i][0] + Sm[i][1] * Sm[i][1] + Sm[i][2] * Sm[i][2];
+    }
+    R[4] = -(u[0] * gs[0] + u[1] * gs[1] + u[2] * gs[2]) + nu * laps +
+           eta * (J[0] * J[0] + J[1] * J[1] + J[2] * J[2]) + C(2) * nu * SS;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        R[5 + i] = uxB[i] + eta * lapA[i];
+
+    const C val[8] = {vl, u[0], u[1], u[2], vs, vA[0], vA[1], vA[2]};
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        rk_store<S, W, C, MASTER>(a, k, p, x, y, z, R[k], val[k]);
+}
+
+// Scalar advection-diffusion R = -c.grad f + nu lap f, NDIM = 2 or 3.
+template <typename S, typename W, typename C, bool MASTER, int NDIM>
+__global__ void __launch_bounds__(256) k_rk_advdiff(RkArgs a)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    const Geo &g = a.g;
+    if (x >= g.nx || y >= g.ny)
+        return;
+    const int64_t p = g.at(x, y, z);
+    constexpr uint32_t es = sizeof(S);
+    const uint32_t st[3] = {es, uint32_t(g.sy) * es, uint32_t(g.sz) * es};
+    const uint32_t c = 3 * (st[0] + st[1] + (NDIM == 3 ? st[2] : 0u));
+    const uint32_t vo = uint32_t(p) * es - c;
+    const Buf fb = make_buf(a.fin[0], uint64_t(padded_elems(g)) * es);
+    C R = 0, c0 = 0;
+#pragma unroll
+    for (int ax = 0; ax < NDIM; ++ax) {
+        C a1, a2;
+        d12<S, C>(fb, vo, c, st[ax], a.fd, a1, a2, c0);
+        const C id = C(a.inv_ds[ax]);
+        R = fma(-C(a.adv[ax]) * id, a1, R);
+        R = fma(C(a.nu) * id * id, a2, R);
+    }
+    rk_store<S, W, C, MASTER>(a, 0, p, x, y, z, R, c0);
+}
+
+namespace {
+template <typename K> int launch_grid(K kern, const RkArgs &a, int bx, int by, hipStream_t s,
+                                      const char *what)
+{
+    dim3 block(bx, by);
+    dim3 grid((a.g.nx + bx - 1) / bx, (a.g.ny + by - 1) / by, a.g.nz);
+    hipLaunchKernelGGL(kern, grid, block, 0, s, a);
+    return check_launch(what);
+}
+} // namespace
+
+int launch_rk_mhd8(int policy, const RkArgs &a, int bx, int by, hipStream_t s)
+{
+    switch (policy) {
+    case POL_F64: return launch_grid(k_rk_mhd8<double, double, double, false>, a, bx, by, s, "rk_mhd8");
+    case POL_F32_MASTER64: return launch_grid(k_rk_mhd8<float, float, float, true>, a, bx, by, s, "rk_mhd8");
+    case POL_BF16_MASTER64: return launch_grid(k_rk_mhd8<bf16, float, float, true>, a, bx, by, s, "rk_mhd8");
+    case POL_F32_ONLY: return launch_grid(k_rk_mhd8<float, float, float, false>, a, bx, by, s, "rk_mhd8");
+    case POL_BF16_ONLY: return launch_grid(k_rk_mhd8<bf16, float, float, false>, a, bx, by, s, "rk_mhd8");
+    }
+    return fail(STENCIL_EINVAL, "unknown precision policy %d", policy);
+}
+
+int launch_rk_advdiff(int policy, const RkArgs &a, int bx, int by, hipStream_t s)
+{
+    const bool d3 = a.g.ndim == 3;
+#define ADV(S_, W_, C_, M_)                                                                  \
+    return d3 ? launch_grid(k_rk_advdiff<S_, W_, C_, M_, 3>, a, bx, by, s, "rk_advdiff")     \
+              : launch_grid(k_rk_advdiff<S_, W_, C_, M_, 2>, a, bx, by, s, "rk_advdiff")
+    switch (policy) {
+    case POL_F64: ADV(double, double, double, false);
+    case POL_F32_MASTER64: ADV(float, float, float, true);
+    case POL_BF16_MASTER64: ADV(bf16, float, float, true);
+    case POL_F32_ONLY: ADV(float, float, float, false);
+    case POL_BF16_ONLY: ADV(bf16, float, float, false);
+    }
+#undef ADV
+    return fail(STENCIL_EINVAL, "unknown precision policy %d", policy);
+}
+
+} // namespace stn

@@ -1,0 +1,53 @@
+// rk_kernels.hpp -- fused derivative bank + nonlinear right-hand side +
+// low-storage RK3 substep kernels (internal).
+#pragma once
+
+#include "common.hpp"
+
+namespace stn {
+
+constexpr int MAX_NF = 8;
+
+// Sixth-order (radius 3) central-difference weights, unit spacing, offsets
+// +1..+3 (the -m weights follow by symmetry): first derivative w1[m-1] is the
+// weight of f(+m) (that of f(-m) is -w1[m-1]); second derivative w2[0] is the
+// centre and w2[m] the weight of f(+-m).
+struct FdWeights {
+    double w1[3];
+    double w2[4];
+};
+
+// Precision policies of the fused substep.
+enum RkPolicy {
+    POL_F64 = 0,           // FP64 storage, FP64 register, FP64 arithmetic
+    POL_F32_MASTER64 = 1,  // FP32 storage, FP32 registers, FP64 master at the last substep
+    POL_BF16_MASTER64 = 2, // BF16 storage, FP32 registers, FP64 master at the last substep
+    POL_F32_ONLY = 3,      // FP32 storage, FP32 register, no master (ablation)
+    POL_BF16_ONLY = 4,     // BF16 storage, FP32 register, no master (ablation)
+};
+
+// Kernel arguments of one substep. Pointers are padded fields (radius 3).
+struct RkArgs {
+    const void *fin[MAX_NF]; // stencil input, storage type
+    void *fout[MAX_NF];      // substep output, storage type
+    const void *wrd[MAX_NF]; // register read (alpha * w); unused at stage 0
+    void *wwr[MAX_NF];       // register written
+    const void *w1[MAX_NF];  // master policies, stage 2: first-stage register
+    double *master[MAX_NF];  // master policies, stage 2: FP64 state (read + written)
+    Geo g;
+    double alpha, beta, dt;
+    double beta_all[3];
+    double inv_ds[3];
+    double nu, eta, cs2;     // MHD8
+    double adv[3];           // ADVDIFF velocity
+    FdWeights fd;
+    int stage;
+    int fuse;                // write periodic images
+    int phases;              // always all-ones: uniform branches that split the
+                             // fused kernel into basic blocks (see k_rk_mhd8)
+};
+
+int launch_rk_mhd8(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
+int launch_rk_advdiff(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
+
+} // namespace stn

@@ -81,7 +81,11 @@ def run_case(dims, r, g, dtype, variant, tile=None, iters=1, seed=1, autotune=Fa
     if dtype != S.F64:
         assert iters == 1
         absconv = O.xcorr(np.abs(O.pad_periodic(inner, r)), r, np.abs(g))
-    assert_close(res, ref, dtype, absconv, ntaps, what="%s r=%d var=%d tile=%s" % (dims, r, variant, tile))
+    what = "%s r=%d var=%d tile=%s" % (dims, r, variant, tile)
+    assert_close(O.interior(res, r), O.interior(ref, r), dtype,
+                 None if absconv is None else O.interior(absconv, r), ntaps, what=what)
+    # the halo written by the library is the exact periodic image of its interior
+    assert np.array_equal(res, O.fill_periodic(res.copy(), r)), what + ": halo"
     return plan
 
 
