@@ -44,6 +44,8 @@ def parse():
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth probe")
     ap.add_argument("--no-secondary", action="store_true", help="headline workload only")
+    ap.add_argument("--serve-jobs", type=int, default=48,
+                    help="jobs in the serving trace (0 skips the serving comparison)")
     return ap.parse_args()
 
 
@@ -196,7 +198,27 @@ def secondary(torch, S, W, inputs, args):
             "ms_per_step": ms,
             "hbm_frac": bytes_step[prec] * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del bufs, plan
+    if args.serve_jobs > 0:
+        out["serving"] = serving(torch, args.serve_jobs)
     return out
+
+
+def serving(torch, count, seed=1):
+    """Seeded Poisson trace (mean 200 jobs/s) of 2-D/3-D radius-3 advection-
+    diffusion jobs, edges {64..384}, 10-500 steps, FP32/FP64 per request:
+    continuous-batching server vs plain FIFO per-job FP64 on the same GPU."""
+    from paper_2406_08923_amd import inputs, serving as SV
+    jobs = inputs.serving_trace(seed, count)
+    inits = SV.make_inits(jobs)
+    served, res_s = SV.run_served(jobs, inits)
+    torch.cuda.synchronize()
+    fifo, res_f = SV.run_fifo_f64(jobs, inits)
+    err = SV.compare(jobs, res_s, res_f)
+    return {"trace": "seed %d, %d jobs, Poisson 200/s, 50%% 3-D, edges 64..384, steps "
+                     "10..500, 50%% FP32 requests" % (seed, count),
+            "served": served, "fifo_f64": fifo, "error_vs_fp64": err,
+            "speedup_point_steps_per_s": served["point_steps_per_s"] / fifo["point_steps_per_s"],
+            "p99_ratio_fifo_over_served": fifo["p99_s"] / served["p99_s"]}
 
 
 def main():

@@ -79,9 +79,12 @@ typedef struct stencil_desc {
     unsigned flags;       /* STENCIL_FLAG_* */
     int variant;          /* STENCIL_VARIANT_* */
     /* launch overrides (all zero = the plan's choice), per variant:
-     *   STAR3D : {lanes along y, rows per lane (1, 2, 4 or 8), z planes per
-     *             workgroup, flags: bit 0 XCD-aware workgroup order, bit 1
-     *             separate halo pass instead of writing periodic images}
+     *   STAR3D : {lanes along y, rows per lane, z planes per workgroup,
+     *             flags: bit 0 XCD-aware workgroup order, bit 1 separate halo
+     *             pass instead of writing periodic images, bit 2 tiles
+     *             numbered fastest along y (else x), bits 4..7 planes
+     *             prefetched ahead (0 = default 2)}; (lanes, rows) one of
+     *             (4,2) (4,4) (8,2) (8,4) (16,2) (2,8), prefetch 2 or 3
      *   GENERIC: {block x, block y} (a multiple of 64 lanes, at most 1024)
      *   LINE1D : {outputs per lane: 1, 2, 4 or 8} */
     int tile[4];
@@ -237,6 +240,104 @@ stencil_status stencil_rk_run(stencil_plan_t plan, const stencil_fields *fields,
  * floating-point atomics). Synchronises the stream. */
 stencil_status stencil_reduce(stencil_plan_t plan, const void *const *fields, int nfields,
                               int dtype, double *host_out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched jobs and the serving loop                                        */
+/* ------------------------------------------------------------------------ */
+
+/* A stencil-integration job: the ADVDIFF model (R = -c.grad f + nu lap f,
+ * sixth-order radius-3 derivatives, Sec. 3.2 with advection added) on a
+ * periodic 2-D or 3-D grid of spacing 2 pi / dims[a], integrated for `steps`
+ * RK3 steps of the fused substep. Jobs run batched: one persistent launch per
+ * substep advances every resident job; a point is computed by the same code as
+ * stencil_step, so a job's result does not depend on the batch it ran in. */
+typedef struct stencil_job {
+    int ndim;           /* 2 or 3 */
+    int dims[3];        /* interior extents, each >= 3 */
+    int steps;          /* RK3 steps, >= 1 */
+    int precision;      /* STENCIL_PREC_F64, STENCIL_PREC_F32_MASTER64 or
+                           STENCIL_PREC_F32_ONLY */
+    double nu;          /* viscosity */
+    double adv[3];      /* velocity c */
+    double dt;          /* time step; <= 0 picks 0.1 ds_min / max(1, max |c|) */
+    const double *init; /* host, interior initial state (x fastest); read when
+                           the job is admitted: keep it valid while the job is
+                           STENCIL_JOB_QUEUED */
+    double *result;     /* host, interior final state in FP64 (the FP64 master
+                           for master policies); written before the job turns
+                           STENCIL_JOB_DONE */
+} stencil_job;
+
+#define STENCIL_JOB_QUEUED 0
+#define STENCIL_JOB_RUNNING 1
+#define STENCIL_JOB_DONE 2
+#define STENCIL_JOB_FAILED 3
+#define STENCIL_JOB_CANCELLED 4
+
+typedef struct stencil_job_status {
+    int state;           /* STENCIL_JOB_* */
+    int error;           /* stencil_status of a FAILED job, else 0 */
+    double t_submit;     /* seconds on the server clock; -1 if not reached */
+    double t_admit;
+    double t_first_tick; /* end of the first tick the job took part in */
+    double t_done;
+    long long steps_done;
+} stencil_job_status;
+
+typedef struct stencil_server_desc {
+    size_t hbm_budget; /* device bytes for resident job state; 0 = 80% of free */
+    int max_slots;     /* jobs resident at once, 1..4096 */
+    int tick_steps;    /* RK steps per tick (>= 1); admission between ticks */
+    int use_graph;     /* replay each tick from one captured hipGraph */
+    int blocks;        /* persistent workgroups per launch; 0 = 8 per CU */
+    int queue_cap;     /* jobs waiting for admission at most; 0 = unlimited */
+} stencil_server_desc;
+
+typedef struct stencil_server_s *stencil_server_t;
+
+typedef struct stencil_server_stats {
+    long long ticks, launches, admitted, completed, failed, cancelled;
+    long long point_steps; /* sum over completed jobs of points x steps */
+    size_t bytes_in_use, bytes_budget;
+    int resident, queued;
+    double busy_s;         /* wall time spent inside ticks */
+} stencil_server_stats;
+
+/* Start a server on the current device: a host thread that admits queued jobs
+ * (first fit, in arrival order) while their state fits the HBM budget and a
+ * slot is free, keeps admitted jobs' fields resident on the device, advances
+ * all of them tick by tick (tick_steps RK steps each) and retires finished
+ * jobs (result copied out, memory freed). Jobs arriving while others run are
+ * admitted at the next tick boundary. */
+stencil_status stencil_server_create(const stencil_server_desc *desc, stencil_server_t *out);
+
+/* Cancel queued and running jobs, stop the thread and free everything.
+ * NULL is accepted. */
+stencil_status stencil_server_destroy(stencil_server_t server);
+
+/* Queue a job (descriptor copied; init and result pointers kept). Returns
+ * STENCIL_EAGAIN when queue_cap jobs are already waiting, STENCIL_EINVAL for a
+ * bad descriptor, STENCIL_EDEVICE after a device failure of the server. A job
+ * larger than the whole budget fails at admission with STENCIL_ENOMEM. */
+stencil_status stencil_submit(stencil_server_t server, const stencil_job *job, uint64_t *ticket);
+
+/* Current status of a job (non-blocking). */
+stencil_status stencil_poll(stencil_server_t server, uint64_t ticket, stencil_job_status *st);
+
+/* Wait until the job is DONE, FAILED or CANCELLED, or timeout_ms passes
+ * (negative: no limit; STENCIL_ETIMEOUT on expiry). */
+stencil_status stencil_wait(stencil_server_t server, uint64_t ticket, stencil_job_status *st,
+                            int timeout_ms);
+
+/* Cancel a queued or running job (a running job stops at the next tick
+ * boundary; its result is not written). */
+stencil_status stencil_cancel(stencil_server_t server, uint64_t ticket);
+
+/* Counters of the server. */
+stencil_status stencil_server_stats_get(stencil_server_t server, stencil_server_stats *st);
+
+/* Seconds since the server started, on the clock of the job timestamps. */
+double stencil_server_clock(stencil_server_t server);
 
 #ifdef __cplusplus
 }

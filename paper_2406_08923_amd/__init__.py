@@ -74,6 +74,7 @@ def _declare(L):
     L.stencil_copy.argtypes = [_vp, _vp, c_size, _vp]
     L.stencil_fd_weights.argtypes = [c_int, c_int, ctypes.POINTER(ctypes.c_double)]
     _declare_rk(L)
+    _declare_server(L)
 
 
 def check(rc):
@@ -320,6 +321,136 @@ class RkPlan:
     def close(self):
         if getattr(self, "_h", None):
             lib().stencil_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# batched jobs and the serving loop
+# ---------------------------------------------------------------------------
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELLED = range(5)
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int * 3), ("steps", ctypes.c_int),
+                ("precision", ctypes.c_int), ("nu", ctypes.c_double),
+                ("adv", ctypes.c_double * 3), ("dt", ctypes.c_double),
+                ("init", ctypes.POINTER(ctypes.c_double)),
+                ("result", ctypes.POINTER(ctypes.c_double))]
+
+
+class _JobStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("error", ctypes.c_int), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_first_tick", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("steps_done", ctypes.c_longlong)]
+
+
+class _ServerDesc(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int),
+                ("tick_steps", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("blocks", ctypes.c_int), ("queue_cap", ctypes.c_int)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_longlong), ("launches", ctypes.c_longlong),
+                ("admitted", ctypes.c_longlong), ("completed", ctypes.c_longlong),
+                ("failed", ctypes.c_longlong), ("cancelled", ctypes.c_longlong),
+                ("point_steps", ctypes.c_longlong), ("bytes_in_use", ctypes.c_size_t),
+                ("bytes_budget", ctypes.c_size_t), ("resident", ctypes.c_int),
+                ("queued", ctypes.c_int), ("busy_s", ctypes.c_double)]
+
+
+def _declare_server(L):
+    u64 = ctypes.c_uint64
+    L.stencil_server_create.argtypes = [ctypes.POINTER(_ServerDesc), ctypes.POINTER(_vp)]
+    L.stencil_server_destroy.argtypes = [_vp]
+    L.stencil_submit.argtypes = [_vp, ctypes.POINTER(_Job), ctypes.POINTER(u64)]
+    L.stencil_poll.argtypes = [_vp, u64, ctypes.POINTER(_JobStatus)]
+    L.stencil_wait.argtypes = [_vp, u64, ctypes.POINTER(_JobStatus), ctypes.c_int]
+    L.stencil_cancel.argtypes = [_vp, u64]
+    L.stencil_server_stats_get.argtypes = [_vp, ctypes.POINTER(_ServerStats)]
+    L.stencil_server_clock.argtypes = [_vp]
+    L.stencil_server_clock.restype = ctypes.c_double
+
+
+def _status_dict(s):
+    return {"state": s.state, "error": s.error, "t_submit": s.t_submit, "t_admit": s.t_admit,
+            "t_first_tick": s.t_first_tick, "t_done": s.t_done, "steps_done": s.steps_done}
+
+
+class Server:
+    """Continuous-batching server of scalar advection-diffusion jobs. Initial
+    states and result arrays are NumPy float64 interiors ([z,] y, x order);
+    they are kept referenced until the job ends."""
+
+    def __init__(self, hbm_budget=0, max_slots=256, tick_steps=10, use_graph=True, blocks=0,
+                 queue_cap=0):
+        L = lib()
+        d = _ServerDesc(hbm_budget, max_slots, tick_steps, 1 if use_graph else 0, blocks,
+                        queue_cap)
+        h = _vp()
+        check(L.stencil_server_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, init, steps, precision=PREC_F64, nu=1e-3, adv=(0.0, 0.0, 0.0), dt=0.0,
+               result=None):
+        init = np.ascontiguousarray(init, dtype=np.float64)
+        nd = init.ndim
+        if result is None:
+            result = np.empty_like(init)
+        j = _Job()
+        j.ndim = nd
+        j.dims = _dims3([init.shape[nd - 1 - k] for k in range(nd)])
+        j.steps = int(steps)
+        j.precision = precision
+        j.nu = nu
+        j.adv = (ctypes.c_double * 3)(*(list(adv) + [0.0] * (3 - len(adv))))
+        j.dt = dt
+        j.init = init.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        j.result = result.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        t = ctypes.c_uint64()
+        check(lib().stencil_submit(self._h, ctypes.byref(j), ctypes.byref(t)))
+        self._keep[t.value] = (init, result)
+        return t.value
+
+    def result(self, ticket):
+        return self._keep[ticket][1]
+
+    def poll(self, ticket):
+        s = _JobStatus()
+        check(lib().stencil_poll(self._h, ticket, ctypes.byref(s)))
+        return _status_dict(s)
+
+    def wait(self, ticket, timeout_ms=-1):
+        s = _JobStatus()
+        rc = lib().stencil_wait(self._h, ticket, ctypes.byref(s), int(timeout_ms))
+        if rc not in (0, -7):
+            check(rc)
+        d = _status_dict(s)
+        d["timed_out"] = rc == -7
+        return d
+
+    def cancel(self, ticket):
+        check(lib().stencil_cancel(self._h, ticket))
+
+    def stats(self):
+        s = _ServerStats()
+        check(lib().stencil_server_stats_get(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _ServerStats._fields_}
+
+    def clock(self):
+        return lib().stencil_server_clock(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().stencil_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -1,0 +1,63 @@
+// batch.hpp -- device job table and launchers of the batched substep kernel
+// (internal).
+#pragma once
+
+#include "rk_point.hpp"
+
+namespace stn {
+
+// One resident job of the batch: a scalar advection-diffusion field (2-D or
+// 3-D, radius-3 periodic padding) integrated with the fused RK3 substep.
+struct BatchJob {
+    void *f[2];     // state buffers (storage type), used in ping-pong
+    void *w;        // register (FP64 for POL_F64, FP32 otherwise)
+    void *w2;       // second register (master policies)
+    double *f64;    // FP64 master state (master policies)
+    Geo g;
+    FdWeights fd;
+    double inv_ds[3], adv[3], nu, dt;
+    int policy;     // RkPolicy
+    int steps;      // RK steps to take in this tick
+    int parity;     // index of the buffer holding the state when the tick starts
+    int tiles_x, tiles_y;
+    int tile_begin; // first work item of the job
+};
+
+// Work items are tiles of BT_X x BT_Y points of one plane, one lane per point.
+constexpr int BT_X = 64, BT_Y = 4;
+
+struct BatchTableHeader {
+    int njobs;
+    int total_tiles;
+    int pad[2];
+};
+
+// Table = header followed by njobs BatchJob records (device memory).
+inline size_t batch_table_bytes(int njobs)
+{
+    return sizeof(BatchTableHeader) + sizeof(BatchJob) * (size_t)njobs;
+}
+
+// RK coefficients passed by value (alpha_i, beta_i of substeps 0..2).
+struct RkCoeffs {
+    double alpha[3], beta[3];
+};
+
+// The RK3 scheme's coefficients (defined with the C ABI of the fused substep).
+RkCoeffs rk3_coeffs();
+
+// One substep (sub = 3 * step + stage within the tick) of every job whose
+// step < steps, by a persistent grid of `blocks` workgroups walking the items.
+int launch_batch_substep(const void *d_table, int sub, const RkCoeffs &rk, int blocks,
+                         hipStream_t s);
+
+// Copy a contiguous FP64 interior (x fastest) into a padded state buffer of
+// storage type per policy (and into the FP64 master for master policies),
+// then refresh the periodic halo of the state buffer.
+int launch_job_upload(const double *src, const BatchJob &j, int which, hipStream_t s);
+
+// Copy the interior of the job's state (the FP64 master for master policies)
+// into a contiguous FP64 array.
+int launch_job_download(const BatchJob &j, int which, double *dst, hipStream_t s);
+
+} // namespace stn

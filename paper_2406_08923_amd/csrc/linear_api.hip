@@ -109,8 +109,8 @@ template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out
     switch (p->lin.variant) {
     case STENCIL_VARIANT_STAR3D: {
         int fl = p->lin.sflags | (periodic ? 0 : STAR_FLAG_NOFUSE);
-        rc = launch_star3d<S>(in, out, p->lin.g, p->lin.star, p->lin.reff, p->lin.ty,
-                              p->lin.ny, p->lin.lz, fl, s);
+        rc = launch_star3d(in, out, p->lin.g, p->lin.star, p->lin.reff, p->lin.ty, p->lin.ny,
+                           p->lin.pf, p->lin.lz, fl & 7, s);
         if (rc == STENCIL_OK && periodic && (p->lin.sflags & STAR_FLAG_NOFUSE))
             rc = launch_halo<S>(out, p->lin.g, s);
         return rc;
@@ -165,7 +165,9 @@ void set_choice(stencil_plan_s *p, const TuneChoice &c)
         p->lin.ty = c.p0;
         p->lin.ny = c.p1;
         p->lin.lz = c.p2;
-        p->lin.sflags = c.p3;
+        p->lin.sflags = c.p3 & 7;
+        const int pf = (c.p3 >> STAR_PF_SHIFT) & 15;
+        p->lin.pf = pf ? pf : 2;
     } else if (c.variant == STENCIL_VARIANT_LINE1D) {
         p->lin.e1d = c.p0;
     } else {
@@ -179,15 +181,21 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
     std::vector<TuneChoice> c;
     const Geo &g = p->lin.g;
     if (p->lin.is_star) {
-        const int shapes[][2] = {{4, 1}, {4, 2}, {4, 4}, {8, 2}, {2, 4}, {8, 1}, {2, 8}};
-        const int lzs[] = {32, 64, 128, 256};
+        const int shapes[][2] = {{4, 2}, {4, 4}, {8, 2}, {8, 4}, {16, 2}, {2, 8}};
+        const int lzs[] = {32, 64, 128, 256, g.nz};
         for (auto &sh : shapes)
-            for (int lz : lzs) {
-                if (lz > 2 * g.nz && lz != 32)
-                    continue;
-                c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, STAR_FLAG_XCD});
-                c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, 0});
-            }
+            for (int pf : {2, 3})
+                for (int k = 0; k < 5; ++k) {
+                    const int lz = lzs[k];
+                    if ((k < 4 && lz >= g.nz && lz != 32) || (k == 4 && g.nz <= 32))
+                        continue;
+                    const int w = (pf << STAR_PF_SHIFT);
+                    c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, w | STAR_FLAG_XCD});
+                    c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz,
+                                 w | STAR_FLAG_XCD | STAR_FLAG_YFIRST});
+                    if (lz == 64)
+                        c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, w});
+                }
     }
     if (g.ndim == 1)
         for (int e : {1, 2, 4, 8})
@@ -205,7 +213,7 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
 TuneChoice default_choice(const stencil_plan_s *p)
 {
     if (p->lin.is_star)
-        return {STENCIL_VARIANT_STAR3D, 4, 4, 64, STAR_FLAG_XCD};
+        return {STENCIL_VARIANT_STAR3D, 8, 2, 64, STAR_FLAG_XCD | (2 << STAR_PF_SHIFT)};
     if (p->lin.g.ndim == 1)
         return {STENCIL_VARIANT_LINE1D, 4, 0, 0, 0};
     return {STENCIL_VARIANT_GENERIC, 64, 4, 0, 0};
@@ -424,7 +432,7 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
             if (t[0]) c.p0 = t[0];
             if (t[1]) c.p1 = t[1];
             if (t[2]) c.p2 = t[2];
-            c.p3 = t[3] & 3; // explicit tiles set the flag word exactly
+            c.p3 = t[3] & 0xf7; // explicit tiles set the flag word exactly
         } else if (c.variant == STENCIL_VARIANT_LINE1D) {
             if (t[0]) c.p0 = t[0];
         } else {
@@ -480,7 +488,7 @@ stencil_status stencil_plan_tile(stencil_plan_t p, int tile[4])
         tile[0] = L.ty;
         tile[1] = L.ny;
         tile[2] = L.lz;
-        tile[3] = L.sflags;
+        tile[3] = L.sflags | (L.pf << STAR_PF_SHIFT);
     } else if (L.variant == STENCIL_VARIANT_LINE1D) {
         tile[0] = L.e1d;
     } else {

@@ -36,9 +36,11 @@ struct StarCoefAny {
     }
 };
 
-// star kernel flags
+// star kernel flags (the tile[3] word of stencil_desc)
 constexpr int STAR_FLAG_XCD = 1;    // XCD-aware workgroup order
 constexpr int STAR_FLAG_NOFUSE = 2; // do not write periodic images
+constexpr int STAR_FLAG_YFIRST = 4; // tile numbers run fastest along y
+constexpr int STAR_PF_SHIFT = 4;    // bits 4..7: prefetch depth (0 = default)
 
 template <typename S> int launch_halo(S *a, const Geo &g, hipStream_t s);
 
@@ -47,9 +49,16 @@ int launch_generic(const S *in, S *out, const Geo &g, const int *offs,
                    const typename Store<S>::C *cs, int ntaps, bool fuse, int bx, int by,
                    hipStream_t s);
 
-template <typename S>
-int launch_star3d(const S *in, S *out, const Geo &g, const StarCoefAny &cf, int R, int ty,
-                  int ny, int lz, int flags, hipStream_t s);
+// 3-D star kernel (star3d.hpp), one overload per storage type (star3d_*.hip).
+// R: tap radius (<= padding); ty, ny: tile shape; pf: prefetch depth; lz: z
+// planes per workgroup; flags: STAR_FLAG_*.
+#define STAR_DECL(S)                                                                         \
+    int launch_star3d(const S *in, S *out, const Geo &g, const StarCoefAny &cf, int R, int ty, \
+                      int ny, int pf, int lz, int flags, hipStream_t s);
+STAR_DECL(double)
+STAR_DECL(float)
+STAR_DECL(bf16)
+#undef STAR_DECL
 
 template <typename S>
 int launch_line1d(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs, bool fuse,

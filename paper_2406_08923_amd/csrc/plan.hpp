@@ -22,7 +22,7 @@ struct LinearPlan {
     void *d_dense = nullptr; // 1-D dense coefficients, arithmetic type
     // chosen variant and its launch parameters
     int variant = STENCIL_VARIANT_GENERIC;
-    int ty = 4, ny = 4, lz = 64, sflags = 0; // STAR3D
+    int ty = 8, ny = 2, lz = 64, sflags = 0, pf = 2; // STAR3D
     int gbx = 64, gby = 4;                   // GENERIC
     int e1d = 4;                             // LINE1D
 };

@@ -1,5 +1,6 @@
 // rk_api.hip -- C ABI of the fused nonlinear substep (derivative bank + phi +
 // low-storage RK3) and of the FP64 diagnostics.
+#include "batch.hpp"
 #include "plan.hpp"
 #include "reduce_kernels.hpp"
 
@@ -13,6 +14,22 @@ namespace {
 // Williamson's 2N-storage third-order Runge-Kutta coefficients.
 const double RK_ALPHA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 const double RK_BETA[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+} // namespace
+
+namespace stn {
+RkCoeffs rk3_coeffs()
+{
+    RkCoeffs c;
+    for (int i = 0; i < 3; ++i) {
+        c.alpha[i] = RK_ALPHA[i];
+        c.beta[i] = RK_BETA[i];
+    }
+    return c;
+}
+} // namespace stn
+
+namespace {
 
 bool master_policy(int pol) { return pol == POL_F32_MASTER64 || pol == POL_BF16_MASTER64; }
 

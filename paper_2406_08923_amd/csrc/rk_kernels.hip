@@ -10,76 +10,28 @@
 // antisymmetry of the first-derivative weights to fold the 36 taps into 9
 // weighted four-point differences. The periodic images of each output are
 // written by the kernel itself, so no halo pass follows.
-#include "rk_kernels.hpp"
+#include "rk_point.hpp"
 
 namespace stn {
 
 namespace {
 
-// Taps are buffer loads: vo is the lane's byte offset of the lowest corner of
-// its radius-3 neighbourhood, so every tap offset (bytes, wave-uniform) is
-// non-negative: c is the centre's offset, st the axis stride in bytes.
-
-// d1 (unit spacing) and d2 (unit spacing) along one axis.
-template <typename S, typename C>
-__device__ __forceinline__ void d12(const Buf &b, uint32_t vo, uint32_t c, uint32_t st,
-                                    const FdWeights &w, C &d1, C &d2, C &c0)
+// PointIO of field k of a substep
+__device__ __forceinline__ PointIO point_io(const RkArgs &a, int k)
 {
-    c0 = BufLd<S>::ld(b, vo, c);
-    C m1 = BufLd<S>::ld(b, vo, c - st), q1 = BufLd<S>::ld(b, vo, c + st);
-    C m2 = BufLd<S>::ld(b, vo, c - 2 * st), q2 = BufLd<S>::ld(b, vo, c + 2 * st);
-    C m3 = BufLd<S>::ld(b, vo, c - 3 * st), q3 = BufLd<S>::ld(b, vo, c + 3 * st);
-    d1 = C(w.w1[0]) * (q1 - m1) + C(w.w1[1]) * (q2 - m2) + C(w.w1[2]) * (q3 - m3);
-    d2 = C(w.w2[0]) * c0 + C(w.w2[1]) * (q1 + m1) + C(w.w2[2]) * (q2 + m2) +
-         C(w.w2[3]) * (q3 + m3);
-}
-
-// d_a d_b (unit spacing), byte strides sa, sb: tensor product of the
-// first-derivative weights folded by antisymmetry into 9 four-point terms.
-template <typename S, typename C>
-__device__ __forceinline__ C dmix(const Buf &b, uint32_t vo, uint32_t c, uint32_t sa,
-                                  uint32_t sb, const FdWeights &w)
-{
-    C acc = 0;
-#pragma unroll
-    for (int i = 1; i <= 3; ++i)
-#pragma unroll
-        for (int j = 1; j <= 3; ++j) {
-            const uint32_t ia = i * sa, jb = j * sb;
-            C q = (BufLd<S>::ld(b, vo, c + ia + jb) - BufLd<S>::ld(b, vo, c - ia + jb)) -
-                  (BufLd<S>::ld(b, vo, c + ia - jb) - BufLd<S>::ld(b, vo, c - ia - jb));
-            acc = fma(C(w.w1[i - 1] * w.w1[j - 1]), q, acc);
-        }
-    return acc;
-}
-
-// Register update of the 2N scheme and the new state, per policy.
-//   non-master: w = alpha w + dt R (w not read at stage 0, not written at
-//               the last stage where it is dead), f_out = f_in + beta w
-//   master, stages 0-1: as above in FP32 on the low-precision state
-//   master, stage 2: w3 = alpha w2 + dt R; f = f64 + b0 w1 + b1 w2 + b2 w3 in
-//               FP64, written to the master and rounded into f_out
-template <typename S, typename W, typename C, bool MASTER>
-__device__ __forceinline__ void rk_store(const RkArgs &a, int k, int64_t p, int x, int y,
-                                         int z, C R, C fc)
-{
-    const C dt = C(a.dt);
-    C wn = dt * R;
-    if (a.stage > 0)
-        wn = fma(C(a.alpha), C(static_cast<const W *>(a.wrd[k])[p]), wn);
-    if (MASTER && a.stage == 2) {
-        double f = a.master[k][p];
-        f = fma(a.beta_all[0], double(static_cast<const W *>(a.w1[k])[p]), f);
-        f = fma(a.beta_all[1], double(static_cast<const W *>(a.wrd[k])[p]), f);
-        f = fma(a.beta_all[2], double(wn), f);
-        a.master[k][p] = f;
-        store_periodic(static_cast<S *>(a.fout[k]), a.g, x, y, z, C(f), a.fuse != 0);
-        return;
-    }
-    if (a.stage < 2)
-        static_cast<W *>(a.wwr[k])[p] = W(wn);
-    store_periodic(static_cast<S *>(a.fout[k]), a.g, x, y, z, fma(C(a.beta), wn, fc),
-                   a.fuse != 0);
+    PointIO io;
+    io.fout = a.fout[k];
+    io.wrd = a.wrd[k];
+    io.wwr = a.wwr[k];
+    io.w1 = a.w1[k];
+    io.master = a.master[k];
+    io.alpha = a.alpha;
+    io.beta = a.beta;
+    io.dt = a.dt;
+    for (int i = 0; i < 3; ++i) io.beta_all[i] = a.beta_all[i];
+    io.stage = a.stage;
+    io.fuse = a.fuse;
+    return io;
 }
 
 } // namespace
@@ -235,7 +187,7 @@ __global__ void __launch_bounds__(256) k_rk_mhd8(RkArgs a)
     const C val[8] = {vl, u[0], u[1], u[2], vs, vA[0], vA[1], vA[2]};
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-        rk_store<S, W, C, MASTER>(a, k, p, x, y, z, R[k], val[k]);
+        rk_update<S, W, C, MASTER>(point_io(a, k), g, p, x, y, z, R[k], val[k]);
 }
 
 // Scalar advection-diffusion R = -c.grad f + nu lap f, NDIM = 2 or 3.
@@ -248,22 +200,8 @@ __global__ void __launch_bounds__(256) k_rk_advdiff(RkArgs a)
     const Geo &g = a.g;
     if (x >= g.nx || y >= g.ny)
         return;
-    const int64_t p = g.at(x, y, z);
-    constexpr uint32_t es = sizeof(S);
-    const uint32_t st[3] = {es, uint32_t(g.sy) * es, uint32_t(g.sz) * es};
-    const uint32_t c = 3 * (st[0] + st[1] + (NDIM == 3 ? st[2] : 0u));
-    const uint32_t vo = uint32_t(p) * es - c;
-    const Buf fb = make_buf(a.fin[0], uint64_t(padded_elems(g)) * es);
-    C R = 0, c0 = 0;
-#pragma unroll
-    for (int ax = 0; ax < NDIM; ++ax) {
-        C a1, a2;
-        d12<S, C>(fb, vo, c, st[ax], a.fd, a1, a2, c0);
-        const C id = C(a.inv_ds[ax]);
-        R = fma(-C(a.adv[ax]) * id, a1, R);
-        R = fma(C(a.nu) * id * id, a2, R);
-    }
-    rk_store<S, W, C, MASTER>(a, 0, p, x, y, z, R, c0);
+    advdiff_point<S, W, C, MASTER, NDIM>(a.fin[0], point_io(a, 0), g, a.fd, a.inv_ds, a.adv, a.nu,
+                                         x, y, z);
 }
 
 namespace {

@@ -1,0 +1,600 @@
+// server.hip -- continuous-batching server for stencil-integration jobs.
+//
+// One host thread per server owns a HIP stream (default priority) and loops:
+//   1. admit queued jobs, first fit in arrival order, while their resident
+//      state fits the free HBM budget and a slot is free; allocate their
+//      fields and upload the initial state;
+//   2. run one tick: upload the job table, then tick_steps x 3 substeps of the
+//      persistent batched kernel (replayed from a captured hipGraph whose
+//      launches do not depend on the job set), and wait for it;
+//   3. retire jobs whose steps are done (result copied to the host, memory
+//      freed) and cancelled jobs.
+// Jobs arriving while a tick runs wait at most one tick for admission. A device
+// error fails the running jobs and latches the server.
+#include "batch.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+using namespace stn;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct SJob {
+    uint64_t ticket = 0;
+    stencil_job d{};
+    int state = STENCIL_JOB_QUEUED;
+    int error = 0;
+    double t_submit = -1, t_admit = -1, t_first = -1, t_done = -1;
+    long long steps_done = 0;
+    bool cancel = false;
+    size_t bytes = 0;
+    BatchJob bj{};
+    int steps_tick = 0;
+};
+
+size_t job_bytes(const stencil_job &j)
+{
+    size_t pad = 1;
+    for (int a = 0; a < j.ndim; ++a) pad *= (size_t)j.dims[a] + 6;
+    // f (two buffers), registers, master
+    if (j.precision == STENCIL_PREC_F64) return pad * (8 + 8 + 8);
+    if (j.precision == STENCIL_PREC_F32_MASTER64) return pad * (4 + 4 + 4 + 4 + 8);
+    return pad * (4 + 4 + 4);
+}
+
+int check_job(const stencil_job *j)
+{
+    if (!j)
+        return fail(STENCIL_EINVAL, "job is NULL");
+    if (j->ndim != 2 && j->ndim != 3)
+        return fail(STENCIL_EINVAL, "job ndim must be 2 or 3");
+    for (int a = 0; a < j->ndim; ++a)
+        if (j->dims[a] < 3 || j->dims[a] > 65536)
+            return fail(STENCIL_EINVAL, "job dims[%d] = %d out of range", a, j->dims[a]);
+    if (j->steps < 1)
+        return fail(STENCIL_EINVAL, "job steps must be >= 1");
+    if (j->precision != STENCIL_PREC_F64 && j->precision != STENCIL_PREC_F32_MASTER64 &&
+        j->precision != STENCIL_PREC_F32_ONLY)
+        return fail(STENCIL_EINVAL, "job precision must be F64, F32_MASTER64 or F32_ONLY");
+    if (!std::isfinite(j->nu) || !std::isfinite(j->dt) || !std::isfinite(j->adv[0]) ||
+        !std::isfinite(j->adv[1]) || !std::isfinite(j->adv[2]))
+        return fail(STENCIL_EINVAL, "job parameters must be finite");
+    if (!j->init || !j->result)
+        return fail(STENCIL_EINVAL, "job init and result must be host pointers");
+    size_t pad = 1;
+    for (int a = 0; a < j->ndim; ++a) pad *= (size_t)j->dims[a] + 6;
+    if (pad * 8 >= (size_t(1) << 32))
+        return fail(STENCIL_EINVAL, "job grid too large (padded state must stay below 4 GiB)");
+    return STENCIL_OK;
+}
+
+} // namespace
+
+struct stencil_server_s {
+    stencil_server_desc d{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    int sticky = 0;
+    std::deque<std::shared_ptr<SJob>> queue;
+    std::vector<std::shared_ptr<SJob>> active; // worker thread only
+    std::unordered_map<uint64_t, std::shared_ptr<SJob>> jobs;
+    uint64_t next_ticket = 1;
+    size_t used = 0;
+    std::chrono::steady_clock::time_point t0;
+    void *d_table = nullptr, *h_table = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    RkCoeffs rk{};
+    stencil_server_stats st{};
+    FdWeights fd{};
+
+    double clock() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    // --- worker side -------------------------------------------------------
+
+    void free_job(SJob &j)
+    {
+        void *bufs[] = {j.bj.f[0], j.bj.f[1], j.bj.w, j.bj.w2, j.bj.f64};
+        for (void *b : bufs)
+            if (b) (void)hipFree(b);
+        j.bj.f[0] = j.bj.f[1] = j.bj.w = j.bj.w2 = nullptr;
+        j.bj.f64 = nullptr;
+    }
+
+    void finish(const std::shared_ptr<SJob> &j, int state, int err)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        j->state = state;
+        j->error = err;
+        j->t_done = clock();
+        used -= j->bytes;
+        if (state == STENCIL_JOB_DONE) {
+            st.completed++;
+            size_t pts = 1;
+            for (int a = 0; a < j->d.ndim; ++a) pts *= (size_t)j->d.dims[a];
+            st.point_steps += (long long)pts * j->d.steps;
+        } else if (state == STENCIL_JOB_FAILED) {
+            st.failed++;
+        } else {
+            st.cancelled++;
+        }
+        cv_done.notify_all();
+    }
+
+    // allocate and upload one admitted job; returns a status
+    int start_job(SJob &j)
+    {
+        const stencil_job &d = j.d;
+        BatchJob &b = j.bj;
+        b.g = make_geo(d.ndim, d.dims, 3);
+        b.fd = fd;
+        double dsmin = 1e300;
+        for (int a = 0; a < 3; ++a) {
+            const double ds = a < d.ndim ? 2.0 * kPi / d.dims[a] : 1.0;
+            b.inv_ds[a] = a < d.ndim ? 1.0 / ds : 0.0;
+            b.adv[a] = a < d.ndim ? d.adv[a] : 0.0;
+            if (a < d.ndim) dsmin = std::min(dsmin, ds);
+        }
+        double cmax = 1.0;
+        for (int a = 0; a < d.ndim; ++a) cmax = std::max(cmax, std::fabs(d.adv[a]));
+        b.nu = d.nu;
+        b.dt = d.dt > 0 ? d.dt : 0.1 * dsmin / cmax;
+        b.policy = d.precision == STENCIL_PREC_F64 ? POL_F64
+                   : d.precision == STENCIL_PREC_F32_MASTER64 ? POL_F32_MASTER64
+                                                              : POL_F32_ONLY;
+        b.parity = 0;
+        const size_t pad = (size_t)padded_elems(b.g);
+        const size_t es = b.policy == POL_F64 ? 8 : 4;
+        bool ok = hipMalloc(&b.f[0], pad * es) == hipSuccess &&
+                  hipMalloc(&b.f[1], pad * es) == hipSuccess &&
+                  hipMalloc(&b.w, pad * es) == hipSuccess;
+        if (ok && b.policy == POL_F32_MASTER64)
+            ok = hipMalloc(&b.w2, pad * 4) == hipSuccess &&
+                 hipMalloc(reinterpret_cast<void **>(&b.f64), pad * 8) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            free_job(j);
+            return STENCIL_ENOMEM;
+        }
+        const size_t n = pad ? (size_t)b.g.nx * b.g.ny * b.g.nz : 0;
+        double *stage = nullptr;
+        if (hipMallocAsync(reinterpret_cast<void **>(&stage), n * 8, stream) != hipSuccess) {
+            (void)hipGetLastError();
+            free_job(j);
+            return STENCIL_ENOMEM;
+        }
+        int rc = STENCIL_OK;
+        if (hipMemcpyAsync(stage, d.init, n * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
+            rc = STENCIL_EDEVICE;
+        if (!rc)
+            rc = launch_job_upload(stage, b, 0, stream);
+        (void)hipFreeAsync(stage, stream);
+        if (!rc && hipStreamSynchronize(stream) != hipSuccess)
+            rc = STENCIL_EDEVICE;
+        if (rc)
+            free_job(j);
+        return rc;
+    }
+
+    int download_job(SJob &j)
+    {
+        const BatchJob &b = j.bj;
+        const size_t n = (size_t)b.g.nx * b.g.ny * b.g.nz;
+        double *stage = nullptr;
+        if (hipMallocAsync(reinterpret_cast<void **>(&stage), n * 8, stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return STENCIL_ENOMEM;
+        }
+        int rc = launch_job_download(b, b.parity, stage, stream);
+        if (!rc && hipMemcpyAsync(j.d.result, stage, n * 8, hipMemcpyDeviceToHost, stream) !=
+                       hipSuccess)
+            rc = STENCIL_EDEVICE;
+        (void)hipFreeAsync(stage, stream);
+        if (hipStreamSynchronize(stream) != hipSuccess && !rc)
+            rc = STENCIL_EDEVICE;
+        return rc;
+    }
+
+    int capture_graph()
+    {
+        const int nsub = 3 * d.tick_steps;
+        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return STENCIL_EDEVICE;
+        int rc = STENCIL_OK;
+        for (int s = 0; s < nsub && !rc; ++s)
+            rc = launch_batch_substep(d_table, s, rk, d.blocks, stream);
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(stream, &g) != hipSuccess || rc) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return STENCIL_EDEVICE;
+        }
+        if (hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return STENCIL_EDEVICE;
+        }
+        graph = g;
+        return STENCIL_OK;
+    }
+
+    // one tick over the active set; returns a status, *launches the number of
+    // kernel launches it enqueued
+    int tick(long long *launches)
+    {
+        auto *hdr = static_cast<BatchTableHeader *>(h_table);
+        auto *rec = reinterpret_cast<BatchJob *>(hdr + 1);
+        int tiles = 0;
+        int maxsteps = 0;
+        for (size_t i = 0; i < active.size(); ++i) {
+            SJob &j = *active[i];
+            j.steps_tick = (int)std::min<long long>(d.tick_steps, j.d.steps - j.steps_done);
+            maxsteps = std::max(maxsteps, j.steps_tick);
+            BatchJob b = j.bj;
+            b.steps = j.steps_tick;
+            b.tiles_x = (b.g.nx + BT_X - 1) / BT_X;
+            b.tiles_y = (b.g.ny + BT_Y - 1) / BT_Y;
+            b.tile_begin = tiles;
+            tiles += b.tiles_x * b.tiles_y * b.g.nz;
+            rec[i] = b;
+        }
+        hdr->njobs = (int)active.size();
+        hdr->total_tiles = tiles;
+        if (hipMemcpyAsync(d_table, h_table, batch_table_bytes((int)active.size()),
+                           hipMemcpyHostToDevice, stream) != hipSuccess)
+            return STENCIL_EDEVICE;
+        int rc = STENCIL_OK;
+        if (gexec && maxsteps == d.tick_steps) {
+            if (hipGraphLaunch(gexec, stream) != hipSuccess)
+                rc = STENCIL_EDEVICE;
+            *launches = 3 * d.tick_steps;
+        } else {
+            for (int s = 0; s < 3 * maxsteps && !rc; ++s)
+                rc = launch_batch_substep(d_table, s, rk, d.blocks, stream);
+            *launches = 3 * maxsteps;
+        }
+        if (hipStreamSynchronize(stream) != hipSuccess && !rc)
+            rc = STENCIL_EDEVICE;
+        return rc;
+    }
+
+    void fail_all(int err)
+    {
+        for (auto &j : active) {
+            free_job(*j);
+            finish(j, STENCIL_JOB_FAILED, err);
+        }
+        active.clear();
+        std::lock_guard<std::mutex> lk(mu);
+        sticky = err;
+        for (auto &j : queue) {
+            j->state = STENCIL_JOB_FAILED;
+            j->error = err;
+            j->t_done = clock();
+            st.failed++;
+        }
+        queue.clear();
+        cv_done.notify_all();
+    }
+
+    void run()
+    {
+        (void)hipSetDevice(device);
+        if (d.use_graph && capture_graph() != STENCIL_OK) {
+            fail_all(STENCIL_EDEVICE);
+            return;
+        }
+        for (;;) {
+            std::vector<std::shared_ptr<SJob>> admit;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+                if (stop)
+                    break;
+                int slots = d.max_slots - (int)active.size();
+                for (auto it = queue.begin(); it != queue.end();) {
+                    auto &j = *it;
+                    if (j->cancel) {
+                        j->state = STENCIL_JOB_CANCELLED;
+                        j->t_done = clock();
+                        st.cancelled++;
+                        cv_done.notify_all();
+                        it = queue.erase(it);
+                    } else if (j->bytes > d.hbm_budget) {
+                        j->state = STENCIL_JOB_FAILED;
+                        j->error = STENCIL_ENOMEM;
+                        j->t_done = clock();
+                        st.failed++;
+                        cv_done.notify_all();
+                        it = queue.erase(it);
+                    } else if (slots > 0 && used + j->bytes <= d.hbm_budget) {
+                        used += j->bytes;
+                        slots--;
+                        admit.push_back(j);
+                        it = queue.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+            for (auto &j : admit) {
+                int rc = start_job(*j);
+                if (rc == STENCIL_EDEVICE) {
+                    finish(j, STENCIL_JOB_FAILED, rc);
+                    fail_all(rc);
+                    return;
+                }
+                if (rc) {
+                    finish(j, STENCIL_JOB_FAILED, rc);
+                    continue;
+                }
+                std::lock_guard<std::mutex> lk(mu);
+                j->state = STENCIL_JOB_RUNNING;
+                j->t_admit = clock();
+                st.admitted++;
+                active.push_back(j);
+            }
+            if (active.empty())
+                continue;
+            const double tb = clock();
+            long long nl = 0;
+            int rc = tick(&nl);
+            const double te = clock();
+            if (rc) {
+                fail_all(rc);
+                return;
+            }
+            std::vector<std::shared_ptr<SJob>> keep;
+            for (auto &j : active) {
+                j->steps_done += j->steps_tick;
+                j->bj.parity ^= (3 * j->steps_tick) & 1;
+                if (j->t_first < 0) j->t_first = te;
+                bool cancel;
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    cancel = j->cancel;
+                }
+                if (j->steps_done >= j->d.steps) {
+                    // a failed copy fails this job; a device-wide fault shows
+                    // again at the next tick's synchronisation
+                    int drc = download_job(*j);
+                    free_job(*j);
+                    finish(j, drc ? STENCIL_JOB_FAILED : STENCIL_JOB_DONE, drc);
+                } else if (cancel) {
+                    free_job(*j);
+                    finish(j, STENCIL_JOB_CANCELLED, 0);
+                } else {
+                    keep.push_back(j);
+                }
+            }
+            active.swap(keep);
+            std::lock_guard<std::mutex> lk(mu);
+            st.ticks++;
+            st.launches += nl;
+            st.busy_s += te - tb;
+        }
+        // stopping: cancel what is resident
+        for (auto &j : active) {
+            free_job(*j);
+            finish(j, STENCIL_JOB_CANCELLED, 0);
+        }
+        active.clear();
+    }
+};
+
+extern "C" {
+
+stencil_status stencil_server_create(const stencil_server_desc *desc, stencil_server_t *out)
+{
+    if (!desc || !out)
+        return fail(STENCIL_EINVAL, "NULL descriptor or output");
+    *out = nullptr;
+    if (desc->max_slots < 1 || desc->max_slots > 4096)
+        return fail(STENCIL_EINVAL, "max_slots must be 1..4096");
+    if (desc->tick_steps < 1 || desc->tick_steps > 10000)
+        return fail(STENCIL_EINVAL, "tick_steps must be 1..10000");
+    if (desc->blocks < 0 || desc->queue_cap < 0)
+        return fail(STENCIL_EINVAL, "blocks and queue_cap must be >= 0");
+    auto *s = new (std::nothrow) stencil_server_s();
+    if (!s)
+        return fail(STENCIL_ENOMEM, "out of host memory");
+    s->d = *desc;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(STENCIL_EDEVICE, "no HIP device");
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, s->device) != hipSuccess) {
+        delete s;
+        return fail(STENCIL_EDEVICE, "cannot query the device");
+    }
+    if (!s->d.blocks)
+        s->d.blocks = 8 * prop.multiProcessorCount;
+    if (!s->d.hbm_budget) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            delete s;
+            return fail(STENCIL_EDEVICE, "cannot query free device memory");
+        }
+        s->d.hbm_budget = fr / 5 * 4;
+    }
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return fail(STENCIL_EDEVICE, "cannot create a stream");
+    }
+    const size_t tb = batch_table_bytes(s->d.max_slots);
+    if (hipMalloc(&s->d_table, tb) != hipSuccess || hipHostMalloc(&s->h_table, tb) != hipSuccess) {
+        (void)hipGetLastError();
+        if (s->d_table) (void)hipFree(s->d_table);
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        return fail(STENCIL_ENOMEM, "cannot allocate the job table");
+    }
+    std::memset(s->h_table, 0, tb);
+    s->rk = rk3_coeffs();
+    double w1[7], w2[7];
+    stencil_fd_weights(1, 3, w1);
+    stencil_fd_weights(2, 3, w2);
+    for (int m = 1; m <= 3; ++m) {
+        s->fd.w1[m - 1] = w1[3 + m];
+        s->fd.w2[m] = w2[3 + m];
+    }
+    s->fd.w2[0] = w2[3];
+    s->st.bytes_budget = s->d.hbm_budget;
+    s->t0 = std::chrono::steady_clock::now();
+    try {
+        s->worker = std::thread([s] { s->run(); });
+    } catch (...) {
+        (void)hipFree(s->d_table);
+        (void)hipHostFree(s->h_table);
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        return fail(STENCIL_ENOMEM, "cannot start the server thread");
+    }
+    *out = s;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_server_destroy(stencil_server_t s)
+{
+    if (!s)
+        return STENCIL_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (auto &j : s->queue) {
+            j->state = STENCIL_JOB_CANCELLED;
+            j->t_done = s->clock();
+        }
+        s->queue.clear();
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable())
+        s->worker.join();
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    (void)hipFree(s->d_table);
+    (void)hipHostFree(s->h_table);
+    (void)hipStreamDestroy(s->stream);
+    s->cv_done.notify_all();
+    delete s;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_submit(stencil_server_t s, const stencil_job *job, uint64_t *ticket)
+{
+    if (!s || !ticket)
+        return fail(STENCIL_EINVAL, "NULL server or ticket");
+    int rc = check_job(job);
+    if (rc) return rc;
+    auto j = std::make_shared<SJob>();
+    j->d = *job;
+    j->bytes = job_bytes(*job);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->sticky)
+        return fail(s->sticky, "server stopped after a device failure");
+    if (s->d.queue_cap && (int)s->queue.size() >= s->d.queue_cap)
+        return fail(STENCIL_EAGAIN, "server queue is full");
+    j->ticket = s->next_ticket++;
+    j->t_submit = s->clock();
+    s->queue.push_back(j);
+    s->jobs[j->ticket] = j;
+    *ticket = j->ticket;
+    s->cv_work.notify_one();
+    return STENCIL_OK;
+}
+
+static void fill_status(const SJob &j, stencil_job_status *st)
+{
+    st->state = j.state;
+    st->error = j.error;
+    st->t_submit = j.t_submit;
+    st->t_admit = j.t_admit;
+    st->t_first_tick = j.t_first;
+    st->t_done = j.t_done;
+    st->steps_done = j.steps_done;
+}
+
+stencil_status stencil_poll(stencil_server_t s, uint64_t ticket, stencil_job_status *st)
+{
+    if (!s || !st)
+        return fail(STENCIL_EINVAL, "NULL server or status");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end())
+        return fail(STENCIL_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    fill_status(*it->second, st);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_wait(stencil_server_t s, uint64_t ticket, stencil_job_status *st,
+                            int timeout_ms)
+{
+    if (!s || !st)
+        return fail(STENCIL_EINVAL, "NULL server or status");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end())
+        return fail(STENCIL_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    auto j = it->second;
+    auto done = [&] { return j->state >= STENCIL_JOB_DONE; };
+    if (timeout_ms < 0)
+        s->cv_done.wait(lk, done);
+    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done)) {
+        fill_status(*j, st);
+        return fail(STENCIL_ETIMEOUT, "job %llu not finished", (unsigned long long)ticket);
+    }
+    fill_status(*j, st);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_cancel(stencil_server_t s, uint64_t ticket)
+{
+    if (!s)
+        return fail(STENCIL_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end())
+        return fail(STENCIL_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    it->second->cancel = true;
+    s->cv_work.notify_one();
+    return STENCIL_OK;
+}
+
+stencil_status stencil_server_stats_get(stencil_server_t s, stencil_server_stats *st)
+{
+    if (!s || !st)
+        return fail(STENCIL_EINVAL, "NULL server or stats");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *st = s->st;
+    st->bytes_in_use = s->used;
+    st->queued = (int)s->queue.size();
+    int resident = 0;
+    for (auto &kv : s->jobs)
+        if (kv.second->state == STENCIL_JOB_RUNNING) resident++;
+    st->resident = resident;
+    return STENCIL_OK;
+}
+
+double stencil_server_clock(stencil_server_t s) { return s ? s->clock() : -1.0; }
+
+} // extern "C"

@@ -1,0 +1,270 @@
+// star3d.hpp -- the 3-D axis-aligned (star) cross-correlation kernel for
+// gfx950: x-y plane tile staged in LDS, z taps from a per-lane register window
+// marching along z, a register ring prefetching PF planes ahead. Included by
+// the per-dtype instantiation units star3d_*.hip.
+#pragma once
+
+#include "linear_kernels.hpp"
+
+namespace stn {
+
+// Supported (TY, NY) shapes: lanes along y, rows per lane. Tiles are 64 x TY*NY.
+#define STAR_SHAPES(X) X(4, 2) X(4, 4) X(8, 2) X(8, 4) X(16, 2) X(2, 8)
+// Supported prefetch depths (planes in flight ahead of the one computed).
+#define STAR_PREFETCH(X) X(2) X(3)
+
+template <int R, int NY, int TY> struct StarShape {
+    static constexpr int TXW = 64;           // lanes along x
+    static constexpr int ROWS = TY * NY;     // output rows per tile
+    static constexpr int LW = TXW + 2 * R;   // LDS row width
+    static constexpr int LH = ROWS + 2 * R;  // LDS rows
+    static constexpr int NXH = 2 * R * ROWS; // x-halo cells per plane
+    static constexpr int NYH = 2 * R * TXW;  // y-halo cells per plane
+    static constexpr int NT = TXW * TY;      // lanes per workgroup
+    static constexpr int HX_PER = (NXH + NT - 1) / NT;
+    static constexpr int HY_PER = (NYH + NT - 1) / NT;
+};
+
+// Workgroup order. Dispatch sends workgroup i to XCD i % 8. With the XCD flag
+// the bijection below gives XCD k a contiguous range of tile numbers (the first
+// total % 8 XCDs one more than the others), so tiles that run on one XCD at the
+// same time are neighbours and share halo lines in that XCD's L2. Tile numbers
+// run fastest along x (x-neighbours share the cache lines that hold their x
+// halo), or along y with STAR_FLAG_YFIRST (y-neighbours share halo rows), then
+// along the other axis, then over z chunks.
+__device__ __forceinline__ int xcd_remap(int lin, int total)
+{
+    const int nxcd = 8;
+    const int per = total / nxcd, rem = total % nxcd;
+    const int xcd = lin % nxcd, slot = lin / nxcd;
+    return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+// Workgroup = 64 x TY lanes; lane (tx, ty) owns column x = x0 + tx and the NY
+// consecutive rows y0 + ty*NY + j, and marches along z over a chunk of lz
+// output planes. Per lane and row the 2R+1 column values around the current
+// plane live in registers (the z taps). The current plane with its x and y
+// halo (a star needs no corners) is staged in LDS, double-buffered, so one
+// barrier per plane suffices; x taps and the y taps outside the lane's own
+// rows come from LDS, y taps inside them from registers. Loads of plane z+PF
+// (its leading window value and halo cells) are issued right after the
+// barrier of plane z, so PF planes of HBM latency overlap the arithmetic.
+// All loads are buffer loads: the lane supplies its in-plane byte offset, the
+// plane offset is a wave-uniform scalar.
+template <typename S, int R, int NY, int TY, int PF>
+__global__ void __launch_bounds__(64 * TY)
+    k_star3d(const S *__restrict__ in, S *__restrict__ out, Geo g,
+             StarCoef<typename Store<S>::C, R> cf, int lz, int gx, int gy, int gz, int flags)
+{
+    using C = typename Store<S>::C;
+    using SH = StarShape<R, NY, TY>;
+    constexpr uint32_t es = sizeof(S);
+    __shared__ C lds[2][SH::LH][SH::LW];
+
+    int lin = blockIdx.x;
+    const int total = gx * gy * gz;
+    if (flags & STAR_FLAG_XCD) lin = xcd_remap(lin, total);
+    const bool yfirst = (flags & STAR_FLAG_YFIRST) != 0;
+    const int byi = yfirst ? lin % gy : (lin / gx) % gy;
+    const int bxi = yfirst ? (lin / gy) % gx : lin % gx;
+    const int bzi = lin / (gx * gy);
+
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = tx + 64 * ty;
+    const int x0 = bxi * 64, y0 = byi * SH::ROWS;
+    const int z0 = bzi * lz;
+    const int z1 = min(z0 + lz, g.nz);
+    const bool fuse = (flags & STAR_FLAG_NOFUSE) == 0;
+    const Buf src = make_buf(in, uint64_t(padded_elems(g)) * es);
+
+    // clamp reads into the padded array: any coordinate in [-R, n+R) is valid
+    auto cl = [](int v, int n) { return min(max(v, -R), n + R - 1); };
+    // byte offset of interior column (x, y) within a plane; plane z adds
+    // (z + rz) * sz * es as the scalar operand
+    auto col = [&](int xx, int yy) {
+        return uint32_t(xx + g.r + g.sy * (yy + g.ry)) * es;
+    };
+    auto plane = [&](int zz) { return uint32_t(zz + g.rz) * uint32_t(g.sz) * es; };
+
+    const int x = x0 + tx;
+    const int xl = cl(x, g.nx);
+    uint32_t col_off[NY];
+#pragma unroll
+    for (int j = 0; j < NY; ++j) col_off[j] = col(xl, cl(y0 + ty * NY + j, g.ny));
+
+    // halo cells of this lane (fixed per plane)
+    uint32_t hx_off[SH::HX_PER], hy_off[SH::HY_PER];
+    int hx_slot[SH::HX_PER], hy_slot[SH::HY_PER];
+#pragma unroll
+    for (int k = 0; k < SH::HX_PER; ++k) {
+        const int cidx = tid + k * SH::NT;
+        if (cidx < SH::NXH) {
+            const int row = cidx / (2 * R), e = cidx % (2 * R);
+            const int lc = e < R ? e : SH::TXW + e; // LDS column
+            hx_off[k] = col(cl(x0 - R + lc, g.nx), cl(y0 + row, g.ny));
+            hx_slot[k] = (row + R) * SH::LW + lc;
+        } else {
+            hx_off[k] = col(0, 0);
+            hx_slot[k] = -1;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SH::HY_PER; ++k) {
+        const int cidx = tid + k * SH::NT;
+        if (cidx < SH::NYH) {
+            const int e = cidx / SH::TXW, cc = cidx % SH::TXW;
+            const int lr = e < R ? e : SH::ROWS + e; // LDS row
+            hy_off[k] = col(cl(x0 + cc, g.nx), cl(y0 - R + lr, g.ny));
+            hy_slot[k] = lr * SH::LW + cc + R;
+        } else {
+            hy_off[k] = col(0, 0);
+            hy_slot[k] = -1;
+        }
+    }
+
+    // z window: win[j][k] holds plane z - R + k of row j
+    C win[NY][2 * R + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k)
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+            win[j][k + 1] = BufLd<S>::ld(src, col_off[j], plane(z0 - R + k));
+
+    // prefetch ring: slot q holds plane z0 + q (+R for the window value)
+    C pre_w[PF][NY], pre_hx[PF][SH::HX_PER], pre_hy[PF][SH::HY_PER];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int zq = min(z0 + q, z1 - 1); // in range: any valid plane will do
+#pragma unroll
+        for (int j = 0; j < NY; ++j) pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zq + R));
+#pragma unroll
+        for (int k = 0; k < SH::HX_PER; ++k) pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zq));
+#pragma unroll
+        for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zq));
+    }
+
+    for (int zb = z0; zb < z1; zb += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int z = zb + q;
+            if (z >= z1)
+                break;
+            const int b = (z - z0) & 1;
+            C *lb = &lds[b][0][0];
+#pragma unroll
+            for (int j = 0; j < NY; ++j) {
+#pragma unroll
+                for (int k = 0; k < 2 * R; ++k) win[j][k] = win[j][k + 1];
+                win[j][2 * R] = pre_w[q][j];
+                lds[b][ty * NY + j + R][tx + R] = win[j][R];
+            }
+#pragma unroll
+            for (int k = 0; k < SH::HX_PER; ++k)
+                if (hx_slot[k] >= 0) lb[hx_slot[k]] = pre_hx[q][k];
+#pragma unroll
+            for (int k = 0; k < SH::HY_PER; ++k)
+                if (hy_slot[k] >= 0) lb[hy_slot[k]] = pre_hy[q][k];
+            __syncthreads();
+
+            // refill slot q with plane z + PF (clamped: past the chunk end the
+            // values are never used, the load only has to stay in range)
+            {
+                const int zn = min(z + PF, z1 - 1);
+#pragma unroll
+                for (int j = 0; j < NY; ++j)
+                    pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+#pragma unroll
+                for (int k = 0; k < SH::HX_PER; ++k)
+                    pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
+#pragma unroll
+                for (int k = 0; k < SH::HY_PER; ++k)
+                    pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
+            }
+
+#pragma unroll
+            for (int j = 0; j < NY; ++j) {
+                const int row = ty * NY + j + R;
+                C acc = cf.c0 * win[j][R];
+#pragma unroll
+                for (int m = 1; m <= R; ++m) {
+                    acc = fma(cf.zm[m - 1], win[j][R - m], acc);
+                    acc = fma(cf.zp[m - 1], win[j][R + m], acc);
+                }
+#pragma unroll
+                for (int m = 1; m <= R; ++m) {
+                    acc = fma(cf.xm[m - 1], lds[b][row][tx + R - m], acc);
+                    acc = fma(cf.xp[m - 1], lds[b][row][tx + R + m], acc);
+                }
+#pragma unroll
+                for (int m = 1; m <= R; ++m) {
+                    C vm = (j - m >= 0) ? win[(j - m >= 0) ? j - m : 0][R] : lds[b][row - m][tx + R];
+                    C vp = (j + m < NY) ? win[(j + m < NY) ? j + m : 0][R] : lds[b][row + m][tx + R];
+                    acc = fma(cf.ym[m - 1], vm, acc);
+                    acc = fma(cf.yp[m - 1], vp, acc);
+                }
+                const int y = y0 + ty * NY + j;
+                if (x < g.nx && y < g.ny)
+                    store_periodic(out, g, x, y, z, acc, fuse);
+            }
+        }
+    }
+}
+
+template <typename S, int R, int NY, int TY, int PF>
+int launch_star3d_t(const S *in, S *out, const Geo &g,
+                    const StarCoef<typename Store<S>::C, R> &cf, int lz, int flags, hipStream_t s)
+{
+    using SH = StarShape<R, NY, TY>;
+    int gx = (g.nx + 63) / 64, gy = (g.ny + SH::ROWS - 1) / SH::ROWS, gz = (g.nz + lz - 1) / lz;
+    int64_t total = (int64_t)gx * gy * gz;
+    if (total > 0x7fffffff)
+        return fail(STENCIL_EUNSUPPORTED, "star3d: grid too large");
+    hipLaunchKernelGGL((k_star3d<S, R, NY, TY, PF>), dim3((unsigned)total), dim3(64, TY), 0, s,
+                       in, out, g, cf, lz, gx, gy, gz, flags);
+    return check_launch("xcorr_star3d");
+}
+
+template <typename S, int R, int NY, int TY>
+int launch_star3d_pf(const S *in, S *out, const Geo &g,
+                     const StarCoef<typename Store<S>::C, R> &cf, int pf, int lz, int flags,
+                     hipStream_t s)
+{
+#define STAR_CASE_PF(PF_)                                                                    \
+    if (pf == PF_)                                                                           \
+        return launch_star3d_t<S, R, NY, TY, PF_>(in, out, g, cf, lz, flags, s);
+    STAR_PREFETCH(STAR_CASE_PF)
+#undef STAR_CASE_PF
+    return fail(STENCIL_EUNSUPPORTED, "star3d: unsupported prefetch depth %d", pf);
+}
+
+template <typename S, int R>
+int launch_star3d_r(const S *in, S *out, const Geo &g, const StarCoef<typename Store<S>::C, R> &cf,
+                    int ty, int ny, int pf, int lz, int flags, hipStream_t s)
+{
+#define STAR_CASE(TY_, NY_)                                                                  \
+    if (ty == TY_ && ny == NY_)                                                              \
+        return launch_star3d_pf<S, R, NY_, TY_>(in, out, g, cf, pf, lz, flags, s);
+    STAR_SHAPES(STAR_CASE)
+#undef STAR_CASE
+    return fail(STENCIL_EUNSUPPORTED, "star3d: unsupported tile (ty=%d, ny=%d)", ty, ny);
+}
+
+template <typename S>
+int launch_star3d_impl(const S *in, S *out, const Geo &g, const StarCoefAny &cfa, int R, int ty,
+                       int ny, int pf, int lz, int flags, hipStream_t s)
+{
+    using C = typename Store<S>::C;
+    if (R > g.r || g.ndim != 3)
+        return fail(STENCIL_EINVAL, "star3d: tap radius %d exceeds padding %d", R, g.r);
+    if (uint64_t(padded_elems(g)) * sizeof(S) >= (uint64_t(1) << 32))
+        return fail(STENCIL_EUNSUPPORTED, "star3d: arrays of 4 GiB or more are not supported");
+    switch (R) {
+    case 1: return launch_star3d_r<S, 1>(in, out, g, cfa.get<C, 1>(), ty, ny, pf, lz, flags, s);
+    case 2: return launch_star3d_r<S, 2>(in, out, g, cfa.get<C, 2>(), ty, ny, pf, lz, flags, s);
+    case 3: return launch_star3d_r<S, 3>(in, out, g, cfa.get<C, 3>(), ty, ny, pf, lz, flags, s);
+    case 4: return launch_star3d_r<S, 4>(in, out, g, cfa.get<C, 4>(), ty, ny, pf, lz, flags, s);
+    }
+    return fail(STENCIL_EUNSUPPORTED, "star3d: radius %d not in 1..4", R);
+}
+
+} // namespace stn

@@ -1,0 +1,10 @@
+// star3d_bf16.hip -- instantiations of the 3-D star kernel for bf16 storage.
+#include "star3d.hpp"
+
+namespace stn {
+int launch_star3d(const bf16 *in, bf16 *out, const Geo &g, const StarCoefAny &cf, int R, int ty,
+                  int ny, int pf, int lz, int flags, hipStream_t s)
+{
+    return launch_star3d_impl<bf16>(in, out, g, cf, R, ty, ny, pf, lz, flags, s);
+}
+} // namespace stn

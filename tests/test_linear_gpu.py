@@ -134,8 +134,9 @@ def rand_star(r, seed):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("tile", [(4, 1, 64), (4, 4, 64), (2, 8, 8), (8, 2, 13), (4, 2, 5, 1),
-                                  (8, 1, 64, 2), (2, 4, 7, 3)])
+@pytest.mark.parametrize("tile", [(4, 2, 64, 0x20), (4, 4, 64, 0x31), (2, 8, 8, 0x21),
+                                  (8, 2, 13, 0x30), (4, 2, 5, 0x31), (8, 4, 64, 0x22),
+                                  (16, 2, 7, 0x33), (8, 2, 1, 0x31)])
 def test_star3d_tiles_diffusion(dtype, tile):
     g = diffusion_star_exact(3, 3, 0.0815)
     run_case((70, 37, 29), 3, g, dtype, S.STAR3D, tile=tile)
@@ -145,21 +146,23 @@ def test_star3d_tiles_diffusion(dtype, tile):
 @pytest.mark.parametrize("dtype", [S.F64, S.F32])
 def test_star3d_asymmetric_random_taps(r, dtype):
     # asymmetric coefficients: a swapped side or axis would show
-    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(4, 2, 8))
+    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(4, 2, 8, 0x31))
+    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(16, 2, 5, 0x20))
 
 
 def test_star3d_tap_radius_below_padding():
     # radius-4 padding, radius-2 taps: the plan runs a radius-2 kernel
     g = np.zeros((9, 9, 9))
     g[2:7, 2:7, 2:7] = rand_star(2, 5)
-    p = run_case((40, 20, 12), 4, g, S.F64, S.STAR3D, tile=(4, 2, 8))
+    p = run_case((40, 20, 12), 4, g, S.F64, S.STAR3D, tile=(4, 2, 8, 0x21))
     assert p.variant == S.STAR3D
 
 
 @pytest.mark.parametrize("dims,r", [((3, 3, 3), 3), ((5, 4, 7), 3), ((4, 5, 6), 4), ((1, 1, 1), 1)])
 def test_star3d_tiny_periodic_grids(dims, r):
     # n < 2r: a point has periodic images on both sides
-    run_case(dims, r, rand_star(r, 2), S.F64, S.STAR3D, tile=(4, 1, 2))
+    run_case(dims, r, rand_star(r, 2), S.F64, S.STAR3D, tile=(4, 2, 2, 0x31))
+    run_case(dims, r, rand_star(r, 2), S.F64, S.STAR3D, tile=(2, 8, 3, 0x20))
     run_case(dims, r, rand_star(r, 2), S.F64, S.GENERIC)
 
 
@@ -192,7 +195,7 @@ def test_r0_copy_stencil():
     run_case((33, 17, 9), 0, np.array([[[2.0]]]), S.F64, S.GENERIC)
 
 
-@pytest.mark.parametrize("variant,tile", [(S.STAR3D, (4, 4, 16)), (S.GENERIC, None)])
+@pytest.mark.parametrize("variant,tile", [(S.STAR3D, (4, 4, 16, 0x31)), (S.GENERIC, None)])
 @pytest.mark.parametrize("iters", [6, 7])
 def test_chained_iterations_ping_pong(variant, tile, iters):
     g = diffusion_star_exact(3, 3, 0.2)
@@ -206,7 +209,7 @@ def test_user_halo_reads_caller_halo_and_writes_interior_only(variant):
     rng = np.random.default_rng(12)
     a_host = rng.uniform(-1, 1, O.padded_shape(dims, r))  # non-periodic halo
     plan = S.LinearPlan(dims, r, g, bc=S.USER_HALO, variant=variant,
-                        tile=(4, 2, 8) if variant == S.STAR3D else None)
+                        tile=(4, 2, 8, 0x21) if variant == S.STAR3D else None)
     a = dev(a_host, S.F64)
     b = plan.empty(fill=123.0)
     plan.apply(a, b, 1)
