@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--radius", type=int, default=3)
     ap.add_argument("--tile", default=None,
                     help="star3d launch shape TY,NY,LZ,FLAGS (skips autotuning)")
+    ap.add_argument("--layout", choices=("auto", "compact", "aligned"), default="auto",
+                    help="field rows: compact (n + 2r cells) or padded so each interior row "
+                         "starts a 128-byte line; auto = compact for FP64, aligned for the "
+                         "narrower types (what measured faster for each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
@@ -121,21 +125,28 @@ def cpu_baseline(n, r, g, seconds):
                       % ((2 * r + 1) ** 3, n, n, nz, t)}
 
 
-def star_run(torch, S, W, inputs, n, r, dtype, steps, warmup, tile=None):
+def star_run(torch, S, W, inputs, n, r, dtype, steps, warmup, tile=None, layout="auto"):
     """Chained iterations of the star workload, one launch per step with an
-    event after each; returns (plan, total ms, per-launch ms list)."""
+    event after each; returns (plan, coefficients, total ms, mean launch ms).
+    layout: "compact", "aligned" (each interior row starts a 128-byte line) or
+    "auto" (compact for FP64, aligned otherwise)."""
     import numpy as np
     dims = (n, n, n)
     g = W.diffusion_star(3, r, W.diffusion_number(n))
+    es = {S.F64: 8, S.F32: 4, S.BF16: 2}[dtype]
+    aligned = layout == "aligned" or (layout == "auto" and dtype != S.F64)
+    pitch, ox = W.aligned_layout(n, r, es) if aligned else (0, 0)
     if tile:
-        plan = S.LinearPlan(dims, r, g, dtype=dtype, variant=S.STAR3D, tile=tile)
+        plan = S.LinearPlan(dims, r, g, dtype=dtype, variant=S.STAR3D, tile=tile,
+                            row_pitch=pitch, x_offset=ox)
     else:
-        plan = S.LinearPlan(dims, r, g, dtype=dtype, autotune=True)
+        plan = S.LinearPlan(dims, r, g, dtype=dtype, autotune=True, row_pitch=pitch,
+                            x_offset=ox)
     a = plan.empty(0.0)
-    a[r:r + n, r:r + n, r:r + n] = torch.from_numpy(inputs.uniform_field(dims, 1)).to(
-        "cuda").to(a.dtype)
+    plan.padded(a)[r:r + n, r:r + n, r:r + n] = torch.from_numpy(
+        inputs.uniform_field(dims, 1)).to("cuda").to(a.dtype)
     b = plan.empty(0.0)
-    S.halo_periodic(a, dims, r, dtype)
+    plan.halo(a)
     cur, nxt = a, b
     for _ in range(warmup):
         plan.apply(cur, nxt, 1, halo_valid=True)
@@ -243,14 +254,14 @@ def main():
     K = args.steps
     t0 = time.perf_counter()
     plan, g, total_ms, avg_launch_ms = star_run(torch, S, W, inputs, n, r, dtype, K,
-                                                args.warmup, tile)
+                                                args.warmup, tile, layout=args.layout)
     wall = time.perf_counter() - t0
     ms_per_step = total_ms / K
     points = n ** 3
     value = points / (ms_per_step * 1e-3)
     alg_bytes = 2 * esize * points  # read f once, write f' once per point
     achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
-    kern_files = ("linear_kernels.hip", "common.hpp", "linear_kernels.hpp")
+    kern_files = ("star3d.hpp", "star3d_%s.hip" % args.dtype, "common.hpp", "linear_kernels.hpp")
     traffic = load_traffic("traffic_star3d_%d_%s.json" % (n, args.dtype), kern_files)
     copy_gbs = None if args.no_copy else copy_bandwidth(torch, S)
 
@@ -274,6 +285,7 @@ def main():
             "grid": [n, n, n], "radius": r, "taps": int((g != 0).sum()),
             "kernel_variant": {0: "generic", 1: "star3d", 2: "line1d"}[plan.variant],
             "tile": list(plan.tile),
+            "layout": {"row_pitch": plan.row_pitch, "x_offset": plan.x_offset},
             "parallelism": "single GPU",
         },
         "roofline": {

@@ -82,12 +82,31 @@ typedef struct stencil_desc {
      *   STAR3D : {lanes along y, rows per lane, z planes per workgroup,
      *             flags: bit 0 XCD-aware workgroup order, bit 1 separate halo
      *             pass instead of writing periodic images, bit 2 tiles
-     *             numbered fastest along y (else x), bits 4..7 planes
-     *             prefetched ahead (0 = default 2)}; (lanes, rows) one of
-     *             (4,2) (4,4) (8,2) (8,4) (16,2) (2,8), prefetch 2 or 3
+     *             numbered fastest along y (else x), bit 3 hardware-cached
+     *             z march (x/y taps through L1/L2, no LDS; 64-lane-wide
+     *             tiles; (lanes, rows) one of (4,1) (4,2) (4,4) (2,4) (8,2)
+     *             and prefetch/width ignored), bits 4..7 planes
+     *             prefetched ahead (0 = default 2; only 2 is built), bits
+     *             8..11 tile width in 64-lane waves (0 = 1)}; (width, lanes,
+     *             rows) one of (1,8,2) (1,4,4) (1,8,4) (1,16,2) (2,4,2)
+     *             (2,4,4) (2,8,2) (4,2,2) (4,2,4) (4,4,2) (8,1,4) (8,2,2)
      *   GENERIC: {block x, block y} (a multiple of 64 lanes, at most 1024)
-     *   LINE1D : {outputs per lane: 1, 2, 4 or 8} */
+     *   LINE1D : {outputs per lane: 1, 2, 4 or 8, iterations fused per
+     *             launch T (0/1 = none; T > 1 periodic only: the block
+     *             loads its range plus r*T wrapped cells once and iterates in
+     *             LDS, the temporal blocking the paper's discussion asks for)} */
     int tile[4];
+    /* Field layout (both 0 = compact, the layout of Eq. 2 with rows of
+     * dims[0] + 2r cells). x_offset: column of interior x = 0 (>= radius);
+     * row_pitch: elements from one row to the next (>= x_offset + dims[0] +
+     * radius; ndim >= 2 only). Cells outside [x_offset - r, x_offset +
+     * dims[0] + r) of a row are never read or written. A field then holds
+     * stencil_plan_padded_elems(plan) elements; y/z padding is unchanged.
+     * Starting the interior of every row on a 128-byte boundary (x_offset *
+     * element size and row_pitch * element size multiples of 128) makes the
+     * star kernel's tile rows whole cache lines. */
+    int row_pitch;
+    int x_offset;
 } stencil_desc;
 
 typedef struct stencil_plan_s *stencil_plan_t;
@@ -98,8 +117,14 @@ const char *stencil_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int stencil_version(void);
 
-/* Number of elements of a field with interior dims padded by r. */
+/* Number of elements of a field with interior dims padded by r (compact
+ * layout). */
 size_t stencil_padded_elems(int ndim, const int dims[3], int radius);
+
+/* Number of elements of one field in the plan's layout (linear plans with a
+ * row pitch: pitch * padded rows * padded planes; otherwise as
+ * stencil_padded_elems). Returns 0 for a NULL plan. */
+size_t stencil_plan_padded_elems(stencil_plan_t plan);
 
 /* Create a linear plan on the current HIP device. The plan owns a device copy
  * of the pruned taps. With STENCIL_FLAG_AUTOTUNE the candidate variants are
@@ -122,8 +147,8 @@ stencil_status stencil_plan_tile(stencil_plan_t plan, int tile[4]);
  * device buffers of the plan's dtype and may not overlap. Iteration k reads
  * one and writes the other, starting d_a -> d_b, so the result is in d_b when
  * iters is odd and in d_a when even (iters = 0 does nothing).
- * PERIODIC: the halo of d_a is refreshed before the first iteration (d_a's
- * halo cells are written) and every result carries a valid periodic halo.
+ * PERIODIC: d_a's halo may be refreshed (its halo cells written) before the
+ * first iteration, and every result carries a valid periodic halo.
  * USER_HALO: iters must be 1; the caller's halo of d_a is read and only the
  * interior of d_b is written. */
 stencil_status stencil_apply(stencil_plan_t plan, void *d_a, void *d_b, int iters,
@@ -142,6 +167,11 @@ stencil_status stencil_apply_ex(stencil_plan_t plan, void *d_a, void *d_b, int i
  * cell congruent to it modulo dims (Eq. 2 with a periodic beta). */
 stencil_status stencil_halo_periodic(int ndim, const int dims[3], int radius, int dtype,
                                      void *d_buf, void *stream);
+
+/* The same periodic halo refresh for one field in a linear plan's layout
+ * (its dims, radius, dtype, row_pitch and x_offset); d_buf holds
+ * stencil_plan_padded_elems(plan) elements. Asynchronous on the stream. */
+stencil_status stencil_plan_halo(stencil_plan_t plan, void *d_buf, void *stream);
 
 /* Streaming copy of nbytes (multiple of 16, both pointers 16-byte aligned):
  * the r = 0 case used to measure achievable HBM bandwidth (Sec. 5.2). */
@@ -192,7 +222,9 @@ typedef struct stencil_rk_desc {
     double ds[3];   /* grid spacing per axis (> 0) */
     double nu, eta, cs2;
     double adv[3];  /* ADVDIFF velocity */
-    int block[2];   /* launch override (x, y lanes); 0 = plan's choice */
+    int block[3];   /* launch override: x lanes, y lanes (x*y a multiple of 64,
+                       at most 256), block[2] 0 or 1 (one z plane per
+                       workgroup); 0 = plan's choice */
 } stencil_rk_desc;
 
 /* Buffers of one substep; all are caller-owned padded (radius 3) device
@@ -291,6 +323,10 @@ typedef struct stencil_server_desc {
     int use_graph;     /* replay each tick from one captured hipGraph */
     int blocks;        /* persistent workgroups per launch; 0 = 8 per CU */
     int queue_cap;     /* jobs waiting for admission at most; 0 = unlimited */
+    long long min_points; /* points per substep a tick gathers, shortest
+                             remaining work first, before it stops adding
+                             resident jobs (0 = 4 Mi; a huge value = every
+                             resident job every tick) */
 } stencil_server_desc;
 
 typedef struct stencil_server_s *stencil_server_t;
@@ -306,9 +342,10 @@ typedef struct stencil_server_stats {
 /* Start a server on the current device: a host thread that admits queued jobs
  * (first fit, in arrival order) while their state fits the HBM budget and a
  * slot is free, keeps admitted jobs' fields resident on the device, advances
- * all of them tick by tick (tick_steps RK steps each) and retires finished
- * jobs (result copied out, memory freed). Jobs arriving while others run are
- * admitted at the next tick boundary. */
+ * them tick by tick (tick_steps RK steps each; a tick takes resident jobs in
+ * order of least remaining work until it holds min_points points) and retires
+ * finished jobs (result copied out, memory freed). Jobs arriving while others
+ * run are admitted at the next tick boundary. */
 stencil_status stencil_server_create(const stencil_server_desc *desc, stencil_server_t *out);
 
 /* Cancel queued and running jobs, stop the thread and free everything.

@@ -37,7 +37,8 @@ class _Desc(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int * 3), ("radius", ctypes.c_int),
                 ("coeffs", ctypes.POINTER(ctypes.c_double)), ("dtype", ctypes.c_int),
                 ("bc", ctypes.c_int), ("flags", ctypes.c_uint), ("variant", ctypes.c_int),
-                ("tile", ctypes.c_int * 4)]
+                ("tile", ctypes.c_int * 4), ("row_pitch", ctypes.c_int),
+                ("x_offset", ctypes.c_int)]
 
 
 _lib = None
@@ -64,6 +65,9 @@ def _declare(L):
     L.stencil_version.restype = c_int
     L.stencil_padded_elems.argtypes = [c_int, ctypes.POINTER(c_int), c_int]
     L.stencil_padded_elems.restype = c_size
+    L.stencil_plan_padded_elems.argtypes = [_vp]
+    L.stencil_plan_padded_elems.restype = c_size
+    L.stencil_plan_halo.argtypes = [_vp, _vp, _vp]
     L.stencil_plan.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_vp)]
     L.stencil_plan_destroy.argtypes = [_vp]
     L.stencil_plan_variant.argtypes = [_vp]
@@ -134,11 +138,13 @@ class LinearPlan:
     (2r+1)^ndim tensor in NumPy order [s_z, s_y, s_x] (x fastest)."""
 
     def __init__(self, dims, radius, coeffs, dtype=F64, bc=PERIODIC, autotune=False,
-                 variant=VARIANT_AUTO, tile=None):
+                 variant=VARIANT_AUTO, tile=None, row_pitch=0, x_offset=0):
         self.dims = tuple(int(v) for v in dims)
         self.ndim = len(self.dims)
         self.radius = int(radius)
         self.dtype = dtype
+        self.x_offset = int(x_offset) or self.radius
+        self.row_pitch = int(row_pitch) or (self.x_offset + self.dims[0] + self.radius)
         c = np.ascontiguousarray(coeffs, dtype=np.float64).reshape(-1)
         if c.size != (2 * radius + 1) ** self.ndim:
             raise ValueError("coeffs must hold (2r+1)^ndim values")
@@ -153,6 +159,8 @@ class LinearPlan:
         d.flags = FLAG_AUTOTUNE if autotune else 0
         d.variant = variant
         d.tile = (ctypes.c_int * 4)(*(list(tile or []) + [0] * 4)[:4])
+        d.row_pitch = int(row_pitch)
+        d.x_offset = int(x_offset)
         h = _vp()
         check(lib().stencil_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -176,19 +184,41 @@ class LinearPlan:
         check(lib().stencil_reduce(self._h, ptrs, len(fields), dtype, out, stream_ptr(stream)))
         return np.array(out[:]).reshape(len(fields), 3)
 
+    @property
+    def storage_shape(self):
+        """Tensor shape [z, y, x] of one field in the plan's layout (rows of
+        row_pitch elements)."""
+        return padded_shape(self.dims, self.radius)[:-1] + (self.row_pitch,)
+
+    def padded(self, t):
+        """View of the padded field (Eq. 2 extents) inside a storage tensor:
+        columns [x_offset - r, x_offset + nx + r) of every row."""
+        lo = self.x_offset - self.radius
+        return t[..., lo:lo + self.dims[0] + 2 * self.radius]
+
     def empty(self, fill=None):
-        """A padded device tensor of the plan's shape and dtype."""
+        """A device tensor of the plan's storage shape and dtype."""
         import torch
-        t = torch.empty(padded_shape(self.dims, self.radius), dtype=torch_dtype(self.dtype),
-                        device="cuda")
+        t = torch.empty(self.storage_shape, dtype=torch_dtype(self.dtype), device="cuda")
         if fill is not None:
             t.fill_(fill)
         return t
 
+    def halo(self, t, stream=None):
+        """Periodic halo refresh of one field in the plan's layout."""
+        self._check_buf(t)
+        check(lib().stencil_plan_halo(self._h, ptr(t), stream_ptr(stream)))
+
+    def _check_buf(self, t):
+        n = int(lib().stencil_plan_padded_elems(self._h))
+        if t.numel() != n or not t.is_contiguous() or t.dtype != torch_dtype(self.dtype):
+            raise ValueError("buffer must be a contiguous tensor of the plan's storage shape "
+                             "and dtype")
+
     def apply(self, a, b, iters=1, stream=None, halo_valid=False):
         """Chained application; the result is in b for odd iters, else in a.
         halo_valid: a's periodic halo is already valid (no refresh launch)."""
-        n = padded_elems(self.dims, self.radius)
+        n = int(lib().stencil_plan_padded_elems(self._h))
         for t in (a, b):
             if t.numel() != n or not t.is_contiguous() or t.dtype != torch_dtype(self.dtype):
                 raise ValueError("buffer must be a contiguous padded tensor of the plan dtype")
@@ -222,7 +252,7 @@ class _RkDesc(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("ndim", ctypes.c_int), ("dims", ctypes.c_int * 3),
                 ("precision", ctypes.c_int), ("ds", ctypes.c_double * 3),
                 ("nu", ctypes.c_double), ("eta", ctypes.c_double), ("cs2", ctypes.c_double),
-                ("adv", ctypes.c_double * 3), ("block", ctypes.c_int * 2)]
+                ("adv", ctypes.c_double * 3), ("block", ctypes.c_int * 3)]
 
 
 class _Fields(ctypes.Structure):
@@ -274,7 +304,7 @@ class RkPlan:
         d.ds = (ctypes.c_double * 3)(*(list(ds) + [1.0] * (3 - len(ds))))
         d.nu, d.eta, d.cs2 = nu, eta, cs2
         d.adv = (ctypes.c_double * 3)(*(list(adv) + [0.0] * (3 - len(adv))))
-        d.block = (ctypes.c_int * 2)(*(list(block or []) + [0, 0])[:2])
+        d.block = (ctypes.c_int * 3)(*(list(block or []) + [0, 0, 0])[:3])
         L = lib()
         h = _vp()
         check(L.stencil_plan_rk(ctypes.byref(d), ctypes.byref(h)))
@@ -354,7 +384,8 @@ class _JobStatus(ctypes.Structure):
 class _ServerDesc(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int),
                 ("tick_steps", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("blocks", ctypes.c_int), ("queue_cap", ctypes.c_int)]
+                ("blocks", ctypes.c_int), ("queue_cap", ctypes.c_int),
+                ("min_points", ctypes.c_longlong)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -390,10 +421,10 @@ class Server:
     they are kept referenced until the job ends."""
 
     def __init__(self, hbm_budget=0, max_slots=256, tick_steps=10, use_graph=True, blocks=0,
-                 queue_cap=0):
+                 queue_cap=0, min_points=0):
         L = lib()
         d = _ServerDesc(hbm_budget, max_slots, tick_steps, 1 if use_graph else 0, blocks,
-                        queue_cap)
+                        queue_cap, min_points)
         h = _vp()
         check(L.stencil_server_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

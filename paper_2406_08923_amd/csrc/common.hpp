@@ -132,20 +132,25 @@ inline size_t dtype_size(int dtype)
 // ---------------------------------------------------------------------------
 
 // Interior extents n, radius r, padded strides. Unused axes have n = 1 and no
-// padding. Interior point (x, y, z) lives at padded cell (x+r, y+ry, z+rz).
+// padding. Interior point (x, y, z) lives at padded cell (x+ox, y+ry, z+rz):
+// by default ox = r and rows hold nx + 2r cells; a layout may instead start
+// the interior at column ox >= r and use a longer row pitch sy, e.g. to put
+// the interior of every row on a cache-line boundary.
 struct Geo {
     int ndim;
     int nx, ny, nz;
     int r, ry, rz;
+    int ox;         // column of interior x = 0
     int64_t sy, sz; // element strides of y and z in the padded array
 
     __host__ __device__ int64_t at(int x, int y, int z) const
     {
-        return static_cast<int64_t>(x + r) + sy * (y + ry) + sz * (z + rz);
+        return static_cast<int64_t>(x + ox) + sy * (y + ry) + sz * (z + rz);
     }
 };
 
-inline Geo make_geo(int ndim, const int *dims, int r)
+// pitch 0 / ox < 0 select the default layout (rows of nx + 2r, ox = r)
+inline Geo make_geo(int ndim, const int *dims, int r, int pitch = 0, int ox = -1)
 {
     Geo g;
     g.ndim = ndim;
@@ -155,7 +160,8 @@ inline Geo make_geo(int ndim, const int *dims, int r)
     g.r = r;
     g.ry = ndim > 1 ? r : 0;
     g.rz = ndim > 2 ? r : 0;
-    g.sy = g.nx + 2 * r;
+    g.ox = ox < 0 ? r : ox;
+    g.sy = pitch > 0 ? pitch : g.nx + 2 * r;
     g.sz = g.sy * (g.ny + 2 * g.ry);
     return g;
 }

@@ -109,8 +109,8 @@ template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out
     switch (p->lin.variant) {
     case STENCIL_VARIANT_STAR3D: {
         int fl = p->lin.sflags | (periodic ? 0 : STAR_FLAG_NOFUSE);
-        rc = launch_star3d(in, out, p->lin.g, p->lin.star, p->lin.reff, p->lin.ty, p->lin.ny,
-                           p->lin.pf, p->lin.lz, fl & 7, s);
+        rc = launch_star3d(in, out, p->lin.g, p->lin.star, p->lin.reff, p->lin.xw, p->lin.ty,
+                           p->lin.ny, p->lin.pf, p->lin.lz, fl & 15, s);
         if (rc == STENCIL_OK && periodic && (p->lin.sflags & STAR_FLAG_NOFUSE))
             rc = launch_halo<S>(out, p->lin.g, s);
         return rc;
@@ -130,6 +130,27 @@ int apply_t(stencil_plan_s *p, void *da, void *db, int iters, hipStream_t s, boo
 {
     S *a = static_cast<S *>(da), *b = static_cast<S *>(db);
     int rc = STENCIL_OK;
+    if (p->lin.bc == STENCIL_BC_PERIODIC && p->lin.variant == STENCIL_VARIANT_LINE1D &&
+        p->lin.t1d > 1) {
+        // temporally blocked: nl launches of up to T iterations each, with nl
+        // of the same parity as iters so the result lands where the
+        // one-iteration-per-launch contract puts it
+        using C = typename Store<S>::C;
+        const int T = p->lin.t1d;
+        int nl = (iters + T - 1) / T;
+        if ((nl & 1) != (iters & 1))
+            ++nl;
+        int done = 0;
+        for (int k = 0; k < nl && rc == STENCIL_OK; ++k) {
+            const int left = nl - k;
+            const int tk = (iters - done + left - 1) / left;
+            rc = launch_line1d_t<S>(a, b, p->lin.g, static_cast<const C *>(p->lin.d_dense), true,
+                                    p->lin.e1d, tk, s);
+            done += tk;
+            std::swap(a, b);
+        }
+        return rc;
+    }
     if (p->lin.bc == STENCIL_BC_PERIODIC && !halo_valid)
         rc = launch_halo<S>(a, p->lin.g, s);
     for (int k = 0; k < iters && rc == STENCIL_OK; ++k) {
@@ -152,9 +173,10 @@ int apply_any(stencil_plan_s *p, void *a, void *b, int iters, hipStream_t s,
 std::string tune_key(const stencil_plan_s *p)
 {
     char buf[256];
-    snprintf(buf, sizeof(buf), "lin|dt%d|nd%d|%dx%dx%d|r%d|reff%d|star%d|bc%d|nt%d", p->lin.dtype,
-             p->lin.g.ndim, p->lin.g.nx, p->lin.g.ny, p->lin.g.nz, p->lin.g.r, p->lin.reff,
-             p->lin.is_star ? 1 : 0, p->lin.bc, p->lin.ntaps);
+    snprintf(buf, sizeof(buf), "lin|dt%d|nd%d|%dx%dx%d|r%d|ox%d|sy%lld|reff%d|star%d|bc%d|nt%d",
+             p->lin.dtype, p->lin.g.ndim, p->lin.g.nx, p->lin.g.ny, p->lin.g.nz, p->lin.g.r,
+             p->lin.g.ox, (long long)p->lin.g.sy, p->lin.reff, p->lin.is_star ? 1 : 0, p->lin.bc,
+             p->lin.ntaps);
     return buf;
 }
 
@@ -165,11 +187,14 @@ void set_choice(stencil_plan_s *p, const TuneChoice &c)
         p->lin.ty = c.p0;
         p->lin.ny = c.p1;
         p->lin.lz = c.p2;
-        p->lin.sflags = c.p3 & 7;
+        p->lin.sflags = c.p3 & 15;
         const int pf = (c.p3 >> STAR_PF_SHIFT) & 15;
+        const int xw = (c.p3 >> STAR_XW_SHIFT) & 15;
         p->lin.pf = pf ? pf : 2;
+        p->lin.xw = xw ? xw : 1;
     } else if (c.variant == STENCIL_VARIANT_LINE1D) {
         p->lin.e1d = c.p0;
+        p->lin.t1d = c.p1 > 1 ? c.p1 : 1;
     } else {
         p->lin.gbx = c.p0;
         p->lin.gby = c.p1;
@@ -181,25 +206,39 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
     std::vector<TuneChoice> c;
     const Geo &g = p->lin.g;
     if (p->lin.is_star) {
-        const int shapes[][2] = {{4, 2}, {4, 4}, {8, 2}, {8, 4}, {16, 2}, {2, 8}};
-        const int lzs[] = {32, 64, 128, 256, g.nz};
-        for (auto &sh : shapes)
-            for (int pf : {2, 3})
-                for (int k = 0; k < 5; ++k) {
-                    const int lz = lzs[k];
-                    if ((k < 4 && lz >= g.nz && lz != 32) || (k == 4 && g.nz <= 32))
-                        continue;
-                    const int w = (pf << STAR_PF_SHIFT);
-                    c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, w | STAR_FLAG_XCD});
-                    c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz,
-                                 w | STAR_FLAG_XCD | STAR_FLAG_YFIRST});
-                    if (lz == 64)
-                        c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, w});
-                }
+        // (x waves, y lanes, rows per lane): tiles 64*xw x ty*ny
+        const int shapes[][3] = {{1, 8, 2}, {1, 4, 4}, {1, 8, 4}, {1, 16, 2}, {2, 4, 2}, {2, 4, 4},
+                                 {2, 8, 2}, {4, 2, 2}, {4, 2, 4}, {4, 4, 2}, {8, 1, 4}, {8, 2, 2}};
+        const int lzs[] = {32, 64, 128, g.nz};
+        for (auto &sh : shapes) {
+            if (64 * sh[0] > 2 * g.nx && sh[0] > 1)
+                continue; // tiles much wider than the grid only add idle lanes
+            for (int k = 0; k < 4; ++k) {
+                const int lz = lzs[k];
+                if ((k < 3 && lz >= g.nz && lz != 32) || (k == 3 && g.nz <= 32))
+                    continue;
+                const int w = (2 << STAR_PF_SHIFT) | (sh[0] << STAR_XW_SHIFT);
+                c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz, w | STAR_FLAG_XCD});
+                c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz,
+                             w | STAR_FLAG_XCD | STAR_FLAG_YFIRST});
+            }
+        }
+        // hardware-cached z march: (lanes along y, rows per lane)
+        const int hshapes[][2] = {{4, 1}, {4, 2}, {4, 4}, {2, 4}, {8, 2}};
+        for (auto &sh : hshapes)
+            for (int k = 0; k < 3; ++k) {
+                const int lz = lzs[k];
+                if (lz >= g.nz && lz != 32)
+                    continue;
+                c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, STAR_FLAG_HWC | STAR_FLAG_XCD});
+                c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, STAR_FLAG_HWC});
+            }
     }
     if (g.ndim == 1)
         for (int e : {1, 2, 4, 8})
-            c.push_back({STENCIL_VARIANT_LINE1D, e, 0, 0, 0});
+            for (int T : {1, 4, 8, 16})
+                if (T == 1 || p->lin.bc == STENCIL_BC_PERIODIC)
+                    c.push_back({STENCIL_VARIANT_LINE1D, e, T, 0, 0});
     if (g.ndim == 1) {
         c.push_back({STENCIL_VARIANT_GENERIC, 256, 1, 0, 0});
     } else {
@@ -213,7 +252,8 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
 TuneChoice default_choice(const stencil_plan_s *p)
 {
     if (p->lin.is_star)
-        return {STENCIL_VARIANT_STAR3D, 8, 2, 64, STAR_FLAG_XCD | (2 << STAR_PF_SHIFT)};
+        return {STENCIL_VARIANT_STAR3D, 8, 2, 32, STAR_FLAG_XCD | (2 << STAR_PF_SHIFT) |
+                                                      (1 << STAR_XW_SHIFT)};
     if (p->lin.g.ndim == 1)
         return {STENCIL_VARIANT_LINE1D, 4, 0, 0, 0};
     return {STENCIL_VARIANT_GENERIC, 64, 4, 0, 0};
@@ -254,7 +294,9 @@ int autotune(stencil_plan_s *p)
             continue;
         }
         if (hipEventRecord(e0, nullptr) != hipSuccess) break;
-        int rc = apply_any(p, a, b, 3, nullptr);
+        // 1-D plans are timed on 10 chained iterations so temporal blocking
+        // is weighed against per-iteration launches
+        int rc = apply_any(p, a, b, p->lin.g.ndim == 1 ? 10 : 3, nullptr);
         if (hipEventRecord(e1, nullptr) != hipSuccess) break;
         if (hipEventSynchronize(e1) != hipSuccess || rc != STENCIL_OK) {
             (void)hipGetLastError();
@@ -289,6 +331,13 @@ const char *stencil_last_error(void) { return g_err; }
 
 int stencil_version(void) { return 10000; }
 
+size_t stencil_plan_padded_elems(stencil_plan_t plan)
+{
+    if (!plan)
+        return 0;
+    return (size_t)padded_elems(plan->kind == PLAN_LINEAR ? plan->lin.g : plan->rk.g);
+}
+
 size_t stencil_padded_elems(int ndim, const int dims[3], int radius)
 {
     if (ndim < 1 || ndim > 3 || !dims || radius < 0)
@@ -319,6 +368,23 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
     if (rc) return rc;
     if (d->variant < STENCIL_VARIANT_AUTO || d->variant > STENCIL_VARIANT_LINE1D)
         return fail(STENCIL_EINVAL, "unknown variant %d", d->variant);
+    const int ox = d->x_offset ? d->x_offset : d->radius;
+    const int64_t min_pitch = (int64_t)ox + d->dims[0] + d->radius;
+    if (d->x_offset < 0 || d->row_pitch < 0)
+        return fail(STENCIL_EINVAL, "negative row_pitch or x_offset");
+    if (ox < d->radius || ox > (1 << 20))
+        return fail(STENCIL_EINVAL, "x_offset %d not in [radius %d, 2^20]", ox, d->radius);
+    if (d->row_pitch && d->ndim < 2)
+        return fail(STENCIL_EINVAL, "row_pitch needs ndim >= 2");
+    if (d->row_pitch && (d->row_pitch < min_pitch || d->row_pitch > (1 << 30)))
+        return fail(STENCIL_EINVAL, "row_pitch %d not in [x_offset + dims[0] + radius = %lld, 2^30]",
+                    d->row_pitch, (long long)min_pitch);
+    {
+        int64_t cells = d->row_pitch ? d->row_pitch : min_pitch;
+        for (int a = 1; a < d->ndim; ++a) cells *= (int64_t)d->dims[a] + 2 * d->radius;
+        if (cells > (int64_t(1) << 40))
+            return fail(STENCIL_EINVAL, "padded array too large");
+    }
     {
         const size_t K = 2 * (size_t)d->radius + 1;
         size_t nc = K;
@@ -340,7 +406,7 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
     const int r = d->radius, nd = d->ndim, K = 2 * r + 1;
     L.dtype = d->dtype;
     L.bc = d->bc;
-    L.g = make_geo(nd, d->dims, r);
+    L.g = make_geo(nd, d->dims, r, d->row_pitch ? d->row_pitch : (int)min_pitch, ox);
     const int Ky = nd > 1 ? K : 1, Kz = nd > 2 ? K : 1;
     L.dense.assign(d->coeffs, d->coeffs + (size_t)K * Ky * Kz);
 
@@ -432,9 +498,18 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
             if (t[0]) c.p0 = t[0];
             if (t[1]) c.p1 = t[1];
             if (t[2]) c.p2 = t[2];
-            c.p3 = t[3] & 0xf7; // explicit tiles set the flag word exactly
+            c.p3 = t[3] & 0xfff; // explicit tiles set the flag word exactly
         } else if (c.variant == STENCIL_VARIANT_LINE1D) {
             if (t[0]) c.p0 = t[0];
+            if (t[1]) c.p1 = t[1];
+            if (c.p1 > 1 && d->bc != STENCIL_BC_PERIODIC) {
+                stencil_plan_destroy(p);
+                return fail(STENCIL_EINVAL, "temporal blocking needs a periodic plan");
+            }
+            if (c.p1 < 0 || c.p1 > 64) {
+                stencil_plan_destroy(p);
+                return fail(STENCIL_EINVAL, "fused iterations must be 1..64");
+            }
         } else {
             if (t[0]) c.p0 = t[0];
             if (t[1]) c.p1 = t[1];
@@ -488,9 +563,10 @@ stencil_status stencil_plan_tile(stencil_plan_t p, int tile[4])
         tile[0] = L.ty;
         tile[1] = L.ny;
         tile[2] = L.lz;
-        tile[3] = L.sflags | (L.pf << STAR_PF_SHIFT);
+        tile[3] = L.sflags | (L.pf << STAR_PF_SHIFT) | (L.xw << STAR_XW_SHIFT);
     } else if (L.variant == STENCIL_VARIANT_LINE1D) {
         tile[0] = L.e1d;
+        tile[1] = L.t1d;
     } else {
         tile[0] = L.gbx;
         tile[1] = L.gby;
@@ -548,6 +624,23 @@ stencil_status stencil_halo_periodic(int ndim, const int dims[3], int radius, in
     case STENCIL_F64: return launch_halo<double>(static_cast<double *>(buf), g, s);
     case STENCIL_F32: return launch_halo<float>(static_cast<float *>(buf), g, s);
     default: return launch_halo<bf16>(static_cast<bf16 *>(buf), g, s);
+    }
+}
+
+stencil_status stencil_plan_halo(stencil_plan_t p, void *buf, void *stream)
+{
+    if (!p || p->kind != PLAN_LINEAR)
+        return fail(STENCIL_EINVAL, "not a linear plan");
+    int rc = check_device(p->device);
+    if (rc) return rc;
+    const size_t es = dtype_size(p->lin.dtype);
+    if (!buf || reinterpret_cast<uintptr_t>(buf) % es)
+        return fail(STENCIL_EINVAL, "NULL or misaligned buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (p->lin.dtype) {
+    case STENCIL_F64: return launch_halo<double>(static_cast<double *>(buf), p->lin.g, s);
+    case STENCIL_F32: return launch_halo<float>(static_cast<float *>(buf), p->lin.g, s);
+    default: return launch_halo<bf16>(static_cast<bf16 *>(buf), p->lin.g, s);
     }
 }
 

@@ -29,7 +29,9 @@ template <typename S>
 __global__ void __launch_bounds__(256) k_halo_periodic(S *a, Geo g, int64_t n_z, int64_t n_y,
                                                        int64_t total)
 {
-    const int64_t Px = g.sy, Py = g.sz / g.sy;
+    // logical padded extents (the cells that hold data; a longer row pitch
+    // only adds unused columns)
+    const int64_t Px = g.nx + 2 * g.r, Py = g.ny + 2 * g.ry;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         int qx, qy, qz;
@@ -61,7 +63,7 @@ __global__ void __launch_bounds__(256) k_halo_periodic(S *a, Geo g, int64_t n_z,
         int sx = wrap_pad(qx, g.r, g.nx);
         int sy = g.ry ? wrap_pad(qy, g.ry, g.ny) : qy;
         int sz = g.rz ? wrap_pad(qz, g.rz, g.nz) : qz;
-        a[qx + g.sy * qy + g.sz * qz] = a[sx + g.sy * sy + g.sz * sz];
+        a[g.at(qx - g.r, qy - g.ry, qz - g.rz)] = a[g.at(sx - g.r, sy - g.ry, sz - g.rz)];
     }
 }
 
@@ -69,7 +71,7 @@ template <typename S> int launch_halo(S *a, const Geo &g, hipStream_t s)
 {
     if (g.r == 0)
         return STENCIL_OK;
-    const int64_t Px = g.sy, Py = g.sz / g.sy;
+    const int64_t Px = g.nx + 2 * g.r, Py = g.ny + 2 * g.ry;
     int64_t n_z = g.rz ? 2 * g.rz * Px * Py : 0;
     int64_t n_y = g.ry ? (int64_t)g.nz * 2 * g.ry * Px : 0;
     int64_t n_x = (int64_t)g.nz * g.ny * 2 * g.r;
@@ -137,10 +139,10 @@ __global__ void __launch_bounds__(256)
     const int r = g.r;
     const int x0 = blockIdx.x * BX;
     const int W = BX + 2 * r;
-    // padded index of interior x0 - r is x0
+    // buf[i] holds interior x0 - r + i (clamped to the padded row)
     for (int i = threadIdx.x; i < W; i += NT) {
-        int q = min(x0 + i, g.nx + 2 * r - 1);
-        buf[i] = Store<S>::ld(in + q);
+        int xi = min(x0 - r + i, g.nx + r - 1);
+        buf[i] = Store<S>::ld(in + g.at(xi, 0, 0));
     }
     __syncthreads();
     const int K = 2 * r + 1;
@@ -175,37 +177,98 @@ int launch_line1d(const S *in, S *out, const Geo &g, const typename Store<S>::C 
 }
 
 // ---------------------------------------------------------------------------
+// 1-D line, temporally blocked: T chained iterations in one launch. A block
+// owning outputs [x0, x0 + BX) loads [x0 - rT, x0 + BX + rT) from the interior
+// with periodic wrap (the input halo is not read), iterates T times in LDS
+// (iteration i is valid on a region shrunk by r(i+1) on each side) and writes
+// its outputs and their periodic images. Each point of each iteration uses
+// the same taps in the same order as a single-iteration launch.
+// ---------------------------------------------------------------------------
+
+template <typename S, int E>
+__global__ void __launch_bounds__(256)
+    k_line1d_t(const S *__restrict__ in, S *__restrict__ out, Geo g,
+               const typename Store<S>::C *__restrict__ cs, int T, int fuse)
+{
+    using C = typename Store<S>::C;
+    constexpr int NT = 256, BX = NT * E;
+    extern __shared__ unsigned char smem_raw[];
+    const int r = g.r, n = g.nx;
+    const int W = BX + 2 * r * T;
+    C *cur = reinterpret_cast<C *>(smem_raw);
+    C *nxt = cur + W;
+    const int x0 = blockIdx.x * BX;
+    for (int i = threadIdx.x; i < W; i += NT) {
+        int xi = (x0 - r * T + i) % n;
+        if (xi < 0) xi += n;
+        cur[i] = Store<S>::ld(in + g.at(xi, 0, 0));
+    }
+    __syncthreads();
+    const int K = 2 * r + 1;
+    for (int it = 0; it < T; ++it) {
+        const int lo = r * (it + 1), hi = W - r * (it + 1);
+        for (int l = lo + threadIdx.x; l < hi; l += NT) {
+            C acc = 0;
+            for (int t = 0; t < K; ++t)
+                acc = fma(cs[t], cur[l - r + t], acc);
+            nxt[l] = acc;
+        }
+        __syncthreads();
+        C *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = threadIdx.x + e * NT;
+        const int x = x0 + k;
+        if (x < n)
+            store_periodic(out, g, x, 0, 0, cur[r * T + k], fuse != 0);
+    }
+}
+
+template <typename S>
+int launch_line1d_t(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs, bool fuse,
+                    int e, int T, hipStream_t s)
+{
+    using C = typename Store<S>::C;
+    const int bx = 256 * e;
+    const size_t shm = 2 * (size_t)(bx + 2 * g.r * T) * sizeof(C);
+    if (shm > 160 * 1024)
+        return fail(STENCIL_EUNSUPPORTED, "line1d: %d fused iterations need too much LDS", T);
+    dim3 grid((g.nx + bx - 1) / bx);
+    switch (e) {
+    case 1: hipLaunchKernelGGL((k_line1d_t<S, 1>), grid, dim3(256), shm, s, in, out, g, cs, T, fuse ? 1 : 0); break;
+    case 2: hipLaunchKernelGGL((k_line1d_t<S, 2>), grid, dim3(256), shm, s, in, out, g, cs, T, fuse ? 1 : 0); break;
+    case 4: hipLaunchKernelGGL((k_line1d_t<S, 4>), grid, dim3(256), shm, s, in, out, g, cs, T, fuse ? 1 : 0); break;
+    case 8: hipLaunchKernelGGL((k_line1d_t<S, 8>), grid, dim3(256), shm, s, in, out, g, cs, T, fuse ? 1 : 0); break;
+    default: return fail(STENCIL_EUNSUPPORTED, "line1d: outputs per lane %d not in {1,2,4,8}", e);
+    }
+    return check_launch("xcorr_line1d_t");
+}
+
+// ---------------------------------------------------------------------------
 // r = 0 streaming copy (effective-bandwidth measurement, Sec. 5.2)
 // ---------------------------------------------------------------------------
 
-// Four 16-byte loads in flight per lane before the stores, non-temporal so the
-// stream does not evict useful cache lines.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_copy16(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
                                                 int64_t n)
 {
+    // one 16-byte vector per lane over a grid covering the whole array (the
+    // shape that measured fastest on gfx950); the loop only runs again when
+    // the array exceeds the grid limit
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        u32x4 v0 = __builtin_nontemporal_load(src + i);
-        u32x4 v1 = __builtin_nontemporal_load(src + i + stride);
-        u32x4 v2 = __builtin_nontemporal_load(src + i + 2 * stride);
-        u32x4 v3 = __builtin_nontemporal_load(src + i + 3 * stride);
-        __builtin_nontemporal_store(v0, dst + i);
-        __builtin_nontemporal_store(v1, dst + i + stride);
-        __builtin_nontemporal_store(v2, dst + i + 2 * stride);
-        __builtin_nontemporal_store(v3, dst + i + 3 * stride);
-    }
-    for (; i < n; i += stride)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = src[i];
 }
 
 int launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t s)
 {
     int64_t n = (int64_t)(nbytes / 16);
-    int64_t blocks = (n + 4 * 256 - 1) / (4 * 256);
-    if (blocks > 256 * 32) blocks = 256 * 32;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > (int64_t(1) << 30)) blocks = int64_t(1) << 30;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const u32x4 *>(src), static_cast<u32x4 *>(dst), n);
@@ -219,7 +282,9 @@ int launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t s)
                                    const typename Store<S>::C *, int, bool, int, int,        \
                                    hipStream_t);                                             \
     template int launch_line1d<S>(const S *, S *, const Geo &, const typename Store<S>::C *, \
-                                  bool, int, hipStream_t);
+                                  bool, int, hipStream_t);                                   \
+    template int launch_line1d_t<S>(const S *, S *, const Geo &,                             \
+                                    const typename Store<S>::C *, bool, int, int, hipStream_t);
 INST(double)
 INST(float)
 INST(bf16)

@@ -40,7 +40,9 @@ struct StarCoefAny {
 constexpr int STAR_FLAG_XCD = 1;    // XCD-aware workgroup order
 constexpr int STAR_FLAG_NOFUSE = 2; // do not write periodic images
 constexpr int STAR_FLAG_YFIRST = 4; // tile numbers run fastest along y
+constexpr int STAR_FLAG_HWC = 8;    // hardware-cached z march (no LDS)
 constexpr int STAR_PF_SHIFT = 4;    // bits 4..7: prefetch depth (0 = default)
+constexpr int STAR_XW_SHIFT = 8;    // bits 8..11: tile width in waves (0 = 1)
 
 template <typename S> int launch_halo(S *a, const Geo &g, hipStream_t s);
 
@@ -50,11 +52,11 @@ int launch_generic(const S *in, S *out, const Geo &g, const int *offs,
                    hipStream_t s);
 
 // 3-D star kernel (star3d.hpp), one overload per storage type (star3d_*.hip).
-// R: tap radius (<= padding); ty, ny: tile shape; pf: prefetch depth; lz: z
-// planes per workgroup; flags: STAR_FLAG_*.
+// R: tap radius (<= padding); xw, ty, ny: tile shape (64*xw x ty*ny points);
+// pf: prefetch depth; lz: z planes per workgroup; flags: STAR_FLAG_*.
 #define STAR_DECL(S)                                                                         \
-    int launch_star3d(const S *in, S *out, const Geo &g, const StarCoefAny &cf, int R, int ty, \
-                      int ny, int pf, int lz, int flags, hipStream_t s);
+    int launch_star3d(const S *in, S *out, const Geo &g, const StarCoefAny &cf, int R, int xw, \
+                      int ty, int ny, int pf, int lz, int flags, hipStream_t s);
 STAR_DECL(double)
 STAR_DECL(float)
 STAR_DECL(bf16)
@@ -63,6 +65,12 @@ STAR_DECL(bf16)
 template <typename S>
 int launch_line1d(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs, bool fuse,
                   int e, hipStream_t s);
+
+// T chained iterations of a 1-D stencil in one launch (periodic only; reads
+// the interior with wrap, writes the output interior and its images).
+template <typename S>
+int launch_line1d_t(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs, bool fuse,
+                    int e, int T, hipStream_t s);
 
 int launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t s);
 

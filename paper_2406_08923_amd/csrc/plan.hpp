@@ -22,9 +22,9 @@ struct LinearPlan {
     void *d_dense = nullptr; // 1-D dense coefficients, arithmetic type
     // chosen variant and its launch parameters
     int variant = STENCIL_VARIANT_GENERIC;
-    int ty = 8, ny = 2, lz = 64, sflags = 0, pf = 2; // STAR3D
+    int ty = 8, ny = 2, lz = 32, sflags = 0, pf = 2, xw = 1; // STAR3D
     int gbx = 64, gby = 4;                   // GENERIC
-    int e1d = 4;                             // LINE1D
+    int e1d = 4, t1d = 1;                    // LINE1D: outputs per lane, fused iterations
 };
 
 struct RkPlan {

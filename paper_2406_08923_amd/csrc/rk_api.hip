@@ -145,6 +145,8 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     int bx = d->block[0] ? d->block[0] : 64, by = d->block[1] ? d->block[1] : 4;
     if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64)
         return fail(STENCIL_EINVAL, "block %dx%d must be a multiple of 64 lanes <= 256", bx, by);
+    if (d->block[2] != 0 && d->block[2] != 1)
+        return fail(STENCIL_EINVAL, "block[2] must be 0 or 1 (one z plane per workgroup)");
 
     auto *p = new (std::nothrow) stencil_plan_s();
     if (!p)

@@ -30,6 +30,7 @@ using namespace stn;
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int STARVE_TICKS = 16;
 
 struct SJob {
     uint64_t ticket = 0;
@@ -42,6 +43,7 @@ struct SJob {
     size_t bytes = 0;
     BatchJob bj{};
     int steps_tick = 0;
+    int idle_ticks = 0; // consecutive ticks the job was resident but left out
 };
 
 size_t job_bytes(const stencil_job &j)
@@ -103,6 +105,7 @@ struct stencil_server_s {
     RkCoeffs rk{};
     stencil_server_stats st{};
     FdWeights fd{};
+    long long min_points = 0;
 
     double clock() const
     {
@@ -237,16 +240,34 @@ struct stencil_server_s {
         return STENCIL_OK;
     }
 
-    // one tick over the active set; returns a status, *launches the number of
-    // kernel launches it enqueued
+    // one tick; returns a status, *launches the number of kernel launches it
+    // enqueued. Shortest remaining work first: resident jobs are taken in
+    // order of remaining point-steps until the tick holds at least
+    // min_points points per substep (enough to fill the GPU), so short jobs
+    // finish within a few ticks while long ones keep the device busy; the
+    // others wait resident for a later tick. A job left out for STARVE_TICKS
+    // ticks in a row is taken regardless, so none waits without bound.
     int tick(long long *launches)
     {
         auto *hdr = static_cast<BatchTableHeader *>(h_table);
         auto *rec = reinterpret_cast<BatchJob *>(hdr + 1);
-        int tiles = 0;
+        std::vector<std::shared_ptr<SJob>> order(active);
+        auto remaining = [](const SJob &j) {
+            return (double)(j.bj.g.nx) * j.bj.g.ny * j.bj.g.nz * (double)(j.d.steps - j.steps_done);
+        };
+        std::stable_sort(order.begin(), order.end(),
+                         [&](const std::shared_ptr<SJob> &a, const std::shared_ptr<SJob> &b) {
+                             return remaining(*a) < remaining(*b);
+                         });
+        for (auto &j : active)
+            j->steps_tick = 0;
+        int tiles = 0, njobs = 0;
         int maxsteps = 0;
-        for (size_t i = 0; i < active.size(); ++i) {
-            SJob &j = *active[i];
+        double points = 0;
+        for (auto &jp : order) {
+            SJob &j = *jp;
+            if (njobs > 0 && points >= (double)min_points && j.idle_ticks < STARVE_TICKS)
+                continue;
             j.steps_tick = (int)std::min<long long>(d.tick_steps, j.d.steps - j.steps_done);
             maxsteps = std::max(maxsteps, j.steps_tick);
             BatchJob b = j.bj;
@@ -255,11 +276,12 @@ struct stencil_server_s {
             b.tiles_y = (b.g.ny + BT_Y - 1) / BT_Y;
             b.tile_begin = tiles;
             tiles += b.tiles_x * b.tiles_y * b.g.nz;
-            rec[i] = b;
+            points += (double)b.g.nx * b.g.ny * b.g.nz;
+            rec[njobs++] = b;
         }
-        hdr->njobs = (int)active.size();
+        hdr->njobs = njobs;
         hdr->total_tiles = tiles;
-        if (hipMemcpyAsync(d_table, h_table, batch_table_bytes((int)active.size()),
+        if (hipMemcpyAsync(d_table, h_table, batch_table_bytes(njobs),
                            hipMemcpyHostToDevice, stream) != hipSuccess)
             return STENCIL_EDEVICE;
         int rc = STENCIL_OK;
@@ -366,8 +388,9 @@ struct stencil_server_s {
             std::vector<std::shared_ptr<SJob>> keep;
             for (auto &j : active) {
                 j->steps_done += j->steps_tick;
+                j->idle_ticks = j->steps_tick ? 0 : j->idle_ticks + 1;
                 j->bj.parity ^= (3 * j->steps_tick) & 1;
-                if (j->t_first < 0) j->t_first = te;
+                if (j->t_first < 0 && j->steps_tick > 0) j->t_first = te;
                 bool cancel;
                 {
                     std::lock_guard<std::mutex> lk(mu);
@@ -460,6 +483,7 @@ stencil_status stencil_server_create(const stencil_server_desc *desc, stencil_se
     }
     s->fd.w2[0] = w2[3];
     s->st.bytes_budget = s->d.hbm_budget;
+    s->min_points = s->d.min_points > 0 ? s->d.min_points : (long long)4 << 20;
     s->t0 = std::chrono::steady_clock::now();
     try {
         s->worker = std::thread([s] { s->run(); });

@@ -8,13 +8,16 @@
 
 namespace stn {
 
-// Supported (TY, NY) shapes: lanes along y, rows per lane. Tiles are 64 x TY*NY.
-#define STAR_SHAPES(X) X(4, 2) X(4, 4) X(8, 2) X(8, 4) X(16, 2) X(2, 8)
+// Supported shapes (XW, TY, NY): tile width 64*XW lanes along x, TY lanes
+// along y, NY rows per lane. Tiles are 64*XW x TY*NY points.
+#define STAR_SHAPES(X)                                                                       \
+    X(1, 8, 2) X(1, 4, 4) X(1, 8, 4) X(1, 16, 2) X(2, 4, 2) X(2, 4, 4) X(2, 8, 2)             \
+    X(4, 2, 2) X(4, 2, 4) X(4, 4, 2) X(8, 1, 4) X(8, 2, 2)
 // Supported prefetch depths (planes in flight ahead of the one computed).
-#define STAR_PREFETCH(X) X(2) X(3)
+#define STAR_PREFETCH(X) X(2)
 
-template <int R, int NY, int TY> struct StarShape {
-    static constexpr int TXW = 64;           // lanes along x
+template <int R, int NY, int TY, int XW> struct StarShape {
+    static constexpr int TXW = 64 * XW;      // lanes along x
     static constexpr int ROWS = TY * NY;     // output rows per tile
     static constexpr int LW = TXW + 2 * R;   // LDS row width
     static constexpr int LH = ROWS + 2 * R;  // LDS rows
@@ -40,7 +43,7 @@ __device__ __forceinline__ int xcd_remap(int lin, int total)
     return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
-// Workgroup = 64 x TY lanes; lane (tx, ty) owns column x = x0 + tx and the NY
+// Workgroup = 64*XW x TY lanes; lane (tx, ty) owns column x = x0 + tx and the NY
 // consecutive rows y0 + ty*NY + j, and marches along z over a chunk of lz
 // output planes. Per lane and row the 2R+1 column values around the current
 // plane live in registers (the z taps). The current plane with its x and y
@@ -51,13 +54,13 @@ __device__ __forceinline__ int xcd_remap(int lin, int total)
 // barrier of plane z, so PF planes of HBM latency overlap the arithmetic.
 // All loads are buffer loads: the lane supplies its in-plane byte offset, the
 // plane offset is a wave-uniform scalar.
-template <typename S, int R, int NY, int TY, int PF>
-__global__ void __launch_bounds__(64 * TY)
+template <typename S, int R, int NY, int TY, int XW, int PF>
+__global__ void __launch_bounds__(64 * XW * TY)
     k_star3d(const S *__restrict__ in, S *__restrict__ out, Geo g,
              StarCoef<typename Store<S>::C, R> cf, int lz, int gx, int gy, int gz, int flags)
 {
     using C = typename Store<S>::C;
-    using SH = StarShape<R, NY, TY>;
+    using SH = StarShape<R, NY, TY, XW>;
     constexpr uint32_t es = sizeof(S);
     __shared__ C lds[2][SH::LH][SH::LW];
 
@@ -70,8 +73,8 @@ __global__ void __launch_bounds__(64 * TY)
     const int bzi = lin / (gx * gy);
 
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int tid = tx + 64 * ty;
-    const int x0 = bxi * 64, y0 = byi * SH::ROWS;
+    const int tid = tx + SH::TXW * ty;
+    const int x0 = bxi * SH::TXW, y0 = byi * SH::ROWS;
     const int z0 = bzi * lz;
     const int z1 = min(z0 + lz, g.nz);
     const bool fuse = (flags & STAR_FLAG_NOFUSE) == 0;
@@ -82,7 +85,7 @@ __global__ void __launch_bounds__(64 * TY)
     // byte offset of interior column (x, y) within a plane; plane z adds
     // (z + rz) * sz * es as the scalar operand
     auto col = [&](int xx, int yy) {
-        return uint32_t(xx + g.r + g.sy * (yy + g.ry)) * es;
+        return uint32_t(xx + g.ox + g.sy * (yy + g.ry)) * es;
     };
     auto plane = [&](int zz) { return uint32_t(zz + g.rz) * uint32_t(g.sz) * es; };
 
@@ -210,28 +213,29 @@ __global__ void __launch_bounds__(64 * TY)
     }
 }
 
-template <typename S, int R, int NY, int TY, int PF>
+template <typename S, int R, int NY, int TY, int XW, int PF>
 int launch_star3d_t(const S *in, S *out, const Geo &g,
                     const StarCoef<typename Store<S>::C, R> &cf, int lz, int flags, hipStream_t s)
 {
-    using SH = StarShape<R, NY, TY>;
-    int gx = (g.nx + 63) / 64, gy = (g.ny + SH::ROWS - 1) / SH::ROWS, gz = (g.nz + lz - 1) / lz;
+    using SH = StarShape<R, NY, TY, XW>;
+    int gx = (g.nx + SH::TXW - 1) / SH::TXW, gy = (g.ny + SH::ROWS - 1) / SH::ROWS;
+    int gz = (g.nz + lz - 1) / lz;
     int64_t total = (int64_t)gx * gy * gz;
     if (total > 0x7fffffff)
         return fail(STENCIL_EUNSUPPORTED, "star3d: grid too large");
-    hipLaunchKernelGGL((k_star3d<S, R, NY, TY, PF>), dim3((unsigned)total), dim3(64, TY), 0, s,
-                       in, out, g, cf, lz, gx, gy, gz, flags);
+    hipLaunchKernelGGL((k_star3d<S, R, NY, TY, XW, PF>), dim3((unsigned)total),
+                       dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
     return check_launch("xcorr_star3d");
 }
 
-template <typename S, int R, int NY, int TY>
+template <typename S, int R, int NY, int TY, int XW>
 int launch_star3d_pf(const S *in, S *out, const Geo &g,
                      const StarCoef<typename Store<S>::C, R> &cf, int pf, int lz, int flags,
                      hipStream_t s)
 {
 #define STAR_CASE_PF(PF_)                                                                    \
     if (pf == PF_)                                                                           \
-        return launch_star3d_t<S, R, NY, TY, PF_>(in, out, g, cf, lz, flags, s);
+        return launch_star3d_t<S, R, NY, TY, XW, PF_>(in, out, g, cf, lz, flags, s);
     STAR_PREFETCH(STAR_CASE_PF)
 #undef STAR_CASE_PF
     return fail(STENCIL_EUNSUPPORTED, "star3d: unsupported prefetch depth %d", pf);
@@ -239,30 +243,173 @@ int launch_star3d_pf(const S *in, S *out, const Geo &g,
 
 template <typename S, int R>
 int launch_star3d_r(const S *in, S *out, const Geo &g, const StarCoef<typename Store<S>::C, R> &cf,
-                    int ty, int ny, int pf, int lz, int flags, hipStream_t s)
+                    int xw, int ty, int ny, int pf, int lz, int flags, hipStream_t s)
 {
-#define STAR_CASE(TY_, NY_)                                                                  \
-    if (ty == TY_ && ny == NY_)                                                              \
-        return launch_star3d_pf<S, R, NY_, TY_>(in, out, g, cf, pf, lz, flags, s);
+#define STAR_CASE(XW_, TY_, NY_)                                                             \
+    if (xw == XW_ && ty == TY_ && ny == NY_)                                                 \
+        return launch_star3d_pf<S, R, NY_, TY_, XW_>(in, out, g, cf, pf, lz, flags, s);
     STAR_SHAPES(STAR_CASE)
 #undef STAR_CASE
-    return fail(STENCIL_EUNSUPPORTED, "star3d: unsupported tile (ty=%d, ny=%d)", ty, ny);
+    return fail(STENCIL_EUNSUPPORTED, "star3d: unsupported tile (xw=%d, ty=%d, ny=%d)", xw, ty,
+                ny);
+}
+
+
+// Hardware-cached variant (the HWC strategy of Sec. 4.1/4.4) of the z march:
+// no LDS and no barriers. Lane (tx, ty) owns column x and NY consecutive rows
+// and marches along z with the 2R+1 column values in registers (z taps); the
+// x and y taps of the current plane are buffer loads that hit in L1/L2 because
+// neighbouring lanes and waves load the same lines in the same plane. Per
+// lane the base offset is the corner (x - R, y - R) of its neighbourhood, so
+// x taps differ by an immediate and y taps by a wave-uniform scalar.
+template <typename S, int R, int NY, int TY>
+__global__ void __launch_bounds__(64 * TY)
+    k_star3d_hwc(const S *__restrict__ in, S *__restrict__ out, Geo g,
+                 StarCoef<typename Store<S>::C, R> cf, int lz, int gx, int gy, int gz, int flags)
+{
+    using C = typename Store<S>::C;
+    constexpr uint32_t es = sizeof(S);
+    constexpr int ROWS = TY * NY;
+    int lin = blockIdx.x;
+    const int total = gx * gy * gz;
+    if (flags & STAR_FLAG_XCD) lin = xcd_remap(lin, total);
+    const bool yfirst = (flags & STAR_FLAG_YFIRST) != 0;
+    const int byi = yfirst ? lin % gy : (lin / gx) % gy;
+    const int bxi = yfirst ? (lin / gy) % gx : lin % gx;
+    const int bzi = lin / (gx * gy);
+    const int x = bxi * 64 + threadIdx.x;
+    const int y0 = byi * ROWS + threadIdx.y * NY;
+    const int z0 = bzi * lz;
+    const int z1 = min(z0 + lz, g.nz);
+    const bool fuse = (flags & STAR_FLAG_NOFUSE) == 0;
+    const Buf src = make_buf(in, uint64_t(padded_elems(g)) * es);
+    const uint32_t row = uint32_t(g.sy) * es;
+    auto cl = [](int v, int n) { return min(max(v, -R), n + R - 1); };
+    auto plane = [&](int zz) { return uint32_t(zz + g.rz) * uint32_t(g.sz) * es; };
+    // lowest corner of the lane's neighbourhood (x - R, y0 - R), clamped in x
+    const int xc = min(max(x, 0), g.nx - 1);
+    const uint32_t base = uint32_t(xc - R + g.ox + g.sy * (y0 - R + g.ry)) * es;
+    // window values: column x, rows y0 + j (clamped rows read valid memory)
+    uint32_t col_off[NY];
+#pragma unroll
+    for (int j = 0; j < NY; ++j)
+        col_off[j] = uint32_t(xc + g.ox + g.sy * (cl(y0 + j, g.ny) + g.ry)) * es;
+    C win[NY][2 * R + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k)
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+            win[j][k + 1] = BufLd<S>::ld(src, col_off[j], plane(z0 - R + k));
+    C pre[NY];
+#pragma unroll
+    for (int j = 0; j < NY; ++j)
+        pre[j] = BufLd<S>::ld(src, col_off[j], plane(min(z0, z1 - 1) + R));
+    // the y range of the neighbourhood may leave the padded array only for
+    // clamped rows past the grid; their outputs are not stored, and loads
+    // beyond the buffer return zero
+    for (int z = z0; z < z1; ++z) {
+#pragma unroll
+        for (int j = 0; j < NY; ++j) {
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k) win[j][k] = win[j][k + 1];
+            win[j][2 * R] = pre[j];
+        }
+        const int zn = min(z + 1, z1 - 1);
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+            pre[j] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+        const uint32_t pz = plane(z);
+        // y taps outside the lane's own rows: rows y0 - R .. y0 - 1 and
+        // y0 + NY .. y0 + NY + R - 1 of column x
+        C yl[R], yh[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            yl[m] = BufLd<S>::ld(src, base + R * es, pz + m * row);
+            yh[m] = BufLd<S>::ld(src, base + R * es, pz + (R + NY + m) * row);
+        }
+#pragma unroll
+        for (int j = 0; j < NY; ++j) {
+            C acc = cf.c0 * win[j][R];
+#pragma unroll
+            for (int m = 1; m <= R; ++m) {
+                acc = fma(cf.zm[m - 1], win[j][R - m], acc);
+                acc = fma(cf.zp[m - 1], win[j][R + m], acc);
+            }
+            const uint32_t prow = pz + (R + j) * row;
+#pragma unroll
+            for (int m = 1; m <= R; ++m) {
+                acc = fma(cf.xm[m - 1], BufLd<S>::ld(src, base + (R - m) * es, prow), acc);
+                acc = fma(cf.xp[m - 1], BufLd<S>::ld(src, base + (R + m) * es, prow), acc);
+            }
+#pragma unroll
+            for (int m = 1; m <= R; ++m) {
+                const int jm = j - m, jp = j + m;
+                const C vm = jm >= 0 ? win[jm >= 0 ? jm : 0][R] : yl[R + jm];
+                const C vp = jp < NY ? win[jp < NY ? jp : 0][R] : yh[jp - NY];
+                acc = fma(cf.ym[m - 1], vm, acc);
+                acc = fma(cf.yp[m - 1], vp, acc);
+            }
+            const int y = y0 + j;
+            if (x < g.nx && y < g.ny)
+                store_periodic(out, g, x, y, z, acc, fuse);
+        }
+    }
+}
+
+template <typename S, int R, int NY, int TY>
+int launch_star3d_hwc_t(const S *in, S *out, const Geo &g,
+                        const StarCoef<typename Store<S>::C, R> &cf, int lz, int flags,
+                        hipStream_t s)
+{
+    constexpr int ROWS = TY * NY;
+    int gx = (g.nx + 63) / 64, gy = (g.ny + ROWS - 1) / ROWS, gz = (g.nz + lz - 1) / lz;
+    int64_t total = (int64_t)gx * gy * gz;
+    if (total > 0x7fffffff)
+        return fail(STENCIL_EUNSUPPORTED, "star3d: grid too large");
+    hipLaunchKernelGGL((k_star3d_hwc<S, R, NY, TY>), dim3((unsigned)total), dim3(64, TY), 0, s,
+                       in, out, g, cf, lz, gx, gy, gz, flags);
+    return check_launch("xcorr_star3d_hwc");
+}
+
+// Shapes (TY, NY) of the hardware-cached variant.
+#define STAR_HWC_SHAPES(X) X(4, 1) X(4, 2) X(4, 4) X(2, 4) X(8, 2)
+
+template <typename S, int R>
+int launch_star3d_hwc_r(const S *in, S *out, const Geo &g,
+                        const StarCoef<typename Store<S>::C, R> &cf, int ty, int ny, int lz,
+                        int flags, hipStream_t s)
+{
+#define STAR_HWC_CASE(TY_, NY_)                                                              \
+    if (ty == TY_ && ny == NY_)                                                              \
+        return launch_star3d_hwc_t<S, R, NY_, TY_>(in, out, g, cf, lz, flags, s);
+    STAR_HWC_SHAPES(STAR_HWC_CASE)
+#undef STAR_HWC_CASE
+    return fail(STENCIL_EUNSUPPORTED, "star3d (cached): unsupported tile (ty=%d, ny=%d)", ty, ny);
 }
 
 template <typename S>
-int launch_star3d_impl(const S *in, S *out, const Geo &g, const StarCoefAny &cfa, int R, int ty,
-                       int ny, int pf, int lz, int flags, hipStream_t s)
+int launch_star3d_impl(const S *in, S *out, const Geo &g, const StarCoefAny &cfa, int R, int xw,
+                       int ty, int ny, int pf, int lz, int flags, hipStream_t s)
 {
     using C = typename Store<S>::C;
     if (R > g.r || g.ndim != 3)
         return fail(STENCIL_EINVAL, "star3d: tap radius %d exceeds padding %d", R, g.r);
     if (uint64_t(padded_elems(g)) * sizeof(S) >= (uint64_t(1) << 32))
         return fail(STENCIL_EUNSUPPORTED, "star3d: arrays of 4 GiB or more are not supported");
+    if (flags & STAR_FLAG_HWC) {
+        switch (R) {
+        case 1: return launch_star3d_hwc_r<S, 1>(in, out, g, cfa.get<C, 1>(), ty, ny, lz, flags, s);
+        case 2: return launch_star3d_hwc_r<S, 2>(in, out, g, cfa.get<C, 2>(), ty, ny, lz, flags, s);
+        case 3: return launch_star3d_hwc_r<S, 3>(in, out, g, cfa.get<C, 3>(), ty, ny, lz, flags, s);
+        case 4: return launch_star3d_hwc_r<S, 4>(in, out, g, cfa.get<C, 4>(), ty, ny, lz, flags, s);
+        }
+        return fail(STENCIL_EUNSUPPORTED, "star3d: radius %d not in 1..4", R);
+    }
     switch (R) {
-    case 1: return launch_star3d_r<S, 1>(in, out, g, cfa.get<C, 1>(), ty, ny, pf, lz, flags, s);
-    case 2: return launch_star3d_r<S, 2>(in, out, g, cfa.get<C, 2>(), ty, ny, pf, lz, flags, s);
-    case 3: return launch_star3d_r<S, 3>(in, out, g, cfa.get<C, 3>(), ty, ny, pf, lz, flags, s);
-    case 4: return launch_star3d_r<S, 4>(in, out, g, cfa.get<C, 4>(), ty, ny, pf, lz, flags, s);
+    case 1: return launch_star3d_r<S, 1>(in, out, g, cfa.get<C, 1>(), xw, ty, ny, pf, lz, flags, s);
+    case 2: return launch_star3d_r<S, 2>(in, out, g, cfa.get<C, 2>(), xw, ty, ny, pf, lz, flags, s);
+    case 3: return launch_star3d_r<S, 3>(in, out, g, cfa.get<C, 3>(), xw, ty, ny, pf, lz, flags, s);
+    case 4: return launch_star3d_r<S, 4>(in, out, g, cfa.get<C, 4>(), xw, ty, ny, pf, lz, flags, s);
     }
     return fail(STENCIL_EUNSUPPORTED, "star3d: radius %d not in 1..4", R);
 }

@@ -2,9 +2,9 @@
 #include "star3d.hpp"
 
 namespace stn {
-int launch_star3d(const bf16 *in, bf16 *out, const Geo &g, const StarCoefAny &cf, int R, int ty,
-                  int ny, int pf, int lz, int flags, hipStream_t s)
+int launch_star3d(const bf16 *in, bf16 *out, const Geo &g, const StarCoefAny &cf, int R, int xw,
+                  int ty, int ny, int pf, int lz, int flags, hipStream_t s)
 {
-    return launch_star3d_impl<bf16>(in, out, g, cf, R, ty, ny, pf, lz, flags, s);
+    return launch_star3d_impl<bf16>(in, out, g, cf, R, xw, ty, ny, pf, lz, flags, s);
 }
 } // namespace stn

@@ -41,3 +41,15 @@ def diffusion_number(n, alpha=1.0, dt_factor=1e-3):
     diffusion setup of Table B2)."""
     ds = 2.0 * math.pi / n
     return alpha * dt_factor * ds / ds ** 2
+
+
+def aligned_layout(nx, r, elem_bytes, line=128):
+    """(row_pitch, x_offset) that start the interior of every row on a
+    ``line``-byte boundary: x_offset is the smallest multiple of the line
+    (in elements) that is >= r, the pitch the smallest multiple >= x_offset +
+    nx + r. Allocations from the HIP allocator are at least 256-byte
+    aligned, so every interior row then starts a cache line."""
+    per = max(1, line // elem_bytes)
+    ox = -(-r // per) * per
+    pitch = -(-(ox + nx + r) // per) * per
+    return pitch, ox

@@ -73,6 +73,8 @@ def _plan_rc(**kw):
     d.dtype = kw.get("dtype", S.F64)
     d.bc = kw.get("bc", S.PERIODIC)
     d.variant = kw.get("variant", S.VARIANT_AUTO)
+    d.row_pitch = kw.get("row_pitch", 0)
+    d.x_offset = kw.get("x_offset", 0)
     h = ctypes.c_void_p()
     return S.lib().stencil_plan(ctypes.byref(d), ctypes.byref(h))
 
@@ -80,7 +82,13 @@ def _plan_rc(**kw):
 @pytest.mark.parametrize("kw", [dict(ndim=4), dict(ndim=0), dict(radius=9), dict(radius=-1),
                                 dict(coeffs=None), dict(dtype=7), dict(bc=3),
                                 dict(dims=(2, 8, 8), radius=3, coeffs=np.ones(343)),
-                                dict(dims=(0, 8, 8)), dict(variant=9)])
+                                dict(dims=(0, 8, 8)), dict(variant=9),
+                                # layout: x_offset below the radius, pitch too short
+                                # for x_offset + nx + r, pitch on a 1-D field, negatives
+                                dict(radius=2, x_offset=1, coeffs=np.ones(125)),
+                                dict(row_pitch=12, x_offset=4),
+                                dict(ndim=1, row_pitch=16, coeffs=np.ones(3)),
+                                dict(row_pitch=-1), dict(x_offset=-2)])
 def test_plan_rejects_bad_descriptors_without_a_device(kw):
     assert _plan_rc(**kw) == -1
     assert S.lib().stencil_last_error()
@@ -108,3 +116,15 @@ def test_copy_and_halo_validate_before_launch():
 def test_apply_rejects_null_plan():
     assert S.lib().stencil_apply(None, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 1,
                                  None) == -1
+
+
+def test_layout_helper_aligns_rows():
+    from paper_2406_08923_amd.workloads import aligned_layout
+    assert aligned_layout(512, 3, 8) == (544, 16)
+    assert aligned_layout(512, 3, 4) == (576, 32)
+    assert aligned_layout(100, 40, 8) == (192, 48)
+    for nx, r, es in [(7, 3, 2), (512, 8, 8), (1, 1, 4)]:
+        pitch, ox = aligned_layout(nx, r, es)
+        assert ox >= r and pitch >= ox + nx + r
+        assert (ox * es) % 128 == 0 and (pitch * es) % 128 == 0
+    assert S.lib().stencil_plan_padded_elems(None) == 0

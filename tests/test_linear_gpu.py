@@ -134,9 +134,12 @@ def rand_star(r, seed):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("tile", [(4, 2, 64, 0x20), (4, 4, 64, 0x31), (2, 8, 8, 0x21),
-                                  (8, 2, 13, 0x30), (4, 2, 5, 0x31), (8, 4, 64, 0x22),
-                                  (16, 2, 7, 0x33), (8, 2, 1, 0x31)])
+@pytest.mark.parametrize("tile", [(8, 2, 64, 0x120), (4, 4, 64, 0x125), (8, 4, 8, 0x121),
+                                  (16, 2, 13, 0x120), (4, 2, 5, 0x225), (4, 4, 64, 0x222),
+                                  (8, 2, 7, 0x227), (2, 2, 1, 0x421), (2, 4, 9, 0x424),
+                                  (4, 2, 6, 0x423), (1, 4, 11, 0x825), (2, 2, 64, 0x821),
+                                  (4, 1, 64, 0x8), (4, 4, 13, 0x9), (2, 4, 7, 0xd),
+                                  (8, 2, 5, 0x9), (4, 2, 64, 0xa)])
 def test_star3d_tiles_diffusion(dtype, tile):
     g = diffusion_star_exact(3, 3, 0.0815)
     run_case((70, 37, 29), 3, g, dtype, S.STAR3D, tile=tile)
@@ -146,23 +149,26 @@ def test_star3d_tiles_diffusion(dtype, tile):
 @pytest.mark.parametrize("dtype", [S.F64, S.F32])
 def test_star3d_asymmetric_random_taps(r, dtype):
     # asymmetric coefficients: a swapped side or axis would show
-    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(4, 2, 8, 0x31))
-    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(16, 2, 5, 0x20))
+    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(4, 4, 8, 0x121))
+    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(16, 2, 5, 0x120))
+    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(2, 4, 6, 0x425))
+    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(4, 2, 6, 0x9))
 
 
 def test_star3d_tap_radius_below_padding():
     # radius-4 padding, radius-2 taps: the plan runs a radius-2 kernel
     g = np.zeros((9, 9, 9))
     g[2:7, 2:7, 2:7] = rand_star(2, 5)
-    p = run_case((40, 20, 12), 4, g, S.F64, S.STAR3D, tile=(4, 2, 8, 0x21))
+    p = run_case((40, 20, 12), 4, g, S.F64, S.STAR3D, tile=(4, 2, 8, 0x221))
     assert p.variant == S.STAR3D
 
 
 @pytest.mark.parametrize("dims,r", [((3, 3, 3), 3), ((5, 4, 7), 3), ((4, 5, 6), 4), ((1, 1, 1), 1)])
 def test_star3d_tiny_periodic_grids(dims, r):
     # n < 2r: a point has periodic images on both sides
-    run_case(dims, r, rand_star(r, 2), S.F64, S.STAR3D, tile=(4, 2, 2, 0x31))
-    run_case(dims, r, rand_star(r, 2), S.F64, S.STAR3D, tile=(2, 8, 3, 0x20))
+    run_case(dims, r, rand_star(r, 2), S.F64, S.STAR3D, tile=(4, 2, 2, 0x221))
+    run_case(dims, r, rand_star(r, 2), S.F64, S.STAR3D, tile=(8, 2, 3, 0x120))
+    run_case(dims, r, rand_star(r, 2), S.F64, S.STAR3D, tile=(2, 4, 2, 0x9))
     run_case(dims, r, rand_star(r, 2), S.F64, S.GENERIC)
 
 
@@ -195,7 +201,7 @@ def test_r0_copy_stencil():
     run_case((33, 17, 9), 0, np.array([[[2.0]]]), S.F64, S.GENERIC)
 
 
-@pytest.mark.parametrize("variant,tile", [(S.STAR3D, (4, 4, 16, 0x31)), (S.GENERIC, None)])
+@pytest.mark.parametrize("variant,tile", [(S.STAR3D, (4, 4, 16, 0x125)), (S.GENERIC, None)])
 @pytest.mark.parametrize("iters", [6, 7])
 def test_chained_iterations_ping_pong(variant, tile, iters):
     g = diffusion_star_exact(3, 3, 0.2)
@@ -209,7 +215,7 @@ def test_user_halo_reads_caller_halo_and_writes_interior_only(variant):
     rng = np.random.default_rng(12)
     a_host = rng.uniform(-1, 1, O.padded_shape(dims, r))  # non-periodic halo
     plan = S.LinearPlan(dims, r, g, bc=S.USER_HALO, variant=variant,
-                        tile=(4, 2, 8, 0x21) if variant == S.STAR3D else None)
+                        tile=(4, 2, 8, 0x221) if variant == S.STAR3D else None)
     a = dev(a_host, S.F64)
     b = plan.empty(fill=123.0)
     plan.apply(a, b, 1)
@@ -242,6 +248,91 @@ def test_apply_validation_on_device():
 # full sizes of the benchmark workloads
 # ---------------------------------------------------------------------------
 
+# ---------------------------------------------------------------------------
+# pitched layout: interior at column x_offset of rows of row_pitch elements
+# ---------------------------------------------------------------------------
+
+def run_pitched(dims, r, g, dtype, variant, row_pitch, x_offset, tile=None, iters=1, seed=5,
+                bc=S.PERIODIC):
+    inner = to_storage_values(inputs.uniform_field(dims, seed), dtype)
+    plan = S.LinearPlan(dims, r, g, dtype=dtype, variant=variant, tile=tile, bc=bc,
+                        row_pitch=row_pitch, x_offset=x_offset)
+    store = np.full(plan.storage_shape, 11.0)  # cells outside the padded rows
+    pad = np.full(O.padded_shape(dims, r), 7.0)
+    O.interior(pad, r)[...] = inner
+    if bc == S.USER_HALO:
+        pad = O.pad_periodic(inner, r)
+    lo = plan.x_offset - r
+    store[..., lo:lo + dims[0] + 2 * r] = pad
+    a = dev(store, dtype)
+    b = plan.empty(fill=-3.0)
+    res_t = plan.apply(a, b, iters)
+    full = host(res_t)
+    res = host(plan.padded(res_t))
+    torch.cuda.synchronize()
+    ref = oracle_apply(inner, r, g, iters)
+    ntaps = int(np.count_nonzero(g))
+    absconv = None
+    if dtype != S.F64:
+        assert iters == 1
+        absconv = O.interior(O.xcorr(np.abs(O.pad_periodic(inner, r)), r, np.abs(g)), r)
+    what = "%s r=%d pitch=%d ox=%d" % (dims, r, row_pitch, x_offset)
+    assert_close(O.interior(res, r), O.interior(ref, r), dtype, absconv, ntaps, what=what)
+    if bc == S.PERIODIC:
+        assert np.array_equal(res, O.fill_periodic(res.copy(), r)), what + ": halo"
+    # columns outside [x_offset - r, x_offset + nx + r) are never touched
+    outside = np.ones(plan.storage_shape[-1], bool)
+    outside[lo:lo + dims[0] + 2 * r] = False
+    expect = -3.0 if iters % 2 else 11.0
+    assert np.all(full[..., outside] == expect), what + ": outside columns written"
+    return plan
+
+
+PITCHED = [  # dims, r, dtype, variant, (row_pitch, x_offset), tile
+    ((70, 37, 29), 3, S.F64, S.STAR3D, (96, 16), (4, 2, 16, 0x221)),
+    ((70, 37, 29), 3, S.F64, S.STAR3D, (96, 16), (4, 1, 16, 0x009)),  # hardware-cached
+    ((70, 37, 29), 3, S.F32, S.STAR3D, (128, 32), (8, 2, 16, 0x021)),
+    ((50, 21, 19), 2, S.BF16, S.STAR3D, (70, 9), (4, 4, 8, 0x001)),
+    ((40, 33), 3, S.F64, S.GENERIC, (51, 5), None),
+    ((23, 17, 11), 2, S.F32, S.GENERIC, (31, 4), None),
+    ((1000,), 3, S.F64, S.LINE1D, (0, 16), (4, 1)),
+    ((1000,), 3, S.BF16, S.LINE1D, (0, 64), (2, 1)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(PITCHED)))
+def test_pitched_layout(case):
+    dims, r, dtype, variant, (pitch, ox), tile = PITCHED[case]
+    g = rand_star(r, 6) if len(dims) == 3 else np.random.default_rng(6).uniform(
+        -1, 1, (2 * r + 1,) * len(dims))
+    run_pitched(dims, r, g, dtype, variant, pitch, ox, tile=tile)
+
+
+@pytest.mark.parametrize("iters", [1, 6, 7])
+def test_pitched_chained_star_and_temporal_line(iters):
+    g = diffusion_star_exact(3, 3, 0.2)
+    run_pitched((40, 33, 21), 3, g, S.F64, S.STAR3D, 64, 16, tile=(4, 2, 8, 0x221),
+                iters=iters)
+    g1 = np.array([0.1, 0.2, 0.4, 0.2, 0.1])
+    run_pitched((4099,), 2, g1, S.F64, S.LINE1D, 0, 8, tile=(4, 8), iters=iters + 3)
+
+
+def test_pitched_user_halo_and_plan_halo():
+    dims, r = (45, 26, 17), 3
+    run_pitched(dims, r, rand_star(3, 4), S.F64, S.STAR3D, 64, 8, tile=(4, 2, 8, 0x221),
+                bc=S.USER_HALO)
+    plan = S.LinearPlan(dims, r, rand_star(3, 4), row_pitch=64, x_offset=8)
+    inner = inputs.uniform_field(dims, 8)
+    store = np.full(plan.storage_shape, 5.0)
+    pv = store[..., 5:5 + dims[0] + 2 * r]
+    O.interior(pv, r)[...] = inner
+    t = dev(store, S.F64)
+    plan.halo(t)
+    got = host(t)
+    assert np.array_equal(got[..., 5:5 + dims[0] + 2 * r], O.pad_periodic(inner, r))
+    assert np.all(got[..., :5] == 5.0) and np.all(got[..., 5 + dims[0] + 2 * r:] == 5.0)
+
+
 def test_smoother_2pow20_ten_iterations():
     n = 2 ** 20
     g = W.smoother3()
@@ -258,21 +349,26 @@ def sample_points(dims, count, seed):
 
 
 @pytest.mark.parametrize("dtype", [S.F64, S.F32])
-def test_star_512_cubed_sampled_points(dtype):
+@pytest.mark.parametrize("aligned", [False, True])
+def test_star_512_cubed_sampled_points(dtype, aligned):
+    # aligned: the cache-line-aligned row layout the benchmark times
     dims, r = (512, 512, 512), 3
     s = W.diffusion_number(512)
     g_prod = W.diffusion_star(3, 3, s)
     g_ref = diffusion_star_exact(3, 3, s)
     assert np.max(np.abs(g_prod - g_ref)) < 1e-15
     inner = to_storage_values(inputs.uniform_field(dims, 1), dtype)
-    plan = S.LinearPlan(dims, r, g_prod, dtype=dtype, autotune=True)
+    pitch, ox = W.aligned_layout(512, r, 8 if dtype == S.F64 else 4) if aligned else (0, 0)
+    plan = S.LinearPlan(dims, r, g_prod, dtype=dtype, autotune=True, row_pitch=pitch,
+                        x_offset=ox)
     a_host = np.zeros(O.padded_shape(dims, r))
     O.interior(a_host, r)[...] = inner
     del inner
-    a = dev(a_host, dtype)
+    a = plan.empty(0.0)
+    plan.padded(a).copy_(dev(a_host, dtype))
     b = plan.empty(0.0)
     plan.apply(a, b, 1)
-    got = host(b)
+    got = host(plan.padded(b))
     O.fill_periodic(a_host, r)
     pts = sample_points(dims, 4000, 2)
     ref = O.xcorr_at(a_host, r, g_ref, pts)
@@ -304,3 +400,17 @@ def test_star_512_cubed_hundred_iterations_fourier_mode():
     got = O.interior(host(res), r)
     err = np.max(np.abs(got - lam ** N * inner))
     assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("n,r,e,T,iters", [(5000, 1, 4, 4, 10), (777, 4, 2, 16, 17),
+                                           (3, 3, 1, 8, 5), (1000, 2, 8, 16, 2),
+                                           (1 << 20, 1, 4, 10, 10), (4099, 1, 1, 3, 1)])
+def test_line1d_temporal_blocking(n, r, e, T, iters):
+    g = np.random.default_rng(13).uniform(-0.3, 0.3, 2 * r + 1)
+    g[r] = 1.0 - (np.abs(g).sum() - abs(g[r]))  # keep the iteration bounded
+    run_case((n,), r, g, S.F64, S.LINE1D, tile=(e, T), iters=iters)
+
+
+def test_line1d_temporal_needs_periodic():
+    with pytest.raises(S.StencilError):
+        S.LinearPlan((100,), 1, W.smoother3(), bc=S.USER_HALO, variant=S.LINE1D, tile=(4, 8))
