@@ -38,7 +38,10 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="grid edge")
     ap.add_argument("--radius", type=int, default=3)
     ap.add_argument("--tile", default=None,
-                    help="star3d launch shape TY,NY,LZ,FLAGS (skips autotuning)")
+                    help="star3d launch shape TY,NY,LZ,FLAGS (FLAGS may be hex)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the launch candidates first (default: the plan's default "
+                         "shape, the one measured fastest for this workload)")
     ap.add_argument("--layout", choices=("auto", "compact", "aligned"), default="auto",
                     help="field rows: compact (n + 2r cells) or padded so each interior row "
                          "starts a 128-byte line; auto = compact for FP64, aligned for the "
@@ -125,7 +128,8 @@ def cpu_baseline(n, r, g, seconds):
                       % ((2 * r + 1) ** 3, n, n, nz, t)}
 
 
-def star_run(torch, S, W, inputs, n, r, dtype, steps, warmup, tile=None, layout="auto"):
+def star_run(torch, S, W, inputs, n, r, dtype, steps, warmup, tile=None, layout="auto",
+             autotune=False):
     """Chained iterations of the star workload, one launch per step with an
     event after each; returns (plan, coefficients, total ms, mean launch ms).
     layout: "compact", "aligned" (each interior row starts a 128-byte line) or
@@ -140,7 +144,7 @@ def star_run(torch, S, W, inputs, n, r, dtype, steps, warmup, tile=None, layout=
         plan = S.LinearPlan(dims, r, g, dtype=dtype, variant=S.STAR3D, tile=tile,
                             row_pitch=pitch, x_offset=ox)
     else:
-        plan = S.LinearPlan(dims, r, g, dtype=dtype, autotune=True, row_pitch=pitch,
+        plan = S.LinearPlan(dims, r, g, dtype=dtype, autotune=autotune, row_pitch=pitch,
                             x_offset=ox)
     a = plan.empty(0.0)
     plan.padded(a)[r:r + n, r:r + n, r:r + n] = torch.from_numpy(
@@ -250,11 +254,12 @@ def main():
     torch.cuda.set_device(0)
     n, r = args.n, args.radius
     dtype, esize = DTYPES[args.dtype]
-    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    tile = tuple(int(v, 0) for v in args.tile.split(",")) if args.tile else None
     K = args.steps
     t0 = time.perf_counter()
     plan, g, total_ms, avg_launch_ms = star_run(torch, S, W, inputs, n, r, dtype, K,
-                                                args.warmup, tile, layout=args.layout)
+                                                args.warmup, tile, layout=args.layout,
+                                                autotune=args.autotune)
     wall = time.perf_counter() - t0
     ms_per_step = total_ms / K
     points = n ** 3
@@ -295,6 +300,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated; null if the kernel source changed since)",
+            "traffic_rate_gbs": (traffic / (avg_launch_ms * 1e-3) / 1e9) if traffic else None,
             "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_ms": avg_launch_ms,
         },
