@@ -87,9 +87,17 @@ typedef struct stencil_desc {
      *             tiles; (lanes, rows) one of (4,1) (4,2) (4,4) (2,4) (8,2)
      *             and prefetch/width ignored), bits 4..7 planes
      *             prefetched ahead (0 = default 2; only 2 is built), bits
-     *             8..11 tile width in 64-lane waves (0 = 1)}; (width, lanes,
-     *             rows) one of (1,8,2) (1,4,4) (1,8,4) (1,16,2) (2,4,2)
-     *             (2,4,4) (2,8,2) (4,2,2) (4,2,4) (4,4,2) (8,1,4) (8,2,2)
+     *             8..11 tile width in 64-lane waves (0 = 1), bits 12..15
+     *             iterations per launch (0/1 = one; 2 = two chained
+     *             iterations in one pass over HBM, periodic plans and the LDS
+     *             variant only: the temporal blocking the paper's discussion
+     *             asks for; results are bitwise those of one-iteration
+     *             launches)}; one-iteration (width, lanes, rows) one of
+     *             (1,8,2) (1,4,4) (1,8,4) (1,16,2) (2,4,2) (2,4,4) (2,8,2)
+     *             (4,2,2) (4,2,4) (4,4,2) (8,1,4) (8,2,2); two-iteration
+     *             (1,8,2) (1,16,1) (1,16,2) (1,12,2) (2,8,2) (1,8,4), the
+     *             lane grid 64*width x lanes*rows yielding (64*width - 2r) x
+     *             (lanes*rows - 2r) outputs per tile
      *   GENERIC: {block x, block y} (a multiple of 64 lanes, at most 1024)
      *   LINE1D : {outputs per lane: 1, 2, 4 or 8, iterations fused per
      *             launch T (0/1 = none; T > 1 periodic only: the block

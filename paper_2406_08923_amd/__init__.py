@@ -185,6 +185,28 @@ class LinearPlan:
         return np.array(out[:]).reshape(len(fields), 3)
 
     @property
+    def iterations_per_launch(self):
+        """Chained iterations one kernel launch performs (2 for a periodic
+        star planned with temporal blocking, else 1)."""
+        if self.variant == STAR3D:
+            return 2 if (self.tile[3] >> 12) & 15 == 2 else 1
+        if self.variant == LINE1D:
+            return max(1, self.tile[1])
+        return 1
+
+    def launches(self, iters):
+        """(launches of the multi-iteration kernel, one-iteration launches)
+        that apply(a, b, iters) issues for a two-iteration star plan: the
+        launch count has the parity of iters, so the result lands where the
+        one-iteration-per-launch contract puts it."""
+        if self.iterations_per_launch != 2 or self.variant != STAR3D:
+            return 0, iters
+        nl = (iters + 1) // 2
+        if nl % 2 != iters % 2:
+            nl += 1
+        return iters - nl, 2 * nl - iters
+
+    @property
     def storage_shape(self):
         """Tensor shape [z, y, x] of one field in the plan's layout (rows of
         row_pitch elements)."""

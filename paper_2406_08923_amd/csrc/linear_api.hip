@@ -151,6 +151,31 @@ int apply_t(stencil_plan_s *p, void *da, void *db, int iters, hipStream_t s, boo
         }
         return rc;
     }
+    if (p->lin.bc == STENCIL_BC_PERIODIC && p->lin.variant == STENCIL_VARIANT_STAR3D &&
+        p->lin.tstar == 2) {
+        // nl launches of two or one iterations, nl of the parity of iters;
+        // the two-iteration launches come first (they read the input with
+        // periodic wrap, not its halo, and write their output's images)
+        int nl = (iters + 1) / 2;
+        if ((nl & 1) != (iters & 1))
+            ++nl;
+        const int n2 = iters - nl, n1 = nl - n2;
+        const int fl = p->lin.sflags & (STAR_FLAG_XCD | STAR_FLAG_YFIRST);
+        if (n2 == 0 && !halo_valid)
+            rc = launch_halo<S>(a, p->lin.g, s);
+        for (int k = 0; k < n2 && rc == STENCIL_OK; ++k) {
+            rc = launch_star3d_t2(a, b, p->lin.g, p->lin.star, p->lin.reff, p->lin.xw, p->lin.ty,
+                                  p->lin.ny, p->lin.lz, fl, s);
+            std::swap(a, b);
+        }
+        const int *q = p->lin.s1;
+        for (int k = 0; k < n1 && rc == STENCIL_OK; ++k) {
+            rc = launch_star3d(a, b, p->lin.g, p->lin.star, p->lin.reff, q[4], q[0], q[1], 2,
+                               q[2], q[3] & 15, s);
+            std::swap(a, b);
+        }
+        return rc;
+    }
     if (p->lin.bc == STENCIL_BC_PERIODIC && !halo_valid)
         rc = launch_halo<S>(a, p->lin.g, s);
     for (int k = 0; k < iters && rc == STENCIL_OK; ++k) {
@@ -190,8 +215,10 @@ void set_choice(stencil_plan_s *p, const TuneChoice &c)
         p->lin.sflags = c.p3 & 15;
         const int pf = (c.p3 >> STAR_PF_SHIFT) & 15;
         const int xw = (c.p3 >> STAR_XW_SHIFT) & 15;
+        const int t = (c.p3 >> STAR_T_SHIFT) & 15;
         p->lin.pf = pf ? pf : 2;
         p->lin.xw = xw ? xw : 1;
+        p->lin.tstar = t == 2 ? 2 : 1;
     } else if (c.variant == STENCIL_VARIANT_LINE1D) {
         p->lin.e1d = c.p0;
         p->lin.t1d = c.p1 > 1 ? c.p1 : 1;
@@ -223,6 +250,17 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
                              w | STAR_FLAG_XCD | STAR_FLAG_YFIRST});
             }
         }
+        // two iterations per launch (periodic): (x waves, y lanes, rows per lane)
+        if (p->lin.bc == STENCIL_BC_PERIODIC) {
+            const int t2[][3] = {{1, 8, 2}, {1, 16, 1}, {1, 16, 2}, {1, 12, 2}, {2, 8, 2}, {1, 8, 4}};
+            for (auto &sh : t2)
+                for (int lz : {32, 64, 128}) {
+                    if (lz >= g.nz && lz != 32)
+                        continue;
+                    c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz,
+                                 STAR_FLAG_XCD | (sh[0] << STAR_XW_SHIFT) | (2 << STAR_T_SHIFT)});
+                }
+        }
         // hardware-cached z march: (lanes along y, rows per lane)
         const int hshapes[][2] = {{4, 1}, {4, 2}, {4, 4}, {2, 4}, {8, 2}};
         for (auto &sh : hshapes)
@@ -249,16 +287,27 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
     return c;
 }
 
-TuneChoice default_choice(const stencil_plan_s *p)
+// One-iteration star shape that measured fastest at 512^3: 128 x 8 tiles for
+// FP64, 64 x 16 for the narrower types.
+TuneChoice default_star1(const stencil_plan_s *p)
 {
-    // the shapes that measured fastest at 512^3: 128 x 8 tiles for FP64,
-    // 64 x 16 for the narrower types
-    if (p->lin.is_star && p->lin.dtype == STENCIL_F64)
+    if (p->lin.dtype == STENCIL_F64)
         return {STENCIL_VARIANT_STAR3D, 4, 2, 32, STAR_FLAG_XCD | (2 << STAR_PF_SHIFT) |
                                                       (2 << STAR_XW_SHIFT)};
+    return {STENCIL_VARIANT_STAR3D, 8, 2, 32, STAR_FLAG_XCD | (2 << STAR_PF_SHIFT) |
+                                                  (1 << STAR_XW_SHIFT)};
+}
+
+TuneChoice default_choice(const stencil_plan_s *p)
+{
+    // periodic stars: two iterations per launch, the lane grids that measured
+    // fastest at 512^3 (64 x 24 for FP64, 64 x 32 for the narrower types)
+    if (p->lin.is_star && p->lin.bc == STENCIL_BC_PERIODIC)
+        return {STENCIL_VARIANT_STAR3D, p->lin.dtype == STENCIL_F64 ? 12 : 8,
+                p->lin.dtype == STENCIL_F64 ? 2 : 4, p->lin.dtype == STENCIL_F64 ? 64 : 32,
+                STAR_FLAG_XCD | (1 << STAR_XW_SHIFT) | (2 << STAR_T_SHIFT)};
     if (p->lin.is_star)
-        return {STENCIL_VARIANT_STAR3D, 8, 2, 32, STAR_FLAG_XCD | (2 << STAR_PF_SHIFT) |
-                                                      (1 << STAR_XW_SHIFT)};
+        return default_star1(p);
     if (p->lin.g.ndim == 1)
         return {STENCIL_VARIANT_LINE1D, 4, 0, 0, 0};
     return {STENCIL_VARIANT_GENERIC, 64, 4, 0, 0};
@@ -294,7 +343,7 @@ int autotune(stencil_plan_s *p)
     TuneChoice best_c = default_choice(p);
     for (const TuneChoice &c : candidates(p)) {
         set_choice(p, c);
-        if (apply_any(p, a, b, 1, nullptr) != STENCIL_OK) {
+        if (apply_any(p, a, b, p->lin.is_star ? 2 : 1, nullptr) != STENCIL_OK) {
             (void)hipGetLastError();
             continue;
         }
@@ -303,8 +352,10 @@ int autotune(stencil_plan_s *p)
         for (int rep = 0; rep < 2 && ok; ++rep) {
             if (hipEventRecord(e0, nullptr) != hipSuccess) { ok = false; break; }
             // 1-D plans are timed on 10 chained iterations so temporal
-            // blocking is weighed against per-iteration launches
-            int rc = apply_any(p, a, b, p->lin.g.ndim == 1 ? 10 : 3, nullptr);
+            // blocking is weighed against per-iteration launches, and
+            // 3-D stars on 4, so one- and two-iteration launches do equal work
+            const int it = p->lin.g.ndim == 1 ? 10 : p->lin.is_star ? 4 : 3;
+            int rc = apply_any(p, a, b, it, nullptr);
             if (hipEventRecord(e1, nullptr) != hipSuccess) { ok = false; break; }
             if (hipEventSynchronize(e1) != hipSuccess || rc != STENCIL_OK) {
                 (void)hipGetLastError();
@@ -500,6 +551,15 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
         return fail(STENCIL_EUNSUPPORTED, "LINE1D needs ndim = 1");
     }
     TuneChoice c = default_choice(p);
+    if (L.is_star) {
+        // the one-iteration shape that runs beside two-iteration launches
+        const TuneChoice c1 = default_star1(p);
+        L.s1[0] = c1.p0;
+        L.s1[1] = c1.p1;
+        L.s1[2] = c1.p2;
+        L.s1[3] = c1.p3 & 15;
+        L.s1[4] = (c1.p3 >> STAR_XW_SHIFT) & 15;
+    }
     if (d->variant != STENCIL_VARIANT_AUTO) {
         c.variant = d->variant;
         if (c.variant != default_choice(p).variant) {
@@ -511,7 +571,14 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
             if (t[0]) c.p0 = t[0];
             if (t[1]) c.p1 = t[1];
             if (t[2]) c.p2 = t[2];
-            c.p3 = t[3] & 0xfff; // explicit tiles set the flag word exactly
+            c.p3 = t[3] & 0xffff; // explicit tiles set the flag word exactly
+            const int tb = (c.p3 >> STAR_T_SHIFT) & 15;
+            if (tb > 2 || (tb == 2 && d->bc != STENCIL_BC_PERIODIC) ||
+                (tb == 2 && (c.p3 & (STAR_FLAG_HWC | STAR_FLAG_NOFUSE)))) {
+                stencil_plan_destroy(p);
+                return fail(STENCIL_EINVAL, "two iterations per launch need a periodic plan and "
+                                            "the LDS variant (and 1 or 2 iterations only)");
+            }
         } else if (c.variant == STENCIL_VARIANT_LINE1D) {
             if (t[0]) c.p0 = t[0];
             if (t[1]) c.p1 = t[1];
@@ -523,7 +590,7 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "fused iterations must be 1..64");
             }
-        } else {
+        } else if (c.variant == STENCIL_VARIANT_GENERIC) {
             if (t[0]) c.p0 = t[0];
             if (t[1]) c.p1 = t[1];
             if (c.p0 < 1 || c.p1 < 1 || c.p0 * c.p1 > 1024 || (c.p0 * c.p1) % 64) {
@@ -576,7 +643,8 @@ stencil_status stencil_plan_tile(stencil_plan_t p, int tile[4])
         tile[0] = L.ty;
         tile[1] = L.ny;
         tile[2] = L.lz;
-        tile[3] = L.sflags | (L.pf << STAR_PF_SHIFT) | (L.xw << STAR_XW_SHIFT);
+        tile[3] = L.sflags | (L.pf << STAR_PF_SHIFT) | (L.xw << STAR_XW_SHIFT) |
+                  (L.tstar == 2 ? 2 << STAR_T_SHIFT : 0);
     } else if (L.variant == STENCIL_VARIANT_LINE1D) {
         tile[0] = L.e1d;
         tile[1] = L.t1d;

@@ -43,6 +43,7 @@ constexpr int STAR_FLAG_YFIRST = 4; // tile numbers run fastest along y
 constexpr int STAR_FLAG_HWC = 8;    // hardware-cached z march (no LDS)
 constexpr int STAR_PF_SHIFT = 4;    // bits 4..7: prefetch depth (0 = default)
 constexpr int STAR_XW_SHIFT = 8;    // bits 8..11: tile width in waves (0 = 1)
+constexpr int STAR_T_SHIFT = 12;    // bits 12..15: iterations per launch (0/1 = 1, or 2)
 
 template <typename S> int launch_halo(S *a, const Geo &g, hipStream_t s);
 
@@ -56,7 +57,9 @@ int launch_generic(const S *in, S *out, const Geo &g, const int *offs,
 // pf: prefetch depth; lz: z planes per workgroup; flags: STAR_FLAG_*.
 #define STAR_DECL(S)                                                                         \
     int launch_star3d(const S *in, S *out, const Geo &g, const StarCoefAny &cf, int R, int xw, \
-                      int ty, int ny, int pf, int lz, int flags, hipStream_t s);
+                      int ty, int ny, int pf, int lz, int flags, hipStream_t s);              \
+    int launch_star3d_t2(const S *in, S *out, const Geo &g, const StarCoefAny &cf, int R,      \
+                         int xw, int ty, int ny, int lz, int flags, hipStream_t s);
 STAR_DECL(double)
 STAR_DECL(float)
 STAR_DECL(bf16)

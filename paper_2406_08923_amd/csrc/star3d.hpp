@@ -387,6 +387,32 @@ int launch_star3d_hwc_r(const S *in, S *out, const Geo &g,
     return fail(STENCIL_EUNSUPPORTED, "star3d (cached): unsupported tile (ty=%d, ny=%d)", ty, ny);
 }
 
+} // namespace stn
+
+#include "star3d_t2.hpp"
+
+namespace stn {
+
+template <typename S>
+int launch_star3d_t2_impl(const S *in, S *out, const Geo &g, const StarCoefAny &cfa, int R,
+                          int xw, int ty, int ny, int lz, int flags, hipStream_t s)
+{
+    using C = typename Store<S>::C;
+    if (g.ndim != 3 || R < 1)
+        return fail(STENCIL_EINVAL, "star3d (two iterations): needs a 3-D star");
+    if (uint64_t(padded_elems(g)) * sizeof(S) >= (uint64_t(1) << 32))
+        return fail(STENCIL_EUNSUPPORTED, "star3d: arrays of 4 GiB or more are not supported");
+    if (lz < 1)
+        return fail(STENCIL_EINVAL, "star3d: z planes per workgroup must be >= 1");
+    switch (R) {
+    case 1: return launch_star3d_t2_r<S, 1>(in, out, g, cfa.get<C, 1>(), xw, ty, ny, lz, flags, s);
+    case 2: return launch_star3d_t2_r<S, 2>(in, out, g, cfa.get<C, 2>(), xw, ty, ny, lz, flags, s);
+    case 3: return launch_star3d_t2_r<S, 3>(in, out, g, cfa.get<C, 3>(), xw, ty, ny, lz, flags, s);
+    case 4: return launch_star3d_t2_r<S, 4>(in, out, g, cfa.get<C, 4>(), xw, ty, ny, lz, flags, s);
+    }
+    return fail(STENCIL_EUNSUPPORTED, "star3d: radius %d not in 1..4", R);
+}
+
 template <typename S>
 int launch_star3d_impl(const S *in, S *out, const Geo &g, const StarCoefAny &cfa, int R, int xw,
                        int ty, int ny, int pf, int lz, int flags, hipStream_t s)

@@ -7,4 +7,9 @@ int launch_star3d(const double *in, double *out, const Geo &g, const StarCoefAny
 {
     return launch_star3d_impl<double>(in, out, g, cf, R, xw, ty, ny, pf, lz, flags, s);
 }
+int launch_star3d_t2(const double *in, double *out, const Geo &g, const StarCoefAny &cf, int R, int xw,
+                     int ty, int ny, int lz, int flags, hipStream_t s)
+{
+    return launch_star3d_t2_impl<double>(in, out, g, cf, R, xw, ty, ny, lz, flags, s);
+}
 } // namespace stn

@@ -1,0 +1,263 @@
+// star3d_t2.hpp -- two chained iterations of the 3-D star cross-correlation in
+// one pass over HBM (temporal blocking of the z march), periodic boundaries.
+// Included by star3d.hpp.
+#pragma once
+
+namespace stn {
+
+// Shapes (XW, TY, NY) built for the two-iteration kernel: the lane grid is
+// 64*XW x TY*NY; each tile produces (64*XW - 2R) x (TY*NY - 2R) outputs.
+#define STAR_T2_SHAPES(X) X(1, 8, 2) X(1, 16, 1) X(1, 16, 2) X(1, 12, 2) X(2, 8, 2) X(1, 8, 4)
+
+// storage rounding of an intermediate iterate: what a one-iteration launch
+// would have stored and the next launch read back
+template <typename S> struct RoundS {
+    static __device__ __forceinline__ typename Store<S>::C f(typename Store<S>::C v) { return v; }
+};
+template <> struct RoundS<bf16> {
+    static __device__ __forceinline__ float f(float v) { return bf16_to_f32(f32_to_bf16(v)); }
+};
+
+__device__ __forceinline__ int wrap_mod(int v, int n)
+{
+    int m = v % n;
+    return m < 0 ? m + n : m;
+}
+
+// Lane (tx, ty) owns column xf = fx0 + tx and rows yf = fy0 + ty*NY + j of the
+// lane grid, which is the tile's output region widened by R on every side.
+// The workgroup marches a z step zA at a time:
+//   * the f0 window (planes zA-R..zA+R of the lane's columns) and f0's plane zA
+//     with its x/y halo in LDS give f1 at plane zA on the whole lane grid
+//     (stage A), rounded to the storage type and pushed into the lane's f1
+//     window;
+//   * the f1 window (planes zB-R..zB+R, zB = zA-1-R) and f1's plane zB in LDS
+//     give f2 at plane zB on the inner lanes (stage B), stored with its
+//     periodic images.
+// Stage B runs one plane behind stage A so that a single barrier per step
+// covers both LDS planes (each double-buffered). Every f0 read uses wrapped
+// interior coordinates, so the input halo is never read and any grid size
+// works. Both stages evaluate every point with the taps in the order of the
+// one-iteration kernel, so the result is bitwise that of two chained launches.
+template <typename S, int R, int NY, int TY, int XW>
+__global__ void __launch_bounds__(64 * XW * TY)
+    k_star3d_t2(const S *__restrict__ in, S *__restrict__ out, Geo g,
+                StarCoef<typename Store<S>::C, R> cf, int lz, int gx, int gy, int gz, int flags)
+{
+    using C = typename Store<S>::C;
+    using SH = StarShape<R, NY, TY, XW>;
+    constexpr int PF = 2;
+    constexpr uint32_t es = sizeof(S);
+    constexpr int OX = SH::TXW - 2 * R, OY = SH::ROWS - 2 * R;
+    __shared__ C lda[2][SH::LH][SH::LW];      // f0 plane zA with its halo
+    __shared__ C ldb[2][SH::ROWS][SH::TXW];   // f1 plane zB on the lane grid
+
+    int lin = blockIdx.x;
+    const int total = gx * gy * gz;
+    if (flags & STAR_FLAG_XCD) lin = xcd_remap(lin, total);
+    const bool yfirst = (flags & STAR_FLAG_YFIRST) != 0;
+    const int byi = yfirst ? lin % gy : (lin / gx) % gy;
+    const int bxi = yfirst ? (lin / gy) % gx : lin % gx;
+    const int bzi = lin / (gx * gy);
+
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = tx + SH::TXW * ty;
+    const int fx0 = bxi * OX - R, fy0 = byi * OY - R;
+    const int z0 = bzi * lz;
+    const int z1 = min(z0 + lz, g.nz);
+    const bool fuse = (flags & STAR_FLAG_NOFUSE) == 0;
+    const Buf src = make_buf(in, uint64_t(padded_elems(g)) * es);
+
+    auto col = [&](int xx, int yy) {
+        return uint32_t(wrap_mod(xx, g.nx) + g.ox + g.sy * (wrap_mod(yy, g.ny) + g.ry)) * es;
+    };
+    auto plane = [&](int zz) { return uint32_t(wrap_mod(zz, g.nz) + g.rz) * uint32_t(g.sz) * es; };
+
+    uint32_t col_off[NY];
+#pragma unroll
+    for (int j = 0; j < NY; ++j) col_off[j] = col(fx0 + tx, fy0 + ty * NY + j);
+
+    uint32_t hx_off[SH::HX_PER], hy_off[SH::HY_PER];
+    int hx_slot[SH::HX_PER], hy_slot[SH::HY_PER];
+#pragma unroll
+    for (int k = 0; k < SH::HX_PER; ++k) {
+        const int cidx = tid + k * SH::NT;
+        if (cidx < SH::NXH) {
+            const int row = cidx / (2 * R), e = cidx % (2 * R);
+            const int lc = e < R ? e : SH::TXW + e; // LDS column
+            hx_off[k] = col(fx0 - R + lc, fy0 + row);
+            hx_slot[k] = (row + R) * SH::LW + lc;
+        } else {
+            hx_off[k] = 0;
+            hx_slot[k] = -1;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SH::HY_PER; ++k) {
+        const int cidx = tid + k * SH::NT;
+        if (cidx < SH::NYH) {
+            const int e = cidx / SH::TXW, cc = cidx % SH::TXW;
+            const int lr = e < R ? e : SH::ROWS + e; // LDS row
+            hy_off[k] = col(fx0 + cc, fy0 - R + lr);
+            hy_slot[k] = lr * SH::LW + cc + R;
+        } else {
+            hy_off[k] = 0;
+            hy_slot[k] = -1;
+        }
+    }
+
+    // steps zA = zs .. ze; stage B is live from zA = z0 + R + 1 on
+    const int zs = z0 - R, ze = z1 + R;
+    C win[NY][2 * R + 1], w1[NY][2 * R + 1];
+#pragma unroll
+    for (int j = 0; j < NY; ++j)
+#pragma unroll
+        for (int k = 0; k <= 2 * R; ++k) w1[j][k] = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k)
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+            win[j][k + 1] = BufLd<S>::ld(src, col_off[j], plane(zs - R + k));
+
+    C pre_w[PF][NY], pre_hx[PF][SH::HX_PER], pre_hy[PF][SH::HY_PER];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+#pragma unroll
+        for (int j = 0; j < NY; ++j) pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zs + q + R));
+#pragma unroll
+        for (int k = 0; k < SH::HX_PER; ++k) pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zs + q));
+#pragma unroll
+        for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zs + q));
+    }
+
+    for (int zb = zs; zb <= ze; zb += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int zA = zb + q;
+            if (zA > ze)
+                break;
+            const int b = (zA - zs) & 1;
+            C *la = &lda[b][0][0];
+#pragma unroll
+            for (int j = 0; j < NY; ++j) {
+#pragma unroll
+                for (int k = 0; k < 2 * R; ++k) win[j][k] = win[j][k + 1];
+                win[j][2 * R] = pre_w[q][j];
+                lda[b][ty * NY + j + R][tx + R] = win[j][R];
+                ldb[b][ty * NY + j][tx] = w1[j][R];
+            }
+#pragma unroll
+            for (int k = 0; k < SH::HX_PER; ++k)
+                if (hx_slot[k] >= 0) la[hx_slot[k]] = pre_hx[q][k];
+#pragma unroll
+            for (int k = 0; k < SH::HY_PER; ++k)
+                if (hy_slot[k] >= 0) la[hy_slot[k]] = pre_hy[q][k];
+            __syncthreads();
+
+            {
+                const int zn = zA + PF; // wrapped: always a valid plane
+#pragma unroll
+                for (int j = 0; j < NY; ++j)
+                    pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+#pragma unroll
+                for (int k = 0; k < SH::HX_PER; ++k)
+                    pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
+#pragma unroll
+                for (int k = 0; k < SH::HY_PER; ++k)
+                    pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
+            }
+
+            // stage B: f2 at plane zB from the f1 window and f1's plane in LDS
+            const int zB = zA - 1 - R;
+            if (zB >= z0) {
+#pragma unroll
+                for (int j = 0; j < NY; ++j) {
+                    const int row = ty * NY + j;
+                    const int xo = fx0 + tx, yo = fy0 + row;
+                    if (tx >= R && tx < SH::TXW - R && row >= R && row < SH::ROWS - R &&
+                        xo < g.nx && yo < g.ny) {
+                        C acc = cf.c0 * w1[j][R];
+#pragma unroll
+                        for (int m = 1; m <= R; ++m) {
+                            acc = fma(cf.zm[m - 1], w1[j][R - m], acc);
+                            acc = fma(cf.zp[m - 1], w1[j][R + m], acc);
+                        }
+#pragma unroll
+                        for (int m = 1; m <= R; ++m) {
+                            acc = fma(cf.xm[m - 1], ldb[b][row][tx - m], acc);
+                            acc = fma(cf.xp[m - 1], ldb[b][row][tx + m], acc);
+                        }
+#pragma unroll
+                        for (int m = 1; m <= R; ++m) {
+                            C vm = (j - m >= 0) ? w1[(j - m >= 0) ? j - m : 0][R] : ldb[b][row - m][tx];
+                            C vp = (j + m < NY) ? w1[(j + m < NY) ? j + m : 0][R] : ldb[b][row + m][tx];
+                            acc = fma(cf.ym[m - 1], vm, acc);
+                            acc = fma(cf.yp[m - 1], vp, acc);
+                        }
+                        store_periodic(out, g, xo, yo, zB, acc, fuse);
+                    }
+                }
+            }
+
+            // stage A: f1 at plane zA on the whole lane grid
+#pragma unroll
+            for (int j = 0; j < NY; ++j) {
+                const int row = ty * NY + j + R;
+                C acc = cf.c0 * win[j][R];
+#pragma unroll
+                for (int m = 1; m <= R; ++m) {
+                    acc = fma(cf.zm[m - 1], win[j][R - m], acc);
+                    acc = fma(cf.zp[m - 1], win[j][R + m], acc);
+                }
+#pragma unroll
+                for (int m = 1; m <= R; ++m) {
+                    acc = fma(cf.xm[m - 1], lda[b][row][tx + R - m], acc);
+                    acc = fma(cf.xp[m - 1], lda[b][row][tx + R + m], acc);
+                }
+#pragma unroll
+                for (int m = 1; m <= R; ++m) {
+                    C vm = (j - m >= 0) ? win[(j - m >= 0) ? j - m : 0][R] : lda[b][row - m][tx + R];
+                    C vp = (j + m < NY) ? win[(j + m < NY) ? j + m : 0][R] : lda[b][row + m][tx + R];
+                    acc = fma(cf.ym[m - 1], vm, acc);
+                    acc = fma(cf.yp[m - 1], vp, acc);
+                }
+#pragma unroll
+                for (int k = 0; k < 2 * R; ++k) w1[j][k] = w1[j][k + 1];
+                w1[j][2 * R] = RoundS<S>::f(acc);
+            }
+        }
+    }
+}
+
+template <typename S, int R, int NY, int TY, int XW>
+int launch_star3d_t2_t(const S *in, S *out, const Geo &g,
+                       const StarCoef<typename Store<S>::C, R> &cf, int lz, int flags,
+                       hipStream_t s)
+{
+    using SH = StarShape<R, NY, TY, XW>;
+    const int OX = SH::TXW - 2 * R, OY = SH::ROWS - 2 * R;
+    int gx = (g.nx + OX - 1) / OX, gy = (g.ny + OY - 1) / OY;
+    int gz = (g.nz + lz - 1) / lz;
+    int64_t total = (int64_t)gx * gy * gz;
+    if (total > 0x7fffffff)
+        return fail(STENCIL_EUNSUPPORTED, "star3d (two iterations): grid too large");
+    hipLaunchKernelGGL((k_star3d_t2<S, R, NY, TY, XW>), dim3((unsigned)total),
+                       dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+    return check_launch("xcorr_star3d_t2");
+}
+
+template <typename S, int R>
+int launch_star3d_t2_r(const S *in, S *out, const Geo &g,
+                       const StarCoef<typename Store<S>::C, R> &cf, int xw, int ty, int ny,
+                       int lz, int flags, hipStream_t s)
+{
+#define STAR_T2_CASE(XW_, TY_, NY_)                                                          \
+    if (xw == XW_ && ty == TY_ && ny == NY_)                                                 \
+        return launch_star3d_t2_t<S, R, NY_, TY_, XW_>(in, out, g, cf, lz, flags, s);
+    STAR_T2_SHAPES(STAR_T2_CASE)
+#undef STAR_T2_CASE
+    return fail(STENCIL_EUNSUPPORTED,
+                "star3d (two iterations): unsupported tile (xw=%d, ty=%d, ny=%d)", xw, ty, ny);
+}
+
+} // namespace stn

@@ -249,6 +249,88 @@ def test_apply_validation_on_device():
 # ---------------------------------------------------------------------------
 
 # ---------------------------------------------------------------------------
+# two chained iterations per launch (3-D star, periodic)
+# ---------------------------------------------------------------------------
+
+T2_TILES = [(8, 2, 32, 0x2101), (16, 1, 64, 0x2101), (16, 2, 16, 0x2101), (12, 2, 8, 0x2105),
+            (8, 2, 32, 0x2201), (8, 4, 16, 0x2101)]
+ONE_TILE = (4, 2, 8, 0x221)
+
+
+def run_star_iters(dims, r, g, dtype, tile, iters, seed=3, layout=(0, 0)):
+    inner = to_storage_values(inputs.uniform_field(dims, seed), dtype)
+    plan = S.LinearPlan(dims, r, g, dtype=dtype, variant=S.STAR3D, tile=tile,
+                        row_pitch=layout[0], x_offset=layout[1])
+    a = plan.empty(fill=5.0)
+    pad = np.full(O.padded_shape(dims, r), 7.0)  # halo garbage: the library ignores it
+    O.interior(pad, r)[...] = inner
+    plan.padded(a).copy_(dev(pad, dtype))
+    b = plan.empty(fill=-3.0)
+    res = plan.apply(a, b, iters)
+    return host(plan.padded(res)), plan, inner
+
+
+@pytest.mark.parametrize("tile", T2_TILES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_star_two_iterations_bitwise_equal_to_one_iteration_launches(tile, dtype):
+    dims, r = (70, 45, 37), 3
+    g = diffusion_star_exact(3, 3, 0.0815)
+    for iters in (2, 5, 6):
+        got, plan, inner = run_star_iters(dims, r, g, dtype, tile, iters)
+        assert plan.tile[3] >> 12 == 2
+        ref, _, _ = run_star_iters(dims, r, g, dtype, ONE_TILE, iters)
+        assert np.array_equal(got, ref), (tile, iters)
+        if dtype == S.F64:
+            want = oracle_apply(inner, r, g, iters)
+            assert_close(O.interior(got, r), O.interior(want, r), S.F64, what=str((tile, iters)))
+            assert np.array_equal(got, O.fill_periodic(got.copy(), r))
+
+
+@pytest.mark.parametrize("r", [1, 2, 4])
+def test_star_two_iterations_other_radii_random_taps(r):
+    dims = (66, 29, 31)
+    g = rand_star(r, 21) * 0.15
+    got, _, inner = run_star_iters(dims, r, g, S.F64, (16, 2, 16, 0x2101), 4)
+    ref, _, _ = run_star_iters(dims, r, g, S.F64, (4, 2, 8, 0x221), 4)
+    assert np.array_equal(got, ref)
+    want = oracle_apply(inner, r, g, 4)
+    assert_close(O.interior(got, r), O.interior(want, r), S.F64)
+
+
+@pytest.mark.parametrize("dims,r", [((3, 3, 3), 3), ((5, 4, 7), 3), ((1, 1, 1), 1),
+                                    ((130, 7, 5), 2)])
+def test_star_two_iterations_tiny_and_thin_grids(dims, r):
+    g = rand_star(r, 8) * 0.2
+    for iters in (4, 5):  # two-iteration launches only / plus one single
+        got, _, inner = run_star_iters(dims, r, g, S.F64, (8, 2, 32, 0x2101), iters)
+        want = oracle_apply(inner, r, g, iters)
+        assert_close(O.interior(got, r), O.interior(want, r), S.F64)
+        assert np.array_equal(got, O.fill_periodic(got.copy(), r))
+
+
+def test_star_two_iterations_pitched_layout():
+    dims, r = (70, 45, 37), 3
+    g = diffusion_star_exact(3, 3, 0.0815)
+    got, _, inner = run_star_iters(dims, r, g, S.F32, (8, 2, 32, 0x2101), 6, layout=(128, 32))
+    ref, _, _ = run_star_iters(dims, r, g, S.F32, ONE_TILE, 6)
+    assert np.array_equal(got, ref)
+
+
+def test_star_plan_without_tile_keeps_the_default_shape():
+    g = diffusion_star_exact(3, 3, 0.1)
+    p = S.LinearPlan((40, 40, 40), 3, g, variant=S.STAR3D)
+    assert p.variant == S.STAR3D and p.tile[0] > 0
+
+
+def test_star_two_iterations_needs_periodic_lds_variant():
+    g = diffusion_star_exact(3, 3, 0.1)
+    for bc, tile in ((S.USER_HALO, (8, 2, 32, 0x2101)), (S.PERIODIC, (4, 2, 32, 0x2109)),
+                     (S.PERIODIC, (8, 2, 32, 0x3101))):
+        with pytest.raises(S.StencilError):
+            S.LinearPlan((32, 32, 32), 3, g, bc=bc, variant=S.STAR3D, tile=tile)
+
+
+# ---------------------------------------------------------------------------
 # pitched layout: interior at column x_offset of rows of row_pitch elements
 # ---------------------------------------------------------------------------
 
@@ -380,6 +462,41 @@ def test_star_512_cubed_sampled_points(dtype, aligned):
         assert np.all(np.abs(vals - ref) <= 2 * 20 * 2.0 ** -24 * absconv + 2.0 ** -24 * np.abs(ref))
     # the output halo is the periodic image of its interior
     assert np.array_equal(got[:r], got[512:512 + r]) and np.array_equal(got[:, :, -r:], got[:, :, r:2 * r])
+
+
+@pytest.mark.parametrize("dtype", [S.F64, S.F32])
+def test_star_512_cubed_two_iteration_launches(dtype):
+    # 4 iterations = two launches of the two-iteration kernel: bitwise equal
+    # to four one-iteration launches at full size, and (FP64) the oracle's
+    # fourth iterate at sampled points
+    dims, r, iters = (512, 512, 512), 3, 4
+    s = W.diffusion_number(512)
+    g_ref = diffusion_star_exact(3, 3, s)
+    inner = to_storage_values(inputs.uniform_field(dims, 4), dtype)
+    pitch, ox = W.aligned_layout(512, r, 4) if dtype == S.F32 else (0, 0)
+    pad = np.zeros(O.padded_shape(dims, r))
+    O.interior(pad, r)[...] = inner
+    del inner
+    outs = []
+    for tile in ((8, 2, 64, 0x2101), (4, 2, 32, 0x221)):
+        plan = S.LinearPlan(dims, r, W.diffusion_star(3, 3, s), dtype=dtype, variant=S.STAR3D,
+                            tile=tile, row_pitch=pitch, x_offset=ox)
+        a = plan.empty(0.0)
+        plan.padded(a).copy_(dev(pad, dtype))
+        b = plan.empty(0.0)
+        res = plan.apply(a, b, iters)
+        outs.append(host(plan.padded(res)))
+        del a, b, res, plan
+    assert np.array_equal(outs[0], outs[1])
+    if dtype == S.F64:
+        O.fill_periodic(pad, r)
+        cur = pad
+        for _ in range(iters - 1):
+            cur = O.fill_periodic(O.xcorr(cur, r, g_ref), r)
+        pts = sample_points(dims, 2000, 7)
+        ref = O.xcorr_at(cur, r, g_ref, pts)
+        vals = outs[0][pts[:, 2] + r, pts[:, 1] + r, pts[:, 0] + r]
+        assert np.max(np.abs(vals - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
 def test_star_512_cubed_hundred_iterations_fourier_mode():
