@@ -230,10 +230,22 @@ typedef struct stencil_rk_desc {
     double ds[3];   /* grid spacing per axis (> 0) */
     double nu, eta, cs2;
     double adv[3];  /* ADVDIFF velocity */
-    int block[3];   /* launch override: x lanes, y lanes (x*y a multiple of 64,
-                       at most 256), block[2] 0 or 1 (one z plane per
-                       workgroup); 0 = plan's choice */
+    int block[3];   /* launch override (0 = plan's choice). CACHED: x lanes, y
+                       lanes (x*y a multiple of 64, at most 256), block[2] 0
+                       or 1 (one z plane per workgroup). LDS: the brick of
+                       output points per workgroup, one of 16x8x4 16x8x8
+                       32x4x4 8x8x8 */
+    int variant;    /* STENCIL_RK_VARIANT_*: how the derivative bank reads its
+                       taps */
 } stencil_rk_desc;
+
+/* Derivative-bank strategies (Sec. 4.1/4.4): AUTO = LDS for MHD8, CACHED for
+ * ADVDIFF. CACHED: one lane per point, every tap a load through L1/L2. LDS
+ * (MHD8 only): a workgroup owns a brick of points and streams the fields one
+ * at a time through an LDS tile of the brick plus its halo. */
+#define STENCIL_RK_VARIANT_AUTO 0
+#define STENCIL_RK_VARIANT_CACHED 1
+#define STENCIL_RK_VARIANT_LDS 2
 
 /* Buffers of one substep; all are caller-owned padded (radius 3) device
  * arrays of the plan's dims, one per field (entries beyond the model's field

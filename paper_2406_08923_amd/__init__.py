@@ -265,6 +265,7 @@ class LinearPlan:
 # ---------------------------------------------------------------------------
 
 MODEL_MHD8, MODEL_ADVDIFF = 0, 1
+RK_AUTO, RK_CACHED, RK_LDS = 0, 1, 2
 PREC_F64, PREC_F32_MASTER64, PREC_BF16_MASTER64, PREC_F32_ONLY, PREC_BF16_ONLY = range(5)
 _PREC_STORE = {PREC_F64: F64, PREC_F32_MASTER64: F32, PREC_BF16_MASTER64: BF16,
                PREC_F32_ONLY: F32, PREC_BF16_ONLY: BF16}
@@ -274,7 +275,8 @@ class _RkDesc(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("ndim", ctypes.c_int), ("dims", ctypes.c_int * 3),
                 ("precision", ctypes.c_int), ("ds", ctypes.c_double * 3),
                 ("nu", ctypes.c_double), ("eta", ctypes.c_double), ("cs2", ctypes.c_double),
-                ("adv", ctypes.c_double * 3), ("block", ctypes.c_int * 3)]
+                ("adv", ctypes.c_double * 3), ("block", ctypes.c_int * 3),
+                ("variant", ctypes.c_int)]
 
 
 class _Fields(ctypes.Structure):
@@ -308,7 +310,7 @@ class RkPlan:
     MODEL_ADVDIFF: 1 field, 2-D or 3-D), radius-3 periodic padding."""
 
     def __init__(self, model, dims, precision=PREC_F64, ds=None, nu=1e-3, eta=1e-3, cs2=1.0,
-                 adv=(0.0, 0.0, 0.0), block=None):
+                 adv=(0.0, 0.0, 0.0), block=None, variant=0):
         import math
         self.model = model
         self.dims = tuple(int(v) for v in dims)
@@ -327,6 +329,8 @@ class RkPlan:
         d.nu, d.eta, d.cs2 = nu, eta, cs2
         d.adv = (ctypes.c_double * 3)(*(list(adv) + [0.0] * (3 - len(adv))))
         d.block = (ctypes.c_int * 3)(*(list(block or []) + [0, 0, 0])[:3])
+        d.variant = int(variant)
+        self.variant = int(variant)
         L = lib()
         h = _vp()
         check(L.stencil_plan_rk(ctypes.byref(d), ctypes.byref(h)))

@@ -78,6 +78,8 @@ int launch_substep(const stencil_plan_s *p, const stencil_fields *f, int sub, do
     a.stage = sub;
     a.fuse = 1;
     a.phases = -1;
+    if (P.model == STENCIL_MODEL_MHD8 && P.variant == STENCIL_RK_VARIANT_LDS)
+        return launch_rk_mhd8_lds(P.policy, a, P.bx, P.by, P.bz, s);
     if (P.model == STENCIL_MODEL_MHD8)
         return launch_rk_mhd8(P.policy, a, P.bx, P.by, s);
     return launch_rk_advdiff(P.policy, a, P.bx, P.by, s);
@@ -142,11 +144,37 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     for (double v : prm)
         if (!std::isfinite(v))
             return fail(STENCIL_EINVAL, "non-finite model parameter");
-    int bx = d->block[0] ? d->block[0] : 64, by = d->block[1] ? d->block[1] : 4;
-    if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64)
-        return fail(STENCIL_EINVAL, "block %dx%d must be a multiple of 64 lanes <= 256", bx, by);
-    if (d->block[2] != 0 && d->block[2] != 1)
-        return fail(STENCIL_EINVAL, "block[2] must be 0 or 1 (one z plane per workgroup)");
+    if (d->variant < STENCIL_RK_VARIANT_AUTO || d->variant > STENCIL_RK_VARIANT_LDS)
+        return fail(STENCIL_EINVAL, "unknown derivative-bank variant %d", d->variant);
+    if (d->variant == STENCIL_RK_VARIANT_LDS && d->model != STENCIL_MODEL_MHD8)
+        return fail(STENCIL_EUNSUPPORTED, "the LDS bank is built for MHD8 only");
+    const int variant = d->variant != STENCIL_RK_VARIANT_AUTO ? d->variant
+                        : d->model == STENCIL_MODEL_MHD8      ? STENCIL_RK_VARIANT_LDS
+                                                              : STENCIL_RK_VARIANT_CACHED;
+    int bx, by, bz;
+    if (variant == STENCIL_RK_VARIANT_LDS) {
+        // bricks that measured fastest at 256^3: 16x8x8 (FP64 state, 1024
+        // lanes), 32x4x4 (FP32/BF16 storage, 512 lanes)
+        const bool f64 = d->precision == STENCIL_PREC_F64;
+        bx = d->block[0] ? d->block[0] : f64 ? 16 : 32;
+        by = d->block[1] ? d->block[1] : f64 ? 8 : 4;
+        bz = d->block[2] ? d->block[2] : f64 ? 8 : 4;
+        bool ok = false;
+#define RK_BRICK_OK(X_, Y_, Z_) ok = ok || (bx == X_ && by == Y_ && bz == Z_);
+        RK_BRICK_SHAPES(RK_BRICK_OK)
+#undef RK_BRICK_OK
+        if (!ok)
+            return fail(STENCIL_EINVAL, "brick %dx%dx%d is not built", bx, by, bz);
+    } else {
+        bx = d->block[0] ? d->block[0] : 64;
+        by = d->block[1] ? d->block[1] : 4;
+        bz = 1;
+        if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64)
+            return fail(STENCIL_EINVAL, "block %dx%d must be a multiple of 64 lanes <= 256",
+                        bx, by);
+        if (d->block[2] != 0 && d->block[2] != 1)
+            return fail(STENCIL_EINVAL, "block[2] must be 0 or 1 (one z plane per workgroup)");
+    }
 
     auto *p = new (std::nothrow) stencil_plan_s();
     if (!p)
@@ -176,8 +204,10 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     P.nu = d->nu;
     P.eta = d->eta;
     P.cs2 = d->cs2;
+    P.variant = variant;
     P.bx = bx;
     P.by = by;
+    P.bz = bz;
     P.store_size = dtype_size(store_dtype(P.policy));
     P.reg_size = P.policy == POL_F64 ? 8 : 4;
     *out = p;

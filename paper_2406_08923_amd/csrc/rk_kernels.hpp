@@ -48,6 +48,11 @@ struct RkArgs {
 };
 
 int launch_rk_mhd8(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
+
+// LDS-brick variant of the MHD8 substep (rk_mhd8_lds.hip): bricks of
+// bx x by x bz output points, one of RK_BRICK_SHAPES
+#define RK_BRICK_SHAPES(X) X(16, 8, 4) X(16, 8, 8) X(32, 4, 4) X(8, 8, 8)
+int launch_rk_mhd8_lds(int policy, const RkArgs &a, int bx, int by, int bz, hipStream_t s);
 int launch_rk_advdiff(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
 
 } // namespace stn

@@ -128,3 +128,32 @@ def test_layout_helper_aligns_rows():
         assert ox >= r and pitch >= ox + nx + r
         assert (ox * es) % 128 == 0 and (pitch * es) % 128 == 0
     assert S.lib().stencil_plan_padded_elems(None) == 0
+
+
+def _rk_rc(**kw):
+    d = S._RkDesc()
+    d.model = kw.get("model", S.MODEL_MHD8)
+    d.ndim = kw.get("ndim", 3)
+    d.dims = (ctypes.c_int * 3)(*kw.get("dims", (16, 16, 16)))
+    d.precision = kw.get("precision", S.PREC_F64)
+    d.ds = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    d.nu, d.eta, d.cs2 = 1e-3, 1e-3, 1.0
+    d.block = (ctypes.c_int * 3)(*kw.get("block", (0, 0, 0)))
+    d.variant = kw.get("variant", 0)
+    h = ctypes.c_void_p()
+    return S.lib().stencil_plan_rk(ctypes.byref(d), ctypes.byref(h))
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(variant=3), -1),                                  # unknown bank
+    (dict(variant=-1), -1),
+    (dict(model=S.MODEL_ADVDIFF, variant=S.RK_LDS), -3),    # LDS bank is MHD8-only
+    (dict(variant=S.RK_LDS, block=(16, 8, 2)), -1),         # brick not built
+    (dict(variant=S.RK_LDS, block=(64, 4, 1)), -1),
+    (dict(variant=S.RK_CACHED, block=(64, 4, 2)), -1),      # one plane per workgroup
+    (dict(variant=S.RK_CACHED, block=(48, 1, 0)), -1),      # not a multiple of 64 lanes
+    (dict(ndim=2, dims=(16, 16, 1)), -1),                   # MHD8 is 3-D
+])
+def test_rk_plan_rejects_bad_descriptors_without_a_device(kw, code):
+    assert _rk_rc(**kw) == code
+    assert S.lib().stencil_last_error()

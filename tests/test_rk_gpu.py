@@ -48,14 +48,21 @@ def ds_of(n):
     return [2 * math.pi / v for v in n]
 
 
+BANKS = [(S.RK_CACHED, None), (S.RK_LDS, None), (S.RK_LDS, (16, 8, 8)), (S.RK_LDS, (32, 4, 4)),
+         (S.RK_LDS, (8, 8, 8))]
+
+
+@pytest.mark.parametrize("bank", range(len(BANKS)))
 @pytest.mark.parametrize("stage", [0, 1, 2])
-def test_mhd8_substep_f64(stage):
+def test_mhd8_substep_f64(stage, bank):
     n = (40, 24, 20)
     ds = ds_of(n)
     dt = 0.1 * min(ds)
     f = mhd_fields(n, 1)
     rng = np.random.default_rng(2)
-    plan = S.RkPlan(S.MODEL_MHD8, n, S.PREC_F64, nu=NU, eta=ETA, cs2=CS2)
+    variant, block = BANKS[bank]
+    plan = S.RkPlan(S.MODEL_MHD8, n, S.PREC_F64, nu=NU, eta=ETA, cs2=CS2, variant=variant,
+                    block=block)
     b = plan.alloc()
     fin = [O.pad_periodic(v, 3) for v in f]
     w0 = [rng.uniform(-1e-2, 1e-2, fin[0].shape) for _ in range(8)]
@@ -75,6 +82,41 @@ def test_mhd8_substep_f64(stage):
             assert relerr(gw, O.interior(w_ref[k], 3)) <= 1e-12, (stage, k)
         else:
             assert np.array_equal(gw, O.interior(w0[k], 3))  # dead register not written
+
+
+@pytest.mark.parametrize("n", [(3, 3, 3), (5, 4, 7), (17, 9, 33)])
+@pytest.mark.parametrize("block", [(16, 8, 4), (8, 8, 8)])
+def test_mhd8_lds_bricks_on_tiny_and_ragged_grids(n, block):
+    ds = ds_of(n)
+    dt = 0.05 * min(ds)
+    f = mhd_fields(n, 4, kmax=1)
+    plan = S.RkPlan(S.MODEL_MHD8, n, S.PREC_F64, nu=NU, eta=ETA, cs2=CS2, variant=S.RK_LDS,
+                    block=block)
+    b = plan.alloc()
+    for k in range(8):
+        put(b["f_a"][k], O.pad_periodic(f[k], 3))
+    res = plan.run(b["f_a"], b["f_b"], b["w"], 2, dt)
+    ref = O.rk3_steps(O.MODEL_MHD8, [O.pad_periodic(v, 3) for v in f], ds, dt, 2, nu=NU,
+                      eta=ETA, cs2=CS2)
+    for k in range(8):
+        assert relerr(host(res[k]), ref[k]) <= 1e-12, (n, block, k)
+
+
+@pytest.mark.parametrize("prec", [S.PREC_F32_MASTER64, S.PREC_BF16_MASTER64, S.PREC_F32_ONLY])
+def test_mhd8_lds_and_cached_banks_agree_in_mixed_precision(prec):
+    # same arithmetic type, different summation order of the grad(div)
+    # terms: the banks agree to a few units of the storage rounding
+    n = (40, 24, 20)
+    ds = ds_of(n)
+    dt = 0.1 * min(ds)
+    f = mhd_fields(n, 9)
+    outs = []
+    for variant in (S.RK_CACHED, S.RK_LDS):
+        lp, master = run_policy(n, prec, f, 2, dt, nu=NU, eta=ETA, cs2=CS2, variant=variant)
+        outs.append(master if master is not None else lp)
+    tol = 1e-5 if prec != S.PREC_BF16_MASTER64 else 1e-4
+    for k in range(8):
+        assert relerr(outs[1][k], outs[0][k]) <= tol, (prec, k)
 
 
 def test_mhd8_three_steps_f64_run():
