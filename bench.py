@@ -52,6 +52,8 @@ def parse():
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth probe")
     ap.add_argument("--no-secondary", action="store_true", help="headline workload only")
+    ap.add_argument("--no-precision-error", action="store_true",
+                    help="skip the 1000-step mixed-precision error measurement")
     ap.add_argument("--serve-jobs", type=int, default=48,
                     help="jobs in the serving trace (0 skips the serving comparison)")
     return ap.parse_args()
@@ -217,8 +219,53 @@ def secondary(torch, S, W, inputs, args):
             "ms_per_step": ms,
             "hbm_frac": bytes_step[prec] * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del bufs, plan
+    if not args.no_precision_error:
+        out["mhd8_mixed_precision_error_64"] = mixed_precision_error(torch, S, inputs)
     if args.serve_jobs > 0:
         out["serving"] = serving(torch, args.serve_jobs)
+    return out
+
+
+def mixed_precision_error(torch, S, inputs, n=64, checkpoints=(1, 10, 100, 1000)):
+    """Normwise relative error per field of the FP32- and BF16-storage states
+    (FP64 master, and the no-master ablation) against the FP64 path after 1,
+    10, 100 and 1000 RK3 steps of the 8-field model at n^3 (Fourier-mode
+    initial data, amplitude 0.01, |k| <= 8; dt = 0.1 ds). The FP64 path is
+    the reference: it matches the CPU oracle to 1e-12 in the parity tests."""
+    import numpy as np
+    dims = (n, n, n)
+    dt = 0.1 * 2 * math.pi / n
+    f, _ = inputs.fourier_fields(dims, 1, nf=8, modes=8, kmax=8, amp=0.01)
+    runs = {}
+    for name, prec in (("f64", S.PREC_F64), ("f32_master64", S.PREC_F32_MASTER64),
+                       ("bf16_master64", S.PREC_BF16_MASTER64), ("f32_only", S.PREC_F32_ONLY),
+                       ("bf16_only", S.PREC_BF16_ONLY)):
+        plan = S.RkPlan(S.MODEL_MHD8, dims, prec)
+        b = plan.alloc()
+        for k in range(8):
+            b["f_a"][k][3:n + 3, 3:n + 3, 3:n + 3] = torch.from_numpy(f[k]).cuda().to(
+                b["f_a"][k].dtype)
+            if plan.master:
+                b["f64"][k][3:n + 3, 3:n + 3, 3:n + 3] = torch.from_numpy(f[k]).cuda()
+        snaps, done, cur, nxt = {}, 0, b["f_a"], b["f_b"]
+        for cp in checkpoints:
+            res = plan.run(cur, nxt, b["w"], cp - done, dt, w2=b["w2"], f64=b["f64"])
+            if res is nxt:
+                cur, nxt = nxt, cur
+            done = cp
+            state = b["f64"] if plan.master else cur
+            snaps[cp] = [t[3:n + 3, 3:n + 3, 3:n + 3].to(torch.float64).cpu().numpy()
+                         for t in state]
+        runs[name] = snaps
+        del b, plan
+    out = {"grid": n, "reference": "GPU FP64 path", "steps": list(checkpoints)}
+    for name in ("f32_master64", "bf16_master64", "f32_only", "bf16_only"):
+        per = {}
+        for cp in checkpoints:
+            ref, got = runs["f64"][cp], runs[name][cp]
+            per[str(cp)] = [float(np.max(np.abs(got[k] - ref[k])) / np.max(np.abs(ref[k])))
+                            for k in range(8)]
+        out[name] = per
     return out
 
 
