@@ -237,6 +237,11 @@ typedef struct stencil_rk_desc {
                        32x4x4 8x8x8 */
     int variant;    /* STENCIL_RK_VARIANT_*: how the derivative bank reads its
                        taps */
+    int row_pitch;  /* field layout, as in stencil_desc (both 0 = compact):  */
+    int x_offset;   /* interior x = 0 at column x_offset >= 3 of rows of
+                       row_pitch >= x_offset + dims[0] + 3 elements; every
+                       buffer of the plan (f, w, w2, f64) uses this layout and
+                       holds stencil_plan_padded_elems(plan) elements */
 } stencil_rk_desc;
 
 /* Derivative-bank strategies (Sec. 4.1/4.4): AUTO = LDS for MHD8, CACHED for

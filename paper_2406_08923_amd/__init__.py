@@ -276,7 +276,8 @@ class _RkDesc(ctypes.Structure):
                 ("precision", ctypes.c_int), ("ds", ctypes.c_double * 3),
                 ("nu", ctypes.c_double), ("eta", ctypes.c_double), ("cs2", ctypes.c_double),
                 ("adv", ctypes.c_double * 3), ("block", ctypes.c_int * 3),
-                ("variant", ctypes.c_int)]
+                ("variant", ctypes.c_int), ("row_pitch", ctypes.c_int),
+                ("x_offset", ctypes.c_int)]
 
 
 class _Fields(ctypes.Structure):
@@ -310,7 +311,7 @@ class RkPlan:
     MODEL_ADVDIFF: 1 field, 2-D or 3-D), radius-3 periodic padding."""
 
     def __init__(self, model, dims, precision=PREC_F64, ds=None, nu=1e-3, eta=1e-3, cs2=1.0,
-                 adv=(0.0, 0.0, 0.0), block=None, variant=0):
+                 adv=(0.0, 0.0, 0.0), block=None, variant=0, row_pitch=0, x_offset=0):
         import math
         self.model = model
         self.dims = tuple(int(v) for v in dims)
@@ -331,6 +332,10 @@ class RkPlan:
         d.block = (ctypes.c_int * 3)(*(list(block or []) + [0, 0, 0])[:3])
         d.variant = int(variant)
         self.variant = int(variant)
+        d.row_pitch = int(row_pitch)
+        d.x_offset = int(x_offset)
+        self.x_offset = int(x_offset) or 3
+        self.row_pitch = int(row_pitch) or (self.x_offset + self.dims[0] + 3)
         L = lib()
         h = _vp()
         check(L.stencil_plan_rk(ctypes.byref(d), ctypes.byref(h)))
@@ -346,13 +351,27 @@ class RkPlan:
         """Device buffers of one integration: f_a, f_b (storage), w, w2
         (registers) and f64 (master), as lists of padded tensors."""
         import torch
-        shp = padded_shape(self.dims, 3)
+        shp = self.storage_shape
         sd = torch_dtype(self.dtype)
         mk = lambda dt: [torch.zeros(shp, dtype=dt, device="cuda") for _ in range(self.nfields)]
         bufs = {"f_a": mk(sd), "f_b": mk(sd), "w": mk(self.reg_dtype)}
         bufs["w2"] = mk(self.reg_dtype) if self.master else None
         bufs["f64"] = mk(torch.float64) if self.master else None
         return bufs
+
+    @property
+    def storage_shape(self):
+        """Tensor shape [z, y, x] of one buffer in the plan's layout."""
+        return padded_shape(self.dims, 3)[:-1] + (self.row_pitch,)
+
+    def padded(self, t):
+        """View of the padded field (extents n + 6) inside a storage tensor."""
+        lo = self.x_offset - 3
+        return t[..., lo:lo + self.dims[0] + 6]
+
+    def interior(self, t):
+        """View of the interior points inside a storage tensor."""
+        return self.padded(t)[(slice(3, -3),) * self.ndim]
 
     def step(self, f_in, f_out, w, substep, dt, w2=None, f64=None, stream=None):
         fs = _fields_struct(f_in, f_out, w, w2, f64)

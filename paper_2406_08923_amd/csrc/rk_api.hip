@@ -144,6 +144,13 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     for (double v : prm)
         if (!std::isfinite(v))
             return fail(STENCIL_EINVAL, "non-finite model parameter");
+    const int ox = d->x_offset ? d->x_offset : 3;
+    const int64_t min_pitch = (int64_t)ox + d->dims[0] + 3;
+    if (d->x_offset < 0 || d->row_pitch < 0 || ox < 3 || ox > (1 << 20))
+        return fail(STENCIL_EINVAL, "x_offset %d must be in [3, 2^20]", ox);
+    if (d->row_pitch && (d->row_pitch < min_pitch || d->row_pitch > (1 << 30)))
+        return fail(STENCIL_EINVAL, "row_pitch %d not in [x_offset + dims[0] + 3 = %lld, 2^30]",
+                    d->row_pitch, (long long)min_pitch);
     if (d->variant < STENCIL_RK_VARIANT_AUTO || d->variant > STENCIL_RK_VARIANT_LDS)
         return fail(STENCIL_EINVAL, "unknown derivative-bank variant %d", d->variant);
     if (d->variant == STENCIL_RK_VARIANT_LDS && d->model != STENCIL_MODEL_MHD8)
@@ -188,7 +195,7 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     P.model = d->model;
     P.policy = d->precision;
     P.nf = d->model == STENCIL_MODEL_MHD8 ? 8 : 1;
-    P.g = make_geo(d->ndim, d->dims, 3);
+    P.g = make_geo(d->ndim, d->dims, 3, d->row_pitch ? d->row_pitch : (int)min_pitch, ox);
     double w1[7], w2[7];
     stencil_fd_weights(1, 3, w1);
     stencil_fd_weights(2, 3, w2);

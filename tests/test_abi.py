@@ -157,3 +157,18 @@ def _rk_rc(**kw):
 def test_rk_plan_rejects_bad_descriptors_without_a_device(kw, code):
     assert _rk_rc(**kw) == code
     assert S.lib().stencil_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(x_offset=2), dict(x_offset=8, row_pitch=20),
+                                dict(row_pitch=-4), dict(x_offset=-1)])
+def test_rk_plan_rejects_bad_layouts_without_a_device(kw):
+    d = S._RkDesc()
+    d.model, d.ndim = S.MODEL_MHD8, 3
+    d.dims = (ctypes.c_int * 3)(16, 16, 16)
+    d.precision = S.PREC_F64
+    d.ds = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    d.nu, d.eta, d.cs2 = 1e-3, 1e-3, 1.0
+    d.row_pitch = kw.get("row_pitch", 0)
+    d.x_offset = kw.get("x_offset", 0)
+    h = ctypes.c_void_p()
+    assert S.lib().stencil_plan_rk(ctypes.byref(d), ctypes.byref(h)) == -1

@@ -267,3 +267,69 @@ def test_step_validation():
     mb = mp.alloc()
     with pytest.raises(S.StencilError):
         mp.step(mb["f_a"], mb["f_b"], mb["w"], 2, 0.1)  # master policy needs w2 and f64
+
+
+# ---------------------------------------------------------------------------
+# pitched layout: interior at column x_offset of rows of row_pitch elements
+# ---------------------------------------------------------------------------
+
+def run_layout(model, n, prec, f, steps, dt, layout, **kw):
+    plan = S.RkPlan(model, n, prec, row_pitch=layout[0], x_offset=layout[1], **kw)
+    b = plan.alloc()
+    for k, v in enumerate(f):
+        b["f_a"][k].fill_(11.0)  # columns outside the padded rows
+        plan.padded(b["f_a"][k]).copy_(
+            torch.from_numpy(O.pad_periodic(v, 3)).cuda().to(b["f_a"][k].dtype))
+        if plan.master:
+            plan.padded(b["f64"][k]).copy_(torch.from_numpy(O.pad_periodic(v, 3)).cuda())
+    res = plan.run(b["f_a"], b["f_b"], b["w"], steps, dt, w2=b["w2"], f64=b["f64"])
+    state = b["f64"] if plan.master else res
+    out = [host(plan.padded(t)) for t in state]
+    lo, hi = plan.x_offset - 3, plan.x_offset + n[0] + 3
+    untouched = all(bool((host(t)[..., :lo] == 11.0).all() and (host(t)[..., hi:] == 11.0).all())
+                    for t in b["f_a"])
+    red = plan.reduce(state, dtype=S.F64 if plan.master else None)
+    return out, untouched, red
+
+
+@pytest.mark.parametrize("bank", [S.RK_LDS, S.RK_CACHED])
+def test_mhd8_pitched_layout_f64_matches_oracle(bank):
+    n = (40, 24, 20)
+    ds = ds_of(n)
+    dt = 0.1 * min(ds)
+    f = mhd_fields(n, 5)
+    out, untouched, red = run_layout(S.MODEL_MHD8, n, S.PREC_F64, f, 2, dt, (64, 16),
+                                     nu=NU, eta=ETA, cs2=CS2, variant=bank)
+    ref = O.rk3_steps(O.MODEL_MHD8, [O.pad_periodic(v, 3) for v in f], ds, dt, 2, nu=NU,
+                      eta=ETA, cs2=CS2)
+    for k in range(8):
+        assert relerr(out[k], ref[k]) <= 1e-12, k
+        assert np.array_equal(out[k], O.fill_periodic(out[k].copy(), 3))
+        want = O.reduce(ref[k], 3)
+        assert abs(red[k][0] - want[0]) <= 1e-12 * np.sum(np.abs(O.interior(ref[k], 3)))
+    assert untouched
+
+
+@pytest.mark.parametrize("prec", [S.PREC_F32_MASTER64, S.PREC_BF16_MASTER64])
+def test_mhd8_pitched_layout_bitwise_equal_to_compact(prec):
+    n = (40, 24, 20)
+    dt = 0.1 * min(ds_of(n))
+    f = mhd_fields(n, 6)
+    a, _, _ = run_layout(S.MODEL_MHD8, n, prec, f, 2, dt, (0, 0))
+    b, untouched, _ = run_layout(S.MODEL_MHD8, n, prec, f, 2, dt, (96, 32))
+    for k in range(8):
+        assert np.array_equal(a[k], b[k]), k
+    assert untouched
+
+
+@pytest.mark.parametrize("n", [(50, 37), (30, 20, 17)])
+def test_advdiff_pitched_layout(n):
+    ds = ds_of(n)
+    c = (0.7, -0.4, 0.3)[:len(n)]
+    dt = 0.1 * min(ds) / max(1.0, max(abs(v) for v in c))
+    f0 = inputs.uniform_field(n, 5)
+    out, untouched, _ = run_layout(S.MODEL_ADVDIFF, n, S.PREC_F64, [f0], 2, dt,
+                                   (n[0] + 20, 8), nu=0.01, adv=c)
+    ref = O.rk3_steps(O.MODEL_ADVDIFF, [O.pad_periodic(f0, 3)], ds, dt, 2, nu=0.01, c=c)
+    assert relerr(out[0], ref[0]) <= 1e-12
+    assert untouched
