@@ -194,6 +194,7 @@ def secondary(torch, S, W, inputs, args):
                                    "us_per_iteration": ms * 100.0,
                                    "variant": p1.variant, "tile": list(p1.tile)}
     del a, b
+    out["line_radius_sweep_2^24_f64"] = radius_sweep(torch, S, inputs)
     # fused 8-field RK3 step, 256^3
     nm = 256
     f, _ = inputs.fourier_fields((nm, nm, nm), 1, nf=8, modes=8, kmax=8, amp=0.01)
@@ -224,6 +225,30 @@ def secondary(torch, S, W, inputs, args):
     if args.serve_jobs > 0:
         out["serving"] = serving(torch, args.serve_jobs)
     return out
+
+
+def radius_sweep(torch, S, inputs, n=1 << 24, radii=(1, 2, 4, 8, 16, 64, 256, 1024)):
+    """1-D FP64 lines of 2^24 points (the paper's 1-D size), radius 1..1024,
+    random taps with sum |g| = 1, autotuned plan; 10 chained iterations per
+    timed call. Reports updates/s and the effective bandwidth 16 B per update
+    (the radius study of Sec. 5, Fig. 8: bandwidth-bound at small r, on-chip
+    bound at large r)."""
+    import numpy as np
+    res = {}
+    x = torch.from_numpy(inputs.uniform_field((n,), 1)).cuda()
+    for r in radii:
+        g = np.random.default_rng(r).uniform(-1, 1, 2 * r + 1)
+        g /= np.abs(g).sum()
+        p = S.LinearPlan((n,), r, g, autotune=True)
+        a = p.empty(0.0)
+        a[r:r + n] = x
+        b = p.empty(0.0)
+        ms = timed(torch, lambda: p.apply(a, b, 10), 5, warm=1) / 10
+        res[str(r)] = {"ms_per_iteration": ms, "updates_per_s": n / (ms * 1e-3),
+                       "effective_gbs": 16 * n / (ms * 1e-3) / 1e9,
+                       "variant": p.variant, "tile": list(p.tile)}
+        del a, b, p
+    return res
 
 
 def mixed_precision_error(torch, S, inputs, n=64, checkpoints=(1, 10, 100, 1000)):

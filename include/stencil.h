@@ -67,8 +67,9 @@ typedef enum { STENCIL_BC_PERIODIC = 0, STENCIL_BC_USER_HALO = 1 } stencil_bc;
 /* Linear stencil descriptor (Eq. 3 generalised by Eq. 6-7):
  *   out_p = sum over s in [-r, r]^ndim of coeffs_s * in_{p+s}.
  * coeffs: host pointer to the dense (2r+1)^ndim tensor, x fastest, copied by
- * stencil_plan; zero taps are pruned. radius 0..8 (r = 0 is a copy).
- * Periodic planes need dims[a] >= r on every active axis. */
+ * stencil_plan; zero taps are pruned. radius 0..1024 for ndim 1 (the
+ * large-radius regime of Sec. 5, Fig. 8), 0..8 for ndim 2 and 3 (r = 0 is a
+ * copy). Periodic plans need dims[a] >= r on every active axis. */
 typedef struct stencil_desc {
     int ndim;             /* 1, 2 or 3 */
     int dims[3];          /* interior extents (unused axes ignored) */
@@ -102,7 +103,11 @@ typedef struct stencil_desc {
      *   LINE1D : {outputs per lane: 1, 2, 4 or 8, iterations fused per
      *             launch T (0/1 = none; T > 1 periodic only: the block
      *             loads its range plus r*T wrapped cells once and iterates in
-     *             LDS, the temporal blocking the paper's discussion asks for)} */
+     *             LDS, the temporal blocking the paper's discussion asks for),
+     *             register blocking (nonzero: the lane's outputs are adjacent
+     *             and each input read from LDS feeds all of them; outputs per
+     *             lane 4, 8 or 16, needs 2r + 1 >= outputs - 1 and T <= 1;
+     *             bitwise equal to the plain line)} */
     int tile[4];
     /* Field layout (both 0 = compact, the layout of Eq. 2 with rows of
      * dims[0] + 2r cells). x_offset: column of interior x = 0 (>= radius);

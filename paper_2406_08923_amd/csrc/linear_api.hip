@@ -42,6 +42,11 @@ int check_launch(const char *what)
 // validation helpers
 // ---------------------------------------------------------------------------
 
+// Largest radius a plan accepts: 1-D lines reach the large-radius regime of
+// the paper's radius study (Sec. 5, Fig. 8); multi-dimensional dense boxes
+// stop at 8 ((2r+1)^3 = 4913 taps).
+int max_radius(int ndim) { return ndim == 1 ? 1024 : 8; }
+
 int check_dims(int ndim, const int *dims, int r, int bc)
 {
     if (ndim < 1 || ndim > 3)
@@ -116,6 +121,9 @@ template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out
         return rc;
     }
     case STENCIL_VARIANT_LINE1D:
+        if (p->lin.rb1d)
+            return launch_line1d_rb<S>(in, out, p->lin.g, static_cast<const C *>(p->lin.d_dense),
+                                       periodic, p->lin.e1d, s);
         return launch_line1d<S>(in, out, p->lin.g, static_cast<const C *>(p->lin.d_dense),
                                 periodic, p->lin.e1d, s);
     default:
@@ -222,6 +230,7 @@ void set_choice(stencil_plan_s *p, const TuneChoice &c)
     } else if (c.variant == STENCIL_VARIANT_LINE1D) {
         p->lin.e1d = c.p0;
         p->lin.t1d = c.p1 > 1 ? c.p1 : 1;
+        p->lin.rb1d = c.p2 ? 1 : 0;
     } else {
         p->lin.gbx = c.p0;
         p->lin.gby = c.p1;
@@ -272,11 +281,16 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
                 c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, STAR_FLAG_HWC});
             }
     }
-    if (g.ndim == 1)
+    if (g.ndim == 1) {
         for (int e : {1, 2, 4, 8})
             for (int T : {1, 4, 8, 16})
                 if (T == 1 || p->lin.bc == STENCIL_BC_PERIODIC)
                     c.push_back({STENCIL_VARIANT_LINE1D, e, T, 0, 0});
+        // register-blocked lines for the large-radius regime
+        for (int e : {4, 8, 16})
+            if (2 * g.r + 1 >= e - 1 && g.r >= 8)
+                c.push_back({STENCIL_VARIANT_LINE1D, e, 1, 1, 0});
+    }
     if (g.ndim == 1) {
         c.push_back({STENCIL_VARIANT_GENERIC, 256, 1, 0, 0});
     } else {
@@ -420,8 +434,9 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
     if (!d || !out)
         return fail(STENCIL_EINVAL, "NULL descriptor or output");
     *out = nullptr;
-    if (d->radius < 0 || d->radius > 8)
-        return fail(STENCIL_EINVAL, "radius %d not in 0..8", d->radius);
+    if (d->ndim >= 1 && d->ndim <= 3 && (d->radius < 0 || d->radius > max_radius(d->ndim)))
+        return fail(STENCIL_EINVAL, "radius %d not in 0..%d for ndim %d", d->radius,
+                    max_radius(d->ndim), d->ndim);
     if (d->dtype < STENCIL_F64 || d->dtype > STENCIL_BF16)
         return fail(STENCIL_EINVAL, "unknown dtype %d", d->dtype);
     if (d->bc != STENCIL_BC_PERIODIC && d->bc != STENCIL_BC_USER_HALO)
@@ -582,6 +597,12 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
         } else if (c.variant == STENCIL_VARIANT_LINE1D) {
             if (t[0]) c.p0 = t[0];
             if (t[1]) c.p1 = t[1];
+            c.p2 = t[2] ? 1 : 0;
+            if (c.p2 && c.p1 > 1) {
+                stencil_plan_destroy(p);
+                return fail(STENCIL_EINVAL, "register blocking and fused iterations exclude "
+                                            "each other");
+            }
             if (c.p1 > 1 && d->bc != STENCIL_BC_PERIODIC) {
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "temporal blocking needs a periodic plan");
@@ -648,6 +669,7 @@ stencil_status stencil_plan_tile(stencil_plan_t p, int tile[4])
     } else if (L.variant == STENCIL_VARIANT_LINE1D) {
         tile[0] = L.e1d;
         tile[1] = L.t1d;
+        tile[2] = L.rb1d;
     } else {
         tile[0] = L.gbx;
         tile[1] = L.gby;
@@ -692,8 +714,9 @@ stencil_status stencil_halo_periodic(int ndim, const int dims[3], int radius, in
 {
     int rc = check_dims(ndim, dims, radius, STENCIL_BC_PERIODIC);
     if (rc) return rc;
-    if (radius < 0 || radius > 8)
-        return fail(STENCIL_EINVAL, "radius %d not in 0..8", radius);
+    if (radius < 0 || radius > max_radius(ndim))
+        return fail(STENCIL_EINVAL, "radius %d not in 0..%d for ndim %d", radius,
+                    max_radius(ndim), ndim);
     const size_t es = dtype_size(dtype);
     if (!es)
         return fail(STENCIL_EINVAL, "unknown dtype %d", dtype);

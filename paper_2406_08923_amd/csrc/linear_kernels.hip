@@ -177,6 +177,97 @@ int launch_line1d(const S *in, S *out, const Geo &g, const typename Store<S>::C 
 }
 
 // ---------------------------------------------------------------------------
+// 1-D line, register-blocked for large radii: lane l owns the E adjacent
+// outputs x0 + l*E + e and walks the inputs once, each value feeding all E
+// accumulators (with the matching tap from a sliding window of coefficients),
+// so LDS is read once per input instead of once per tap. The LDS row is
+// padded by one cell every E cells, so the lanes' stride-E reads hit distinct
+// banks. Every output is the same fma chain over taps 0..K-1 as in k_line1d,
+// so results are bitwise equal. Needs K = 2r + 1 >= E - 1.
+// ---------------------------------------------------------------------------
+
+template <typename S, int E>
+__global__ void __launch_bounds__(256)
+    k_line1d_rb(const S *__restrict__ in, S *__restrict__ out, Geo g,
+                const typename Store<S>::C *__restrict__ cs, int fuse)
+{
+    using C = typename Store<S>::C;
+    constexpr int NT = 256, BX = NT * E;
+    extern __shared__ unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int r = g.r, K = 2 * r + 1;
+    const int x0 = blockIdx.x * BX;
+    const int W = BX + 2 * r;
+    for (int i = threadIdx.x; i < W; i += NT) {
+        const int xi = min(x0 - r + i, g.nx + r - 1);
+        buf[i + i / E] = Store<S>::ld(in + g.at(xi, 0, 0));
+    }
+    __syncthreads();
+    const int base = threadIdx.x * E;
+    auto at = [&](int j) { const int i = base + j; return buf[i + i / E]; };
+    C acc[E], cw[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = cw[e] = 0;
+    // head: inputs j = 0..E-2 feed outputs e <= j (taps j - e)
+#pragma unroll
+    for (int j = 0; j < E - 1; ++j) {
+#pragma unroll
+        for (int e = E - 1; e > 0; --e) cw[e] = cw[e - 1];
+        cw[0] = cs[j];
+        const C v = at(j);
+#pragma unroll
+        for (int e = 0; e <= j; ++e) acc[e] = fma(cw[e], v, acc[e]);
+    }
+    // body: inputs j = E-1..K-1 feed every output
+    for (int j = E - 1; j < K; ++j) {
+#pragma unroll
+        for (int e = E - 1; e > 0; --e) cw[e] = cw[e - 1];
+        cw[0] = cs[j];
+        const C v = at(j);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = fma(cw[e], v, acc[e]);
+    }
+    // tail: inputs j = K..K+E-2 feed outputs e >= j - K + 1
+#pragma unroll
+    for (int d = 1; d < E; ++d) {
+#pragma unroll
+        for (int e = E - 1; e > 0; --e) cw[e] = cw[e - 1];
+        const C v = at(K - 1 + d);
+#pragma unroll
+        for (int e = d; e < E; ++e) acc[e] = fma(cw[e], v, acc[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int x = x0 + base + e;
+        if (x < g.nx)
+            store_periodic(out, g, x, 0, 0, acc[e], fuse != 0);
+    }
+}
+
+template <typename S>
+int launch_line1d_rb(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs,
+                     bool fuse, int e, hipStream_t s)
+{
+    using C = typename Store<S>::C;
+    if (2 * g.r + 1 < e - 1)
+        return fail(STENCIL_EUNSUPPORTED, "line1d: register blocking of %d needs radius >= %d", e,
+                    (e - 2) / 2);
+    const int bx = 256 * e;
+    const size_t w = (size_t)bx + 2 * g.r;
+    const size_t shm = (w + w / e + 1) * sizeof(C);
+    if (shm > 160 * 1024)
+        return fail(STENCIL_EUNSUPPORTED, "line1d: radius %d too large for LDS", g.r);
+    dim3 grid((g.nx + bx - 1) / bx);
+    switch (e) {
+    case 4: hipLaunchKernelGGL((k_line1d_rb<S, 4>), grid, dim3(256), shm, s, in, out, g, cs, fuse ? 1 : 0); break;
+    case 8: hipLaunchKernelGGL((k_line1d_rb<S, 8>), grid, dim3(256), shm, s, in, out, g, cs, fuse ? 1 : 0); break;
+    case 16: hipLaunchKernelGGL((k_line1d_rb<S, 16>), grid, dim3(256), shm, s, in, out, g, cs, fuse ? 1 : 0); break;
+    default: return fail(STENCIL_EUNSUPPORTED, "line1d: register blocking %d not in {4,8,16}", e);
+    }
+    return check_launch("xcorr_line1d_rb");
+}
+
+// ---------------------------------------------------------------------------
 // 1-D line, temporally blocked: T chained iterations in one launch. A block
 // owning outputs [x0, x0 + BX) loads [x0 - rT, x0 + BX + rT) from the interior
 // with periodic wrap (the input halo is not read), iterates T times in LDS
@@ -284,7 +375,9 @@ int launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t s)
     template int launch_line1d<S>(const S *, S *, const Geo &, const typename Store<S>::C *, \
                                   bool, int, hipStream_t);                                   \
     template int launch_line1d_t<S>(const S *, S *, const Geo &,                             \
-                                    const typename Store<S>::C *, bool, int, int, hipStream_t);
+                                    const typename Store<S>::C *, bool, int, int, hipStream_t); \
+    template int launch_line1d_rb<S>(const S *, S *, const Geo &,                            \
+                                     const typename Store<S>::C *, bool, int, hipStream_t);
 INST(double)
 INST(float)
 INST(bf16)

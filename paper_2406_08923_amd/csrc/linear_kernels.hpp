@@ -75,6 +75,12 @@ template <typename S>
 int launch_line1d_t(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs, bool fuse,
                     int e, int T, hipStream_t s);
 
+// Register-blocked 1-D line: e in {4, 8, 16} adjacent outputs per lane, for
+// large radii (2r + 1 >= e - 1); bitwise equal to launch_line1d.
+template <typename S>
+int launch_line1d_rb(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs,
+                     bool fuse, int e, hipStream_t s);
+
 int launch_copy(const void *src, void *dst, size_t nbytes, hipStream_t s);
 
 } // namespace stn

@@ -27,7 +27,8 @@ struct LinearPlan {
     int s1[5] = {0};        // one-iteration STAR3D shape used beside tstar = 2:
                             // {ty, ny, lz, flags, xw}
     int gbx = 64, gby = 4;                   // GENERIC
-    int e1d = 4, t1d = 1;                    // LINE1D: outputs per lane, fused iterations
+    int e1d = 4, t1d = 1, rb1d = 0;          // LINE1D: outputs per lane, fused
+                                             // iterations, adjacent (register-blocked)
 };
 
 struct RkPlan {

@@ -83,6 +83,8 @@ def _plan_rc(**kw):
                                 dict(coeffs=None), dict(dtype=7), dict(bc=3),
                                 dict(dims=(2, 8, 8), radius=3, coeffs=np.ones(343)),
                                 dict(dims=(0, 8, 8)), dict(variant=9),
+                                dict(ndim=1, dims=(4096, 1, 1), radius=1025, coeffs=np.ones(2051)),
+                                dict(ndim=2, dims=(64, 64, 1), radius=9, coeffs=np.ones(361)),
                                 # layout: x_offset below the radius, pitch too short
                                 # for x_offset + nx + r, pitch on a 1-D field, negatives
                                 dict(radius=2, x_offset=1, coeffs=np.ones(125)),

@@ -528,6 +528,66 @@ def test_line1d_temporal_blocking(n, r, e, T, iters):
     run_case((n,), r, g, S.F64, S.LINE1D, tile=(e, T), iters=iters)
 
 
+# ---------------------------------------------------------------------------
+# large radius (1-D lines up to r = 1024, the radius study of Sec. 5)
+# ---------------------------------------------------------------------------
+
+def bounded_taps(r, seed):
+    g = np.random.default_rng(seed).uniform(-1, 1, 2 * r + 1)
+    return g / np.abs(g).sum()  # sum |g| = 1: chained iterations stay bounded
+
+
+@pytest.mark.parametrize("r", [16, 100, 1024])
+@pytest.mark.parametrize("variant,tile", [(S.LINE1D, (1, 1)), (S.LINE1D, (8, 1)),
+                                          (S.LINE1D, (4, 2)), (S.GENERIC, None),
+                                          (S.LINE1D, (4, 1, 1)), (S.LINE1D, (8, 1, 1)),
+                                          (S.LINE1D, (16, 1, 1))])
+def test_line1d_large_radius(r, variant, tile):
+    n = 65536 + 37
+    g = bounded_taps(r, r)
+    run_case((n,), r, g, S.F64, variant, tile=tile, iters=3)
+
+
+@pytest.mark.parametrize("r", [64, 1024])
+def test_line1d_large_radius_fp32(r):
+    run_case((20011,), r, bounded_taps(r, 3), S.F32, S.LINE1D, tile=(4, 1))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("e,r,n", [(4, 2, 5000), (8, 4, 2049), (16, 7, 777), (16, 300, 4099),
+                                   (8, 1024, 70000)])
+def test_line1d_register_blocked_bitwise_equal_to_plain_line(dtype, e, r, n):
+    g = bounded_taps(r, 11)
+    inner = to_storage_values(inputs.uniform_field((n,), 2), dtype)
+    outs = []
+    for tile in ((1, 1), (e, 1, 1)):
+        plan = S.LinearPlan((n,), r, g, dtype=dtype, variant=S.LINE1D, tile=tile)
+        a = dev(O.pad_periodic(inner, r), dtype)
+        b = plan.empty(0.0)
+        outs.append(host(plan.apply(a, b, 2)))
+    assert np.array_equal(outs[0], outs[1])
+    if dtype == S.F64:
+        ref = oracle_apply(inner, r, g, 2)
+        assert_close(O.interior(outs[1], r), O.interior(ref, r), S.F64)
+
+
+def test_line1d_register_blocking_validation():
+    g = bounded_taps(1, 1)
+    with pytest.raises(S.StencilError):
+        S.LinearPlan((1000,), 1, g, variant=S.LINE1D, tile=(16, 1, 1)).apply(
+            torch.zeros(1002, dtype=torch.float64, device="cuda"),
+            torch.zeros(1002, dtype=torch.float64, device="cuda"))
+    with pytest.raises(S.StencilError):
+        S.LinearPlan((1000,), 8, bounded_taps(8, 1), variant=S.LINE1D, tile=(8, 4, 1))
+
+
+def test_line1d_radius_equal_to_length():
+    # periodic with n == r: every output reads each input several times
+    r = n = 300
+    run_case((n,), r, bounded_taps(r, 5), S.F64, S.LINE1D, tile=(2, 1), iters=2)
+    run_case((n,), r, bounded_taps(r, 5), S.F64, S.GENERIC, iters=2)
+
+
 def test_line1d_temporal_needs_periodic():
     with pytest.raises(S.StencilError):
         S.LinearPlan((100,), 1, W.smoother3(), bc=S.USER_HALO, variant=S.LINE1D, tile=(4, 8))
