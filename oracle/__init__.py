@@ -21,6 +21,8 @@ MODEL_MHD8 = 0
 MODEL_ADVDIFF = 1
 # field order of the 8-field system (Table A1)
 LNRHO, UX, UY, UZ, SS, AX, AY, AZ = range(8)
+# window filter codes (max filter of Sec. 2.3; median filter of Sec. 1)
+FILTER_MAX, FILTER_MIN, FILTER_MEDIAN = 1, 2, 3
 # derivative operator codes
 OP_X, OP_Y, OP_Z, OP_XX, OP_YY, OP_ZZ, OP_XY, OP_XZ, OP_YZ = range(9)
 
@@ -56,6 +58,9 @@ def lib():
                                             ctypes.c_double, _lp, ctypes.c_long, _dp, _dp]
         L.oracle_rk3_substep_at.restype = ctypes.c_int
         L.oracle_reduce.argtypes = [_dp, ctypes.c_int, _lp, ctypes.c_int, _dp]
+        L.oracle_filter.argtypes = [_dp, _dp, ctypes.c_int, _lp, ctypes.c_int, _dp, ctypes.c_int]
+        L.oracle_filter_at.argtypes = [_dp, ctypes.c_int, _lp, ctypes.c_int, _dp, ctypes.c_int,
+                                       _lp, ctypes.c_long, _dp]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -140,6 +145,37 @@ def xcorr_periodic_iterate(a, r, g, iters):
     for _ in range(iters):
         cur = fill_periodic(xcorr(cur, r, g), r)
     return cur
+
+
+def filter(a, r, mask, op):
+    """Window filter of padded a (op FILTER_MAX / FILTER_MIN / FILTER_MEDIAN)
+    over the offsets where the dense (2r+1)^ndim mask is nonzero. Values are
+    ordered numerically with -0 below +0; a window holding a NaN gives NaN;
+    the median of m values is the element of rank (m-1)//2. Returns a padded
+    array, halo zero."""
+    nd, n = _dims(a, r)
+    mask = np.ascontiguousarray(mask, dtype=np.float64)
+    assert mask.shape == (2 * r + 1,) * nd
+    out = np.zeros_like(a)
+    if lib().oracle_filter(_ptr(a), _ptr(out), nd, n, r, _ptr(mask), int(op)) != 0:
+        raise ValueError("unknown filter op")
+    return out
+
+
+def filter_at(a, r, mask, op, pts):
+    """The window filter at interior points pts (rows of (x, y, z))."""
+    nd, n = _dims(a, r)
+    mask = np.ascontiguousarray(mask, dtype=np.float64)
+    assert mask.shape == (2 * r + 1,) * nd
+    pts = np.ascontiguousarray(pts, dtype=np.int64).reshape(-1, 3)
+    nn = [n[0], n[1], n[2]]
+    if len(pts) and (pts.min() < 0 or any(pts[:, a].max() >= nn[a] for a in range(3))):
+        raise ValueError("point outside the interior")
+    out = np.zeros(len(pts))
+    if lib().oracle_filter_at(_ptr(a), nd, n, r, _ptr(mask), int(op), pts.ctypes.data_as(_lp),
+                              len(pts), _ptr(out)) != 0:
+        raise ValueError("unknown filter op")
+    return out
 
 
 def xcorr_at(a, r, g, pts):

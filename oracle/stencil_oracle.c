@@ -22,7 +22,9 @@
  * Parity status: every function here is pinned by the CPU test-suite against
  * closed forms (moment conditions, polynomial exactness, Fourier symbols,
  * conservation, dense-matrix brute force, the RK3 stability polynomial and
- * term-by-term special cases of the right-hand side).
+ * term-by-term special cases of the right-hand side); the window filters
+ * against scipy's rank filters with periodic wrap, a brute force over shifted
+ * copies, max/min duality, signed-zero order and NaN confinement.
  */
 #include <math.h>
 #include <stddef.h>
@@ -133,6 +135,110 @@ void oracle_xcorr_at(const double *in, int ndim, const long *n, int r, const dou
     long P[3] = {ext(ndim, 0, n, r), ext(ndim, 1, n, r), ext(ndim, 2, n, r)};
     for (long k = 0; k < count; ++k)
         out[k] = xcorr_point(in, P, ndim, r, g, pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nonlinear window filters (Sec. 2.3: max filtering; Sec. 1: median)       */
+/* ------------------------------------------------------------------------ */
+
+/* The window is the set of offsets whose mask entry is nonzero (the dense
+ * (2r+1)^ndim layout of the cross-correlation coefficients). Values are
+ * ordered by IEEE totalOrder restricted to non-NaN numbers: numeric order,
+ * with -0 below +0, so the maximum, minimum and median are unique elements of
+ * the window whatever the order they are visited in. A window holding a NaN
+ * yields NaN. The median of m values is the element of rank (m-1)/2 from the
+ * bottom (the lower median when m is even). */
+enum { FILTER_MAX = 1, FILTER_MIN = 2, FILTER_MEDIAN = 3 };
+
+static int total_less(double a, double b)
+{
+    if (a == b)
+        return a == 0.0 && signbit(a) && !signbit(b);
+    return a < b;
+}
+
+static double filter_point(const double *in, const long *P, int ndim, int r, const double *mask,
+                           int op, long x, long y, long z, double *scratch)
+{
+    int K = 2 * r + 1;
+    int rx = r, ry = ndim > 1 ? r : 0, rz = ndim > 2 ? r : 0;
+    int Ky = ndim > 1 ? K : 1;
+    int m = 0, has_nan = 0;
+    for (int sz = -rz; sz <= rz; ++sz)
+        for (int sy = -ry; sy <= ry; ++sy)
+            for (int sx = -rx; sx <= rx; ++sx) {
+                if (mask[(sx + r) + (size_t)K * ((sy + ry) + (size_t)Ky * (sz + rz))] == 0.0)
+                    continue;
+                double v = in[at(P, x + rx + sx, y + ry + sy, z + rz + sz)];
+                if (isnan(v))
+                    has_nan = 1;
+                scratch[m++] = v;
+            }
+    if (has_nan || m == 0)
+        return NAN;
+    if (op == FILTER_MAX || op == FILTER_MIN) {
+        double best = scratch[0];
+        for (int i = 1; i < m; ++i)
+            if (op == FILTER_MAX ? total_less(best, scratch[i]) : total_less(scratch[i], best))
+                best = scratch[i];
+        return best;
+    }
+    /* median: insertion sort, then the element of rank (m - 1) / 2 */
+    for (int i = 1; i < m; ++i) {
+        double v = scratch[i];
+        int j = i - 1;
+        while (j >= 0 && total_less(v, scratch[j])) {
+            scratch[j + 1] = scratch[j];
+            --j;
+        }
+        scratch[j + 1] = v;
+    }
+    return scratch[(m - 1) / 2];
+}
+
+/* Interior of out receives the filter of in over the window; halo untouched.
+ * Returns -1 for an unknown op. */
+int oracle_filter(const double *in, double *out, int ndim, const long *n, int r,
+                  const double *mask, int op)
+{
+    if (op < FILTER_MAX || op > FILTER_MEDIAN)
+        return -1;
+    long P[3] = {ext(ndim, 0, n, r), ext(ndim, 1, n, r), ext(ndim, 2, n, r)};
+    long nz = ndim > 2 ? n[2] : 1, ny = ndim > 1 ? n[1] : 1, nx = n[0];
+    int ry = ndim > 1 ? r : 0, rz = ndim > 2 ? r : 0;
+    size_t K = 2 * (size_t)r + 1, cap = K;
+    for (int a = 1; a < ndim; ++a)
+        cap *= K;
+#pragma omp parallel
+    {
+        double *scratch = malloc(cap * sizeof(double));
+#pragma omp for schedule(static)
+        for (long z = 0; z < nz; ++z)
+            for (long y = 0; y < ny; ++y)
+                for (long x = 0; x < nx; ++x)
+                    out[at(P, x + r, y + ry, z + rz)] =
+                        filter_point(in, P, ndim, r, mask, op, x, y, z, scratch);
+        free(scratch);
+    }
+    return 0;
+}
+
+/* The same filter at listed interior points (count triples x, y, z). */
+int oracle_filter_at(const double *in, int ndim, const long *n, int r, const double *mask,
+                     int op, const long *pts, long count, double *out)
+{
+    if (op < FILTER_MAX || op > FILTER_MEDIAN)
+        return -1;
+    long P[3] = {ext(ndim, 0, n, r), ext(ndim, 1, n, r), ext(ndim, 2, n, r)};
+    size_t K = 2 * (size_t)r + 1, cap = K;
+    for (int a = 1; a < ndim; ++a)
+        cap *= K;
+    double *scratch = malloc(cap * sizeof(double));
+    for (long k = 0; k < count; ++k)
+        out[k] = filter_point(in, P, ndim, r, mask, op, pts[3 * k], pts[3 * k + 1], pts[3 * k + 2],
+                              scratch);
+    free(scratch);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
