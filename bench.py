@@ -195,6 +195,7 @@ def secondary(torch, S, W, inputs, args):
                                    "variant": p1.variant, "tile": list(p1.tile)}
     del a, b
     out["line_radius_sweep_2^24_f64"] = radius_sweep(torch, S, inputs)
+    out["filters_512_f64"] = filters(torch, S, inputs, args.n)
     # fused 8-field RK3 step, 256^3
     nm = 256
     f, _ = inputs.fourier_fields((nm, nm, nm), 1, nf=8, modes=8, kmax=8, amp=0.01)
@@ -224,6 +225,28 @@ def secondary(torch, S, W, inputs, args):
         out["mhd8_mixed_precision_error_64"] = mixed_precision_error(torch, S, inputs)
     if args.serve_jobs > 0:
         out["serving"] = serving(torch, args.serve_jobs)
+    return out
+
+
+def filters(torch, S, inputs, n):
+    """Window filters on the n^3 FP64 field: 3x3x3 max (z-march kernel) and
+    3x3x3 median (gather kernel, rank selection among 27 keys), one periodic
+    application per launch; 16 B per point (read once, write once)."""
+    import numpy as np
+    dims, r = (n, n, n), 1
+    out = {}
+    x = torch.from_numpy(inputs.uniform_field(dims, 1)).cuda()
+    for name, op in (("max_3x3x3", S.OP_MAX), ("median_3x3x3", S.OP_MEDIAN)):
+        p = S.LinearPlan(dims, r, np.ones((3, 3, 3)), op=op)
+        a = p.empty(0.0)
+        p.padded(a)[r:r + n, r:r + n, r:r + n] = x
+        b = p.empty(0.0)
+        p.halo(a)
+        ms = timed(torch, lambda: p.apply(a, b, 1, halo_valid=True), 20, warm=2)
+        out[name] = {"ms_per_launch": ms, "updates_per_s": n ** 3 / (ms * 1e-3),
+                     "hbm_frac": 16 * n ** 3 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "variant": p.variant, "tile": list(p.tile)}
+        del a, b, p
     return out
 
 

@@ -120,7 +120,25 @@ typedef struct stencil_desc {
      * star kernel's tile rows whole cache lines. */
     int row_pitch;
     int x_offset;
+    /* What the stencil function zeta computes (STENCIL_OP_*). XCORR (0): the
+     * cross-correlation above. MAX / MIN: the max filter of Sec. 2.3 (and its
+     * min twin) over the window of offsets whose coeffs entry is nonzero (the
+     * values only mark the window). MEDIAN: the median filter of Sec. 1 over
+     * that window (at most STENCIL_MEDIAN_MAX cells; the lower median when
+     * the count is even). Filters order values numerically with -0 below +0;
+     * a window holding a NaN yields NaN; results are elements of the window
+     * (no rounding). Filters run the GENERIC gather (any window) or, for 3-D
+     * max/min over a full box of radius 1..3, the STAR3D z march (tile: {y
+     * lanes 4 or 8, 0, z planes per workgroup, 0}); LINE1D and fused
+     * iterations are cross-correlation only. */
+    int op;
 } stencil_desc;
+
+#define STENCIL_OP_XCORR 0
+#define STENCIL_OP_MAX 1
+#define STENCIL_OP_MIN 2
+#define STENCIL_OP_MEDIAN 3
+#define STENCIL_MEDIAN_MAX 27
 
 typedef struct stencil_plan_s *stencil_plan_t;
 

@@ -20,6 +20,10 @@ LIB_PATH = os.path.join(_HERE, "libstencil.so")
 F64, F32, BF16 = 0, 1, 2
 PERIODIC, USER_HALO = 0, 1
 VARIANT_AUTO, GENERIC, STAR3D, LINE1D = -1, 0, 1, 2
+# stencil function: cross-correlation, or a window filter (max filter of
+# Sec. 2.3, its min twin, median filter of Sec. 1)
+OP_XCORR, OP_MAX, OP_MIN, OP_MEDIAN = 0, 1, 2, 3
+MEDIAN_MAX = 27
 FLAG_AUTOTUNE = 1
 APPLY_HALO_VALID = 1
 
@@ -38,7 +42,7 @@ class _Desc(ctypes.Structure):
                 ("coeffs", ctypes.POINTER(ctypes.c_double)), ("dtype", ctypes.c_int),
                 ("bc", ctypes.c_int), ("flags", ctypes.c_uint), ("variant", ctypes.c_int),
                 ("tile", ctypes.c_int * 4), ("row_pitch", ctypes.c_int),
-                ("x_offset", ctypes.c_int)]
+                ("x_offset", ctypes.c_int), ("op", ctypes.c_int)]
 
 
 _lib = None
@@ -135,10 +139,12 @@ def copy(src, dst, nbytes=None, stream=None):
 
 class LinearPlan:
     """Plan of a linear stencil (Eq. 3 / Eq. 6-7): ``coeffs`` is the dense
-    (2r+1)^ndim tensor in NumPy order [s_z, s_y, s_x] (x fastest)."""
+    (2r+1)^ndim tensor in NumPy order [s_z, s_y, s_x] (x fastest). With op
+    OP_MAX / OP_MIN / OP_MEDIAN the plan is a window filter over the offsets
+    where coeffs is nonzero."""
 
     def __init__(self, dims, radius, coeffs, dtype=F64, bc=PERIODIC, autotune=False,
-                 variant=VARIANT_AUTO, tile=None, row_pitch=0, x_offset=0):
+                 variant=VARIANT_AUTO, tile=None, row_pitch=0, x_offset=0, op=OP_XCORR):
         self.dims = tuple(int(v) for v in dims)
         self.ndim = len(self.dims)
         self.radius = int(radius)
@@ -161,6 +167,8 @@ class LinearPlan:
         d.tile = (ctypes.c_int * 4)(*(list(tile or []) + [0] * 4)[:4])
         d.row_pitch = int(row_pitch)
         d.x_offset = int(x_offset)
+        d.op = int(op)
+        self.op = int(op)
         h = _vp()
         check(lib().stencil_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

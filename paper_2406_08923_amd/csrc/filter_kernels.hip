@@ -1,0 +1,296 @@
+// filter_kernels.hip -- nonlinear window filters for gfx950: the max filter of
+// Sec. 2.3 (and its min twin) and the median filter named in Sec. 1, over the
+// window given by the nonzero pattern of a (2r+1)^ndim mask.
+//
+// Every result is one element of the window, so the kernels compare order-
+// preserving integer keys and never round: a value's key orders numbers
+// numerically with -0 below +0 (IEEE totalOrder on non-NaN values), and a NaN
+// maps to a sentinel that wins every comparison of the op, so a window holding
+// a NaN yields NaN. The maximum, minimum and median are therefore unique and
+// independent of the order the window is visited in: results are bit-exact.
+#include "filter_kernels.hpp"
+
+namespace stn {
+
+namespace {
+
+template <typename C> struct Key;
+
+template <> struct Key<double> {
+    using U = uint64_t;
+    static constexpr U NAN_MAX = ~U(0), NAN_MIN = U(0);
+    static __device__ __forceinline__ U of(double v)
+    {
+        const U b = __builtin_bit_cast(U, v);
+        return (b >> 63) ? ~b : (b | (U(1) << 63));
+    }
+    static __device__ __forceinline__ double val(U k)
+    {
+        return __builtin_bit_cast(double, (k >> 63) ? (k & ~(U(1) << 63)) : ~k);
+    }
+};
+
+template <> struct Key<float> {
+    using U = uint32_t;
+    static constexpr U NAN_MAX = ~U(0), NAN_MIN = U(0);
+    static __device__ __forceinline__ U of(float v)
+    {
+        const U b = __builtin_bit_cast(U, v);
+        return (b >> 31) ? ~b : (b | (U(1) << 31));
+    }
+    static __device__ __forceinline__ float val(U k)
+    {
+        return __builtin_bit_cast(float, (k >> 31) ? (k & ~(U(1) << 31)) : ~k);
+    }
+};
+
+// key of v for a max (NaN on top) or a min (NaN at the bottom) reduction
+template <typename C, int OP> __device__ __forceinline__ typename Key<C>::U mkey(C v)
+{
+    if (v != v)
+        return OP == FILTER_OP_MAX ? Key<C>::NAN_MAX : Key<C>::NAN_MIN;
+    return Key<C>::of(v);
+}
+
+template <typename C, int OP> __device__ __forceinline__ C unkey(typename Key<C>::U k)
+{
+    if (k == (OP == FILTER_OP_MAX ? Key<C>::NAN_MAX : Key<C>::NAN_MIN))
+        return C(__builtin_nan(""));
+    return Key<C>::val(k);
+}
+
+template <int OP, typename U> __device__ __forceinline__ U pick(U a, U b)
+{
+    return OP == FILTER_OP_MAX ? (a > b ? a : b) : (a < b ? a : b);
+}
+
+} // namespace
+
+// Gather form (the hardware-cached strategy of Sec. 4.1): one lane per output,
+// the window's offsets listed in lexicographic (s_z, s_y, s_x) order.
+template <typename S, int OP>
+__global__ void __launch_bounds__(256)
+    k_filter_minmax(const S *__restrict__ in, S *__restrict__ out, Geo g,
+                    const int *__restrict__ offs, int ntaps, int fuse)
+{
+    using C = typename Store<S>::C;
+    using U = typename Key<C>::U;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny)
+        return;
+    const int64_t p = g.at(x, y, z);
+    U best = mkey<C, OP>(Store<S>::ld(in + p + offs[0]));
+    for (int t = 1; t < ntaps; ++t)
+        best = pick<OP>(best, mkey<C, OP>(Store<S>::ld(in + p + offs[t])));
+    store_periodic(out, g, x, y, z, unkey<C, OP>(best), fuse != 0);
+}
+
+// Median of up to FILTER_MEDIAN_MAX window values: the element whose rank
+// (count of smaller keys, ties broken by window position) is (m - 1) / 2.
+template <typename S>
+__global__ void __launch_bounds__(256)
+    k_filter_median(const S *__restrict__ in, S *__restrict__ out, Geo g,
+                    const int *__restrict__ offs, int m, int fuse)
+{
+    using C = typename Store<S>::C;
+    using U = typename Key<C>::U;
+    constexpr int MM = FILTER_MEDIAN_MAX;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny)
+        return;
+    const int64_t p = g.at(x, y, z);
+    U k[MM];
+    bool nan = false;
+#pragma unroll
+    for (int t = 0; t < MM; ++t) {
+        k[t] = 0;
+        if (t < m) {
+            const C v = Store<S>::ld(in + p + offs[t]);
+            nan = nan || (v != v);
+            k[t] = Key<C>::of(v);
+        }
+    }
+    const int want = (m - 1) / 2;
+    U res = k[0];
+    // fully unrolled (compile-time indices keep k in registers); cells past
+    // m are excluded by the wave-uniform guards
+#pragma unroll
+    for (int i = 0; i < MM; ++i) {
+        int cnt = 0;
+#pragma unroll
+        for (int j = 0; j < MM; ++j)
+            cnt += (j < m) & ((k[j] < k[i]) | ((k[j] == k[i]) & (j < i)));
+        res = (i < m && cnt == want) ? k[i] : res;
+    }
+    const C v = nan ? C(__builtin_nan("")) : Key<C>::val(res);
+    store_periodic(out, g, x, y, z, v, fuse != 0);
+}
+
+// 3-D box window (all (2R+1)^3 offsets), max or min: a z march. The workgroup
+// (64 x TY lanes) stages each plane of its tile plus an R-wide halo (corners
+// included) as keys in LDS, reduces the (2R+1)^2 square around each lane's
+// column, and keeps the last 2R+1 square reductions in registers; the output
+// at plane z is the reduction of the window around z. Planes are double-
+// buffered in LDS, so one barrier per plane suffices, and the next plane's
+// cells are loaded into registers before the current one is reduced.
+template <typename S, int R, int OP, int TY>
+__global__ void __launch_bounds__(64 * TY)
+    k_filter_box3d(const S *__restrict__ in, S *__restrict__ out, Geo g, int lz, int gx, int gy,
+                   int fuse)
+{
+    using C = typename Store<S>::C;
+    using U = typename Key<C>::U;
+    constexpr int TX = 64, LW = TX + 2 * R, LH = TY + 2 * R, NT = TX * TY;
+    constexpr int CELLS = LW * LH, PER = (CELLS + NT - 1) / NT;
+    __shared__ U lds[2][LH][LW];
+
+    const int bxi = blockIdx.x % gx, byi = (blockIdx.x / gx) % gy, bzi = blockIdx.x / (gx * gy);
+    const int x0 = bxi * TX, y0 = byi * TY, z0 = bzi * lz;
+    const int z1 = min(z0 + lz, g.nz);
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+    const int x = x0 + tx, y = y0 + ty;
+
+    // this lane's cells of a plane tile: padded coordinates clamped into the
+    // padded extent (cells past a ragged edge are never used)
+    int64_t coff[PER];
+    int slot[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + q * NT;
+        slot[q] = e < CELLS ? e : -1;
+        const int ex = e % LW, ey = e / LW;
+        const int px = min(x0 - R + ex, g.nx + g.r - 1), py = min(y0 - R + ey, g.ny + g.r - 1);
+        coff[q] = e < CELLS ? g.at(px, py, 0) - g.at(0, 0, 0) : 0;
+    }
+    const int64_t base = g.at(0, 0, 0);
+    auto plane_ptr = [&](int zz) { return in + base + (int64_t)zz * g.sz; };
+
+    U win[2 * R + 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) win[k] = 0;
+    U pre[PER];
+    const int zs = z0 - R, ze = z1 + R; // planes loaded: zs .. ze-1
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (slot[q] >= 0) pre[q] = mkey<C, OP>(Store<S>::ld(plane_ptr(zs) + coff[q]));
+    for (int zz = zs; zz < ze; ++zz) {
+        const int b = (zz - zs) & 1;
+        U *lb = &lds[b][0][0];
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (slot[q] >= 0) lb[slot[q]] = pre[q];
+        __syncthreads();
+        if (zz + 1 < ze) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (slot[q] >= 0) pre[q] = mkey<C, OP>(Store<S>::ld(plane_ptr(zz + 1) + coff[q]));
+        }
+        U sq = lds[b][ty][tx];
+#pragma unroll
+        for (int dy = 0; dy <= 2 * R; ++dy)
+#pragma unroll
+            for (int dx = 0; dx <= 2 * R; ++dx)
+                sq = pick<OP>(sq, lds[b][ty + dy][tx + dx]);
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k) win[k] = win[k + 1];
+        win[2 * R] = sq;
+        const int zo = zz - R;
+        if (zo >= z0 && x < g.nx && y < g.ny) {
+            U best = win[0];
+#pragma unroll
+            for (int k = 1; k <= 2 * R; ++k) best = pick<OP>(best, win[k]);
+            store_periodic(out, g, x, y, zo, unkey<C, OP>(best), fuse != 0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <typename S>
+int launch_filter_gather(const S *in, S *out, const Geo &g, const int *offs, int ntaps, int op,
+                         bool fuse, int bx, int by, hipStream_t s)
+{
+    dim3 block(bx, by), grid((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, g.nz);
+    switch (op) {
+    case FILTER_OP_MAX:
+        hipLaunchKernelGGL((k_filter_minmax<S, FILTER_OP_MAX>), grid, block, 0, s, in, out, g,
+                           offs, ntaps, fuse ? 1 : 0);
+        break;
+    case FILTER_OP_MIN:
+        hipLaunchKernelGGL((k_filter_minmax<S, FILTER_OP_MIN>), grid, block, 0, s, in, out, g,
+                           offs, ntaps, fuse ? 1 : 0);
+        break;
+    case FILTER_OP_MEDIAN:
+        if (ntaps > FILTER_MEDIAN_MAX)
+            return fail(STENCIL_EUNSUPPORTED, "median of %d > %d values", ntaps, FILTER_MEDIAN_MAX);
+        hipLaunchKernelGGL(k_filter_median<S>, grid, block, 0, s, in, out, g, offs, ntaps,
+                           fuse ? 1 : 0);
+        break;
+    default: return fail(STENCIL_EINVAL, "unknown filter op %d", op);
+    }
+    return check_launch("filter_gather");
+}
+
+template <typename S, int R, int OP>
+int launch_box3d_t(const S *in, S *out, const Geo &g, int ty, int lz, bool fuse, hipStream_t s)
+{
+    const int gx = (g.nx + 63) / 64, gy = (g.ny + ty - 1) / ty, gz = (g.nz + lz - 1) / lz;
+    const int64_t total = (int64_t)gx * gy * gz;
+    if (total > 0x7fffffff)
+        return fail(STENCIL_EUNSUPPORTED, "box filter: grid too large");
+    switch (ty) {
+    case 4:
+        hipLaunchKernelGGL((k_filter_box3d<S, R, OP, 4>), dim3((unsigned)total), dim3(64, 4), 0, s,
+                           in, out, g, lz, gx, gy, fuse ? 1 : 0);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_filter_box3d<S, R, OP, 8>), dim3((unsigned)total), dim3(64, 8), 0, s,
+                           in, out, g, lz, gx, gy, fuse ? 1 : 0);
+        break;
+    default: return fail(STENCIL_EUNSUPPORTED, "box filter: lanes along y %d not in {4, 8}", ty);
+    }
+    return check_launch("filter_box3d");
+}
+
+template <typename S, int OP>
+int launch_box3d_op(const S *in, S *out, const Geo &g, int R, int ty, int lz, bool fuse,
+                    hipStream_t s)
+{
+    switch (R) {
+    case 1: return launch_box3d_t<S, 1, OP>(in, out, g, ty, lz, fuse, s);
+    case 2: return launch_box3d_t<S, 2, OP>(in, out, g, ty, lz, fuse, s);
+    case 3: return launch_box3d_t<S, 3, OP>(in, out, g, ty, lz, fuse, s);
+    }
+    return fail(STENCIL_EUNSUPPORTED, "box filter: radius %d not in 1..3", R);
+}
+
+template <typename S>
+int launch_filter_box3d(const S *in, S *out, const Geo &g, int R, int op, bool fuse, int ty,
+                        int lz, hipStream_t s)
+{
+    if (g.ndim != 3 || R > g.r || lz < 1)
+        return fail(STENCIL_EINVAL, "box filter: needs a 3-D plan, radius <= padding, lz >= 1");
+    if (op == FILTER_OP_MAX)
+        return launch_box3d_op<S, FILTER_OP_MAX>(in, out, g, R, ty, lz, fuse, s);
+    if (op == FILTER_OP_MIN)
+        return launch_box3d_op<S, FILTER_OP_MIN>(in, out, g, R, ty, lz, fuse, s);
+    return fail(STENCIL_EUNSUPPORTED, "box filter: op %d is not max or min", op);
+}
+
+#define INST(S)                                                                              \
+    template int launch_filter_gather<S>(const S *, S *, const Geo &, const int *, int, int,   \
+                                         bool, int, int, hipStream_t);                        \
+    template int launch_filter_box3d<S>(const S *, S *, const Geo &, int, int, bool, int, int, \
+                                        hipStream_t);
+INST(double)
+INST(float)
+INST(bf16)
+#undef INST
+
+} // namespace stn

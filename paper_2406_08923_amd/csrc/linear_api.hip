@@ -2,6 +2,7 @@
 // autotuning, chained application with periodic halos, finite-difference
 // weights, copy.
 #include "linear_kernels.hpp"
+#include "filter_kernels.hpp"
 #include "plan.hpp"
 
 #include <algorithm>
@@ -111,6 +112,14 @@ template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out
     using C = typename Store<S>::C;
     const bool periodic = p->lin.bc == STENCIL_BC_PERIODIC;
     int rc;
+    if (p->lin.op != STENCIL_OP_XCORR) {
+        if (p->lin.variant == STENCIL_VARIANT_STAR3D)
+            return launch_filter_box3d<S>(in, out, p->lin.g, p->lin.reff, p->lin.op, periodic,
+                                          p->lin.ty, p->lin.lz, s);
+        return launch_filter_gather<S>(in, out, p->lin.g, static_cast<const int *>(p->lin.d_offs),
+                                       p->lin.ntaps, p->lin.op, periodic, p->lin.gbx, p->lin.gby,
+                                       s);
+    }
     switch (p->lin.variant) {
     case STENCIL_VARIANT_STAR3D: {
         int fl = p->lin.sflags | (periodic ? 0 : STAR_FLAG_NOFUSE);
@@ -139,7 +148,7 @@ int apply_t(stencil_plan_s *p, void *da, void *db, int iters, hipStream_t s, boo
     S *a = static_cast<S *>(da), *b = static_cast<S *>(db);
     int rc = STENCIL_OK;
     if (p->lin.bc == STENCIL_BC_PERIODIC && p->lin.variant == STENCIL_VARIANT_LINE1D &&
-        p->lin.t1d > 1) {
+        p->lin.t1d > 1 && p->lin.op == STENCIL_OP_XCORR) {
         // temporally blocked: nl launches of up to T iterations each, with nl
         // of the same parity as iters so the result lands where the
         // one-iteration-per-launch contract puts it
@@ -160,7 +169,7 @@ int apply_t(stencil_plan_s *p, void *da, void *db, int iters, hipStream_t s, boo
         return rc;
     }
     if (p->lin.bc == STENCIL_BC_PERIODIC && p->lin.variant == STENCIL_VARIANT_STAR3D &&
-        p->lin.tstar == 2) {
+        p->lin.tstar == 2 && p->lin.op == STENCIL_OP_XCORR) {
         // nl launches of two or one iterations, nl of the parity of iters;
         // the two-iteration launches come first (they read the input with
         // periodic wrap, not its halo, and write their output's images)
@@ -206,10 +215,10 @@ int apply_any(stencil_plan_s *p, void *a, void *b, int iters, hipStream_t s,
 std::string tune_key(const stencil_plan_s *p)
 {
     char buf[256];
-    snprintf(buf, sizeof(buf), "lin|dt%d|nd%d|%dx%dx%d|r%d|ox%d|sy%lld|reff%d|star%d|bc%d|nt%d",
+    snprintf(buf, sizeof(buf), "lin|dt%d|nd%d|%dx%dx%d|r%d|ox%d|sy%lld|reff%d|star%d|bc%d|nt%d|op%d|box%d",
              p->lin.dtype, p->lin.g.ndim, p->lin.g.nx, p->lin.g.ny, p->lin.g.nz, p->lin.g.r,
              p->lin.g.ox, (long long)p->lin.g.sy, p->lin.reff, p->lin.is_star ? 1 : 0, p->lin.bc,
-             p->lin.ntaps);
+             p->lin.ntaps, p->lin.op, p->lin.is_box ? 1 : 0);
     return buf;
 }
 
@@ -241,6 +250,16 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
 {
     std::vector<TuneChoice> c;
     const Geo &g = p->lin.g;
+    if (p->lin.op != STENCIL_OP_XCORR) {
+        if (p->lin.is_box && p->lin.op != STENCIL_OP_MEDIAN)
+            for (int ty : {4, 8})
+                for (int lz : {16, 32, 64})
+                    c.push_back({STENCIL_VARIANT_STAR3D, ty, 1, lz, 0});
+        c.push_back({STENCIL_VARIANT_GENERIC, 64, 4, 0, 0});
+        c.push_back({STENCIL_VARIANT_GENERIC, 64, 8, 0, 0});
+        c.push_back({STENCIL_VARIANT_GENERIC, 128, 2, 0, 0});
+        return c;
+    }
     if (p->lin.is_star) {
         // (x waves, y lanes, rows per lane): tiles 64*xw x ty*ny
         const int shapes[][3] = {{1, 8, 2}, {1, 4, 4}, {1, 8, 4}, {1, 16, 2}, {2, 4, 2}, {2, 4, 4},
@@ -314,6 +333,12 @@ TuneChoice default_star1(const stencil_plan_s *p)
 
 TuneChoice default_choice(const stencil_plan_s *p)
 {
+    if (p->lin.op != STENCIL_OP_XCORR) {
+        if (p->lin.is_box && p->lin.op != STENCIL_OP_MEDIAN)
+            return {STENCIL_VARIANT_STAR3D, 4, 1, 32, 0};
+        return {STENCIL_VARIANT_GENERIC, p->lin.g.ndim == 1 ? 256 : 64,
+                p->lin.g.ndim == 1 ? 1 : 4, 0, 0};
+    }
     // periodic stars: two iterations per launch, the lane grids that measured
     // fastest at 512^3 (64 x 24 for FP64, 64 x 32 for the narrower types)
     if (p->lin.is_star && p->lin.bc == STENCIL_BC_PERIODIC)
@@ -441,6 +466,8 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
         return fail(STENCIL_EINVAL, "unknown dtype %d", d->dtype);
     if (d->bc != STENCIL_BC_PERIODIC && d->bc != STENCIL_BC_USER_HALO)
         return fail(STENCIL_EINVAL, "unknown boundary mode %d", d->bc);
+    if (d->op < STENCIL_OP_XCORR || d->op > STENCIL_OP_MEDIAN)
+        return fail(STENCIL_EINVAL, "unknown stencil op %d", d->op);
     if (!d->coeffs)
         return fail(STENCIL_EINVAL, "coeffs is NULL");
     int rc = check_dims(d->ndim, d->dims, d->radius, d->bc);
@@ -508,7 +535,9 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
             }
     L.reff = reff;
     L.ntaps = (int)taps.size();
-    L.is_star = star && reff >= 1 && reff <= STAR_MAX_R;
+    L.op = d->op;
+    L.is_star = star && reff >= 1 && reff <= STAR_MAX_R && L.op == STENCIL_OP_XCORR;
+    L.is_box = nd == 3 && r >= 1 && r <= 3 && L.ntaps == K * K * K && L.op != STENCIL_OP_XCORR;
     if (L.is_star) {
         std::memset(&L.star, 0, sizeof(L.star));
         for (int sz = -reff; sz <= reff; ++sz)
@@ -557,7 +586,19 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
     }
 
     // variant choice
-    if (d->variant == STENCIL_VARIANT_STAR3D && !L.is_star) {
+    if (L.op != STENCIL_OP_XCORR) {
+        if (L.ntaps < 1 || (L.op == STENCIL_OP_MEDIAN && L.ntaps > STENCIL_MEDIAN_MAX)) {
+            stencil_plan_destroy(p);
+            return fail(STENCIL_EUNSUPPORTED, "filter window of %d cells (median: 1..%d)", L.ntaps,
+                        STENCIL_MEDIAN_MAX);
+        }
+        if (d->variant == STENCIL_VARIANT_LINE1D ||
+            (d->variant == STENCIL_VARIANT_STAR3D && (!L.is_box || L.op == STENCIL_OP_MEDIAN))) {
+            stencil_plan_destroy(p);
+            return fail(STENCIL_EUNSUPPORTED, "filters run GENERIC, or STAR3D for 3-D box max/min "
+                                              "of radius 1..3");
+        }
+    } else if (d->variant == STENCIL_VARIANT_STAR3D && !L.is_star) {
         stencil_plan_destroy(p);
         return fail(STENCIL_EUNSUPPORTED, "STAR3D needs a 3-D axis-aligned stencil of radius 1..4");
     }

@@ -16,6 +16,8 @@ struct LinearPlan {
     std::vector<double> dense; // (2r+1)^ndim coefficients, x fastest
     int ntaps = 0, reff = 0;   // pruned taps and their radius
     bool is_star = false;
+    int op = STENCIL_OP_XCORR; // window filters: STENCIL_OP_MAX / MIN / MEDIAN
+    bool is_box = false;       // 3-D window covering the full (2r+1)^3 box
     StarCoefAny star{};
     void *d_offs = nullptr;  // int32 tap offsets in the padded array
     void *d_taps = nullptr;  // tap coefficients, arithmetic type

@@ -75,6 +75,7 @@ def _plan_rc(**kw):
     d.variant = kw.get("variant", S.VARIANT_AUTO)
     d.row_pitch = kw.get("row_pitch", 0)
     d.x_offset = kw.get("x_offset", 0)
+    d.op = kw.get("op", 0)
     h = ctypes.c_void_p()
     return S.lib().stencil_plan(ctypes.byref(d), ctypes.byref(h))
 
@@ -85,6 +86,7 @@ def _plan_rc(**kw):
                                 dict(dims=(0, 8, 8)), dict(variant=9),
                                 dict(ndim=1, dims=(4096, 1, 1), radius=1025, coeffs=np.ones(2051)),
                                 dict(ndim=2, dims=(64, 64, 1), radius=9, coeffs=np.ones(361)),
+                                dict(op=4), dict(op=-1),
                                 # layout: x_offset below the radius, pitch too short
                                 # for x_offset + nx + r, pitch on a 1-D field, negatives
                                 dict(radius=2, x_offset=1, coeffs=np.ones(125)),

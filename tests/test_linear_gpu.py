@@ -591,3 +591,148 @@ def test_line1d_radius_equal_to_length():
 def test_line1d_temporal_needs_periodic():
     with pytest.raises(S.StencilError):
         S.LinearPlan((100,), 1, W.smoother3(), bc=S.USER_HALO, variant=S.LINE1D, tile=(4, 8))
+
+
+# ---------------------------------------------------------------------------
+# window filters (max filter of Sec. 2.3, min, median of Sec. 1): bit-exact
+# ---------------------------------------------------------------------------
+
+def star_mask(ndim, r):
+    m = np.zeros((2 * r + 1,) * ndim)
+    for a in range(ndim):
+        for k in range(2 * r + 1):
+            idx = [r] * ndim
+            idx[a] = k
+            m[tuple(idx)] = 1.0
+    return m
+
+
+def holey_mask(ndim, r, seed, max_cells=None):
+    rng = np.random.default_rng(seed)
+    m = (rng.uniform(size=(2 * r + 1,) * ndim) < 0.45).astype(float)
+    m[(r,) * ndim] = 1.0
+    if max_cells is not None:
+        on = np.flatnonzero(m.reshape(-1))
+        for k in on[max_cells:]:
+            m.reshape(-1)[k] = 0.0
+        m[(r,) * ndim] = 1.0
+    return m
+
+
+def run_filter(dims, r, mask, op, dtype, variant=S.VARIANT_AUTO, tile=None, seed=4, inner=None,
+               iters=1):
+    """Periodic filter through the library (input halo garbage: the library
+    fills it) and the oracle's iterate; returns interiors, plan, padded result."""
+    if inner is None:
+        inner = to_storage_values(inputs.uniform_field(dims, seed), dtype)
+    plan = S.LinearPlan(dims, r, mask, dtype=dtype, variant=variant, tile=tile, op=op)
+    a_h = np.full(O.padded_shape(dims, r), 7.0)
+    O.interior(a_h, r)[...] = inner
+    a = dev(a_h, dtype)
+    b = plan.empty(fill=-3.0)
+    res = host(plan.apply(a, b, iters))
+    code = {S.OP_MAX: O.FILTER_MAX, S.OP_MIN: O.FILTER_MIN, S.OP_MEDIAN: O.FILTER_MEDIAN}[op]
+    ref = O.pad_periodic(inner, r)
+    for _ in range(iters):
+        ref = O.fill_periodic(O.filter(ref, r, mask, code), r)
+    return O.interior(res, r), O.interior(ref, r), plan, res
+
+
+def same_bits(a, b):
+    return np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(
+        np.nan_to_num(a, nan=0.0), np.nan_to_num(b, nan=0.0)) and np.array_equal(
+        np.signbit(a[~np.isnan(a)]), np.signbit(b[~np.isnan(b)]))
+
+
+FILTER_CASES = [((1000,), 3, "box"), ((333,), 13, "box"), ((45, 37), 2, "box"), ((45, 37), 3, "star"),
+                ((29, 17, 23), 1, "box"), ((29, 17, 23), 2, "star"), ((29, 17, 23), 3, "holey"),
+                ((70, 33, 21), 2, "box")]
+
+
+@pytest.mark.parametrize("case", range(len(FILTER_CASES)))
+@pytest.mark.parametrize("op", [S.OP_MAX, S.OP_MIN, S.OP_MEDIAN])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_filters_bit_exact(case, op, dtype):
+    dims, r, shape = FILTER_CASES[case]
+    nd = len(dims)
+    mask = {"box": np.ones((2 * r + 1,) * nd), "star": star_mask(nd, r),
+            "holey": holey_mask(nd, r, 3, max_cells=S.MEDIAN_MAX)}[shape]
+    if op == S.OP_MEDIAN and int(np.count_nonzero(mask)) > S.MEDIAN_MAX:
+        with pytest.raises(S.StencilError):
+            S.LinearPlan(dims, r, mask, dtype=dtype, op=op)
+        return
+    got, ref, plan, res = run_filter(dims, r, mask, op, dtype)
+    assert same_bits(got, ref), (dims, r, shape, op, plan.variant, plan.tile)
+    assert np.array_equal(res, O.fill_periodic(res.copy(), r))
+
+
+@pytest.mark.parametrize("op", [S.OP_MAX, S.OP_MIN])
+@pytest.mark.parametrize("r", [1, 2, 3])
+@pytest.mark.parametrize("tile", [(4, 0, 16, 0), (8, 0, 32, 0), (4, 0, 5, 0)])
+def test_box_filter_z_march_bit_exact(op, r, tile):
+    dims = (70, 33, 21)
+    mask = np.ones((2 * r + 1,) * 3)
+    got, ref, plan, _ = run_filter(dims, r, mask, op, S.F64, variant=S.STAR3D, tile=tile)
+    assert plan.variant == S.STAR3D
+    assert same_bits(got, ref)
+    got2, _, _, _ = run_filter(dims, r, mask, op, S.F64, variant=S.GENERIC)
+    assert same_bits(got, got2)
+
+
+@pytest.mark.parametrize("op", [S.OP_MAX, S.OP_MIN, S.OP_MEDIAN])
+@pytest.mark.parametrize("variant", [S.STAR3D, S.GENERIC])
+def test_filters_signed_zeros_and_nan(op, variant):
+    if op == S.OP_MEDIAN and variant == S.STAR3D:
+        return
+    dims, r = (40, 20, 12), 1
+    rng = np.random.default_rng(5)
+    inner = rng.choice(np.array([-0.0, 0.0, -1.0, 1.0]), size=dims[::-1])
+    inner[5, 7, 9] = np.nan
+    got, ref, _, _ = run_filter(dims, r, np.ones((3, 3, 3)), op, S.F64, variant=variant,
+                                inner=inner)
+    assert same_bits(got, ref)
+    assert int(np.isnan(got).sum()) == 27
+
+
+def test_filters_chained_and_user_halo():
+    dims, r = (45, 26, 17), 1
+    mask = np.ones((3, 3, 3))
+    got, ref, _, _ = run_filter(dims, r, mask, S.OP_MAX, S.F32, iters=3)
+    assert same_bits(got, ref)
+    rng = np.random.default_rng(12)
+    a_host = rng.uniform(-1, 1, O.padded_shape(dims, r))  # non-periodic halo
+    for variant in (S.STAR3D, S.GENERIC):
+        plan = S.LinearPlan(dims, r, mask, bc=S.USER_HALO, variant=variant, op=S.OP_MIN)
+        b = plan.empty(fill=123.0)
+        plan.apply(dev(a_host, S.F64), b, 1)
+        out = host(b)
+        want = O.filter(a_host, r, mask, O.FILTER_MIN)
+        assert np.array_equal(O.interior(out, r), O.interior(want, r))
+
+
+def test_filter_variant_validation():
+    with pytest.raises(S.StencilError):  # median has no z-march form
+        S.LinearPlan((32, 32, 32), 1, np.ones((3, 3, 3)), op=S.OP_MEDIAN, variant=S.STAR3D)
+    with pytest.raises(S.StencilError):  # star window is not a box
+        S.LinearPlan((32, 32, 32), 1, star_mask(3, 1), op=S.OP_MAX, variant=S.STAR3D)
+    with pytest.raises(S.StencilError):
+        S.LinearPlan((1000,), 1, np.ones(3), op=S.OP_MAX, variant=S.LINE1D)
+
+
+@pytest.mark.parametrize("op", [S.OP_MAX, S.OP_MEDIAN])
+def test_filter_512_cubed_sampled_points(op):
+    dims, r = (512, 512, 512), 1
+    mask = np.ones((3, 3, 3))
+    inner = inputs.uniform_field(dims, 6)
+    plan = S.LinearPlan(dims, r, mask, op=op)
+    a_host = np.zeros(O.padded_shape(dims, r))
+    O.interior(a_host, r)[...] = inner
+    del inner
+    b = plan.empty(0.0)
+    plan.apply(dev(a_host, S.F64), b, 1)
+    got = host(b)
+    O.fill_periodic(a_host, r)
+    pts = sample_points(dims, 3000, 8)
+    ref = O.filter_at(a_host, r, mask, {S.OP_MAX: O.FILTER_MAX, S.OP_MEDIAN: O.FILTER_MEDIAN}[op],
+                      pts)
+    assert np.array_equal(got[pts[:, 2] + r, pts[:, 1] + r, pts[:, 0] + r], ref)
