@@ -255,9 +255,9 @@ typedef struct stencil_rk_desc {
     double adv[3];  /* ADVDIFF velocity */
     int block[3];   /* launch override (0 = plan's choice). CACHED: x lanes, y
                        lanes (x*y a multiple of 64, at most 256), block[2] 0
-                       or 1 (one z plane per workgroup). LDS: the brick of
-                       output points per workgroup, one of 16x8x4 16x8x8
-                       32x4x4 8x8x8 */
+                       or 1 (one z plane per workgroup). LDS, MHD8: the brick
+                       of output points per workgroup, one of 16x8x4 16x8x8
+                       32x4x4 8x8x8. LDS, ADVDIFF: {0, 0, z planes} */
     int variant;    /* STENCIL_RK_VARIANT_*: how the derivative bank reads its
                        taps */
     int row_pitch;  /* field layout, as in stencil_desc (both 0 = compact):  */
@@ -267,10 +267,13 @@ typedef struct stencil_rk_desc {
                        holds stencil_plan_padded_elems(plan) elements */
 } stencil_rk_desc;
 
-/* Derivative-bank strategies (Sec. 4.1/4.4): AUTO = LDS for MHD8, CACHED for
- * ADVDIFF. CACHED: one lane per point, every tap a load through L1/L2. LDS
- * (MHD8 only): a workgroup owns a brick of points and streams the fields one
- * at a time through an LDS tile of the brick plus its halo. */
+/* Derivative-bank strategies (Sec. 4.1/4.4): AUTO = LDS for MHD8 and 3-D
+ * ADVDIFF, CACHED for 2-D ADVDIFF. CACHED: one lane per point, every tap a
+ * load through L1/L2. LDS, MHD8: a workgroup owns a brick of points and
+ * streams the fields one at a time through an LDS tile of the brick plus its
+ * halo. LDS, 3-D ADVDIFF: the right-hand side is a radius-3 star, computed as
+ * a z march over 64 x 16 tiles (x-y plane in LDS, z taps in registers) with
+ * the RK update as its epilogue; block[2] = z planes per tile (0 = 32). */
 #define STENCIL_RK_VARIANT_AUTO 0
 #define STENCIL_RK_VARIANT_CACHED 1
 #define STENCIL_RK_VARIANT_LDS 2

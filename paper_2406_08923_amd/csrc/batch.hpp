@@ -19,17 +19,23 @@ struct BatchJob {
     int policy;     // RkPolicy
     int steps;      // RK steps to take in this tick
     int parity;     // index of the buffer holding the state when the tick starts
-    int tiles_x, tiles_y;
-    int tile_begin; // first work item of the job
+    int tiles_x, tiles_y; // per-point: 64 x 4 tiles; z march: 64 x 16 tiles
+    int lz;               // z march: planes per tile
+    int tile_begin; // first work item of the job (within its kind)
 };
 
 // Work items are tiles of BT_X x BT_Y points of one plane, one lane per point.
 constexpr int BT_X = 64, BT_Y = 4;
 
+// Table order: the n2d per-point jobs first (2-D jobs and small 3-D jobs:
+// 64 x 4 tiles of one plane, total_tiles items), then the z-march jobs (3-D
+// jobs of at least ZM_MIN_POINTS points: tiles of 64 x 16 points x lz
+// planes, total3 items); each job's tile_begin counts within its own kind.
 struct BatchTableHeader {
     int njobs;
     int total_tiles;
-    int pad[2];
+    int n2d;
+    int total3;
 };
 
 // Table = header followed by njobs BatchJob records (device memory).
@@ -47,7 +53,8 @@ struct RkCoeffs {
 RkCoeffs rk3_coeffs();
 
 // One substep (sub = 3 * step + stage within the tick) of every job whose
-// step < steps, by a persistent grid of `blocks` workgroups walking the items.
+// step < steps, by persistent grids of `blocks` workgroups walking the items
+// (one launch for the 2-D jobs, one for the 3-D jobs).
 int launch_batch_substep(const void *d_table, int sub, const RkCoeffs &rk, int blocks,
                          hipStream_t s);
 

@@ -3,6 +3,7 @@
 // job (2-D or 3-D, FP64 or FP32 storage with FP64 master). The per-point
 // arithmetic is advdiff_point, the same code as the solo kernel, so a job's
 // result does not depend on what else is in the batch.
+#include "advdiff_zm.hpp"
 #include "batch.hpp"
 #include "linear_kernels.hpp"
 
@@ -13,7 +14,7 @@ __global__ void __launch_bounds__(BT_X * BT_Y) k_batch_advdiff(const void *__res
 {
     const BatchTableHeader *hdr = static_cast<const BatchTableHeader *>(table);
     const BatchJob *jobs = reinterpret_cast<const BatchJob *>(hdr + 1);
-    const int njobs = hdr->njobs, total = hdr->total_tiles;
+    const int njobs = hdr->n2d, total = hdr->total_tiles; // the per-point jobs
     const int stage = sub % 3, step = sub / 3;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         // job owning the item: last job whose first item is <= item
@@ -67,11 +68,79 @@ __global__ void __launch_bounds__(BT_X * BT_Y) k_batch_advdiff(const void *__res
     }
 }
 
+// The z-march jobs (3-D, at least ZM_MIN_POINTS points): items are z-march
+// tiles (advdiff_zm.hpp), the same routine and arithmetic as the solo substep
+// of such a job.
+__global__ void __launch_bounds__(ZM_NT) k_batch_advdiff3(const void *__restrict__ table, int sub,
+                                                          RkCoeffs rk)
+{
+    __shared__ ZmLds<double> lds;
+    const BatchTableHeader *hdr = static_cast<const BatchTableHeader *>(table);
+    const BatchJob *jobs = reinterpret_cast<const BatchJob *>(hdr + 1);
+    const int first = hdr->n2d, last = hdr->njobs - 1, total = hdr->total3;
+    const int stage = sub % 3, step = sub / 3;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        int lo = first, hi = last;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_begin <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchJob &J = jobs[lo];
+        if (step >= J.steps)
+            continue; // the whole workgroup skips: no barrier is left unmatched
+        const int t = item - J.tile_begin;
+        const int bx = t % J.tiles_x, rest = t / J.tiles_x;
+        const int by = rest % J.tiles_y, bz = rest / J.tiles_y;
+        const int x0 = bx * ZM_TX, y0 = by * ZM_ROWS, z0 = bz * J.lz;
+        const int z1 = min(z0 + J.lz, J.g.nz);
+        const int pin = (J.parity + sub) & 1;
+        PointIO io;
+        io.fout = J.f[pin ^ 1];
+        const bool master = J.policy == POL_F32_MASTER64 || J.policy == POL_BF16_MASTER64;
+        io.wrd = master ? (stage == 1 ? J.w : J.w2) : J.w;
+        io.wwr = master ? (stage == 0 ? J.w : J.w2) : J.w;
+        io.w1 = J.w;
+        io.master = J.f64;
+        io.alpha = rk.alpha[stage];
+        io.beta = rk.beta[stage];
+        io.dt = J.dt;
+        for (int i = 0; i < 3; ++i) io.beta_all[i] = rk.beta[i];
+        io.stage = stage;
+        io.fuse = 1;
+        const void *fin = J.f[pin];
+        switch (J.policy) {
+        case POL_F64:
+            advdiff3_zmarch<double, double, double, false>(
+                fin, io, J.g, advdiff_star<double>(J.fd, J.inv_ds, J.adv, J.nu), x0, y0, z0, z1,
+                lds);
+            break;
+        case POL_F32_MASTER64:
+            advdiff3_zmarch<float, float, float, true>(
+                fin, io, J.g, advdiff_star<float>(J.fd, J.inv_ds, J.adv, J.nu), x0, y0, z0, z1,
+                *reinterpret_cast<ZmLds<float> *>(&lds));
+            break;
+        case POL_F32_ONLY:
+            advdiff3_zmarch<float, float, float, false>(
+                fin, io, J.g, advdiff_star<float>(J.fd, J.inv_ds, J.adv, J.nu), x0, y0, z0, z1,
+                *reinterpret_cast<ZmLds<float> *>(&lds));
+            break;
+        default:
+            break; // other policies are rejected at submission
+        }
+    }
+}
+
 int launch_batch_substep(const void *d_table, int sub, const RkCoeffs &rk, int blocks,
                          hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_advdiff, dim3(blocks), dim3(BT_X, BT_Y), 0, s, d_table, sub, rk);
-    return check_launch("batch_advdiff");
+    int rc = check_launch("batch_advdiff");
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(k_batch_advdiff3, dim3(blocks), dim3(ZM_TX, ZM_TY), 0, s, d_table, sub,
+                       rk);
+    return check_launch("batch_advdiff3");
 }
 
 template <typename S>

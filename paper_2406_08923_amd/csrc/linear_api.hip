@@ -303,7 +303,9 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
     if (g.ndim == 1) {
         for (int e : {1, 2, 4, 8})
             for (int T : {1, 4, 8, 16})
-                if (T == 1 || p->lin.bc == STENCIL_BC_PERIODIC)
+                // fused iterations only where the block's apron (r*T cells a
+                // side) stays within the block it serves
+                if (T == 1 || (p->lin.bc == STENCIL_BC_PERIODIC && 2 * g.r * T <= 256 * e))
                     c.push_back({STENCIL_VARIANT_LINE1D, e, T, 0, 0});
         // register-blocked lines for the large-radius regime
         for (int e : {4, 8, 16})

@@ -1,5 +1,6 @@
 // rk_api.hip -- C ABI of the fused nonlinear substep (derivative bank + phi +
 // low-storage RK3) and of the FP64 diagnostics.
+#include "advdiff_zm.hpp"
 #include "batch.hpp"
 #include "plan.hpp"
 #include "reduce_kernels.hpp"
@@ -80,6 +81,8 @@ int launch_substep(const stencil_plan_s *p, const stencil_fields *f, int sub, do
     a.phases = -1;
     if (P.model == STENCIL_MODEL_MHD8 && P.variant == STENCIL_RK_VARIANT_LDS)
         return launch_rk_mhd8_lds(P.policy, a, P.bx, P.by, P.bz, s);
+    if (P.model == STENCIL_MODEL_ADVDIFF && P.variant == STENCIL_RK_VARIANT_LDS)
+        return launch_rk_advdiff3_zm(P.policy, a, P.bz, s);
     if (P.model == STENCIL_MODEL_MHD8)
         return launch_rk_mhd8(P.policy, a, P.bx, P.by, s);
     return launch_rk_advdiff(P.policy, a, P.bx, P.by, s);
@@ -153,13 +156,30 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
                     d->row_pitch, (long long)min_pitch);
     if (d->variant < STENCIL_RK_VARIANT_AUTO || d->variant > STENCIL_RK_VARIANT_LDS)
         return fail(STENCIL_EINVAL, "unknown derivative-bank variant %d", d->variant);
-    if (d->variant == STENCIL_RK_VARIANT_LDS && d->model != STENCIL_MODEL_MHD8)
-        return fail(STENCIL_EUNSUPPORTED, "the LDS bank is built for MHD8 only");
+    if (d->variant == STENCIL_RK_VARIANT_LDS && d->model == STENCIL_MODEL_ADVDIFF &&
+        d->ndim != 3)
+        return fail(STENCIL_EUNSUPPORTED, "the staged advection kernel is 3-D");
+    // AUTO: LDS bricks for MHD8, the z march for 3-D advection grids of at
+    // least ZM_MIN_POINTS points (the rule the batched job kernel applies),
+    // the cached per-point kernel otherwise
+    long long npts = 1;
+    for (int a = 0; a < d->ndim && a < 3; ++a) npts *= d->dims[a];
     const int variant = d->variant != STENCIL_RK_VARIANT_AUTO ? d->variant
-                        : d->model == STENCIL_MODEL_MHD8      ? STENCIL_RK_VARIANT_LDS
-                                                              : STENCIL_RK_VARIANT_CACHED;
+                        : (d->model == STENCIL_MODEL_MHD8 ||
+                           (d->ndim == 3 && npts >= ZM_MIN_POINTS))
+                            ? STENCIL_RK_VARIANT_LDS
+                            : STENCIL_RK_VARIANT_CACHED;
     int bx, by, bz;
-    if (variant == STENCIL_RK_VARIANT_LDS) {
+    if (variant == STENCIL_RK_VARIANT_LDS && d->model == STENCIL_MODEL_ADVDIFF) {
+        // z march: fixed 64 x 16 tiles; block[2] = z planes per tile
+        if (d->block[0] || d->block[1])
+            return fail(STENCIL_EINVAL, "the advection z march takes only block[2] (z planes)");
+        bx = ZM_TX;
+        by = ZM_ROWS;
+        bz = d->block[2];
+        if (bz < 0 || bz > 4096)
+            return fail(STENCIL_EINVAL, "z planes per tile must be 1..4096 (0 = by grid size)");
+    } else if (variant == STENCIL_RK_VARIANT_LDS) {
         // bricks that measured fastest at 256^3: 16x8x8 (FP64 state, 1024
         // lanes), 32x4x4 (FP32/BF16 storage, 512 lanes)
         const bool f64 = d->precision == STENCIL_PREC_F64;
@@ -215,6 +235,8 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     P.bx = bx;
     P.by = by;
     P.bz = bz;
+    if (P.model == STENCIL_MODEL_ADVDIFF && variant == STENCIL_RK_VARIANT_LDS && !P.bz)
+        P.bz = advdiff_zmarch_lz(P.g);
     P.store_size = dtype_size(store_dtype(P.policy));
     P.reg_size = P.policy == POL_F64 ? 8 : 4;
     *out = p;

@@ -10,6 +10,7 @@
 // antisymmetry of the first-derivative weights to fold the 36 taps into 9
 // weighted four-point differences. The periodic images of each output are
 // written by the kernel itself, so no halo pass follows.
+#include "advdiff_zm.hpp"
 #include "rk_point.hpp"
 
 namespace stn {
@@ -204,6 +205,20 @@ __global__ void __launch_bounds__(256) k_rk_advdiff(RkArgs a)
                                          x, y, z);
 }
 
+// 3-D advection-diffusion as a z march over 64 x 16 tiles and lz planes: the
+// right-hand side is a radius-3 star, computed like the linear star, with the
+// RK update as the epilogue (advdiff_zm.hpp; the batched job kernel uses the
+// same routine).
+template <typename S, typename W, typename C, bool MASTER>
+__global__ void __launch_bounds__(ZM_NT) k_rk_advdiff3_zm(RkArgs a, int lz)
+{
+    __shared__ ZmLds<C> lds;
+    const StarCoef<C, 3> cf = advdiff_star<C>(a.fd, a.inv_ds, a.adv, a.nu);
+    const int x0 = blockIdx.x * ZM_TX, y0 = blockIdx.y * ZM_ROWS, z0 = blockIdx.z * lz;
+    advdiff3_zmarch<S, W, C, MASTER>(a.fin[0], point_io(a, 0), a.g, cf, x0, y0, z0,
+                                     min(z0 + lz, a.g.nz), lds);
+}
+
 namespace {
 template <typename K> int launch_grid(K kern, const RkArgs &a, int bx, int by, hipStream_t s,
                                       const char *what)
@@ -223,6 +238,33 @@ int launch_rk_mhd8(int policy, const RkArgs &a, int bx, int by, hipStream_t s)
     case POL_BF16_MASTER64: return launch_grid(k_rk_mhd8<bf16, float, float, true>, a, bx, by, s, "rk_mhd8");
     case POL_F32_ONLY: return launch_grid(k_rk_mhd8<float, float, float, false>, a, bx, by, s, "rk_mhd8");
     case POL_BF16_ONLY: return launch_grid(k_rk_mhd8<bf16, float, float, false>, a, bx, by, s, "rk_mhd8");
+    }
+    return fail(STENCIL_EINVAL, "unknown precision policy %d", policy);
+}
+
+namespace {
+template <typename S, typename W, typename C, bool M>
+int launch_zm(const RkArgs &a, int lz, hipStream_t s)
+{
+    const dim3 grid((a.g.nx + ZM_TX - 1) / ZM_TX, (a.g.ny + ZM_ROWS - 1) / ZM_ROWS,
+                    (a.g.nz + lz - 1) / lz);
+    hipLaunchKernelGGL((k_rk_advdiff3_zm<S, W, C, M>), grid, dim3(ZM_TX, ZM_TY), 0, s, a, lz);
+    return check_launch("rk_advdiff3_zm");
+}
+} // namespace
+
+int launch_rk_advdiff3_zm(int policy, const RkArgs &a, int lz, hipStream_t s)
+{
+    if (a.g.ndim != 3 || lz < 1)
+        return fail(STENCIL_EINVAL, "advdiff z march: needs a 3-D plan and lz >= 1");
+    if (uint64_t(padded_elems(a.g)) * 8 >= (uint64_t(1) << 32))
+        return fail(STENCIL_EUNSUPPORTED, "advdiff: arrays of 4 GiB or more are not supported");
+    switch (policy) {
+    case POL_F64: return launch_zm<double, double, double, false>(a, lz, s);
+    case POL_F32_MASTER64: return launch_zm<float, float, float, true>(a, lz, s);
+    case POL_BF16_MASTER64: return launch_zm<bf16, float, float, true>(a, lz, s);
+    case POL_F32_ONLY: return launch_zm<float, float, float, false>(a, lz, s);
+    case POL_BF16_ONLY: return launch_zm<bf16, float, float, false>(a, lz, s);
     }
     return fail(STENCIL_EINVAL, "unknown precision policy %d", policy);
 }

@@ -54,5 +54,27 @@ int launch_rk_mhd8(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
 #define RK_BRICK_SHAPES(X) X(16, 8, 4) X(16, 8, 8) X(32, 4, 4) X(8, 8, 8)
 int launch_rk_mhd8_lds(int policy, const RkArgs &a, int bx, int by, int bz, hipStream_t s);
 int launch_rk_advdiff(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
+// 3-D advection-diffusion substep as a z march (64 x 16 tiles, lz planes)
+int launch_rk_advdiff3_zm(int policy, const RkArgs &a, int lz, hipStream_t s);
+// z planes per tile of the z march (solo and batched)
+constexpr int ZM_LZ = 32;
+// The z march pays off once a 3-D grid fills the GPU with its 64 x 16 x ZM_LZ
+// tiles; smaller grids keep the per-point kernel (more, smaller workgroups).
+// The solo plan and the batched job table apply the same rule, so a job's
+// arithmetic does not depend on how it is run.
+constexpr long long ZM_MIN_POINTS = 1ll << 20;
+inline bool advdiff_uses_zmarch(const Geo &g)
+{
+    return g.ndim == 3 && (long long)g.nx * g.ny * g.nz >= ZM_MIN_POINTS;
+}
+// z planes per z-march tile for a grid: deep tiles (ZM_LZ) on large grids,
+// shallower ones (down to 8) where that is needed for about 1024 tiles, so a
+// mid-size job still spreads over every CU. The depth changes no result.
+inline int advdiff_zmarch_lz(const Geo &g)
+{
+    const long long txy = (long long)((g.nx + 63) / 64) * ((g.ny + 15) / 16);
+    const long long lz = (long long)g.nz * txy / 1024;
+    return (int)(lz < 8 ? 8 : lz > ZM_LZ ? ZM_LZ : lz);
+}
 
 } // namespace stn

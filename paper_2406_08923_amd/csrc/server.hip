@@ -1,16 +1,21 @@
 // server.hip -- continuous-batching server for stencil-integration jobs.
 //
-// One host thread per server owns a HIP stream (default priority) and loops:
+// One host thread per server owns two HIP streams (default priority: one for
+// compute, one for copies) and loops:
 //   1. admit queued jobs, first fit in arrival order, while their resident
-//      state fits the free HBM budget and a slot is free; allocate their
-//      fields and upload the initial state;
-//   2. run one tick: upload the job table, then tick_steps x 3 substeps of the
-//      persistent batched kernel (replayed from a captured hipGraph whose
-//      launches do not depend on the job set), and wait for it;
-//   3. retire jobs whose steps are done (result copied to the host, memory
-//      freed) and cancelled jobs.
-// Jobs arriving while a tick runs wait at most one tick for admission. A device
-// error fails the running jobs and latches the server.
+//      state fits the free HBM budget and a slot is free;
+//   2. enqueue one tick on the compute stream: upload the job table, then
+//      tick_steps x 3 substeps of the persistent batched kernels (replayed
+//      from a captured hipGraph whose launches do not depend on the job set);
+//   3. while the tick runs, on the copy stream: download and free the jobs
+//      that finished in the previous tick, allocate and upload the jobs just
+//      admitted (they join the next tick);
+//   4. wait for both streams; retire finished and cancelled jobs.
+// Host-device transfers thus overlap the batched compute. Jobs arriving while
+// a tick runs wait at most one tick for admission plus one for their upload;
+// a finished job's result lands one tick later. A device error fails the
+// running jobs and latches the server.
+#include "advdiff_zm.hpp"
 #include "batch.hpp"
 
 #include <algorithm>
@@ -87,7 +92,8 @@ int check_job(const stencil_job *j)
 struct stencil_server_s {
     stencil_server_desc d{};
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // compute
+    hipStream_t cstream = nullptr; // copies, allocation and frees
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -114,11 +120,13 @@ struct stencil_server_s {
 
     // --- worker side -------------------------------------------------------
 
+    // stream-ordered free on the copy stream (no device-wide synchronisation;
+    // callers only free jobs that no enqueued tick uses)
     void free_job(SJob &j)
     {
         void *bufs[] = {j.bj.f[0], j.bj.f[1], j.bj.w, j.bj.w2, j.bj.f64};
         for (void *b : bufs)
-            if (b) (void)hipFree(b);
+            if (b) (void)hipFreeAsync(b, cstream);
         j.bj.f[0] = j.bj.f[1] = j.bj.w = j.bj.w2 = nullptr;
         j.bj.f64 = nullptr;
     }
@@ -165,14 +173,16 @@ struct stencil_server_s {
                    : d.precision == STENCIL_PREC_F32_MASTER64 ? POL_F32_MASTER64
                                                               : POL_F32_ONLY;
         b.parity = 0;
+        // stream-ordered allocation and upload on the copy stream; the caller
+        // waits for the copy stream before the job joins a tick
         const size_t pad = (size_t)padded_elems(b.g);
         const size_t es = b.policy == POL_F64 ? 8 : 4;
-        bool ok = hipMalloc(&b.f[0], pad * es) == hipSuccess &&
-                  hipMalloc(&b.f[1], pad * es) == hipSuccess &&
-                  hipMalloc(&b.w, pad * es) == hipSuccess;
+        auto alloc = [&](void **p, size_t bytes) {
+            return hipMallocAsync(p, bytes, cstream) == hipSuccess;
+        };
+        bool ok = alloc(&b.f[0], pad * es) && alloc(&b.f[1], pad * es) && alloc(&b.w, pad * es);
         if (ok && b.policy == POL_F32_MASTER64)
-            ok = hipMalloc(&b.w2, pad * 4) == hipSuccess &&
-                 hipMalloc(reinterpret_cast<void **>(&b.f64), pad * 8) == hipSuccess;
+            ok = alloc(&b.w2, pad * 4) && alloc(reinterpret_cast<void **>(&b.f64), pad * 8);
         if (!ok) {
             (void)hipGetLastError();
             free_job(j);
@@ -180,19 +190,17 @@ struct stencil_server_s {
         }
         const size_t n = pad ? (size_t)b.g.nx * b.g.ny * b.g.nz : 0;
         double *stage = nullptr;
-        if (hipMallocAsync(reinterpret_cast<void **>(&stage), n * 8, stream) != hipSuccess) {
+        if (!alloc(reinterpret_cast<void **>(&stage), n * 8)) {
             (void)hipGetLastError();
             free_job(j);
             return STENCIL_ENOMEM;
         }
         int rc = STENCIL_OK;
-        if (hipMemcpyAsync(stage, d.init, n * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
+        if (hipMemcpyAsync(stage, d.init, n * 8, hipMemcpyHostToDevice, cstream) != hipSuccess)
             rc = STENCIL_EDEVICE;
         if (!rc)
-            rc = launch_job_upload(stage, b, 0, stream);
-        (void)hipFreeAsync(stage, stream);
-        if (!rc && hipStreamSynchronize(stream) != hipSuccess)
-            rc = STENCIL_EDEVICE;
+            rc = launch_job_upload(stage, b, 0, cstream);
+        (void)hipFreeAsync(stage, cstream);
         if (rc)
             free_job(j);
         return rc;
@@ -203,17 +211,15 @@ struct stencil_server_s {
         const BatchJob &b = j.bj;
         const size_t n = (size_t)b.g.nx * b.g.ny * b.g.nz;
         double *stage = nullptr;
-        if (hipMallocAsync(reinterpret_cast<void **>(&stage), n * 8, stream) != hipSuccess) {
+        if (hipMallocAsync(reinterpret_cast<void **>(&stage), n * 8, cstream) != hipSuccess) {
             (void)hipGetLastError();
             return STENCIL_ENOMEM;
         }
-        int rc = launch_job_download(b, b.parity, stage, stream);
-        if (!rc && hipMemcpyAsync(j.d.result, stage, n * 8, hipMemcpyDeviceToHost, stream) !=
+        int rc = launch_job_download(b, b.parity, stage, cstream);
+        if (!rc && hipMemcpyAsync(j.d.result, stage, n * 8, hipMemcpyDeviceToHost, cstream) !=
                        hipSuccess)
             rc = STENCIL_EDEVICE;
-        (void)hipFreeAsync(stage, stream);
-        if (hipStreamSynchronize(stream) != hipSuccess && !rc)
-            rc = STENCIL_EDEVICE;
+        (void)hipFreeAsync(stage, cstream);
         return rc;
     }
 
@@ -261,26 +267,50 @@ struct stencil_server_s {
                          });
         for (auto &j : active)
             j->steps_tick = 0;
-        int tiles = 0, njobs = 0;
-        int maxsteps = 0;
+        int maxsteps = 0, nsel = 0;
         double points = 0;
+        std::vector<SJob *> sel;
         for (auto &jp : order) {
             SJob &j = *jp;
-            if (njobs > 0 && points >= (double)min_points && j.idle_ticks < STARVE_TICKS)
+            if (nsel > 0 && points >= (double)min_points && j.idle_ticks < STARVE_TICKS)
                 continue;
             j.steps_tick = (int)std::min<long long>(d.tick_steps, j.d.steps - j.steps_done);
             maxsteps = std::max(maxsteps, j.steps_tick);
-            BatchJob b = j.bj;
-            b.steps = j.steps_tick;
-            b.tiles_x = (b.g.nx + BT_X - 1) / BT_X;
-            b.tiles_y = (b.g.ny + BT_Y - 1) / BT_Y;
-            b.tile_begin = tiles;
-            tiles += b.tiles_x * b.tiles_y * b.g.nz;
-            points += (double)b.g.nx * b.g.ny * b.g.nz;
-            rec[njobs++] = b;
+            points += (double)j.bj.g.nx * j.bj.g.ny * j.bj.g.nz;
+            sel.push_back(&j);
+            ++nsel;
         }
+        // table: the 2-D jobs (per-point tiles), then the 3-D jobs (z-march
+        // tiles), each kind numbering its own work items
+        int tiles = 0, tiles3 = 0, njobs = 0, n2d = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1)
+                n2d = njobs;
+            for (SJob *jp : sel) {
+                const bool d3 = advdiff_uses_zmarch(jp->bj.g);
+                if (d3 != (pass == 1))
+                    continue;
+                BatchJob b = jp->bj;
+                b.steps = jp->steps_tick;
+                if (!d3) {
+                    b.tiles_x = (b.g.nx + BT_X - 1) / BT_X;
+                    b.tiles_y = (b.g.ny + BT_Y - 1) / BT_Y;
+                    b.tile_begin = tiles;
+                    tiles += b.tiles_x * b.tiles_y * b.g.nz;
+                } else {
+                    b.tiles_x = (b.g.nx + ZM_TX - 1) / ZM_TX;
+                    b.tiles_y = (b.g.ny + ZM_ROWS - 1) / ZM_ROWS;
+                    b.lz = advdiff_zmarch_lz(b.g);
+                    b.tile_begin = tiles3;
+                    tiles3 += b.tiles_x * b.tiles_y * ((b.g.nz + b.lz - 1) / b.lz);
+                }
+                rec[njobs++] = b;
+            }
+        }
+        hdr->n2d = n2d;
         hdr->njobs = njobs;
         hdr->total_tiles = tiles;
+        hdr->total3 = tiles3;
         if (hipMemcpyAsync(d_table, h_table, batch_table_bytes(njobs),
                            hipMemcpyHostToDevice, stream) != hipSuccess)
             return STENCIL_EDEVICE;
@@ -294,9 +324,7 @@ struct stencil_server_s {
                 rc = launch_batch_substep(d_table, s, rk, d.blocks, stream);
             *launches = 3 * maxsteps;
         }
-        if (hipStreamSynchronize(stream) != hipSuccess && !rc)
-            rc = STENCIL_EDEVICE;
-        return rc;
+        return rc; // enqueued; the caller waits for the stream
     }
 
     void fail_all(int err)
@@ -325,14 +353,29 @@ struct stencil_server_s {
             fail_all(STENCIL_EDEVICE);
             return;
         }
+        // jobs whose steps finished in the previous tick: their results are
+        // copied out (and their memory freed) while the next tick runs
+        std::vector<std::shared_ptr<SJob>> to_download;
+        auto fail_lists = [&](int err, std::vector<std::shared_ptr<SJob>> &extra) {
+            for (auto *lst : {&to_download, &extra})
+                for (auto &j : *lst) {
+                    free_job(*j);
+                    finish(j, STENCIL_JOB_FAILED, err);
+                }
+            to_download.clear();
+            extra.clear();
+            fail_all(err);
+        };
         for (;;) {
             std::vector<std::shared_ptr<SJob>> admit;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+                cv_work.wait(lk, [&] {
+                    return stop || !queue.empty() || !active.empty() || !to_download.empty();
+                });
                 if (stop)
                     break;
-                int slots = d.max_slots - (int)active.size();
+                int slots = d.max_slots - (int)active.size() - (int)to_download.size();
                 for (auto it = queue.begin(); it != queue.end();) {
                     auto &j = *it;
                     if (j->cancel) {
@@ -358,69 +401,101 @@ struct stencil_server_s {
                     }
                 }
             }
+
+            // 1. the tick of the resident jobs, enqueued on the compute stream
+            const double tb = clock();
+            long long nl = 0;
+            const bool ticked = !active.empty();
+            int rc = ticked ? tick(&nl) : STENCIL_OK;
+            if (rc) {
+                fail_lists(rc, admit);
+                return;
+            }
+            // 2. meanwhile, on the copy stream: results of the jobs finished in
+            //    the previous tick, then the initial states of the admitted ones
+            std::vector<int> drc(to_download.size());
+            for (size_t k = 0; k < to_download.size(); ++k) {
+                drc[k] = download_job(*to_download[k]);
+                free_job(*to_download[k]);
+            }
+            std::vector<std::shared_ptr<SJob>> started;
             for (auto &j : admit) {
-                int rc = start_job(*j);
-                if (rc == STENCIL_EDEVICE) {
-                    finish(j, STENCIL_JOB_FAILED, rc);
-                    fail_all(rc);
+                const int urc = start_job(*j);
+                if (urc == STENCIL_EDEVICE) {
+                    finish(j, STENCIL_JOB_FAILED, urc);
+                    fail_lists(urc, started);
                     return;
                 }
-                if (rc) {
-                    finish(j, STENCIL_JOB_FAILED, rc);
-                    continue;
+                if (urc)
+                    finish(j, STENCIL_JOB_FAILED, urc);
+                else
+                    started.push_back(j);
+            }
+            // 3. wait for both streams
+            const bool ok_compute = hipStreamSynchronize(stream) == hipSuccess;
+            const bool ok_copy = hipStreamSynchronize(cstream) == hipSuccess;
+            const double te = clock();
+            if (!ok_compute || !ok_copy) {
+                fail_lists(STENCIL_EDEVICE, started);
+                return;
+            }
+            for (size_t k = 0; k < to_download.size(); ++k)
+                finish(to_download[k], drc[k] ? STENCIL_JOB_FAILED : STENCIL_JOB_DONE, drc[k]);
+            to_download.clear();
+
+            // 4. bookkeeping of the tick
+            if (ticked) {
+                std::vector<std::shared_ptr<SJob>> keep;
+                for (auto &j : active) {
+                    j->steps_done += j->steps_tick;
+                    j->idle_ticks = j->steps_tick ? 0 : j->idle_ticks + 1;
+                    j->bj.parity ^= (3 * j->steps_tick) & 1;
+                    if (j->t_first < 0 && j->steps_tick > 0) j->t_first = te;
+                    bool cancel;
+                    {
+                        std::lock_guard<std::mutex> lk(mu);
+                        cancel = j->cancel;
+                    }
+                    if (j->steps_done >= j->d.steps) {
+                        to_download.push_back(j);
+                    } else if (cancel) {
+                        free_job(*j);
+                        finish(j, STENCIL_JOB_CANCELLED, 0);
+                    } else {
+                        keep.push_back(j);
+                    }
                 }
-                std::lock_guard<std::mutex> lk(mu);
+                active.swap(keep);
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto &j : started) {
                 j->state = STENCIL_JOB_RUNNING;
-                j->t_admit = clock();
+                j->t_admit = te;
                 st.admitted++;
                 active.push_back(j);
             }
-            if (active.empty())
-                continue;
-            const double tb = clock();
-            long long nl = 0;
-            int rc = tick(&nl);
-            const double te = clock();
-            if (rc) {
-                fail_all(rc);
-                return;
+            if (ticked) {
+                st.ticks++;
+                st.launches += nl;
+                st.busy_s += te - tb;
             }
-            std::vector<std::shared_ptr<SJob>> keep;
-            for (auto &j : active) {
-                j->steps_done += j->steps_tick;
-                j->idle_ticks = j->steps_tick ? 0 : j->idle_ticks + 1;
-                j->bj.parity ^= (3 * j->steps_tick) & 1;
-                if (j->t_first < 0 && j->steps_tick > 0) j->t_first = te;
-                bool cancel;
-                {
-                    std::lock_guard<std::mutex> lk(mu);
-                    cancel = j->cancel;
-                }
-                if (j->steps_done >= j->d.steps) {
-                    // a failed copy fails this job; a device-wide fault shows
-                    // again at the next tick's synchronisation
-                    int drc = download_job(*j);
-                    free_job(*j);
-                    finish(j, drc ? STENCIL_JOB_FAILED : STENCIL_JOB_DONE, drc);
-                } else if (cancel) {
-                    free_job(*j);
-                    finish(j, STENCIL_JOB_CANCELLED, 0);
-                } else {
-                    keep.push_back(j);
-                }
-            }
-            active.swap(keep);
-            std::lock_guard<std::mutex> lk(mu);
-            st.ticks++;
-            st.launches += nl;
-            st.busy_s += te - tb;
         }
-        // stopping: cancel what is resident
+        // stopping: deliver the results already computed, cancel the rest
+        std::vector<int> drc(to_download.size());
+        for (size_t k = 0; k < to_download.size(); ++k) {
+            drc[k] = download_job(*to_download[k]);
+            free_job(*to_download[k]);
+        }
+        const bool ok = hipStreamSynchronize(cstream) == hipSuccess;
+        for (size_t k = 0; k < to_download.size(); ++k)
+            finish(to_download[k], (!ok || drc[k]) ? STENCIL_JOB_FAILED : STENCIL_JOB_DONE,
+                   !ok ? STENCIL_EDEVICE : drc[k]);
         for (auto &j : active) {
             free_job(*j);
             finish(j, STENCIL_JOB_CANCELLED, 0);
         }
         active.clear();
+        (void)hipStreamSynchronize(cstream);
     }
 };
 
@@ -464,11 +539,17 @@ stencil_status stencil_server_create(const stencil_server_desc *desc, stencil_se
         delete s;
         return fail(STENCIL_EDEVICE, "cannot create a stream");
     }
+    if (hipStreamCreateWithFlags(&s->cstream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        return fail(STENCIL_EDEVICE, "cannot create a stream");
+    }
     const size_t tb = batch_table_bytes(s->d.max_slots);
     if (hipMalloc(&s->d_table, tb) != hipSuccess || hipHostMalloc(&s->h_table, tb) != hipSuccess) {
         (void)hipGetLastError();
         if (s->d_table) (void)hipFree(s->d_table);
         (void)hipStreamDestroy(s->stream);
+        (void)hipStreamDestroy(s->cstream);
         delete s;
         return fail(STENCIL_ENOMEM, "cannot allocate the job table");
     }
@@ -491,6 +572,7 @@ stencil_status stencil_server_create(const stencil_server_desc *desc, stencil_se
         (void)hipFree(s->d_table);
         (void)hipHostFree(s->h_table);
         (void)hipStreamDestroy(s->stream);
+        (void)hipStreamDestroy(s->cstream);
         delete s;
         return fail(STENCIL_ENOMEM, "cannot start the server thread");
     }
@@ -519,6 +601,7 @@ stencil_status stencil_server_destroy(stencil_server_t s)
     (void)hipFree(s->d_table);
     (void)hipHostFree(s->h_table);
     (void)hipStreamDestroy(s->stream);
+    (void)hipStreamDestroy(s->cstream);
     s->cv_done.notify_all();
     delete s;
     return STENCIL_OK;

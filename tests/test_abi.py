@@ -151,7 +151,8 @@ def _rk_rc(**kw):
 @pytest.mark.parametrize("kw,code", [
     (dict(variant=3), -1),                                  # unknown bank
     (dict(variant=-1), -1),
-    (dict(model=S.MODEL_ADVDIFF, variant=S.RK_LDS), -3),    # LDS bank is MHD8-only
+    (dict(model=S.MODEL_ADVDIFF, ndim=2, dims=(16, 16, 1), variant=S.RK_LDS), -3),  # 3-D only
+    (dict(model=S.MODEL_ADVDIFF, variant=S.RK_LDS, block=(64, 16, 32)), -1),  # z planes only
     (dict(variant=S.RK_LDS, block=(16, 8, 2)), -1),         # brick not built
     (dict(variant=S.RK_LDS, block=(64, 4, 1)), -1),
     (dict(variant=S.RK_CACHED, block=(64, 4, 2)), -1),      # one plane per workgroup

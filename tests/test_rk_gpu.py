@@ -333,3 +333,24 @@ def test_advdiff_pitched_layout(n):
     ref = O.rk3_steps(O.MODEL_ADVDIFF, [O.pad_periodic(f0, 3)], ds, dt, 2, nu=0.01, c=c)
     assert relerr(out[0], ref[0]) <= 1e-12
     assert untouched
+
+
+@pytest.mark.parametrize("prec", [S.PREC_F64, S.PREC_F32_MASTER64])
+@pytest.mark.parametrize("lz", [0, 5, 64])
+def test_advdiff_zmarch_matches_oracle_and_cached(prec, lz):
+    n = (70, 37, 41)  # ragged against the 64 x 16 tiles
+    ds = ds_of(n)
+    c = (0.7, -0.4, 0.3)
+    dt = 0.1 * min(ds) / max(1.0, max(abs(v) for v in c))
+    f0 = inputs.uniform_field(n, 5)
+    outs = []
+    for variant, block in ((S.RK_LDS, (0, 0, lz)), (S.RK_CACHED, None)):
+        lp, master = run_policy(n, prec, [f0], 3, dt, model=S.MODEL_ADVDIFF, nu=0.01, adv=c,
+                                variant=variant, block=block)
+        # the FP64 master holds interior values only (its halo is never read)
+        outs.append(O.interior(master[0] if master is not None else lp[0], 3))
+    ref = O.interior(O.rk3_steps(O.MODEL_ADVDIFF, [O.pad_periodic(f0, 3)], ds, dt, 3, nu=0.01,
+                                 c=c)[0], 3)
+    tol = 1e-12 if prec == S.PREC_F64 else 1e-5
+    assert relerr(outs[0], ref) <= tol
+    assert relerr(outs[0], outs[1]) <= tol

@@ -203,3 +203,31 @@ def test_submit_validation_and_queue_cap():
     srv.cancel(first)
     srv.cancel(second)
     srv.close()
+
+
+# 3-D jobs of at least 2^20 points run as z-march tiles in the batch (and in
+# the solo plan); smaller ones keep the per-point kernel
+BIG = [((128, 96, 96), 3, S.PREC_F64, (0.4, -0.6, 0.2), 0.01, 11),
+       ((112, 100, 96), 2, S.PREC_F32_MASTER64, (-0.3, 0.5, 0.9), 0.02, 12),
+       ((100, 104, 101), 2, S.PREC_F32_ONLY, (0.7, 0.1, -0.2), 0.005, 13)]
+
+
+def test_zmarch_jobs_bitwise_alone_mixed_graph_and_solo():
+    jobs = BIG + JOBS[:2]
+    mix, stats = run_server(jobs, tick_steps=2, use_graph=True, max_slots=8)
+    assert stats["completed"] == len(jobs)
+    nograph, _ = run_server(jobs, tick_steps=1, use_graph=False, max_slots=2)
+    for k, job in enumerate(BIG):
+        alone, _ = run_server([job], tick_steps=3, use_graph=True, max_slots=1)
+        assert np.array_equal(mix[k], alone[0]), k
+        assert np.array_equal(mix[k], nograph[k]), k
+        assert np.array_equal(mix[k], solo_path(*job)), k
+
+
+def test_zmarch_job_matches_oracle():
+    dims, steps, prec, c, nu, seed = BIG[0]
+    out, _ = run_server([BIG[0]], tick_steps=2)
+    ds = [2 * math.pi / v for v in dims]
+    ref = O.rk3_steps(O.MODEL_ADVDIFF, [O.pad_periodic(make_init(dims, seed), 3)], ds,
+                      job_dt(dims, c), steps, nu=nu, c=c)[0]
+    assert relerr(out[0], O.interior(ref, 3)) <= 1e-12
