@@ -19,6 +19,11 @@ _lib = None
 
 MODEL_MHD8 = 0
 MODEL_ADVDIFF = 1
+MODEL_MHD_FULL = 2
+# constants of the full model that the paper leaves to its reference [44]
+# (ideal-gas closure; heating, cooling, conduction, bulk viscosity)
+MHD_DEFAULTS = dict(zeta=0.0, mu0=1.0, gamma=5.0 / 3.0, cp=1.0, lnrho0=0.0, K=0.0, heat=0.0,
+                    cool=0.0)
 # field order of the 8-field system (Table A1)
 LNRHO, UX, UY, UZ, SS, AX, AY, AZ = range(8)
 # window filter codes (max filter of Sec. 2.3; median filter of Sec. 1)
@@ -220,39 +225,48 @@ def deriv(f, ds, op):
     return out
 
 
-def _model_prm(model, nu, eta, cs2, c):
+def _model_prm(model, nu, eta, cs2, c, mhd=None):
     if model == MODEL_MHD8:
         return (ctypes.c_double * 4)(nu, eta, cs2, 0.0)
+    if model == MODEL_MHD_FULL:
+        m = dict(MHD_DEFAULTS, **(mhd or {}))
+        return (ctypes.c_double * 11)(nu, eta, cs2, m["zeta"], m["mu0"], m["gamma"], m["cp"],
+                                      m["lnrho0"], m["K"], m["heat"], m["cool"])
     c = list(c) + [0.0] * (3 - len(c))
     return (ctypes.c_double * 4)(nu, *c)
 
 
-def rhs(model, fields, ds, nu=1e-3, eta=1e-3, cs2=1.0, c=(0.0, 0.0, 0.0)):
+def _nf(model):
+    return 1 if model == MODEL_ADVDIFF else 8
+
+
+def rhs(model, fields, ds, nu=1e-3, eta=1e-3, cs2=1.0, c=(0.0, 0.0, 0.0), mhd=None):
     """Right-hand side R of the model over the interior; returns padded arrays
-    (halo zero), one per field."""
+    (halo zero), one per field. For MODEL_MHD_FULL, cs2 is cs0^2 and mhd
+    overrides MHD_DEFAULTS."""
     nd, n = _dims(fields[0], 3)
-    if len(fields) != (8 if model == MODEL_MHD8 else 1):
+    if len(fields) != _nf(model):
         raise ValueError("wrong number of fields for the model")
     R = [np.zeros_like(fields[0]) for _ in fields]
     rc = lib().oracle_rhs(model, _ptrs(fields), _ptrs(R), nd, n, _d3(ds),
-                          _model_prm(model, nu, eta, cs2, c))
+                          _model_prm(model, nu, eta, cs2, c, mhd))
     if rc != 0:
         raise ValueError("bad model/dimension")
     return R
 
 
 def rk3_substep(model, stage, fin, w, ds, dt, nu=1e-3, eta=1e-3, cs2=1.0,
-                c=(0.0, 0.0, 0.0)):
+                c=(0.0, 0.0, 0.0), mhd=None):
     """One Williamson substep: updates the arrays in w in place and returns
     new padded f arrays with a periodic halo."""
     nd, n = _dims(fin[0], 3)
-    if len(fin) != len(w) or len(fin) != (8 if model == MODEL_MHD8 else 1):
+    if len(fin) != len(w) or len(fin) != _nf(model):
         raise ValueError("wrong number of fields for the model")
     if any(a.shape != fin[0].shape for a in w):
         raise ValueError("w must match the fields' padded shape")
     fout = [np.zeros_like(a) for a in fin]
     rc = lib().oracle_rk3_substep(model, stage, _ptrs(fin), _ptrs(w), _ptrs(fout), nd, n,
-                                  _d3(ds), _model_prm(model, nu, eta, cs2, c), dt)
+                                  _d3(ds), _model_prm(model, nu, eta, cs2, c, mhd), dt)
     if rc != 0:
         raise ValueError("bad model/dimension/stage")
     return fout
@@ -270,13 +284,13 @@ def rk3_steps(model, f, ds, dt, steps, **kw):
 
 
 def rk3_substep_at(model, stage, fin, w_in, ds, dt, pts, nu=1e-3, eta=1e-3, cs2=1.0,
-                   c=(0.0, 0.0, 0.0)):
+                   c=(0.0, 0.0, 0.0), mhd=None):
     """Substep at listed interior points. w_in: (nf, count) old w (ignored at
     stage 0). Returns (w_out, f_out), each (nf, count)."""
     nd, n = _dims(fin[0], 3)
     pts = np.ascontiguousarray(pts, dtype=np.int64).reshape(-1, 3)
     nf = len(fin)
-    if nf != (8 if model == MODEL_MHD8 else 1):
+    if nf != _nf(model):
         raise ValueError("wrong number of fields for the model")
     nn = [n[0], n[1], n[2]]
     if len(pts) and (pts.min() < 0 or any(pts[:, a].max() >= nn[a] for a in range(3))):
@@ -287,7 +301,7 @@ def rk3_substep_at(model, stage, fin, w_in, ds, dt, pts, nu=1e-3, eta=1e-3, cs2=
     w_out = np.zeros((nf, cnt))
     f_out = np.zeros((nf, cnt))
     rc = lib().oracle_rk3_substep_at(model, stage, _ptrs(fin), _ptr(w_in), nd, n, _d3(ds),
-                                     _model_prm(model, nu, eta, cs2, c), dt,
+                                     _model_prm(model, nu, eta, cs2, c, mhd), dt,
                                      pts.ctypes.data_as(_lp), cnt, _ptr(w_out), _ptr(f_out))
     if rc != 0:
         raise ValueError("bad model/dimension/stage")

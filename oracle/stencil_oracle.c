@@ -343,6 +343,89 @@ int oracle_deriv(const double *f, double *out, int ndim, const long *n, const do
  * specific entropy, magnetic vector potential (3). */
 enum { LNRHO = 0, UX = 1, UY = 2, UZ = 3, SS = 4, AX = 5, AY = 6, AZ = 7 };
 
+/* The derivative bank gamma (Eq. 8) of the 8-field system at one padded cell:
+ * values of u, gradients and Laplacians of lnrho and s, the velocity and
+ * vector-potential Jacobians d_a v_b, their Laplacians and grad(div v), where
+ * grad(div v)_a = sum_b d_a d_b v_b takes the pure second derivative when
+ * a == b and the mixed derivative otherwise. */
+typedef struct {
+    double u[3], gl[3], gs[3], du[3][3], dA[3][3];
+    double lapl, laps, lapu[3], lapA[3], gdivu[3], gdivA[3];
+} mhd_bank;
+
+static void mhd_bank_eval(const double *const *f, const long *P, long x, long y, long z,
+                          const double *ds, mhd_bank *k)
+{
+    size_t p = at(P, x, y, z);
+    k->lapl = 0.0;
+    k->laps = 0.0;
+    for (int b = 0; b < 3; ++b)
+        k->u[b] = f[UX + b][p];
+    for (int a = 0; a < 3; ++a) {
+        k->gl[a] = d1(f[LNRHO], P, x, y, z, a, ds);
+        k->gs[a] = d1(f[SS], P, x, y, z, a, ds);
+        k->lapl += d2(f[LNRHO], P, x, y, z, a, ds);
+        k->laps += d2(f[SS], P, x, y, z, a, ds);
+        for (int b = 0; b < 3; ++b) {
+            k->du[a][b] = d1(f[UX + b], P, x, y, z, a, ds); /* d_a u_b */
+            k->dA[a][b] = d1(f[AX + b], P, x, y, z, a, ds); /* d_a A_b */
+        }
+    }
+    for (int b = 0; b < 3; ++b) {
+        k->lapu[b] = 0.0;
+        k->lapA[b] = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            k->lapu[b] += d2(f[UX + b], P, x, y, z, a, ds);
+            k->lapA[b] += d2(f[AX + b], P, x, y, z, a, ds);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        k->gdivu[a] = 0.0;
+        k->gdivA[a] = 0.0;
+        for (int b = 0; b < 3; ++b) {
+            if (a == b) {
+                k->gdivu[a] += d2(f[UX + b], P, x, y, z, a, ds);
+                k->gdivA[a] += d2(f[AX + b], P, x, y, z, a, ds);
+            } else {
+                k->gdivu[a] += d11(f[UX + b], P, x, y, z, a, b, ds);
+                k->gdivA[a] += d11(f[AX + b], P, x, y, z, a, b, ds);
+            }
+        }
+    }
+}
+
+/* Quantities shared by both MHD right-hand sides: div u, B = curl A, the
+ * traceless rate of shear S_ab = (d_a u_b + d_b u_a)/2 - delta_ab div(u)/3,
+ * (u.grad) u, S.grad(lnrho), S:S and u x B. */
+typedef struct {
+    double divu, B[3], S[3][3], adv[3], Sgl[3], SS2, uxB[3];
+} mhd_derived;
+
+static void mhd_derive(const mhd_bank *k, mhd_derived *d)
+{
+    d->divu = k->du[0][0] + k->du[1][1] + k->du[2][2];
+    d->B[0] = k->dA[1][2] - k->dA[2][1];
+    d->B[1] = k->dA[2][0] - k->dA[0][2];
+    d->B[2] = k->dA[0][1] - k->dA[1][0];
+    d->SS2 = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            d->S[a][b] = 0.5 * (k->du[a][b] + k->du[b][a]) - (a == b ? d->divu / 3.0 : 0.0);
+            d->SS2 += d->S[a][b] * d->S[a][b];
+        }
+    for (int a = 0; a < 3; ++a) {
+        d->adv[a] = 0.0;
+        d->Sgl[a] = 0.0;
+        for (int b = 0; b < 3; ++b) {
+            d->adv[a] += k->u[b] * k->du[b][a]; /* (u.grad) u_a */
+            d->Sgl[a] += d->S[a][b] * k->gl[b]; /* (S.grad lnrho)_a */
+        }
+    }
+    d->uxB[0] = k->u[1] * d->B[2] - k->u[2] * d->B[1];
+    d->uxB[1] = k->u[2] * d->B[0] - k->u[0] * d->B[2];
+    d->uxB[2] = k->u[0] * d->B[1] - k->u[1] * d->B[0];
+}
+
 /* Eight-field proxy of the non-ideal MHD equations (Eq. A1-A4) with rho, T,
  * c_p and mu_0 set to one and heating, cooling, conduction and bulk viscosity
  * dropped, plus a nu-Laplacian on log density and entropy:
@@ -351,88 +434,92 @@ enum { LNRHO = 0, UX = 1, UY = 2, UZ = 3, SS = 4, AX = 5, AY = 6, AZ = 7 };
  *             + nu [lap u + grad(div u)/3 + 2 S.grad(lnrho)]
  *   R_s     = -u.grad(s) + nu lap(s) + eta |j|^2 + 2 nu S:S
  *   R_A     = u x B + eta lap(A)
- * with B = curl A, j = grad(div A) - lap A (curl curl A, mu_0 = 1) and the
- * traceless rate of shear S_ab = (d_a u_b + d_b u_a)/2 - delta_ab div(u)/3.
+ * with B = curl A and j = grad(div A) - lap A (curl curl A, mu_0 = 1).
  * f points at 8 radius-3 padded 3-D fields; (x, y, z) is a padded cell. */
 static void mhd8_rhs_point(const double *const *f, const long *P, long x, long y, long z,
                            const double *ds, const double *prm, double *R)
 {
     const double nu = prm[0], eta = prm[1], cs2 = prm[2];
-    size_t p = at(P, x, y, z);
-    double u[3], gl[3], gs[3], du[3][3], dA[3][3];
-    double lapl = 0.0, laps = 0.0, lapu[3], lapA[3], gdivu[3], gdivA[3];
-
-    for (int b = 0; b < 3; ++b)
-        u[b] = f[UX + b][p];
-    for (int a = 0; a < 3; ++a) {
-        gl[a] = d1(f[LNRHO], P, x, y, z, a, ds);
-        gs[a] = d1(f[SS], P, x, y, z, a, ds);
-        lapl += d2(f[LNRHO], P, x, y, z, a, ds);
-        laps += d2(f[SS], P, x, y, z, a, ds);
-        for (int b = 0; b < 3; ++b) {
-            du[a][b] = d1(f[UX + b], P, x, y, z, a, ds); /* d_a u_b */
-            dA[a][b] = d1(f[AX + b], P, x, y, z, a, ds); /* d_a A_b */
-        }
-    }
-    for (int b = 0; b < 3; ++b) {
-        lapu[b] = 0.0;
-        lapA[b] = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            lapu[b] += d2(f[UX + b], P, x, y, z, a, ds);
-            lapA[b] += d2(f[AX + b], P, x, y, z, a, ds);
-        }
-    }
-    /* grad(div v)_a = sum_b d_a d_b v_b: pure second derivative when a == b,
-     * mixed derivative otherwise. */
-    for (int a = 0; a < 3; ++a) {
-        gdivu[a] = 0.0;
-        gdivA[a] = 0.0;
-        for (int b = 0; b < 3; ++b) {
-            if (a == b) {
-                gdivu[a] += d2(f[UX + b], P, x, y, z, a, ds);
-                gdivA[a] += d2(f[AX + b], P, x, y, z, a, ds);
-            } else {
-                gdivu[a] += d11(f[UX + b], P, x, y, z, a, b, ds);
-                gdivA[a] += d11(f[AX + b], P, x, y, z, a, b, ds);
-            }
-        }
-    }
-
-    double divu = du[0][0] + du[1][1] + du[2][2];
-    double B[3] = {dA[1][2] - dA[2][1], dA[2][0] - dA[0][2], dA[0][1] - dA[1][0]};
-    double j[3], S[3][3];
+    mhd_bank k;
+    mhd_derived d;
+    mhd_bank_eval(f, P, x, y, z, ds, &k);
+    mhd_derive(&k, &d);
+    double j[3];
     for (int a = 0; a < 3; ++a)
-        j[a] = gdivA[a] - lapA[a];
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-            S[a][b] = 0.5 * (du[a][b] + du[b][a]) - (a == b ? divu / 3.0 : 0.0);
-    double jxB[3] = {j[1] * B[2] - j[2] * B[1], j[2] * B[0] - j[0] * B[2],
-                     j[0] * B[1] - j[1] * B[0]};
-    double uxB[3] = {u[1] * B[2] - u[2] * B[1], u[2] * B[0] - u[0] * B[2],
-                     u[0] * B[1] - u[1] * B[0]};
-
-    double ugl = 0.0, ugs = 0.0, jj = 0.0, SS2 = 0.0;
+        j[a] = k.gdivA[a] - k.lapA[a];
+    double jxB[3] = {j[1] * d.B[2] - j[2] * d.B[1], j[2] * d.B[0] - j[0] * d.B[2],
+                     j[0] * d.B[1] - j[1] * d.B[0]};
+    double ugl = 0.0, ugs = 0.0, jj = 0.0;
     for (int a = 0; a < 3; ++a) {
-        ugl += u[a] * gl[a];
-        ugs += u[a] * gs[a];
+        ugl += k.u[a] * k.gl[a];
+        ugs += k.u[a] * k.gs[a];
         jj += j[a] * j[a];
-        for (int b = 0; b < 3; ++b)
-            SS2 += S[a][b] * S[a][b];
     }
-
-    R[LNRHO] = -ugl - divu + nu * lapl;
-    for (int a = 0; a < 3; ++a) {
-        double adv = 0.0, Sgl = 0.0;
-        for (int b = 0; b < 3; ++b) {
-            adv += u[b] * du[b][a];   /* (u.grad) u_a */
-            Sgl += S[a][b] * gl[b];   /* (S.grad lnrho)_a */
-        }
-        R[UX + a] = -adv - cs2 * (gs[a] + gl[a]) + jxB[a] +
-                    nu * (lapu[a] + gdivu[a] / 3.0 + 2.0 * Sgl);
-    }
-    R[SS] = -ugs + nu * laps + eta * jj + 2.0 * nu * SS2;
+    R[LNRHO] = -ugl - d.divu + nu * k.lapl;
     for (int a = 0; a < 3; ++a)
-        R[AX + a] = uxB[a] + eta * lapA[a];
+        R[UX + a] = -d.adv[a] - cs2 * (k.gs[a] + k.gl[a]) + jxB[a] +
+                    nu * (k.lapu[a] + k.gdivu[a] / 3.0 + 2.0 * d.Sgl[a]);
+    R[SS] = -ugs + nu * k.laps + eta * jj + 2.0 * nu * d.SS2;
+    for (int a = 0; a < 3; ++a)
+        R[AX + a] = d.uxB[a] + eta * k.lapA[a];
+}
+
+/* The non-ideal MHD equations as written (Eq. A1-A4), with the closure the
+ * paper leaves to its reference [44] chosen as an ideal gas:
+ *   rho = exp(lnrho)
+ *   cs2 = cs0^2 exp(gamma s / c_p + (gamma - 1)(lnrho - lnrho0))
+ *   T   = cs2 / ((gamma - 1) c_p)
+ *   j   = mu_0^-1 curl B = mu_0^-1 (grad(div A) - lap A)
+ *   R_lnrho = -u.grad(lnrho) - div u                                   (A1)
+ *   R_u     = -(u.grad)u - cs2 grad(s / c_p + lnrho) + j x B / rho
+ *             + nu [lap u + grad(div u)/3 + 2 S.grad(lnrho)]
+ *             + zeta grad(div u)                                       (A2)
+ *   R_s     = -u.grad(s) + [H - C + K lap T + eta mu_0 |j|^2
+ *             + 2 rho nu S:S + zeta rho (div u)^2] / (rho T)           (A3)
+ *   R_A     = u x B + eta lap(A)                                       (A4)
+ * with constant conductivity K, heating H and cooling C, and lap T taken by
+ * the chain rule from the bank's derivatives of s and lnrho:
+ *   grad T = T g,  g = (gamma / c_p) grad s + (gamma - 1) grad lnrho,
+ *   lap T  = T [(gamma / c_p) lap s + (gamma - 1) lap lnrho + |g|^2].
+ * prm = {nu, eta, cs0^2, zeta, mu_0, gamma, c_p, lnrho0, K, H, C}. */
+static void mhdfull_rhs_point(const double *const *f, const long *P, long x, long y, long z,
+                              const double *ds, const double *prm, double *R)
+{
+    const double nu = prm[0], eta = prm[1], cs02 = prm[2], zeta = prm[3], mu0 = prm[4];
+    const double gamma = prm[5], cp = prm[6], lnrho0 = prm[7], K = prm[8], H = prm[9],
+                 C = prm[10];
+    mhd_bank k;
+    mhd_derived d;
+    mhd_bank_eval(f, P, x, y, z, ds, &k);
+    mhd_derive(&k, &d);
+    size_t p = at(P, x, y, z);
+    const double lnrho = f[LNRHO][p], s = f[SS][p];
+    const double rho = exp(lnrho);
+    const double cs2 = cs02 * exp(gamma * s / cp + (gamma - 1.0) * (lnrho - lnrho0));
+    const double T = cs2 / ((gamma - 1.0) * cp);
+    double j[3], g[3], gg = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        j[a] = (k.gdivA[a] - k.lapA[a]) / mu0;
+        g[a] = gamma / cp * k.gs[a] + (gamma - 1.0) * k.gl[a];
+        gg += g[a] * g[a];
+    }
+    const double lapT = T * (gamma / cp * k.laps + (gamma - 1.0) * k.lapl + gg);
+    double jxB[3] = {j[1] * d.B[2] - j[2] * d.B[1], j[2] * d.B[0] - j[0] * d.B[2],
+                     j[0] * d.B[1] - j[1] * d.B[0]};
+    double ugl = 0.0, ugs = 0.0, jj = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        ugl += k.u[a] * k.gl[a];
+        ugs += k.u[a] * k.gs[a];
+        jj += j[a] * j[a];
+    }
+    R[LNRHO] = -ugl - d.divu;
+    for (int a = 0; a < 3; ++a)
+        R[UX + a] = -d.adv[a] - cs2 * (k.gs[a] / cp + k.gl[a]) + jxB[a] / rho +
+                    nu * (k.lapu[a] + k.gdivu[a] / 3.0 + 2.0 * d.Sgl[a]) + zeta * k.gdivu[a];
+    R[SS] = -ugs + (H - C + K * lapT + eta * mu0 * jj + 2.0 * rho * nu * d.SS2 +
+                    zeta * rho * d.divu * d.divu) / (rho * T);
+    for (int a = 0; a < 3; ++a)
+        R[AX + a] = d.uxB[a] + eta * k.lapA[a];
 }
 
 /* Scalar advection-diffusion: R = -c.grad f + nu lap f in ndim = 2 or 3
@@ -448,22 +535,24 @@ static void advdiff_rhs_point(const double *const *f, const long *P, int ndim, l
     R[0] = acc;
 }
 
-enum { MODEL_MHD8 = 0, MODEL_ADVDIFF = 1 };
+enum { MODEL_MHD8 = 0, MODEL_ADVDIFF = 1, MODEL_MHD_FULL = 2 };
 
-static int model_nf(int model) { return model == MODEL_MHD8 ? 8 : 1; }
+static int model_nf(int model) { return model == MODEL_ADVDIFF ? 1 : 8; }
 
 static void rhs_point(int model, const double *const *f, const long *P, int ndim, long x,
                       long y, long z, const double *ds, const double *prm, double *R)
 {
     if (model == MODEL_MHD8)
         mhd8_rhs_point(f, P, x, y, z, ds, prm, R);
+    else if (model == MODEL_MHD_FULL)
+        mhdfull_rhs_point(f, P, x, y, z, ds, prm, R);
     else
         advdiff_rhs_point(f, P, ndim, x, y, z, ds, prm, R);
 }
 
 static int model_ok(int model, int ndim)
 {
-    return (model == MODEL_MHD8 && ndim == 3) ||
+    return ((model == MODEL_MHD8 || model == MODEL_MHD_FULL) && ndim == 3) ||
            (model == MODEL_ADVDIFF && (ndim == 2 || ndim == 3));
 }
 
