@@ -230,9 +230,27 @@ stencil_status stencil_fd_weights(int order, int radius, double *out);
  *           of shear: Eq. A1-A4 with rho, T, c_p, mu_0 = 1 and no heating,
  *           cooling, conduction or bulk viscosity.
  *  ADVDIFF: 1 field, 2-D or 3-D: R = -c.grad f + nu lap f.
+ *  MHD_FULL: the same 8 fields, 3-D, the non-ideal MHD equations as written
+ *           (Eq. A1-A4), closed by an ideal gas (the paper defers the
+ *           closure to its reference [44]; this one is chosen here):
+ *           rho = exp(lnrho), cs2 = cs0^2 exp(gamma s / c_p
+ *           + (gamma - 1)(lnrho - lnrho0)) with cs0^2 = desc.cs2,
+ *           T = cs2 / ((gamma - 1) c_p), j = (grad div A - lap A) / mu_0,
+ *           R_lnrho = -u.grad lnrho - div u
+ *           R_u     = -(u.grad)u - cs2 grad(s / c_p + lnrho) + j x B / rho
+ *                     + nu [lap u + grad(div u)/3 + 2 S.grad lnrho]
+ *                     + zeta grad(div u)
+ *           R_s     = -u.grad s + [H - C + K lap T + eta mu_0 |j|^2
+ *                     + 2 rho nu S:S + zeta rho (div u)^2] / (rho T)
+ *           R_A     = u x B + eta lap A
+ *           with constant conductivity K, heating H and cooling C, and
+ *           lap T = T [(gamma / c_p) lap s + (gamma - 1) lap lnrho + |g|^2],
+ *           g = (gamma / c_p) grad s + (gamma - 1) grad lnrho (the chain
+ *           rule on the bank's derivatives of s and lnrho).
  * Mixed derivatives are tensor products of the first-derivative stencil. */
 #define STENCIL_MODEL_MHD8 0
 #define STENCIL_MODEL_ADVDIFF 1
+#define STENCIL_MODEL_MHD_FULL 2
 
 /* Precision policies. F64: FP64 everywhere. F32_MASTER64 / BF16_MASTER64:
  * fields stored in FP32 / BF16, derivatives and RK registers in FP32, and an
@@ -247,7 +265,7 @@ stencil_status stencil_fd_weights(int order, int radius, double *out);
 
 typedef struct stencil_rk_desc {
     int model;      /* STENCIL_MODEL_* */
-    int ndim;       /* 3 for MHD8, 2 or 3 for ADVDIFF */
+    int ndim;       /* 3 for MHD8 and MHD_FULL, 2 or 3 for ADVDIFF */
     int dims[3];    /* interior extents, each >= 3 (periodic, radius 3) */
     int precision;  /* STENCIL_PREC_* */
     double ds[3];   /* grid spacing per axis (> 0) */
@@ -255,9 +273,10 @@ typedef struct stencil_rk_desc {
     double adv[3];  /* ADVDIFF velocity */
     int block[3];   /* launch override (0 = plan's choice). CACHED: x lanes, y
                        lanes (x*y a multiple of 64, at most 256), block[2] 0
-                       or 1 (one z plane per workgroup). LDS, MHD8: the brick
-                       of output points per workgroup, one of 16x8x4 16x8x8
-                       32x4x4 8x8x8. LDS, ADVDIFF: {0, 0, z planes} */
+                       or 1 (one z plane per workgroup). LDS, MHD8 and
+                       MHD_FULL: the brick of output points per workgroup,
+                       one of 16x8x4 16x8x8 32x4x4 8x8x8. LDS, ADVDIFF:
+                       {0, 0, z planes} */
     int variant;    /* STENCIL_RK_VARIANT_*: how the derivative bank reads its
                        taps */
     int row_pitch;  /* field layout, as in stencil_desc (both 0 = compact):  */
@@ -265,15 +284,22 @@ typedef struct stencil_rk_desc {
                        row_pitch >= x_offset + dims[0] + 3 elements; every
                        buffer of the plan (f, w, w2, f64) uses this layout and
                        holds stencil_plan_padded_elems(plan) elements */
+    /* MHD_FULL only (ignored otherwise; cs2 above is cs0^2 > 0): bulk
+       viscosity zeta, vacuum permeability mu0 > 0, adiabatic index
+       gamma > 1, specific heat c_p > 0, reference log density lnrho0,
+       conductivity K, heating H and cooling C (all finite) */
+    double zeta, mu0, gamma, cp, lnrho0, K, heat, cool;
 } stencil_rk_desc;
 
-/* Derivative-bank strategies (Sec. 4.1/4.4): AUTO = LDS for MHD8 and 3-D
- * ADVDIFF, CACHED for 2-D ADVDIFF. CACHED: one lane per point, every tap a
- * load through L1/L2. LDS, MHD8: a workgroup owns a brick of points and
- * streams the fields one at a time through an LDS tile of the brick plus its
- * halo. LDS, 3-D ADVDIFF: the right-hand side is a radius-3 star, computed as
- * a z march over 64 x 16 tiles (x-y plane in LDS, z taps in registers) with
- * the RK update as its epilogue; block[2] = z planes per tile (0 = 32). */
+/* Derivative-bank strategies (Sec. 4.1/4.4): AUTO = LDS for MHD8, MHD_FULL
+ * and 3-D ADVDIFF grids of at least 2^20 points, CACHED otherwise. CACHED:
+ * one lane per point, every tap a load through L1/L2. LDS, MHD8/MHD_FULL: a
+ * workgroup owns a brick of points and streams the fields one at a time
+ * through an LDS tile of the brick plus its halo. LDS, 3-D ADVDIFF: the
+ * right-hand side is a radius-3 star, computed as a z march over 64 x 16
+ * tiles (x-y plane in LDS, z taps in registers) with the RK update as its
+ * epilogue; block[2] = z planes per tile (0 = chosen from the grid size:
+ * 8..32, aiming at about 1024 tiles). */
 #define STENCIL_RK_VARIANT_AUTO 0
 #define STENCIL_RK_VARIANT_CACHED 1
 #define STENCIL_RK_VARIANT_LDS 2
@@ -302,7 +328,8 @@ typedef struct stencil_fields {
  * 15/16, 8/15), substep i: w = alpha_i w + dt R(f), f = f + beta_i w. */
 stencil_status stencil_plan_rk(const stencil_rk_desc *desc, stencil_plan_t *out);
 
-/* Number of fields of the plan's model (8 or 1), or a negative status. */
+/* Number of fields of the plan's model (8 for MHD8 and MHD_FULL, 1 for
+ * ADVDIFF), or a negative status. */
 int stencil_plan_nfields(stencil_plan_t plan);
 
 /* One fused substep (substep = 0, 1, 2) as one kernel launch on stream. */

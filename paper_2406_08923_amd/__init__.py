@@ -272,7 +272,11 @@ class LinearPlan:
 # fused nonlinear substep (derivative bank + phi + low-storage RK3)
 # ---------------------------------------------------------------------------
 
-MODEL_MHD8, MODEL_ADVDIFF = 0, 1
+MODEL_MHD8, MODEL_ADVDIFF, MODEL_MHD_FULL = 0, 1, 2
+# constants of MODEL_MHD_FULL beyond nu, eta and cs2 (= cs0^2); a plan's mhd
+# dict overrides any of them
+MHD_FULL_DEFAULTS = dict(zeta=0.0, mu0=1.0, gamma=5.0 / 3.0, cp=1.0, lnrho0=0.0, K=0.0,
+                         heat=0.0, cool=0.0)
 RK_AUTO, RK_CACHED, RK_LDS = 0, 1, 2
 PREC_F64, PREC_F32_MASTER64, PREC_BF16_MASTER64, PREC_F32_ONLY, PREC_BF16_ONLY = range(5)
 _PREC_STORE = {PREC_F64: F64, PREC_F32_MASTER64: F32, PREC_BF16_MASTER64: BF16,
@@ -285,7 +289,9 @@ class _RkDesc(ctypes.Structure):
                 ("nu", ctypes.c_double), ("eta", ctypes.c_double), ("cs2", ctypes.c_double),
                 ("adv", ctypes.c_double * 3), ("block", ctypes.c_int * 3),
                 ("variant", ctypes.c_int), ("row_pitch", ctypes.c_int),
-                ("x_offset", ctypes.c_int)]
+                ("x_offset", ctypes.c_int)] + [
+                    (k, ctypes.c_double) for k in ("zeta", "mu0", "gamma", "cp", "lnrho0", "K",
+                                                   "heat", "cool")]
 
 
 class _Fields(ctypes.Structure):
@@ -315,11 +321,14 @@ def _fields_struct(f_in, f_out, w, w2=None, f64=None):
 
 
 class RkPlan:
-    """Plan of the fused substep of a model (MODEL_MHD8: 8 fields, 3-D;
-    MODEL_ADVDIFF: 1 field, 2-D or 3-D), radius-3 periodic padding."""
+    """Plan of the fused substep of a model (MODEL_MHD8, MODEL_MHD_FULL: 8
+    fields, 3-D; MODEL_ADVDIFF: 1 field, 2-D or 3-D), radius-3 periodic
+    padding. For MODEL_MHD_FULL, cs2 is cs0^2 and mhd overrides
+    MHD_FULL_DEFAULTS."""
 
     def __init__(self, model, dims, precision=PREC_F64, ds=None, nu=1e-3, eta=1e-3, cs2=1.0,
-                 adv=(0.0, 0.0, 0.0), block=None, variant=0, row_pitch=0, x_offset=0):
+                 adv=(0.0, 0.0, 0.0), block=None, variant=0, row_pitch=0, x_offset=0,
+                 mhd=None):
         import math
         self.model = model
         self.dims = tuple(int(v) for v in dims)
@@ -342,6 +351,11 @@ class RkPlan:
         self.variant = int(variant)
         d.row_pitch = int(row_pitch)
         d.x_offset = int(x_offset)
+        unknown = set(mhd or {}) - set(MHD_FULL_DEFAULTS)
+        if unknown:
+            raise ValueError("unknown MHD constants %s" % sorted(unknown))
+        for k, v in dict(MHD_FULL_DEFAULTS, **(mhd or {})).items():
+            setattr(d, k, float(v))
         self.x_offset = int(x_offset) or 3
         self.row_pitch = int(row_pitch) or (self.x_offset + self.dims[0] + 3)
         L = lib()

@@ -38,7 +38,8 @@ struct RkPlan {
     Geo g{};
     FdWeights fd{};
     double inv_ds[3] = {1, 1, 1};
-    double nu = 0, eta = 0, cs2 = 0, adv[3] = {0, 0, 0};
+    double nu = 0, adv[3] = {0, 0, 0}; // ADVDIFF
+    MhdParams mhd{};                     // MHD8 / MHD_FULL
     int variant = STENCIL_RK_VARIANT_CACHED;
     int bx = 64, by = 4, bz = 1; // CACHED: lanes; LDS: brick
     size_t store_size = 8, reg_size = 8; // bytes per element of f and of w

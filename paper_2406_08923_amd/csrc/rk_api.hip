@@ -73,19 +73,17 @@ int launch_substep(const stencil_plan_s *p, const stencil_fields *f, int sub, do
     }
     a.dt = dt;
     a.nu = P.nu;
-    a.eta = P.eta;
-    a.cs2 = P.cs2;
+    a.mhd = P.mhd;
     a.fd = P.fd;
     a.stage = sub;
     a.fuse = 1;
     a.phases = -1;
-    if (P.model == STENCIL_MODEL_MHD8 && P.variant == STENCIL_RK_VARIANT_LDS)
-        return launch_rk_mhd8_lds(P.policy, a, P.bx, P.by, P.bz, s);
-    if (P.model == STENCIL_MODEL_ADVDIFF && P.variant == STENCIL_RK_VARIANT_LDS)
-        return launch_rk_advdiff3_zm(P.policy, a, P.bz, s);
-    if (P.model == STENCIL_MODEL_MHD8)
-        return launch_rk_mhd8(P.policy, a, P.bx, P.by, s);
-    return launch_rk_advdiff(P.policy, a, P.bx, P.by, s);
+    if (P.model == STENCIL_MODEL_ADVDIFF)
+        return P.variant == STENCIL_RK_VARIANT_LDS ? launch_rk_advdiff3_zm(P.policy, a, P.bz, s)
+                                                   : launch_rk_advdiff(P.policy, a, P.bx, P.by, s);
+    if (P.variant == STENCIL_RK_VARIANT_LDS)
+        return launch_rk_mhd8_lds(P.model, P.policy, a, P.bx, P.by, P.bz, s);
+    return launch_rk_mhd8(P.model, P.policy, a, P.bx, P.by, s);
 }
 
 int check_fields(const stencil_plan_s *p, const stencil_fields *f, int sub)
@@ -130,10 +128,12 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     if (!d || !out)
         return fail(STENCIL_EINVAL, "NULL descriptor or output");
     *out = nullptr;
-    if (d->model != STENCIL_MODEL_MHD8 && d->model != STENCIL_MODEL_ADVDIFF)
+    if (d->model != STENCIL_MODEL_MHD8 && d->model != STENCIL_MODEL_ADVDIFF &&
+        d->model != STENCIL_MODEL_MHD_FULL)
         return fail(STENCIL_EINVAL, "unknown model %d", d->model);
-    if (d->model == STENCIL_MODEL_MHD8 && d->ndim != 3)
-        return fail(STENCIL_EINVAL, "MHD8 is three-dimensional");
+    const bool mhd = d->model != STENCIL_MODEL_ADVDIFF;
+    if (mhd && d->ndim != 3)
+        return fail(STENCIL_EINVAL, "the MHD models are three-dimensional");
     if (d->model == STENCIL_MODEL_ADVDIFF && d->ndim != 2 && d->ndim != 3)
         return fail(STENCIL_EINVAL, "ADVDIFF needs ndim 2 or 3");
     if (d->precision < STENCIL_PREC_F64 || d->precision > STENCIL_PREC_BF16_ONLY)
@@ -147,6 +147,16 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     for (double v : prm)
         if (!std::isfinite(v))
             return fail(STENCIL_EINVAL, "non-finite model parameter");
+    if (d->model == STENCIL_MODEL_MHD_FULL) {
+        const double full[] = {d->zeta, d->mu0, d->gamma, d->cp, d->lnrho0, d->K, d->heat,
+                               d->cool};
+        for (double v : full)
+            if (!std::isfinite(v))
+                return fail(STENCIL_EINVAL, "non-finite model parameter");
+        if (!(d->mu0 > 0.0) || !(d->cp > 0.0) || !(d->gamma > 1.0) || !(d->cs2 > 0.0))
+            return fail(STENCIL_EINVAL,
+                        "MHD_FULL needs mu0 > 0, cp > 0, gamma > 1 and cs2 (cs0^2) > 0");
+    }
     const int ox = d->x_offset ? d->x_offset : 3;
     const int64_t min_pitch = (int64_t)ox + d->dims[0] + 3;
     if (d->x_offset < 0 || d->row_pitch < 0 || ox < 3 || ox > (1 << 20))
@@ -159,14 +169,13 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     if (d->variant == STENCIL_RK_VARIANT_LDS && d->model == STENCIL_MODEL_ADVDIFF &&
         d->ndim != 3)
         return fail(STENCIL_EUNSUPPORTED, "the staged advection kernel is 3-D");
-    // AUTO: LDS bricks for MHD8, the z march for 3-D advection grids of at
+    // AUTO: LDS bricks for the MHD models, the z march for 3-D advection grids of at
     // least ZM_MIN_POINTS points (the rule the batched job kernel applies),
     // the cached per-point kernel otherwise
     long long npts = 1;
     for (int a = 0; a < d->ndim && a < 3; ++a) npts *= d->dims[a];
     const int variant = d->variant != STENCIL_RK_VARIANT_AUTO ? d->variant
-                        : (d->model == STENCIL_MODEL_MHD8 ||
-                           (d->ndim == 3 && npts >= ZM_MIN_POINTS))
+                        : (mhd || (d->ndim == 3 && npts >= ZM_MIN_POINTS))
                             ? STENCIL_RK_VARIANT_LDS
                             : STENCIL_RK_VARIANT_CACHED;
     int bx, by, bz;
@@ -214,7 +223,7 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     RkPlan &P = p->rk;
     P.model = d->model;
     P.policy = d->precision;
-    P.nf = d->model == STENCIL_MODEL_MHD8 ? 8 : 1;
+    P.nf = mhd ? 8 : 1;
     P.g = make_geo(d->ndim, d->dims, 3, d->row_pitch ? d->row_pitch : (int)min_pitch, ox);
     double w1[7], w2[7];
     stencil_fd_weights(1, 3, w1);
@@ -229,8 +238,19 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
         P.adv[a] = a < d->ndim ? d->adv[a] : 0.0;
     }
     P.nu = d->nu;
-    P.eta = d->eta;
-    P.cs2 = d->cs2;
+    P.mhd.nu = d->nu;
+    P.mhd.eta = d->eta;
+    P.mhd.cs2 = d->cs2;
+    if (d->model == STENCIL_MODEL_MHD_FULL) {
+        P.mhd.zeta = d->zeta;
+        P.mhd.mu0 = d->mu0;
+        P.mhd.gamma = d->gamma;
+        P.mhd.cp = d->cp;
+        P.mhd.lnrho0 = d->lnrho0;
+        P.mhd.K = d->K;
+        P.mhd.heat = d->heat;
+        P.mhd.cool = d->cool;
+    }
     P.variant = variant;
     P.bx = bx;
     P.by = by;

@@ -11,6 +11,7 @@
 // weighted four-point differences. The periodic images of each output are
 // written by the kernel itself, so no halo pass follows.
 #include "advdiff_zm.hpp"
+#include "mhd_phi.hpp"
 #include "rk_point.hpp"
 
 namespace stn {
@@ -108,8 +109,8 @@ __device__ __forceinline__ void scalar_bank(const Buf &fb, uint32_t vo, uint32_t
 // Field order (Table A1): lnrho, u_x, u_y, u_z, s, A_x, A_y, A_z. The bank is
 // evaluated field group by field group (A, then u, then the scalars) and each
 // group is reduced at once to the quantities phi needs, so few values stay
-// live at a time.
-template <typename S, typename W, typename C, bool MASTER>
+// live at a time. MODEL selects phi (mhd_phi.hpp).
+template <typename S, typename W, typename C, bool MASTER, int MODEL>
 __global__ void __launch_bounds__(256) k_rk_mhd8(RkArgs a)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -134,61 +135,34 @@ __global__ void __launch_bounds__(256) k_rk_mhd8(RkArgs a)
     // argument that is always all-ones: the branches split the kernel into
     // basic blocks, so no scheduler hoists the loads of a later group above an
     // earlier one (which would keep hundreds of values live at once).
-    // gamma, magnetic potential: B = curl A, j = grad(div A) - lap A
-    C vA[3] = {}, B[3] = {}, J[3] = {}, lapA[3] = {};
+    MhdBank<C> k{};
+    // gamma, magnetic potential: B = curl A, J = grad(div A) - lap A
     if (a.phases & 1) {
         C dA[3][3], gdivA[3];
-        vector_bank<S, C>(fb + 5, vo, c, st, a.fd, ids, vA, dA, lapA, gdivA);
-        B[0] = dA[1][2] - dA[2][1];
-        B[1] = dA[2][0] - dA[0][2];
-        B[2] = dA[0][1] - dA[1][0];
+        vector_bank<S, C>(fb + 5, vo, c, st, a.fd, ids, k.A, dA, k.lapA, gdivA);
+        k.B[0] = dA[1][2] - dA[2][1];
+        k.B[1] = dA[2][0] - dA[0][2];
+        k.B[2] = dA[0][1] - dA[1][0];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-            J[i] = gdivA[i] - lapA[i];
+            k.J[i] = gdivA[i] - k.lapA[i];
     }
     // gamma, velocity
-    C u[3] = {}, du[3][3] = {}, lapu[3] = {}, gdivu[3] = {};
     if (a.phases & 2)
-        vector_bank<S, C>(fb + 1, vo, c, st, a.fd, ids, u, du, lapu, gdivu);
+        vector_bank<S, C>(fb + 1, vo, c, st, a.fd, ids, k.u, k.du, k.lapu, k.gdivu);
     // gamma, log density and entropy
-    C vl = 0, vs = 0, gl[3] = {}, gs[3] = {}, lapl = 0, laps = 0;
     if (a.phases & 4)
-        scalar_bank<S, C>(fb[0], vo, c, st, a.fd, ids, vl, gl, lapl);
+        scalar_bank<S, C>(fb[0], vo, c, st, a.fd, ids, k.l, k.gl, k.lapl);
     if (a.phases & 8)
-        scalar_bank<S, C>(fb[4], vo, c, st, a.fd, ids, vs, gs, laps);
+        scalar_bank<S, C>(fb[4], vo, c, st, a.fd, ids, k.s, k.gs, k.laps);
 
     // phi: the 8-field right-hand side
-    const C nu = C(a.nu), eta = C(a.eta), cs2 = C(a.cs2);
-    const C divu = du[0][0] + du[1][1] + du[2][2];
-    C Sm[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            Sm[i][j] = C(0.5) * (du[i][j] + du[j][i]) - (i == j ? divu / C(3) : C(0));
     C R[8];
-    R[0] = -(u[0] * gl[0] + u[1] * gl[1] + u[2] * gl[2]) - divu + nu * lapl;
-    const C jxB[3] = {J[1] * B[2] - J[2] * B[1], J[2] * B[0] - J[0] * B[2], J[0] * B[1] - J[1] * B[0]};
-    const C uxB[3] = {u[1] * B[2] - u[2] * B[1], u[2] * B[0] - u[0] * B[2], u[0] * B[1] - u[1] * B[0]};
-    C SS = 0;
+    mhd_phi<MODEL, C>(k, a.mhd, R);
+    const C val[8] = {k.l, k.u[0], k.u[1], k.u[2], k.s, k.A[0], k.A[1], k.A[2]};
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const C adv = u[0] * du[0][i] + u[1] * du[1][i] + u[2] * du[2][i];
-        const C Sgl = Sm[i][0] * gl[0] + Sm[i][1] * gl[1] + Sm[i][2] * gl[2];
-        R[1 + i] = -adv - cs2 * (gs[i] + gl[i]) + jxB[i] +
-                   nu * (lapu[i] + gdivu[i] / C(3) + C(2) * Sgl);
-        SS += Sm[i][0] * Sm[i][0] + Sm[i][1] * Sm[i][1] + Sm[i][2] * Sm[i][2];
-    }
-    R[4] = -(u[0] * gs[0] + u[1] * gs[1] + u[2] * gs[2]) + nu * laps +
-           eta * (J[0] * J[0] + J[1] * J[1] + J[2] * J[2]) + C(2) * nu * SS;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        R[5 + i] = uxB[i] + eta * lapA[i];
-
-    const C val[8] = {vl, u[0], u[1], u[2], vs, vA[0], vA[1], vA[2]};
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-        rk_update<S, W, C, MASTER>(point_io(a, k), g, p, x, y, z, R[k], val[k]);
+    for (int q = 0; q < 8; ++q)
+        rk_update<S, W, C, MASTER>(point_io(a, q), g, p, x, y, z, R[q], val[q]);
 }
 
 // Scalar advection-diffusion R = -c.grad f + nu lap f, NDIM = 2 or 3.
@@ -230,16 +204,26 @@ template <typename K> int launch_grid(K kern, const RkArgs &a, int bx, int by, h
 }
 } // namespace
 
-int launch_rk_mhd8(int policy, const RkArgs &a, int bx, int by, hipStream_t s)
+namespace {
+template <int MODEL>
+int launch_mhd_model(int policy, const RkArgs &a, int bx, int by, hipStream_t s)
 {
     switch (policy) {
-    case POL_F64: return launch_grid(k_rk_mhd8<double, double, double, false>, a, bx, by, s, "rk_mhd8");
-    case POL_F32_MASTER64: return launch_grid(k_rk_mhd8<float, float, float, true>, a, bx, by, s, "rk_mhd8");
-    case POL_BF16_MASTER64: return launch_grid(k_rk_mhd8<bf16, float, float, true>, a, bx, by, s, "rk_mhd8");
-    case POL_F32_ONLY: return launch_grid(k_rk_mhd8<float, float, float, false>, a, bx, by, s, "rk_mhd8");
-    case POL_BF16_ONLY: return launch_grid(k_rk_mhd8<bf16, float, float, false>, a, bx, by, s, "rk_mhd8");
+    case POL_F64: return launch_grid(k_rk_mhd8<double, double, double, false, MODEL>, a, bx, by, s, "rk_mhd8");
+    case POL_F32_MASTER64: return launch_grid(k_rk_mhd8<float, float, float, true, MODEL>, a, bx, by, s, "rk_mhd8");
+    case POL_BF16_MASTER64: return launch_grid(k_rk_mhd8<bf16, float, float, true, MODEL>, a, bx, by, s, "rk_mhd8");
+    case POL_F32_ONLY: return launch_grid(k_rk_mhd8<float, float, float, false, MODEL>, a, bx, by, s, "rk_mhd8");
+    case POL_BF16_ONLY: return launch_grid(k_rk_mhd8<bf16, float, float, false, MODEL>, a, bx, by, s, "rk_mhd8");
     }
     return fail(STENCIL_EINVAL, "unknown precision policy %d", policy);
+}
+} // namespace
+
+int launch_rk_mhd8(int model, int policy, const RkArgs &a, int bx, int by, hipStream_t s)
+{
+    if (model == MHD_PROXY) return launch_mhd_model<MHD_PROXY>(policy, a, bx, by, s);
+    if (model == MHD_FULL) return launch_mhd_model<MHD_FULL>(policy, a, bx, by, s);
+    return fail(STENCIL_EINVAL, "rk_mhd8: unknown model %d", model);
 }
 
 namespace {

@@ -26,6 +26,14 @@ enum RkPolicy {
     POL_BF16_ONLY = 4,     // BF16 storage, FP32 register, no master (ablation)
 };
 
+// Constants of the MHD right-hand sides (the proxy reads nu, eta, cs2; the
+// full model all of them, with cs2 = cs0^2, the sound speed squared at s = 0,
+// lnrho = lnrho0).
+struct MhdParams {
+    double nu, eta, cs2;
+    double zeta, mu0, gamma, cp, lnrho0, K, heat, cool;
+};
+
 // Kernel arguments of one substep. Pointers are padded fields (radius 3).
 struct RkArgs {
     const void *fin[MAX_NF]; // stencil input, storage type
@@ -38,8 +46,9 @@ struct RkArgs {
     double alpha, beta, dt;
     double beta_all[3];
     double inv_ds[3];
-    double nu, eta, cs2;     // MHD8
+    double nu;               // ADVDIFF diffusivity
     double adv[3];           // ADVDIFF velocity
+    MhdParams mhd;           // MHD models
     FdWeights fd;
     int stage;
     int fuse;                // write periodic images
@@ -47,12 +56,14 @@ struct RkArgs {
                              // fused kernel into basic blocks (see k_rk_mhd8)
 };
 
-int launch_rk_mhd8(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
+// model: 0 = the 8-field proxy, 2 = the full non-ideal MHD equations
+int launch_rk_mhd8(int model, int policy, const RkArgs &a, int bx, int by, hipStream_t s);
 
 // LDS-brick variant of the MHD8 substep (rk_mhd8_lds.hip): bricks of
 // bx x by x bz output points, one of RK_BRICK_SHAPES
 #define RK_BRICK_SHAPES(X) X(16, 8, 4) X(16, 8, 8) X(32, 4, 4) X(8, 8, 8)
-int launch_rk_mhd8_lds(int policy, const RkArgs &a, int bx, int by, int bz, hipStream_t s);
+int launch_rk_mhd8_lds(int model, int policy, const RkArgs &a, int bx, int by, int bz,
+                       hipStream_t s);
 int launch_rk_advdiff(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
 // 3-D advection-diffusion substep as a z march (64 x 16 tiles, lz planes)
 int launch_rk_advdiff3_zm(int policy, const RkArgs &a, int lz, hipStream_t s);

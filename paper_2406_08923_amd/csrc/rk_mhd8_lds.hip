@@ -6,6 +6,7 @@
 // field's tile is in flight in registers while the current one is
 // differentiated, so a field costs one barrier. Every derivative tap is an LDS
 // read; HBM/L2 see each field once per brick (times the halo overhead).
+#include "mhd_phi.hpp"
 #include "rk_point.hpp"
 
 namespace stn {
@@ -148,8 +149,8 @@ __device__ __forceinline__ void scalar_field(const C *t, int c, const FdWeights 
 } // namespace
 
 // Field order (Table A1): lnrho, u_x, u_y, u_z, s, A_x, A_y, A_z; streamed as
-// A_x, A_y, A_z, u_x, u_y, u_z, lnrho, s.
-template <typename S, typename W, typename C, bool MASTER, int BX, int BY, int BZ>
+// A_x, A_y, A_z, u_x, u_y, u_z, lnrho, s. MODEL selects phi (mhd_phi.hpp).
+template <typename S, typename W, typename C, bool MASTER, int MODEL, int BX, int BY, int BZ>
 __global__ void __launch_bounds__(BX *BY *BZ)
     k_rk_mhd8_lds(RkArgs a, int gx, int gy, int gz)
 {
@@ -261,44 +262,31 @@ __global__ void __launch_bounds__(BX *BY *BZ)
     if (!live)
         return;
 
-    C gdivu[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        gdivu[i] = U.diag[i] + U.gdivm[i];
-    const C(&u)[3] = U.val;
-    const C(&du)[3][3] = U.d1;
-
-    // phi: the 8-field right-hand side
-    const C nu = C(a.nu), eta = C(a.eta), cs2 = C(a.cs2);
-    const C divu = du[0][0] + du[1][1] + du[2][2];
-    C Sm[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            Sm[i][j] = C(0.5) * (du[i][j] + du[j][i]) - (i == j ? divu / C(3) : C(0));
-    C R[8];
-    R[0] = -(u[0] * gl[0] + u[1] * gl[1] + u[2] * gl[2]) - divu + nu * lapl;
-    const C jxB[3] = {J[1] * Bf[2] - J[2] * Bf[1], J[2] * Bf[0] - J[0] * Bf[2],
-                      J[0] * Bf[1] - J[1] * Bf[0]};
-    const C uxB[3] = {u[1] * Bf[2] - u[2] * Bf[1], u[2] * Bf[0] - u[0] * Bf[2],
-                      u[0] * Bf[1] - u[1] * Bf[0]};
-    C SS = 0;
+    MhdBank<C> bank;
+    bank.l = vl;
+    bank.s = vs;
+    bank.lapl = lapl;
+    bank.laps = laps;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const C adv = u[0] * du[0][i] + u[1] * du[1][i] + u[2] * du[2][i];
-        const C Sgl = Sm[i][0] * gl[0] + Sm[i][1] * gl[1] + Sm[i][2] * gl[2];
-        R[1 + i] = -adv - cs2 * (gs[i] + gl[i]) + jxB[i] +
-                   nu * (U.lap[i] + gdivu[i] / C(3) + C(2) * Sgl);
-        SS += Sm[i][0] * Sm[i][0] + Sm[i][1] * Sm[i][1] + Sm[i][2] * Sm[i][2];
-    }
-    R[4] = -(u[0] * gs[0] + u[1] * gs[1] + u[2] * gs[2]) + nu * laps +
-           eta * (J[0] * J[0] + J[1] * J[1] + J[2] * J[2]) + C(2) * nu * SS;
+        bank.gl[i] = gl[i];
+        bank.gs[i] = gs[i];
+        bank.u[i] = U.val[i];
+        bank.lapu[i] = U.lap[i];
+        bank.gdivu[i] = U.diag[i] + U.gdivm[i];
+        bank.A[i] = A.val[i];
+        bank.B[i] = Bf[i];
+        bank.J[i] = J[i];
+        bank.lapA[i] = A.lap[i];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-        R[5 + i] = uxB[i] + eta * A.lap[i];
+        for (int j = 0; j < 3; ++j)
+            bank.du[i][j] = U.d1[i][j];
+    }
 
-    const C val[8] = {vl, u[0], u[1], u[2], vs, A.val[0], A.val[1], A.val[2]};
+    // phi: the 8-field right-hand side
+    C R[8];
+    mhd_phi<MODEL, C>(bank, a.mhd, R);
+    const C val[8] = {vl, bank.u[0], bank.u[1], bank.u[2], vs, bank.A[0], bank.A[1], bank.A[2]};
     const int64_t p = g.at(x, y, z);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -320,7 +308,7 @@ __global__ void __launch_bounds__(BX *BY *BZ)
 
 namespace {
 
-template <typename S, typename W, typename C, bool M, int BX, int BY, int BZ>
+template <typename S, typename W, typename C, bool M, int MODEL, int BX, int BY, int BZ>
 int launch_brick(const RkArgs &a, hipStream_t s)
 {
     const int gx = (a.g.nx + BX - 1) / BX, gy = (a.g.ny + BY - 1) / BY,
@@ -328,17 +316,17 @@ int launch_brick(const RkArgs &a, hipStream_t s)
     const int64_t total = (int64_t)gx * gy * gz;
     if (total > 0x7fffffff)
         return fail(STENCIL_EUNSUPPORTED, "rk_mhd8 (LDS): grid too large");
-    hipLaunchKernelGGL((k_rk_mhd8_lds<S, W, C, M, BX, BY, BZ>), dim3((unsigned)total),
+    hipLaunchKernelGGL((k_rk_mhd8_lds<S, W, C, M, MODEL, BX, BY, BZ>), dim3((unsigned)total),
                        dim3(BX * BY * BZ), 0, s, a, gx, gy, gz);
     return check_launch("rk_mhd8_lds");
 }
 
-template <typename S, typename W, typename C, bool M>
+template <typename S, typename W, typename C, bool M, int MODEL>
 int launch_brick_shape(const RkArgs &a, int bx, int by, int bz, hipStream_t s)
 {
 #define RK_BRICK(BX_, BY_, BZ_)                                                              \
     if (bx == BX_ && by == BY_ && bz == BZ_)                                                 \
-        return launch_brick<S, W, C, M, BX_, BY_, BZ_>(a, s);
+        return launch_brick<S, W, C, M, MODEL, BX_, BY_, BZ_>(a, s);
     RK_BRICK_SHAPES(RK_BRICK)
 #undef RK_BRICK
     return fail(STENCIL_EUNSUPPORTED, "rk_mhd8 (LDS): unsupported brick %dx%dx%d", bx, by, bz);
@@ -346,18 +334,27 @@ int launch_brick_shape(const RkArgs &a, int bx, int by, int bz, hipStream_t s)
 
 } // namespace
 
-int launch_rk_mhd8_lds(int policy, const RkArgs &a, int bx, int by, int bz, hipStream_t s)
+template <int MODEL>
+int launch_lds_model(int policy, const RkArgs &a, int bx, int by, int bz, hipStream_t s)
+{
+    switch (policy) {
+    case POL_F64: return launch_brick_shape<double, double, double, false, MODEL>(a, bx, by, bz, s);
+    case POL_F32_MASTER64: return launch_brick_shape<float, float, float, true, MODEL>(a, bx, by, bz, s);
+    case POL_BF16_MASTER64: return launch_brick_shape<bf16, float, float, true, MODEL>(a, bx, by, bz, s);
+    case POL_F32_ONLY: return launch_brick_shape<float, float, float, false, MODEL>(a, bx, by, bz, s);
+    case POL_BF16_ONLY: return launch_brick_shape<bf16, float, float, false, MODEL>(a, bx, by, bz, s);
+    }
+    return fail(STENCIL_EINVAL, "unknown precision policy %d", policy);
+}
+
+int launch_rk_mhd8_lds(int model, int policy, const RkArgs &a, int bx, int by, int bz,
+                       hipStream_t s)
 {
     if (uint64_t(padded_elems(a.g)) * 8 >= (uint64_t(1) << 32))
         return fail(STENCIL_EUNSUPPORTED, "rk_mhd8: arrays of 4 GiB or more are not supported");
-    switch (policy) {
-    case POL_F64: return launch_brick_shape<double, double, double, false>(a, bx, by, bz, s);
-    case POL_F32_MASTER64: return launch_brick_shape<float, float, float, true>(a, bx, by, bz, s);
-    case POL_BF16_MASTER64: return launch_brick_shape<bf16, float, float, true>(a, bx, by, bz, s);
-    case POL_F32_ONLY: return launch_brick_shape<float, float, float, false>(a, bx, by, bz, s);
-    case POL_BF16_ONLY: return launch_brick_shape<bf16, float, float, false>(a, bx, by, bz, s);
-    }
-    return fail(STENCIL_EINVAL, "unknown precision policy %d", policy);
+    if (model == MHD_PROXY) return launch_lds_model<MHD_PROXY>(policy, a, bx, by, bz, s);
+    if (model == MHD_FULL) return launch_lds_model<MHD_FULL>(policy, a, bx, by, bz, s);
+    return fail(STENCIL_EINVAL, "rk_mhd8 (LDS): unknown model %d", model);
 }
 
 } // namespace stn

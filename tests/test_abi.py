@@ -144,6 +144,10 @@ def _rk_rc(**kw):
     d.nu, d.eta, d.cs2 = 1e-3, 1e-3, 1.0
     d.block = (ctypes.c_int * 3)(*kw.get("block", (0, 0, 0)))
     d.variant = kw.get("variant", 0)
+    for k, v in dict(S.MHD_FULL_DEFAULTS, **kw.get("mhd", {})).items():
+        setattr(d, k, v)
+    if "cs2" in kw:
+        d.cs2 = kw["cs2"]
     h = ctypes.c_void_p()
     return S.lib().stencil_plan_rk(ctypes.byref(d), ctypes.byref(h))
 
@@ -158,6 +162,15 @@ def _rk_rc(**kw):
     (dict(variant=S.RK_CACHED, block=(64, 4, 2)), -1),      # one plane per workgroup
     (dict(variant=S.RK_CACHED, block=(48, 1, 0)), -1),      # not a multiple of 64 lanes
     (dict(ndim=2, dims=(16, 16, 1)), -1),                   # MHD8 is 3-D
+    (dict(model=3), -1),                                    # unknown model
+    (dict(model=S.MODEL_MHD_FULL, ndim=2, dims=(16, 16, 1)), -1),  # 3-D
+    (dict(model=S.MODEL_MHD_FULL, mhd=dict(mu0=0.0)), -1),  # closure constants
+    (dict(model=S.MODEL_MHD_FULL, mhd=dict(gamma=1.0)), -1),
+    (dict(model=S.MODEL_MHD_FULL, mhd=dict(cp=-1.0)), -1),
+    (dict(model=S.MODEL_MHD_FULL, cs2=0.0), -1),
+    (dict(model=S.MODEL_MHD_FULL, mhd=dict(K=float("nan"))), -1),
+    (dict(model=S.MODEL_MHD_FULL, mhd=dict(heat=float("inf"))), -1),
+    (dict(model=S.MODEL_MHD_FULL, variant=S.RK_LDS, block=(16, 8, 2)), -1),
 ])
 def test_rk_plan_rejects_bad_descriptors_without_a_device(kw, code):
     assert _rk_rc(**kw) == code
@@ -177,3 +190,15 @@ def test_rk_plan_rejects_bad_layouts_without_a_device(kw):
     d.x_offset = kw.get("x_offset", 0)
     h = ctypes.c_void_p()
     assert S.lib().stencil_plan_rk(ctypes.byref(d), ctypes.byref(h)) == -1
+
+
+def test_full_mhd_constants_are_ignored_by_the_proxy_model():
+    # the proxy plan reaches device selection (no GPU here) instead of
+    # rejecting closure constants it does not read
+    rc = _rk_rc(model=S.MODEL_MHD8, mhd=dict(mu0=0.0, gamma=0.5))
+    assert rc != -1
+
+
+def test_rk_plan_rejects_unknown_mhd_constant_names():
+    with pytest.raises(ValueError):
+        S.RkPlan(S.MODEL_MHD_FULL, (8, 8, 8), mhd=dict(kappa=1.0))
