@@ -202,9 +202,17 @@ def secondary(torch, S, W, inputs, args):
     ds = 2 * math.pi / nm
     dt = 0.1 * ds
     bytes_step = {S.PREC_F64: 640, S.PREC_F32_MASTER64: 480, S.PREC_BF16_MASTER64: 384}
-    for prec, name in ((S.PREC_F64, "f64"), (S.PREC_F32_MASTER64, "f32_master64"),
-                       (S.PREC_BF16_MASTER64, "bf16_master64")):
-        plan = S.RkPlan(S.MODEL_MHD8, (nm, nm, nm), prec)
+    # the full non-ideal model (Eq. A1-A4, ideal gas) with every closure term on
+    full = dict(zeta=3e-3, mu0=1.0, gamma=5.0 / 3.0, cp=1.0, lnrho0=0.0, K=4e-3, heat=2e-3,
+                cool=5e-4)
+    for model, mname, prec, name in (
+            (S.MODEL_MHD8, "mhd8", S.PREC_F64, "f64"),
+            (S.MODEL_MHD8, "mhd8", S.PREC_F32_MASTER64, "f32_master64"),
+            (S.MODEL_MHD8, "mhd8", S.PREC_BF16_MASTER64, "bf16_master64"),
+            (S.MODEL_MHD_FULL, "mhd_full", S.PREC_F64, "f64"),
+            (S.MODEL_MHD_FULL, "mhd_full", S.PREC_F32_MASTER64, "f32_master64")):
+        plan = S.RkPlan(model, (nm, nm, nm), prec,
+                        mhd=full if model == S.MODEL_MHD_FULL else None)
         bufs = plan.alloc()
         for k in range(8):
             bufs["f_a"][k][3:nm + 3, 3:nm + 3, 3:nm + 3] = torch.from_numpy(f[k]).cuda().to(
@@ -215,7 +223,7 @@ def secondary(torch, S, W, inputs, args):
         ms = timed(torch, lambda: plan.run(bufs["f_a"], bufs["f_b"], bufs["w"], steps, dt,
                                            w2=bufs["w2"], f64=bufs["f64"]), 2, warm=1) / steps
         pts = nm ** 3
-        out["mhd8_%d_%s" % (nm, name)] = {
+        out["%s_%d_%s" % (mname, nm, name)] = {
             "point_steps_per_s": pts / (ms * 1e-3),
             "point_substeps_per_s": 3 * pts / (ms * 1e-3),
             "ms_per_step": ms,
@@ -223,6 +231,8 @@ def secondary(torch, S, W, inputs, args):
         del bufs, plan
     if not args.no_precision_error:
         out["mhd8_mixed_precision_error_64"] = mixed_precision_error(torch, S, inputs)
+        out["mhd_full_mixed_precision_error_64"] = mixed_precision_error(
+            torch, S, inputs, model=S.MODEL_MHD_FULL, mhd=full)
     if args.serve_jobs > 0:
         out["serving"] = serving(torch, args.serve_jobs)
     return out
@@ -274,12 +284,15 @@ def radius_sweep(torch, S, inputs, n=1 << 24, radii=(1, 2, 4, 8, 16, 64, 256, 10
     return res
 
 
-def mixed_precision_error(torch, S, inputs, n=64, checkpoints=(1, 10, 100, 1000)):
+def mixed_precision_error(torch, S, inputs, n=64, checkpoints=(1, 10, 100, 1000), model=None,
+                          mhd=None):
     """Normwise relative error per field of the FP32- and BF16-storage states
     (FP64 master, and the no-master ablation) against the FP64 path after 1,
-    10, 100 and 1000 RK3 steps of the 8-field model at n^3 (Fourier-mode
-    initial data, amplitude 0.01, |k| <= 8; dt = 0.1 ds). The FP64 path is
-    the reference: it matches the CPU oracle to 1e-12 in the parity tests."""
+    10, 100 and 1000 RK3 steps of an 8-field model (default: the proxy) at
+    n^3 (Fourier-mode initial data, amplitude 0.01, |k| <= 8; dt = 0.1 ds).
+    The FP64 path is the reference: it matches the CPU oracle to 1e-12 in the
+    parity tests."""
+    model = S.MODEL_MHD8 if model is None else model
     import numpy as np
     dims = (n, n, n)
     dt = 0.1 * 2 * math.pi / n
@@ -288,7 +301,7 @@ def mixed_precision_error(torch, S, inputs, n=64, checkpoints=(1, 10, 100, 1000)
     for name, prec in (("f64", S.PREC_F64), ("f32_master64", S.PREC_F32_MASTER64),
                        ("bf16_master64", S.PREC_BF16_MASTER64), ("f32_only", S.PREC_F32_ONLY),
                        ("bf16_only", S.PREC_BF16_ONLY)):
-        plan = S.RkPlan(S.MODEL_MHD8, dims, prec)
+        plan = S.RkPlan(model, dims, prec, mhd=mhd)
         b = plan.alloc()
         for k in range(8):
             b["f_a"][k][3:n + 3, 3:n + 3, 3:n + 3] = torch.from_numpy(f[k]).cuda().to(

@@ -231,8 +231,8 @@ stencil_status stencil_fd_weights(int order, int radius, double *out);
  *           cooling, conduction or bulk viscosity.
  *  ADVDIFF: 1 field, 2-D or 3-D: R = -c.grad f + nu lap f.
  *  MHD_FULL: the same 8 fields, 3-D, the non-ideal MHD equations as written
- *           (Eq. A1-A4), closed by an ideal gas (the paper defers the
- *           closure to its reference [44]; this one is chosen here):
+ *           (Eq. A1-A4), closed by the ideal gas law (Sec. 3.3 names it
+ *           but does not write it out; this form is chosen here):
  *           rho = exp(lnrho), cs2 = cs0^2 exp(gamma s / c_p
  *           + (gamma - 1)(lnrho - lnrho0)) with cs0^2 = desc.cs2,
  *           T = cs2 / ((gamma - 1) c_p), j = (grad div A - lap A) / mu_0,

@@ -464,8 +464,8 @@ static void mhd8_rhs_point(const double *const *f, const long *P, long x, long y
         R[AX + a] = d.uxB[a] + eta * k.lapA[a];
 }
 
-/* The non-ideal MHD equations as written (Eq. A1-A4), with the closure the
- * paper leaves to its reference [44] chosen as an ideal gas:
+/* The non-ideal MHD equations as written (Eq. A1-A4), closed by the ideal gas
+ * law that Sec. 3.3 names without writing it out; the form taken here:
  *   rho = exp(lnrho)
  *   cs2 = cs0^2 exp(gamma s / c_p + (gamma - 1)(lnrho - lnrho0))
  *   T   = cs2 / ((gamma - 1) c_p)
