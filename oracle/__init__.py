@@ -30,6 +30,10 @@ LNRHO, UX, UY, UZ, SS, AX, AY, AZ = range(8)
 FILTER_MAX, FILTER_MIN, FILTER_MEDIAN = 1, 2, 3
 # derivative operator codes
 OP_X, OP_Y, OP_Z, OP_XX, OP_YY, OP_ZZ, OP_XY, OP_XZ, OP_YZ = range(9)
+# mixed derivatives from the diagonals of the plane (12 taps)
+OP_XY_DIAG, OP_XZ_DIAG, OP_YZ_DIAG = 9, 10, 11
+# mixed-derivative forms of the MHD derivative bank
+MIXED_TENSOR, MIXED_DIAG = "tensor", "diag"
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _lp = ctypes.POINTER(ctypes.c_long)
@@ -240,15 +244,26 @@ def _nf(model):
     return 1 if model == MODEL_ADVDIFF else 8
 
 
-def rhs(model, fields, ds, nu=1e-3, eta=1e-3, cs2=1.0, c=(0.0, 0.0, 0.0), mhd=None):
+def _code(model, mixed):
+    """Model code for the C oracle: the MHD models take the bank's mixed
+    derivatives from the tensor product (default) or the diagonals."""
+    if mixed == MIXED_TENSOR:
+        return model
+    if mixed == MIXED_DIAG and model != MODEL_ADVDIFF:
+        return model | 0x100
+    raise ValueError("mixed must be 'tensor' or 'diag' (MHD models only)")
+
+
+def rhs(model, fields, ds, nu=1e-3, eta=1e-3, cs2=1.0, c=(0.0, 0.0, 0.0), mhd=None,
+        mixed=MIXED_TENSOR):
     """Right-hand side R of the model over the interior; returns padded arrays
     (halo zero), one per field. For MODEL_MHD_FULL, cs2 is cs0^2 and mhd
-    overrides MHD_DEFAULTS."""
+    overrides MHD_DEFAULTS. mixed selects the bank's mixed derivatives."""
     nd, n = _dims(fields[0], 3)
     if len(fields) != _nf(model):
         raise ValueError("wrong number of fields for the model")
     R = [np.zeros_like(fields[0]) for _ in fields]
-    rc = lib().oracle_rhs(model, _ptrs(fields), _ptrs(R), nd, n, _d3(ds),
+    rc = lib().oracle_rhs(_code(model, mixed), _ptrs(fields), _ptrs(R), nd, n, _d3(ds),
                           _model_prm(model, nu, eta, cs2, c, mhd))
     if rc != 0:
         raise ValueError("bad model/dimension")
@@ -256,7 +271,7 @@ def rhs(model, fields, ds, nu=1e-3, eta=1e-3, cs2=1.0, c=(0.0, 0.0, 0.0), mhd=No
 
 
 def rk3_substep(model, stage, fin, w, ds, dt, nu=1e-3, eta=1e-3, cs2=1.0,
-                c=(0.0, 0.0, 0.0), mhd=None):
+                c=(0.0, 0.0, 0.0), mhd=None, mixed=MIXED_TENSOR):
     """One Williamson substep: updates the arrays in w in place and returns
     new padded f arrays with a periodic halo."""
     nd, n = _dims(fin[0], 3)
@@ -265,7 +280,8 @@ def rk3_substep(model, stage, fin, w, ds, dt, nu=1e-3, eta=1e-3, cs2=1.0,
     if any(a.shape != fin[0].shape for a in w):
         raise ValueError("w must match the fields' padded shape")
     fout = [np.zeros_like(a) for a in fin]
-    rc = lib().oracle_rk3_substep(model, stage, _ptrs(fin), _ptrs(w), _ptrs(fout), nd, n,
+    rc = lib().oracle_rk3_substep(_code(model, mixed), stage, _ptrs(fin), _ptrs(w),
+                                  _ptrs(fout), nd, n,
                                   _d3(ds), _model_prm(model, nu, eta, cs2, c, mhd), dt)
     if rc != 0:
         raise ValueError("bad model/dimension/stage")
@@ -284,7 +300,7 @@ def rk3_steps(model, f, ds, dt, steps, **kw):
 
 
 def rk3_substep_at(model, stage, fin, w_in, ds, dt, pts, nu=1e-3, eta=1e-3, cs2=1.0,
-                   c=(0.0, 0.0, 0.0), mhd=None):
+                   c=(0.0, 0.0, 0.0), mhd=None, mixed=MIXED_TENSOR):
     """Substep at listed interior points. w_in: (nf, count) old w (ignored at
     stage 0). Returns (w_out, f_out), each (nf, count)."""
     nd, n = _dims(fin[0], 3)
@@ -300,7 +316,8 @@ def rk3_substep_at(model, stage, fin, w_in, ds, dt, pts, nu=1e-3, eta=1e-3, cs2=
                                 dtype=np.float64)
     w_out = np.zeros((nf, cnt))
     f_out = np.zeros((nf, cnt))
-    rc = lib().oracle_rk3_substep_at(model, stage, _ptrs(fin), _ptr(w_in), nd, n, _d3(ds),
+    rc = lib().oracle_rk3_substep_at(_code(model, mixed), stage, _ptrs(fin), _ptr(w_in), nd, n,
+                                     _d3(ds),
                                      _model_prm(model, nu, eta, cs2, c, mhd), dt,
                                      pts.ctypes.data_as(_lp), cnt, _ptr(w_out), _ptr(f_out))
     if rc != 0:

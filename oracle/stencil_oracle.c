@@ -298,8 +298,31 @@ static double d11(const double *f, const long *P, long x, long y, long z, int a,
     return acc / (ds[a] * ds[b]);
 }
 
+/* Mixed derivative d_a d_b (a != b) from the two diagonals of the a-b plane
+ * through the point (12 nonzero taps). With h_a, h_b the spacings, the lines
+ * g(s) = f(p + s h_a e_a + s h_b e_b) and k(s) = f(p + s h_a e_a - s h_b e_b)
+ * satisfy g''(0) - k''(0) = 4 h_a h_b d_a d_b f; taking both second
+ * derivatives with the sixth-order weights C2 (unit step in s), the centre
+ * weights cancel, and the result is sixth-order accurate. */
+static double d11_diag(const double *f, const long *P, long x, long y, long z, int a, int b,
+                       const double *ds)
+{
+    double acc = 0.0;
+    for (int m = 1; m <= 3; ++m) {
+        long ax = m * (a == 0), ay = m * (a == 1), az = m * (a == 2);
+        long bx = m * (b == 0), by = m * (b == 1), bz = m * (b == 2);
+        double along = f[at(P, x + ax + bx, y + ay + by, z + az + bz)] +
+                       f[at(P, x - ax - bx, y - ay - by, z - az - bz)];
+        double across = f[at(P, x + ax - bx, y + ay - by, z + az - bz)] +
+                        f[at(P, x - ax + bx, y - ay + by, z - az + bz)];
+        acc += C2[m + 3] * (along - across);
+    }
+    return acc / (4.0 * ds[a] * ds[b]);
+}
+
 /* Operator codes for oracle_deriv: 0..2 first derivative along x, y, z;
- * 3..5 second derivative along x, y, z; 6 = xy, 7 = xz, 8 = yz mixed. */
+ * 3..5 second derivative along x, y, z; 6 = xy, 7 = xz, 8 = yz mixed (tensor
+ * product); 9 = xy, 10 = xz, 11 = yz mixed (diagonals). */
 static double deriv_op(const double *f, const long *P, long x, long y, long z, int op,
                        const double *ds)
 {
@@ -309,6 +332,9 @@ static double deriv_op(const double *f, const long *P, long x, long y, long z, i
     case 6: return d11(f, P, x, y, z, 0, 1, ds);
     case 7: return d11(f, P, x, y, z, 0, 2, ds);
     case 8: return d11(f, P, x, y, z, 1, 2, ds);
+    case 9: return d11_diag(f, P, x, y, z, 0, 1, ds);
+    case 10: return d11_diag(f, P, x, y, z, 0, 2, ds);
+    case 11: return d11_diag(f, P, x, y, z, 1, 2, ds);
     }
     return NAN;
 }
@@ -320,8 +346,8 @@ int oracle_deriv(const double *f, double *out, int ndim, const long *n, const do
                  int op)
 {
     const int r = 3;
-    int axes_needed = op < 3 ? op : op < 6 ? op - 3 : op == 6 ? 1 : 2;
-    if (op < 0 || op > 8 || axes_needed >= ndim)
+    int axes_needed = op < 3 ? op : op < 6 ? op - 3 : (op == 6 || op == 9) ? 1 : 2;
+    if (op < 0 || op > 11 || axes_needed >= ndim)
         return -1;
     long P[3] = {ext(ndim, 0, n, r), ext(ndim, 1, n, r), ext(ndim, 2, n, r)};
     long nz = ndim > 2 ? n[2] : 1, ny = ndim > 1 ? n[1] : 1;
@@ -354,7 +380,7 @@ typedef struct {
 } mhd_bank;
 
 static void mhd_bank_eval(const double *const *f, const long *P, long x, long y, long z,
-                          const double *ds, mhd_bank *k)
+                          const double *ds, int diag, mhd_bank *k)
 {
     size_t p = at(P, x, y, z);
     k->lapl = 0.0;
@@ -386,6 +412,9 @@ static void mhd_bank_eval(const double *const *f, const long *P, long x, long y,
             if (a == b) {
                 k->gdivu[a] += d2(f[UX + b], P, x, y, z, a, ds);
                 k->gdivA[a] += d2(f[AX + b], P, x, y, z, a, ds);
+            } else if (diag) {
+                k->gdivu[a] += d11_diag(f[UX + b], P, x, y, z, a, b, ds);
+                k->gdivA[a] += d11_diag(f[AX + b], P, x, y, z, a, b, ds);
             } else {
                 k->gdivu[a] += d11(f[UX + b], P, x, y, z, a, b, ds);
                 k->gdivA[a] += d11(f[AX + b], P, x, y, z, a, b, ds);
@@ -437,12 +466,12 @@ static void mhd_derive(const mhd_bank *k, mhd_derived *d)
  * with B = curl A and j = grad(div A) - lap A (curl curl A, mu_0 = 1).
  * f points at 8 radius-3 padded 3-D fields; (x, y, z) is a padded cell. */
 static void mhd8_rhs_point(const double *const *f, const long *P, long x, long y, long z,
-                           const double *ds, const double *prm, double *R)
+                           const double *ds, int diag, const double *prm, double *R)
 {
     const double nu = prm[0], eta = prm[1], cs2 = prm[2];
     mhd_bank k;
     mhd_derived d;
-    mhd_bank_eval(f, P, x, y, z, ds, &k);
+    mhd_bank_eval(f, P, x, y, z, ds, diag, &k);
     mhd_derive(&k, &d);
     double j[3];
     for (int a = 0; a < 3; ++a)
@@ -483,14 +512,14 @@ static void mhd8_rhs_point(const double *const *f, const long *P, long x, long y
  *   lap T  = T [(gamma / c_p) lap s + (gamma - 1) lap lnrho + |g|^2].
  * prm = {nu, eta, cs0^2, zeta, mu_0, gamma, c_p, lnrho0, K, H, C}. */
 static void mhdfull_rhs_point(const double *const *f, const long *P, long x, long y, long z,
-                              const double *ds, const double *prm, double *R)
+                              const double *ds, int diag, const double *prm, double *R)
 {
     const double nu = prm[0], eta = prm[1], cs02 = prm[2], zeta = prm[3], mu0 = prm[4];
     const double gamma = prm[5], cp = prm[6], lnrho0 = prm[7], K = prm[8], H = prm[9],
                  C = prm[10];
     mhd_bank k;
     mhd_derived d;
-    mhd_bank_eval(f, P, x, y, z, ds, &k);
+    mhd_bank_eval(f, P, x, y, z, ds, diag, &k);
     mhd_derive(&k, &d);
     size_t p = at(P, x, y, z);
     const double lnrho = f[LNRHO][p], s = f[SS][p];
@@ -537,23 +566,34 @@ static void advdiff_rhs_point(const double *const *f, const long *P, int ndim, l
 
 enum { MODEL_MHD8 = 0, MODEL_ADVDIFF = 1, MODEL_MHD_FULL = 2 };
 
-static int model_nf(int model) { return model == MODEL_ADVDIFF ? 1 : 8; }
+/* A model code may carry MIXED_DIAG (MHD models only): the bank then takes
+ * its mixed derivatives from the diagonals (d11_diag) instead of the tensor
+ * product (d11). */
+enum { MIXED_DIAG = 0x100 };
+
+static int model_nf(int model) { return (model & 0xff) == MODEL_ADVDIFF ? 1 : 8; }
 
 static void rhs_point(int model, const double *const *f, const long *P, int ndim, long x,
                       long y, long z, const double *ds, const double *prm, double *R)
 {
-    if (model == MODEL_MHD8)
-        mhd8_rhs_point(f, P, x, y, z, ds, prm, R);
-    else if (model == MODEL_MHD_FULL)
-        mhdfull_rhs_point(f, P, x, y, z, ds, prm, R);
+    const int base = model & 0xff, diag = (model & MIXED_DIAG) != 0;
+    if (base == MODEL_MHD8)
+        mhd8_rhs_point(f, P, x, y, z, ds, diag, prm, R);
+    else if (base == MODEL_MHD_FULL)
+        mhdfull_rhs_point(f, P, x, y, z, ds, diag, prm, R);
     else
         advdiff_rhs_point(f, P, ndim, x, y, z, ds, prm, R);
 }
 
 static int model_ok(int model, int ndim)
 {
-    return ((model == MODEL_MHD8 || model == MODEL_MHD_FULL) && ndim == 3) ||
-           (model == MODEL_ADVDIFF && (ndim == 2 || ndim == 3));
+    const int base = model & 0xff;
+    if (model & ~(0xff | MIXED_DIAG))
+        return 0;
+    if ((model & MIXED_DIAG) && base == MODEL_ADVDIFF)
+        return 0;
+    return ((base == MODEL_MHD8 || base == MODEL_MHD_FULL) && ndim == 3) ||
+           (base == MODEL_ADVDIFF && (ndim == 2 || ndim == 3));
 }
 
 /* R over the whole interior (R's halos untouched). Returns -1 for an invalid
