@@ -210,9 +210,13 @@ def secondary(torch, S, W, inputs, args):
             (S.MODEL_MHD8, "mhd8", S.PREC_F32_MASTER64, "f32_master64"),
             (S.MODEL_MHD8, "mhd8", S.PREC_BF16_MASTER64, "bf16_master64"),
             (S.MODEL_MHD_FULL, "mhd_full", S.PREC_F64, "f64"),
-            (S.MODEL_MHD_FULL, "mhd_full", S.PREC_F32_MASTER64, "f32_master64")):
+            (S.MODEL_MHD_FULL, "mhd_full", S.PREC_F32_MASTER64, "f32_master64"),
+            # 12-tap diagonal mixed derivatives instead of the tensor product
+            (S.MODEL_MHD8, "mhd8_diag", S.PREC_F64, "f64"),
+            (S.MODEL_MHD_FULL, "mhd_full_diag", S.PREC_F64, "f64")):
         plan = S.RkPlan(model, (nm, nm, nm), prec,
-                        mhd=full if model == S.MODEL_MHD_FULL else None)
+                        mhd=full if model == S.MODEL_MHD_FULL else None,
+                        mixed=S.MIXED_DIAGONAL if mname.endswith("_diag") else S.MIXED_TENSOR)
         bufs = plan.alloc()
         for k in range(8):
             bufs["f_a"][k][3:nm + 3, 3:nm + 3, 3:nm + 3] = torch.from_numpy(f[k]).cuda().to(

@@ -289,7 +289,19 @@ typedef struct stencil_rk_desc {
        gamma > 1, specific heat c_p > 0, reference log density lnrho0,
        conductivity K, heating H and cooling C (all finite) */
     double zeta, mu0, gamma, cp, lnrho0, K, heat, cool;
+    int mixed;      /* MHD8 and MHD_FULL: form of the bank's mixed derivatives
+                       d_a d_b (a != b) in grad(div u) and grad(div A),
+                       STENCIL_MIXED_*; must be 0 for ADVDIFF */
 } stencil_rk_desc;
+
+/* Mixed-derivative forms (the paper fixes sixth-order central differences,
+ * Sec. 3.3, but not the mixed stencil). TENSOR: the product of the two
+ * first-derivative stencils on the a-b plane (36 taps). DIAGONAL: the
+ * second-derivative stencil along the two diagonals of the plane,
+ * d_a d_b f = [D2 along (+a,+b) - D2 along (+a,-b)] / (4 h_a h_b) (12 taps,
+ * also sixth-order). The two differ by O(h^6). */
+#define STENCIL_MIXED_TENSOR 0
+#define STENCIL_MIXED_DIAGONAL 1
 
 /* Derivative-bank strategies (Sec. 4.1/4.4): AUTO = LDS for MHD8, MHD_FULL
  * and 3-D ADVDIFF grids of at least 2^20 points, CACHED otherwise. CACHED:

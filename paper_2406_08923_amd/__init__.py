@@ -273,6 +273,8 @@ class LinearPlan:
 # ---------------------------------------------------------------------------
 
 MODEL_MHD8, MODEL_ADVDIFF, MODEL_MHD_FULL = 0, 1, 2
+# mixed derivatives of the MHD banks: tensor product (36 taps) or diagonals (12)
+MIXED_TENSOR, MIXED_DIAGONAL = 0, 1
 # constants of MODEL_MHD_FULL beyond nu, eta and cs2 (= cs0^2); a plan's mhd
 # dict overrides any of them
 MHD_FULL_DEFAULTS = dict(zeta=0.0, mu0=1.0, gamma=5.0 / 3.0, cp=1.0, lnrho0=0.0, K=0.0,
@@ -291,7 +293,7 @@ class _RkDesc(ctypes.Structure):
                 ("variant", ctypes.c_int), ("row_pitch", ctypes.c_int),
                 ("x_offset", ctypes.c_int)] + [
                     (k, ctypes.c_double) for k in ("zeta", "mu0", "gamma", "cp", "lnrho0", "K",
-                                                   "heat", "cool")]
+                                                   "heat", "cool")] + [("mixed", ctypes.c_int)]
 
 
 class _Fields(ctypes.Structure):
@@ -324,11 +326,12 @@ class RkPlan:
     """Plan of the fused substep of a model (MODEL_MHD8, MODEL_MHD_FULL: 8
     fields, 3-D; MODEL_ADVDIFF: 1 field, 2-D or 3-D), radius-3 periodic
     padding. For MODEL_MHD_FULL, cs2 is cs0^2 and mhd overrides
-    MHD_FULL_DEFAULTS."""
+    MHD_FULL_DEFAULTS. mixed (MHD models): MIXED_TENSOR or MIXED_DIAGONAL
+    mixed derivatives in the bank."""
 
     def __init__(self, model, dims, precision=PREC_F64, ds=None, nu=1e-3, eta=1e-3, cs2=1.0,
                  adv=(0.0, 0.0, 0.0), block=None, variant=0, row_pitch=0, x_offset=0,
-                 mhd=None):
+                 mhd=None, mixed=MIXED_TENSOR):
         import math
         self.model = model
         self.dims = tuple(int(v) for v in dims)
@@ -356,6 +359,8 @@ class RkPlan:
             raise ValueError("unknown MHD constants %s" % sorted(unknown))
         for k, v in dict(MHD_FULL_DEFAULTS, **(mhd or {})).items():
             setattr(d, k, float(v))
+        d.mixed = int(mixed)
+        self.mixed = int(mixed)
         self.x_offset = int(x_offset) or 3
         self.row_pitch = int(row_pitch) or (self.x_offset + self.dims[0] + 3)
         L = lib()

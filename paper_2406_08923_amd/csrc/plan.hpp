@@ -35,6 +35,7 @@ struct LinearPlan {
 
 struct RkPlan {
     int model = 0, policy = 0, nf = 0;
+    int mixed = 0; // STENCIL_MIXED_*
     Geo g{};
     FdWeights fd{};
     double inv_ds[3] = {1, 1, 1};

@@ -82,8 +82,8 @@ int launch_substep(const stencil_plan_s *p, const stencil_fields *f, int sub, do
         return P.variant == STENCIL_RK_VARIANT_LDS ? launch_rk_advdiff3_zm(P.policy, a, P.bz, s)
                                                    : launch_rk_advdiff(P.policy, a, P.bx, P.by, s);
     if (P.variant == STENCIL_RK_VARIANT_LDS)
-        return launch_rk_mhd8_lds(P.model, P.policy, a, P.bx, P.by, P.bz, s);
-    return launch_rk_mhd8(P.model, P.policy, a, P.bx, P.by, s);
+        return launch_rk_mhd8_lds(P.model, P.mixed, P.policy, a, P.bx, P.by, P.bz, s);
+    return launch_rk_mhd8(P.model, P.mixed, P.policy, a, P.bx, P.by, s);
 }
 
 int check_fields(const stencil_plan_s *p, const stencil_fields *f, int sub)
@@ -134,6 +134,10 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     const bool mhd = d->model != STENCIL_MODEL_ADVDIFF;
     if (mhd && d->ndim != 3)
         return fail(STENCIL_EINVAL, "the MHD models are three-dimensional");
+    if (d->mixed != STENCIL_MIXED_TENSOR && d->mixed != STENCIL_MIXED_DIAGONAL)
+        return fail(STENCIL_EINVAL, "unknown mixed-derivative form %d", d->mixed);
+    if (!mhd && d->mixed != STENCIL_MIXED_TENSOR)
+        return fail(STENCIL_EINVAL, "ADVDIFF has no mixed derivatives (mixed must be 0)");
     if (d->model == STENCIL_MODEL_ADVDIFF && d->ndim != 2 && d->ndim != 3)
         return fail(STENCIL_EINVAL, "ADVDIFF needs ndim 2 or 3");
     if (d->precision < STENCIL_PREC_F64 || d->precision > STENCIL_PREC_BF16_ONLY)
@@ -224,6 +228,7 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     P.model = d->model;
     P.policy = d->precision;
     P.nf = mhd ? 8 : 1;
+    P.mixed = d->mixed;
     P.g = make_geo(d->ndim, d->dims, 3, d->row_pitch ? d->row_pitch : (int)min_pitch, ox);
     double w1[7], w2[7];
     stencil_fd_weights(1, 3, w1);

@@ -43,7 +43,19 @@ __device__ __forceinline__ PointIO point_io(const RkArgs &a, int k)
 // grad(div v)_a = sum_b d_a d_b v_b (pure second derivative for b == a, mixed
 // otherwise). Scheduling fences between the groups of loads keep the
 // compiler from hoisting all of them, which would exhaust the registers.
-template <typename S, typename C>
+// MIXED selects the mixed derivatives: the folded tensor product (36 taps)
+// or the diagonals (12 taps).
+template <typename S, typename C, int MIXED>
+__device__ __forceinline__ C dmix_form(const Buf &b, uint32_t vo, uint32_t c, uint32_t sa,
+                                       uint32_t sb, const FdWeights &w)
+{
+    if constexpr (MIXED == MIX_DIAG)
+        return dmix_diag<S, C>(b, vo, c, sa, sb, w);
+    else
+        return dmix<S, C>(b, vo, c, sa, sb, w);
+}
+
+template <typename S, typename C, int MIXED>
 __device__ __forceinline__ void vector_bank(const Buf *fb, uint32_t vo, uint32_t c,
                                             const uint32_t *st, const FdWeights &w,
                                             const C *ids, C *val, C (*d1)[3], C *lap, C *gdiv)
@@ -69,22 +81,22 @@ __device__ __forceinline__ void vector_bank(const Buf *fb, uint32_t vo, uint32_t
     gdiv[1] = diag[1];
     gdiv[2] = diag[2];
     C m;
-    m = dmix<S, C>(fb[1], vo, c, st[0], st[1], w); // d_x d_y v_y
+    m = dmix_form<S, C, MIXED>(fb[1], vo, c, st[0], st[1], w); // d_x d_y v_y
     gdiv[0] = fma(sxy, m, gdiv[0]);
     __builtin_amdgcn_sched_barrier(0);
-    m = dmix<S, C>(fb[2], vo, c, st[0], st[2], w); // d_x d_z v_z
+    m = dmix_form<S, C, MIXED>(fb[2], vo, c, st[0], st[2], w); // d_x d_z v_z
     gdiv[0] = fma(sxz, m, gdiv[0]);
     __builtin_amdgcn_sched_barrier(0);
-    m = dmix<S, C>(fb[0], vo, c, st[0], st[1], w); // d_x d_y v_x
+    m = dmix_form<S, C, MIXED>(fb[0], vo, c, st[0], st[1], w); // d_x d_y v_x
     gdiv[1] = fma(sxy, m, gdiv[1]);
     __builtin_amdgcn_sched_barrier(0);
-    m = dmix<S, C>(fb[2], vo, c, st[1], st[2], w); // d_y d_z v_z
+    m = dmix_form<S, C, MIXED>(fb[2], vo, c, st[1], st[2], w); // d_y d_z v_z
     gdiv[1] = fma(syz, m, gdiv[1]);
     __builtin_amdgcn_sched_barrier(0);
-    m = dmix<S, C>(fb[0], vo, c, st[0], st[2], w); // d_x d_z v_x
+    m = dmix_form<S, C, MIXED>(fb[0], vo, c, st[0], st[2], w); // d_x d_z v_x
     gdiv[2] = fma(sxz, m, gdiv[2]);
     __builtin_amdgcn_sched_barrier(0);
-    m = dmix<S, C>(fb[1], vo, c, st[1], st[2], w); // d_y d_z v_y
+    m = dmix_form<S, C, MIXED>(fb[1], vo, c, st[1], st[2], w); // d_y d_z v_y
     gdiv[2] = fma(syz, m, gdiv[2]);
     __builtin_amdgcn_sched_barrier(0);
 }
@@ -110,7 +122,7 @@ __device__ __forceinline__ void scalar_bank(const Buf &fb, uint32_t vo, uint32_t
 // evaluated field group by field group (A, then u, then the scalars) and each
 // group is reduced at once to the quantities phi needs, so few values stay
 // live at a time. MODEL selects phi (mhd_phi.hpp).
-template <typename S, typename W, typename C, bool MASTER, int MODEL>
+template <typename S, typename W, typename C, bool MASTER, int MODEL, int MIXED>
 __global__ void __launch_bounds__(256) k_rk_mhd8(RkArgs a)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -139,7 +151,7 @@ __global__ void __launch_bounds__(256) k_rk_mhd8(RkArgs a)
     // gamma, magnetic potential: B = curl A, J = grad(div A) - lap A
     if (a.phases & 1) {
         C dA[3][3], gdivA[3];
-        vector_bank<S, C>(fb + 5, vo, c, st, a.fd, ids, k.A, dA, k.lapA, gdivA);
+        vector_bank<S, C, MIXED>(fb + 5, vo, c, st, a.fd, ids, k.A, dA, k.lapA, gdivA);
         k.B[0] = dA[1][2] - dA[2][1];
         k.B[1] = dA[2][0] - dA[0][2];
         k.B[2] = dA[0][1] - dA[1][0];
@@ -149,7 +161,7 @@ __global__ void __launch_bounds__(256) k_rk_mhd8(RkArgs a)
     }
     // gamma, velocity
     if (a.phases & 2)
-        vector_bank<S, C>(fb + 1, vo, c, st, a.fd, ids, k.u, k.du, k.lapu, k.gdivu);
+        vector_bank<S, C, MIXED>(fb + 1, vo, c, st, a.fd, ids, k.u, k.du, k.lapu, k.gdivu);
     // gamma, log density and entropy
     if (a.phases & 4)
         scalar_bank<S, C>(fb[0], vo, c, st, a.fd, ids, k.l, k.gl, k.lapl);
@@ -205,25 +217,31 @@ template <typename K> int launch_grid(K kern, const RkArgs &a, int bx, int by, h
 } // namespace
 
 namespace {
-template <int MODEL>
+template <int MODEL, int MIXED>
 int launch_mhd_model(int policy, const RkArgs &a, int bx, int by, hipStream_t s)
 {
     switch (policy) {
-    case POL_F64: return launch_grid(k_rk_mhd8<double, double, double, false, MODEL>, a, bx, by, s, "rk_mhd8");
-    case POL_F32_MASTER64: return launch_grid(k_rk_mhd8<float, float, float, true, MODEL>, a, bx, by, s, "rk_mhd8");
-    case POL_BF16_MASTER64: return launch_grid(k_rk_mhd8<bf16, float, float, true, MODEL>, a, bx, by, s, "rk_mhd8");
-    case POL_F32_ONLY: return launch_grid(k_rk_mhd8<float, float, float, false, MODEL>, a, bx, by, s, "rk_mhd8");
-    case POL_BF16_ONLY: return launch_grid(k_rk_mhd8<bf16, float, float, false, MODEL>, a, bx, by, s, "rk_mhd8");
+    case POL_F64: return launch_grid(k_rk_mhd8<double, double, double, false, MODEL, MIXED>, a, bx, by, s, "rk_mhd8");
+    case POL_F32_MASTER64: return launch_grid(k_rk_mhd8<float, float, float, true, MODEL, MIXED>, a, bx, by, s, "rk_mhd8");
+    case POL_BF16_MASTER64: return launch_grid(k_rk_mhd8<bf16, float, float, true, MODEL, MIXED>, a, bx, by, s, "rk_mhd8");
+    case POL_F32_ONLY: return launch_grid(k_rk_mhd8<float, float, float, false, MODEL, MIXED>, a, bx, by, s, "rk_mhd8");
+    case POL_BF16_ONLY: return launch_grid(k_rk_mhd8<bf16, float, float, false, MODEL, MIXED>, a, bx, by, s, "rk_mhd8");
     }
     return fail(STENCIL_EINVAL, "unknown precision policy %d", policy);
 }
 } // namespace
 
-int launch_rk_mhd8(int model, int policy, const RkArgs &a, int bx, int by, hipStream_t s)
+int launch_rk_mhd8(int model, int mixed, int policy, const RkArgs &a, int bx, int by,
+                   hipStream_t s)
 {
-    if (model == MHD_PROXY) return launch_mhd_model<MHD_PROXY>(policy, a, bx, by, s);
-    if (model == MHD_FULL) return launch_mhd_model<MHD_FULL>(policy, a, bx, by, s);
-    return fail(STENCIL_EINVAL, "rk_mhd8: unknown model %d", model);
+#define RK_MODEL_MIXED(M_, X_)                                                               \
+    if (model == M_ && mixed == X_) return launch_mhd_model<M_, X_>(policy, a, bx, by, s);
+    RK_MODEL_MIXED(MHD_PROXY, MIX_TENSOR)
+    RK_MODEL_MIXED(MHD_PROXY, MIX_DIAG)
+    RK_MODEL_MIXED(MHD_FULL, MIX_TENSOR)
+    RK_MODEL_MIXED(MHD_FULL, MIX_DIAG)
+#undef RK_MODEL_MIXED
+    return fail(STENCIL_EINVAL, "rk_mhd8: unknown model %d / mixed form %d", model, mixed);
 }
 
 namespace {

@@ -56,14 +56,16 @@ struct RkArgs {
                              // fused kernel into basic blocks (see k_rk_mhd8)
 };
 
-// model: 0 = the 8-field proxy, 2 = the full non-ideal MHD equations
-int launch_rk_mhd8(int model, int policy, const RkArgs &a, int bx, int by, hipStream_t s);
+// model: 0 = the 8-field proxy, 2 = the full non-ideal MHD equations;
+// mixed: 0 = tensor-product mixed derivatives, 1 = diagonal (12 taps)
+int launch_rk_mhd8(int model, int mixed, int policy, const RkArgs &a, int bx, int by,
+                   hipStream_t s);
 
 // LDS-brick variant of the MHD8 substep (rk_mhd8_lds.hip): bricks of
 // bx x by x bz output points, one of RK_BRICK_SHAPES
 #define RK_BRICK_SHAPES(X) X(16, 8, 4) X(16, 8, 8) X(32, 4, 4) X(8, 8, 8)
-int launch_rk_mhd8_lds(int model, int policy, const RkArgs &a, int bx, int by, int bz,
-                       hipStream_t s);
+int launch_rk_mhd8_lds(int model, int mixed, int policy, const RkArgs &a, int bx, int by,
+                       int bz, hipStream_t s);
 int launch_rk_advdiff(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
 // 3-D advection-diffusion substep as a z march (64 x 16 tiles, lz planes)
 int launch_rk_advdiff3_zm(int policy, const RkArgs &a, int lz, hipStream_t s);

@@ -37,20 +37,20 @@ __device__ __forceinline__ void d12_lds(const C *t, int c, int st, const FdWeigh
          C(w.w2[3]) * (q3 + m3);
 }
 
-// d_a d_b (unit spacing) from LDS: the tensor product of the first-derivative
-// weights folded by antisymmetry into nine four-point differences
+// d_a d_b (unit spacing) from LDS along the two diagonals of the a-b plane:
+// second-derivative weights along (+a, +b) minus along (+a, -b) give
+// 4 d_a d_b; the centre cancels, 12 reads.
 template <typename C>
-__device__ __forceinline__ C dmix_lds(const C *t, int c, int sa, int sb, const FdWeights &w)
+__device__ __forceinline__ C dmix_diag_lds(const C *t, int c, int sa, int sb, const FdWeights &w)
 {
     C acc = 0;
 #pragma unroll
-    for (int i = 1; i <= 3; ++i)
-#pragma unroll
-        for (int j = 1; j <= 3; ++j) {
-            const int ia = i * sa, jb = j * sb;
-            const C q = (t[c + ia + jb] - t[c - ia + jb]) - (t[c + ia - jb] - t[c - ia - jb]);
-            acc = fma(C(w.w1[i - 1] * w.w1[j - 1]), q, acc);
-        }
+    for (int m = 1; m <= 3; ++m) {
+        const int ma = m * sa, mb = m * sb;
+        const C along = t[c + ma + mb] + t[c - ma - mb];
+        const C across = t[c + ma - mb] + t[c - ma + mb];
+        acc = fma(C(0.25 * w.w2[m]), along - across, acc);
+    }
     return acc;
 }
 
@@ -71,12 +71,14 @@ template <typename C> struct VecAcc {
 
 // One component b of a vector field from the tile: its d1/d2 along every
 // axis and its two mixed derivatives, scattered into the grad(div v) sums.
-// The mixed derivatives d_a d_b v_b (a != b) are taken separably: g = d_b v_b
-// (unit spacing) is evaluated once per cell of the brick widened by 3 along
-// both other axes and staged in LDS (gb), then d_a g is read from there:
-// about 15 LDS accesses per point for the pair instead of 72. The region
-// writes and reads are separated by a barrier every lane reaches.
-template <typename C, int BX, int BY, int BZ>
+// Tensor form (MIX_TENSOR): the mixed derivatives d_a d_b v_b (a != b) are
+// taken separably: g = d_b v_b (unit spacing) is evaluated once per cell of
+// the brick widened by 3 along both other axes and staged in LDS (gb), then
+// d_a g is read from there: about 15 LDS accesses per point for the pair
+// instead of 72. The region writes and reads are separated by a barrier every
+// lane reaches. Diagonal form (MIX_DIAG): 12 tile reads per mixed
+// derivative, no staging and no barrier (gb unused).
+template <typename C, int BX, int BY, int BZ, int MIXED>
 __device__ __forceinline__ void vec_component(const C *t, C *gb, int tid, int lx, int ly, int lz,
                                               int b, const FdWeights &w, const C *ids,
                                               VecAcc<C> &v)
@@ -101,6 +103,16 @@ __device__ __forceinline__ void vec_component(const C *t, C *gb, int tid, int lx
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) pin(v.d1[ax][b]);
 
+    if constexpr (MIXED == MIX_DIAG) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a == b) continue;
+            const C m = dmix_diag_lds<C>(t, c, st[a], st[b], w);
+            v.gdivm[a] = fma(ids[a] * ids[b], m, v.gdivm[a]);
+            pin(v.gdivm[a]);
+        }
+        return;
+    }
     // region: the brick widened by 3 on both sides of every axis except b
     const int RX = b == 0 ? BX : BX + 6, RY = b == 1 ? BY : BY + 6, RZ = b == 2 ? BZ : BZ + 6;
     const int ox = b == 0 ? 3 : 0, oy = b == 1 ? 3 : 0, oz = b == 2 ? 3 : 0; // tile offset
@@ -149,18 +161,21 @@ __device__ __forceinline__ void scalar_field(const C *t, int c, const FdWeights 
 } // namespace
 
 // Field order (Table A1): lnrho, u_x, u_y, u_z, s, A_x, A_y, A_z; streamed as
-// A_x, A_y, A_z, u_x, u_y, u_z, lnrho, s. MODEL selects phi (mhd_phi.hpp).
-template <typename S, typename W, typename C, bool MASTER, int MODEL, int BX, int BY, int BZ>
+// A_x, A_y, A_z, u_x, u_y, u_z, lnrho, s. MODEL selects phi (mhd_phi.hpp),
+// MIXED the form of the mixed derivatives.
+template <typename S, typename W, typename C, bool MASTER, int MODEL, int MIXED, int BX, int BY,
+          int BZ>
 __global__ void __launch_bounds__(BX *BY *BZ)
     k_rk_mhd8_lds(RkArgs a, int gx, int gy, int gz)
 {
     using B = Brick<BX, BY, BZ>;
     __shared__ C tile[2][B::TN];
-    // staging of d_b v_b on the brick widened along the other two axes (the
-    // largest of the three regions)
+    // tensor form: staging of d_b v_b on the brick widened along the other two
+    // axes (the largest of the three regions); the diagonal form needs none
     constexpr int G0 = BX * (BY + 6) * (BZ + 6), G1 = (BX + 6) * BY * (BZ + 6),
                   G2 = (BX + 6) * (BY + 6) * BZ;
-    constexpr int GN = G0 > G1 ? (G0 > G2 ? G0 : G2) : (G1 > G2 ? G1 : G2);
+    constexpr int GT = G0 > G1 ? (G0 > G2 ? G0 : G2) : (G1 > G2 ? G1 : G2);
+    constexpr int GN = MIXED == MIX_TENSOR ? GT : 1;
     __shared__ C gbuf[GN];
     constexpr uint32_t es = sizeof(S);
     const Geo &g = a.g;
@@ -219,15 +234,15 @@ __global__ void __launch_bounds__(BX *BY *BZ)
     RK_STORE(0);
     __syncthreads();
     RK_LOAD(6);
-    vec_component<C, BX, BY, BZ>(tile[0], gbuf, tid, lx, ly, lz, 0, a.fd, ids, A);
+    vec_component<C, BX, BY, BZ, MIXED>(tile[0], gbuf, tid, lx, ly, lz, 0, a.fd, ids, A);
     RK_STORE(1);
     __syncthreads();
     RK_LOAD(7);
-    vec_component<C, BX, BY, BZ>(tile[1], gbuf, tid, lx, ly, lz, 1, a.fd, ids, A);
+    vec_component<C, BX, BY, BZ, MIXED>(tile[1], gbuf, tid, lx, ly, lz, 1, a.fd, ids, A);
     RK_STORE(0);
     __syncthreads();
     RK_LOAD(1);
-    vec_component<C, BX, BY, BZ>(tile[0], gbuf, tid, lx, ly, lz, 2, a.fd, ids, A);
+    vec_component<C, BX, BY, BZ, MIXED>(tile[0], gbuf, tid, lx, ly, lz, 2, a.fd, ids, A);
     // magnetic field B = curl A, current j = grad(div A) - lap A: reduce the
     // A bank at once so its 21 values need not stay live
     C Bf[3] = {A.d1[1][2] - A.d1[2][1], A.d1[2][0] - A.d1[0][2], A.d1[0][1] - A.d1[1][0]};
@@ -241,15 +256,15 @@ __global__ void __launch_bounds__(BX *BY *BZ)
     RK_STORE(1);
     __syncthreads();
     RK_LOAD(2);
-    vec_component<C, BX, BY, BZ>(tile[1], gbuf, tid, lx, ly, lz, 0, a.fd, ids, U);
+    vec_component<C, BX, BY, BZ, MIXED>(tile[1], gbuf, tid, lx, ly, lz, 0, a.fd, ids, U);
     RK_STORE(0);
     __syncthreads();
     RK_LOAD(3);
-    vec_component<C, BX, BY, BZ>(tile[0], gbuf, tid, lx, ly, lz, 1, a.fd, ids, U);
+    vec_component<C, BX, BY, BZ, MIXED>(tile[0], gbuf, tid, lx, ly, lz, 1, a.fd, ids, U);
     RK_STORE(1);
     __syncthreads();
     RK_LOAD(0);
-    vec_component<C, BX, BY, BZ>(tile[1], gbuf, tid, lx, ly, lz, 2, a.fd, ids, U);
+    vec_component<C, BX, BY, BZ, MIXED>(tile[1], gbuf, tid, lx, ly, lz, 2, a.fd, ids, U);
     RK_STORE(0);
     __syncthreads();
     RK_LOAD(4);
@@ -308,7 +323,8 @@ __global__ void __launch_bounds__(BX *BY *BZ)
 
 namespace {
 
-template <typename S, typename W, typename C, bool M, int MODEL, int BX, int BY, int BZ>
+template <typename S, typename W, typename C, bool M, int MODEL, int MIXED, int BX, int BY,
+          int BZ>
 int launch_brick(const RkArgs &a, hipStream_t s)
 {
     const int gx = (a.g.nx + BX - 1) / BX, gy = (a.g.ny + BY - 1) / BY,
@@ -316,17 +332,17 @@ int launch_brick(const RkArgs &a, hipStream_t s)
     const int64_t total = (int64_t)gx * gy * gz;
     if (total > 0x7fffffff)
         return fail(STENCIL_EUNSUPPORTED, "rk_mhd8 (LDS): grid too large");
-    hipLaunchKernelGGL((k_rk_mhd8_lds<S, W, C, M, MODEL, BX, BY, BZ>), dim3((unsigned)total),
+    hipLaunchKernelGGL((k_rk_mhd8_lds<S, W, C, M, MODEL, MIXED, BX, BY, BZ>), dim3((unsigned)total),
                        dim3(BX * BY * BZ), 0, s, a, gx, gy, gz);
     return check_launch("rk_mhd8_lds");
 }
 
-template <typename S, typename W, typename C, bool M, int MODEL>
+template <typename S, typename W, typename C, bool M, int MODEL, int MIXED>
 int launch_brick_shape(const RkArgs &a, int bx, int by, int bz, hipStream_t s)
 {
 #define RK_BRICK(BX_, BY_, BZ_)                                                              \
     if (bx == BX_ && by == BY_ && bz == BZ_)                                                 \
-        return launch_brick<S, W, C, M, MODEL, BX_, BY_, BZ_>(a, s);
+        return launch_brick<S, W, C, M, MODEL, MIXED, BX_, BY_, BZ_>(a, s);
     RK_BRICK_SHAPES(RK_BRICK)
 #undef RK_BRICK
     return fail(STENCIL_EUNSUPPORTED, "rk_mhd8 (LDS): unsupported brick %dx%dx%d", bx, by, bz);
@@ -334,27 +350,32 @@ int launch_brick_shape(const RkArgs &a, int bx, int by, int bz, hipStream_t s)
 
 } // namespace
 
-template <int MODEL>
+template <int MODEL, int MIXED>
 int launch_lds_model(int policy, const RkArgs &a, int bx, int by, int bz, hipStream_t s)
 {
     switch (policy) {
-    case POL_F64: return launch_brick_shape<double, double, double, false, MODEL>(a, bx, by, bz, s);
-    case POL_F32_MASTER64: return launch_brick_shape<float, float, float, true, MODEL>(a, bx, by, bz, s);
-    case POL_BF16_MASTER64: return launch_brick_shape<bf16, float, float, true, MODEL>(a, bx, by, bz, s);
-    case POL_F32_ONLY: return launch_brick_shape<float, float, float, false, MODEL>(a, bx, by, bz, s);
-    case POL_BF16_ONLY: return launch_brick_shape<bf16, float, float, false, MODEL>(a, bx, by, bz, s);
+    case POL_F64: return launch_brick_shape<double, double, double, false, MODEL, MIXED>(a, bx, by, bz, s);
+    case POL_F32_MASTER64: return launch_brick_shape<float, float, float, true, MODEL, MIXED>(a, bx, by, bz, s);
+    case POL_BF16_MASTER64: return launch_brick_shape<bf16, float, float, true, MODEL, MIXED>(a, bx, by, bz, s);
+    case POL_F32_ONLY: return launch_brick_shape<float, float, float, false, MODEL, MIXED>(a, bx, by, bz, s);
+    case POL_BF16_ONLY: return launch_brick_shape<bf16, float, float, false, MODEL, MIXED>(a, bx, by, bz, s);
     }
     return fail(STENCIL_EINVAL, "unknown precision policy %d", policy);
 }
 
-int launch_rk_mhd8_lds(int model, int policy, const RkArgs &a, int bx, int by, int bz,
-                       hipStream_t s)
+int launch_rk_mhd8_lds(int model, int mixed, int policy, const RkArgs &a, int bx, int by,
+                       int bz, hipStream_t s)
 {
     if (uint64_t(padded_elems(a.g)) * 8 >= (uint64_t(1) << 32))
         return fail(STENCIL_EUNSUPPORTED, "rk_mhd8: arrays of 4 GiB or more are not supported");
-    if (model == MHD_PROXY) return launch_lds_model<MHD_PROXY>(policy, a, bx, by, bz, s);
-    if (model == MHD_FULL) return launch_lds_model<MHD_FULL>(policy, a, bx, by, bz, s);
-    return fail(STENCIL_EINVAL, "rk_mhd8 (LDS): unknown model %d", model);
+#define RK_MODEL_MIXED(M_, X_)                                                               \
+    if (model == M_ && mixed == X_) return launch_lds_model<M_, X_>(policy, a, bx, by, bz, s);
+    RK_MODEL_MIXED(MHD_PROXY, MIX_TENSOR)
+    RK_MODEL_MIXED(MHD_PROXY, MIX_DIAG)
+    RK_MODEL_MIXED(MHD_FULL, MIX_TENSOR)
+    RK_MODEL_MIXED(MHD_FULL, MIX_DIAG)
+#undef RK_MODEL_MIXED
+    return fail(STENCIL_EINVAL, "rk_mhd8 (LDS): unknown model %d / mixed form %d", model, mixed);
 }
 
 } // namespace stn

@@ -46,6 +46,27 @@ __device__ __forceinline__ C dmix(const Buf &b, uint32_t vo, uint32_t c, uint32_
     return acc;
 }
 
+// d_a d_b (unit spacing) from the two diagonals of the a-b plane: the
+// second-derivative weights taken along (+a, +b) and along (+a, -b); the
+// difference of the two is 4 d_a d_b, the centre cancels, 12 loads.
+template <typename S, typename C>
+__device__ __forceinline__ C dmix_diag(const Buf &b, uint32_t vo, uint32_t c, uint32_t sa,
+                                       uint32_t sb, const FdWeights &w)
+{
+    C acc = 0;
+#pragma unroll
+    for (int m = 1; m <= 3; ++m) {
+        const uint32_t ma = m * sa, mb = m * sb;
+        const C along = BufLd<S>::ld(b, vo, c + ma + mb) + BufLd<S>::ld(b, vo, c - ma - mb);
+        const C across = BufLd<S>::ld(b, vo, c + ma - mb) + BufLd<S>::ld(b, vo, c - ma + mb);
+        acc = fma(C(0.25 * w.w2[m]), along - across, acc);
+    }
+    return acc;
+}
+
+// Forms of the mixed derivatives in the MHD banks (STENCIL_MIXED_*).
+constexpr int MIX_TENSOR = 0, MIX_DIAG = 1;
+
 // Register update of the 2N scheme and the new state, per policy.
 //   non-master: w = alpha w + dt R (w not read at stage 0, not written at
 //               the last stage where it is dead), f_out = f_in + beta w

@@ -148,6 +148,7 @@ def _rk_rc(**kw):
         setattr(d, k, v)
     if "cs2" in kw:
         d.cs2 = kw["cs2"]
+    d.mixed = kw.get("mixed", 0)
     h = ctypes.c_void_p()
     return S.lib().stencil_plan_rk(ctypes.byref(d), ctypes.byref(h))
 
@@ -171,6 +172,9 @@ def _rk_rc(**kw):
     (dict(model=S.MODEL_MHD_FULL, mhd=dict(K=float("nan"))), -1),
     (dict(model=S.MODEL_MHD_FULL, mhd=dict(heat=float("inf"))), -1),
     (dict(model=S.MODEL_MHD_FULL, variant=S.RK_LDS, block=(16, 8, 2)), -1),
+    (dict(mixed=2), -1),                                    # unknown mixed form
+    (dict(mixed=-1), -1),
+    (dict(model=S.MODEL_ADVDIFF, mixed=S.MIXED_DIAGONAL), -1),  # no mixed terms
 ])
 def test_rk_plan_rejects_bad_descriptors_without_a_device(kw, code):
     assert _rk_rc(**kw) == code

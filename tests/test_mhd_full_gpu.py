@@ -234,3 +234,76 @@ def test_full_mhd_256_cubed_sampled_points():
         vw = gw[pts[:, 2] + 3, pts[:, 1] + 3, pts[:, 0] + 3]
         assert relerr(vf, f_at[k]) <= 1e-12, k
         assert relerr(vw, w_at[k]) <= 1e-12, k
+
+
+# diagonal (12-tap) mixed derivatives in the bank, both models, both banks
+
+DIAG_BANKS = [(S.RK_CACHED, None), (S.RK_LDS, (16, 8, 8)), (S.RK_LDS, (32, 4, 4)),
+              (S.RK_LDS, (16, 8, 4)), (S.RK_LDS, (8, 8, 8))]
+
+
+@pytest.mark.parametrize("model", [S.MODEL_MHD8, S.MODEL_MHD_FULL])
+@pytest.mark.parametrize("bank", range(len(DIAG_BANKS)))
+@pytest.mark.parametrize("stage", [0, 2])
+def test_diagonal_mixed_substep_f64(model, bank, stage):
+    n = (40, 24, 20)
+    ds = ds_of(n)
+    dt = 0.1 * min(ds)
+    f = fields(n, 21)
+    rng = np.random.default_rng(22)
+    variant, block = DIAG_BANKS[bank]
+    print("diagonal mixed: model %d stage %d bank %s %s" % (model, stage, variant, block),
+          flush=True)
+    mhd = MHD if model == S.MODEL_MHD_FULL else None
+    plan = S.RkPlan(model, n, S.PREC_F64, variant=variant, block=block, mhd=mhd,
+                    mixed=S.MIXED_DIAGONAL, **KW)
+    b = plan.alloc()
+    fin = [O.pad_periodic(v, 3) for v in f]
+    w0 = [rng.uniform(-1e-2, 1e-2, fin[0].shape) for _ in range(8)]
+    for k in range(8):
+        put(b["f_a"][k], fin[k])
+        put(b["w"][k], w0[k] if stage else np.full(fin[0].shape, np.nan))
+    plan.step(b["f_a"], b["f_b"], b["w"], stage, dt)
+    torch.cuda.synchronize()
+    w_ref = [a.copy() for a in w0]
+    ref = O.rk3_substep(model, stage, fin, w_ref, ds, dt, mhd=mhd, mixed=O.MIXED_DIAG, **KW)
+    ref_t = O.rk3_substep(model, stage, fin, [a.copy() for a in w0], ds, dt, mhd=mhd, **KW)
+    for k in range(8):
+        got = host(b["f_b"][k])
+        assert relerr(got, ref[k]) <= 1e-12, (stage, k, relerr(got, ref[k]))
+    # the two forms differ (u and A carry mixed terms), so the test can tell
+    assert max(relerr(ref[k], ref_t[k]) for k in range(8)) > 1e-9
+
+
+@pytest.mark.parametrize("n", [(3, 3, 3), (5, 4, 7), (17, 9, 33)])
+def test_diagonal_mixed_on_tiny_and_ragged_grids(n):
+    ds = ds_of(n)
+    dt = 0.05 * min(ds)
+    f = fields(n, 4, kmax=1)
+    for variant, block in ((S.RK_LDS, (16, 8, 4)), (S.RK_CACHED, None)):
+        plan = S.RkPlan(S.MODEL_MHD_FULL, n, S.PREC_F64, variant=variant, block=block, mhd=MHD,
+                        mixed=S.MIXED_DIAGONAL, **KW)
+        b = plan.alloc()
+        for k in range(8):
+            put(b["f_a"][k], O.pad_periodic(f[k], 3))
+        res = plan.run(b["f_a"], b["f_b"], b["w"], 2, dt)
+        ref = O.rk3_steps(O.MODEL_MHD_FULL, [O.pad_periodic(v, 3) for v in f], ds, dt, 2,
+                          mhd=MHD, mixed=O.MIXED_DIAG, **KW)
+        for k in range(8):
+            assert relerr(host(res[k]), ref[k]) <= 1e-12, (n, variant, k)
+
+
+@pytest.mark.parametrize("prec", [S.PREC_F32_MASTER64, S.PREC_BF16_MASTER64])
+def test_diagonal_mixed_lds_and_cached_agree_in_mixed_precision(prec):
+    n = (40, 24, 20)
+    ds = ds_of(n)
+    dt = 0.1 * min(ds)
+    f = fields(n, 9)
+    outs = []
+    for variant in (S.RK_CACHED, S.RK_LDS):
+        _, master = run_policy(n, prec, f, 2, dt, variant=variant, mhd=MHD,
+                               mixed=S.MIXED_DIAGONAL, **KW)
+        outs.append(master)
+    tol = 1e-5 if prec == S.PREC_F32_MASTER64 else 2.0 ** -8 * 0.18 * 1.5
+    for k in range(8):
+        assert relerr(outs[1][k], outs[0][k]) <= tol, (prec, k)
