@@ -45,6 +45,7 @@ constexpr int STAR_PF_SHIFT = 4;    // bits 4..7: prefetch depth (0 = default)
 constexpr int STAR_XW_SHIFT = 8;    // bits 8..11: tile width in waves (0 = 1)
 constexpr int STAR_T_SHIFT = 12;    // bits 12..15: iterations per launch (0/1 = 1, or 2)
 
+
 template <typename S> int launch_halo(S *a, const Geo &g, hipStream_t s);
 
 template <typename S>

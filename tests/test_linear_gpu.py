@@ -253,7 +253,7 @@ def test_apply_validation_on_device():
 # ---------------------------------------------------------------------------
 
 T2_TILES = [(8, 2, 32, 0x2101), (16, 1, 64, 0x2101), (16, 2, 16, 0x2101), (12, 2, 8, 0x2105),
-            (8, 2, 32, 0x2201), (8, 4, 16, 0x2101)]
+            (8, 2, 32, 0x2201), (8, 4, 16, 0x2101), (12, 2, 64, 0x2101), (8, 2, 32, 0x2105)]
 ONE_TILE = (4, 2, 8, 0x221)
 
 
@@ -277,7 +277,7 @@ def test_star_two_iterations_bitwise_equal_to_one_iteration_launches(tile, dtype
     g = diffusion_star_exact(3, 3, 0.0815)
     for iters in (2, 5, 6):
         got, plan, inner = run_star_iters(dims, r, g, dtype, tile, iters)
-        assert plan.tile[3] >> 12 == 2
+        assert (plan.tile[3] >> 12) & 15 == 2
         ref, _, _ = run_star_iters(dims, r, g, dtype, ONE_TILE, iters)
         assert np.array_equal(got, ref), (tile, iters)
         if dtype == S.F64:
@@ -287,10 +287,13 @@ def test_star_two_iterations_bitwise_equal_to_one_iteration_launches(tile, dtype
 
 
 @pytest.mark.parametrize("r", [1, 2, 4])
-def test_star_two_iterations_other_radii_random_taps(r):
+@pytest.mark.parametrize("tile", [(16, 2, 16, 0x2101), (12, 2, 16, 0x2101), (8, 2, 16, 0x2101)])
+def test_star_two_iterations_other_radii_random_taps(r, tile):
+    # 1024-lane (shifting-window march) and 768/512-lane (register rings for
+    # r <= 3) workgroups
     dims = (66, 29, 31)
     g = rand_star(r, 21) * 0.15
-    got, _, inner = run_star_iters(dims, r, g, S.F64, (16, 2, 16, 0x2101), 4)
+    got, _, inner = run_star_iters(dims, r, g, S.F64, tile, 4)
     ref, _, _ = run_star_iters(dims, r, g, S.F64, (4, 2, 8, 0x221), 4)
     assert np.array_equal(got, ref)
     want = oracle_apply(inner, r, g, 4)
@@ -299,10 +302,11 @@ def test_star_two_iterations_other_radii_random_taps(r):
 
 @pytest.mark.parametrize("dims,r", [((3, 3, 3), 3), ((5, 4, 7), 3), ((1, 1, 1), 1),
                                     ((130, 7, 5), 2)])
-def test_star_two_iterations_tiny_and_thin_grids(dims, r):
+@pytest.mark.parametrize("tile", [(8, 2, 32, 0x2101), (12, 2, 64, 0x2101)])
+def test_star_two_iterations_tiny_and_thin_grids(dims, r, tile):
     g = rand_star(r, 8) * 0.2
     for iters in (4, 5):  # two-iteration launches only / plus one single
-        got, _, inner = run_star_iters(dims, r, g, S.F64, (8, 2, 32, 0x2101), iters)
+        got, _, inner = run_star_iters(dims, r, g, S.F64, tile, iters)
         want = oracle_apply(inner, r, g, iters)
         assert_close(O.interior(got, r), O.interior(want, r), S.F64)
         assert np.array_equal(got, O.fill_periodic(got.copy(), r))
@@ -478,7 +482,8 @@ def test_star_512_cubed_two_iteration_launches(dtype):
     O.interior(pad, r)[...] = inner
     del inner
     outs = []
-    for tile in ((8, 2, 64, 0x2101), (4, 2, 32, 0x221)):
+    # two-iteration (shifting window; register rings), one-iteration
+    for tile in ((8, 2, 64, 0x2101), (4, 2, 32, 0x221), (12, 2, 64, 0x2101)):
         plan = S.LinearPlan(dims, r, W.diffusion_star(3, 3, s), dtype=dtype, variant=S.STAR3D,
                             tile=tile, row_pitch=pitch, x_offset=ox)
         a = plan.empty(0.0)
@@ -488,6 +493,7 @@ def test_star_512_cubed_two_iteration_launches(dtype):
         outs.append(host(plan.padded(res)))
         del a, b, res, plan
     assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[2], outs[1])
     if dtype == S.F64:
         O.fill_periodic(pad, r)
         cur = pad
