@@ -183,6 +183,29 @@ def secondary(torch, S, W, inputs, args):
                               "avg_launch_ms": per, "tile": list(p32.tile),
                               "layout": [p32.row_pitch, p32.x_offset]}
     del p32
+    # the secondary star of the same workload: 25 points, radius 4, FP64
+    p4, _, tot, per, nl = star_run(torch, S, W, inputs, n, 4, S.F64, 100, 4)
+    ipl = p4.iterations_per_launch if nl[1] == 0 else 1
+    out["star_%d_f64_r4" % n] = {"updates_per_s": n ** 3 / (tot / 100 * 1e-3),
+                                 "ms_per_iteration": tot / 100,
+                                 "iterations_per_launch": ipl,
+                                 "hbm_frac": ipl * 16 * n ** 3 / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "avg_launch_ms": per, "tile": list(p4.tile)}
+    del p4
+    # 1-D radius-1 smoother at 2^28 points (2 GiB per buffer): 10 chained
+    # iterations per call, autotuned plan (temporal blocking allowed)
+    N = 1 << 28
+    pl = S.LinearPlan((N,), 1, W.smoother3(), autotune=True)
+    a = pl.empty(0.0)
+    a[1:N + 1] = torch.from_numpy(inputs.uniform_field((N,), 1)).cuda()
+    b = pl.empty(0.0)
+    ms = timed(torch, lambda: pl.apply(a, b, 10), 3, warm=1)
+    out["line_2^28_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
+                                   "algorithmic_frac": 16 * N * 10 / (ms * 1e-3) / 1e9 /
+                                   HBM_PEAK_GBS,
+                                   "iterations_per_launch": pl.iterations_per_launch,
+                                   "variant": pl.variant, "tile": list(pl.tile)}
+    del a, b, pl
     # 1-D radius-1 smoother, 2^20 points, 10 chained iterations per call
     N = 1 << 20
     p1 = S.LinearPlan((N,), 1, W.smoother3(), autotune=True)
