@@ -56,25 +56,43 @@ __device__ __forceinline__ StarCoef<C, 3> advdiff_star(const FdWeights &fd, cons
 // 3-D job (padding 3, periodic images in the input's halo). Every lane of the
 // workgroup (ZM_TX x ZM_TY) must call it; it ends with a barrier, so the LDS
 // may be reused at once.
+//
+// Register rings: plane p of the input's z window lives in slot
+// (p - z0 + R) mod NR (NR = 2R + 1 + PF: the window plus PF planes in
+// flight); the x/y halo of plane p, and the old register values the RK update
+// of plane p reads, in slot (p - z0) mod NH (NH = PF + 1). The march is
+// unrolled by NR steps (a multiple of NH), so every slot index is a
+// compile-time constant: loads land in the registers they are read from and
+// no register is copied across the loop back-edge (such a copy would wait for
+// a load issued just before). The register values of plane z + PF are loaded
+// at step z with the rest of that plane, so the update does not wait for them.
 template <typename S, typename W, typename C, bool MASTER>
 __device__ __forceinline__ void advdiff3_zmarch(const void *fin_v, const PointIO &io, const Geo &g,
                                                 const StarCoef<C, 3> &cf, int x0, int y0, int z0,
                                                 int z1, ZmLds<C> &lds)
 {
     constexpr int R = ZM_R, NY = ZM_NY, PF = ZM_PF;
+    constexpr int NR = 2 * R + 1 + PF, NH = PF + 1;
+    static_assert(NR % NH == 0, "the unrolled march must cover whole halo rings");
     constexpr uint32_t es = sizeof(S);
     const S *fin = static_cast<const S *>(fin_v);
-    const Buf src = make_buf(fin, uint64_t(padded_elems(g)) * es);
+    const uint64_t n_el = uint64_t(padded_elems(g));
+    const Buf src = make_buf(fin, n_el * es);
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ZM_TX * ty;
 
     auto cl = [](int v, int n) { return min(max(v, -R), n + R - 1); };
-    auto col = [&](int xx, int yy) { return uint32_t(xx + g.ox + g.sy * (yy + g.ry)) * es; };
-    auto plane = [&](int zz) { return uint32_t(zz + g.rz) * uint32_t(g.sz) * es; };
+    auto cole = [&](int xx, int yy) { return uint32_t(xx + g.ox + g.sy * (yy + g.ry)); };
+    auto col = [&](int xx, int yy) { return cole(xx, yy) * es; };
+    auto plane_e = [&](int zz) { return uint32_t(zz + g.rz) * uint32_t(g.sz); };
+    auto plane = [&](int zz) { return plane_e(zz) * es; };
 
     const int x = x0 + tx;
-    uint32_t col_off[NY];
+    uint32_t col_off[NY], col_el[NY];
 #pragma unroll
-    for (int j = 0; j < NY; ++j) col_off[j] = col(cl(x, g.nx), cl(y0 + ty * NY + j, g.ny));
+    for (int j = 0; j < NY; ++j) {
+        col_el[j] = cole(cl(x, g.nx), cl(y0 + ty * NY + j, g.ny));
+        col_off[j] = col_el[j] * es;
+    }
     uint32_t hx_off[ZM_HX], hy_off[ZM_HY];
     int hx_slot[ZM_HX], hy_slot[ZM_HY];
 #pragma unroll
@@ -104,66 +122,98 @@ __device__ __forceinline__ void advdiff3_zmarch(const void *fin_v, const PointIO
         }
     }
 
-    C win[NY][2 * R + 1];
+    // which old values the update reads (uniform over the launch)
+    const bool rd_w = io.stage > 0, rd_m = MASTER && io.stage == 2;
+    const Buf wsrc = make_buf(rd_w ? io.wrd : fin_v, n_el * sizeof(W));
+    const Buf w1src = make_buf(rd_m ? io.w1 : fin_v, n_el * sizeof(W));
+    const Buf msrc = make_buf(rd_m ? (const void *)io.master : fin_v, n_el * sizeof(double));
+
+    C ring[NY][NR];
+    C hxr[NH][ZM_HX], hyr[NH][ZM_HY];
+    W wr[NH][NY], w1r[NH][NY];
+    double mr[NH][NY];
+    auto load_old = [&](int slot_dummy, int zz, W (&wv)[NY], W (&w1v)[NY], double (&mv)[NY]) {
+        (void)slot_dummy;
+#pragma unroll
+        for (int j = 0; j < NY; ++j) {
+            wv[j] = W(0);
+            w1v[j] = W(0);
+            mv[j] = 0.0;
+        }
+        if (rd_w) {
+#pragma unroll
+            for (int j = 0; j < NY; ++j)
+                wv[j] = W(BufLd<W>::ld(wsrc, col_el[j] * uint32_t(sizeof(W)),
+                                       plane_e(zz) * uint32_t(sizeof(W))));
+        }
+        if (rd_m) {
+#pragma unroll
+            for (int j = 0; j < NY; ++j) {
+                w1v[j] = W(BufLd<W>::ld(w1src, col_el[j] * uint32_t(sizeof(W)),
+                                        plane_e(zz) * uint32_t(sizeof(W))));
+                mv[j] = BufLd<double>::ld(msrc, col_el[j] * 8u, plane_e(zz) * 8u);
+            }
+        }
+    };
+    // planes z0 - R .. z0 + R - 1 (slots 0 .. 2R - 1), then the first PF
+    // planes ahead (clamped to the chunk: a clamped load is never used)
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k)
 #pragma unroll
         for (int j = 0; j < NY; ++j)
-            win[j][k + 1] = BufLd<S>::ld(src, col_off[j], plane(z0 - R + k));
-    C pre_w[PF][NY], pre_hx[PF][ZM_HX], pre_hy[PF][ZM_HY];
+            ring[j][k] = BufLd<S>::ld(src, col_off[j], plane(z0 - R + k));
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
         const int zq = min(z0 + q, z1 - 1);
 #pragma unroll
-        for (int j = 0; j < NY; ++j) pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zq + R));
+        for (int j = 0; j < NY; ++j) ring[j][2 * R + q] = BufLd<S>::ld(src, col_off[j], plane(zq + R));
 #pragma unroll
-        for (int k = 0; k < ZM_HX; ++k) pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zq));
+        for (int k = 0; k < ZM_HX; ++k) hxr[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zq));
 #pragma unroll
-        for (int k = 0; k < ZM_HY; ++k) pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zq));
+        for (int k = 0; k < ZM_HY; ++k) hyr[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zq));
+        load_old(q, zq, wr[q], w1r[q], mr[q]);
     }
 
-    for (int zb = z0; zb < z1; zb += PF) {
+    for (int zb = z0; zb < z1; zb += NR) {
 #pragma unroll
-        for (int q = 0; q < PF; ++q) {
+        for (int q = 0; q < NR; ++q) {
             const int z = zb + q;
             if (z >= z1)
                 break;
+#define RS(k_) ((q + R + (k_) + 2 * NR) % NR)
             const int b = (z - z0) & 1;
             C *lb = &lds[b][0][0];
 #pragma unroll
-            for (int j = 0; j < NY; ++j) {
-#pragma unroll
-                for (int k = 0; k < 2 * R; ++k) win[j][k] = win[j][k + 1];
-                win[j][2 * R] = pre_w[q][j];
-                lds[b][ty * NY + j + R][tx + R] = win[j][R];
-            }
+            for (int j = 0; j < NY; ++j) lds[b][ty * NY + j + R][tx + R] = ring[j][RS(0)];
 #pragma unroll
             for (int k = 0; k < ZM_HX; ++k)
-                if (hx_slot[k] >= 0) lb[hx_slot[k]] = pre_hx[q][k];
+                if (hx_slot[k] >= 0) lb[hx_slot[k]] = hxr[q % NH][k];
 #pragma unroll
             for (int k = 0; k < ZM_HY; ++k)
-                if (hy_slot[k] >= 0) lb[hy_slot[k]] = pre_hy[q][k];
+                if (hy_slot[k] >= 0) lb[hy_slot[k]] = hyr[q % NH][k];
             __syncthreads();
             {
+                // plane z + PF (clamped) into the slots freed by plane z - R - 1
                 const int zn = min(z + PF, z1 - 1);
 #pragma unroll
                 for (int j = 0; j < NY; ++j)
-                    pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+                    ring[j][RS(R + PF)] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
 #pragma unroll
                 for (int k = 0; k < ZM_HX; ++k)
-                    pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
+                    hxr[(q + PF) % NH][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
 #pragma unroll
                 for (int k = 0; k < ZM_HY; ++k)
-                    pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
+                    hyr[(q + PF) % NH][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
+                load_old(q, zn, wr[(q + PF) % NH], w1r[(q + PF) % NH], mr[(q + PF) % NH]);
             }
 #pragma unroll
             for (int j = 0; j < NY; ++j) {
                 const int row = ty * NY + j + R;
-                C acc = cf.c0 * win[j][R];
+                C acc = cf.c0 * ring[j][RS(0)];
 #pragma unroll
                 for (int m = 1; m <= R; ++m) {
-                    acc = fma(cf.zm[m - 1], win[j][R - m], acc);
-                    acc = fma(cf.zp[m - 1], win[j][R + m], acc);
+                    acc = fma(cf.zm[m - 1], ring[j][RS(-m)], acc);
+                    acc = fma(cf.zp[m - 1], ring[j][RS(m)], acc);
                 }
 #pragma unroll
                 for (int m = 1; m <= R; ++m) {
@@ -172,15 +222,20 @@ __device__ __forceinline__ void advdiff3_zmarch(const void *fin_v, const PointIO
                 }
 #pragma unroll
                 for (int m = 1; m <= R; ++m) {
-                    C vm = (j - m >= 0) ? win[(j - m >= 0) ? j - m : 0][R] : lds[b][row - m][tx + R];
-                    C vp = (j + m < NY) ? win[(j + m < NY) ? j + m : 0][R] : lds[b][row + m][tx + R];
+                    C vm = (j - m >= 0) ? ring[(j - m >= 0) ? j - m : 0][RS(0)]
+                                        : lds[b][row - m][tx + R];
+                    C vp = (j + m < NY) ? ring[(j + m < NY) ? j + m : 0][RS(0)]
+                                        : lds[b][row + m][tx + R];
                     acc = fma(cf.ym[m - 1], vm, acc);
                     acc = fma(cf.yp[m - 1], vp, acc);
                 }
                 const int y = y0 + ty * NY + j;
                 if (x < g.nx && y < g.ny)
-                    rk_update<S, W, C, MASTER>(io, g, g.at(x, y, z), x, y, z, acc, win[j][R]);
+                    rk_update_pre<S, W, C, MASTER>(io, g, g.at(x, y, z), x, y, z, acc,
+                                                   ring[j][RS(0)], wr[q % NH][j], w1r[q % NH][j],
+                                                   mr[q % NH][j]);
             }
+#undef RS
         }
     }
     __syncthreads();

@@ -85,18 +85,21 @@ struct PointIO {
     int fuse;
 };
 
+// The update with its reads already done: wold = the register (read when
+// stage > 0), w1v and mst = the first-stage register and the FP64 state
+// (read at the master policies' last stage); unused otherwise.
 template <typename S, typename W, typename C, bool MASTER>
-__device__ __forceinline__ void rk_update(const PointIO &io, const Geo &g, int64_t p, int x,
-                                          int y, int z, C R, C fc)
+__device__ __forceinline__ void rk_update_pre(const PointIO &io, const Geo &g, int64_t p, int x,
+                                              int y, int z, C R, C fc, W wold, W w1v, double mst)
 {
     const C dt = C(io.dt);
     C wn = dt * R;
     if (io.stage > 0)
-        wn = fma(C(io.alpha), C(static_cast<const W *>(io.wrd)[p]), wn);
+        wn = fma(C(io.alpha), C(wold), wn);
     if (MASTER && io.stage == 2) {
-        double f = io.master[p];
-        f = fma(io.beta_all[0], double(static_cast<const W *>(io.w1)[p]), f);
-        f = fma(io.beta_all[1], double(static_cast<const W *>(io.wrd)[p]), f);
+        double f = mst;
+        f = fma(io.beta_all[0], double(w1v), f);
+        f = fma(io.beta_all[1], double(wold), f);
         f = fma(io.beta_all[2], double(wn), f);
         io.master[p] = f;
         store_periodic(static_cast<S *>(io.fout), g, x, y, z, C(f), io.fuse != 0);
@@ -106,6 +109,17 @@ __device__ __forceinline__ void rk_update(const PointIO &io, const Geo &g, int64
         static_cast<W *>(io.wwr)[p] = W(wn);
     store_periodic(static_cast<S *>(io.fout), g, x, y, z, fma(C(io.beta), wn, fc),
                    io.fuse != 0);
+}
+
+template <typename S, typename W, typename C, bool MASTER>
+__device__ __forceinline__ void rk_update(const PointIO &io, const Geo &g, int64_t p, int x,
+                                          int y, int z, C R, C fc)
+{
+    const W wold = io.stage > 0 ? static_cast<const W *>(io.wrd)[p] : W(0);
+    const bool last = MASTER && io.stage == 2;
+    const W w1v = last ? static_cast<const W *>(io.w1)[p] : W(0);
+    const double mst = last ? io.master[p] : 0.0;
+    rk_update_pre<S, W, C, MASTER>(io, g, p, x, y, z, R, fc, wold, w1v, mst);
 }
 
 // Scalar advection-diffusion R = -c.grad f + nu lap f at interior point
