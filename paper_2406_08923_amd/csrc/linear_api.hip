@@ -322,15 +322,12 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
     return c;
 }
 
-// One-iteration star shape that measured fastest at 512^3: 128 x 8 tiles for
-// FP64, 64 x 16 for the narrower types.
+// One-iteration star shape that measured fastest at 512^3: 128 x 8 tiles,
+// 64 z planes per workgroup for FP64 and 32 for the narrower types.
 TuneChoice default_star1(const stencil_plan_s *p)
 {
-    if (p->lin.dtype == STENCIL_F64)
-        return {STENCIL_VARIANT_STAR3D, 4, 2, 32, STAR_FLAG_XCD | (2 << STAR_PF_SHIFT) |
-                                                      (2 << STAR_XW_SHIFT)};
-    return {STENCIL_VARIANT_STAR3D, 8, 2, 32, STAR_FLAG_XCD | (2 << STAR_PF_SHIFT) |
-                                                  (1 << STAR_XW_SHIFT)};
+    return {STENCIL_VARIANT_STAR3D, 4, 2, p->lin.dtype == STENCIL_F64 ? 64 : 32,
+            STAR_FLAG_XCD | (2 << STAR_PF_SHIFT) | (2 << STAR_XW_SHIFT)};
 }
 
 TuneChoice default_choice(const stencil_plan_s *p)

@@ -125,89 +125,180 @@ __global__ void __launch_bounds__(64 * XW * TY)
         }
     }
 
-    // z window: win[j][k] holds plane z - R + k of row j
-    C win[NY][2 * R + 1];
+    // Register-ring march where the halo ring (PF + 1 slots) divides the z
+    // ring (2R + 1 + PF slots), i.e. PF + 1 divides 2R (r = 3 with PF = 2):
+    // plane p lives in slot (p - z0 + R) mod NR of ring, its halo in slot
+    // (p - z0) mod NH; the march is unrolled by NR steps so every slot index
+    // is a compile-time constant, loads land in the registers they are read
+    // from and nothing is copied across the loop back-edge (such a copy
+    // would wait for a load issued just before). Other radii keep the
+    // shifting window below.
+    constexpr int NR = 2 * R + 1 + PF, NH = PF + 1;
+    if constexpr (NR % NH == 0) {
+        C ring[NY][NR];
+        C hxr[NH][SH::HX_PER], hyr[NH][SH::HY_PER];
 #pragma unroll
-    for (int k = 0; k < 2 * R; ++k)
+        for (int k = 0; k < 2 * R; ++k)
 #pragma unroll
-        for (int j = 0; j < NY; ++j)
-            win[j][k + 1] = BufLd<S>::ld(src, col_off[j], plane(z0 - R + k));
-
-    // prefetch ring: slot q holds plane z0 + q (+R for the window value)
-    C pre_w[PF][NY], pre_hx[PF][SH::HX_PER], pre_hy[PF][SH::HY_PER];
-#pragma unroll
-    for (int q = 0; q < PF; ++q) {
-        const int zq = min(z0 + q, z1 - 1); // in range: any valid plane will do
-#pragma unroll
-        for (int j = 0; j < NY; ++j) pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zq + R));
-#pragma unroll
-        for (int k = 0; k < SH::HX_PER; ++k) pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zq));
-#pragma unroll
-        for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zq));
-    }
-
-    for (int zb = z0; zb < z1; zb += PF) {
+            for (int j = 0; j < NY; ++j)
+                ring[j][k] = BufLd<S>::ld(src, col_off[j], plane(z0 - R + k));
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            const int z = zb + q;
-            if (z >= z1)
-                break;
-            const int b = (z - z0) & 1;
-            C *lb = &lds[b][0][0];
+            const int zq = min(z0 + q, z1 - 1); // in range: any valid plane will do
 #pragma unroll
-            for (int j = 0; j < NY; ++j) {
+            for (int j = 0; j < NY; ++j)
+                ring[j][2 * R + q] = BufLd<S>::ld(src, col_off[j], plane(zq + R));
 #pragma unroll
-                for (int k = 0; k < 2 * R; ++k) win[j][k] = win[j][k + 1];
-                win[j][2 * R] = pre_w[q][j];
-                lds[b][ty * NY + j + R][tx + R] = win[j][R];
-            }
+            for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zq));
 #pragma unroll
-            for (int k = 0; k < SH::HX_PER; ++k)
-                if (hx_slot[k] >= 0) lb[hx_slot[k]] = pre_hx[q][k];
+            for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zq));
+        }
+        for (int zb = z0; zb < z1; zb += NR) {
 #pragma unroll
-            for (int k = 0; k < SH::HY_PER; ++k)
-                if (hy_slot[k] >= 0) lb[hy_slot[k]] = pre_hy[q][k];
-            __syncthreads();
-
-            // refill slot q with plane z + PF (clamped: past the chunk end the
-            // values are never used, the load only has to stay in range)
-            {
-                const int zn = min(z + PF, z1 - 1);
+            for (int q = 0; q < NR; ++q) {
+                const int z = zb + q;
+                if (z >= z1)
+                    break;
+#define RS(k_) ((q + R + (k_) + 2 * NR) % NR)
+                const int b = (z - z0) & 1;
+                C *lb = &lds[b][0][0];
 #pragma unroll
-                for (int j = 0; j < NY; ++j)
-                    pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+                for (int j = 0; j < NY; ++j) lds[b][ty * NY + j + R][tx + R] = ring[j][RS(0)];
 #pragma unroll
                 for (int k = 0; k < SH::HX_PER; ++k)
-                    pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
+                    if (hx_slot[k] >= 0) lb[hx_slot[k]] = hxr[q % NH][k];
 #pragma unroll
                 for (int k = 0; k < SH::HY_PER; ++k)
-                    pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
+                    if (hy_slot[k] >= 0) lb[hy_slot[k]] = hyr[q % NH][k];
+                __syncthreads();
+                {
+                    // plane z + PF (clamped) into the slots of plane z - R - 1
+                    const int zn = min(z + PF, z1 - 1);
+#pragma unroll
+                    for (int j = 0; j < NY; ++j)
+                        ring[j][RS(R + PF)] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+#pragma unroll
+                    for (int k = 0; k < SH::HX_PER; ++k)
+                        hxr[(q + PF) % NH][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
+#pragma unroll
+                    for (int k = 0; k < SH::HY_PER; ++k)
+                        hyr[(q + PF) % NH][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
+                }
+#pragma unroll
+                for (int j = 0; j < NY; ++j) {
+                    const int row = ty * NY + j + R;
+                    C acc = cf.c0 * ring[j][RS(0)];
+#pragma unroll
+                    for (int m = 1; m <= R; ++m) {
+                        acc = fma(cf.zm[m - 1], ring[j][RS(-m)], acc);
+                        acc = fma(cf.zp[m - 1], ring[j][RS(m)], acc);
+                    }
+#pragma unroll
+                    for (int m = 1; m <= R; ++m) {
+                        acc = fma(cf.xm[m - 1], lds[b][row][tx + R - m], acc);
+                        acc = fma(cf.xp[m - 1], lds[b][row][tx + R + m], acc);
+                    }
+#pragma unroll
+                    for (int m = 1; m <= R; ++m) {
+                        C vm = (j - m >= 0) ? ring[(j - m >= 0) ? j - m : 0][RS(0)]
+                                            : lds[b][row - m][tx + R];
+                        C vp = (j + m < NY) ? ring[(j + m < NY) ? j + m : 0][RS(0)]
+                                            : lds[b][row + m][tx + R];
+                        acc = fma(cf.ym[m - 1], vm, acc);
+                        acc = fma(cf.yp[m - 1], vp, acc);
+                    }
+                    const int y = y0 + ty * NY + j;
+                    if (x < g.nx && y < g.ny)
+                        store_periodic(out, g, x, y, z, acc, fuse);
+                }
+#undef RS
             }
+        }
+    } else {
+        // z window: win[j][k] holds plane z - R + k of row j
+        C win[NY][2 * R + 1];
+    #pragma unroll
+        for (int k = 0; k < 2 * R; ++k)
+    #pragma unroll
+            for (int j = 0; j < NY; ++j)
+                win[j][k + 1] = BufLd<S>::ld(src, col_off[j], plane(z0 - R + k));
 
-#pragma unroll
-            for (int j = 0; j < NY; ++j) {
-                const int row = ty * NY + j + R;
-                C acc = cf.c0 * win[j][R];
-#pragma unroll
-                for (int m = 1; m <= R; ++m) {
-                    acc = fma(cf.zm[m - 1], win[j][R - m], acc);
-                    acc = fma(cf.zp[m - 1], win[j][R + m], acc);
+        // prefetch ring: slot q holds plane z0 + q (+R for the window value)
+        C pre_w[PF][NY], pre_hx[PF][SH::HX_PER], pre_hy[PF][SH::HY_PER];
+    #pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int zq = min(z0 + q, z1 - 1); // in range: any valid plane will do
+    #pragma unroll
+            for (int j = 0; j < NY; ++j) pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zq + R));
+    #pragma unroll
+            for (int k = 0; k < SH::HX_PER; ++k) pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zq));
+    #pragma unroll
+            for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zq));
+        }
+
+        for (int zb = z0; zb < z1; zb += PF) {
+    #pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int z = zb + q;
+                if (z >= z1)
+                    break;
+                const int b = (z - z0) & 1;
+                C *lb = &lds[b][0][0];
+    #pragma unroll
+                for (int j = 0; j < NY; ++j) {
+    #pragma unroll
+                    for (int k = 0; k < 2 * R; ++k) win[j][k] = win[j][k + 1];
+                    win[j][2 * R] = pre_w[q][j];
+                    lds[b][ty * NY + j + R][tx + R] = win[j][R];
                 }
-#pragma unroll
-                for (int m = 1; m <= R; ++m) {
-                    acc = fma(cf.xm[m - 1], lds[b][row][tx + R - m], acc);
-                    acc = fma(cf.xp[m - 1], lds[b][row][tx + R + m], acc);
+    #pragma unroll
+                for (int k = 0; k < SH::HX_PER; ++k)
+                    if (hx_slot[k] >= 0) lb[hx_slot[k]] = pre_hx[q][k];
+    #pragma unroll
+                for (int k = 0; k < SH::HY_PER; ++k)
+                    if (hy_slot[k] >= 0) lb[hy_slot[k]] = pre_hy[q][k];
+                __syncthreads();
+
+                // refill slot q with plane z + PF (clamped: past the chunk end the
+                // values are never used, the load only has to stay in range)
+                {
+                    const int zn = min(z + PF, z1 - 1);
+    #pragma unroll
+                    for (int j = 0; j < NY; ++j)
+                        pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+    #pragma unroll
+                    for (int k = 0; k < SH::HX_PER; ++k)
+                        pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
+    #pragma unroll
+                    for (int k = 0; k < SH::HY_PER; ++k)
+                        pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
                 }
-#pragma unroll
-                for (int m = 1; m <= R; ++m) {
-                    C vm = (j - m >= 0) ? win[(j - m >= 0) ? j - m : 0][R] : lds[b][row - m][tx + R];
-                    C vp = (j + m < NY) ? win[(j + m < NY) ? j + m : 0][R] : lds[b][row + m][tx + R];
-                    acc = fma(cf.ym[m - 1], vm, acc);
-                    acc = fma(cf.yp[m - 1], vp, acc);
+
+    #pragma unroll
+                for (int j = 0; j < NY; ++j) {
+                    const int row = ty * NY + j + R;
+                    C acc = cf.c0 * win[j][R];
+    #pragma unroll
+                    for (int m = 1; m <= R; ++m) {
+                        acc = fma(cf.zm[m - 1], win[j][R - m], acc);
+                        acc = fma(cf.zp[m - 1], win[j][R + m], acc);
+                    }
+    #pragma unroll
+                    for (int m = 1; m <= R; ++m) {
+                        acc = fma(cf.xm[m - 1], lds[b][row][tx + R - m], acc);
+                        acc = fma(cf.xp[m - 1], lds[b][row][tx + R + m], acc);
+                    }
+    #pragma unroll
+                    for (int m = 1; m <= R; ++m) {
+                        C vm = (j - m >= 0) ? win[(j - m >= 0) ? j - m : 0][R] : lds[b][row - m][tx + R];
+                        C vp = (j + m < NY) ? win[(j + m < NY) ? j + m : 0][R] : lds[b][row + m][tx + R];
+                        acc = fma(cf.ym[m - 1], vm, acc);
+                        acc = fma(cf.yp[m - 1], vp, acc);
+                    }
+                    const int y = y0 + ty * NY + j;
+                    if (x < g.nx && y < g.ny)
+                        store_periodic(out, g, x, y, z, acc, fuse);
                 }
-                const int y = y0 + ty * NY + j;
-                if (x < g.nx && y < g.ny)
-                    store_periodic(out, g, x, y, z, acc, fuse);
             }
         }
     }
