@@ -132,8 +132,8 @@ __device__ __forceinline__ void advdiff3_zmarch(const void *fin_v, const PointIO
     C hxr[NH][ZM_HX], hyr[NH][ZM_HY];
     W wr[NH][NY], w1r[NH][NY];
     double mr[NH][NY];
-    auto load_old = [&](int slot_dummy, int zz, W (&wv)[NY], W (&w1v)[NY], double (&mv)[NY]) {
-        (void)slot_dummy;
+    // the old register values of plane zz (zero where the substep reads none)
+    auto load_old = [&](int zz, W (&wv)[NY], W (&w1v)[NY], double (&mv)[NY]) {
 #pragma unroll
         for (int j = 0; j < NY; ++j) {
             wv[j] = W(0);
@@ -171,7 +171,7 @@ __device__ __forceinline__ void advdiff3_zmarch(const void *fin_v, const PointIO
         for (int k = 0; k < ZM_HX; ++k) hxr[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zq));
 #pragma unroll
         for (int k = 0; k < ZM_HY; ++k) hyr[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zq));
-        load_old(q, zq, wr[q], w1r[q], mr[q]);
+        load_old(zq, wr[q], w1r[q], mr[q]);
     }
 
     for (int zb = z0; zb < z1; zb += NR) {
@@ -204,7 +204,7 @@ __device__ __forceinline__ void advdiff3_zmarch(const void *fin_v, const PointIO
 #pragma unroll
                 for (int k = 0; k < ZM_HY; ++k)
                     hyr[(q + PF) % NH][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
-                load_old(q, zn, wr[(q + PF) % NH], w1r[(q + PF) % NH], mr[(q + PF) % NH]);
+                load_old(zn, wr[(q + PF) % NH], w1r[(q + PF) % NH], mr[(q + PF) % NH]);
             }
 #pragma unroll
             for (int j = 0; j < NY; ++j) {
