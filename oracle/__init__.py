@@ -67,6 +67,7 @@ def lib():
                                             ctypes.c_double, _lp, ctypes.c_long, _dp, _dp]
         L.oracle_rk3_substep_at.restype = ctypes.c_int
         L.oracle_reduce.argtypes = [_dp, ctypes.c_int, _lp, ctypes.c_int, _dp]
+        L.oracle_energy.argtypes = [ctypes.POINTER(_dp), _lp, _dp, _dp]
         L.oracle_filter.argtypes = [_dp, _dp, ctypes.c_int, _lp, ctypes.c_int, _dp, ctypes.c_int]
         L.oracle_filter_at.argtypes = [_dp, ctypes.c_int, _lp, ctypes.c_int, _dp, ctypes.c_int,
                                        _lp, ctypes.c_long, _dp]
@@ -330,4 +331,16 @@ def reduce(f, r):
     nd, n = _dims(f, r)
     out = np.zeros(3)
     lib().oracle_reduce(_ptr(f), nd, n, r, _ptr(out))
+    return out
+
+
+def energy(fields, ds):
+    """(1/2 sum |u|^2, 1/2 sum |curl A|^2) over the interior of the 8 padded
+    MHD fields (Table A1 order, periodic halos), sixth-order first
+    derivatives, sequential FP64 sums over grid points."""
+    nd, n = _dims(fields[0], 3)
+    if nd != 3 or len(fields) != 8:
+        raise ValueError("needs the 8 padded 3-D MHD fields")
+    out = np.zeros(2)
+    lib().oracle_energy(_ptrs(fields), n, _d3(ds), _ptr(out))
     return out

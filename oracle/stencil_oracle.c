@@ -731,3 +731,34 @@ void oracle_reduce(const double *f, int ndim, const long *n, int r, double *out)
     out[1] = s2;
     out[2] = mx;
 }
+
+/* Kinetic and magnetic energy of the 8-field MHD state (Table A1 order), as
+ * plain sums over the interior grid points, accumulated sequentially in FP64:
+ *   out[0] = 1/2 sum |u|^2,
+ *   out[1] = 1/2 sum |B|^2,  B = curl A with the sixth-order first derivatives
+ *            (B_x = d_y A_z - d_z A_y, B_y = d_z A_x - d_x A_z,
+ *             B_z = d_x A_y - d_y A_x).
+ * f: 8 radius-3 padded 3-D fields with periodic halos. */
+void oracle_energy(const double *const *f, const long *n, const double *ds, double *out)
+{
+    const int r = 3;
+    long P[3] = {ext(3, 0, n, r), ext(3, 1, n, r), ext(3, 2, n, r)};
+    double ek = 0.0, em = 0.0;
+    for (long z = 0; z < n[2]; ++z)
+        for (long y = 0; y < n[1]; ++y)
+            for (long x = 0; x < n[0]; ++x) {
+                const long X = x + r, Y = y + r, Z = z + r;
+                size_t p = at(P, X, Y, Z);
+                double u2 = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    u2 += f[UX + a][p] * f[UX + a][p];
+                const double B[3] = {
+                    d1(f[AZ], P, X, Y, Z, 1, ds) - d1(f[AY], P, X, Y, Z, 2, ds),
+                    d1(f[AX], P, X, Y, Z, 2, ds) - d1(f[AZ], P, X, Y, Z, 0, ds),
+                    d1(f[AY], P, X, Y, Z, 0, ds) - d1(f[AX], P, X, Y, Z, 1, ds)};
+                ek += u2;
+                em += B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+            }
+    out[0] = 0.5 * ek;
+    out[1] = 0.5 * em;
+}
