@@ -363,6 +363,18 @@ stencil_status stencil_rk_run(stencil_plan_t plan, const stencil_fields *fields,
 stencil_status stencil_reduce(stencil_plan_t plan, const void *const *fields, int nfields,
                               int dtype, double *host_out, void *stream);
 
+/* Kinetic and magnetic energy of an MHD plan's state (MHD8 or MHD_FULL; the
+ * fields of Eq. A1-A4 in Table A1 order): host_out[0] = 1/2 sum |u|^2 and
+ * host_out[1] = 1/2 sum |B|^2 over the interior grid points, B = curl A by the
+ * plan's sixth-order first-derivative stencil and spacing (plain sums over
+ * points: multiply by the cell volume for integrals). fields: the 8 padded
+ * buffers of the plan's layout stored as dtype, periodic halos valid (as
+ * stencil_step and stencil_rk_run leave f_out). FP64 accumulation,
+ * deterministic (fixed partition and tree, no floating-point atomics).
+ * Synchronises the stream. */
+stencil_status stencil_energy(stencil_plan_t plan, const void *const *fields, int dtype,
+                              double *host_out, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched jobs and the serving loop                                        */
 /* ------------------------------------------------------------------------ */

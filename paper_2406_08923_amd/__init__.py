@@ -309,6 +309,8 @@ def _declare_rk(L):
     L.stencil_rk_run.argtypes = [_vp, ctypes.POINTER(_Fields), c_int, ctypes.c_double, _vp]
     L.stencil_reduce.argtypes = [_vp, ctypes.POINTER(_vp), c_int, c_int,
                                  ctypes.POINTER(ctypes.c_double), _vp]
+    L.stencil_energy.argtypes = [_vp, ctypes.POINTER(_vp), c_int,
+                                 ctypes.POINTER(ctypes.c_double), _vp]
 
 
 def _fields_struct(f_in, f_out, w, w2=None, f64=None):
@@ -419,6 +421,17 @@ class RkPlan:
         out = (ctypes.c_double * (3 * len(fields)))()
         check(lib().stencil_reduce(self._h, ptrs, len(fields), dtype, out, stream_ptr(stream)))
         return np.array(out[:]).reshape(len(fields), 3)
+
+    def energy(self, fields, dtype=None, stream=None):
+        """(1/2 sum |u|^2, 1/2 sum |curl A|^2) of the 8 MHD fields (padded
+        buffers with valid halos), FP64, deterministic."""
+        dtype = self.dtype if dtype is None else dtype
+        if len(fields) != 8:
+            raise ValueError("energy needs the 8 MHD fields")
+        ptrs = (_vp * 8)(*[t.data_ptr() for t in fields])
+        out = (ctypes.c_double * 2)()
+        check(lib().stencil_energy(self._h, ptrs, dtype, out, stream_ptr(stream)))
+        return np.array(out[:])
 
     def close(self):
         if getattr(self, "_h", None):

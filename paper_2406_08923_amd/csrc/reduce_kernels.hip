@@ -84,6 +84,63 @@ __global__ void __launch_bounds__(RT) k_reduce_pass2(const double *partial, int 
     }
 }
 
+// Energy pass 1: the same fixed row partition; per point |u|^2 and |B|^2 with
+// B = curl A by the sixth-order first derivatives (unit-spacing weights w1,
+// inverse spacings ids), accumulated in FP64 (fields in Table A1 order).
+template <typename S>
+__global__ void __launch_bounds__(RT) k_energy_pass1(FieldPtrs fields, Geo g, EnergyCoef ec,
+                                                     int64_t rows_per_block, double *partial)
+{
+    __shared__ double s0[RT], s1[RT], s2[RT];
+    const S *u[3] = {static_cast<const S *>(fields.p[1]), static_cast<const S *>(fields.p[2]),
+                     static_cast<const S *>(fields.p[3])};
+    const S *A[3] = {static_cast<const S *>(fields.p[5]), static_cast<const S *>(fields.p[6]),
+                     static_cast<const S *>(fields.p[7])};
+    const int64_t st[3] = {1, g.sy, g.sz};
+    const int64_t nrows = (int64_t)g.ny * g.nz;
+    const int64_t r0 = blockIdx.x * rows_per_block;
+    const int64_t r1 = min(nrows, r0 + rows_per_block);
+    const int64_t len = (r1 > r0 ? r1 - r0 : 0) * g.nx;
+    // d_a A_b at padded index p
+    auto d1 = [&](int b, int a, int64_t p) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 1; m <= 3; ++m) {
+            const double fp = static_cast<double>(Store<S>::ld(A[b] + p + m * st[a]));
+            const double fm = static_cast<double>(Store<S>::ld(A[b] + p - m * st[a]));
+            acc = fma(ec.w1[m - 1], fp - fm, acc);
+        }
+        return acc * ec.ids[a];
+    };
+    double ek = 0.0, em = 0.0, unused = 0.0;
+    for (int64_t i = threadIdx.x; i < len; i += RT) {
+        const int64_t row = r0 + i / g.nx;
+        const int x = static_cast<int>(i % g.nx);
+        const int y = static_cast<int>(row % g.ny), z = static_cast<int>(row / g.ny);
+        const int64_t p = g.at(x, y, z);
+        double u2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double v = static_cast<double>(Store<S>::ld(u[c] + p));
+            u2 = fma(v, v, u2);
+        }
+        const double bx = d1(2, 1, p) - d1(1, 2, p);
+        const double by = d1(0, 2, p) - d1(2, 0, p);
+        const double bz = d1(1, 0, p) - d1(0, 1, p);
+        ek += u2;
+        em = fma(bx, bx, em);
+        em = fma(by, by, em);
+        em = fma(bz, bz, em);
+    }
+    tree3(s0, s1, s2, ek, em, unused);
+    if (threadIdx.x == 0) {
+        double *o = partial + 3 * blockIdx.x;
+        o[0] = ek;
+        o[1] = em;
+        o[2] = 0.0;
+    }
+}
+
 int reduce_nblocks(const Geo &g)
 {
     const int64_t nrows = (int64_t)g.ny * g.nz;
@@ -111,6 +168,26 @@ int launch_reduce(const FieldPtrs &d_fields, int nfields, int dtype, const Geo &
     if (rc) return rc;
     hipLaunchKernelGGL(k_reduce_pass2, dim3(nfields), dim3(RT), 0, s, d_partial, nb, d_out);
     return check_launch("reduce_pass2");
+}
+
+int launch_energy(const FieldPtrs &d_fields, int dtype, const Geo &g, const EnergyCoef &ec,
+                  double *d_partial, double *d_out, hipStream_t s)
+{
+    if (g.ndim != 3)
+        return fail(STENCIL_EINVAL, "energy: needs a 3-D plan");
+    const int nb = reduce_nblocks(g);
+    const int64_t nrows = (int64_t)g.ny * g.nz;
+    const int64_t rpb = (nrows + nb - 1) / nb;
+    switch (dtype) {
+    case STENCIL_F64: hipLaunchKernelGGL(k_energy_pass1<double>, dim3(nb), dim3(RT), 0, s, d_fields, g, ec, rpb, d_partial); break;
+    case STENCIL_F32: hipLaunchKernelGGL(k_energy_pass1<float>, dim3(nb), dim3(RT), 0, s, d_fields, g, ec, rpb, d_partial); break;
+    case STENCIL_BF16: hipLaunchKernelGGL(k_energy_pass1<bf16>, dim3(nb), dim3(RT), 0, s, d_fields, g, ec, rpb, d_partial); break;
+    default: return fail(STENCIL_EINVAL, "unknown dtype %d", dtype);
+    }
+    int rc = check_launch("energy_pass1");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_reduce_pass2, dim3(1), dim3(RT), 0, s, d_partial, nb, d_out);
+    return check_launch("energy_pass2");
 }
 
 } // namespace stn

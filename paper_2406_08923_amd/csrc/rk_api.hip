@@ -377,4 +377,53 @@ stencil_status stencil_reduce(stencil_plan_t p, const void *const *fields, int n
     return rc;
 }
 
+stencil_status stencil_energy(stencil_plan_t p, const void *const *fields, int dtype,
+                              double *host_out, void *stream)
+{
+    if (!p || p->kind != PLAN_RK || p->rk.nf != 8)
+        return fail(STENCIL_EINVAL, "energy needs an MHD plan (MHD8 or MHD_FULL)");
+    if (!fields || !host_out)
+        return fail(STENCIL_EINVAL, "NULL fields or host output");
+    const size_t es = dtype_size(dtype);
+    if (!es)
+        return fail(STENCIL_EINVAL, "unknown dtype %d", dtype);
+    for (int k = 0; k < 8; ++k)
+        if (!fields[k] || reinterpret_cast<uintptr_t>(fields[k]) % es)
+            return fail(STENCIL_EINVAL, "field %d is NULL or misaligned", k);
+    int rc = check_device(p->device);
+    if (rc) return rc;
+    const RkPlan &P = p->rk;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nb = reduce_nblocks(P.g);
+    double *d_partial = nullptr, *d_out = nullptr;
+    STN_HIP(hipMallocAsync(reinterpret_cast<void **>(&d_partial), sizeof(double) * 3 * (size_t)nb,
+                           s));
+    if (hipMallocAsync(reinterpret_cast<void **>(&d_out), sizeof(double) * 3, s) != hipSuccess) {
+        (void)hipFreeAsync(d_partial, s);
+        return fail(STENCIL_ENOMEM, "energy: cannot allocate scratch");
+    }
+    FieldPtrs fp{};
+    for (int k = 0; k < 8; ++k)
+        fp.p[k] = fields[k];
+    EnergyCoef ec{};
+    for (int a = 0; a < 3; ++a) {
+        ec.w1[a] = P.fd.w1[a];
+        ec.ids[a] = P.inv_ds[a];
+    }
+    double sums[3] = {0, 0, 0};
+    rc = launch_energy(fp, dtype, P.g, ec, d_partial, d_out, s);
+    if (rc == STENCIL_OK &&
+        hipMemcpyAsync(sums, d_out, sizeof(sums), hipMemcpyDeviceToHost, s) != hipSuccess)
+        rc = fail(STENCIL_EDEVICE, "energy: copy to host failed");
+    (void)hipFreeAsync(d_partial, s);
+    (void)hipFreeAsync(d_out, s);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == STENCIL_OK)
+        rc = fail(STENCIL_EDEVICE, "energy: stream synchronisation failed");
+    if (rc == STENCIL_OK) {
+        host_out[0] = 0.5 * sums[0];
+        host_out[1] = 0.5 * sums[1];
+    }
+    return rc;
+}
+
 } // extern "C"

@@ -206,3 +206,9 @@ def test_full_mhd_constants_are_ignored_by_the_proxy_model():
 def test_rk_plan_rejects_unknown_mhd_constant_names():
     with pytest.raises(ValueError):
         S.RkPlan(S.MODEL_MHD_FULL, (8, 8, 8), mhd=dict(kappa=1.0))
+
+
+def test_energy_rejects_a_missing_plan_without_a_device():
+    out = (ctypes.c_double * 2)()
+    assert S.lib().stencil_energy(None, None, S.F64, out, None) == -1
+    assert S.lib().stencil_last_error()
