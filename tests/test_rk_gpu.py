@@ -354,3 +354,30 @@ def test_advdiff_zmarch_matches_oracle_and_cached(prec, lz):
     tol = 1e-12 if prec == S.PREC_F64 else 1e-5
     assert relerr(outs[0], ref) <= tol
     assert relerr(outs[0], outs[1]) <= tol
+
+
+@pytest.mark.parametrize("prec", [S.PREC_BF16_MASTER64, S.PREC_F32_ONLY, S.PREC_BF16_ONLY])
+def test_advdiff_zmarch_other_policies(prec):
+    # the z march's prefetched registers per policy: no master (F32/BF16
+    # only) and the BF16 master; compared with the FP64 oracle and with the
+    # per-point kernel (same arithmetic type, other summation order)
+    n = (70, 37, 41)
+    ds = ds_of(n)
+    c = (0.7, -0.4, 0.3)
+    dt = 0.1 * min(ds) / max(1.0, max(abs(v) for v in c))
+    f0 = inputs.uniform_field(n, 5)
+    outs = []
+    for variant, block in ((S.RK_LDS, (0, 0, 8)), (S.RK_CACHED, None)):
+        lp, master = run_policy(n, prec, [f0], 3, dt, model=S.MODEL_ADVDIFF, nu=0.01, adv=c,
+                                variant=variant, block=block)
+        outs.append(O.interior(master[0] if master is not None else lp[0], 3))
+    ref = O.interior(O.rk3_steps(O.MODEL_ADVDIFF, [O.pad_periodic(f0, 3)], ds, dt, 3, nu=0.01,
+                                 c=c)[0], 3)
+    bf16 = prec in (S.PREC_BF16_MASTER64, S.PREC_BF16_ONLY)
+    # storage rounding (2^-8 BF16, 2^-24 FP32, relative) entering each of the
+    # 9 substeps, amplified by at most the step operator's norm (< 2 here)
+    u = 2.0 ** -8 if bf16 else 2.0 ** -24
+    print("advdiff z march, precision %d: error vs FP64 %.2e, vs per-point kernel %.2e"
+          % (prec, relerr(outs[0], ref), relerr(outs[0], outs[1])))
+    assert relerr(outs[0], ref) <= 9 * 2 * u
+    assert relerr(outs[0], outs[1]) <= 9 * 2 * u
