@@ -137,6 +137,18 @@ __device__ __forceinline__ void star3d_t2_segment(
             for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zs + q));
         }
 
+        // Halo cells are written unconditionally: a lane without one writes
+        // into its own first interior cell, before the interior value is
+        // stored there (one lane's LDS writes complete in program order), so
+        // no lane mask is kept live across the march.
+        const int own = (ty * NY + R) * SH::LW + tx + R;
+        int hx_dst[SH::HX_PER], hy_dst[SH::HY_PER];
+    #pragma unroll
+        for (int k = 0; k < SH::HX_PER; ++k) hx_dst[k] = hx_slot[k] >= 0 ? hx_slot[k] : own;
+    #pragma unroll
+        for (int k = 0; k < SH::HY_PER; ++k) hy_dst[k] = hy_slot[k] >= 0 ? hy_slot[k] : own;
+
+        const uint32_t pbytes = uint32_t(g.sz) * es;
         for (int zb = zs; zb <= ze; zb += NR) {
     #pragma unroll
             for (int q = 0; q < NR; ++q) {
@@ -150,31 +162,34 @@ __device__ __forceinline__ void star3d_t2_segment(
     #define F0(k_) ((q + R + (k_) + 2 * NR) % NR)
     #define F1(k_) ((q - 1 + (k_) + 2 * NR) % NR)
     #pragma unroll
+                for (int k = 0; k < SH::HX_PER; ++k) la[hx_dst[k]] = hxr[q % NH][k];
+    #pragma unroll
+                for (int k = 0; k < SH::HY_PER; ++k) la[hy_dst[k]] = hyr[q % NH][k];
+    #pragma unroll
                 for (int j = 0; j < NY; ++j) {
                     lda[b][ty * NY + j + R][tx + R] = ring[j][F0(0)];
                     ldb[b][ty * NY + j][tx] = r1[j][F1(0)];
                 }
-    #pragma unroll
-                for (int k = 0; k < SH::HX_PER; ++k)
-                    if (hx_slot[k] >= 0) la[hx_slot[k]] = hxr[q % NH][k];
-    #pragma unroll
-                for (int k = 0; k < SH::HY_PER; ++k)
-                    if (hy_slot[k] >= 0) la[hy_slot[k]] = hyr[q % NH][k];
                 __syncthreads();
 
                 {
                     // plane zA + R + PF into the slot of plane zA - R - 1 (free
                     // since the previous step); halo of plane zA + PF likewise
-                    const int zn = zA + PF; // wrapped: always a valid plane
+                    // zA >= -R and a periodic axis holds at least R planes,
+                    // so zA + PF + nz >= 0: an unsigned remainder wraps it, at
+                    // half the scalar work of a signed one
+                    const uint32_t nzu = uint32_t(g.nz), zu = uint32_t(zA + PF + g.nz);
+                    const uint32_t pw = ((zu + R) % nzu + uint32_t(g.rz)) * pbytes;
+                    const uint32_t ph = (zu % nzu + uint32_t(g.rz)) * pbytes;
     #pragma unroll
                     for (int j = 0; j < NY; ++j)
-                        ring[j][F0(R + PF)] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+                        ring[j][F0(R + PF)] = BufLd<S>::ld(src, col_off[j], pw);
     #pragma unroll
                     for (int k = 0; k < SH::HX_PER; ++k)
-                        hxr[(q + PF) % NH][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
+                        hxr[(q + PF) % NH][k] = BufLd<S>::ld(src, hx_off[k], ph);
     #pragma unroll
                     for (int k = 0; k < SH::HY_PER; ++k)
-                        hyr[(q + PF) % NH][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
+                        hyr[(q + PF) % NH][k] = BufLd<S>::ld(src, hy_off[k], ph);
                 }
 
                 // stage B: f2 at plane zB from the f1 ring and f1's plane in LDS
@@ -268,6 +283,15 @@ __device__ __forceinline__ void star3d_t2_segment(
             for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zs + q));
         }
 
+        // halo cells written unconditionally, as in the ring march
+        const int own = (ty * NY + R) * SH::LW + tx + R;
+        int hx_dst[SH::HX_PER], hy_dst[SH::HY_PER];
+    #pragma unroll
+        for (int k = 0; k < SH::HX_PER; ++k) hx_dst[k] = hx_slot[k] >= 0 ? hx_slot[k] : own;
+    #pragma unroll
+        for (int k = 0; k < SH::HY_PER; ++k) hy_dst[k] = hy_slot[k] >= 0 ? hy_slot[k] : own;
+        const uint32_t pbytes = uint32_t(g.sz) * es;
+
         for (int zb = zs; zb <= ze; zb += PF) {
     #pragma unroll
             for (int q = 0; q < PF; ++q) {
@@ -277,6 +301,10 @@ __device__ __forceinline__ void star3d_t2_segment(
                 const int b = (zA - zs) & 1;
                 C *la = &lda[b][0][0];
     #pragma unroll
+                for (int k = 0; k < SH::HX_PER; ++k) la[hx_dst[k]] = pre_hx[q][k];
+    #pragma unroll
+                for (int k = 0; k < SH::HY_PER; ++k) la[hy_dst[k]] = pre_hy[q][k];
+    #pragma unroll
                 for (int j = 0; j < NY; ++j) {
     #pragma unroll
                     for (int k = 0; k < 2 * R; ++k) win[j][k] = win[j][k + 1];
@@ -284,25 +312,22 @@ __device__ __forceinline__ void star3d_t2_segment(
                     lda[b][ty * NY + j + R][tx + R] = win[j][R];
                     ldb[b][ty * NY + j][tx] = w1[j][R];
                 }
-    #pragma unroll
-                for (int k = 0; k < SH::HX_PER; ++k)
-                    if (hx_slot[k] >= 0) la[hx_slot[k]] = pre_hx[q][k];
-    #pragma unroll
-                for (int k = 0; k < SH::HY_PER; ++k)
-                    if (hy_slot[k] >= 0) la[hy_slot[k]] = pre_hy[q][k];
                 __syncthreads();
 
                 {
-                    const int zn = zA + PF; // wrapped: always a valid plane
+                    // zA + PF + nz >= 0: unsigned remainder, as in the ring march
+                    const uint32_t nzu = uint32_t(g.nz), zu = uint32_t(zA + PF + g.nz);
+                    const uint32_t pw = ((zu + R) % nzu + uint32_t(g.rz)) * pbytes;
+                    const uint32_t ph = (zu % nzu + uint32_t(g.rz)) * pbytes;
     #pragma unroll
                     for (int j = 0; j < NY; ++j)
-                        pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+                        pre_w[q][j] = BufLd<S>::ld(src, col_off[j], pw);
     #pragma unroll
                     for (int k = 0; k < SH::HX_PER; ++k)
-                        pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
+                        pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], ph);
     #pragma unroll
                     for (int k = 0; k < SH::HY_PER; ++k)
-                        pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
+                        pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], ph);
                 }
 
                 // stage B: f2 at plane zB from the f1 window and f1's plane in LDS
