@@ -125,6 +125,17 @@ __global__ void __launch_bounds__(64 * XW * TY)
         }
     }
 
+    // Halo cells are written unconditionally: a lane without one writes into
+    // its own first interior cell, before the interior value is stored there
+    // (one lane's LDS writes complete in program order), so no lane mask is
+    // kept live across the march.
+    const int own = (ty * NY + R) * SH::LW + tx + R;
+    int hx_dst[SH::HX_PER], hy_dst[SH::HY_PER];
+#pragma unroll
+    for (int k = 0; k < SH::HX_PER; ++k) hx_dst[k] = hx_slot[k] >= 0 ? hx_slot[k] : own;
+#pragma unroll
+    for (int k = 0; k < SH::HY_PER; ++k) hy_dst[k] = hy_slot[k] >= 0 ? hy_slot[k] : own;
+
     // Register-ring march where the halo ring (PF + 1 slots) divides the z
     // ring (2R + 1 + PF slots), i.e. PF + 1 divides 2R (r = 3 with PF = 2):
     // plane p lives in slot (p - z0 + R) mod NR of ring, its halo in slot
@@ -163,13 +174,11 @@ __global__ void __launch_bounds__(64 * XW * TY)
                 const int b = (z - z0) & 1;
                 C *lb = &lds[b][0][0];
 #pragma unroll
+                for (int k = 0; k < SH::HX_PER; ++k) lb[hx_dst[k]] = hxr[q % NH][k];
+#pragma unroll
+                for (int k = 0; k < SH::HY_PER; ++k) lb[hy_dst[k]] = hyr[q % NH][k];
+#pragma unroll
                 for (int j = 0; j < NY; ++j) lds[b][ty * NY + j + R][tx + R] = ring[j][RS(0)];
-#pragma unroll
-                for (int k = 0; k < SH::HX_PER; ++k)
-                    if (hx_slot[k] >= 0) lb[hx_slot[k]] = hxr[q % NH][k];
-#pragma unroll
-                for (int k = 0; k < SH::HY_PER; ++k)
-                    if (hy_slot[k] >= 0) lb[hy_slot[k]] = hyr[q % NH][k];
                 __syncthreads();
                 {
                     // plane z + PF (clamped) into the slots of plane z - R - 1
@@ -249,14 +258,13 @@ __global__ void __launch_bounds__(64 * XW * TY)
     #pragma unroll
                     for (int k = 0; k < 2 * R; ++k) win[j][k] = win[j][k + 1];
                     win[j][2 * R] = pre_w[q][j];
-                    lds[b][ty * NY + j + R][tx + R] = win[j][R];
                 }
     #pragma unroll
-                for (int k = 0; k < SH::HX_PER; ++k)
-                    if (hx_slot[k] >= 0) lb[hx_slot[k]] = pre_hx[q][k];
+                for (int k = 0; k < SH::HX_PER; ++k) lb[hx_dst[k]] = pre_hx[q][k];
     #pragma unroll
-                for (int k = 0; k < SH::HY_PER; ++k)
-                    if (hy_slot[k] >= 0) lb[hy_slot[k]] = pre_hy[q][k];
+                for (int k = 0; k < SH::HY_PER; ++k) lb[hy_dst[k]] = pre_hy[q][k];
+    #pragma unroll
+                for (int j = 0; j < NY; ++j) lds[b][ty * NY + j + R][tx + R] = win[j][R];
                 __syncthreads();
 
                 // refill slot q with plane z + PF (clamped: past the chunk end the
