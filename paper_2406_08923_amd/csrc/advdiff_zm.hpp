@@ -122,6 +122,17 @@ __device__ __forceinline__ void advdiff3_zmarch(const void *fin_v, const PointIO
         }
     }
 
+    // Halo cells are written unconditionally: a lane without one writes into
+    // its own first interior cell, before the interior value is stored there
+    // (one lane's LDS writes complete in program order), so no lane mask is
+    // kept live across the march.
+    const int own = (ty * NY + R) * ZM_LW + tx + R;
+    int hx_dst[ZM_HX], hy_dst[ZM_HY];
+#pragma unroll
+    for (int k = 0; k < ZM_HX; ++k) hx_dst[k] = hx_slot[k] >= 0 ? hx_slot[k] : own;
+#pragma unroll
+    for (int k = 0; k < ZM_HY; ++k) hy_dst[k] = hy_slot[k] >= 0 ? hy_slot[k] : own;
+
     // which old values the update reads (uniform over the launch)
     const bool rd_w = io.stage > 0, rd_m = MASTER && io.stage == 2;
     const Buf wsrc = make_buf(rd_w ? io.wrd : fin_v, n_el * sizeof(W));
@@ -184,13 +195,11 @@ __device__ __forceinline__ void advdiff3_zmarch(const void *fin_v, const PointIO
             const int b = (z - z0) & 1;
             C *lb = &lds[b][0][0];
 #pragma unroll
+            for (int k = 0; k < ZM_HX; ++k) lb[hx_dst[k]] = hxr[q % NH][k];
+#pragma unroll
+            for (int k = 0; k < ZM_HY; ++k) lb[hy_dst[k]] = hyr[q % NH][k];
+#pragma unroll
             for (int j = 0; j < NY; ++j) lds[b][ty * NY + j + R][tx + R] = ring[j][RS(0)];
-#pragma unroll
-            for (int k = 0; k < ZM_HX; ++k)
-                if (hx_slot[k] >= 0) lb[hx_slot[k]] = hxr[q % NH][k];
-#pragma unroll
-            for (int k = 0; k < ZM_HY; ++k)
-                if (hy_slot[k] >= 0) lb[hy_slot[k]] = hyr[q % NH][k];
             __syncthreads();
             {
                 // plane z + PF (clamped) into the slots freed by plane z - R - 1
