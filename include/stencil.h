@@ -93,7 +93,10 @@ typedef struct stencil_desc {
      *             iterations in one pass over HBM, periodic plans and the LDS
      *             variant only: the temporal blocking the paper's discussion
      *             asks for; results are bitwise those of one-iteration
-     *             launches)}; one-iteration (width, lanes, rows) one of
+     *             launches), bit 16 (two iterations, two rows per lane,
+     *             r <= 3, at most 768 lanes) LDS planes stored y-fastest so
+     *             a lane's two rows are one 2-wide read}; one-iteration
+     *             (width, lanes, rows) one of
      *             (1,8,2) (1,4,4) (1,8,4) (1,16,2) (2,4,2) (2,4,4) (2,8,2)
      *             (4,2,2) (4,2,4) (4,4,2) (8,1,4) (8,2,2); two-iteration
      *             (1,8,2) (1,16,1) (1,16,2) (1,12,2) (2,8,2) (1,8,4), the

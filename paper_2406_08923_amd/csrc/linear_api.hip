@@ -177,7 +177,8 @@ int apply_t(stencil_plan_s *p, void *da, void *db, int iters, hipStream_t s, boo
         if ((nl & 1) != (iters & 1))
             ++nl;
         const int n2 = iters - nl, n1 = nl - n2;
-        const int fl = p->lin.sflags & (STAR_FLAG_XCD | STAR_FLAG_YFIRST);
+        const int fl = (p->lin.sflags & (STAR_FLAG_XCD | STAR_FLAG_YFIRST)) |
+                       (p->lin.pairs ? STAR_FLAG_PAIRS : 0);
         if (n2 == 0 && !halo_valid)
             rc = launch_halo<S>(a, p->lin.g, s);
         for (int k = 0; k < n2 && rc == STENCIL_OK; ++k) {
@@ -236,6 +237,7 @@ void set_choice(stencil_plan_s *p, const TuneChoice &c)
         p->lin.pf = pf ? pf : 2;
         p->lin.xw = xw ? xw : 1;
         p->lin.tstar = t == 2 ? 2 : 1;
+        p->lin.pairs = (c.p3 & STAR_PAIRS_BIT) != 0 && t == 2;
     } else if (c.variant == STENCIL_VARIANT_LINE1D) {
         p->lin.e1d = c.p0;
         p->lin.t1d = c.p1 > 1 ? c.p1 : 1;
@@ -285,8 +287,10 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
                 for (int lz : {32, 64, 128}) {
                     if (lz >= g.nz && lz != 32)
                         continue;
-                    c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz,
-                                 STAR_FLAG_XCD | (sh[0] << STAR_XW_SHIFT) | (2 << STAR_T_SHIFT)});
+                    const int w = STAR_FLAG_XCD | (sh[0] << STAR_XW_SHIFT) | (2 << STAR_T_SHIFT);
+                    c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz, w});
+                    if (sh[2] == 2 && p->lin.reff <= 3 && 64 * sh[0] * sh[1] <= 768)
+                        c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz, w | STAR_PAIRS_BIT});
                 }
         }
         // hardware-cached z march: (lanes along y, rows per lane)
@@ -339,11 +343,14 @@ TuneChoice default_choice(const stencil_plan_s *p)
                 p->lin.g.ndim == 1 ? 1 : 4, 0, 0};
     }
     // periodic stars: two iterations per launch, the lane grids that measured
-    // fastest at 512^3 (64 x 24 for FP64, 64 x 32 for the narrower types)
-    if (p->lin.is_star && p->lin.bc == STENCIL_BC_PERIODIC)
-        return {STENCIL_VARIANT_STAR3D, p->lin.dtype == STENCIL_F64 ? 12 : 8,
-                p->lin.dtype == STENCIL_F64 ? 2 : 4, p->lin.dtype == STENCIL_F64 ? 64 : 32,
-                STAR_FLAG_XCD | (1 << STAR_XW_SHIFT) | (2 << STAR_T_SHIFT)};
+    // fastest at 512^3 (64 x 24 for FP64, with pair-layout LDS planes up to
+    // r = 3; 64 x 32 with four rows per lane for the narrower types)
+    if (p->lin.is_star && p->lin.bc == STENCIL_BC_PERIODIC) {
+        const bool f64 = p->lin.dtype == STENCIL_F64;
+        const int pairs = f64 && p->lin.reff <= 3 ? STAR_PAIRS_BIT : 0;
+        return {STENCIL_VARIANT_STAR3D, f64 ? 12 : 8, f64 ? 2 : 4, f64 ? 64 : 32,
+                STAR_FLAG_XCD | (1 << STAR_XW_SHIFT) | (2 << STAR_T_SHIFT) | pairs};
+    }
     if (p->lin.is_star)
         return default_star1(p);
     if (p->lin.g.ndim == 1)
@@ -626,13 +633,21 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
             if (t[0]) c.p0 = t[0];
             if (t[1]) c.p1 = t[1];
             if (t[2]) c.p2 = t[2];
-            c.p3 = t[3] & 0xffff; // explicit tiles set the flag word exactly
+            c.p3 = t[3] & (0xffff | STAR_PAIRS_BIT); // explicit tiles set the flag word exactly
             const int tb = (c.p3 >> STAR_T_SHIFT) & 15;
             if (tb > 2 || (tb == 2 && d->bc != STENCIL_BC_PERIODIC) ||
                 (tb == 2 && (c.p3 & (STAR_FLAG_HWC | STAR_FLAG_NOFUSE)))) {
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "two iterations per launch need a periodic plan and "
                                             "the LDS variant (and 1 or 2 iterations only)");
+            }
+            if ((c.p3 & STAR_PAIRS_BIT) &&
+                (tb != 2 || c.p1 != 2 || L.reff > 3 || 64 * (((c.p3 >> STAR_XW_SHIFT) & 15) ?
+                                                                 ((c.p3 >> STAR_XW_SHIFT) & 15) : 1) *
+                                                                 c.p0 > 768)) {
+                stencil_plan_destroy(p);
+                return fail(STENCIL_EINVAL, "the pair layout needs two iterations per launch, two "
+                                            "rows per lane, radius <= 3 and at most 768 lanes");
             }
         } else if (c.variant == STENCIL_VARIANT_LINE1D) {
             if (t[0]) c.p0 = t[0];
@@ -705,7 +720,7 @@ stencil_status stencil_plan_tile(stencil_plan_t p, int tile[4])
         tile[1] = L.ny;
         tile[2] = L.lz;
         tile[3] = L.sflags | (L.pf << STAR_PF_SHIFT) | (L.xw << STAR_XW_SHIFT) |
-                  (L.tstar == 2 ? 2 << STAR_T_SHIFT : 0);
+                  (L.tstar == 2 ? 2 << STAR_T_SHIFT : 0) | (L.pairs ? STAR_PAIRS_BIT : 0);
     } else if (L.variant == STENCIL_VARIANT_LINE1D) {
         tile[0] = L.e1d;
         tile[1] = L.t1d;

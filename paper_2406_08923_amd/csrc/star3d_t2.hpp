@@ -424,35 +424,4 @@ __global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY>()))
                                         lda, ldb);
 }
 
-template <typename S, int R, int NY, int TY, int XW>
-int launch_star3d_t2_t(const S *in, S *out, const Geo &g,
-                       const StarCoef<typename Store<S>::C, R> &cf, int lz, int flags,
-                       hipStream_t s)
-{
-    using SH = StarShape<R, NY, TY, XW>;
-    const int OX = SH::TXW - 2 * R, OY = SH::ROWS - 2 * R;
-    int gx = (g.nx + OX - 1) / OX, gy = (g.ny + OY - 1) / OY;
-    int gz = (g.nz + lz - 1) / lz;
-    int64_t total = (int64_t)gx * gy * gz;
-    if (total > 0x7fffffff)
-        return fail(STENCIL_EUNSUPPORTED, "star3d (two iterations): grid too large");
-    hipLaunchKernelGGL((k_star3d_t2<S, R, NY, TY, XW>), dim3((unsigned)total),
-                       dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
-    return check_launch("xcorr_star3d_t2");
-}
-
-template <typename S, int R>
-int launch_star3d_t2_r(const S *in, S *out, const Geo &g,
-                       const StarCoef<typename Store<S>::C, R> &cf, int xw, int ty, int ny,
-                       int lz, int flags, hipStream_t s)
-{
-#define STAR_T2_CASE(XW_, TY_, NY_)                                                          \
-    if (xw == XW_ && ty == TY_ && ny == NY_)                                                 \
-        return launch_star3d_t2_t<S, R, NY_, TY_, XW_>(in, out, g, cf, lz, flags, s);
-    STAR_T2_SHAPES(STAR_T2_CASE)
-#undef STAR_T2_CASE
-    return fail(STENCIL_EUNSUPPORTED,
-                "star3d (two iterations): unsupported tile (xw=%d, ty=%d, ny=%d)", xw, ty, ny);
-}
-
 } // namespace stn

@@ -253,7 +253,9 @@ def test_apply_validation_on_device():
 # ---------------------------------------------------------------------------
 
 T2_TILES = [(8, 2, 32, 0x2101), (16, 1, 64, 0x2101), (16, 2, 16, 0x2101), (12, 2, 8, 0x2105),
-            (8, 2, 32, 0x2201), (8, 4, 16, 0x2101), (12, 2, 64, 0x2101), (8, 2, 32, 0x2105)]
+            (8, 2, 32, 0x2201), (8, 4, 16, 0x2101), (12, 2, 64, 0x2101), (8, 2, 32, 0x2105),
+            # pair-layout LDS planes (bit 16)
+            (12, 2, 64, 0x12101), (8, 2, 32, 0x12101), (12, 2, 8, 0x12105)]
 ONE_TILE = (4, 2, 8, 0x221)
 
 
@@ -300,9 +302,26 @@ def test_star_two_iterations_other_radii_random_taps(r, tile):
     assert_close(O.interior(got, r), O.interior(want, r), S.F64)
 
 
+@pytest.mark.parametrize("r", [1, 2, 3])
+@pytest.mark.parametrize("tile", [(12, 2, 16, 0x12101), (8, 2, 16, 0x12105)])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_star_two_iterations_pair_layout_radii_random_taps(r, tile, dtype):
+    # pair-layout LDS planes: every radius the layout takes, asymmetric taps,
+    # a grid that is not a multiple of the tile in any axis
+    dims = (66, 29, 31)
+    g = rand_star(r, 23) * 0.15
+    got, plan, inner = run_star_iters(dims, r, g, dtype, tile, 4)
+    assert plan.tile[3] & (1 << 16)
+    ref, _, _ = run_star_iters(dims, r, g, dtype, (4, 2, 8, 0x221), 4)
+    assert np.array_equal(got, ref)
+    if dtype == S.F64:
+        want = oracle_apply(inner, r, g, 4)
+        assert_close(O.interior(got, r), O.interior(want, r), S.F64)
+
+
 @pytest.mark.parametrize("dims,r", [((3, 3, 3), 3), ((5, 4, 7), 3), ((1, 1, 1), 1),
                                     ((130, 7, 5), 2)])
-@pytest.mark.parametrize("tile", [(8, 2, 32, 0x2101), (12, 2, 64, 0x2101)])
+@pytest.mark.parametrize("tile", [(8, 2, 32, 0x2101), (12, 2, 64, 0x2101), (12, 2, 64, 0x12101)])
 def test_star_two_iterations_tiny_and_thin_grids(dims, r, tile):
     g = rand_star(r, 8) * 0.2
     for iters in (4, 5):  # two-iteration launches only / plus one single
@@ -332,6 +351,19 @@ def test_star_two_iterations_needs_periodic_lds_variant():
                      (S.PERIODIC, (8, 2, 32, 0x3101))):
         with pytest.raises(S.StencilError):
             S.LinearPlan((32, 32, 32), 3, g, bc=bc, variant=S.STAR3D, tile=tile)
+
+
+def test_star_pair_layout_rejects_other_shapes():
+    g3 = diffusion_star_exact(3, 3, 0.1)
+    # one iteration per launch, four rows per lane, 1024 lanes
+    for tile in ((8, 2, 32, 0x10101), (8, 4, 16, 0x12101), (16, 2, 16, 0x12101),
+                 (8, 2, 32, 0x12201)):
+        with pytest.raises(S.StencilError):
+            S.LinearPlan((32, 32, 32), 3, g3, variant=S.STAR3D, tile=tile)
+    # radius 4
+    g4 = rand_star(4, 5) * 0.1
+    with pytest.raises(S.StencilError):
+        S.LinearPlan((32, 32, 32), 4, g4, variant=S.STAR3D, tile=(8, 2, 32, 0x12101))
 
 
 # ---------------------------------------------------------------------------
@@ -483,7 +515,7 @@ def test_star_512_cubed_two_iteration_launches(dtype):
     del inner
     outs = []
     # two-iteration (shifting window; register rings), one-iteration
-    for tile in ((8, 2, 64, 0x2101), (4, 2, 32, 0x221), (12, 2, 64, 0x2101)):
+    for tile in ((8, 2, 64, 0x2101), (4, 2, 32, 0x221), (12, 2, 64, 0x2101), (12, 2, 64, 0x12101)):
         plan = S.LinearPlan(dims, r, W.diffusion_star(3, 3, s), dtype=dtype, variant=S.STAR3D,
                             tile=tile, row_pitch=pitch, x_offset=ox)
         a = plan.empty(0.0)
@@ -494,6 +526,7 @@ def test_star_512_cubed_two_iteration_launches(dtype):
         del a, b, res, plan
     assert np.array_equal(outs[0], outs[1])
     assert np.array_equal(outs[2], outs[1])
+    assert np.array_equal(outs[3], outs[1])
     if dtype == S.F64:
         O.fill_periodic(pad, r)
         cur = pad
