@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="headline workload only")
     ap.add_argument("--no-precision-error", action="store_true",
                     help="skip the 1000-step mixed-precision error measurement")
+    ap.add_argument("--serve-rates", default="10,25,50",
+                    help="mean arrival rates (jobs/s) of the sustainable-load replays of the "
+                         "serving trace (empty: none)")
     ap.add_argument("--serve-jobs", type=int, default=48,
                     help="jobs in the serving trace (0 skips the serving comparison)")
     return ap.parse_args()
@@ -250,18 +253,23 @@ def secondary(torch, S, W, inputs, args):
         ms = timed(torch, lambda: plan.run(bufs["f_a"], bufs["f_b"], bufs["w"], steps, dt,
                                            w2=bufs["w2"], f64=bufs["f64"]), 2, warm=1) / steps
         pts = nm ** 3
+        flops = mhd_flops(model == S.MODEL_MHD_FULL, mname.endswith("_diag"))
+        peak = VALU_PEAK_TFLOPS["f64" if prec == S.PREC_F64 else "f32"]
         out["%s_%d_%s" % (mname, nm, name)] = {
             "point_steps_per_s": pts / (ms * 1e-3),
             "point_substeps_per_s": 3 * pts / (ms * 1e-3),
             "ms_per_step": ms,
-            "hbm_frac": bytes_step[prec] * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "hbm_frac": bytes_step[prec] * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "valu_roof": {"flops_per_point_substep": flops, "peak_tflops": peak,
+                          "frac": 3 * pts / (ms * 1e-3) * flops / (peak * 1e12)}}
         del bufs, plan
     if not args.no_precision_error:
         out["mhd8_mixed_precision_error_64"] = mixed_precision_error(torch, S, inputs)
         out["mhd_full_mixed_precision_error_64"] = mixed_precision_error(
             torch, S, inputs, model=S.MODEL_MHD_FULL, mhd=full)
     if args.serve_jobs > 0:
-        out["serving"] = serving(torch, args.serve_jobs)
+        rates = tuple(float(v) for v in args.serve_rates.split(",") if v)
+        out["serving"] = serving(torch, args.serve_jobs, rates=rates)
     return out
 
 
@@ -357,10 +365,32 @@ def mixed_precision_error(torch, S, inputs, n=64, checkpoints=(1, 10, 100, 1000)
     return out
 
 
-def serving(torch, count, seed=1):
+# dense vector peaks of one MI355X (FP64, FP32 arithmetic), TFLOP/s
+VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+
+
+def mhd_flops(full, diagonal):
+    """Algorithmic flops per point and substep of the fused 8-field step: 24
+    first derivatives (3 antisymmetric differences, 3 multiply-adds and the
+    1/ds scale: 9), 24 second derivatives (3 sums, 3 multiply-adds, the centre
+    tap and the scale: 11), 12 mixed derivatives (tensor product with the
+    antisymmetry folded: 9 four-point differences of 3 adds plus 9
+    multiply-adds, 45; diagonal form: 3 four-point differences plus 3
+    multiply-adds and the scale, 16), about 200 for the proxy right-hand side
+    (about 260 for the full model), and 4 per field for the RK update."""
+    return 24 * 9 + 24 * 11 + 12 * (16 if diagonal else 45) + (260 if full else 200) + 8 * 4
+
+
+def serving(torch, count, seed=1, rates=(10.0, 25.0, 50.0)):
     """Seeded Poisson trace (mean 200 jobs/s) of 2-D/3-D radius-3 advection-
     diffusion jobs, edges {64..384}, 10-500 steps, FP32/FP64 per request:
-    continuous-batching server vs plain FIFO per-job FP64 on the same GPU."""
+    continuous-batching server vs plain FIFO per-job FP64 on the same GPU.
+    The 200/s trace overloads the GPU (its offered work exceeds the HBM roof),
+    so the same jobs are also replayed at lower mean rates (arrival times
+    stretched by 200/rate) for latencies under a load the GPU can sustain.
+    The server runs its default policy (oldest first); the shortest-remaining-
+    work policy is timed beside it."""
+    import paper_2406_08923_amd as S_
     from paper_2406_08923_amd import inputs, serving as SV
     jobs = inputs.serving_trace(seed, count)
     inits = SV.make_inits(jobs)
@@ -368,11 +398,33 @@ def serving(torch, count, seed=1):
     torch.cuda.synchronize()
     fifo, res_f = SV.run_fifo_f64(jobs, inits)
     err = SV.compare(jobs, res_s, res_f)
+    del res_s, res_f
+    torch.cuda.synchronize()
+    shortest, _ = SV.run_served(jobs, inits, policy=S_.SERVE_SHORTEST)
+    keep = ("p50_s", "p99_s", "makespan_s", "point_steps_per_s")
+    sweep = {}
+    for rate in rates:
+        jr = [dict(j, arrival=j["arrival"] * 200.0 / rate) for j in jobs]
+        row = {}
+        for name, fn in (("served", lambda: SV.run_served(jr, inits)),
+                         ("fifo_f64", lambda: SV.run_fifo_f64(jr, inits)),
+                         ("served_shortest_first",
+                          lambda: SV.run_served(jr, inits, policy=S_.SERVE_SHORTEST))):
+            torch.cuda.synchronize()
+            res, _ = fn()
+            row[name] = {k: res[k] for k in keep}
+        sweep["%g_per_s" % rate] = row
+        print("serving at %g jobs/s: p99 served %.3f s, fifo %.3f s, shortest-first %.3f s" %
+              (rate, row["served"]["p99_s"], row["fifo_f64"]["p99_s"],
+               row["served_shortest_first"]["p99_s"]), file=sys.stderr, flush=True)
     return {"trace": "seed %d, %d jobs, Poisson 200/s, 50%% 3-D, edges 64..384, steps "
                      "10..500, 50%% FP32 requests" % (seed, count),
+            "policy": "oldest submission first, shorter jobs filling up to a quarter more",
             "served": served, "fifo_f64": fifo, "error_vs_fp64": err,
+            "served_shortest_first": {k: shortest[k] for k in keep},
             "speedup_point_steps_per_s": served["point_steps_per_s"] / fifo["point_steps_per_s"],
-            "p99_ratio_fifo_over_served": fifo["p99_s"] / served["p99_s"]}
+            "p99_ratio_fifo_over_served": fifo["p99_s"] / served["p99_s"],
+            "rate_sweep": sweep}
 
 
 def main():

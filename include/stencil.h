@@ -428,11 +428,21 @@ typedef struct stencil_server_desc {
     int use_graph;     /* replay each tick from one captured hipGraph */
     int blocks;        /* persistent workgroups per launch; 0 = 8 per CU */
     int queue_cap;     /* jobs waiting for admission at most; 0 = unlimited */
-    long long min_points; /* points per substep a tick gathers, shortest
-                             remaining work first, before it stops adding
-                             resident jobs (0 = 4 Mi; a huge value = every
-                             resident job every tick) */
+    long long min_points; /* points per substep a tick gathers before it
+                             stops adding resident jobs (0 = 4 Mi; a huge
+                             value = every resident job every tick) */
+    int policy;        /* order in which a tick takes resident jobs:
+                          STENCIL_SERVE_OLDEST (0, default) oldest
+                          submission first until min_points, then shorter
+                          jobs while the tick grows by at most a quarter (no
+                          job is passed by a later one: bounds the tail);
+                          STENCIL_SERVE_SHORTEST (1) least remaining work
+                          first, a job left out 16 ticks in a row taken
+                          regardless (lowest median under overload) */
 } stencil_server_desc;
+
+#define STENCIL_SERVE_OLDEST 0
+#define STENCIL_SERVE_SHORTEST 1
 
 typedef struct stencil_server_s *stencil_server_t;
 
@@ -448,7 +458,7 @@ typedef struct stencil_server_stats {
  * (first fit, in arrival order) while their state fits the HBM budget and a
  * slot is free, keeps admitted jobs' fields resident on the device, advances
  * them tick by tick (tick_steps RK steps each; a tick takes resident jobs in
- * order of least remaining work until it holds min_points points) and retires
+ * the order the policy sets until it holds min_points points) and retires
  * finished jobs (result copied out, memory freed). Jobs arriving while others
  * run are admitted at the next tick boundary. */
 stencil_status stencil_server_create(const stencil_server_desc *desc, stencil_server_t *out);

@@ -450,6 +450,8 @@ class RkPlan:
 # ---------------------------------------------------------------------------
 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELLED = range(5)
+# order in which a server tick takes resident jobs (stencil_server_desc.policy)
+SERVE_OLDEST, SERVE_SHORTEST = 0, 1
 
 
 class _Job(ctypes.Structure):
@@ -470,7 +472,7 @@ class _ServerDesc(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int),
                 ("tick_steps", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("blocks", ctypes.c_int), ("queue_cap", ctypes.c_int),
-                ("min_points", ctypes.c_longlong)]
+                ("min_points", ctypes.c_longlong), ("policy", ctypes.c_int)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -506,10 +508,10 @@ class Server:
     they are kept referenced until the job ends."""
 
     def __init__(self, hbm_budget=0, max_slots=256, tick_steps=10, use_graph=True, blocks=0,
-                 queue_cap=0, min_points=0):
+                 queue_cap=0, min_points=0, policy=SERVE_OLDEST):
         L = lib()
         d = _ServerDesc(hbm_budget, max_slots, tick_steps, 1 if use_graph else 0, blocks,
-                        queue_cap, min_points)
+                        queue_cap, min_points, policy)
         h = _vp()
         check(L.stencil_server_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

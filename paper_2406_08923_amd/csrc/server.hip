@@ -247,38 +247,67 @@ struct stencil_server_s {
     }
 
     // one tick; returns a status, *launches the number of kernel launches it
-    // enqueued. Shortest remaining work first: resident jobs are taken in
-    // order of remaining point-steps until the tick holds at least
-    // min_points points per substep (enough to fill the GPU), so short jobs
-    // finish within a few ticks while long ones keep the device busy; the
-    // others wait resident for a later tick. A job left out for STARVE_TICKS
-    // ticks in a row is taken regardless, so none waits without bound.
+    // enqueued. The tick takes resident jobs until it holds at least
+    // min_points points per substep (enough to fill the GPU); the others wait
+    // resident for a later tick. STENCIL_SERVE_OLDEST (the default) takes them
+    // in submission order (no job is passed by a later one, which bounds the
+    // tail as a first-come queue does), then adds shorter jobs, least
+    // remaining work first, while the tick's points grow by at most a quarter,
+    // so small jobs still pass a large one. STENCIL_SERVE_SHORTEST takes them
+    // in order of remaining point-steps, so short jobs finish within a few
+    // ticks while long ones keep the device busy (the lowest median latency
+    // under overload, at the cost of the tail); a job left out for
+    // STARVE_TICKS ticks in a row is taken regardless, so none waits without
+    // bound.
     int tick(long long *launches)
     {
         auto *hdr = static_cast<BatchTableHeader *>(h_table);
         auto *rec = reinterpret_cast<BatchJob *>(hdr + 1);
         std::vector<std::shared_ptr<SJob>> order(active);
-        auto remaining = [](const SJob &j) {
-            return (double)(j.bj.g.nx) * j.bj.g.ny * j.bj.g.nz * (double)(j.d.steps - j.steps_done);
+        auto pts = [](const SJob &j) { return (double)(j.bj.g.nx) * j.bj.g.ny * j.bj.g.nz; };
+        auto remaining = [&](const SJob &j) { return pts(j) * (double)(j.d.steps - j.steps_done); };
+        auto by_remaining = [&](const std::shared_ptr<SJob> &a, const std::shared_ptr<SJob> &b) {
+            return remaining(*a) < remaining(*b);
         };
-        std::stable_sort(order.begin(), order.end(),
-                         [&](const std::shared_ptr<SJob> &a, const std::shared_ptr<SJob> &b) {
-                             return remaining(*a) < remaining(*b);
-                         });
+        if (d.policy == STENCIL_SERVE_OLDEST)
+            std::stable_sort(order.begin(), order.end(),
+                             [](const std::shared_ptr<SJob> &a, const std::shared_ptr<SJob> &b) {
+                                 return a->ticket < b->ticket;
+                             });
+        else
+            std::stable_sort(order.begin(), order.end(), by_remaining);
         for (auto &j : active)
             j->steps_tick = 0;
         int maxsteps = 0, nsel = 0;
         double points = 0;
         std::vector<SJob *> sel;
-        for (auto &jp : order) {
-            SJob &j = *jp;
-            if (nsel > 0 && points >= (double)min_points && j.idle_ticks < STARVE_TICKS)
-                continue;
+        auto take = [&](SJob &j) {
             j.steps_tick = (int)std::min<long long>(d.tick_steps, j.d.steps - j.steps_done);
             maxsteps = std::max(maxsteps, j.steps_tick);
-            points += (double)j.bj.g.nx * j.bj.g.ny * j.bj.g.nz;
+            points += pts(j);
             sel.push_back(&j);
             ++nsel;
+        };
+        if (d.policy == STENCIL_SERVE_OLDEST) {
+            std::vector<std::shared_ptr<SJob>> rest;
+            for (auto &jp : order) {
+                if (nsel == 0 || points < (double)min_points)
+                    take(*jp);
+                else
+                    rest.push_back(jp);
+            }
+            std::stable_sort(rest.begin(), rest.end(), by_remaining);
+            const double cap = 1.25 * points;
+            for (auto &jp : rest)
+                if (points + pts(*jp) <= cap)
+                    take(*jp);
+        } else {
+            for (auto &jp : order) {
+                SJob &j = *jp;
+                if (nsel > 0 && points >= (double)min_points && j.idle_ticks < STARVE_TICKS)
+                    continue;
+                take(j);
+            }
         }
         // table: the 2-D jobs (per-point tiles), then the 3-D jobs (z-march
         // tiles), each kind numbering its own work items
@@ -512,6 +541,8 @@ stencil_status stencil_server_create(const stencil_server_desc *desc, stencil_se
         return fail(STENCIL_EINVAL, "tick_steps must be 1..10000");
     if (desc->blocks < 0 || desc->queue_cap < 0)
         return fail(STENCIL_EINVAL, "blocks and queue_cap must be >= 0");
+    if (desc->policy != STENCIL_SERVE_SHORTEST && desc->policy != STENCIL_SERVE_OLDEST)
+        return fail(STENCIL_EINVAL, "policy must be STENCIL_SERVE_SHORTEST or STENCIL_SERVE_OLDEST");
     auto *s = new (std::nothrow) stencil_server_s();
     if (!s)
         return fail(STENCIL_ENOMEM, "out of host memory");

@@ -91,6 +91,20 @@ def test_batch_matches_solo_mix_and_graph_bitwise():
         assert np.array_equal(mix[k], solo_path(*job)), k
 
 
+@pytest.mark.parametrize("min_points", [0, 3000, 1 << 40])
+def test_both_policies_give_the_same_results(min_points):
+    # the policy only changes which resident jobs a tick takes: every job's
+    # result is bitwise that of the other policy and of the solo path, with
+    # a tick size that fits all jobs, some, or one at a time
+    ref, _ = run_server(JOBS, tick_steps=3, max_slots=16, policy=S.SERVE_SHORTEST)
+    old, stats = run_server(JOBS, tick_steps=3, max_slots=16, min_points=min_points,
+                            policy=S.SERVE_OLDEST)
+    assert stats["completed"] == len(JOBS) and stats["failed"] == 0
+    for k, job in enumerate(JOBS):
+        assert np.array_equal(old[k], ref[k]), k
+        assert np.array_equal(old[k], solo_path(*job)), k
+
+
 @pytest.mark.parametrize("k", range(len(JOBS)))
 def test_server_jobs_match_oracle(k):
     dims, steps, prec, c, nu, seed = JOBS[k]
@@ -182,6 +196,8 @@ def test_nan_job_is_isolated():
 
 
 def test_submit_validation_and_queue_cap():
+    with pytest.raises(S.StencilError):
+        S.Server(max_slots=1, tick_steps=1, policy=2)
     srv = S.Server(max_slots=1, tick_steps=1, queue_cap=1)
     with pytest.raises(S.StencilError):
         srv.submit(np.zeros((2, 8)), 3)  # dims < 3
