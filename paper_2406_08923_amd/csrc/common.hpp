@@ -210,4 +210,48 @@ __device__ __forceinline__ void store_periodic(S *out, const Geo &g, int x, int 
                     Store<S>::st(out + g.at(xs[ix], ys[iy], zs[iz]), v);
 }
 
+// Periodic images of one interior point on a grid whose axes all hold at
+// least 2r points (then a point has at most one image per axis): the element
+// offsets of its x, y and z images, 0 where it has none. A kernel that stores
+// several fields at the point computes them once. Offsets fit 32 bits for
+// arrays below 4 GiB.
+struct PointImages {
+    int32_t dx, dy, dz;
+};
+
+__host__ __device__ inline bool images_simple(const Geo &g)
+{
+    return g.nx >= 2 * g.r && (!g.ry || g.ny >= 2 * g.r) && (!g.rz || g.nz >= 2 * g.r);
+}
+
+__device__ __forceinline__ PointImages point_images(const Geo &g, int x, int y, int z)
+{
+    const int r = g.r;
+    PointImages m;
+    m.dx = x < r ? g.nx : x >= g.nx - r ? -g.nx : 0;
+    m.dy = !g.ry ? 0 : (y < r ? g.ny : y >= g.ny - r ? -g.ny : 0) * int32_t(g.sy);
+    m.dz = !g.rz ? 0 : (z < r ? g.nz : z >= g.nz - r ? -g.nz : 0) * int32_t(g.sz);
+    return m;
+}
+
+// store_periodic for a point whose images point_images gave
+template <typename S>
+__device__ __forceinline__ void store_images(S *out, int64_t p, const PointImages &m,
+                                             typename Store<S>::C v, bool fuse)
+{
+    S *const q = out + p;
+    Store<S>::st(q, v);
+    if (!fuse || !(m.dx | m.dy | m.dz))
+        return;
+    if (m.dx) Store<S>::st(q + m.dx, v);
+    if (m.dy) Store<S>::st(q + m.dy, v);
+    if (m.dx && m.dy) Store<S>::st(q + m.dx + m.dy, v);
+    if (m.dz) {
+        Store<S>::st(q + m.dz, v);
+        if (m.dx) Store<S>::st(q + m.dz + m.dx, v);
+        if (m.dy) Store<S>::st(q + m.dz + m.dy, v);
+        if (m.dx && m.dy) Store<S>::st(q + m.dz + m.dx + m.dy, v);
+    }
+}
+
 } // namespace stn

@@ -303,8 +303,7 @@ __global__ void __launch_bounds__(BX *BY *BZ)
     mhd_phi<MODEL, C>(bank, a.mhd, R);
     const C val[8] = {vl, bank.u[0], bank.u[1], bank.u[2], vs, bank.A[0], bank.A[1], bank.A[2]};
     const int64_t p = g.at(x, y, z);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    auto io_of = [&](int k) {
         PointIO io;
         io.fout = a.fout[k];
         io.wrd = a.wrd[k];
@@ -317,7 +316,20 @@ __global__ void __launch_bounds__(BX *BY *BZ)
         for (int q = 0; q < 3; ++q) io.beta_all[q] = a.beta_all[q];
         io.stage = a.stage;
         io.fuse = a.fuse;
-        rk_update<S, W, C, MASTER>(io, g, p, x, y, z, R[k], val[k]);
+        return io;
+    };
+    // the point's periodic images, found once for the eight stores (this
+    // also freed the FP64 full model's spilled registers); with FP32 storage
+    // it measured slower, so that policy finds them per store
+    if (sizeof(S) != 4 && images_simple(g)) {
+        const PointImages im = point_images(g, x, y, z);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            rk_update<S, W, C, MASTER, true>(io_of(k), g, p, x, y, z, R[k], val[k], &im);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            rk_update<S, W, C, MASTER>(io_of(k), g, p, x, y, z, R[k], val[k]);
     }
 }
 

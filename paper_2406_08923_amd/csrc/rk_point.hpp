@@ -88,38 +88,47 @@ struct PointIO {
 // The update with its reads already done: wold = the register (read when
 // stage > 0), w1v and mst = the first-stage register and the FP64 state
 // (read at the master policies' last stage); unused otherwise.
-template <typename S, typename W, typename C, bool MASTER>
+// IMG: the point's periodic images come precomputed in *im (point_images on
+// a grid with images_simple), else store_periodic finds them.
+template <typename S, typename W, typename C, bool MASTER, bool IMG = false>
 __device__ __forceinline__ void rk_update_pre(const PointIO &io, const Geo &g, int64_t p, int x,
-                                              int y, int z, C R, C fc, W wold, W w1v, double mst)
+                                              int y, int z, C R, C fc, W wold, W w1v, double mst,
+                                              const PointImages *im = nullptr)
 {
     const C dt = C(io.dt);
     C wn = dt * R;
     if (io.stage > 0)
         wn = fma(C(io.alpha), C(wold), wn);
+    auto store = [&](C v) {
+        if constexpr (IMG)
+            store_images(static_cast<S *>(io.fout), p, *im, v, io.fuse != 0);
+        else
+            store_periodic(static_cast<S *>(io.fout), g, x, y, z, v, io.fuse != 0);
+    };
     if (MASTER && io.stage == 2) {
         double f = mst;
         f = fma(io.beta_all[0], double(w1v), f);
         f = fma(io.beta_all[1], double(wold), f);
         f = fma(io.beta_all[2], double(wn), f);
         io.master[p] = f;
-        store_periodic(static_cast<S *>(io.fout), g, x, y, z, C(f), io.fuse != 0);
+        store(C(f));
         return;
     }
     if (io.stage < 2)
         static_cast<W *>(io.wwr)[p] = W(wn);
-    store_periodic(static_cast<S *>(io.fout), g, x, y, z, fma(C(io.beta), wn, fc),
-                   io.fuse != 0);
+    store(fma(C(io.beta), wn, fc));
 }
 
-template <typename S, typename W, typename C, bool MASTER>
+template <typename S, typename W, typename C, bool MASTER, bool IMG = false>
 __device__ __forceinline__ void rk_update(const PointIO &io, const Geo &g, int64_t p, int x,
-                                          int y, int z, C R, C fc)
+                                          int y, int z, C R, C fc,
+                                          const PointImages *im = nullptr)
 {
     const W wold = io.stage > 0 ? static_cast<const W *>(io.wrd)[p] : W(0);
     const bool last = MASTER && io.stage == 2;
     const W w1v = last ? static_cast<const W *>(io.w1)[p] : W(0);
     const double mst = last ? io.master[p] : 0.0;
-    rk_update_pre<S, W, C, MASTER>(io, g, p, x, y, z, R, fc, wold, w1v, mst);
+    rk_update_pre<S, W, C, MASTER, IMG>(io, g, p, x, y, z, R, fc, wold, w1v, mst, im);
 }
 
 // Scalar advection-diffusion R = -c.grad f + nu lap f at interior point
