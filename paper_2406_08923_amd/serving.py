@@ -37,7 +37,7 @@ def _percentiles(lat):
             "max_s": float(a[-1]), "mean_s": float(a.mean())}
 
 
-def run_served(jobs, inits, tick_steps=8, max_slots=512, use_graph=True, min_points=0,
+def run_served(jobs, inits, tick_steps=16, max_slots=512, use_graph=True, min_points=0,
                policy=SERVE_OLDEST):
     srv = Server(max_slots=max_slots, tick_steps=tick_steps, use_graph=use_graph,
                  min_points=min_points, policy=policy)

@@ -331,11 +331,15 @@ def test_star_two_iterations_tiny_and_thin_grids(dims, r, tile):
         assert np.array_equal(got, O.fill_periodic(got.copy(), r))
 
 
-def test_star_two_iterations_pitched_layout():
+@pytest.mark.parametrize("dtype,tile", [(S.F32, (8, 2, 32, 0x2101)), (S.F64, (12, 2, 16, 0x12101)),
+                                        (S.BF16, (8, 2, 16, 0x12105))])
+def test_star_two_iterations_pitched_layout(dtype, tile):
+    # rows of 128 elements with the interior at column 32, in the row and the
+    # pair LDS layouts
     dims, r = (70, 45, 37), 3
     g = diffusion_star_exact(3, 3, 0.0815)
-    got, _, inner = run_star_iters(dims, r, g, S.F32, (8, 2, 32, 0x2101), 6, layout=(128, 32))
-    ref, _, _ = run_star_iters(dims, r, g, S.F32, ONE_TILE, 6)
+    got, _, inner = run_star_iters(dims, r, g, dtype, tile, 6, layout=(128, 32))
+    ref, _, _ = run_star_iters(dims, r, g, dtype, ONE_TILE, 6)
     assert np.array_equal(got, ref)
 
 

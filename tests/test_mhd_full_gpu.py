@@ -88,6 +88,39 @@ def test_full_mhd_substep_f64(stage, bank):
             assert np.array_equal(gw, O.interior(w0[k], 3))  # dead register not written
 
 
+@pytest.mark.parametrize("model", [S.MODEL_MHD8, S.MODEL_MHD_FULL])
+@pytest.mark.parametrize("n", [(20, 4, 5), (6, 7, 9)])
+def test_lds_bank_short_axes_and_their_halo_images(n, model):
+    # axes shorter than 2r (a point has two images along them: the general
+    # image search) and axes of exactly 2r (one image each side: the images
+    # found once per point); the whole padded output, halo included, against
+    # the oracle at every stage
+    ds = ds_of(n)
+    dt = 0.1 * min(ds)
+    f = fields(n, 5, kmax=1)
+    rng = np.random.default_rng(6)
+    mhd = MHD if model == S.MODEL_MHD_FULL else None
+    for stage in (0, 1, 2):
+        print("short axes %s model %d stage %d" % (n, model, stage), flush=True)
+        plan = S.RkPlan(model, n, S.PREC_F64, variant=S.RK_LDS, mhd=mhd, **KW)
+        b = plan.alloc()
+        fin = [O.pad_periodic(v, 3) for v in f]
+        w0 = [rng.uniform(-1e-2, 1e-2, fin[0].shape) for _ in range(8)]
+        for k in range(8):
+            put(b["f_a"][k], fin[k])
+            put(b["w"][k], w0[k])
+            b["f_b"][k].fill_(-9.0)
+        plan.step(b["f_a"], b["f_b"], b["w"], stage, dt)
+        torch.cuda.synchronize()
+        w_ref = [a.copy() for a in w0]
+        omodel = O.MODEL_MHD_FULL if model == S.MODEL_MHD_FULL else O.MODEL_MHD8
+        ref = O.rk3_substep(omodel, stage, fin, w_ref, ds, dt, mhd=mhd, **KW)
+        for k in range(8):
+            got = host(b["f_b"][k])
+            assert relerr(got, ref[k]) <= 1e-12, (n, stage, k, relerr(got, ref[k]))
+            assert np.array_equal(got, O.fill_periodic(got.copy(), 3)), (n, stage, k)
+
+
 def test_full_mhd_right_hand_side_terms_reach_the_update():
     # dt R is the stage-0 register: compare it with the oracle's right-hand
     # side directly, per field, on a state where every closure term is active
