@@ -355,7 +355,11 @@ stencil_status stencil_step(stencil_plan_t plan, const stencil_fields *fields, i
  * halo is refreshed first) and f_in / f_out are used in ping-pong, so the
  * result is in f_out when nsteps is odd and in f_in when even. Registers and
  * the master (master policies: f64 must hold the FP64 copy of f_in) as in
- * stencil_step. */
+ * stencil_step. A 2-D FP64 advection-diffusion plan created with the
+ * automatic variant on an nx x ny grid with nx, ny >= 6, nx ny <= 5200 and
+ * (nx + 6)(ny + 6) <= 7000 runs the whole call in one launch with its state
+ * in LDS (temporal blocking of small grids); the buffers end as the substep
+ * launches would leave them, bit for bit. */
 stencil_status stencil_rk_run(stencil_plan_t plan, const stencil_fields *fields, int nsteps,
                               double dt, void *stream);
 

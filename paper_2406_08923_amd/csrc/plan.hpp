@@ -45,6 +45,7 @@ struct RkPlan {
     int variant = STENCIL_RK_VARIANT_CACHED;
     int bx = 64, by = 4, bz = 1; // CACHED: lanes; LDS: brick
     size_t store_size = 8, reg_size = 8; // bytes per element of f and of w
+    int resident = 0; // run whole runs in one launch in LDS (small 2-D FP64 advection)
 };
 
 // validation helpers shared by the C-ABI translation units

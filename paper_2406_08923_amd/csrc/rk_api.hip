@@ -264,6 +264,10 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
         P.bz = advdiff_zmarch_lz(P.g);
     P.store_size = dtype_size(store_dtype(P.policy));
     P.reg_size = P.policy == POL_F64 ? 8 : 4;
+    // AUTO, 2-D FP64 advection grid small enough for LDS: stencil_rk_run keeps
+    // the state in LDS for the whole run (one launch)
+    P.resident = d->variant == STENCIL_RK_VARIANT_AUTO && d->model == STENCIL_MODEL_ADVDIFF &&
+                 P.policy == POL_F64 && resident_fits(d->ndim, d->dims[0], d->dims[1]);
     *out = p;
     return STENCIL_OK;
 }
@@ -312,6 +316,35 @@ stencil_status stencil_rk_run(stencil_plan_t p, const stencil_fields *f, int nst
     if (nsteps == 0)
         return STENCIL_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->rk.resident) {
+        // the whole run in LDS; the states land where 3 nsteps substeps with
+        // ping-pong buffers would leave them (the last in f_out when 3 nsteps
+        // is odd), the register as the last substep that wrote it left it
+        const RkPlan &P = p->rk;
+        ResidentArgs ra{};
+        const bool odd = (nsteps & 1) != 0;
+        ra.fin = static_cast<const double *>(f->f_in[0]);
+        ra.out_last = static_cast<double *>(odd ? f->f_out[0] : f->f_in[0]);
+        ra.out_prev = static_cast<double *>(odd ? f->f_in[0] : f->f_out[0]);
+        ra.w = static_cast<double *>(f->w[0]);
+        ra.g = P.g;
+        ra.fd = P.fd;
+        for (int a = 0; a < 2; ++a) {
+            ra.inv_ds[a] = P.inv_ds[a];
+            ra.adv[a] = P.adv[a];
+        }
+        ra.nu = P.nu;
+        ra.dt = dt;
+        for (int i = 0; i < 3; ++i) {
+            ra.alpha[i] = RK_ALPHA[i];
+            ra.beta[i] = RK_BETA[i];
+        }
+        ra.nsteps = nsteps;
+        rc = launch_rk_advdiff2_resident(ra, s);
+        if (rc == STENCIL_EDEVICE)
+            p->sticky = rc;
+        return rc;
+    }
     switch (store_dtype(p->rk.policy)) {
     case STENCIL_F64: rc = halo_fields<double>(p, f->f_in, s); break;
     case STENCIL_F32: rc = halo_fields<float>(p, f->f_in, s); break;

@@ -271,6 +271,95 @@ int launch_rk_advdiff3_zm(int policy, const RkArgs &a, int lz, hipStream_t s)
     return fail(STENCIL_EINVAL, "unknown precision policy %d", policy);
 }
 
+// Every step of a run of a small 2-D FP64 advection-diffusion grid, in LDS:
+// one 1024-lane workgroup holds both states with a 3-cell periodic halo (each
+// point also writes its images into the halo, so taps are fixed offsets and
+// a substep needs one barrier), runs 3 nsteps substeps and writes the two
+// last states (with their periodic images) and the register back. The point
+// arithmetic is the per-substep kernel's (d12_vals, advdiff_axis,
+// rk_register, the same update), so the states are bitwise those of
+// 3 nsteps substep launches; HBM is touched once per run.
+constexpr int RES_THREADS = 1024, RES_PER = (RES_MAX_POINTS + RES_THREADS - 1) / RES_THREADS;
+
+__global__ void __launch_bounds__(RES_THREADS) k_rk_advdiff2_resident(ResidentArgs a)
+{
+    __shared__ double lf[2][RES_MAX_CELLS];
+    __shared__ double lw[RES_MAX_POINTS];
+    const Geo &g = a.g;
+    const int nx = g.nx, ny = g.ny, n = nx * ny, lw_ = nx + 6;
+    // the lane's points: LDS cell and the cell offsets of their x / y images
+    int cell[RES_PER], dxi[RES_PER], dyi[RES_PER];
+#pragma unroll
+    for (int k = 0; k < RES_PER; ++k) {
+        const int p = threadIdx.x + k * RES_THREADS;
+        const int x = p < n ? p % nx : 0, y = p < n ? p / nx : 0;
+        cell[k] = (y + 3) * lw_ + x + 3;
+        dxi[k] = x < 3 ? nx : x >= nx - 3 ? -nx : 0;
+        dyi[k] = (y < 3 ? ny : y >= ny - 3 ? -ny : 0) * lw_;
+    }
+    auto put = [&](double *f, int k, double v) {
+        const int c = cell[k];
+        f[c] = v;
+        if (dxi[k]) f[c + dxi[k]] = v;
+        if (dyi[k]) f[c + dyi[k]] = v;
+        if (dxi[k] && dyi[k]) f[c + dxi[k] + dyi[k]] = v;
+    };
+#pragma unroll
+    for (int k = 0; k < RES_PER; ++k) {
+        const int p = threadIdx.x + k * RES_THREADS;
+        if (p < n) {
+            put(lf[0], k, a.fin[g.at(p % nx, p / nx, 0)]);
+            lw[p] = 0.0;
+        }
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int step = 0; step < a.nsteps; ++step) {
+        for (int stage = 0; stage < 3; ++stage) {
+            const double *f = lf[cur];
+            double *fo = lf[cur ^ 1];
+#pragma unroll
+            for (int k = 0; k < RES_PER; ++k) {
+                const int p = threadIdx.x + k * RES_THREADS;
+                if (p >= n)
+                    break;
+                const double *q = f + cell[k];
+                const double c0 = q[0];
+                double a1, a2, R = 0;
+                d12_vals(c0, q[-1], q[1], q[-2], q[2], q[-3], q[3], a.fd, a1, a2);
+                R = advdiff_axis(R, a1, a2, a.adv[0], a.inv_ds[0], a.nu);
+                d12_vals(c0, q[-lw_], q[lw_], q[-2 * lw_], q[2 * lw_], q[-3 * lw_], q[3 * lw_],
+                         a.fd, a1, a2);
+                R = advdiff_axis(R, a1, a2, a.adv[1], a.inv_ds[1], a.nu);
+                const double wn = rk_register<double, double>(a.dt, a.alpha[stage], stage, R, lw[p]);
+                if (stage < 2)
+                    lw[p] = wn;
+                put(fo, k, fma(a.beta[stage], wn, c0));
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RES_PER; ++k) {
+        const int p = threadIdx.x + k * RES_THREADS;
+        if (p < n) {
+            const int x = p % nx, y = p / nx;
+            store_periodic(a.out_last, g, x, y, 0, lf[cur][cell[k]], true);
+            store_periodic(a.out_prev, g, x, y, 0, lf[cur ^ 1][cell[k]], true);
+            a.w[g.at(x, y, 0)] = lw[p];
+        }
+    }
+}
+
+int launch_rk_advdiff2_resident(const ResidentArgs &a, hipStream_t s)
+{
+    if (!resident_fits(a.g.ndim, a.g.nx, a.g.ny) || a.nsteps < 1)
+        return fail(STENCIL_EINVAL, "resident run: a 2-D grid of at most %d points", RES_MAX_POINTS);
+    hipLaunchKernelGGL(k_rk_advdiff2_resident, dim3(1), dim3(RES_THREADS), 0, s, a);
+    return check_launch("rk_advdiff2_resident");
+}
+
 int launch_rk_advdiff(int policy, const RkArgs &a, int bx, int by, hipStream_t s)
 {
     const bool d3 = a.g.ndim == 3;

@@ -67,6 +67,28 @@ int launch_rk_mhd8(int model, int mixed, int policy, const RkArgs &a, int bx, in
 int launch_rk_mhd8_lds(int model, int mixed, int policy, const RkArgs &a, int bx, int by,
                        int bz, hipStream_t s);
 int launch_rk_advdiff(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
+// Small 2-D FP64 advection-diffusion grids whose state fits in LDS: every
+// step of a run in one launch of one workgroup (k_rk_advdiff2_resident).
+// LDS: two states with a 3-cell halo (at most RES_MAX_CELLS cells each) and
+// the register (at most RES_MAX_POINTS), FP64: 8 B x (2 x 7000 + 5200) = 150 KiB
+constexpr int RES_MAX_POINTS = 5200, RES_MAX_CELLS = 7000;
+inline bool resident_fits(int ndim, int nx, int ny)
+{
+    return ndim == 2 && nx >= 6 && ny >= 6 && int64_t(nx) * ny <= RES_MAX_POINTS &&
+           int64_t(nx + 6) * (ny + 6) <= RES_MAX_CELLS;
+}
+struct ResidentArgs {
+    const double *fin;  // padded input state
+    double *out_last;   // receives the last substep's state (with its images)
+    double *out_prev;   // receives the state of the substep before it
+    double *w;          // the register, as the last substep that wrote it left it
+    Geo g;
+    FdWeights fd;
+    double inv_ds[2], adv[2], nu, dt;
+    double alpha[3], beta[3];
+    int nsteps;
+};
+int launch_rk_advdiff2_resident(const ResidentArgs &a, hipStream_t s);
 // 3-D advection-diffusion substep as a z march (64 x 16 tiles, lz planes)
 int launch_rk_advdiff3_zm(int policy, const RkArgs &a, int lz, hipStream_t s);
 // z planes per tile of the z march (solo and batched)

@@ -13,7 +13,18 @@ namespace stn {
 // its radius-3 neighbourhood, so every tap offset (bytes, wave-uniform) is
 // non-negative: c is the centre's offset, st the axis stride in bytes.
 
-// d1 (unit spacing) and d2 (unit spacing) along one axis.
+// d1 (unit spacing) and d2 (unit spacing) along one axis from the centre c0
+// and the taps m_k / q_k at -k / +k.
+template <typename C>
+__device__ __forceinline__ void d12_vals(C c0, C m1, C q1, C m2, C q2, C m3, C q3,
+                                         const FdWeights &w, C &d1, C &d2)
+{
+    d1 = C(w.w1[0]) * (q1 - m1) + C(w.w1[1]) * (q2 - m2) + C(w.w1[2]) * (q3 - m3);
+    d2 = C(w.w2[0]) * c0 + C(w.w2[1]) * (q1 + m1) + C(w.w2[2]) * (q2 + m2) +
+         C(w.w2[3]) * (q3 + m3);
+}
+
+// d1 and d2 along one axis, taps read from the buffer.
 template <typename S, typename C>
 __device__ __forceinline__ void d12(const Buf &b, uint32_t vo, uint32_t c, uint32_t st,
                                     const FdWeights &w, C &d1, C &d2, C &c0)
@@ -22,9 +33,28 @@ __device__ __forceinline__ void d12(const Buf &b, uint32_t vo, uint32_t c, uint3
     C m1 = BufLd<S>::ld(b, vo, c - st), q1 = BufLd<S>::ld(b, vo, c + st);
     C m2 = BufLd<S>::ld(b, vo, c - 2 * st), q2 = BufLd<S>::ld(b, vo, c + 2 * st);
     C m3 = BufLd<S>::ld(b, vo, c - 3 * st), q3 = BufLd<S>::ld(b, vo, c + 3 * st);
-    d1 = C(w.w1[0]) * (q1 - m1) + C(w.w1[1]) * (q2 - m2) + C(w.w1[2]) * (q3 - m3);
-    d2 = C(w.w2[0]) * c0 + C(w.w2[1]) * (q1 + m1) + C(w.w2[2]) * (q2 + m2) +
-         C(w.w2[3]) * (q3 + m3);
+    d12_vals(c0, m1, q1, m2, q2, m3, q3, w, d1, d2);
+}
+
+// One axis of the advection-diffusion right-hand side added to R:
+// R - c_a/ds_a d1 + nu/ds_a^2 d2.
+template <typename C>
+__device__ __forceinline__ C advdiff_axis(C R, C a1, C a2, double adv, double inv_ds, double nu)
+{
+    const C id = C(inv_ds);
+    R = fma(-C(adv) * id, a1, R);
+    return fma(C(nu) * id * id, a2, R);
+}
+
+// The new register of the 2N scheme: w = alpha w + dt R (w not read at the
+// first stage).
+template <typename C, typename W>
+__device__ __forceinline__ C rk_register(double dt, double alpha, int stage, C R, W wold)
+{
+    C wn = C(dt) * R;
+    if (stage > 0)
+        wn = fma(C(alpha), C(wold), wn);
+    return wn;
 }
 
 // d_a d_b (unit spacing), byte strides sa, sb: tensor product of the
@@ -95,10 +125,7 @@ __device__ __forceinline__ void rk_update_pre(const PointIO &io, const Geo &g, i
                                               int y, int z, C R, C fc, W wold, W w1v, double mst,
                                               const PointImages *im = nullptr)
 {
-    const C dt = C(io.dt);
-    C wn = dt * R;
-    if (io.stage > 0)
-        wn = fma(C(io.alpha), C(wold), wn);
+    const C wn = rk_register<C, W>(io.dt, io.alpha, io.stage, R, wold);
     auto store = [&](C v) {
         if constexpr (IMG)
             store_images(static_cast<S *>(io.fout), p, *im, v, io.fuse != 0);
@@ -149,9 +176,7 @@ __device__ __forceinline__ void advdiff_point(const void *fin, const PointIO &io
     for (int ax = 0; ax < NDIM; ++ax) {
         C a1, a2;
         d12<S, C>(fb, vo, c, st[ax], fd, a1, a2, c0);
-        const C id = C(inv_ds[ax]);
-        R = fma(-C(adv[ax]) * id, a1, R);
-        R = fma(C(nu) * id * id, a2, R);
+        R = advdiff_axis(R, a1, a2, adv[ax], inv_ds[ax], nu);
     }
     rk_update<S, W, C, MASTER>(io, g, p, x, y, z, R, c0);
 }

@@ -149,6 +149,39 @@ def test_advdiff_steps_f64(n):
     assert relerr(host(res[0]), ref[0]) <= 1e-12
 
 
+@pytest.mark.parametrize("n,layout", [((48, 40), (0, 0)), ((72, 72), (0, 0)), ((64, 6), (0, 0)),
+                                      ((50, 37), (70, 8))])
+@pytest.mark.parametrize("steps", [1, 2, 7])
+def test_advdiff_resident_run_bitwise_equal_to_substep_launches(n, layout, steps):
+    # a small 2-D FP64 plan with the automatic variant keeps the whole run in
+    # LDS (one launch); the per-point variant launches every substep. Both
+    # state buffers (with their halos) and the register must agree bitwise.
+    ds = ds_of(n)
+    c = (0.6, -0.8)
+    dt = 0.1 * min(ds) / max(1.0, max(abs(v) for v in c))
+    f0 = inputs.uniform_field(n, 9)
+    outs = []
+    for variant in (0, S.RK_CACHED):
+        plan = S.RkPlan(S.MODEL_ADVDIFF, n, S.PREC_F64, nu=0.02, adv=c, variant=variant,
+                        row_pitch=layout[0], x_offset=layout[1])
+        b = plan.alloc()
+        pad = O.pad_periodic(f0, 3)
+        plan.padded(b["f_a"][0]).copy_(torch.from_numpy(pad).cuda())
+        b["f_b"][0].fill_(-7.0)
+        b["w"][0].fill_(0.0)
+        res = plan.run(b["f_a"], b["f_b"], b["w"], steps, dt)
+        torch.cuda.synchronize()
+        outs.append([host(plan.padded(b["f_a"][0])), host(plan.padded(b["f_b"][0])),
+                     O.interior(host(plan.padded(b["w"][0])), 3),
+                     res[0].data_ptr() == b["f_b"][0].data_ptr()])
+    for k in range(4):
+        assert np.array_equal(outs[0][k], outs[1][k]), (n, steps, k)
+    assert outs[0][3] == (steps % 2 == 1)
+    ref = O.rk3_steps(O.MODEL_ADVDIFF, [O.pad_periodic(f0, 3)], ds, dt, steps, nu=0.02, c=c)
+    last = outs[0][1] if steps % 2 else outs[0][0]
+    assert relerr(last, ref[0]) <= 1e-12
+
+
 def run_policy(n, prec, f, steps, dt, model=S.MODEL_MHD8, **kw):
     plan = S.RkPlan(model, n, prec, **kw)
     b = plan.alloc()
