@@ -182,7 +182,10 @@ stencil_status stencil_plan_tile(stencil_plan_t plan, int tile[4]);
  * one and writes the other, starting d_a -> d_b, so the result is in d_b when
  * iters is odd and in d_a when even (iters = 0 does nothing).
  * PERIODIC: d_a's halo may be refreshed (its halo cells written) before the
- * first iteration, and every result carries a valid periodic halo.
+ * first iteration, and the result carries a valid periodic halo; the other
+ * buffer's contents are unspecified on return (launches of two iterations
+ * never materialise the odd iterate, and only the last of them writes its
+ * output's halo).
  * USER_HALO: iters must be 1; the caller's halo of d_a is read and only the
  * interior of d_b is written. */
 stencil_status stencil_apply(stencil_plan_t plan, void *d_a, void *d_b, int iters,

@@ -171,8 +171,10 @@ int apply_t(stencil_plan_s *p, void *da, void *db, int iters, hipStream_t s, boo
     if (p->lin.bc == STENCIL_BC_PERIODIC && p->lin.variant == STENCIL_VARIANT_STAR3D &&
         p->lin.tstar == 2 && p->lin.op == STENCIL_OP_XCORR) {
         // nl launches of two or one iterations, nl of the parity of iters;
-        // the two-iteration launches come first (they read the input with
-        // periodic wrap, not its halo, and write their output's images)
+        // the two-iteration launches come first. They read the input with
+        // periodic wrap, never its halo, so only the last of them writes
+        // its output's periodic images (which the one-iteration launches
+        // after it and the caller read).
         int nl = (iters + 1) / 2;
         if ((nl & 1) != (iters & 1))
             ++nl;
@@ -183,7 +185,8 @@ int apply_t(stencil_plan_s *p, void *da, void *db, int iters, hipStream_t s, boo
             rc = launch_halo<S>(a, p->lin.g, s);
         for (int k = 0; k < n2 && rc == STENCIL_OK; ++k) {
             rc = launch_star3d_t2(a, b, p->lin.g, p->lin.star, p->lin.reff, p->lin.xw, p->lin.ty,
-                                  p->lin.ny, p->lin.lz, fl, s);
+                                  p->lin.ny, p->lin.lz, fl | (k + 1 < n2 ? STAR_FLAG_NOFUSE : 0),
+                                  s);
             std::swap(a, b);
         }
         const int *q = p->lin.s1;
