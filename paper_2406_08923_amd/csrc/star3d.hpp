@@ -505,10 +505,15 @@ int launch_star3d_t2_t(const S *in, S *out, const Geo &g,
     int64_t total = (int64_t)gx * gy * gz;
     if (total > 0x7fffffff)
         return fail(STENCIL_EUNSUPPORTED, "star3d (two iterations): grid too large");
+    const bool img = (flags & STAR_FLAG_NOFUSE) == 0;
     if (flags & STAR_FLAG_PAIRS) {
         if constexpr (NY == 2 && R <= 3 && 64 * XW * TY <= 768) {
-            hipLaunchKernelGGL((k_star3d_t2p<S, R, TY, XW>), dim3((unsigned)total),
-                               dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+            if (img)
+                hipLaunchKernelGGL((k_star3d_t2p<S, R, TY, XW, true>), dim3((unsigned)total),
+                                   dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+            else
+                hipLaunchKernelGGL((k_star3d_t2p<S, R, TY, XW, false>), dim3((unsigned)total),
+                                   dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
             return check_launch("xcorr_star3d_t2 (pair layout)");
         } else {
             return fail(STENCIL_EUNSUPPORTED,
@@ -516,8 +521,12 @@ int launch_star3d_t2_t(const S *in, S *out, const Geo &g,
                         "radius <= 3 and at most 768 lanes");
         }
     }
-    hipLaunchKernelGGL((k_star3d_t2<S, R, NY, TY, XW>), dim3((unsigned)total),
-                       dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+    if (img)
+        hipLaunchKernelGGL((k_star3d_t2<S, R, NY, TY, XW, true>), dim3((unsigned)total),
+                           dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+    else
+        hipLaunchKernelGGL((k_star3d_t2<S, R, NY, TY, XW, false>), dim3((unsigned)total),
+                           dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
     return check_launch("xcorr_star3d_t2");
 }
 

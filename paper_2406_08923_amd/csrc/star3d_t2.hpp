@@ -40,7 +40,7 @@ __device__ __forceinline__ int wrap_mod(int v, int n)
 // interior coordinates, so the input halo is never read and any grid size
 // works. Both stages evaluate every point with the taps in the order of the
 // one-iteration kernel, so the result is bitwise that of two chained launches.
-template <typename S, int R, int NY, int TY, int XW>
+template <typename S, int R, int NY, int TY, int XW, bool IMG>
 __device__ __forceinline__ void star3d_t2_segment(
     const S *__restrict__ in, S *__restrict__ out, const Geo g,
     const StarCoef<typename Store<S>::C, R> cf, int bxi, int byi, int z0, int z1, int flags,
@@ -63,7 +63,7 @@ __device__ __forceinline__ void star3d_t2_segment(
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + SH::TXW * ty;
     const int fx0 = bxi * OX - R, fy0 = byi * OY - R;
-    const bool fuse = (flags & STAR_FLAG_NOFUSE) == 0;
+    constexpr bool fuse = IMG; // write the output's periodic images
     const Buf src = make_buf(in, uint64_t(padded_elems(g)) * es);
 
     auto col = [&](int xx, int yy) {
@@ -397,14 +397,18 @@ __device__ __forceinline__ void star3d_t2_segment(
 // per SIMD, two workgroups per CU, so one's barrier waits overlap the other's
 // work), which they reach without spills; other instances take the
 // compiler's choice.
-template <typename S, int XW, int TY> constexpr int t2_min_waves()
+// Two 512-lane workgroups per CU (4 waves per SIMD, at most 128 VGPRs) for
+// BF16, and for FP32 without the image store (with it, the cap spills).
+template <typename S, int XW, int TY, bool IMG> constexpr int t2_min_waves()
 {
-    return (64 * XW * TY == 512 && sizeof(S) == 2) ? 4 : 1;
+    return (64 * XW * TY == 512 && (sizeof(S) == 2 || (sizeof(S) == 4 && !IMG))) ? 4 : 1;
 }
 
 // Workgroup = (tile column, z chunk of lz planes), gx * gy * gz of them.
-template <typename S, int R, int NY, int TY, int XW>
-__global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY>()))
+// IMG: the output's periodic images are written (a compile-time choice, so a
+// launch without them carries none of their scalar and exec-mask work).
+template <typename S, int R, int NY, int TY, int XW, bool IMG>
+__global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY, IMG>()))
     k_star3d_t2(const S *__restrict__ in, S *__restrict__ out, Geo g,
                 StarCoef<typename Store<S>::C, R> cf, int lz, int gx, int gy, int gz, int flags)
 {
@@ -420,8 +424,8 @@ __global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY>()))
     const int byi = yfirst ? lin % gy : (lin / gx) % gy;
     const int bxi = yfirst ? (lin / gy) % gx : lin % gx;
     const int z0 = (lin / (gx * gy)) * lz;
-    star3d_t2_segment<S, R, NY, TY, XW>(in, out, g, cf, bxi, byi, z0, min(z0 + lz, g.nz), flags,
-                                        lda, ldb);
+    star3d_t2_segment<S, R, NY, TY, XW, IMG>(in, out, g, cf, bxi, byi, z0, min(z0 + lz, g.nz),
+                                             flags, lda, ldb);
 }
 
 } // namespace stn

@@ -42,7 +42,7 @@ template <int R, int TY, int XW> struct PairShape {
 
 // One segment (planes z0..z1-1 of tile column (bxi, byi)) of the register-ring
 // march of star3d_t2_segment with pair-layout LDS planes.
-template <typename S, int R, int TY, int XW>
+template <typename S, int R, int TY, int XW, bool IMG>
 __device__ __forceinline__ void star3d_t2p_segment(
     const S *__restrict__ in, S *__restrict__ out, const Geo g,
     const StarCoef<typename Store<S>::C, R> cf, int bxi, int byi, int z0, int z1, int flags,
@@ -64,7 +64,7 @@ __device__ __forceinline__ void star3d_t2p_segment(
     const int tid = tx + SH::TXW * ty;
     const int r0 = ty * NY; // the lane's first lane-grid row
     const int fx0 = bxi * OX - R, fy0 = byi * OY - R;
-    const bool fuse = (flags & STAR_FLAG_NOFUSE) == 0;
+    constexpr bool fuse = IMG; // write the output's periodic images
     const Buf src = make_buf(in, uint64_t(padded_elems(g)) * es);
 
     auto col = [&](int xx, int yy) {
@@ -277,9 +277,10 @@ __device__ __forceinline__ void star3d_t2p_segment(
     }
 }
 
-// Workgroup = (tile column, z chunk of lz planes), gx * gy * gz of them.
-template <typename S, int R, int TY, int XW>
-__global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY>()))
+// Workgroup = (tile column, z chunk of lz planes), gx * gy * gz of them;
+// IMG as in k_star3d_t2.
+template <typename S, int R, int TY, int XW, bool IMG>
+__global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY, IMG>()))
     k_star3d_t2p(const S *__restrict__ in, S *__restrict__ out, Geo g,
                  StarCoef<typename Store<S>::C, R> cf, int lz, int gx, int gy, int gz, int flags)
 {
@@ -295,7 +296,7 @@ __global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY>()))
     const int byi = yfirst ? lin % gy : (lin / gx) % gy;
     const int bxi = yfirst ? (lin / gy) % gx : lin % gx;
     const int z0 = (lin / (gx * gy)) * lz;
-    star3d_t2p_segment<S, R, TY, XW>(in, out, g, cf, bxi, byi, z0, min(z0 + lz, g.nz), flags, lda,
+    star3d_t2p_segment<S, R, TY, XW, IMG>(in, out, g, cf, bxi, byi, z0, min(z0 + lz, g.nz), flags, lda,
                                      ldb);
 }
 
