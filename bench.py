@@ -8,11 +8,15 @@ the default plan runs two iterations per kernel launch (temporal blocking,
 bitwise equal to one-iteration launches), so 100 steps are 50 launches.
 Input: seeded uniform [-1, 1), resident in HBM before timing starts.
 
-Prints one JSON line: grid-point updates/s, the HBM roofline of the dominant
-kernel (algorithmic bytes per launch / average launch duration from HIP events
-recorded on the launch stream), the CPU oracle timed on a bounded sample, and
-secondary lines for the other workloads (FP32 star, 1-D radius-1 smoother,
-fused 8-field RK3 step in FP64 and with FP32/BF16 storage).
+Prints one JSON line (kept short): grid-point updates/s, the HBM roofline of
+the dominant kernel (algorithmic bytes per launch / average launch duration
+from HIP events recorded on the launch stream), the measured HBM traffic of
+that kernel, the CPU oracle timed on a bounded sample, and one compact entry
+per other workload (1-D radius-1 smoother; FP32 star with its error against
+FP64; radius-4 star; fused 8-field RK3 step in FP64 and with FP32/BF16
+storage, with the storage policies' error after 1/10/100/1000 steps; the
+serving trace). The full record (per-field errors, radius sweep, filters,
+serving rate sweep) goes to stderr and, with --detail-out, to a file.
 """
 import argparse
 import hashlib
@@ -28,6 +32,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 DTYPES = {"f64": (0, 8), "f32": (1, 4), "bf16": (2, 2)}
 METRIC = "grid-point updates/s + % HBM roofline; served p50/p99 latency vs plain FP64"
+# constants of the full non-ideal model in the benchmark: every closure term on
+FULL_MHD = dict(zeta=3e-3, mu0=1.0, gamma=5.0 / 3.0, cp=1.0, lnrho0=0.0, K=4e-3, heat=2e-3,
+                cool=5e-4)
 
 
 def parse():
@@ -54,11 +61,17 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="headline workload only")
     ap.add_argument("--no-precision-error", action="store_true",
                     help="skip the 1000-step mixed-precision error measurement")
+    ap.add_argument("--precision-n", type=int, default=256,
+                    help="grid edge of the 1000-step mixed-precision error measurement")
     ap.add_argument("--serve-rates", default="10,25,50",
                     help="mean arrival rates (jobs/s) of the sustainable-load replays of the "
                          "serving trace (empty: none)")
-    ap.add_argument("--serve-jobs", type=int, default=48,
+    ap.add_argument("--serve-jobs", type=int, default=400,
                     help="jobs in the serving trace (0 skips the serving comparison)")
+    ap.add_argument("--serve-sweep-jobs", type=int, default=48,
+                    help="jobs of the trace replayed at the sustainable rates")
+    ap.add_argument("--detail-out", default=None,
+                    help="also write the full record (JSON) to this file")
     return ap.parse_args()
 
 
@@ -173,28 +186,78 @@ def star_run(torch, S, W, inputs, n, r, dtype, steps, warmup, tile=None, layout=
     return plan, g, total, total / max(1, nlaunch), (n_multi, n_single)
 
 
+def progress(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def sig(v, digits=4):
+    """v rounded to a few significant digits (keeps the result line short)."""
+    if isinstance(v, float):
+        return float("%.*g" % (digits, v)) if math.isfinite(v) else None
+    if isinstance(v, dict):
+        return {k: sig(x, digits) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [sig(x, digits) for x in v]
+    return v
+
+
+def star_f32_error(torch, S, W, inputs, n, r, iters=100):
+    """Normwise relative error of the FP32-storage star after ``iters``
+    chained iterations against the FP64 path on the same FP32-exact input
+    (the FP64 path matches the CPU oracle to 1e-12 at this size)."""
+    dims = (n, n, n)
+    g = W.diffusion_star(3, r, W.diffusion_number(n))
+    x = torch.from_numpy(inputs.uniform_field(dims, 1)).cuda().to(torch.float32)
+    outs = []
+    for dtype in (S.F64, S.F32):
+        es = 8 if dtype == S.F64 else 4
+        pitch, ox = W.aligned_layout(n, r, es) if dtype == S.F32 else (0, 0)
+        p = S.LinearPlan(dims, r, g, dtype=dtype, row_pitch=pitch, x_offset=ox)
+        a = p.empty(0.0)
+        p.padded(a)[r:r + n, r:r + n, r:r + n] = x.to(a.dtype)
+        b = p.empty(0.0)
+        res = p.apply(a, b, iters)
+        outs.append(p.padded(res)[r:r + n, r:r + n, r:r + n].to(torch.float64))
+        del a, b, res, p
+    err = float((outs[1] - outs[0]).abs().max() / outs[0].abs().max())
+    del outs, x
+    torch.cuda.empty_cache()
+    return err
+
+
 def secondary(torch, S, W, inputs, args):
-    out = {}
-    # FP32 storage of the same star workload
+    """The other configurations. Returns (compact, detail): compact goes into
+    the result line, detail to stderr and --detail-out."""
+    comp, det = {}, {}
     n, r = args.n, args.radius
+    progress("FP32 star")
+    # FP32 storage of the same star workload, and its error against FP64
     p32, _, tot, per, nl = star_run(torch, S, W, inputs, n, r, S.F32, 100, 4)
     ipl = p32.iterations_per_launch if nl[1] == 0 else 1
-    out["star_%d_f32" % n] = {"updates_per_s": n ** 3 / (tot / 100 * 1e-3),
-                              "ms_per_iteration": tot / 100,
-                              "iterations_per_launch": ipl,
+    det["star_%d_f32" % n] = {"updates_per_s": n ** 3 / (tot / 100 * 1e-3),
+                              "ms_per_iteration": tot / 100, "iterations_per_launch": ipl,
                               "hbm_frac": ipl * 8 * n ** 3 / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
                               "avg_launch_ms": per, "tile": list(p32.tile),
                               "layout": [p32.row_pitch, p32.x_offset]}
     del p32
+    err32 = star_f32_error(torch, S, W, inputs, n, r)
+    d = det["star_%d_f32" % n]
+    d["rel_err_vs_f64_100_iterations"] = err32
+    comp["c1_star512_f32"] = {"ups": d["updates_per_s"], "ms_it": d["ms_per_iteration"],
+                              "frac": d["hbm_frac"], "err_vs_f64_100it": err32}
+    progress("radius-4 star")
     # the secondary star of the same workload: 25 points, radius 4, FP64
     p4, _, tot, per, nl = star_run(torch, S, W, inputs, n, 4, S.F64, 100, 4)
     ipl = p4.iterations_per_launch if nl[1] == 0 else 1
-    out["star_%d_f64_r4" % n] = {"updates_per_s": n ** 3 / (tot / 100 * 1e-3),
-                                 "ms_per_iteration": tot / 100,
-                                 "iterations_per_launch": ipl,
-                                 "hbm_frac": ipl * 16 * n ** 3 / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                 "avg_launch_ms": per, "tile": list(p4.tile)}
+    d = det["star_%d_f64_r4" % n] = {
+        "updates_per_s": n ** 3 / (tot / 100 * 1e-3), "ms_per_iteration": tot / 100,
+        "iterations_per_launch": ipl,
+        "hbm_frac": ipl * 16 * n ** 3 / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "avg_launch_ms": per, "tile": list(p4.tile)}
+    comp["c1_star512_f64_r4"] = {"ups": d["updates_per_s"], "ms_it": d["ms_per_iteration"],
+                                 "frac": d["hbm_frac"]}
     del p4
+    progress("1-D lines")
     # 1-D radius-1 smoother at 2^28 points (2 GiB per buffer): 10 chained
     # iterations per call, autotuned plan (temporal blocking allowed)
     N = 1 << 28
@@ -203,7 +266,7 @@ def secondary(torch, S, W, inputs, args):
     a[1:N + 1] = torch.from_numpy(inputs.uniform_field((N,), 1)).cuda()
     b = pl.empty(0.0)
     ms = timed(torch, lambda: pl.apply(a, b, 10), 3, warm=1)
-    out["line_2^28_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
+    det["line_2^28_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
                                    "algorithmic_frac": 16 * N * 10 / (ms * 1e-3) / 1e9 /
                                    HBM_PEAK_GBS,
                                    "iterations_per_launch": pl.iterations_per_launch,
@@ -216,21 +279,21 @@ def secondary(torch, S, W, inputs, args):
     a[1:N + 1] = torch.from_numpy(inputs.uniform_field((N,), 1)).cuda()
     b = p1.empty(0.0)
     ms = timed(torch, lambda: p1.apply(a, b, 10), 50)
-    out["line_2^20_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
-                                   "us_per_iteration": ms * 100.0,
-                                   "variant": p1.variant, "tile": list(p1.tile)}
+    d = det["line_2^20_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
+                                       "us_per_iteration": ms * 100.0,
+                                       "variant": p1.variant, "tile": list(p1.tile)}
+    comp["c0_line2^20_f64_10it"] = {"ups": d["updates_per_s"], "us_it": d["us_per_iteration"]}
     del a, b
-    out["line_radius_sweep_2^24_f64"] = radius_sweep(torch, S, inputs)
-    out["filters_512_f64"] = filters(torch, S, inputs, args.n)
+    progress("radius sweep, filters")
+    det["line_radius_sweep_2^24_f64"] = radius_sweep(torch, S, inputs)
+    det["filters_512_f64"] = filters(torch, S, inputs, args.n)
+    progress("fused 8-field steps")
     # fused 8-field RK3 step, 256^3
     nm = 256
     f, _ = inputs.fourier_fields((nm, nm, nm), 1, nf=8, modes=8, kmax=8, amp=0.01)
     ds = 2 * math.pi / nm
     dt = 0.1 * ds
     bytes_step = {S.PREC_F64: 640, S.PREC_F32_MASTER64: 480, S.PREC_BF16_MASTER64: 384}
-    # the full non-ideal model (Eq. A1-A4, ideal gas) with every closure term on
-    full = dict(zeta=3e-3, mu0=1.0, gamma=5.0 / 3.0, cp=1.0, lnrho0=0.0, K=4e-3, heat=2e-3,
-                cool=5e-4)
     for model, mname, prec, name in (
             (S.MODEL_MHD8, "mhd8", S.PREC_F64, "f64"),
             (S.MODEL_MHD8, "mhd8", S.PREC_F32_MASTER64, "f32_master64"),
@@ -241,7 +304,7 @@ def secondary(torch, S, W, inputs, args):
             (S.MODEL_MHD8, "mhd8_diag", S.PREC_F64, "f64"),
             (S.MODEL_MHD_FULL, "mhd_full_diag", S.PREC_F64, "f64")):
         plan = S.RkPlan(model, (nm, nm, nm), prec,
-                        mhd=full if model == S.MODEL_MHD_FULL else None,
+                        mhd=FULL_MHD if model == S.MODEL_MHD_FULL else None,
                         mixed=S.MIXED_DIAGONAL if mname.endswith("_diag") else S.MIXED_TENSOR)
         bufs = plan.alloc()
         for k in range(8):
@@ -255,22 +318,47 @@ def secondary(torch, S, W, inputs, args):
         pts = nm ** 3
         flops = mhd_flops(model == S.MODEL_MHD_FULL, mname.endswith("_diag"))
         peak = VALU_PEAK_TFLOPS["f64" if prec == S.PREC_F64 else "f32"]
-        out["%s_%d_%s" % (mname, nm, name)] = {
+        d = det["%s_%d_%s" % (mname, nm, name)] = {
             "point_steps_per_s": pts / (ms * 1e-3),
             "point_substeps_per_s": 3 * pts / (ms * 1e-3),
             "ms_per_step": ms,
             "hbm_frac": bytes_step[prec] * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "valu_roof": {"flops_per_point_substep": flops, "peak_tflops": peak,
                           "frac": 3 * pts / (ms * 1e-3) * flops / (peak * 1e12)}}
+        key = ("c2_" if prec == S.PREC_F64 else "c3_") + "%s_256_%s" % (mname, name)
+        comp[key] = {"ms_step": ms, "pt_steps_s": d["point_steps_per_s"],
+                     "hbm_frac": d["hbm_frac"], "valu_frac": d["valu_roof"]["frac"]}
         del bufs, plan
+    del f
+    torch.cuda.empty_cache()
     if not args.no_precision_error:
-        out["mhd8_mixed_precision_error_64"] = mixed_precision_error(torch, S, inputs)
-        out["mhd_full_mixed_precision_error_64"] = mixed_precision_error(
-            torch, S, inputs, model=S.MODEL_MHD_FULL, mhd=full)
+        for model, mname in ((S.MODEL_MHD8, "mhd8"), (S.MODEL_MHD_FULL, "mhd_full")):
+            progress("precision study %s" % mname)
+            res = mixed_precision_error(torch, S, inputs, n=args.precision_n, model=model,
+                                        mhd=FULL_MHD if model == S.MODEL_MHD_FULL else None)
+            det["%s_mixed_precision_error_%d" % (mname, args.precision_n)] = res
+            comp["c3_err_%s_%d" % (mname, args.precision_n)] = {
+                "steps": res["steps"],
+                **{k: [max(res[k][str(cp)]) for cp in res["steps"]]
+                   for k in ("f32_master64", "bf16_master64", "f32_only", "bf16_only")}}
     if args.serve_jobs > 0:
         rates = tuple(float(v) for v in args.serve_rates.split(",") if v)
-        out["serving"] = serving(torch, args.serve_jobs, rates=rates)
-    return out
+        progress("serving trace (%d jobs)" % args.serve_jobs)
+        sv = serving(torch, args.serve_jobs, rates=rates, sweep_jobs=args.serve_sweep_jobs)
+        det["serving"] = sv
+        keep = ("p50_s", "p99_s", "point_steps_per_s")
+        comp["c4_serving"] = {
+            "jobs": args.serve_jobs, "rate_per_s": 200,
+            "served": {k: sv["served"][k] for k in keep},
+            "fifo_f64": {k: sv["fifo_f64"][k] for k in keep},
+            "served_by_dtype": sv["served"]["by_dtype"],
+            "fifo_by_dtype": sv["fifo_f64"]["by_dtype"],
+            "speedup": sv["speedup_point_steps_per_s"],
+            "p99_ratio_fifo_over_served": sv["p99_ratio_fifo_over_served"],
+            "err_vs_f64": sv["error_vs_fp64"],
+            "sweep_p99_served_vs_fifo": {k: [v["served"]["p99_s"], v["fifo_f64"]["p99_s"]]
+                                         for k, v in sv["rate_sweep"].items()}}
+    return comp, det
 
 
 def filters(torch, S, inputs, n):
@@ -319,49 +407,52 @@ def radius_sweep(torch, S, inputs, n=1 << 24, radii=(1, 2, 4, 8, 16, 64, 256, 10
     return res
 
 
-def mixed_precision_error(torch, S, inputs, n=64, checkpoints=(1, 10, 100, 1000), model=None,
+def mixed_precision_error(torch, S, inputs, n=256, checkpoints=(1, 10, 100, 1000), model=None,
                           mhd=None):
     """Normwise relative error per field of the FP32- and BF16-storage states
     (FP64 master, and the no-master ablation) against the FP64 path after 1,
     10, 100 and 1000 RK3 steps of an 8-field model (default: the proxy) at
     n^3 (Fourier-mode initial data, amplitude 0.01, |k| <= 8; dt = 0.1 ds).
-    The FP64 path is the reference: it matches the CPU oracle to 1e-12 in the
-    parity tests."""
+    The FP64 path is the reference: it matches the CPU oracle to 1e-12 at
+    every point at 256^3 for each substep, and over 1000 steps at 32^3. The
+    differences are taken on the GPU; the FP64 snapshots stay in HBM."""
     model = S.MODEL_MHD8 if model is None else model
-    import numpy as np
     dims = (n, n, n)
     dt = 0.1 * 2 * math.pi / n
     f, _ = inputs.fourier_fields(dims, 1, nf=8, modes=8, kmax=8, amp=0.01)
-    runs = {}
+    f = [torch.from_numpy(v).cuda() for v in f]
+    ref = {}
+    out = {"grid": n, "reference": "GPU FP64 path (oracle-anchored)", "steps": list(checkpoints)}
+    t0 = time.perf_counter()
     for name, prec in (("f64", S.PREC_F64), ("f32_master64", S.PREC_F32_MASTER64),
                        ("bf16_master64", S.PREC_BF16_MASTER64), ("f32_only", S.PREC_F32_ONLY),
                        ("bf16_only", S.PREC_BF16_ONLY)):
         plan = S.RkPlan(model, dims, prec, mhd=mhd)
         b = plan.alloc()
         for k in range(8):
-            b["f_a"][k][3:n + 3, 3:n + 3, 3:n + 3] = torch.from_numpy(f[k]).cuda().to(
-                b["f_a"][k].dtype)
+            b["f_a"][k][3:n + 3, 3:n + 3, 3:n + 3] = f[k].to(b["f_a"][k].dtype)
             if plan.master:
-                b["f64"][k][3:n + 3, 3:n + 3, 3:n + 3] = torch.from_numpy(f[k]).cuda()
-        snaps, done, cur, nxt = {}, 0, b["f_a"], b["f_b"]
+                b["f64"][k][3:n + 3, 3:n + 3, 3:n + 3] = f[k]
+        per, done, cur, nxt = {}, 0, b["f_a"], b["f_b"]
         for cp in checkpoints:
             res = plan.run(cur, nxt, b["w"], cp - done, dt, w2=b["w2"], f64=b["f64"])
             if res is nxt:
                 cur, nxt = nxt, cur
             done = cp
             state = b["f64"] if plan.master else cur
-            snaps[cp] = [t[3:n + 3, 3:n + 3, 3:n + 3].to(torch.float64).cpu().numpy()
-                         for t in state]
-        runs[name] = snaps
+            snap = [t[3:n + 3, 3:n + 3, 3:n + 3].to(torch.float64) for t in state]
+            if name == "f64":
+                ref[cp] = [s.clone() for s in snap]
+            else:
+                per[str(cp)] = [float((snap[k] - ref[cp][k]).abs().max() /
+                                      ref[cp][k].abs().max()) for k in range(8)]
+            del snap
+        if name != "f64":
+            out[name] = per
         del b, plan
-    out = {"grid": n, "reference": "GPU FP64 path", "steps": list(checkpoints)}
-    for name in ("f32_master64", "bf16_master64", "f32_only", "bf16_only"):
-        per = {}
-        for cp in checkpoints:
-            ref, got = runs["f64"][cp], runs[name][cp]
-            per[str(cp)] = [float(np.max(np.abs(got[k] - ref[k])) / np.max(np.abs(ref[k])))
-                            for k in range(8)]
-        out[name] = per
+    out["seconds"] = time.perf_counter() - t0
+    del ref, f
+    torch.cuda.empty_cache()
     return out
 
 
@@ -381,44 +472,49 @@ def mhd_flops(full, diagonal):
     return 24 * 9 + 24 * 11 + 12 * (16 if diagonal else 45) + (260 if full else 200) + 8 * 4
 
 
-def serving(torch, count, seed=1, rates=(10.0, 25.0, 50.0)):
+def serving(torch, count, seed=1, rates=(10.0, 25.0, 50.0), sweep_jobs=48):
     """Seeded Poisson trace (mean 200 jobs/s) of 2-D/3-D radius-3 advection-
     diffusion jobs, edges {64..384}, 10-500 steps, FP32/FP64 per request:
     continuous-batching server vs plain FIFO per-job FP64 on the same GPU.
-    The 200/s trace overloads the GPU (its offered work exceeds the HBM roof),
-    so the same jobs are also replayed at lower mean rates (arrival times
-    stretched by 200/rate) for latencies under a load the GPU can sustain.
-    The server runs its default policy (oldest first); the shortest-remaining-
-    work policy is timed beside it."""
+    The 200/s trace overloads the GPU (its offered work exceeds the HBM roof);
+    the first ``sweep_jobs`` jobs are also replayed at lower mean rates
+    (arrival times stretched by 200/rate) for latencies under a load the GPU
+    can sustain. The server runs its default policy (oldest first); the
+    shortest-remaining-work policy is timed beside it."""
     import paper_2406_08923_amd as S_
     from paper_2406_08923_amd import inputs, serving as SV
     jobs = inputs.serving_trace(seed, count)
     inits = SV.make_inits(jobs)
+    progress("serving: inits ready")
     served, res_s = SV.run_served(jobs, inits)
     torch.cuda.synchronize()
+    progress("serving: served run %.1f s" % served["makespan_s"])
     fifo, res_f = SV.run_fifo_f64(jobs, inits)
+    progress("serving: FIFO run %.1f s" % fifo["makespan_s"])
     err = SV.compare(jobs, res_s, res_f)
     del res_s, res_f
     torch.cuda.synchronize()
     shortest, _ = SV.run_served(jobs, inits, policy=S_.SERVE_SHORTEST)
     keep = ("p50_s", "p99_s", "makespan_s", "point_steps_per_s")
     sweep = {}
+    sj, si = jobs[:sweep_jobs], inits[:sweep_jobs]
     for rate in rates:
-        jr = [dict(j, arrival=j["arrival"] * 200.0 / rate) for j in jobs]
+        jr = [dict(j, arrival=j["arrival"] * 200.0 / rate) for j in sj]
         row = {}
-        for name, fn in (("served", lambda: SV.run_served(jr, inits)),
-                         ("fifo_f64", lambda: SV.run_fifo_f64(jr, inits)),
+        for name, fn in (("served", lambda: SV.run_served(jr, si)),
+                         ("fifo_f64", lambda: SV.run_fifo_f64(jr, si)),
                          ("served_shortest_first",
-                          lambda: SV.run_served(jr, inits, policy=S_.SERVE_SHORTEST))):
+                          lambda: SV.run_served(jr, si, policy=S_.SERVE_SHORTEST))):
             torch.cuda.synchronize()
             res, _ = fn()
             row[name] = {k: res[k] for k in keep}
         sweep["%g_per_s" % rate] = row
-        print("serving at %g jobs/s: p99 served %.3f s, fifo %.3f s, shortest-first %.3f s" %
-              (rate, row["served"]["p99_s"], row["fifo_f64"]["p99_s"],
-               row["served_shortest_first"]["p99_s"]), file=sys.stderr, flush=True)
+        print("serving at %g jobs/s (%d jobs): p99 served %.3f s, fifo %.3f s, shortest-first "
+              "%.3f s" % (rate, len(sj), row["served"]["p99_s"], row["fifo_f64"]["p99_s"],
+                          row["served_shortest_first"]["p99_s"]), file=sys.stderr, flush=True)
     return {"trace": "seed %d, %d jobs, Poisson 200/s, 50%% 3-D, edges 64..384, steps "
-                     "10..500, 50%% FP32 requests" % (seed, count),
+                     "10..500, 50%% FP32 requests; rate sweep on the first %d jobs"
+                     % (seed, count, len(sj)),
             "policy": "oldest submission first, shorter jobs filling up to a quarter more",
             "served": served, "fifo_f64": fifo, "error_vs_fp64": err,
             "served_shortest_first": {k: shortest[k] for k in keep},
@@ -467,6 +563,7 @@ def main():
     kern_files = ("star3d.hpp", "star3d_t2.hpp", "star3d_t2p.hpp", "star3d_%s.hip" % args.dtype,
                   "common.hpp", "linear_kernels.hpp", "linear_api.hip")
     traffic = load_traffic("traffic_star3d_%d_%s.json" % (n, args.dtype), kern_files)
+    traffic_gbs = traffic / (avg_launch_ms * 1e-3) / 1e9 if traffic else None
     copy_gbs = None if args.no_copy else copy_bandwidth(torch, S)
 
     out = {
@@ -483,15 +580,13 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic: seeded uniform [-1,1) field, periodic halo",
         "config": {
-            "workload": "3-D linear cross-correlation, 19-point radius-%d star (6th-order "
+            "workload": "3-D linear cross-correlation, %d-point radius-%d star (6th-order "
                         "diffusion step, s=%.4f), %d^3 %s, periodic halo, %d chained iterations"
-                        % (r, W.diffusion_number(n), n, args.dtype.upper(), K),
-            "grid": [n, n, n], "radius": r, "taps": int((g != 0).sum()),
-            "kernel_variant": {0: "generic", 1: "star3d", 2: "line1d"}[plan.variant],
+                        % (int((g != 0).sum()), r, W.diffusion_number(n), n,
+                           args.dtype.upper(), K),
             "tile": list(plan.tile),
             "iterations_per_launch": ipl,
             "launches": n_multi + n_single,
-            "layout": {"row_pitch": plan.row_pitch, "x_offset": plan.x_offset},
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -501,25 +596,32 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                            "copy-calibrated; null if the kernel source changed since)",
-            "traffic_rate_gbs": (traffic / (avg_launch_ms * 1e-3) / 1e9) if traffic else None,
-            "algorithmic_bytes_per_launch": alg_bytes,
-            "algorithmic_bytes_rule": "%d B per grid point per iteration (read once, write "
-                                      "once) x %d iteration(s) per launch; a two-iteration "
-                                      "launch moves about one pass of HBM traffic, so "
-                                      "traffic < algorithmic bytes" % (2 * esize, ipl),
             "avg_launch_ms": avg_launch_ms,
+            "basis": "achieved: algorithmic %d B/pt/iteration x %d iterations per launch; "
+                     "traffic: measured HBM B/launch (rocprofv3, copy-calibrated)"
+                     % (2 * esize, ipl),
         },
-        "hbm_roofline_pct": 100.0 * achieved / HBM_PEAK_GBS,
+        # the share of the HBM roof the kernel's measured traffic uses (one
+        # pass of bytes, not the algorithmic bytes of both iterations)
+        "hbm_traffic_pct": 100.0 * traffic_gbs / HBM_PEAK_GBS if traffic_gbs else None,
+        "effective_bandwidth_gbs": achieved,
         "copy_bandwidth_gbs": copy_gbs,
-        "pct_of_copy_bandwidth": (100.0 * achieved / copy_gbs) if copy_gbs else None,
         "wall_s_star_phase": wall,
     }
+    detail = {}
     if not args.no_secondary:
-        out["secondary"] = secondary(torch, S, W, inputs, args)
+        comp, detail = secondary(torch, S, W, inputs, args)
+        out["workloads"] = sig(comp, 3)
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(n, r, g, args.cpu_seconds)
+    if detail:
+        detail["headline"] = {k: out[k] for k in ("value", "ms_per_step", "roofline")}
+        text = json.dumps(detail)
+        print("detail: " + text, file=sys.stderr, flush=True)
+        if args.detail_out:
+            with open(args.detail_out, "w") as fh:
+                fh.write(text + "\n")
     print(json.dumps(out), flush=True)
 
 

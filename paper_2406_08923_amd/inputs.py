@@ -59,6 +59,27 @@ def eval_modes(n, modes):
     return f
 
 
+def eval_modes_device(n, modes, device="cuda"):
+    """eval_modes evaluated with torch on ``device`` (FP64), returned as a
+    NumPy array: the same sum of cosines, for grids too large to sample
+    quickly on the host (the serving trace's 384^3 jobs)."""
+    import torch
+    nd = len(n)
+    X = []
+    for a in range(nd):
+        c = 2.0 * math.pi * torch.arange(n[a], dtype=torch.float64, device=device) / n[a]
+        shape = [1] * nd
+        shape[nd - 1 - a] = n[a]
+        X.append(c.reshape(shape))
+    f = torch.zeros(tuple(int(v) for v in reversed(n)), dtype=torch.float64, device=device)
+    for k, amp, ph in modes:
+        arg = torch.full((1,) * nd, ph, dtype=torch.float64, device=device)
+        for ax in range(nd):
+            arg = arg + k[ax] * X[ax]
+        f += amp * torch.cos(arg)
+    return f.cpu().numpy()
+
+
 def fourier_fields(n, seed, nf=8, modes=8, kmax=8, amp=0.01):
     """nf fields, each a sum of ``modes`` random Fourier modes (|k|_inf <= kmax).
     Draw order: field-major, then mode. Returns (list of interior arrays, the

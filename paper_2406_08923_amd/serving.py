@@ -27,14 +27,30 @@ def job_dt(job):
 
 
 def make_inits(jobs):
-    """Initial fields (sum of the job's Fourier modes), generated once."""
-    return [inputs.eval_modes(job_dims(j), j["modes"]) for j in jobs]
+    """Initial fields (sum of the job's Fourier modes), generated once, on the
+    GPU (the host takes minutes for a 384^3 job)."""
+    return [inputs.eval_modes_device(job_dims(j), j["modes"]) for j in jobs]
 
 
 def _percentiles(lat):
     a = np.sort(np.asarray(lat))
     return {"p50_s": float(np.percentile(a, 50)), "p99_s": float(np.percentile(a, 99)),
             "max_s": float(a[-1]), "mean_s": float(a.mean())}
+
+
+def _by_dtype(jobs, lat, makespan):
+    """p50/p99 latency and point-steps/s (over the whole makespan) of the FP32
+    and the FP64 requests separately."""
+    out = {}
+    for dt in ("f32", "f64"):
+        idx = [k for k, j in enumerate(jobs) if j["dtype"] == dt]
+        if not idx:
+            continue
+        ps = sum(int(np.prod(job_dims(jobs[k]))) * jobs[k]["steps"] for k in idx)
+        a = np.asarray([lat[k] for k in idx])
+        out[dt] = {"jobs": len(idx), "p50_s": float(np.percentile(a, 50)),
+                   "p99_s": float(np.percentile(a, 99)), "point_steps_per_s": ps / makespan}
+    return out
 
 
 def run_served(jobs, inits, tick_steps=16, max_slots=512, use_graph=True, min_points=0,
@@ -72,7 +88,7 @@ def run_served(jobs, inits, tick_steps=16, max_slots=512, use_graph=True, min_po
     out.update({"makespan_s": makespan, "point_steps": stats["point_steps"],
                 "point_steps_per_s": stats["point_steps"] / makespan,
                 "ticks": stats["ticks"], "launches": stats["launches"],
-                "busy_s": stats["busy_s"]})
+                "busy_s": stats["busy_s"], "by_dtype": _by_dtype(jobs, lat, makespan)})
     return out, results
 
 
@@ -102,7 +118,8 @@ def run_fifo_f64(jobs, inits):
     makespan = time.perf_counter() - t0
     o = _percentiles(lat)
     o.update({"makespan_s": makespan, "point_steps": pts_steps,
-              "point_steps_per_s": pts_steps / makespan})
+              "point_steps_per_s": pts_steps / makespan,
+              "by_dtype": _by_dtype(jobs, lat, makespan)})
     return o, results
 
 

@@ -153,6 +153,7 @@ def test_star3d_asymmetric_random_taps(r, dtype):
     run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(16, 2, 5, 0x120))
     run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(2, 4, 6, 0x425))
     run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(4, 2, 6, 0x9))
+    run_case((67, 21, 19), r, rand_star(r, 10 + r), dtype, S.STAR3D, tile=(2, 2, 9, 0x821))
 
 
 def test_star3d_tap_radius_below_padding():
@@ -289,10 +290,11 @@ def test_star_two_iterations_bitwise_equal_to_one_iteration_launches(tile, dtype
 
 
 @pytest.mark.parametrize("r", [1, 2, 4])
-@pytest.mark.parametrize("tile", [(16, 2, 16, 0x2101), (12, 2, 16, 0x2101), (8, 2, 16, 0x2101)])
+@pytest.mark.parametrize("tile", [(16, 2, 16, 0x2101), (12, 2, 16, 0x2101), (8, 2, 16, 0x2101),
+                                  (8, 2, 16, 0x2201)])
 def test_star_two_iterations_other_radii_random_taps(r, tile):
-    # 1024-lane (shifting-window march) and 768/512-lane (register rings for
-    # r <= 3) workgroups
+    # 1024-lane (shifting-window march; 64 x 16 and 128 x 8 lanes) and
+    # 768/512-lane (register rings for r <= 3) workgroups
     dims = (66, 29, 31)
     g = rand_star(r, 21) * 0.15
     got, _, inner = run_star_iters(dims, r, g, S.F64, tile, 4)
@@ -300,6 +302,19 @@ def test_star_two_iterations_other_radii_random_taps(r, tile):
     assert np.array_equal(got, ref)
     want = oracle_apply(inner, r, g, 4)
     assert_close(O.interior(got, r), O.interior(want, r), S.F64)
+
+
+@pytest.mark.parametrize("dtype", [S.F32, S.BF16])
+def test_star_two_iterations_radius_4_four_rows(dtype):
+    # radius 4, four rows per lane (the shifting-window march, whose BF16
+    # instance spills registers): bitwise equal to one-iteration launches
+    dims, r = (66, 29, 31), 4
+    g = rand_star(r, 23) * 0.15
+    for iters in (2, 4, 5):
+        got, plan, inner = run_star_iters(dims, r, g, dtype, (8, 4, 16, 0x2101), iters)
+        assert (plan.tile[3] >> 12) & 15 == 2
+        ref, _, _ = run_star_iters(dims, r, g, dtype, (4, 2, 8, 0x221), iters)
+        assert np.array_equal(got, ref), iters
 
 
 @pytest.mark.parametrize("r", [1, 2, 3])
@@ -542,16 +557,20 @@ def test_star_512_cubed_two_iteration_launches(dtype):
         assert np.max(np.abs(vals - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-def test_star_512_cubed_hundred_iterations_fourier_mode():
+@pytest.mark.parametrize("autotune", [False, True])
+def test_star_512_cubed_hundred_iterations_fourier_mode(autotune):
     # a single Fourier mode is an eigenvector: after N iterations it is scaled
-    # by the symbol to the N-th power (closed form, any size)
+    # by the symbol to the N-th power (closed form, any size); the default
+    # plan is the one the benchmark times (50 two-iteration launches)
     dims, r, N = (512, 512, 512), 3, 100
     s = W.diffusion_number(512)
     k = (3, -5, 7)
     X = inputs.grid_coords(dims)
     inner = np.cos(sum(k[a] * X[a] for a in range(3)) + 0.25)
     lam = 1.0 + s * sum(laplacian_symbol_grid(k[a], 512, r) for a in range(3))
-    plan = S.LinearPlan(dims, r, W.diffusion_star(3, 3, s), autotune=True)
+    plan = S.LinearPlan(dims, r, W.diffusion_star(3, 3, s), autotune=autotune)
+    if not autotune:
+        assert plan.launches(N) == (N // 2, 0)
     a_host = np.zeros(O.padded_shape(dims, r))
     O.interior(a_host, r)[...] = inner
     a = dev(a_host, S.F64)

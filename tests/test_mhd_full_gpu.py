@@ -237,6 +237,26 @@ def test_full_mhd_lds_and_cached_banks_agree_in_mixed_precision(prec):
         assert e <= tol, (prec, k)
 
 
+@pytest.mark.parametrize("prec", [S.PREC_F32_ONLY, S.PREC_BF16_ONLY])
+def test_full_mhd_lds_and_cached_banks_agree_without_master(prec):
+    # the no-master ablations: the stored states of the two banks after two
+    # steps; a rounding of the stored state can differ by one unit (2^-24
+    # FP32, 2^-8 BF16, relative) at any of the 6 substeps
+    n = (40, 24, 20)
+    ds = ds_of(n)
+    dt = 0.1 * min(ds)
+    f = fields(n, 9)
+    outs = []
+    for variant in (S.RK_CACHED, S.RK_LDS):
+        lp, _ = run_policy(n, prec, f, 2, dt, variant=variant, mhd=MHD, **KW)
+        outs.append(lp)
+    tol = 1e-5 if prec == S.PREC_F32_ONLY else 6 * 2.0 ** -8
+    for k in range(8):
+        e = relerr(outs[1][k], outs[0][k])
+        print("full MHD banks, precision %d, field %d: rel diff %.2e" % (prec, k, e))
+        assert e <= tol, (prec, k)
+
+
 def test_full_mhd_256_cubed_sampled_points():
     n = (256, 256, 256)
     ds = ds_of(n)

@@ -102,7 +102,8 @@ def test_mhd8_lds_bricks_on_tiny_and_ragged_grids(n, block):
         assert relerr(host(res[k]), ref[k]) <= 1e-12, (n, block, k)
 
 
-@pytest.mark.parametrize("prec", [S.PREC_F32_MASTER64, S.PREC_BF16_MASTER64, S.PREC_F32_ONLY])
+@pytest.mark.parametrize("prec", [S.PREC_F32_MASTER64, S.PREC_BF16_MASTER64, S.PREC_F32_ONLY,
+                                  S.PREC_BF16_ONLY])
 def test_mhd8_lds_and_cached_banks_agree_in_mixed_precision(prec):
     # same arithmetic type, different summation order of the grad(div)
     # terms: the banks agree to a few units of the storage rounding
@@ -114,7 +115,11 @@ def test_mhd8_lds_and_cached_banks_agree_in_mixed_precision(prec):
     for variant in (S.RK_CACHED, S.RK_LDS):
         lp, master = run_policy(n, prec, f, 2, dt, nu=NU, eta=ETA, cs2=CS2, variant=variant)
         outs.append(master if master is not None else lp)
-    tol = 1e-5 if prec != S.PREC_BF16_MASTER64 else 1e-4
+    tol = 1e-4 if prec in (S.PREC_BF16_MASTER64, S.PREC_BF16_ONLY) else 1e-5
+    if prec == S.PREC_BF16_ONLY:
+        # no master: a BF16 rounding of the two banks' states can differ by
+        # one unit (2^-8 relative) after any of the 6 substeps
+        tol = 6 * 2.0 ** -8
     for k in range(8):
         assert relerr(outs[1][k], outs[0][k]) <= tol, (prec, k)
 
