@@ -163,7 +163,10 @@ size_t stencil_plan_padded_elems(stencil_plan_t plan);
 /* Create a linear plan on the current HIP device. The plan owns a device copy
  * of the pruned taps. With STENCIL_FLAG_AUTOTUNE the candidate variants are
  * timed once on scratch buffers (synchronous) and the choice is cached per
- * process for the same shape class. */
+ * process for the same shape class (and in the file STENCIL_TUNE_CACHE names,
+ * if set). Arrays of any size are accepted; the STAR3D variant reads its
+ * input plane by plane (one buffer resource per plane), except its
+ * hardware-cached form (tile flag bit 3), which needs arrays below 4 GiB. */
 stencil_status stencil_plan(const stencil_desc *desc, stencil_plan_t *out);
 
 /* Release a plan (waits for nothing: the caller must not destroy a plan with
@@ -193,8 +196,11 @@ stencil_status stencil_apply(stencil_plan_t plan, void *d_a, void *d_b, int iter
 
 /* stencil_apply with flags. STENCIL_APPLY_HALO_VALID: the caller guarantees
  * d_a's periodic halo is already valid (e.g. it is the result of an earlier
- * apply), so no refresh is launched and d_a is not written; each iteration is
- * then exactly one kernel launch. Other bits must be zero. */
+ * apply), so no halo refresh is launched and d_a is not written before the
+ * first iteration. The launches are those of stencil_apply: a plan with two
+ * iterations per launch issues a number of launches with the parity of iters
+ * (e.g. iters = 2 runs as two one-iteration launches, iters = 4 as two
+ * two-iteration launches). Other bits must be zero. */
 #define STENCIL_APPLY_HALO_VALID 1u
 stencil_status stencil_apply_ex(stencil_plan_t plan, void *d_a, void *d_b, int iters,
                                 unsigned flags, void *stream);
@@ -298,7 +304,29 @@ typedef struct stencil_rk_desc {
     int mixed;      /* MHD8 and MHD_FULL: form of the bank's mixed derivatives
                        d_a d_b (a != b) in grad(div u) and grad(div A),
                        STENCIL_MIXED_*; must be 0 for ADVDIFF */
+    unsigned flags; /* STENCIL_RK_FLAG_*; 0 = the plan's fixed defaults */
+    int occupancy;  /* LDS bricks of MHD8 / MHD_FULL: waves per SIMD the
+                       kernel is compiled for (0 = the compiler's choice; 4
+                       with a 512-lane brick: at most 128 VGPRs, two
+                       workgroups per CU); one of the built (brick, occupancy)
+                       pairs, see block[]. Changes no result. */
 } stencil_rk_desc;
+
+/* Plan-time search (Sec. 5.1: the launch parameters are searched at runtime,
+ * failed launches dropped; Sec. 5.4: register allocation is a tuning knob).
+ * The plan times one RK3 step (three substeps, best of two after a warm-up)
+ * of every candidate schedule on scratch buffers of the plan's shape and
+ * keeps the fastest: MHD8 / MHD_FULL: the LDS bricks with their occupancy
+ * targets and the CACHED variant's lane tiles; 3-D ADVDIFF: the z march with
+ * 8, 16, 32 or 64 planes per tile and the CACHED tiles; 2-D ADVDIFF: the
+ * CACHED tiles. Only block[] / occupancy / variant fields left at 0 (AUTO)
+ * are searched. Every candidate computes the same arithmetic per point, so
+ * results are bitwise those of the untuned plan. Choices are cached per
+ * shape class in the process and, if the environment variable
+ * STENCIL_TUNE_CACHE names a file, in that file across processes. Needs
+ * scratch device memory of the plan's buffers for the search (released before
+ * return). */
+#define STENCIL_RK_FLAG_AUTOTUNE 1u
 
 /* Mixed-derivative forms (the paper fixes sixth-order central differences,
  * Sec. 3.3, but not the mixed stencil). TENSOR: the product of the two
@@ -343,12 +371,21 @@ typedef struct stencil_fields {
 
 /* Plan of the fused substep of a model; RK coefficients are Williamson's
  * 2N-storage third-order scheme: alpha = (0, -5/9, -153/128), beta = (1/3,
- * 15/16, 8/15), substep i: w = alpha_i w + dt R(f), f = f + beta_i w. */
+ * 15/16, 8/15), substep i: w = alpha_i w + dt R(f), f = f + beta_i w.
+ * STENCIL_EUNSUPPORTED if one padded FP64 buffer of the plan's layout would
+ * reach 4 GiB (the substep kernels address each field with 32-bit offsets;
+ * about 810^3 points per field). */
 stencil_status stencil_plan_rk(const stencil_rk_desc *desc, stencil_plan_t *out);
 
 /* Number of fields of the plan's model (8 for MHD8 and MHD_FULL, 1 for
  * ADVDIFF), or a negative status. */
 int stencil_plan_nfields(stencil_plan_t plan);
+
+/* The launch schedule an RK plan runs (after any search): out[0] = variant
+ * (STENCIL_RK_VARIANT_CACHED or _LDS), out[1..3] = block (CACHED: x lanes, y
+ * lanes, 1; LDS: the brick, or {64, 16, z planes} for the ADVDIFF z march),
+ * out[4] = occupancy target (0 = compiler's choice). */
+stencil_status stencil_plan_rk_schedule(stencil_plan_t plan, int out[5]);
 
 /* One fused substep (substep = 0, 1, 2) as one kernel launch on stream. */
 stencil_status stencil_step(stencil_plan_t plan, const stencil_fields *fields, int substep,
@@ -446,6 +483,15 @@ typedef struct stencil_server_desc {
                           STENCIL_SERVE_SHORTEST (1) least remaining work
                           first, a job left out 16 ticks in a row taken
                           regardless (lowest median under overload) */
+    int tune;          /* nonzero: search the batch schedule of every job class
+                          (ndim, dims, precision) the first time it is
+                          admitted (Sec. 5.1): z-march jobs 8/16/32/64 planes
+                          per tile, per-point jobs 64x4/128x2/256x1/32x8
+                          point tiles, each timed on one RK3 step of the
+                          batched kernels between ticks; choices cached per
+                          class (and in STENCIL_TUNE_CACHE's file). Changes no
+                          result. 0: fixed schedule (depth from the grid size,
+                          64x4 tiles) */
 } stencil_server_desc;
 
 #define STENCIL_SERVE_OLDEST 0
@@ -459,6 +505,7 @@ typedef struct stencil_server_stats {
     size_t bytes_in_use, bytes_budget;
     int resident, queued;
     double busy_s;         /* wall time spent inside ticks */
+    int tuned_classes;     /* job classes whose batch schedule was searched */
 } stencil_server_stats;
 
 /* Start a server on the current device: a host thread that admits queued jobs

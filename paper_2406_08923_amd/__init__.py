@@ -293,7 +293,11 @@ class _RkDesc(ctypes.Structure):
                 ("variant", ctypes.c_int), ("row_pitch", ctypes.c_int),
                 ("x_offset", ctypes.c_int)] + [
                     (k, ctypes.c_double) for k in ("zeta", "mu0", "gamma", "cp", "lnrho0", "K",
-                                                   "heat", "cool")] + [("mixed", ctypes.c_int)]
+                                                   "heat", "cool")] + [
+                    ("mixed", ctypes.c_int), ("flags", ctypes.c_uint), ("occupancy", ctypes.c_int)]
+
+
+RK_FLAG_AUTOTUNE = 1
 
 
 class _Fields(ctypes.Structure):
@@ -305,6 +309,7 @@ def _declare_rk(L):
     c_int = ctypes.c_int
     L.stencil_plan_rk.argtypes = [ctypes.POINTER(_RkDesc), ctypes.POINTER(_vp)]
     L.stencil_plan_nfields.argtypes = [_vp]
+    L.stencil_plan_rk_schedule.argtypes = [_vp, ctypes.POINTER(c_int)]
     L.stencil_step.argtypes = [_vp, ctypes.POINTER(_Fields), c_int, ctypes.c_double, _vp]
     L.stencil_rk_run.argtypes = [_vp, ctypes.POINTER(_Fields), c_int, ctypes.c_double, _vp]
     L.stencil_reduce.argtypes = [_vp, ctypes.POINTER(_vp), c_int, c_int,
@@ -333,7 +338,7 @@ class RkPlan:
 
     def __init__(self, model, dims, precision=PREC_F64, ds=None, nu=1e-3, eta=1e-3, cs2=1.0,
                  adv=(0.0, 0.0, 0.0), block=None, variant=0, row_pitch=0, x_offset=0,
-                 mhd=None, mixed=MIXED_TENSOR):
+                 mhd=None, mixed=MIXED_TENSOR, autotune=False, occupancy=0):
         import math
         self.model = model
         self.dims = tuple(int(v) for v in dims)
@@ -363,6 +368,8 @@ class RkPlan:
             setattr(d, k, float(v))
         d.mixed = int(mixed)
         self.mixed = int(mixed)
+        d.flags = RK_FLAG_AUTOTUNE if autotune else 0
+        d.occupancy = int(occupancy)
         self.x_offset = int(x_offset) or 3
         self.row_pitch = int(row_pitch) or (self.x_offset + self.dims[0] + 3)
         L = lib()
@@ -370,6 +377,14 @@ class RkPlan:
         check(L.stencil_plan_rk(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
         self.nfields = L.stencil_plan_nfields(h)
+
+    @property
+    def schedule(self):
+        """(variant, bx, by, bz, occupancy) the plan launches (after any
+        search)."""
+        out = (ctypes.c_int * 5)()
+        check(lib().stencil_plan_rk_schedule(self._h, out))
+        return tuple(out)
 
     @property
     def reg_dtype(self):
@@ -472,7 +487,8 @@ class _ServerDesc(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int),
                 ("tick_steps", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("blocks", ctypes.c_int), ("queue_cap", ctypes.c_int),
-                ("min_points", ctypes.c_longlong), ("policy", ctypes.c_int)]
+                ("min_points", ctypes.c_longlong), ("policy", ctypes.c_int),
+                ("tune", ctypes.c_int)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -481,7 +497,8 @@ class _ServerStats(ctypes.Structure):
                 ("failed", ctypes.c_longlong), ("cancelled", ctypes.c_longlong),
                 ("point_steps", ctypes.c_longlong), ("bytes_in_use", ctypes.c_size_t),
                 ("bytes_budget", ctypes.c_size_t), ("resident", ctypes.c_int),
-                ("queued", ctypes.c_int), ("busy_s", ctypes.c_double)]
+                ("queued", ctypes.c_int), ("busy_s", ctypes.c_double),
+                ("tuned_classes", ctypes.c_int)]
 
 
 def _declare_server(L):
@@ -508,10 +525,10 @@ class Server:
     they are kept referenced until the job ends."""
 
     def __init__(self, hbm_budget=0, max_slots=256, tick_steps=10, use_graph=True, blocks=0,
-                 queue_cap=0, min_points=0, policy=SERVE_OLDEST):
+                 queue_cap=0, min_points=0, policy=SERVE_OLDEST, tune=False):
         L = lib()
         d = _ServerDesc(hbm_budget, max_slots, tick_steps, 1 if use_graph else 0, blocks,
-                        queue_cap, min_points, policy)
+                        queue_cap, min_points, policy, 1 if tune else 0)
         h = _vp()
         check(L.stencil_server_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

@@ -19,12 +19,16 @@ struct BatchJob {
     int policy;     // RkPolicy
     int steps;      // RK steps to take in this tick
     int parity;     // index of the buffer holding the state when the tick starts
-    int tiles_x, tiles_y; // per-point: 64 x 4 tiles; z march: 64 x 16 tiles
+    int tiles_x, tiles_y; // per-point: tile_w x tile_h tiles; z march: 64 x 16 tiles
     int lz;               // z march: planes per tile
+    int tile_w, tile_h;   // per-point: points per tile along x and y (product BT_X * BT_Y)
     int tile_begin; // first work item of the job (within its kind)
 };
 
-// Work items are tiles of BT_X x BT_Y points of one plane, one lane per point.
+// Per-point work items are tiles of one plane, one lane per point: BT_X x
+// BT_Y lanes per workgroup, shaped per job as tile_w x tile_h points
+// (tile_w * tile_h = BT_X * BT_Y; 64 x 4 unless the server's search chose
+// another shape for the job's class). The shape changes no result.
 constexpr int BT_X = 64, BT_Y = 4;
 
 // Table order: the n2d per-point jobs first (2-D jobs and small 3-D jobs:

@@ -30,7 +30,8 @@ __global__ void __launch_bounds__(BT_X * BT_Y) k_batch_advdiff(const void *__res
         const int t = item - J.tile_begin;
         const int bx = t % J.tiles_x, rest = t / J.tiles_x;
         const int by = rest % J.tiles_y, z = rest / J.tiles_y;
-        const int x = bx * BT_X + threadIdx.x, y = by * BT_Y + threadIdx.y;
+        const int lid = threadIdx.x + BT_X * threadIdx.y;
+        const int x = bx * J.tile_w + lid % J.tile_w, y = by * J.tile_h + lid / J.tile_w;
         if (x >= J.g.nx || y >= J.g.ny)
             continue;
         const int pin = (J.parity + sub) & 1;

@@ -99,6 +99,16 @@ __device__ __forceinline__ Buf make_buf(const void *base, uint64_t bytes)
                                                  static_cast<int>(n), BUF_DWORD3)};
 }
 
+// Buffer resource of one padded plane zp (0 .. nz + 2 rz - 1) of an array:
+// lane offsets within a plane stay far below 4 GiB, so kernels that address
+// the input plane by plane work for arrays of any size.
+template <typename S>
+__device__ __forceinline__ Buf plane_buf(const S *base, int64_t sz, int zp)
+{
+    const uint64_t pb = uint64_t(sz) * sizeof(S);
+    return make_buf(reinterpret_cast<const char *>(base) + uint64_t(zp) * pb, pb);
+}
+
 template <typename S> struct BufLd;
 
 template <> struct BufLd<double> {

@@ -4,6 +4,7 @@
 #include "linear_kernels.hpp"
 #include "filter_kernels.hpp"
 #include "plan.hpp"
+#include "tune_cache.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -104,8 +105,6 @@ struct TuneChoice {
     int variant, p0, p1, p2, p3;
 };
 
-std::mutex g_tune_mu;
-std::map<std::string, TuneChoice> g_tune_cache;
 
 template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out, hipStream_t s)
 {
@@ -368,10 +367,9 @@ int autotune(stencil_plan_s *p)
 {
     std::string key = tune_key(p);
     {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            set_choice(p, it->second);
+        std::vector<int> v;
+        if (tune_cache_get(key, v) && v.size() == 5) {
+            set_choice(p, {v[0], v[1], v[2], v[3], v[4]});
             return STENCIL_OK;
         }
     }
@@ -426,8 +424,7 @@ int autotune(stencil_plan_s *p)
     (void)hipFree(a);
     (void)hipFree(b);
     set_choice(p, best_c);
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = best_c;
+    tune_cache_put(key, {best_c.variant, best_c.p0, best_c.p1, best_c.p2, best_c.p3});
     return STENCIL_OK;
 }
 

@@ -44,6 +44,7 @@ struct RkPlan {
     MhdParams mhd{};                     // MHD8 / MHD_FULL
     int variant = STENCIL_RK_VARIANT_CACHED;
     int bx = 64, by = 4, bz = 1; // CACHED: lanes; LDS: brick
+    int occ = 0;                 // LDS bricks: occupancy target (waves per SIMD)
     size_t store_size = 8, reg_size = 8; // bytes per element of f and of w
     int resident = 0; // run whole runs in one launch in LDS (small 2-D FP64 advection)
 };

@@ -3,7 +3,8 @@
 //
 // Two fixed levels, no floating-point atomics: pass 1 gives every workgroup a
 // fixed contiguous range of interior rows and reduces it (lane-strided
-// sequential sums, then a fixed tree in LDS) to one partial triple; pass 2
+// sequential sums over the run's elements, x fastest, then a fixed tree in
+// LDS) to one partial triple; pass 2
 // reduces the partials of each field in one workgroup with the same fixed
 // tree. The result depends only on the grid shape, never on timing.
 #include "reduce_kernels.hpp"
@@ -33,6 +34,37 @@ __device__ __forceinline__ void tree3(double *s0, double *s1, double *s2, double
     b = s1[0];
     c = s2[0];
 }
+// Lane position in a block's contiguous run of interior rows: element i of
+// the run (rows r0.., x fastest) is (x, y, z); step() advances it by RT
+// elements, so the per-element walk needs no 64-bit division (a division
+// only when the row index wraps past a plane).
+struct RowWalk {
+    int x, y, z, dx, dy, nx, ny;
+    __device__ RowWalk(const Geo &g, int64_t r0, int i)
+        : nx(g.nx), ny(g.ny)
+    {
+        const int64_t row = r0 + i / g.nx;
+        x = i % g.nx;
+        y = static_cast<int>(row % g.ny);
+        z = static_cast<int>(row / g.ny);
+        dx = RT % g.nx;
+        dy = RT / g.nx;
+    }
+    __device__ __forceinline__ void step()
+    {
+        x += dx;
+        int cy = dy;
+        if (x >= nx) {
+            x -= nx;
+            ++cy;
+        }
+        y += cy;
+        if (y >= ny) {
+            z += y / ny;
+            y %= ny;
+        }
+    }
+};
 } // namespace
 
 template <typename S>
@@ -47,11 +79,9 @@ __global__ void __launch_bounds__(RT) k_reduce_pass1(FieldPtrs fields, Geo g,
     const int64_t r1 = min(nrows, r0 + rows_per_block);
     const int64_t len = (r1 > r0 ? r1 - r0 : 0) * g.nx;
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int64_t i = threadIdx.x; i < len; i += RT) {
-        int64_t row = r0 + i / g.nx;
-        int x = static_cast<int>(i % g.nx);
-        int y = static_cast<int>(row % g.ny), z = static_cast<int>(row / g.ny);
-        double v = static_cast<double>(Store<S>::ld(f + g.at(x, y, z)));
+    RowWalk w(g, r0, threadIdx.x);
+    for (int64_t i = threadIdx.x; i < len; i += RT, w.step()) {
+        double v = static_cast<double>(Store<S>::ld(f + g.at(w.x, w.y, w.z)));
         a += v;
         b = fma(v, v, b);
         c = fmax(c, fabs(v));
@@ -113,11 +143,9 @@ __global__ void __launch_bounds__(RT) k_energy_pass1(FieldPtrs fields, Geo g, En
         return acc * ec.ids[a];
     };
     double ek = 0.0, em = 0.0, unused = 0.0;
-    for (int64_t i = threadIdx.x; i < len; i += RT) {
-        const int64_t row = r0 + i / g.nx;
-        const int x = static_cast<int>(i % g.nx);
-        const int y = static_cast<int>(row % g.ny), z = static_cast<int>(row / g.ny);
-        const int64_t p = g.at(x, y, z);
+    RowWalk w(g, r0, threadIdx.x);
+    for (int64_t i = threadIdx.x; i < len; i += RT, w.step()) {
+        const int64_t p = g.at(w.x, w.y, w.z);
         double u2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {

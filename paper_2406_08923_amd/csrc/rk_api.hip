@@ -4,9 +4,15 @@
 #include "batch.hpp"
 #include "plan.hpp"
 #include "reduce_kernels.hpp"
+#include "tune_cache.hpp"
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <new>
+#include <utility>
+#include <string>
+#include <vector>
 
 using namespace stn;
 
@@ -82,7 +88,7 @@ int launch_substep(const stencil_plan_s *p, const stencil_fields *f, int sub, do
         return P.variant == STENCIL_RK_VARIANT_LDS ? launch_rk_advdiff3_zm(P.policy, a, P.bz, s)
                                                    : launch_rk_advdiff(P.policy, a, P.bx, P.by, s);
     if (P.variant == STENCIL_RK_VARIANT_LDS)
-        return launch_rk_mhd8_lds(P.model, P.mixed, P.policy, a, P.bx, P.by, P.bz, s);
+        return launch_rk_mhd8_lds(P.model, P.mixed, P.policy, a, P.bx, P.by, P.bz, P.occ, s);
     return launch_rk_mhd8(P.model, P.mixed, P.policy, a, P.bx, P.by, s);
 }
 
@@ -116,6 +122,167 @@ template <typename S> int halo_fields(const stencil_plan_s *p, void *const *bufs
         int rc = launch_halo<S>(static_cast<S *>(bufs[k]), p->rk.g, s);
         if (rc) return rc;
     }
+    return STENCIL_OK;
+}
+
+bool brick_built(int bx, int by, int bz, int occ)
+{
+    bool ok = false;
+#define RK_BRICK_OK(X_, Y_, Z_, O_) ok = ok || (bx == X_ && by == Y_ && bz == Z_ && occ == O_);
+    RK_BRICK_SHAPES(RK_BRICK_OK)
+#undef RK_BRICK_OK
+    return ok;
+}
+
+// A schedule of an RK plan: variant, block (bx, by, bz), occupancy target.
+struct RkSched {
+    int variant, bx, by, bz, occ;
+};
+
+std::string rk_tune_key(const RkPlan &P)
+{
+    char buf[256];
+    snprintf(buf, sizeof(buf), "rk|m%d|x%d|p%d|nd%d|%dx%dx%d|ox%d|sy%lld", P.model, P.mixed,
+             P.policy, P.g.ndim, P.g.nx, P.g.ny, P.g.nz, P.g.ox, (long long)P.g.sy);
+    return buf;
+}
+
+// Candidate schedules; fixed_* restrict the search to what the descriptor
+// pinned.
+std::vector<RkSched> rk_candidates(const RkPlan &P, int fixed_variant, bool fixed_block,
+                                   bool fixed_occ)
+{
+    std::vector<RkSched> c;
+    const bool mhd = P.model != STENCIL_MODEL_ADVDIFF;
+    auto want = [&](int v) { return fixed_variant == STENCIL_RK_VARIANT_AUTO || fixed_variant == v; };
+    if (want(STENCIL_RK_VARIANT_LDS)) {
+        if (mhd) {
+#define RK_BRICK_CAND(X_, Y_, Z_, O_)                                                        \
+    if ((!fixed_block || (P.bx == X_ && P.by == Y_ && P.bz == Z_)) && (!fixed_occ || P.occ == O_)) \
+        c.push_back({STENCIL_RK_VARIANT_LDS, X_, Y_, Z_, O_});
+            RK_BRICK_SHAPES(RK_BRICK_CAND)
+#undef RK_BRICK_CAND
+        } else if (P.g.ndim == 3) {
+            for (int lz : {8, 16, 32, 64})
+                if (!fixed_block || P.bz == lz)
+                    c.push_back({STENCIL_RK_VARIANT_LDS, ZM_TX, ZM_ROWS, lz, 0});
+        }
+    }
+    if (want(STENCIL_RK_VARIANT_CACHED) && !fixed_occ) {
+        const int tiles[][2] = {{64, 4}, {64, 2}, {128, 2}, {256, 1}, {64, 1}};
+        for (auto &t : tiles)
+            if (!fixed_block || (P.bx == t[0] && P.by == t[1]))
+                c.push_back({STENCIL_RK_VARIANT_CACHED, t[0], t[1], 1, 0});
+    }
+    return c;
+}
+
+void set_sched(RkPlan &P, const RkSched &c)
+{
+    P.variant = c.variant;
+    P.bx = c.bx;
+    P.by = c.by;
+    P.bz = c.bz;
+    P.occ = c.occ;
+}
+
+// Time one RK3 step of every candidate on scratch buffers (one warm-up step,
+// best of two timed steps; candidates whose launch fails are dropped) and keep
+// the fastest. The field values do not matter for the timing: the buffers are
+// zero (a valid state of every model).
+int rk_autotune(stencil_plan_s *p, int fixed_variant, bool fixed_block, bool fixed_occ)
+{
+    RkPlan &P = p->rk;
+    const std::string key = rk_tune_key(P) + "|v" + std::to_string(fixed_variant) +
+                            (fixed_block ? "|b" + std::to_string(P.bx) + "x" + std::to_string(P.by) +
+                                               "x" + std::to_string(P.bz)
+                                         : std::string()) +
+                            (fixed_occ ? "|o" + std::to_string(P.occ) : std::string());
+    {
+        std::vector<int> v;
+        if (tune_cache_get(key, v) && v.size() == 5) {
+            set_sched(P, {v[0], v[1], v[2], v[3], v[4]});
+            return STENCIL_OK;
+        }
+    }
+    const std::vector<RkSched> cands = rk_candidates(P, fixed_variant, fixed_block, fixed_occ);
+    if (cands.empty())
+        return STENCIL_OK;
+    const size_t n = (size_t)padded_elems(P.g);
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; }; // keep every buffer aligned
+    const size_t fb = up(n * P.store_size), wb = up(n * P.reg_size), mb = up(n * 8);
+    const bool master = master_policy(P.policy);
+    const size_t per = 2 * fb + wb + (master ? wb + mb : 0);
+    char *base = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&base), per * P.nf) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(STENCIL_ENOMEM, "rk autotune: cannot allocate %zu bytes of scratch",
+                    per * P.nf);
+    }
+    if (hipMemset(base, 0, per * P.nf) != hipSuccess) {
+        (void)hipFree(base);
+        return fail(STENCIL_EDEVICE, "rk autotune: cannot clear the scratch buffers");
+    }
+    stencil_fields f{};
+    for (int k = 0; k < P.nf; ++k) {
+        char *q = base + per * k;
+        f.f_in[k] = q;
+        f.f_out[k] = q + fb;
+        f.w[k] = q + 2 * fb;
+        if (master) {
+            f.w2[k] = q + 2 * fb + wb;
+            f.f64[k] = reinterpret_cast<double *>(q + 2 * fb + 2 * wb);
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipFree(base);
+        return fail(STENCIL_EDEVICE, "rk autotune: cannot create timing events");
+    }
+    const double dt = 1e-3;
+    auto one_step = [&]() {
+        stencil_fields cur = f;
+        int rc = STENCIL_OK;
+        for (int sub = 0; sub < 3 && rc == STENCIL_OK; ++sub) {
+            rc = launch_substep(p, &cur, sub, dt, nullptr);
+            for (int k = 0; k < P.nf; ++k)
+                std::swap(cur.f_in[k], cur.f_out[k]);
+        }
+        return rc;
+    };
+    float best = 1e30f;
+    RkSched best_c = {P.variant, P.bx, P.by, P.bz, P.occ};
+    for (const RkSched &c : cands) {
+        set_sched(P, c);
+        if (one_step() != STENCIL_OK || hipDeviceSynchronize() != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        float ms = 1e30f;
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {
+            ok = hipEventRecord(e0, nullptr) == hipSuccess && one_step() == STENCIL_OK &&
+                 hipEventRecord(e1, nullptr) == hipSuccess &&
+                 hipEventSynchronize(e1) == hipSuccess;
+            float t = 0;
+            if (ok && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+                ms = std::min(ms, t);
+        }
+        if (!ok) {
+            (void)hipGetLastError();
+            continue;
+        }
+        if (ms < best) {
+            best = ms;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(base);
+    set_sched(P, best_c);
+    tune_cache_put(key, {best_c.variant, best_c.bx, best_c.by, best_c.bz, best_c.occ});
     return STENCIL_OK;
 }
 
@@ -170,6 +337,12 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
                     d->row_pitch, (long long)min_pitch);
     if (d->variant < STENCIL_RK_VARIANT_AUTO || d->variant > STENCIL_RK_VARIANT_LDS)
         return fail(STENCIL_EINVAL, "unknown derivative-bank variant %d", d->variant);
+    if (d->flags & ~STENCIL_RK_FLAG_AUTOTUNE)
+        return fail(STENCIL_EINVAL, "unknown RK plan flags 0x%x", d->flags);
+    if (d->occupancy < 0 || d->occupancy > 8)
+        return fail(STENCIL_EINVAL, "occupancy %d not in 0..8", d->occupancy);
+    if (d->occupancy && (!mhd || d->variant == STENCIL_RK_VARIANT_CACHED))
+        return fail(STENCIL_EINVAL, "an occupancy target applies to the MHD LDS bricks only");
     if (d->variant == STENCIL_RK_VARIANT_LDS && d->model == STENCIL_MODEL_ADVDIFF &&
         d->ndim != 3)
         return fail(STENCIL_EUNSUPPORTED, "the staged advection kernel is 3-D");
@@ -199,12 +372,9 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
         bx = d->block[0] ? d->block[0] : f64 ? 16 : 32;
         by = d->block[1] ? d->block[1] : f64 ? 8 : 4;
         bz = d->block[2] ? d->block[2] : f64 ? 8 : 4;
-        bool ok = false;
-#define RK_BRICK_OK(X_, Y_, Z_) ok = ok || (bx == X_ && by == Y_ && bz == Z_);
-        RK_BRICK_SHAPES(RK_BRICK_OK)
-#undef RK_BRICK_OK
-        if (!ok)
-            return fail(STENCIL_EINVAL, "brick %dx%dx%d is not built", bx, by, bz);
+        if (!brick_built(bx, by, bz, d->occupancy))
+            return fail(STENCIL_EINVAL, "brick %dx%dx%d with occupancy %d is not built", bx, by,
+                        bz, d->occupancy);
     } else {
         bx = d->block[0] ? d->block[0] : 64;
         by = d->block[1] ? d->block[1] : 4;
@@ -216,6 +386,16 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
             return fail(STENCIL_EINVAL, "block[2] must be 0 or 1 (one z plane per workgroup)");
     }
 
+    {
+        // the fused-substep kernels address each buffer with 32-bit offsets
+        // (raw buffer loads): FP64 buffers must stay below 4 GiB
+        int64_t cells = d->row_pitch ? d->row_pitch : min_pitch;
+        for (int a = 1; a < d->ndim; ++a) cells *= (int64_t)d->dims[a] + 6;
+        if (cells * 8 >= (int64_t(1) << 32))
+            return fail(STENCIL_EUNSUPPORTED,
+                        "RK plans need padded buffers below 4 GiB in FP64 (%lld cells)",
+                        (long long)cells);
+    }
     auto *p = new (std::nothrow) stencil_plan_s();
     if (!p)
         return fail(STENCIL_ENOMEM, "out of host memory");
@@ -260,6 +440,7 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     P.bx = bx;
     P.by = by;
     P.bz = bz;
+    P.occ = variant == STENCIL_RK_VARIANT_LDS && mhd ? d->occupancy : 0;
     if (P.model == STENCIL_MODEL_ADVDIFF && variant == STENCIL_RK_VARIANT_LDS && !P.bz)
         P.bz = advdiff_zmarch_lz(P.g);
     P.store_size = dtype_size(store_dtype(P.policy));
@@ -268,7 +449,30 @@ stencil_status stencil_plan_rk(const stencil_rk_desc *d, stencil_plan_t *out)
     // the state in LDS for the whole run (one launch)
     P.resident = d->variant == STENCIL_RK_VARIANT_AUTO && d->model == STENCIL_MODEL_ADVDIFF &&
                  P.policy == POL_F64 && resident_fits(d->ndim, d->dims[0], d->dims[1]);
+    if ((d->flags & STENCIL_RK_FLAG_AUTOTUNE) && !P.resident) {
+        const bool fixed_block = d->block[0] || d->block[1] || d->block[2];
+        const int rc2 = rk_autotune(p, d->variant, fixed_block, d->occupancy != 0);
+        if (rc2) {
+            delete p;
+            return rc2;
+        }
+    }
     *out = p;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_plan_rk_schedule(stencil_plan_t p, int out[5])
+{
+    if (!p || p->kind != PLAN_RK)
+        return fail(STENCIL_EINVAL, "not an RK plan");
+    if (!out)
+        return fail(STENCIL_EINVAL, "NULL output");
+    const RkPlan &P = p->rk;
+    out[0] = P.variant;
+    out[1] = P.bx;
+    out[2] = P.by;
+    out[3] = P.bz;
+    out[4] = P.occ;
     return STENCIL_OK;
 }
 

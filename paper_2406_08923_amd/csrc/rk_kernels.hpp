@@ -61,11 +61,14 @@ struct RkArgs {
 int launch_rk_mhd8(int model, int mixed, int policy, const RkArgs &a, int bx, int by,
                    hipStream_t s);
 
-// LDS-brick variant of the MHD8 substep (rk_mhd8_lds.hip): bricks of
-// bx x by x bz output points, one of RK_BRICK_SHAPES
-#define RK_BRICK_SHAPES(X) X(16, 8, 4) X(16, 8, 8) X(32, 4, 4) X(8, 8, 8)
+// LDS-brick variant of the MHD8 substep (rk_mhd8_lds.hpp): bricks of
+// bx x by x bz output points with an occupancy target (waves per SIMD the
+// compiler is held to; 0 = its own choice), one of RK_BRICK_SHAPES
+#define RK_BRICK_SHAPES(X)                                                                   \
+    X(16, 8, 4, 0) X(16, 8, 4, 4) X(16, 8, 8, 0) X(32, 4, 4, 0) X(32, 4, 4, 4) X(8, 8, 8, 0)  \
+    X(8, 8, 8, 4)
 int launch_rk_mhd8_lds(int model, int mixed, int policy, const RkArgs &a, int bx, int by,
-                       int bz, hipStream_t s);
+                       int bz, int occ, hipStream_t s);
 int launch_rk_advdiff(int policy, const RkArgs &a, int bx, int by, hipStream_t s);
 // Small 2-D FP64 advection-diffusion grids whose state fits in LDS: every
 // step of a run in one launch of one workgroup (k_rk_advdiff2_resident).

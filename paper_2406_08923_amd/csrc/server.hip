@@ -17,6 +17,7 @@
 // running jobs and latches the server.
 #include "advdiff_zm.hpp"
 #include "batch.hpp"
+#include "tune_cache.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -26,6 +27,7 @@
 #include <deque>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -112,6 +114,9 @@ struct stencil_server_s {
     stencil_server_stats st{};
     FdWeights fd{};
     long long min_points = 0;
+    // batch schedule per job class (ndim, dims, policy): z-march jobs {lz, 0},
+    // per-point jobs {tile_w, tile_h}; filled by the search (desc.tune)
+    std::unordered_map<std::string, std::pair<int, int>> sched;
 
     double clock() const
     {
@@ -151,11 +156,151 @@ struct stencil_server_s {
         cv_done.notify_all();
     }
 
-    // allocate and upload one admitted job; returns a status
-    int start_job(SJob &j)
+    static int job_policy(const stencil_job &d)
     {
-        const stencil_job &d = j.d;
-        BatchJob &b = j.bj;
+        return d.precision == STENCIL_PREC_F64 ? POL_F64
+               : d.precision == STENCIL_PREC_F32_MASTER64 ? POL_F32_MASTER64
+                                                          : POL_F32_ONLY;
+    }
+
+    static std::string class_key(const stencil_job &d)
+    {
+        return "batch|nd" + std::to_string(d.ndim) + "|" + std::to_string(d.dims[0]) + "x" +
+               std::to_string(d.dims[1]) + "x" + std::to_string(d.ndim == 3 ? d.dims[2] : 1) +
+               "|p" + std::to_string(job_policy(d));
+    }
+
+    // the default schedule of a job (no search): z march depth from the grid
+    // size, 64 x 4 per-point tiles
+    static std::pair<int, int> default_sched(const BatchJob &b)
+    {
+        if (advdiff_uses_zmarch(b.g))
+            return {advdiff_zmarch_lz(b.g), 0};
+        return {BT_X, BT_Y};
+    }
+
+    // Search of a job class's batch schedule (Sec. 5.1: candidates timed,
+    // failed launches dropped): the job's substeps are run through the
+    // batched kernels as a one-job table on scratch buffers of its size, for
+    // every candidate (z-march jobs: 8, 16, 32, 64 planes per tile; per-point
+    // jobs: 64 x 4, 128 x 2, 256 x 1, 32 x 8 point tiles); one warm-up step,
+    // best of two timed steps. Runs between ticks (the device is idle), on the
+    // compute stream. Every candidate computes the same arithmetic per point.
+    void tune_class(const SJob &j)
+    {
+        const std::string key = class_key(j.d);
+        if (sched.count(key))
+            return;
+        std::vector<int> v;
+        if (tune_cache_get(key, v) && v.size() == 2) {
+            sched[key] = {v[0], v[1]};
+            return;
+        }
+        BatchJob b{};
+        fill_job(j.d, b);
+        const bool zm = advdiff_uses_zmarch(b.g);
+        std::vector<std::pair<int, int>> cands;
+        if (zm) {
+            for (int lz : {8, 16, 32, 64})
+                if (lz <= b.g.nz || lz == 8)
+                    cands.push_back({lz, 0});
+        } else {
+            cands = {{64, 4}, {128, 2}, {256, 1}, {32, 8}};
+        }
+        const size_t pad = (size_t)padded_elems(b.g);
+        const size_t es = b.policy == POL_F64 ? 8 : 4;
+        const bool master = b.policy == POL_F32_MASTER64;
+        char *base = nullptr;
+        void *tab = nullptr;
+        auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+        const size_t fb = up(pad * es), mb = up(pad * 8);
+        const size_t total = 3 * fb + (master ? fb + mb : 0);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        std::pair<int, int> best = default_sched(b);
+        float best_ms = 1e30f;
+        bool ok = hipMalloc(reinterpret_cast<void **>(&base), total) == hipSuccess &&
+                  hipMalloc(&tab, batch_table_bytes(1)) == hipSuccess &&
+                  hipMemset(base, 0, total) == hipSuccess &&
+                  hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+        if (ok) {
+            b.f[0] = base;
+            b.f[1] = base + fb;
+            b.w = base + 2 * fb;
+            if (master) {
+                b.w2 = base + 3 * fb;
+                b.f64 = reinterpret_cast<double *>(base + 4 * fb);
+            }
+            b.steps = 1;
+            b.parity = 0;
+            b.tile_begin = 0;
+            for (const auto &c : cands) {
+                BatchTableHeader h{};
+                BatchJob r = b;
+                if (zm) {
+                    r.tiles_x = (b.g.nx + ZM_TX - 1) / ZM_TX;
+                    r.tiles_y = (b.g.ny + ZM_ROWS - 1) / ZM_ROWS;
+                    r.lz = c.first;
+                    h.njobs = 1;
+                    h.n2d = 0;
+                    h.total3 = r.tiles_x * r.tiles_y * ((b.g.nz + r.lz - 1) / r.lz);
+                } else {
+                    r.tile_w = c.first;
+                    r.tile_h = c.second;
+                    r.tiles_x = (b.g.nx + r.tile_w - 1) / r.tile_w;
+                    r.tiles_y = (b.g.ny + r.tile_h - 1) / r.tile_h;
+                    h.njobs = 1;
+                    h.n2d = 1;
+                    h.total_tiles = r.tiles_x * r.tiles_y * b.g.nz;
+                }
+                std::vector<char> host(batch_table_bytes(1));
+                std::memcpy(host.data(), &h, sizeof(h));
+                std::memcpy(host.data() + sizeof(h), &r, sizeof(r));
+                if (hipMemcpy(tab, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
+                    break;
+                auto one_step = [&]() {
+                    int rc = STENCIL_OK;
+                    for (int sub = 0; sub < 3 && !rc; ++sub)
+                        rc = launch_batch_substep(tab, sub, rk, d.blocks, stream);
+                    return rc;
+                };
+                if (one_step() || hipStreamSynchronize(stream) != hipSuccess) {
+                    (void)hipGetLastError();
+                    continue;
+                }
+                float ms = 1e30f;
+                bool good = true;
+                for (int rep = 0; rep < 2 && good; ++rep) {
+                    good = hipEventRecord(e0, stream) == hipSuccess && one_step() == STENCIL_OK &&
+                           hipEventRecord(e1, stream) == hipSuccess &&
+                           hipEventSynchronize(e1) == hipSuccess;
+                    float t = 0;
+                    if (good && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+                        ms = std::min(ms, t);
+                }
+                if (!good) {
+                    (void)hipGetLastError();
+                    continue;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+        }
+        (void)hipGetLastError();
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (tab) (void)hipFree(tab);
+        if (base) (void)hipFree(base);
+        sched[key] = best;
+        tune_cache_put(key, {best.first, best.second});
+        std::lock_guard<std::mutex> lk(mu);
+        st.tuned_classes++;
+    }
+
+    // geometry and constants of a job's batch record (buffers not set)
+    void fill_job(const stencil_job &d, BatchJob &b) const
+    {
         b.g = make_geo(d.ndim, d.dims, 3);
         b.fd = fd;
         double dsmin = 1e300;
@@ -169,10 +314,18 @@ struct stencil_server_s {
         for (int a = 0; a < d.ndim; ++a) cmax = std::max(cmax, std::fabs(d.adv[a]));
         b.nu = d.nu;
         b.dt = d.dt > 0 ? d.dt : 0.1 * dsmin / cmax;
-        b.policy = d.precision == STENCIL_PREC_F64 ? POL_F64
-                   : d.precision == STENCIL_PREC_F32_MASTER64 ? POL_F32_MASTER64
-                                                              : POL_F32_ONLY;
+        b.policy = job_policy(d);
         b.parity = 0;
+        b.tile_w = BT_X;
+        b.tile_h = BT_Y;
+    }
+
+    // allocate and upload one admitted job; returns a status
+    int start_job(SJob &j)
+    {
+        const stencil_job &d = j.d;
+        BatchJob &b = j.bj;
+        fill_job(d, b);
         // stream-ordered allocation and upload on the copy stream; the caller
         // waits for the copy stream before the job joins a tick
         const size_t pad = (size_t)padded_elems(b.g);
@@ -321,15 +474,23 @@ struct stencil_server_s {
                     continue;
                 BatchJob b = jp->bj;
                 b.steps = jp->steps_tick;
+                std::pair<int, int> sc = default_sched(b);
+                if (d.tune) {
+                    auto it = sched.find(class_key(jp->d));
+                    if (it != sched.end())
+                        sc = it->second;
+                }
                 if (!d3) {
-                    b.tiles_x = (b.g.nx + BT_X - 1) / BT_X;
-                    b.tiles_y = (b.g.ny + BT_Y - 1) / BT_Y;
+                    b.tile_w = sc.first;
+                    b.tile_h = sc.second;
+                    b.tiles_x = (b.g.nx + b.tile_w - 1) / b.tile_w;
+                    b.tiles_y = (b.g.ny + b.tile_h - 1) / b.tile_h;
                     b.tile_begin = tiles;
                     tiles += b.tiles_x * b.tiles_y * b.g.nz;
                 } else {
                     b.tiles_x = (b.g.nx + ZM_TX - 1) / ZM_TX;
                     b.tiles_y = (b.g.ny + ZM_ROWS - 1) / ZM_ROWS;
-                    b.lz = advdiff_zmarch_lz(b.g);
+                    b.lz = sc.first;
                     b.tile_begin = tiles3;
                     tiles3 += b.tiles_x * b.tiles_y * ((b.g.nz + b.lz - 1) / b.lz);
                 }
@@ -430,6 +591,12 @@ struct stencil_server_s {
                     }
                 }
             }
+
+            // 0. schedule search for job classes seen for the first time (the
+            //    device is idle here: the previous tick and copies finished)
+            if (d.tune)
+                for (auto &j : admit)
+                    tune_class(*j);
 
             // 1. the tick of the resident jobs, enqueued on the compute stream
             const double tb = clock();

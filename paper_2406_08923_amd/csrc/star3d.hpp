@@ -78,16 +78,13 @@ __global__ void __launch_bounds__(64 * XW * TY)
     const int z0 = bzi * lz;
     const int z1 = min(z0 + lz, g.nz);
     const bool fuse = (flags & STAR_FLAG_NOFUSE) == 0;
-    const Buf src = make_buf(in, uint64_t(padded_elems(g)) * es);
-
     // clamp reads into the padded array: any coordinate in [-R, n+R) is valid
     auto cl = [](int v, int n) { return min(max(v, -R), n + R - 1); };
-    // byte offset of interior column (x, y) within a plane; plane z adds
-    // (z + rz) * sz * es as the scalar operand
+    // byte offset of interior column (x, y) within a plane; each plane is
+    // read through its own buffer resource (plane_buf)
     auto col = [&](int xx, int yy) {
         return uint32_t(xx + g.ox + g.sy * (yy + g.ry)) * es;
     };
-    auto plane = [&](int zz) { return uint32_t(zz + g.rz) * uint32_t(g.sz) * es; };
 
     const int x = x0 + tx;
     const int xl = cl(x, g.nx);
@@ -152,17 +149,17 @@ __global__ void __launch_bounds__(64 * XW * TY)
         for (int k = 0; k < 2 * R; ++k)
 #pragma unroll
             for (int j = 0; j < NY; ++j)
-                ring[j][k] = BufLd<S>::ld(src, col_off[j], plane(z0 - R + k));
+                ring[j][k] = BufLd<S>::ld(plane_buf(in, g.sz, z0 - R + k + g.rz), col_off[j], 0);
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int zq = min(z0 + q, z1 - 1); // in range: any valid plane will do
 #pragma unroll
             for (int j = 0; j < NY; ++j)
-                ring[j][2 * R + q] = BufLd<S>::ld(src, col_off[j], plane(zq + R));
+                ring[j][2 * R + q] = BufLd<S>::ld(plane_buf(in, g.sz, zq + R + g.rz), col_off[j], 0);
 #pragma unroll
-            for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zq));
+            for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, zq + g.rz), hx_off[k], 0);
 #pragma unroll
-            for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zq));
+            for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, zq + g.rz), hy_off[k], 0);
         }
         for (int zb = z0; zb < z1; zb += NR) {
 #pragma unroll
@@ -185,13 +182,13 @@ __global__ void __launch_bounds__(64 * XW * TY)
                     const int zn = min(z + PF, z1 - 1);
 #pragma unroll
                     for (int j = 0; j < NY; ++j)
-                        ring[j][RS(R + PF)] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+                        ring[j][RS(R + PF)] = BufLd<S>::ld(plane_buf(in, g.sz, zn + R + g.rz), col_off[j], 0);
 #pragma unroll
                     for (int k = 0; k < SH::HX_PER; ++k)
-                        hxr[(q + PF) % NH][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
+                        hxr[(q + PF) % NH][k] = BufLd<S>::ld(plane_buf(in, g.sz, zn + g.rz), hx_off[k], 0);
 #pragma unroll
                     for (int k = 0; k < SH::HY_PER; ++k)
-                        hyr[(q + PF) % NH][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
+                        hyr[(q + PF) % NH][k] = BufLd<S>::ld(plane_buf(in, g.sz, zn + g.rz), hy_off[k], 0);
                 }
 #pragma unroll
                 for (int j = 0; j < NY; ++j) {
@@ -230,7 +227,7 @@ __global__ void __launch_bounds__(64 * XW * TY)
         for (int k = 0; k < 2 * R; ++k)
     #pragma unroll
             for (int j = 0; j < NY; ++j)
-                win[j][k + 1] = BufLd<S>::ld(src, col_off[j], plane(z0 - R + k));
+                win[j][k + 1] = BufLd<S>::ld(plane_buf(in, g.sz, z0 - R + k + g.rz), col_off[j], 0);
 
         // prefetch ring: slot q holds plane z0 + q (+R for the window value)
         C pre_w[PF][NY], pre_hx[PF][SH::HX_PER], pre_hy[PF][SH::HY_PER];
@@ -238,11 +235,11 @@ __global__ void __launch_bounds__(64 * XW * TY)
         for (int q = 0; q < PF; ++q) {
             const int zq = min(z0 + q, z1 - 1); // in range: any valid plane will do
     #pragma unroll
-            for (int j = 0; j < NY; ++j) pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zq + R));
+            for (int j = 0; j < NY; ++j) pre_w[q][j] = BufLd<S>::ld(plane_buf(in, g.sz, zq + R + g.rz), col_off[j], 0);
     #pragma unroll
-            for (int k = 0; k < SH::HX_PER; ++k) pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zq));
+            for (int k = 0; k < SH::HX_PER; ++k) pre_hx[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, zq + g.rz), hx_off[k], 0);
     #pragma unroll
-            for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zq));
+            for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, zq + g.rz), hy_off[k], 0);
         }
 
         for (int zb = z0; zb < z1; zb += PF) {
@@ -273,13 +270,13 @@ __global__ void __launch_bounds__(64 * XW * TY)
                     const int zn = min(z + PF, z1 - 1);
     #pragma unroll
                     for (int j = 0; j < NY; ++j)
-                        pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zn + R));
+                        pre_w[q][j] = BufLd<S>::ld(plane_buf(in, g.sz, zn + R + g.rz), col_off[j], 0);
     #pragma unroll
                     for (int k = 0; k < SH::HX_PER; ++k)
-                        pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zn));
+                        pre_hx[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, zn + g.rz), hx_off[k], 0);
     #pragma unroll
                     for (int k = 0; k < SH::HY_PER; ++k)
-                        pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zn));
+                        pre_hy[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, zn + g.rz), hy_off[k], 0);
                 }
 
     #pragma unroll
@@ -552,8 +549,6 @@ int launch_star3d_t2_impl(const S *in, S *out, const Geo &g, const StarCoefAny &
     using C = typename Store<S>::C;
     if (g.ndim != 3 || R < 1)
         return fail(STENCIL_EINVAL, "star3d (two iterations): needs a 3-D star");
-    if (uint64_t(padded_elems(g)) * sizeof(S) >= (uint64_t(1) << 32))
-        return fail(STENCIL_EUNSUPPORTED, "star3d: arrays of 4 GiB or more are not supported");
     if (lz < 1)
         return fail(STENCIL_EINVAL, "star3d: z planes per workgroup must be >= 1");
     switch (R) {
@@ -572,9 +567,10 @@ int launch_star3d_impl(const S *in, S *out, const Geo &g, const StarCoefAny &cfa
     using C = typename Store<S>::C;
     if (R > g.r || g.ndim != 3)
         return fail(STENCIL_EINVAL, "star3d: tap radius %d exceeds padding %d", R, g.r);
-    if (uint64_t(padded_elems(g)) * sizeof(S) >= (uint64_t(1) << 32))
-        return fail(STENCIL_EUNSUPPORTED, "star3d: arrays of 4 GiB or more are not supported");
     if (flags & STAR_FLAG_HWC) {
+        if (uint64_t(padded_elems(g)) * sizeof(S) >= (uint64_t(1) << 32))
+            return fail(STENCIL_EUNSUPPORTED,
+                        "star3d (hardware-cached): arrays of 4 GiB or more are not supported");
         switch (R) {
         case 1: return launch_star3d_hwc_r<S, 1>(in, out, g, cfa.get<C, 1>(), ty, ny, lz, flags, s);
         case 2: return launch_star3d_hwc_r<S, 2>(in, out, g, cfa.get<C, 2>(), ty, ny, lz, flags, s);

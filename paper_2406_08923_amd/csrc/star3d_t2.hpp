@@ -64,12 +64,10 @@ __device__ __forceinline__ void star3d_t2_segment(
     const int tid = tx + SH::TXW * ty;
     const int fx0 = bxi * OX - R, fy0 = byi * OY - R;
     constexpr bool fuse = IMG; // write the output's periodic images
-    const Buf src = make_buf(in, uint64_t(padded_elems(g)) * es);
 
     auto col = [&](int xx, int yy) {
         return uint32_t(wrap_mod(xx, g.nx) + g.ox + g.sy * (wrap_mod(yy, g.ny) + g.ry)) * es;
     };
-    auto plane = [&](int zz) { return uint32_t(wrap_mod(zz, g.nz) + g.rz) * uint32_t(g.sz) * es; };
 
     uint32_t col_off[NY];
 #pragma unroll
@@ -128,13 +126,13 @@ __device__ __forceinline__ void star3d_t2_segment(
         for (int k = 0; k < 2 * R + PF; ++k)
     #pragma unroll
             for (int j = 0; j < NY; ++j)
-                ring[j][k] = BufLd<S>::ld(src, col_off[j], plane(zs - R + k));
+                ring[j][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs - R + k, g.nz) + g.rz), col_off[j], 0);
     #pragma unroll
         for (int q = 0; q < PF; ++q) {
     #pragma unroll
-            for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zs + q));
+            for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hx_off[k], 0);
     #pragma unroll
-            for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zs + q));
+            for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hy_off[k], 0);
         }
 
         // Halo cells are written unconditionally: a lane without one writes
@@ -147,8 +145,6 @@ __device__ __forceinline__ void star3d_t2_segment(
         for (int k = 0; k < SH::HX_PER; ++k) hx_dst[k] = hx_slot[k] >= 0 ? hx_slot[k] : own;
     #pragma unroll
         for (int k = 0; k < SH::HY_PER; ++k) hy_dst[k] = hy_slot[k] >= 0 ? hy_slot[k] : own;
-
-        const uint32_t pbytes = uint32_t(g.sz) * es;
         for (int zb = zs; zb <= ze; zb += NR) {
     #pragma unroll
             for (int q = 0; q < NR; ++q) {
@@ -179,17 +175,17 @@ __device__ __forceinline__ void star3d_t2_segment(
                     // so zA + PF + nz >= 0: an unsigned remainder wraps it, at
                     // half the scalar work of a signed one
                     const uint32_t nzu = uint32_t(g.nz), zu = uint32_t(zA + PF + g.nz);
-                    const uint32_t pw = ((zu + R) % nzu + uint32_t(g.rz)) * pbytes;
-                    const uint32_t ph = (zu % nzu + uint32_t(g.rz)) * pbytes;
+                    const Buf bw = plane_buf(in, g.sz, int((zu + R) % nzu) + g.rz);
+                    const Buf bh = plane_buf(in, g.sz, int(zu % nzu) + g.rz);
     #pragma unroll
                     for (int j = 0; j < NY; ++j)
-                        ring[j][F0(R + PF)] = BufLd<S>::ld(src, col_off[j], pw);
+                        ring[j][F0(R + PF)] = BufLd<S>::ld(bw, col_off[j], 0);
     #pragma unroll
                     for (int k = 0; k < SH::HX_PER; ++k)
-                        hxr[(q + PF) % NH][k] = BufLd<S>::ld(src, hx_off[k], ph);
+                        hxr[(q + PF) % NH][k] = BufLd<S>::ld(bh, hx_off[k], 0);
     #pragma unroll
                     for (int k = 0; k < SH::HY_PER; ++k)
-                        hyr[(q + PF) % NH][k] = BufLd<S>::ld(src, hy_off[k], ph);
+                        hyr[(q + PF) % NH][k] = BufLd<S>::ld(bh, hy_off[k], 0);
                 }
 
                 // stage B: f2 at plane zB from the f1 ring and f1's plane in LDS
@@ -270,17 +266,17 @@ __device__ __forceinline__ void star3d_t2_segment(
         for (int k = 0; k < 2 * R; ++k)
     #pragma unroll
             for (int j = 0; j < NY; ++j)
-                win[j][k + 1] = BufLd<S>::ld(src, col_off[j], plane(zs - R + k));
+                win[j][k + 1] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs - R + k, g.nz) + g.rz), col_off[j], 0);
 
         C pre_w[PF][NY], pre_hx[PF][SH::HX_PER], pre_hy[PF][SH::HY_PER];
     #pragma unroll
         for (int q = 0; q < PF; ++q) {
     #pragma unroll
-            for (int j = 0; j < NY; ++j) pre_w[q][j] = BufLd<S>::ld(src, col_off[j], plane(zs + q + R));
+            for (int j = 0; j < NY; ++j) pre_w[q][j] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q + R, g.nz) + g.rz), col_off[j], 0);
     #pragma unroll
-            for (int k = 0; k < SH::HX_PER; ++k) pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zs + q));
+            for (int k = 0; k < SH::HX_PER; ++k) pre_hx[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hx_off[k], 0);
     #pragma unroll
-            for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zs + q));
+            for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hy_off[k], 0);
         }
 
         // halo cells written unconditionally, as in the ring march
@@ -290,7 +286,6 @@ __device__ __forceinline__ void star3d_t2_segment(
         for (int k = 0; k < SH::HX_PER; ++k) hx_dst[k] = hx_slot[k] >= 0 ? hx_slot[k] : own;
     #pragma unroll
         for (int k = 0; k < SH::HY_PER; ++k) hy_dst[k] = hy_slot[k] >= 0 ? hy_slot[k] : own;
-        const uint32_t pbytes = uint32_t(g.sz) * es;
 
         for (int zb = zs; zb <= ze; zb += PF) {
     #pragma unroll
@@ -317,17 +312,17 @@ __device__ __forceinline__ void star3d_t2_segment(
                 {
                     // zA + PF + nz >= 0: unsigned remainder, as in the ring march
                     const uint32_t nzu = uint32_t(g.nz), zu = uint32_t(zA + PF + g.nz);
-                    const uint32_t pw = ((zu + R) % nzu + uint32_t(g.rz)) * pbytes;
-                    const uint32_t ph = (zu % nzu + uint32_t(g.rz)) * pbytes;
+                    const Buf bw = plane_buf(in, g.sz, int((zu + R) % nzu) + g.rz);
+                    const Buf bh = plane_buf(in, g.sz, int(zu % nzu) + g.rz);
     #pragma unroll
                     for (int j = 0; j < NY; ++j)
-                        pre_w[q][j] = BufLd<S>::ld(src, col_off[j], pw);
+                        pre_w[q][j] = BufLd<S>::ld(bw, col_off[j], 0);
     #pragma unroll
                     for (int k = 0; k < SH::HX_PER; ++k)
-                        pre_hx[q][k] = BufLd<S>::ld(src, hx_off[k], ph);
+                        pre_hx[q][k] = BufLd<S>::ld(bh, hx_off[k], 0);
     #pragma unroll
                     for (int k = 0; k < SH::HY_PER; ++k)
-                        pre_hy[q][k] = BufLd<S>::ld(src, hy_off[k], ph);
+                        pre_hy[q][k] = BufLd<S>::ld(bh, hy_off[k], 0);
                 }
 
                 // stage B: f2 at plane zB from the f1 window and f1's plane in LDS

@@ -65,12 +65,10 @@ __device__ __forceinline__ void star3d_t2p_segment(
     const int r0 = ty * NY; // the lane's first lane-grid row
     const int fx0 = bxi * OX - R, fy0 = byi * OY - R;
     constexpr bool fuse = IMG; // write the output's periodic images
-    const Buf src = make_buf(in, uint64_t(padded_elems(g)) * es);
 
     auto col = [&](int xx, int yy) {
         return uint32_t(wrap_mod(xx, g.nx) + g.ox + g.sy * (wrap_mod(yy, g.ny) + g.ry)) * es;
     };
-    auto plane = [&](int zz) { return uint32_t(wrap_mod(zz, g.nz) + g.rz) * uint32_t(g.sz) * es; };
     auto pair = [](const C *p) { return *reinterpret_cast<const P *>(p); };
 
     uint32_t col_off[NY];
@@ -123,16 +121,14 @@ __device__ __forceinline__ void star3d_t2p_segment(
     for (int k = 0; k < 2 * R + PF; ++k)
 #pragma unroll
         for (int j = 0; j < NY; ++j)
-            ring[j][k] = BufLd<S>::ld(src, col_off[j], plane(zs - R + k));
+            ring[j][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs - R + k, g.nz) + g.rz), col_off[j], 0);
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
 #pragma unroll
-        for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = BufLd<S>::ld(src, hx_off[k], plane(zs + q));
+        for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hx_off[k], 0);
 #pragma unroll
-        for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = BufLd<S>::ld(src, hy_off[k], plane(zs + q));
+        for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hy_off[k], 0);
     }
-
-    const uint32_t pbytes = uint32_t(g.sz) * es;
     const bool xin = tx >= R && tx < SH::TXW - R;                 // stage B lanes
     const bool yin = r0 + 1 >= R && r0 < SH::ROWS - R;            // a stage-B row
     for (int zb = zs; zb <= ze; zb += NR) {
@@ -165,14 +161,14 @@ __device__ __forceinline__ void star3d_t2p_segment(
                 // plane zA + PF likewise; zA >= -R and a periodic axis holds
                 // at least R planes, so zA + PF + nz >= 0 (unsigned remainder)
                 const uint32_t nzu = uint32_t(g.nz), zu = uint32_t(zA + PF + g.nz);
-                const uint32_t pw = ((zu + R) % nzu + uint32_t(g.rz)) * pbytes;
-                const uint32_t ph = (zu % nzu + uint32_t(g.rz)) * pbytes;
+                const Buf bw = plane_buf(in, g.sz, int((zu + R) % nzu) + g.rz);
+                const Buf bh = plane_buf(in, g.sz, int(zu % nzu) + g.rz);
 #pragma unroll
-                for (int j = 0; j < NY; ++j) ring[j][F0(R + PF)] = BufLd<S>::ld(src, col_off[j], pw);
+                for (int j = 0; j < NY; ++j) ring[j][F0(R + PF)] = BufLd<S>::ld(bw, col_off[j], 0);
 #pragma unroll
-                for (int k = 0; k < SH::HX_PER; ++k) hxr[(q + PF) % NH][k] = BufLd<S>::ld(src, hx_off[k], ph);
+                for (int k = 0; k < SH::HX_PER; ++k) hxr[(q + PF) % NH][k] = BufLd<S>::ld(bh, hx_off[k], 0);
 #pragma unroll
-                for (int k = 0; k < SH::HY_PER; ++k) hyr[(q + PF) % NH][k] = BufLd<S>::ld(src, hy_off[k], ph);
+                for (int k = 0; k < SH::HY_PER; ++k) hyr[(q + PF) % NH][k] = BufLd<S>::ld(bh, hy_off[k], 0);
             }
 
             // stage B: f2 at plane zB from the f1 ring and f1's plane in LDS

@@ -13,6 +13,9 @@ the long-run anchor of the precision study, through the C ABI.
   oracle at steps 1, 10, 100 and 1000, every point; the FP32/BF16 storage
   policies' error per field against the same oracle states (Sec. 5.1: the
   paper verifies on separate small runs).
+* Arrays of 4 GiB or more: the default star plan at 1024 x 1024 x 520 FP64
+  against the oracle at sampled points; RK plans of that size are refused at
+  plan time.
 
 FP64 bar: normwise max relative error <= 1e-12 per field. FP32 star: the
 rounding bound of four chained FP32 iterations (derived below); the measured
@@ -219,3 +222,51 @@ def test_mhd_1000_steps_32_cubed_against_oracle(model):
     assert max(table["f32_master64"][1000]) <= 2e-5
     assert max(table["bf16_master64"][1000]) <= 1e-1
     assert max(table["bf16_master64"][1000]) < max(table["bf16_only"][1000])
+
+
+# ---------------------------------------------------------------------------
+# arrays of 4 GiB or more
+# ---------------------------------------------------------------------------
+
+def test_star_beyond_4_gib_default_plan_sampled_points():
+    # 1024 x 1024 x 520 FP64: 4.46 GB per padded buffer. The default plan
+    # (two-iteration launches) reads its input plane by plane, so 32-bit
+    # offsets never span the array; four iterations against the oracle's
+    # fourth iterate at sampled points (and every point of the output halo
+    # against the periodic image of its interior)
+    dims, r, iters = (1024, 1024, 520), 3, 4
+    s = W.diffusion_number(1024)
+    g_ref = diffusion_star_exact(3, r, s)
+    plan = S.LinearPlan(dims, r, W.diffusion_star(3, r, s))
+    assert plan.iterations_per_launch == 2 and plan.launches(iters) == (2, 0)
+    assert S.padded_elems(dims, r) * 8 >= 1 << 32
+    pad = O.pad_periodic(inputs.uniform_field(dims, 3), r)
+    a = plan.empty(0.0)
+    a.copy_(torch.from_numpy(pad))
+    b = plan.empty(0.0)
+    res = plan.apply(a, b, iters)
+    got = host(res)
+    del a, b, res
+    torch.cuda.empty_cache()
+    cur = O.xcorr_periodic_iterate(pad, r, g_ref, iters - 1)
+    del pad
+    rng = np.random.default_rng(5)
+    pts = np.stack([rng.integers(0, d, 3000) for d in dims], axis=1)
+    corners = np.array([[x, y, z] for x in (0, dims[0] - 1) for y in (0, dims[1] - 1)
+                        for z in (0, dims[2] - 1)])
+    pts = np.concatenate([pts, corners, [[0, 0, 260], [1023, 511, 519]]])
+    ref = O.xcorr_at(cur, r, g_ref, pts)
+    del cur
+    vals = got[pts[:, 2] + r, pts[:, 1] + r, pts[:, 0] + r]
+    assert relerr(vals, ref) <= 1e-12
+    assert np.array_equal(got[:r], got[dims[2]:dims[2] + r])
+    assert np.array_equal(got[-r:], got[r:2 * r])
+    assert np.array_equal(got[:, :, :r], got[:, :, dims[0]:dims[0] + r])
+
+
+def test_rk_plans_beyond_4_gib_are_refused_at_plan_time():
+    with pytest.raises(S.StencilError) as e:
+        S.RkPlan(S.MODEL_MHD8, (1024, 1024, 520), S.PREC_F64)
+    assert e.value.code == -3
+    with pytest.raises(S.StencilError):
+        S.RkPlan(S.MODEL_ADVDIFF, (1024, 1024, 520), S.PREC_F32_MASTER64)

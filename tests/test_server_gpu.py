@@ -247,3 +247,31 @@ def test_zmarch_job_matches_oracle():
     ref = O.rk3_steps(O.MODEL_ADVDIFF, [O.pad_periodic(make_init(dims, seed), 3)], ds,
                       job_dt(dims, c), steps, nu=nu, c=c)[0]
     assert relerr(out[0], O.interior(ref, 3)) <= 1e-12
+
+
+def test_tuned_batch_schedules_change_no_bit(tmp_path, monkeypatch):
+    # the server's per-class schedule search (z-march depth, per-point tile
+    # shape) picks among launches that compute the same arithmetic per point:
+    # every job's result is bitwise that of the fixed schedule and of the solo
+    # path, and each class is searched once
+    cache = tmp_path / "batch_tune.txt"
+    monkeypatch.setenv("STENCIL_TUNE_CACHE", str(cache))
+    jobs = BIG + JOBS
+    fixed, _ = run_server(jobs, tick_steps=2, max_slots=16)
+    tuned, stats = run_server(jobs, tick_steps=2, max_slots=16, tune=True)
+    assert stats["completed"] == len(jobs) and stats["failed"] == 0
+    assert stats["tuned_classes"] == len(jobs)  # every job here is its own class
+    for k, job in enumerate(jobs):
+        assert np.array_equal(tuned[k], fixed[k]), k
+        assert np.array_equal(tuned[k], solo_path(*job)), k
+    lines = [l for l in cache.read_text().splitlines() if l.startswith("batch|")]
+    assert len(lines) == len(jobs)
+    for l in lines:
+        a, b = (int(v) for v in l.split()[1:])
+        assert (a in (8, 16, 32, 64) and b == 0) or (a, b) in ((64, 4), (128, 2), (256, 1),
+                                                                (32, 8)), l
+    # a second server reads the choices back: no new search
+    again, stats2 = run_server(jobs[:2], tick_steps=2, max_slots=16, tune=True)
+    assert stats2["tuned_classes"] == 0
+    for k in range(2):
+        assert np.array_equal(again[k], fixed[k])
