@@ -410,6 +410,18 @@ stencil_status stencil_rk_run(stencil_plan_t plan, const stencil_fields *fields,
 stencil_status stencil_reduce(stencil_plan_t plan, const void *const *fields, int nfields,
                               int dtype, double *host_out, void *stream);
 
+/* stencil_reduce for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and partition, so the same results bit for bit, with the
+ * partials in a fixed device array of the library (386 KiB per GPU, held until
+ * the process ends) instead of memory allocated per call. Arguments, layout
+ * and ownership as stencil_reduce; nfields <= 64 (more: STENCIL_EINVAL).
+ * Every call on one GPU shares that array: calls that overlap in time on one
+ * GPU (several host threads or streams) race and must be serialised by the
+ * caller. Synchronises the stream. */
+stencil_status stencil_reduce_noalloc(stencil_plan_t plan, const void *const *fields,
+                                      int nfields, int dtype, double *host_out, void *stream);
+
 /* Kinetic and magnetic energy of an MHD plan's state (MHD8 or MHD_FULL; the
  * fields of Eq. A1-A4 in Table A1 order): host_out[0] = 1/2 sum |u|^2 and
  * host_out[1] = 1/2 sum |B|^2 over the interior grid points, B = curl A by the

@@ -314,6 +314,8 @@ def _declare_rk(L):
     L.stencil_rk_run.argtypes = [_vp, ctypes.POINTER(_Fields), c_int, ctypes.c_double, _vp]
     L.stencil_reduce.argtypes = [_vp, ctypes.POINTER(_vp), c_int, c_int,
                                  ctypes.POINTER(ctypes.c_double), _vp]
+    L.stencil_reduce_noalloc.argtypes = [_vp, ctypes.POINTER(_vp), c_int, c_int,
+                                         ctypes.POINTER(ctypes.c_double), _vp]
     L.stencil_energy.argtypes = [_vp, ctypes.POINTER(_vp), c_int,
                                  ctypes.POINTER(ctypes.c_double), _vp]
 
@@ -435,6 +437,16 @@ class RkPlan:
         ptrs = (_vp * len(fields))(*[t.data_ptr() for t in fields])
         out = (ctypes.c_double * (3 * len(fields)))()
         check(lib().stencil_reduce(self._h, ptrs, len(fields), dtype, out, stream_ptr(stream)))
+        return np.array(out[:]).reshape(len(fields), 3)
+
+    def reduce_noalloc(self, fields, dtype=None, stream=None):
+        """reduce() without device allocation (the library's fixed scratch
+        array; calls overlapping on one GPU race)."""
+        dtype = self.dtype if dtype is None else dtype
+        ptrs = (_vp * len(fields))(*[t.data_ptr() for t in fields])
+        out = (ctypes.c_double * (3 * len(fields)))()
+        check(lib().stencil_reduce_noalloc(self._h, ptrs, len(fields), dtype, out,
+                                           stream_ptr(stream)))
         return np.array(out[:]).reshape(len(fields), 3)
 
     def energy(self, fields, dtype=None, stream=None):
