@@ -72,6 +72,9 @@ def parse():
                     help="jobs of the trace replayed at the sustainable rates")
     ap.add_argument("--detail-out", default=None,
                     help="also write the full record (JSON) to this file")
+    ap.add_argument("--only", default=None,
+                    help="comma list of secondary sections to run (stars, lines, filters, mhd, "
+                         "precision, serving); default: all")
     return ap.parse_args()
 
 
@@ -230,141 +233,179 @@ def secondary(torch, S, W, inputs, args):
     the result line, detail to stderr and --detail-out."""
     comp, det = {}, {}
     n, r = args.n, args.radius
-    progress("FP32 star")
-    # FP32 storage of the same star workload, and its error against FP64
-    p32, _, tot, per, nl = star_run(torch, S, W, inputs, n, r, S.F32, 100, 4)
-    ipl = p32.iterations_per_launch if nl[1] == 0 else 1
-    det["star_%d_f32" % n] = {"updates_per_s": n ** 3 / (tot / 100 * 1e-3),
-                              "ms_per_iteration": tot / 100, "iterations_per_launch": ipl,
-                              "hbm_frac": ipl * 8 * n ** 3 / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                              "avg_launch_ms": per, "tile": list(p32.tile),
-                              "layout": [p32.row_pitch, p32.x_offset]}
-    del p32
-    err32 = star_f32_error(torch, S, W, inputs, n, r)
-    d = det["star_%d_f32" % n]
-    d["rel_err_vs_f64_100_iterations"] = err32
-    comp["c1_star512_f32"] = {"ups": d["updates_per_s"], "ms_it": d["ms_per_iteration"],
-                              "frac": d["hbm_frac"], "err_vs_f64_100it": err32}
-    progress("radius-4 star")
-    # the secondary star of the same workload: 25 points, radius 4, FP64
-    p4, _, tot, per, nl = star_run(torch, S, W, inputs, n, 4, S.F64, 100, 4)
-    ipl = p4.iterations_per_launch if nl[1] == 0 else 1
-    d = det["star_%d_f64_r4" % n] = {
-        "updates_per_s": n ** 3 / (tot / 100 * 1e-3), "ms_per_iteration": tot / 100,
-        "iterations_per_launch": ipl,
-        "hbm_frac": ipl * 16 * n ** 3 / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "avg_launch_ms": per, "tile": list(p4.tile)}
-    comp["c1_star512_f64_r4"] = {"ups": d["updates_per_s"], "ms_it": d["ms_per_iteration"],
-                                 "frac": d["hbm_frac"]}
-    del p4
-    progress("1-D lines")
-    # 1-D radius-1 smoother at 2^28 points (2 GiB per buffer): 10 chained
-    # iterations per call, autotuned plan (temporal blocking allowed)
-    N = 1 << 28
-    pl = S.LinearPlan((N,), 1, W.smoother3(), autotune=True)
-    a = pl.empty(0.0)
-    a[1:N + 1] = torch.from_numpy(inputs.uniform_field((N,), 1)).cuda()
-    b = pl.empty(0.0)
-    ms = timed(torch, lambda: pl.apply(a, b, 10), 3, warm=1)
-    det["line_2^28_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
-                                   "algorithmic_frac": 16 * N * 10 / (ms * 1e-3) / 1e9 /
-                                   HBM_PEAK_GBS,
-                                   "iterations_per_launch": pl.iterations_per_launch,
-                                   "variant": pl.variant, "tile": list(pl.tile)}
-    del a, b, pl
-    # 1-D radius-1 smoother, 2^20 points, 10 chained iterations per call
-    N = 1 << 20
-    p1 = S.LinearPlan((N,), 1, W.smoother3(), autotune=True)
-    a = p1.empty(0.0)
-    a[1:N + 1] = torch.from_numpy(inputs.uniform_field((N,), 1)).cuda()
-    b = p1.empty(0.0)
-    ms = timed(torch, lambda: p1.apply(a, b, 10), 50)
-    d = det["line_2^20_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
-                                       "us_per_iteration": ms * 100.0,
-                                       "variant": p1.variant, "tile": list(p1.tile)}
-    comp["c0_line2^20_f64_10it"] = {"ups": d["updates_per_s"], "us_it": d["us_per_iteration"]}
-    del a, b
-    progress("radius sweep, filters")
-    det["line_radius_sweep_2^24_f64"] = radius_sweep(torch, S, inputs)
-    det["filters_512_f64"] = filters(torch, S, inputs, args.n)
-    progress("fused 8-field steps")
-    # fused 8-field RK3 step, 256^3
-    nm = 256
-    f, _ = inputs.fourier_fields((nm, nm, nm), 1, nf=8, modes=8, kmax=8, amp=0.01)
-    ds = 2 * math.pi / nm
-    dt = 0.1 * ds
-    bytes_step = {S.PREC_F64: 640, S.PREC_F32_MASTER64: 480, S.PREC_BF16_MASTER64: 384}
-    for model, mname, prec, name in (
-            (S.MODEL_MHD8, "mhd8", S.PREC_F64, "f64"),
-            (S.MODEL_MHD8, "mhd8", S.PREC_F32_MASTER64, "f32_master64"),
-            (S.MODEL_MHD8, "mhd8", S.PREC_BF16_MASTER64, "bf16_master64"),
-            (S.MODEL_MHD_FULL, "mhd_full", S.PREC_F64, "f64"),
-            (S.MODEL_MHD_FULL, "mhd_full", S.PREC_F32_MASTER64, "f32_master64"),
-            # 12-tap diagonal mixed derivatives instead of the tensor product
-            (S.MODEL_MHD8, "mhd8_diag", S.PREC_F64, "f64"),
-            (S.MODEL_MHD_FULL, "mhd_full_diag", S.PREC_F64, "f64")):
-        plan = S.RkPlan(model, (nm, nm, nm), prec,
-                        mhd=FULL_MHD if model == S.MODEL_MHD_FULL else None,
-                        mixed=S.MIXED_DIAGONAL if mname.endswith("_diag") else S.MIXED_TENSOR)
-        bufs = plan.alloc()
-        for k in range(8):
-            bufs["f_a"][k][3:nm + 3, 3:nm + 3, 3:nm + 3] = torch.from_numpy(f[k]).cuda().to(
-                bufs["f_a"][k].dtype)
-            if plan.master:
-                bufs["f64"][k][3:nm + 3, 3:nm + 3, 3:nm + 3] = torch.from_numpy(f[k]).cuda()
-        steps = 5
-        ms = timed(torch, lambda: plan.run(bufs["f_a"], bufs["f_b"], bufs["w"], steps, dt,
-                                           w2=bufs["w2"], f64=bufs["f64"]), 2, warm=1) / steps
-        pts = nm ** 3
-        flops = mhd_flops(model == S.MODEL_MHD_FULL, mname.endswith("_diag"))
-        peak = VALU_PEAK_TFLOPS["f64" if prec == S.PREC_F64 else "f32"]
-        d = det["%s_%d_%s" % (mname, nm, name)] = {
-            "point_steps_per_s": pts / (ms * 1e-3),
-            "point_substeps_per_s": 3 * pts / (ms * 1e-3),
-            "ms_per_step": ms,
-            "hbm_frac": bytes_step[prec] * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "valu_roof": {"flops_per_point_substep": flops, "peak_tflops": peak,
-                          "frac": 3 * pts / (ms * 1e-3) * flops / (peak * 1e12)}}
-        key = ("c2_" if prec == S.PREC_F64 else "c3_") + "%s_256_%s" % (mname, name)
-        comp[key] = {"ms_step": ms, "pt_steps_s": d["point_steps_per_s"],
-                     "hbm_frac": d["hbm_frac"], "valu_frac": d["valu_roof"]["frac"]}
-        del bufs, plan
-    del f
-    torch.cuda.empty_cache()
-    if not args.no_precision_error:
-        for model, mname in ((S.MODEL_MHD8, "mhd8"), (S.MODEL_MHD_FULL, "mhd_full")):
-            progress("precision study %s" % mname)
-            res = mixed_precision_error(torch, S, inputs, n=args.precision_n, model=model,
-                                        mhd=FULL_MHD if model == S.MODEL_MHD_FULL else None)
-            det["%s_mixed_precision_error_%d" % (mname, args.precision_n)] = res
-            comp["c3_err_%s_%d" % (mname, args.precision_n)] = {
-                "steps": res["steps"],
-                **{k: [max(res[k][str(cp)]) for cp in res["steps"]]
-                   for k in ("f32_master64", "bf16_master64", "f32_only", "bf16_only")}}
-    if args.serve_jobs > 0:
-        rates = tuple(float(v) for v in args.serve_rates.split(",") if v)
-        progress("serving trace (%d jobs)" % args.serve_jobs)
-        sv = serving(torch, args.serve_jobs, rates=rates, sweep_jobs=args.serve_sweep_jobs)
-        det["serving"] = sv
-        keep = ("p50_s", "p99_s", "point_steps_per_s")
-        comp["c4_serving"] = {
-            "jobs": args.serve_jobs, "rate_per_s": 200,
-            "served": {k: sv["served"][k] for k in keep},
-            "fifo_f64": {k: sv["fifo_f64"][k] for k in keep},
-            "served_by_dtype": sv["served"]["by_dtype"],
-            "fifo_by_dtype": sv["fifo_f64"]["by_dtype"],
-            "speedup": sv["speedup_point_steps_per_s"],
-            "p99_ratio_fifo_over_served": sv["p99_ratio_fifo_over_served"],
-            "err_vs_f64": sv["error_vs_fp64"],
-            "sweep_p99_served_vs_fifo": {k: [v["served"]["p99_s"], v["fifo_f64"]["p99_s"]]
-                                         for k, v in sv["rate_sweep"].items()}}
+    only = set(args.only.split(",")) if args.only else None
+    want = lambda k: only is None or k in only  # noqa: E731
+    if want("stars"):
+        progress("FP32 star")
+        # FP32 storage of the same star workload, and its error against FP64
+        p32, _, tot, per, nl = star_run(torch, S, W, inputs, n, r, S.F32, 100, 4)
+        ipl = p32.iterations_per_launch if nl[1] == 0 else 1
+        det["star_%d_f32" % n] = {"updates_per_s": n ** 3 / (tot / 100 * 1e-3),
+                                  "ms_per_iteration": tot / 100, "iterations_per_launch": ipl,
+                                  "hbm_frac": ipl * 8 * n ** 3 / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                  "avg_launch_ms": per, "tile": list(p32.tile),
+                                  "layout": [p32.row_pitch, p32.x_offset]}
+        del p32
+        err32 = star_f32_error(torch, S, W, inputs, n, r)
+        d = det["star_%d_f32" % n]
+        d["rel_err_vs_f64_100_iterations"] = err32
+        comp["c1_star512_f32"] = {"ups": d["updates_per_s"], "ms_it": d["ms_per_iteration"],
+                                  "frac": d["hbm_frac"], "err_vs_f64_100it": err32}
+        progress("radius-4 star")
+        # the secondary star of the same workload: 25 points, radius 4, FP64
+        p4, _, tot, per, nl = star_run(torch, S, W, inputs, n, 4, S.F64, 100, 4)
+        ipl = p4.iterations_per_launch if nl[1] == 0 else 1
+        d = det["star_%d_f64_r4" % n] = {
+            "updates_per_s": n ** 3 / (tot / 100 * 1e-3), "ms_per_iteration": tot / 100,
+            "iterations_per_launch": ipl,
+            "hbm_frac": ipl * 16 * n ** 3 / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "avg_launch_ms": per, "tile": list(p4.tile)}
+        comp["c1_star512_f64_r4"] = {"ups": d["updates_per_s"], "ms_it": d["ms_per_iteration"],
+                                     "frac": d["hbm_frac"]}
+        del p4
+    if want("lines"):
+        progress("1-D lines")
+        # 1-D radius-1 smoother at 2^28 points (2 GiB per buffer): 10 chained
+        # iterations per call, autotuned plan (temporal blocking allowed)
+        N = 1 << 28
+        pl = S.LinearPlan((N,), 1, W.smoother3(), autotune=True)
+        a = pl.empty(0.0)
+        a[1:N + 1] = torch.from_numpy(inputs.uniform_field((N,), 1)).cuda()
+        b = pl.empty(0.0)
+        ms = timed(torch, lambda: pl.apply(a, b, 10), 3, warm=1)
+        det["line_2^28_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
+                                       "algorithmic_frac": 16 * N * 10 / (ms * 1e-3) / 1e9 /
+                                       HBM_PEAK_GBS,
+                                       "iterations_per_launch": pl.iterations_per_launch,
+                                       "variant": pl.variant, "tile": list(pl.tile)}
+        del a, b, pl
+        # 1-D radius-1 smoother, 2^20 points, 10 chained iterations per call
+        N = 1 << 20
+        p1 = S.LinearPlan((N,), 1, W.smoother3(), autotune=True)
+        a = p1.empty(0.0)
+        a[1:N + 1] = torch.from_numpy(inputs.uniform_field((N,), 1)).cuda()
+        b = p1.empty(0.0)
+        ms = timed(torch, lambda: p1.apply(a, b, 10), 50)
+        d = det["line_2^20_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
+                                           "us_per_iteration": ms * 100.0,
+                                           "variant": p1.variant, "tile": list(p1.tile)}
+        comp["c0_line2^20_f64_10it"] = {"ups": d["updates_per_s"], "us_it": d["us_per_iteration"]}
+        del a, b
+    if want("lines"):
+        progress("radius sweep")
+        det["line_radius_sweep_2^24_f64"] = radius_sweep(torch, S, inputs)
+    if want("filters"):
+        progress("filters")
+        det["filters_512_f64"] = filters(torch, S, inputs, args.n)
+        f = det["filters_512_f64"]
+        comp["f4_filters_512_f64"] = {"max_ms": f["max_3x3x3"]["ms_per_launch"],
+                                      "median_ms": f["median_3x3x3"]["ms_per_launch"]}
+    if want("mhd"):
+        progress("fused 8-field steps")
+        # fused 8-field RK3 step, 256^3
+        nm = 256
+        f, _ = inputs.fourier_fields((nm, nm, nm), 1, nf=8, modes=8, kmax=8, amp=0.01)
+        ds = 2 * math.pi / nm
+        dt = 0.1 * ds
+        bytes_step = {S.PREC_F64: 640, S.PREC_F32_MASTER64: 480, S.PREC_BF16_MASTER64: 384}
+        for model, mname, prec, name in (
+                (S.MODEL_MHD8, "mhd8", S.PREC_F64, "f64"),
+                (S.MODEL_MHD8, "mhd8", S.PREC_F32_MASTER64, "f32_master64"),
+                (S.MODEL_MHD8, "mhd8", S.PREC_BF16_MASTER64, "bf16_master64"),
+                (S.MODEL_MHD_FULL, "mhd_full", S.PREC_F64, "f64"),
+                (S.MODEL_MHD_FULL, "mhd_full", S.PREC_F32_MASTER64, "f32_master64"),
+                # 12-tap diagonal mixed derivatives instead of the tensor product
+                (S.MODEL_MHD8, "mhd8_diag", S.PREC_F64, "f64"),
+                (S.MODEL_MHD_FULL, "mhd_full_diag", S.PREC_F64, "f64")):
+            plan = S.RkPlan(model, (nm, nm, nm), prec,
+                            mhd=FULL_MHD if model == S.MODEL_MHD_FULL else None,
+                            mixed=S.MIXED_DIAGONAL if mname.endswith("_diag") else S.MIXED_TENSOR)
+            bufs = plan.alloc()
+            for k in range(8):
+                bufs["f_a"][k][3:nm + 3, 3:nm + 3, 3:nm + 3] = torch.from_numpy(f[k]).cuda().to(
+                    bufs["f_a"][k].dtype)
+                if plan.master:
+                    bufs["f64"][k][3:nm + 3, 3:nm + 3, 3:nm + 3] = torch.from_numpy(f[k]).cuda()
+            steps = 5
+            ms = timed(torch, lambda: plan.run(bufs["f_a"], bufs["f_b"], bufs["w"], steps, dt,
+                                               w2=bufs["w2"], f64=bufs["f64"]), 2, warm=1) / steps
+            pts = nm ** 3
+            flops = mhd_flops(model == S.MODEL_MHD_FULL, mname.endswith("_diag"))
+            peak = VALU_PEAK_TFLOPS["f64" if prec == S.PREC_F64 else "f32"]
+            d = det["%s_%d_%s" % (mname, nm, name)] = {
+                "point_steps_per_s": pts / (ms * 1e-3),
+                "point_substeps_per_s": 3 * pts / (ms * 1e-3),
+                "ms_per_step": ms,
+                "hbm_frac": bytes_step[prec] * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "valu_roof": {"flops_per_point_substep": flops, "peak_tflops": peak,
+                              "frac": 3 * pts / (ms * 1e-3) * flops / (peak * 1e12)}}
+            key = ("c2_" if prec == S.PREC_F64 else "c3_") + "%s_256_%s" % (mname, name)
+            comp[key] = {"ms_step": ms, "pt_steps_s": d["point_steps_per_s"],
+                         "hbm_frac": d["hbm_frac"], "valu_frac": d["valu_roof"]["frac"]}
+            if mname in ("mhd8", "mhd_full") and prec in (S.PREC_F64, S.PREC_F32_MASTER64):
+                # the same step with the plan-time schedule search
+                tp = S.RkPlan(model, (nm, nm, nm), prec,
+                              mhd=FULL_MHD if model == S.MODEL_MHD_FULL else None, autotune=True)
+                tms = timed(torch, lambda: tp.run(bufs["f_a"], bufs["f_b"], bufs["w"], steps, dt,
+                                                  w2=bufs["w2"], f64=bufs["f64"]), 2, warm=1) / steps
+                d["autotuned"] = {"ms_per_step": tms, "schedule": list(tp.schedule),
+                                  "default_schedule": list(plan.schedule)}
+                comp[key]["tuned_ms"] = tms
+                comp[key]["tuned_sched"] = list(tp.schedule)
+                del tp
+            if mname == "mhd8" and prec == S.PREC_F64:
+                # FP64 diagnostics of the 8 fields (a7): sums, sums of squares,
+                # maxima; one read of each field (8 B per point and field)
+                state = bufs["f_a"]
+                rms = timed(torch, lambda: plan.reduce(state), 5, warm=1)
+                nms = timed(torch, lambda: plan.reduce_noalloc(state), 5, warm=1)
+                gb = 8 * 8 * pts / 1e9
+                det["reduce_256_f64_8fields"] = {"ms": rms, "noalloc_ms": nms,
+                                                 "hbm_frac": gb / (rms * 1e-3) / HBM_PEAK_GBS,
+                                                 "noalloc_hbm_frac":
+                                                     gb / (nms * 1e-3) / HBM_PEAK_GBS}
+                comp["a7_reduce_256_f64_8f"] = {"ms": rms, "noalloc_ms": nms,
+                                                "hbm_frac": gb / (rms * 1e-3) / HBM_PEAK_GBS}
+            del bufs, plan
+        del f
+        torch.cuda.empty_cache()
+    if want("precision"):
+        if not args.no_precision_error:
+            for model, mname in ((S.MODEL_MHD8, "mhd8"), (S.MODEL_MHD_FULL, "mhd_full")):
+                progress("precision study %s" % mname)
+                res = mixed_precision_error(torch, S, inputs, n=args.precision_n, model=model,
+                                            mhd=FULL_MHD if model == S.MODEL_MHD_FULL else None)
+                det["%s_mixed_precision_error_%d" % (mname, args.precision_n)] = res
+                comp["c3_err_%s_%d" % (mname, args.precision_n)] = {
+                    "steps": res["steps"],
+                    **{k: [max(res[k][str(cp)]) for cp in res["steps"]]
+                       for k in ("f32_master64", "bf16_master64", "f32_only", "bf16_only")}}
+    if want("serving"):
+        if args.serve_jobs > 0:
+            rates = tuple(float(v) for v in args.serve_rates.split(",") if v)
+            progress("serving trace (%d jobs)" % args.serve_jobs)
+            sv = serving(torch, args.serve_jobs, rates=rates, sweep_jobs=args.serve_sweep_jobs)
+            det["serving"] = sv
+            keep = ("p50_s", "p99_s", "point_steps_per_s")
+            comp["c4_serving"] = {
+                "jobs": args.serve_jobs, "rate_per_s": 200,
+                "served": {k: sv["served"][k] for k in keep},
+                "fifo_f64": {k: sv["fifo_f64"][k] for k in keep},
+                "served_by_dtype": sv["served"]["by_dtype"],
+                "fifo_by_dtype": sv["fifo_f64"]["by_dtype"],
+                "served_tuned": {k: sv["served_tuned"][k] for k in keep},
+                "speedup": sv["speedup_point_steps_per_s"],
+                "p99_ratio_fifo_over_served": sv["p99_ratio_fifo_over_served"],
+                "err_vs_f64": sv["error_vs_fp64"],
+                "sweep_p99_served_vs_fifo": {k: [v["served"]["p99_s"], v["fifo_f64"]["p99_s"]]
+                                             for k, v in sv["rate_sweep"].items()}}
     return comp, det
 
 
 def filters(torch, S, inputs, n):
     """Window filters on the n^3 FP64 field: 3x3x3 max (z-march kernel) and
-    3x3x3 median (gather kernel, rank selection among 27 keys), one periodic
-    application per launch; 16 B per point (read once, write once)."""
+    3x3x3 median (gather kernel, forgetful selection among 27 keys), one
+    periodic application per launch; 16 B per point (read once, write once)."""
     import numpy as np
     dims, r = (n, n, n), 1
     out = {}
@@ -481,6 +522,8 @@ def serving(torch, count, seed=1, rates=(10.0, 25.0, 50.0), sweep_jobs=48):
     (arrival times stretched by 200/rate) for latencies under a load the GPU
     can sustain. The server runs its default policy (oldest first); the
     shortest-remaining-work policy is timed beside it."""
+    import numpy as np
+
     import paper_2406_08923_amd as S_
     from paper_2406_08923_amd import inputs, serving as SV
     jobs = inputs.serving_trace(seed, count)
@@ -492,8 +535,12 @@ def serving(torch, count, seed=1, rates=(10.0, 25.0, 50.0), sweep_jobs=48):
     fifo, res_f = SV.run_fifo_f64(jobs, inits)
     progress("serving: FIFO run %.1f s" % fifo["makespan_s"])
     err = SV.compare(jobs, res_s, res_f)
-    del res_s, res_f
+    del res_f
     torch.cuda.synchronize()
+    tuned, res_t = SV.run_served(jobs, inits, tune=True)
+    tuned_bitwise = all(np.array_equal(a, b) for a, b in zip(res_t, res_s)) if res_s else None
+    del res_t, res_s
+    progress("serving: served with batch-schedule search %.1f s" % tuned["makespan_s"])
     shortest, _ = SV.run_served(jobs, inits, policy=S_.SERVE_SHORTEST)
     keep = ("p50_s", "p99_s", "makespan_s", "point_steps_per_s")
     sweep = {}
@@ -518,6 +565,9 @@ def serving(torch, count, seed=1, rates=(10.0, 25.0, 50.0), sweep_jobs=48):
             "policy": "oldest submission first, shorter jobs filling up to a quarter more",
             "served": served, "fifo_f64": fifo, "error_vs_fp64": err,
             "served_shortest_first": {k: shortest[k] for k in keep},
+            "served_tuned": dict({k: tuned[k] for k in keep},
+                                 tuned_classes=tuned["tuned_classes"],
+                                 bitwise_equal_to_untuned=tuned_bitwise),
             "speedup_point_steps_per_s": served["point_steps_per_s"] / fifo["point_steps_per_s"],
             "p99_ratio_fifo_over_served": fifo["p99_s"] / served["p99_s"],
             "rate_sweep": sweep}

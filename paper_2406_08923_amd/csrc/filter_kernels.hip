@@ -130,6 +130,67 @@ __global__ void __launch_bounds__(256)
     store_periodic(out, g, x, y, z, v, fuse != 0);
 }
 
+// Median of an odd number M of window values by forgetful selection: a
+// working set of K + 2 keys (K = (M - 1) / 2) is kept in registers; each
+// round moves the set's minimum and maximum to its two ends with
+// compare-exchanges, drops both and takes in the next window value, until
+// three keys remain, whose middle one is the median (the schedule is checked
+// against sorting on the CPU, with ties, for every M the kernel is built
+// for). The median key is unique as a value, so the result is bitwise that of
+// the rank count above, with about M^2 / 4 instead of M^2 comparisons. All
+// indices are compile-time constants (full unrolling), so the keys stay in
+// registers.
+template <typename U>
+__device__ __forceinline__ void cmpx(U &lo, U &hi)
+{
+    const U a = lo, b = hi;
+    lo = a < b ? a : b;
+    hi = a < b ? b : a;
+}
+
+template <typename S, int M>
+__global__ void __launch_bounds__(256)
+    k_filter_median_fs(const S *__restrict__ in, S *__restrict__ out, Geo g,
+                       const int *__restrict__ offs, int fuse)
+{
+    static_assert(M % 2 == 1 && M >= 3, "odd window sizes only");
+    using C = typename Store<S>::C;
+    using U = typename Key<C>::U;
+    constexpr int K = (M - 1) / 2, S0 = K + 2;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny)
+        return;
+    const int64_t p = g.at(x, y, z);
+    U k[M];
+    bool nan = false;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        const C v = Store<S>::ld(in + p + offs[t]);
+        nan = nan || (v != v);
+        k[t] = Key<C>::of(v);
+    }
+    // round r: working set k[r .. S0 - 1]; its minimum goes to k[r] (dropped
+    // by advancing r), its maximum to k[S0 - 1], which the next window value
+    // then replaces
+#pragma unroll
+    for (int r = 0; r < M - S0; ++r) {
+#pragma unroll
+        for (int i = r + 1; i < S0; ++i) cmpx(k[r], k[i]);
+#pragma unroll
+        for (int i = r + 1; i < S0 - 1; ++i) cmpx(k[i], k[S0 - 1]);
+        k[S0 - 1] = k[S0 + r];
+    }
+    // three keys left: k[K - 1], k[K], k[K + 1]; their middle one
+    U a = k[K - 1], b = k[K], c = k[K + 1];
+    cmpx(a, b);         // a <= b
+    cmpx(b, c);         // c = max of the three, b = max(min(b, c), a) candidate
+    const U med = a > b ? a : b;
+    const C v = nan ? C(__builtin_nan("")) : Key<C>::val(med);
+    store_periodic(out, g, x, y, z, v, fuse != 0);
+}
+
 // 3-D box window (all (2R+1)^3 offsets), max or min: a z march. The workgroup
 // (64 x TY lanes) stages each plane of its tile plus an R-wide halo (corners
 // included) as keys in LDS, reduces the (2R+1)^2 square around each lane's
@@ -229,8 +290,20 @@ int launch_filter_gather(const S *in, S *out, const Geo &g, const int *offs, int
     case FILTER_OP_MEDIAN:
         if (ntaps > FILTER_MEDIAN_MAX)
             return fail(STENCIL_EUNSUPPORTED, "median of %d > %d values", ntaps, FILTER_MEDIAN_MAX);
-        hipLaunchKernelGGL(k_filter_median<S>, grid, block, 0, s, in, out, g, offs, ntaps,
-                           fuse ? 1 : 0);
+        // forgetful selection for the common odd windows (3-D and 2-D 3x3
+        // boxes, the radius-1 3-D star), rank counting otherwise
+        if (ntaps == 27)
+            hipLaunchKernelGGL((k_filter_median_fs<S, 27>), grid, block, 0, s, in, out, g, offs,
+                               fuse ? 1 : 0);
+        else if (ntaps == 9)
+            hipLaunchKernelGGL((k_filter_median_fs<S, 9>), grid, block, 0, s, in, out, g, offs,
+                               fuse ? 1 : 0);
+        else if (ntaps == 7)
+            hipLaunchKernelGGL((k_filter_median_fs<S, 7>), grid, block, 0, s, in, out, g, offs,
+                               fuse ? 1 : 0);
+        else
+            hipLaunchKernelGGL(k_filter_median<S>, grid, block, 0, s, in, out, g, offs, ntaps,
+                               fuse ? 1 : 0);
         break;
     default: return fail(STENCIL_EINVAL, "unknown filter op %d", op);
     }

@@ -54,9 +54,9 @@ def _by_dtype(jobs, lat, makespan):
 
 
 def run_served(jobs, inits, tick_steps=16, max_slots=512, use_graph=True, min_points=0,
-               policy=SERVE_OLDEST):
+               policy=SERVE_OLDEST, tune=False):
     srv = Server(max_slots=max_slots, tick_steps=tick_steps, use_graph=use_graph,
-                 min_points=min_points, policy=policy)
+                 min_points=min_points, policy=policy, tune=tune)
     tickets = [None] * len(jobs)
     start = srv.clock()
 
@@ -88,7 +88,8 @@ def run_served(jobs, inits, tick_steps=16, max_slots=512, use_graph=True, min_po
     out.update({"makespan_s": makespan, "point_steps": stats["point_steps"],
                 "point_steps_per_s": stats["point_steps"] / makespan,
                 "ticks": stats["ticks"], "launches": stats["launches"],
-                "busy_s": stats["busy_s"], "by_dtype": _by_dtype(jobs, lat, makespan)})
+                "busy_s": stats["busy_s"], "tuned_classes": stats["tuned_classes"],
+                "by_dtype": _by_dtype(jobs, lat, makespan)})
     return out, results
 
 

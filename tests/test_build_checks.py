@@ -139,3 +139,45 @@ def test_ring_schedule_model_catches_a_wrong_prefetch_depth():
     # PF + 1 not dividing the ring length breaks the compile-time slots: the
     # model must see it (pin of the model itself)
     assert replay_ring_march(3, 3, 0, 40) != []
+
+
+# ---------------------------------------------------------------------------
+# forgetful-selection schedule of the median filter
+# ---------------------------------------------------------------------------
+
+def forgetful_median(vals):
+    """The median kernel's compare-exchange schedule for an odd window of M
+    values, replayed on a list: working set vals[r .. K + 1] at round r."""
+    k = list(vals)
+    M = len(k)
+    K = (M - 1) // 2
+    S0 = K + 2
+
+    def cmpx(i, j):
+        if k[j] < k[i]:
+            k[i], k[j] = k[j], k[i]
+
+    for r in range(M - S0):
+        for i in range(r + 1, S0):
+            cmpx(r, i)
+        for i in range(r + 1, S0 - 1):
+            cmpx(i, S0 - 1)
+        k[S0 - 1] = k[S0 + r]
+    a, b, c = k[K - 1], k[K], k[K + 1]
+    a, b = min(a, b), max(a, b)
+    b, c = min(b, c), max(b, c)
+    return max(a, b)
+
+
+@pytest.mark.parametrize("M", [7, 9, 27])
+def test_forgetful_median_schedule_matches_sorting(M):
+    import numpy as np
+    rng = np.random.default_rng(M)
+    for t in range(4000):
+        if t % 3 == 0:
+            vals = list(rng.integers(0, 4, M))      # many ties
+        elif t % 3 == 1:
+            vals = list(rng.permutation(M))         # distinct
+        else:
+            vals = list(rng.uniform(-1, 1, M))
+        assert forgetful_median(vals) == sorted(vals)[(M - 1) // 2]
