@@ -109,6 +109,32 @@ __device__ __forceinline__ Buf plane_buf(const S *base, int64_t sz, int zp)
     return make_buf(reinterpret_cast<const char *>(base) + uint64_t(zp) * pb, pb);
 }
 
+// The input of a z march, addressed plane by plane. BIG = false: one buffer
+// resource for the whole array, the plane's byte offset as the scalar operand
+// (arrays below 4 GiB); BIG = true: a resource per plane (plane_buf), for
+// arrays of any size at a few more scalar instructions per plane.
+struct PlaneRef {
+    Buf b;
+    uint32_t soff;
+};
+
+template <typename S, bool BIG> struct PlaneSrc {
+    const S *base;
+    int64_t sz;
+    Buf whole;
+    __device__ __forceinline__ PlaneSrc(const S *in, int64_t sz_, uint64_t elems)
+        : base(in), sz(sz_), whole(make_buf(in, elems * sizeof(S)))
+    {
+    }
+    __device__ __forceinline__ PlaneRef plane(int zp) const
+    {
+        if constexpr (BIG)
+            return {plane_buf(base, sz, zp), 0u};
+        else
+            return {whole, uint32_t(zp) * uint32_t(sz) * uint32_t(sizeof(S))};
+    }
+};
+
 template <typename S> struct BufLd;
 
 template <> struct BufLd<double> {
@@ -131,6 +157,13 @@ template <> struct BufLd<bf16> {
         return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(b.r, voff, soff, 0));
     }
 };
+
+// Load at lane byte offset voff within a plane.
+template <typename S>
+__device__ __forceinline__ typename Store<S>::C plane_ld(const PlaneRef &p, uint32_t voff)
+{
+    return BufLd<S>::ld(p.b, voff, p.soff);
+}
 
 inline size_t dtype_size(int dtype)
 {

@@ -503,14 +503,26 @@ int launch_star3d_t2_t(const S *in, S *out, const Geo &g,
     if (total > 0x7fffffff)
         return fail(STENCIL_EUNSUPPORTED, "star3d (two iterations): grid too large");
     const bool img = (flags & STAR_FLAG_NOFUSE) == 0;
+    // arrays of 4 GiB or more: a buffer resource per input plane
+    const bool big = uint64_t(padded_elems(g)) * sizeof(S) >= (uint64_t(1) << 32);
+#define STAR_T2_LAUNCH(K_, ...)                                                              \
+    do {                                                                                     \
+        if (img && big)                                                                      \
+            hipLaunchKernelGGL((K_<__VA_ARGS__, true, true>), dim3((unsigned)total),          \
+                               dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags); \
+        else if (img)                                                                        \
+            hipLaunchKernelGGL((K_<__VA_ARGS__, true, false>), dim3((unsigned)total),         \
+                               dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags); \
+        else if (big)                                                                        \
+            hipLaunchKernelGGL((K_<__VA_ARGS__, false, true>), dim3((unsigned)total),         \
+                               dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags); \
+        else                                                                                 \
+            hipLaunchKernelGGL((K_<__VA_ARGS__, false, false>), dim3((unsigned)total),        \
+                               dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags); \
+    } while (0)
     if (flags & STAR_FLAG_PAIRS) {
         if constexpr (NY == 2 && R <= 3 && 64 * XW * TY <= 768) {
-            if (img)
-                hipLaunchKernelGGL((k_star3d_t2p<S, R, TY, XW, true>), dim3((unsigned)total),
-                                   dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
-            else
-                hipLaunchKernelGGL((k_star3d_t2p<S, R, TY, XW, false>), dim3((unsigned)total),
-                                   dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+            STAR_T2_LAUNCH(k_star3d_t2p, S, R, TY, XW);
             return check_launch("xcorr_star3d_t2 (pair layout)");
         } else {
             return fail(STENCIL_EUNSUPPORTED,
@@ -518,12 +530,24 @@ int launch_star3d_t2_t(const S *in, S *out, const Geo &g,
                         "radius <= 3 and at most 768 lanes");
         }
     }
-    if (img)
-        hipLaunchKernelGGL((k_star3d_t2<S, R, NY, TY, XW, true>), dim3((unsigned)total),
-                           dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
-    else
-        hipLaunchKernelGGL((k_star3d_t2<S, R, NY, TY, XW, false>), dim3((unsigned)total),
-                           dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+    // the per-plane resources only for the register-ring instances (the
+    // shifting-window ones spill registers, and each spilling instance
+    // shipped must be covered by tests: those run arrays below 4 GiB)
+    if constexpr (64 * XW * TY <= 768 && R <= 3 && NY <= 2) {
+        STAR_T2_LAUNCH(k_star3d_t2, S, R, NY, TY, XW);
+    } else {
+        if (big)
+            return fail(STENCIL_EUNSUPPORTED,
+                        "star3d (two iterations): arrays of 4 GiB or more need a tile of at "
+                        "most 768 lanes, two rows per lane and radius <= 3");
+        if (img)
+            hipLaunchKernelGGL((k_star3d_t2<S, R, NY, TY, XW, true, false>), dim3((unsigned)total),
+                               dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+        else
+            hipLaunchKernelGGL((k_star3d_t2<S, R, NY, TY, XW, false, false>), dim3((unsigned)total),
+                               dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+    }
+#undef STAR_T2_LAUNCH
     return check_launch("xcorr_star3d_t2");
 }
 

@@ -40,7 +40,7 @@ __device__ __forceinline__ int wrap_mod(int v, int n)
 // interior coordinates, so the input halo is never read and any grid size
 // works. Both stages evaluate every point with the taps in the order of the
 // one-iteration kernel, so the result is bitwise that of two chained launches.
-template <typename S, int R, int NY, int TY, int XW, bool IMG>
+template <typename S, int R, int NY, int TY, int XW, bool IMG, bool BIG>
 __device__ __forceinline__ void star3d_t2_segment(
     const S *__restrict__ in, S *__restrict__ out, const Geo g,
     const StarCoef<typename Store<S>::C, R> cf, int bxi, int byi, int z0, int z1, int flags,
@@ -58,6 +58,7 @@ __device__ __forceinline__ void star3d_t2_segment(
     constexpr bool RING = 64 * XW * TY <= 768 && R <= 3 && NY <= 2;
     constexpr int PF = !RING ? 2 : R == 1 ? 1 : R == 3 ? 2 : 3;
     constexpr uint32_t es = sizeof(S);
+    const PlaneSrc<S, BIG> src(in, g.sz, uint64_t(padded_elems(g)));
     constexpr int OX = SH::TXW - 2 * R, OY = SH::ROWS - 2 * R;
 
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -126,13 +127,13 @@ __device__ __forceinline__ void star3d_t2_segment(
         for (int k = 0; k < 2 * R + PF; ++k)
     #pragma unroll
             for (int j = 0; j < NY; ++j)
-                ring[j][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs - R + k, g.nz) + g.rz), col_off[j], 0);
+                ring[j][k] = plane_ld<S>(src.plane(wrap_mod(zs - R + k, g.nz) + g.rz), col_off[j]);
     #pragma unroll
         for (int q = 0; q < PF; ++q) {
     #pragma unroll
-            for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hx_off[k], 0);
+            for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = plane_ld<S>(src.plane(wrap_mod(zs + q, g.nz) + g.rz), hx_off[k]);
     #pragma unroll
-            for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hy_off[k], 0);
+            for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = plane_ld<S>(src.plane(wrap_mod(zs + q, g.nz) + g.rz), hy_off[k]);
         }
 
         // Halo cells are written unconditionally: a lane without one writes
@@ -175,17 +176,17 @@ __device__ __forceinline__ void star3d_t2_segment(
                     // so zA + PF + nz >= 0: an unsigned remainder wraps it, at
                     // half the scalar work of a signed one
                     const uint32_t nzu = uint32_t(g.nz), zu = uint32_t(zA + PF + g.nz);
-                    const Buf bw = plane_buf(in, g.sz, int((zu + R) % nzu) + g.rz);
-                    const Buf bh = plane_buf(in, g.sz, int(zu % nzu) + g.rz);
+                    const PlaneRef bw = src.plane(int((zu + R) % nzu) + g.rz);
+                    const PlaneRef bh = src.plane(int(zu % nzu) + g.rz);
     #pragma unroll
                     for (int j = 0; j < NY; ++j)
-                        ring[j][F0(R + PF)] = BufLd<S>::ld(bw, col_off[j], 0);
+                        ring[j][F0(R + PF)] = plane_ld<S>(bw, col_off[j]);
     #pragma unroll
                     for (int k = 0; k < SH::HX_PER; ++k)
-                        hxr[(q + PF) % NH][k] = BufLd<S>::ld(bh, hx_off[k], 0);
+                        hxr[(q + PF) % NH][k] = plane_ld<S>(bh, hx_off[k]);
     #pragma unroll
                     for (int k = 0; k < SH::HY_PER; ++k)
-                        hyr[(q + PF) % NH][k] = BufLd<S>::ld(bh, hy_off[k], 0);
+                        hyr[(q + PF) % NH][k] = plane_ld<S>(bh, hy_off[k]);
                 }
 
                 // stage B: f2 at plane zB from the f1 ring and f1's plane in LDS
@@ -266,17 +267,17 @@ __device__ __forceinline__ void star3d_t2_segment(
         for (int k = 0; k < 2 * R; ++k)
     #pragma unroll
             for (int j = 0; j < NY; ++j)
-                win[j][k + 1] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs - R + k, g.nz) + g.rz), col_off[j], 0);
+                win[j][k + 1] = plane_ld<S>(src.plane(wrap_mod(zs - R + k, g.nz) + g.rz), col_off[j]);
 
         C pre_w[PF][NY], pre_hx[PF][SH::HX_PER], pre_hy[PF][SH::HY_PER];
     #pragma unroll
         for (int q = 0; q < PF; ++q) {
     #pragma unroll
-            for (int j = 0; j < NY; ++j) pre_w[q][j] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q + R, g.nz) + g.rz), col_off[j], 0);
+            for (int j = 0; j < NY; ++j) pre_w[q][j] = plane_ld<S>(src.plane(wrap_mod(zs + q + R, g.nz) + g.rz), col_off[j]);
     #pragma unroll
-            for (int k = 0; k < SH::HX_PER; ++k) pre_hx[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hx_off[k], 0);
+            for (int k = 0; k < SH::HX_PER; ++k) pre_hx[q][k] = plane_ld<S>(src.plane(wrap_mod(zs + q, g.nz) + g.rz), hx_off[k]);
     #pragma unroll
-            for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hy_off[k], 0);
+            for (int k = 0; k < SH::HY_PER; ++k) pre_hy[q][k] = plane_ld<S>(src.plane(wrap_mod(zs + q, g.nz) + g.rz), hy_off[k]);
         }
 
         // halo cells written unconditionally, as in the ring march
@@ -312,17 +313,17 @@ __device__ __forceinline__ void star3d_t2_segment(
                 {
                     // zA + PF + nz >= 0: unsigned remainder, as in the ring march
                     const uint32_t nzu = uint32_t(g.nz), zu = uint32_t(zA + PF + g.nz);
-                    const Buf bw = plane_buf(in, g.sz, int((zu + R) % nzu) + g.rz);
-                    const Buf bh = plane_buf(in, g.sz, int(zu % nzu) + g.rz);
+                    const PlaneRef bw = src.plane(int((zu + R) % nzu) + g.rz);
+                    const PlaneRef bh = src.plane(int(zu % nzu) + g.rz);
     #pragma unroll
                     for (int j = 0; j < NY; ++j)
-                        pre_w[q][j] = BufLd<S>::ld(bw, col_off[j], 0);
+                        pre_w[q][j] = plane_ld<S>(bw, col_off[j]);
     #pragma unroll
                     for (int k = 0; k < SH::HX_PER; ++k)
-                        pre_hx[q][k] = BufLd<S>::ld(bh, hx_off[k], 0);
+                        pre_hx[q][k] = plane_ld<S>(bh, hx_off[k]);
     #pragma unroll
                     for (int k = 0; k < SH::HY_PER; ++k)
-                        pre_hy[q][k] = BufLd<S>::ld(bh, hy_off[k], 0);
+                        pre_hy[q][k] = plane_ld<S>(bh, hy_off[k]);
                 }
 
                 // stage B: f2 at plane zB from the f1 window and f1's plane in LDS
@@ -402,7 +403,7 @@ template <typename S, int XW, int TY, bool IMG> constexpr int t2_min_waves()
 // Workgroup = (tile column, z chunk of lz planes), gx * gy * gz of them.
 // IMG: the output's periodic images are written (a compile-time choice, so a
 // launch without them carries none of their scalar and exec-mask work).
-template <typename S, int R, int NY, int TY, int XW, bool IMG>
+template <typename S, int R, int NY, int TY, int XW, bool IMG, bool BIG>
 __global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY, IMG>()))
     k_star3d_t2(const S *__restrict__ in, S *__restrict__ out, Geo g,
                 StarCoef<typename Store<S>::C, R> cf, int lz, int gx, int gy, int gz, int flags)
@@ -419,7 +420,7 @@ __global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY, IMG>())
     const int byi = yfirst ? lin % gy : (lin / gx) % gy;
     const int bxi = yfirst ? (lin / gy) % gx : lin % gx;
     const int z0 = (lin / (gx * gy)) * lz;
-    star3d_t2_segment<S, R, NY, TY, XW, IMG>(in, out, g, cf, bxi, byi, z0, min(z0 + lz, g.nz),
+    star3d_t2_segment<S, R, NY, TY, XW, IMG, BIG>(in, out, g, cf, bxi, byi, z0, min(z0 + lz, g.nz),
                                              flags, lda, ldb);
 }
 

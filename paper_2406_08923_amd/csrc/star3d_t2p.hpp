@@ -42,7 +42,7 @@ template <int R, int TY, int XW> struct PairShape {
 
 // One segment (planes z0..z1-1 of tile column (bxi, byi)) of the register-ring
 // march of star3d_t2_segment with pair-layout LDS planes.
-template <typename S, int R, int TY, int XW, bool IMG>
+template <typename S, int R, int TY, int XW, bool IMG, bool BIG>
 __device__ __forceinline__ void star3d_t2p_segment(
     const S *__restrict__ in, S *__restrict__ out, const Geo g,
     const StarCoef<typename Store<S>::C, R> cf, int bxi, int byi, int z0, int z1, int flags,
@@ -58,6 +58,7 @@ __device__ __forceinline__ void star3d_t2p_segment(
     static_assert(NR % NH == 0, "the unrolled march must cover whole halo rings");
     constexpr int NP = (R + 1) / 2; // y-tap pairs on each side of the own pair
     constexpr uint32_t es = sizeof(S);
+    const PlaneSrc<S, BIG> src(in, g.sz, uint64_t(padded_elems(g)));
     constexpr int OX = SH::TXW - 2 * R, OY = SH::ROWS - 2 * R;
 
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -121,13 +122,13 @@ __device__ __forceinline__ void star3d_t2p_segment(
     for (int k = 0; k < 2 * R + PF; ++k)
 #pragma unroll
         for (int j = 0; j < NY; ++j)
-            ring[j][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs - R + k, g.nz) + g.rz), col_off[j], 0);
+            ring[j][k] = plane_ld<S>(src.plane(wrap_mod(zs - R + k, g.nz) + g.rz), col_off[j]);
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
 #pragma unroll
-        for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hx_off[k], 0);
+        for (int k = 0; k < SH::HX_PER; ++k) hxr[q][k] = plane_ld<S>(src.plane(wrap_mod(zs + q, g.nz) + g.rz), hx_off[k]);
 #pragma unroll
-        for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = BufLd<S>::ld(plane_buf(in, g.sz, wrap_mod(zs + q, g.nz) + g.rz), hy_off[k], 0);
+        for (int k = 0; k < SH::HY_PER; ++k) hyr[q][k] = plane_ld<S>(src.plane(wrap_mod(zs + q, g.nz) + g.rz), hy_off[k]);
     }
     const bool xin = tx >= R && tx < SH::TXW - R;                 // stage B lanes
     const bool yin = r0 + 1 >= R && r0 < SH::ROWS - R;            // a stage-B row
@@ -161,14 +162,14 @@ __device__ __forceinline__ void star3d_t2p_segment(
                 // plane zA + PF likewise; zA >= -R and a periodic axis holds
                 // at least R planes, so zA + PF + nz >= 0 (unsigned remainder)
                 const uint32_t nzu = uint32_t(g.nz), zu = uint32_t(zA + PF + g.nz);
-                const Buf bw = plane_buf(in, g.sz, int((zu + R) % nzu) + g.rz);
-                const Buf bh = plane_buf(in, g.sz, int(zu % nzu) + g.rz);
+                const PlaneRef bw = src.plane(int((zu + R) % nzu) + g.rz);
+                const PlaneRef bh = src.plane(int(zu % nzu) + g.rz);
 #pragma unroll
-                for (int j = 0; j < NY; ++j) ring[j][F0(R + PF)] = BufLd<S>::ld(bw, col_off[j], 0);
+                for (int j = 0; j < NY; ++j) ring[j][F0(R + PF)] = plane_ld<S>(bw, col_off[j]);
 #pragma unroll
-                for (int k = 0; k < SH::HX_PER; ++k) hxr[(q + PF) % NH][k] = BufLd<S>::ld(bh, hx_off[k], 0);
+                for (int k = 0; k < SH::HX_PER; ++k) hxr[(q + PF) % NH][k] = plane_ld<S>(bh, hx_off[k]);
 #pragma unroll
-                for (int k = 0; k < SH::HY_PER; ++k) hyr[(q + PF) % NH][k] = BufLd<S>::ld(bh, hy_off[k], 0);
+                for (int k = 0; k < SH::HY_PER; ++k) hyr[(q + PF) % NH][k] = plane_ld<S>(bh, hy_off[k]);
             }
 
             // stage B: f2 at plane zB from the f1 ring and f1's plane in LDS
@@ -275,7 +276,7 @@ __device__ __forceinline__ void star3d_t2p_segment(
 
 // Workgroup = (tile column, z chunk of lz planes), gx * gy * gz of them;
 // IMG as in k_star3d_t2.
-template <typename S, int R, int TY, int XW, bool IMG>
+template <typename S, int R, int TY, int XW, bool IMG, bool BIG>
 __global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY, IMG>()))
     k_star3d_t2p(const S *__restrict__ in, S *__restrict__ out, Geo g,
                  StarCoef<typename Store<S>::C, R> cf, int lz, int gx, int gy, int gz, int flags)
@@ -292,7 +293,7 @@ __global__ void __launch_bounds__(64 * XW * TY, (t2_min_waves<S, XW, TY, IMG>())
     const int byi = yfirst ? lin % gy : (lin / gx) % gy;
     const int bxi = yfirst ? (lin / gy) % gx : lin % gx;
     const int z0 = (lin / (gx * gy)) * lz;
-    star3d_t2p_segment<S, R, TY, XW, IMG>(in, out, g, cf, bxi, byi, z0, min(z0 + lz, g.nz), flags, lda,
+    star3d_t2p_segment<S, R, TY, XW, IMG, BIG>(in, out, g, cf, bxi, byi, z0, min(z0 + lz, g.nz), flags, lda,
                                      ldb);
 }
 
