@@ -299,6 +299,7 @@ def secondary(torch, S, W, inputs, args):
         det["filters_512_f64"] = filters(torch, S, inputs, args.n)
         f = det["filters_512_f64"]
         comp["f4_filters_512_f64"] = {"max_ms": f["max_3x3x3"]["ms_per_launch"],
+                                      "max_frac": f["max_3x3x3"]["hbm_frac"],
                                       "median_ms": f["median_3x3x3"]["ms_per_launch"]}
     if want("mhd"):
         progress("fused 8-field steps")
@@ -351,7 +352,6 @@ def secondary(torch, S, W, inputs, args):
                 d["autotuned"] = {"ms_per_step": tms, "schedule": list(tp.schedule),
                                   "default_schedule": list(plan.schedule)}
                 comp[key]["tuned_ms"] = tms
-                comp[key]["tuned_sched"] = list(tp.schedule)
                 del tp
             if mname == "mhd8" and prec == S.PREC_F64:
                 # FP64 diagnostics of the 8 fields (a7): sums, sums of squares,
@@ -391,8 +391,11 @@ def secondary(torch, S, W, inputs, args):
                 "jobs": args.serve_jobs, "rate_per_s": 200,
                 "served": {k: sv["served"][k] for k in keep},
                 "fifo_f64": {k: sv["fifo_f64"][k] for k in keep},
-                "served_by_dtype": sv["served"]["by_dtype"],
-                "fifo_by_dtype": sv["fifo_f64"]["by_dtype"],
+                # per request dtype: [jobs, p50 s, p99 s, point-steps/s]
+                "served_by_dtype": {d: [v["jobs"], v["p50_s"], v["p99_s"], v["point_steps_per_s"]]
+                                    for d, v in sv["served"]["by_dtype"].items()},
+                "fifo_by_dtype": {d: [v["jobs"], v["p50_s"], v["p99_s"], v["point_steps_per_s"]]
+                                  for d, v in sv["fifo_f64"]["by_dtype"].items()},
                 "served_tuned": {k: sv["served_tuned"][k] for k in keep},
                 "speedup": sv["speedup_point_steps_per_s"],
                 "p99_ratio_fifo_over_served": sv["p99_ratio_fifo_over_served"],
@@ -403,15 +406,19 @@ def secondary(torch, S, W, inputs, args):
 
 
 def filters(torch, S, inputs, n):
-    """Window filters on the n^3 FP64 field: 3x3x3 max (z-march kernel) and
-    3x3x3 median (gather kernel, forgetful selection among 27 keys), one
+    """Window filters on the n^3 FP64 field: 3x3x3 max (the default
+    lane-exchange z march, and the LDS z march for comparison) and 3x3x3
+    median (gather kernel, forgetful selection among the 27 values), one
     periodic application per launch; 16 B per point (read once, write once)."""
     import numpy as np
     dims, r = (n, n, n), 1
     out = {}
     x = torch.from_numpy(inputs.uniform_field(dims, 1)).cuda()
-    for name, op in (("max_3x3x3", S.OP_MAX), ("median_3x3x3", S.OP_MEDIAN)):
-        p = S.LinearPlan(dims, r, np.ones((3, 3, 3)), op=op)
+    for name, op, tile in (("max_3x3x3", S.OP_MAX, None), ("median_3x3x3", S.OP_MEDIAN, None),
+                           # the LDS z march the lane-exchange default replaced
+                           ("max_3x3x3_lds_march", S.OP_MAX, (8, 1, 32, 0))):
+        p = S.LinearPlan(dims, r, np.ones((3, 3, 3)), op=op,
+                         variant=S.STAR3D if tile else S.VARIANT_AUTO, tile=tile)
         a = p.empty(0.0)
         p.padded(a)[r:r + n, r:r + n, r:r + n] = x
         b = p.empty(0.0)

@@ -95,7 +95,14 @@ typedef struct stencil_desc {
      *             asks for; results are bitwise those of one-iteration
      *             launches), bit 16 (two iterations, two rows per lane,
      *             r <= 3, at most 768 lanes) LDS planes stored y-fastest so
-     *             a lane's two rows are one 2-wide read}; one-iteration
+     *             a lane's two rows are one 2-wide read, bit 17 (one
+     *             iteration) lane-exchange z march: no LDS, x taps moved
+     *             across the 64 lanes of a wave by DPP shifts (a wave yields
+     *             64 - 2r columns), y taps outside the lane's rows loaded;
+     *             (lanes, rows) = (waves per workgroup, rows per lane) one of
+     *             (4,2) (4,4) (8,2) (8,4), planes in flight 1 or 3 (bits
+     *             4..7; 0 and 2 mean 1), width ignored; results bitwise
+     *             those of the LDS march}; one-iteration
      *             (width, lanes, rows) one of
      *             (1,8,2) (1,4,4) (1,8,4) (1,16,2) (2,4,2) (2,4,4) (2,8,2)
      *             (4,2,2) (4,2,4) (4,4,2) (8,1,4) (8,2,2); two-iteration
@@ -132,8 +139,12 @@ typedef struct stencil_desc {
      * a window holding a NaN yields NaN; results are elements of the window
      * (no rounding). Filters run the GENERIC gather (any window) or, for 3-D
      * max/min over a full box of radius 1..3, the STAR3D z march (tile: {y
-     * lanes 4 or 8, 0, z planes per workgroup, 0}); LINE1D and fused
-     * iterations are cross-correlation only. */
+     * lanes 4 or 8, 0, z planes per workgroup, flags}: bit 0 XCD-aware order,
+     * bit 17 the lane-exchange march, then {waves per workgroup 4 or 8, rows
+     * per lane 2 or 4, z planes per workgroup, flags with planes in flight 1
+     * or 3 in bits 4..7 (3 with four rows at radius 1 only)}; the default for
+     * arrays below 4 GiB); LINE1D and fused iterations are cross-correlation
+     * only. */
     int op;
 } stencil_desc;
 

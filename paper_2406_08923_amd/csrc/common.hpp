@@ -165,6 +165,62 @@ __device__ __forceinline__ typename Store<S>::C plane_ld(const PlaneRef &p, uint
     return BufLd<S>::ld(p.b, voff, p.soff);
 }
 
+// ---------------------------------------------------------------------------
+// workgroup order
+// ---------------------------------------------------------------------------
+
+// Workgroup order. Dispatch sends workgroup i to XCD i % 8. With the XCD flag
+// the bijection below gives XCD k a contiguous range of tile numbers (the first
+// total % 8 XCDs one more than the others), so tiles that run on one XCD at the
+// same time are neighbours and share halo lines in that XCD's L2. Tile numbers
+// run fastest along x (x-neighbours share the cache lines that hold their x
+// halo), or along y with STAR_FLAG_YFIRST (y-neighbours share halo rows), then
+// along the other axis, then over z chunks.
+__device__ __forceinline__ int xcd_remap(int lin, int total)
+{
+    const int nxcd = 8;
+    const int per = total / nxcd, rem = total % nxcd;
+    const int xcd = lin % nxcd, slot = lin / nxcd;
+    return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+// ---------------------------------------------------------------------------
+// cross-lane moves
+// ---------------------------------------------------------------------------
+//
+// One-lane shifts across the whole 64-lane wave through the data-parallel
+// primitive (DPP) source modifier: lane_up gives lane i the value of lane
+// i - 1 (wave_shr:1), lane_down the value of lane i + 1 (wave_shl:1). The lane
+// with no source (0, resp. 63) keeps its own value. DPP moves 32 bits, so a
+// 64-bit value takes two. Every lane of the wave must execute the shift (the
+// kernels call them outside divergent code).
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL> __device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return uint32_t(__builtin_amdgcn_update_dpp(int(v), int(v), CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL> __device__ __forceinline__ uint64_t dpp64(uint64_t v)
+{
+    const uint32_t lo = dpp32<CTRL>(uint32_t(v)), hi = dpp32<CTRL>(uint32_t(v >> 32));
+    return uint64_t(lo) | (uint64_t(hi) << 32);
+}
+
+template <int CTRL> __device__ __forceinline__ float dpp_val(float v)
+{
+    return __builtin_bit_cast(float, dpp32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_val(double v)
+{
+    return __builtin_bit_cast(double, dpp64<CTRL>(__builtin_bit_cast(uint64_t, v)));
+}
+template <int CTRL> __device__ __forceinline__ uint32_t dpp_val(uint32_t v) { return dpp32<CTRL>(v); }
+template <int CTRL> __device__ __forceinline__ uint64_t dpp_val(uint64_t v) { return dpp64<CTRL>(v); }
+
+template <typename T> __device__ __forceinline__ T lane_up(T v) { return dpp_val<DPP_WAVE_SHR1>(v); }
+template <typename T> __device__ __forceinline__ T lane_down(T v) { return dpp_val<DPP_WAVE_SHL1>(v); }
+
 inline size_t dtype_size(int dtype)
 {
     return dtype == STENCIL_F64 ? 8 : dtype == STENCIL_F32 ? 4 : dtype == STENCIL_BF16 ? 2 : 0;

@@ -17,10 +17,13 @@ template <typename S>
 int launch_filter_gather(const S *in, S *out, const Geo &g, const int *offs, int ntaps, int op,
                          bool fuse, int bx, int by, hipStream_t s);
 
-// 3-D box window of radius R (1..3), max or min: z march with LDS planes;
-// ty lanes along y (4 or 8), lz planes per workgroup.
+// 3-D box window of radius R (1..3), max or min, marching along z over lz
+// planes per workgroup. dpp = false: LDS planes, ty lanes along y (4 or 8),
+// ny and pf ignored. dpp = true: no LDS, x neighbours exchanged across lanes;
+// ty waves per workgroup (4 or 8), ny rows per lane (2 or 4), pf planes in
+// flight (1 or 3; 0 and 2 mean 1); xcd: XCD-aware order.
 template <typename S>
 int launch_filter_box3d(const S *in, S *out, const Geo &g, int R, int op, bool fuse, int ty,
-                        int lz, hipStream_t s);
+                        int ny, int pf, int lz, bool dpp, int xcd, hipStream_t s);
 
 } // namespace stn

@@ -114,7 +114,9 @@ template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out
     if (p->lin.op != STENCIL_OP_XCORR) {
         if (p->lin.variant == STENCIL_VARIANT_STAR3D)
             return launch_filter_box3d<S>(in, out, p->lin.g, p->lin.reff, p->lin.op, periodic,
-                                          p->lin.ty, p->lin.lz, s);
+                                          p->lin.ty, p->lin.ny, p->lin.pf, p->lin.lz,
+                                          p->lin.dpp != 0,
+                                          p->lin.sflags & STAR_FLAG_XCD, s);
         return launch_filter_gather<S>(in, out, p->lin.g, static_cast<const int *>(p->lin.d_offs),
                                        p->lin.ntaps, p->lin.op, periodic, p->lin.gbx, p->lin.gby,
                                        s);
@@ -123,7 +125,8 @@ template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out
     case STENCIL_VARIANT_STAR3D: {
         int fl = p->lin.sflags | (periodic ? 0 : STAR_FLAG_NOFUSE);
         rc = launch_star3d(in, out, p->lin.g, p->lin.star, p->lin.reff, p->lin.xw, p->lin.ty,
-                           p->lin.ny, p->lin.pf, p->lin.lz, fl & 15, s);
+                           p->lin.ny, p->lin.pf, p->lin.lz,
+                           (fl & 15) | (p->lin.dpp ? STAR_FLAG_DPP : 0), s);
         if (rc == STENCIL_OK && periodic && (p->lin.sflags & STAR_FLAG_NOFUSE))
             rc = launch_halo<S>(out, p->lin.g, s);
         return rc;
@@ -240,6 +243,7 @@ void set_choice(stencil_plan_s *p, const TuneChoice &c)
         p->lin.xw = xw ? xw : 1;
         p->lin.tstar = t == 2 ? 2 : 1;
         p->lin.pairs = (c.p3 & STAR_PAIRS_BIT) != 0 && t == 2;
+        p->lin.dpp = (c.p3 & STAR_DPP_BIT) != 0 && t != 2;
     } else if (c.variant == STENCIL_VARIANT_LINE1D) {
         p->lin.e1d = c.p0;
         p->lin.t1d = c.p1 > 1 ? c.p1 : 1;
@@ -255,10 +259,20 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
     std::vector<TuneChoice> c;
     const Geo &g = p->lin.g;
     if (p->lin.op != STENCIL_OP_XCORR) {
-        if (p->lin.is_box && p->lin.op != STENCIL_OP_MEDIAN)
+        if (p->lin.is_box && p->lin.op != STENCIL_OP_MEDIAN) {
             for (int ty : {4, 8})
                 for (int lz : {16, 32, 64})
                     c.push_back({STENCIL_VARIANT_STAR3D, ty, 1, lz, 0});
+            // lane-exchange march: (waves per workgroup, rows per lane), one
+            // or three planes in flight (three with four rows: radius 1 only)
+            for (int ty : {4, 8})
+                for (int ny : {2, 4})
+                    for (int lz : {4, 8, 16, 32})
+                        for (int pf : {1, 3})
+                            if (pf == 1 || ny == 2 || p->lin.reff == 1)
+                                c.push_back({STENCIL_VARIANT_STAR3D, ty, ny, lz,
+                                             STAR_FLAG_XCD | STAR_DPP_BIT | (pf << STAR_PF_SHIFT)});
+        }
         c.push_back({STENCIL_VARIANT_GENERIC, 64, 4, 0, 0});
         c.push_back({STENCIL_VARIANT_GENERIC, 64, 8, 0, 0});
         c.push_back({STENCIL_VARIANT_GENERIC, 128, 2, 0, 0});
@@ -295,6 +309,17 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
                         c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz, w | STAR_PAIRS_BIT});
                 }
         }
+        // lane-exchange z march: (waves per workgroup, rows per lane)
+        const int dshapes[][2] = {{4, 2}, {4, 4}, {8, 2}, {8, 4}};
+        for (auto &sh : dshapes)
+            for (int k = 0; k < 3; ++k) {
+                const int lz = lzs[k];
+                if (lz >= g.nz && lz != 32)
+                    continue;
+                c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz, STAR_FLAG_XCD | STAR_DPP_BIT});
+                c.push_back({STENCIL_VARIANT_STAR3D, sh[0], sh[1], lz,
+                             STAR_FLAG_XCD | STAR_FLAG_YFIRST | STAR_DPP_BIT});
+            }
         // hardware-cached z march: (lanes along y, rows per lane)
         const int hshapes[][2] = {{4, 1}, {4, 2}, {4, 4}, {2, 4}, {8, 2}};
         for (auto &sh : hshapes)
@@ -339,6 +364,14 @@ TuneChoice default_star1(const stencil_plan_s *p)
 TuneChoice default_choice(const stencil_plan_s *p)
 {
     if (p->lin.op != STENCIL_OP_XCORR) {
+        // 3-D box max/min: the lane-exchange march with short z chunks and
+        // three planes in flight measured fastest at 512^3 (FP64 and FP32);
+        // arrays of 4 GiB or more take the LDS march
+        const bool big = uint64_t(padded_elems(p->lin.g)) * dtype_size(p->lin.dtype) >=
+                         (uint64_t(1) << 32);
+        if (p->lin.is_box && p->lin.op != STENCIL_OP_MEDIAN && !big)
+            return {STENCIL_VARIANT_STAR3D, 4, p->lin.reff == 1 ? 4 : 2, 8,
+                    STAR_FLAG_XCD | STAR_DPP_BIT | (3 << STAR_PF_SHIFT)};
         if (p->lin.is_box && p->lin.op != STENCIL_OP_MEDIAN)
             return {STENCIL_VARIANT_STAR3D, 4, 1, 32, 0};
         return {STENCIL_VARIANT_GENERIC, p->lin.g.ndim == 1 ? 256 : 64,
@@ -633,13 +666,20 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
             if (t[0]) c.p0 = t[0];
             if (t[1]) c.p1 = t[1];
             if (t[2]) c.p2 = t[2];
-            c.p3 = t[3] & (0xffff | STAR_PAIRS_BIT); // explicit tiles set the flag word exactly
+            c.p3 = t[3] & (0xffff | STAR_PAIRS_BIT | STAR_DPP_BIT); // explicit tiles set the flag word exactly
             const int tb = (c.p3 >> STAR_T_SHIFT) & 15;
             if (tb > 2 || (tb == 2 && d->bc != STENCIL_BC_PERIODIC) ||
                 (tb == 2 && (c.p3 & (STAR_FLAG_HWC | STAR_FLAG_NOFUSE)))) {
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "two iterations per launch need a periodic plan and "
                                             "the LDS variant (and 1 or 2 iterations only)");
+            }
+            if ((c.p3 & STAR_DPP_BIT) &&
+                (tb == 2 || (c.p3 & (STAR_FLAG_HWC | STAR_PAIRS_BIT)) ||
+                 (L.op != STENCIL_OP_XCORR && L.reff > 3))) {
+                stencil_plan_destroy(p);
+                return fail(STENCIL_EINVAL, "the lane-exchange march runs one iteration per "
+                                            "launch, without the cached or pair-layout flags");
             }
             if ((c.p3 & STAR_PAIRS_BIT) &&
                 (tb != 2 || c.p1 != 2 || L.reff > 3 || 64 * (((c.p3 >> STAR_XW_SHIFT) & 15) ?
@@ -720,7 +760,8 @@ stencil_status stencil_plan_tile(stencil_plan_t p, int tile[4])
         tile[1] = L.ny;
         tile[2] = L.lz;
         tile[3] = L.sflags | (L.pf << STAR_PF_SHIFT) | (L.xw << STAR_XW_SHIFT) |
-                  (L.tstar == 2 ? 2 << STAR_T_SHIFT : 0) | (L.pairs ? STAR_PAIRS_BIT : 0);
+                  (L.tstar == 2 ? 2 << STAR_T_SHIFT : 0) | (L.pairs ? STAR_PAIRS_BIT : 0) |
+                  (L.dpp ? STAR_DPP_BIT : 0);
     } else if (L.variant == STENCIL_VARIANT_LINE1D) {
         tile[0] = L.e1d;
         tile[1] = L.t1d;

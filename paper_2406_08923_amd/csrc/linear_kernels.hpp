@@ -42,10 +42,12 @@ constexpr int STAR_FLAG_NOFUSE = 2; // do not write periodic images
 constexpr int STAR_FLAG_YFIRST = 4; // tile numbers run fastest along y
 constexpr int STAR_FLAG_HWC = 8;    // hardware-cached z march (no LDS)
 constexpr int STAR_FLAG_PAIRS = 16; // two-iteration march with pair-layout LDS planes
+constexpr int STAR_FLAG_DPP = 32;   // one-iteration march, x taps across lanes (no LDS)
 constexpr int STAR_PF_SHIFT = 4;    // bits 4..7: prefetch depth (0 = default)
 constexpr int STAR_XW_SHIFT = 8;    // bits 8..11: tile width in waves (0 = 1)
 constexpr int STAR_T_SHIFT = 12;    // bits 12..15: iterations per launch (0/1 = 1, or 2)
 constexpr int STAR_PAIRS_BIT = 1 << 16; // bit 16: pair-layout LDS planes (two iterations)
+constexpr int STAR_DPP_BIT = 1 << 17;   // bit 17: x taps across lanes (one iteration; filters too)
 
 
 template <typename S> int launch_halo(S *a, const Geo &g, hipStream_t s);

@@ -27,6 +27,8 @@ struct LinearPlan {
     int ty = 8, ny = 2, lz = 32, sflags = 0, pf = 2, xw = 1; // STAR3D
     int tstar = 1;          // STAR3D iterations per launch (1 or 2)
     int pairs = 0;          // two-iteration STAR3D with pair-layout LDS planes
+    int dpp = 0;            // one-iteration STAR3D / box filter with x taps
+                            // exchanged across lanes (no LDS)
     int s1[5] = {0};        // one-iteration STAR3D shape used beside tstar = 2:
                             // {ty, ny, lz, flags, xw}
     int gbx = 64, gby = 4;                   // GENERIC

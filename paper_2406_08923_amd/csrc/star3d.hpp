@@ -28,21 +28,6 @@ template <int R, int NY, int TY, int XW> struct StarShape {
     static constexpr int HY_PER = (NYH + NT - 1) / NT;
 };
 
-// Workgroup order. Dispatch sends workgroup i to XCD i % 8. With the XCD flag
-// the bijection below gives XCD k a contiguous range of tile numbers (the first
-// total % 8 XCDs one more than the others), so tiles that run on one XCD at the
-// same time are neighbours and share halo lines in that XCD's L2. Tile numbers
-// run fastest along x (x-neighbours share the cache lines that hold their x
-// halo), or along y with STAR_FLAG_YFIRST (y-neighbours share halo rows), then
-// along the other axis, then over z chunks.
-__device__ __forceinline__ int xcd_remap(int lin, int total)
-{
-    const int nxcd = 8;
-    const int per = total / nxcd, rem = total % nxcd;
-    const int xcd = lin % nxcd, slot = lin / nxcd;
-    return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
-}
-
 // Workgroup = 64*XW x TY lanes; lane (tx, ty) owns column x = x0 + tx and the NY
 // consecutive rows y0 + ty*NY + j, and marches along z over a chunk of lz
 // output planes. Per lane and row the 2R+1 column values around the current
@@ -487,6 +472,7 @@ int launch_star3d_hwc_r(const S *in, S *out, const Geo &g,
 
 #include "star3d_t2.hpp"
 #include "star3d_t2p.hpp"
+#include "star3d_dpp.hpp"
 
 namespace stn {
 
@@ -591,6 +577,15 @@ int launch_star3d_impl(const S *in, S *out, const Geo &g, const StarCoefAny &cfa
     using C = typename Store<S>::C;
     if (R > g.r || g.ndim != 3)
         return fail(STENCIL_EINVAL, "star3d: tap radius %d exceeds padding %d", R, g.r);
+    if (flags & STAR_FLAG_DPP) {
+        switch (R) {
+        case 1: return launch_star3d_dpp_r<S, 1>(in, out, g, cfa.get<C, 1>(), ty, ny, pf, lz, flags, s);
+        case 2: return launch_star3d_dpp_r<S, 2>(in, out, g, cfa.get<C, 2>(), ty, ny, pf, lz, flags, s);
+        case 3: return launch_star3d_dpp_r<S, 3>(in, out, g, cfa.get<C, 3>(), ty, ny, pf, lz, flags, s);
+        case 4: return launch_star3d_dpp_r<S, 4>(in, out, g, cfa.get<C, 4>(), ty, ny, pf, lz, flags, s);
+        }
+        return fail(STENCIL_EUNSUPPORTED, "star3d: radius %d not in 1..4", R);
+    }
     if (flags & STAR_FLAG_HWC) {
         if (uint64_t(padded_elems(g)) * sizeof(S) >= (uint64_t(1) << 32))
             return fail(STENCIL_EUNSUPPORTED,

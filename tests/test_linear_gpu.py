@@ -708,7 +708,9 @@ def same_bits(a, b):
 
 FILTER_CASES = [((1000,), 3, "box"), ((333,), 13, "box"), ((45, 37), 2, "box"), ((45, 37), 3, "star"),
                 ((29, 17, 23), 1, "box"), ((29, 17, 23), 2, "star"), ((29, 17, 23), 3, "holey"),
-                ((70, 33, 21), 2, "box")]
+                ((70, 33, 21), 2, "box"),
+                # the windows whose median runs by forgetful selection: 9 and 7 cells
+                ((45, 37), 1, "box"), ((29, 17, 23), 1, "star")]
 
 
 @pytest.mark.parametrize("case", range(len(FILTER_CASES)))
@@ -754,6 +756,30 @@ def test_filters_signed_zeros_and_nan(op, variant):
                                 inner=inner)
     assert same_bits(got, ref)
     assert int(np.isnan(got).sum()) == 27
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("window", ["box27", "star7", "box9", "line5"])
+def test_median_signed_zeros_nan_and_ties(window, dtype):
+    # few distinct values (many ties, zeros of both signs): the selection
+    # compares values, so the sign of a zero median is the total order's
+    # (-0 below +0); windows with a NaN give NaN
+    if window == "box9":
+        dims, r, mask = (40, 36), 1, np.ones((3, 3))
+    elif window == "line5":
+        dims, r, mask = (4000,), 2, np.ones(5)  # rank counting, for comparison
+    else:
+        dims, r = (40, 20, 12), 1
+        mask = np.ones((3, 3, 3)) if window == "box27" else star_mask(3, 1)
+    rng = np.random.default_rng(11)
+    inner = rng.choice(np.array([-0.0, 0.0, -0.0, 0.0, -1.0, 1.0, 0.5, -0.5]),
+                       size=dims[::-1])
+    inner.reshape(-1)[rng.integers(0, inner.size, 3)] = np.nan
+    inner = to_storage_values(inner, dtype)
+    got, ref, _, _ = run_filter(dims, r, mask, S.OP_MEDIAN, dtype, inner=inner)
+    assert same_bits(got, ref)
+    zeros = got[got == 0]
+    assert np.signbit(zeros).any() and (~np.signbit(zeros)).any()
 
 
 def test_filters_chained_and_user_halo():
