@@ -165,6 +165,19 @@ __device__ __forceinline__ typename Store<S>::C plane_ld(const PlaneRef &p, uint
     return BufLd<S>::ld(p.b, voff, p.soff);
 }
 
+// least common multiple, for the lengths of unrolled rounds over several
+// register rings
+constexpr int lcm_int(int a, int b)
+{
+    int x = a, y = b;
+    while (y) {
+        const int t = x % y;
+        x = y;
+        y = t;
+    }
+    return a / x * b;
+}
+
 // ---------------------------------------------------------------------------
 // workgroup order
 // ---------------------------------------------------------------------------

@@ -291,17 +291,6 @@ __global__ void __launch_bounds__(64 * TY)
 // register ring; the output at plane z reduces the ring around z. The loads
 // of the next plane are in flight while the current one is reduced. Max and
 // min pick one window element, so the result is bitwise the LDS march's.
-constexpr int lcm_int(int a, int b)
-{
-    int x = a, y = b;
-    while (y) {
-        const int t = x % y;
-        x = y;
-        y = t;
-    }
-    return a / x * b;
-}
-
 template <typename S, int R, int OP, int NY, int TY, int PF>
 __global__ void __launch_bounds__(64 * TY)
     k_filter_box3d_dpp(const S *__restrict__ in, S *__restrict__ out, Geo g, int lz, int gx,

@@ -53,9 +53,16 @@ __device__ __forceinline__ void star3d_t2p_segment(
     using P = typename Pair2<C>::T;
     using SH = PairShape<R, TY, XW>;
     constexpr int NY = 2, E = SH::E, H = SH::H;
-    constexpr int PF = R == 1 ? 1 : R == 3 ? 2 : 3; // PF + 1 divides 2R
+    // PF planes of loads in flight ahead of the step that consumes them. The
+    // march waits on memory latency more than on any unit (about two steps'
+    // worth of loads in flight per CU at 3.6 TB/s), so the FP64 launches
+    // without images take three (0.366 against 0.396 ms per iteration at
+    // 512^3); with image stores or 4-byte storage the longer unrolled round
+    // spills, so those keep two (one at r = 1, three at r = 2 and 4, where
+    // PF + 1 divides the ring).
+    constexpr int PF = R == 1 ? 1 : R == 3 ? (IMG || sizeof(S) != 8 ? 2 : 3) : 3;
     constexpr int NR = 2 * R + 1 + PF, NH = PF + 1;
-    static_assert(NR % NH == 0, "the unrolled march must cover whole halo rings");
+    constexpr int U = lcm_int(NR, NH); // steps per unrolled round: whole turns of both rings
     constexpr int NP = (R + 1) / 2; // y-tap pairs on each side of the own pair
     constexpr uint32_t es = sizeof(S);
     const PlaneSrc<S, BIG> src(in, g.sz, uint64_t(padded_elems(g)));
@@ -109,7 +116,7 @@ __device__ __forceinline__ void star3d_t2p_segment(
     }
 
     // Register rings: f0 / f1 plane p in slot (p - zs + R) mod NR, the f0
-    // halo of plane p in slot (p - zs) mod NH; the march is unrolled by NR
+    // halo of plane p in slot (p - zs) mod NH; the march is unrolled by U
     // steps so every slot index is a compile-time constant.
     const int zs = z0 - R, ze = z1 + R; // steps zA; stage B is live from zA = z0 + R + 1 on
     C ring[NY][NR], r1[NY][NR];
@@ -132,9 +139,9 @@ __device__ __forceinline__ void star3d_t2p_segment(
     }
     const bool xin = tx >= R && tx < SH::TXW - R;                 // stage B lanes
     const bool yin = r0 + 1 >= R && r0 < SH::ROWS - R;            // a stage-B row
-    for (int zb = zs; zb <= ze; zb += NR) {
+    for (int zb = zs; zb <= ze; zb += U) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {
+        for (int q = 0; q < U; ++q) {
             const int zA = zb + q;
             if (zA > ze)
                 break;
