@@ -73,8 +73,8 @@ def parse():
     ap.add_argument("--detail-out", default=None,
                     help="also write the full record (JSON) to this file")
     ap.add_argument("--only", default=None,
-                    help="comma list of secondary sections to run (stars, lines, filters, mhd, "
-                         "precision, serving); default: all")
+                    help="comma list of secondary sections to run (stars, lines, filters, box, "
+                         "mhd, precision, serving); default: all")
     return ap.parse_args()
 
 
@@ -301,6 +301,13 @@ def secondary(torch, S, W, inputs, args):
         comp["f4_filters_512_f64"] = {"max_ms": f["max_3x3x3"]["ms_per_launch"],
                                       "max_frac": f["max_3x3x3"]["hbm_frac"],
                                       "median_ms": f["median_3x3x3"]["ms_per_launch"]}
+    if want("box"):
+        progress("dense box")
+        det["box27_512"] = dense_box(torch, S, inputs, args.n)
+        b = det["box27_512"]
+        comp["f3_box27_512"] = {"f64_ms": b["f64"]["ms_per_launch"], "f64_frac": b["f64"]["hbm_frac"],
+                                "f64_gather_ms": b["f64_gather"]["ms_per_launch"],
+                                "f32_ms": b["f32"]["ms_per_launch"]}
     if want("mhd"):
         progress("fused 8-field steps")
         # fused 8-field RK3 step, 256^3
@@ -426,6 +433,31 @@ def filters(torch, S, inputs, n):
         ms = timed(torch, lambda: p.apply(a, b, 1, halo_valid=True), 20, warm=2)
         out[name] = {"ms_per_launch": ms, "updates_per_s": n ** 3 / (ms * 1e-3),
                      "hbm_frac": 16 * n ** 3 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "variant": p.variant, "tile": list(p.tile)}
+        del a, b, p
+    return out
+
+
+def dense_box(torch, S, inputs, n):
+    """Dense 27-point box (every tap of the radius-1 box nonzero, seeded
+    coefficients) on the n^3 field, one periodic application per launch: the
+    default BOX3D march in FP64 and FP32, and the gather kernel it replaces.
+    2 x storage bytes per point; 27 multiply-adds per point."""
+    import numpy as np
+    dims = (n, n, n)
+    g = np.random.default_rng(1).uniform(0.2, 1.0, (3, 3, 3)) / 27
+    x = torch.from_numpy(inputs.uniform_field(dims, 1)).cuda()
+    out = {}
+    for name, dtype, es, variant in (("f64", S.F64, 8, S.VARIANT_AUTO), ("f32", S.F32, 4, S.VARIANT_AUTO),
+                                     ("f64_gather", S.F64, 8, S.GENERIC)):
+        p = S.LinearPlan(dims, 1, g, dtype=dtype, variant=variant)
+        a = p.empty(0.0)
+        p.padded(a)[1:n + 1, 1:n + 1, 1:n + 1] = x.to(a.dtype)
+        b = p.empty(0.0)
+        p.halo(a)
+        ms = timed(torch, lambda: p.apply(a, b, 1, halo_valid=True), 10, warm=2)
+        out[name] = {"ms_per_launch": ms, "updates_per_s": n ** 3 / (ms * 1e-3),
+                     "hbm_frac": 2 * es * n ** 3 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "variant": p.variant, "tile": list(p.tile)}
         del a, b, p
     return out

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libstencil.so")
 # storage types, boundary modes, variants (include/stencil.h)
 F64, F32, BF16 = 0, 1, 2
 PERIODIC, USER_HALO = 0, 1
-VARIANT_AUTO, GENERIC, STAR3D, LINE1D = -1, 0, 1, 2
+VARIANT_AUTO, GENERIC, STAR3D, LINE1D, BOX3D = -1, 0, 1, 2, 3
 # stencil function: cross-correlation, or a window filter (max filter of
 # Sec. 2.3, its min twin, median filter of Sec. 1)
 OP_XCORR, OP_MAX, OP_MIN, OP_MEDIAN = 0, 1, 2, 3

@@ -36,6 +36,27 @@ struct StarCoefAny {
     }
 };
 
+// Dense box coefficients of radius R: c[((dz + R) W + dy + R) W + dx + R],
+// W = 2R + 1. Passed by value as a kernel argument.
+template <typename C, int R> struct BoxCoef {
+    C c[(2 * R + 1) * (2 * R + 1) * (2 * R + 1)];
+};
+
+constexpr int BOX_MAX_R = 1; // dense boxes with a dedicated kernel: radius 1
+
+struct BoxCoefAny {
+    int R;
+    double c[(2 * BOX_MAX_R + 1) * (2 * BOX_MAX_R + 1) * (2 * BOX_MAX_R + 1)];
+
+    template <typename C, int RR> BoxCoef<C, RR> get() const
+    {
+        BoxCoef<C, RR> o;
+        for (int k = 0; k < (2 * RR + 1) * (2 * RR + 1) * (2 * RR + 1); ++k)
+            o.c[k] = static_cast<C>(c[k]);
+        return o;
+    }
+};
+
 // star kernel flags (the tile[3] word of stencil_desc)
 constexpr int STAR_FLAG_XCD = 1;    // XCD-aware workgroup order
 constexpr int STAR_FLAG_NOFUSE = 2; // do not write periodic images
@@ -69,6 +90,17 @@ STAR_DECL(double)
 STAR_DECL(float)
 STAR_DECL(bf16)
 #undef STAR_DECL
+
+// Dense 3-D box (box3d.hpp), one overload per storage type (box3d_*.hip):
+// ty waves per workgroup, ny rows per lane, pf planes in flight (1 or 3; 0
+// and 2 mean 1), lz z planes per workgroup, flags: STAR_FLAG_XCD / NOFUSE.
+#define BOX_DECL(S)                                                                          \
+    int launch_box3d(const S *in, S *out, const Geo &g, const BoxCoefAny &cf, int ty, int ny, \
+                     int pf, int lz, int flags, hipStream_t s);
+BOX_DECL(double)
+BOX_DECL(float)
+BOX_DECL(bf16)
+#undef BOX_DECL
 
 template <typename S>
 int launch_line1d(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs, bool fuse,

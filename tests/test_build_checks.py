@@ -17,6 +17,7 @@ import ast
 import json
 import os
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -181,3 +182,49 @@ def test_forgetful_median_schedule_matches_sorting(M):
         else:
             vals = list(rng.uniform(-1, 1, M))
         assert forgetful_median(vals) == sorted(vals)[(M - 1) // 2]
+
+
+# ---------------------------------------------------------------------------
+# the dense box march's ring of partial sums (box3d.hpp), replayed on a
+# z column: output plane zo in slot (zo - zs) mod W; at input plane p the slot
+# of output p + R is cleared, every output p - dz gets tap dz, and output
+# p - R is complete
+# ---------------------------------------------------------------------------
+
+def replay_box_ring(f, c, R, z0, z1, clear_shift):
+    W = 2 * R + 1
+    nz = len(f)
+    fp = np.concatenate([f[-R:], f, f[:R]])
+    zs, ze = z0 - R, z1 + R
+    acc = np.zeros(W)
+    out = {}
+    for p in range(zs, ze):
+        q = p - zs
+        acc[(q + clear_shift) % W] = 0.0
+        for dz in range(-R, R + 1):
+            acc[(q - dz) % W] += c[dz + R] * fp[p + R]
+        if p - R >= z0:
+            out[p - R] = acc[(q - R) % W]
+    return out
+
+
+@pytest.mark.parametrize("nz,lz", [(29, 5), (7, 7), (3, 2), (12, 16), (1, 1)])
+def test_box_partial_sum_ring_gives_the_correlation(nz, lz):
+    rng = np.random.default_rng(nz * 31 + lz)
+    R = 1
+    f, c = rng.uniform(-1, 1, nz), rng.uniform(-1, 1, 2 * R + 1)
+    fp = np.concatenate([f[-R:], f, f[:R]])
+    want = [sum(c[dz + R] * fp[z + dz + R] for dz in range(-R, R + 1)) for z in range(nz)]
+    got = {}
+    for z0 in range(0, nz, lz):
+        got.update(replay_box_ring(f, c, R, z0, min(z0 + lz, nz), clear_shift=R))
+    assert np.allclose([got[z] for z in range(nz)], want)
+
+
+def test_box_partial_sum_ring_model_catches_a_wrong_clear():
+    rng = np.random.default_rng(3)
+    f, c = rng.uniform(-1, 1, 29), rng.uniform(-1, 1, 3)
+    fp = np.concatenate([f[-1:], f, f[:1]])
+    want = [sum(c[dz + 1] * fp[z + dz + 1] for dz in (-1, 0, 1)) for z in range(29)]
+    got = replay_box_ring(f, c, 1, 0, 29, clear_shift=2)  # the slot of output p - 1
+    assert not np.allclose([got[z] for z in range(29)], want)

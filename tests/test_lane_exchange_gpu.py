@@ -148,3 +148,66 @@ def test_box_filter_lane_exchange_signed_zeros_nan_user_halo(op):
     code = O.FILTER_MAX if op == S.OP_MAX else O.FILTER_MIN
     want = O.filter(a_host, 2, mask, code)
     assert np.array_equal(O.interior(out, 2), O.interior(want, 2))
+
+
+# ---------------------------------------------------------------------------
+# dense radius-1 box (BOX3D): z march with a ring of partial sums, x taps by
+# lane exchange; not bitwise any other kernel (its own summation order), so
+# checked against the oracle only
+# ---------------------------------------------------------------------------
+
+def rand_box(seed, r_pad=1):
+    rng = np.random.default_rng(seed)
+    k = 2 * r_pad + 1
+    g = np.zeros((k, k, k))
+    g[r_pad - 1:r_pad + 2, r_pad - 1:r_pad + 2, r_pad - 1:r_pad + 2] = rng.uniform(0.2, 1.0, (3, 3, 3)) * \
+        rng.choice([-1.0, 1.0], (3, 3, 3))
+    return g
+
+
+BOX_TILES = [None, (4, 2, 16, XCD), (8, 1, 5, 0), (4, 1, 64, XCD | PF3), (8, 2, 7, XCD | PF3)]
+
+
+@pytest.mark.parametrize("tile", BOX_TILES)
+@pytest.mark.parametrize("dtype", L.DTYPES)
+def test_dense_box_matches_oracle(dtype, tile):
+    dims = (70, 37, 29)  # two tile columns of 62, ragged rows and z chunks
+    g = rand_box(40) * 0.1
+    plan = L.run_case(dims, 1, g, dtype, S.BOX3D if tile else S.VARIANT_AUTO, tile=tile)
+    assert plan.variant == S.BOX3D
+
+
+def test_dense_box_chained_and_wider_padding():
+    L.run_case((45, 26, 17), 1, rand_box(41) * 0.05, S.F64, S.BOX3D, tile=(4, 2, 8, XCD), iters=5)
+    # radius-1 taps in radius-2 padding
+    plan = L.run_case((40, 20, 12), 2, rand_box(42, r_pad=2) * 0.1, S.F64, S.VARIANT_AUTO)
+    assert plan.variant == S.BOX3D
+
+
+@pytest.mark.parametrize("dims", [(3, 3, 3), (1, 1, 1), (62, 5, 4), (63, 5, 4), (2, 70, 9)])
+def test_dense_box_tiny_and_edge_grids(dims):
+    for tile in ((4, 1, 2, XCD), (8, 2, 3, PF3)):
+        L.run_case(dims, 1, rand_box(43), S.F64, S.BOX3D, tile=tile)
+
+
+def test_dense_box_user_halo_and_choice():
+    dims = (45, 26, 17)
+    g = rand_box(44)
+    rng = np.random.default_rng(14)
+    a_host = rng.uniform(-1, 1, O.padded_shape(dims, 1))
+    plan = S.LinearPlan(dims, 1, g, bc=S.USER_HALO)
+    assert plan.variant == S.BOX3D
+    b = plan.empty(fill=123.0)
+    plan.apply(L.dev(a_host, S.F64), b, 1)
+    got = L.host(b)
+    L.assert_close(O.interior(got, 1), O.interior(O.xcorr(a_host, 1, g), 1), S.F64)
+    mask = np.ones(got.shape, bool)
+    O.interior(mask, 1)[...] = False
+    assert np.all(got[mask] == 123.0)
+    g2 = g.copy()
+    g2[0, 0, 0] = 0.0  # not every tap: the gather kernel
+    assert S.LinearPlan(dims, 1, g2).variant == S.GENERIC
+    with pytest.raises(S.StencilError):
+        S.LinearPlan(dims, 1, g2, variant=S.BOX3D)
+    with pytest.raises(S.StencilError):
+        S.LinearPlan(dims, 1, diffusion_star_exact(3, 1, 0.1), variant=S.BOX3D)
