@@ -264,6 +264,44 @@ def test_star_beyond_4_gib_default_plan_sampled_points():
     assert np.array_equal(got[:, :, :r], got[:, :, dims[0]:dims[0] + r])
 
 
+@pytest.mark.parametrize("kind", ["dense_box", "lane_exchange_star"])
+def test_lane_exchange_kernels_beyond_4_gib_sampled_points(kind):
+    # the z marches without LDS address the input plane by plane above 4 GiB
+    # (a buffer resource per plane): one iteration of the dense 27-point box
+    # (default plan) and of the radius-3 star's lane-exchange march at
+    # 1024 x 1024 x 520 FP64, sampled points against the oracle
+    dims = (1024, 1024, 520)
+    if kind == "dense_box":
+        r = 1
+        g = np.random.default_rng(7).uniform(0.2, 1.0, (3, 3, 3)) / 27
+        plan = S.LinearPlan(dims, r, g)
+        assert plan.variant == S.BOX3D
+    else:
+        r = 3
+        g = diffusion_star_exact(3, r, W.diffusion_number(1024))
+        plan = S.LinearPlan(dims, r, g, variant=S.STAR3D, tile=(8, 2, 32, (1 << 17) | 1))
+    assert S.padded_elems(dims, r) * 8 >= 1 << 32
+    pad = O.pad_periodic(inputs.uniform_field(dims, 4), r)
+    a = plan.empty(0.0)
+    a.copy_(torch.from_numpy(pad))
+    b = plan.empty(0.0)
+    res = plan.apply(a, b, 1, halo_valid=True)
+    got = host(res)
+    del a, b, res
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(6)
+    pts = np.stack([rng.integers(0, d, 3000) for d in dims], axis=1)
+    corners = np.array([[x, y, z] for x in (0, dims[0] - 1) for y in (0, dims[1] - 1)
+                        for z in (0, dims[2] - 1)])
+    pts = np.concatenate([pts, corners, [[0, 0, 260], [1023, 511, 519], [61, 62, 300]]])
+    ref = O.xcorr_at(pad, r, g, pts)
+    del pad
+    vals = got[pts[:, 2] + r, pts[:, 1] + r, pts[:, 0] + r]
+    assert relerr(vals, ref) <= 1e-12
+    assert np.array_equal(got[:r], got[dims[2]:dims[2] + r])
+    assert np.array_equal(got[:, :, :r], got[:, :, dims[0]:dims[0] + r])
+
+
 def test_rk_plans_beyond_4_gib_are_refused_at_plan_time():
     with pytest.raises(S.StencilError) as e:
         S.RkPlan(S.MODEL_MHD8, (1024, 1024, 520), S.PREC_F64)
