@@ -80,11 +80,26 @@ __global__ void __launch_bounds__(RT) k_reduce_pass1(FieldPtrs fields, Geo g,
     const int64_t len = (r1 > r0 ? r1 - r0 : 0) * g.nx;
     double a = 0.0, b = 0.0, c = 0.0;
     RowWalk w(g, r0, threadIdx.x);
-    for (int64_t i = threadIdx.x; i < len; i += RT, w.step()) {
-        double v = static_cast<double>(Store<S>::ld(f + g.at(w.x, w.y, w.z)));
-        a += v;
-        b = fma(v, v, b);
-        c = fmax(c, fabs(v));
+    // PU of the lane's elements are loaded before any is added, so PU loads
+    // are in flight per lane; they are then added in the lane's element order
+    // (the same sums as one element per iteration)
+    constexpr int PU = 8;
+    for (int64_t i = threadIdx.x; i < len; i += PU * RT) {
+        double v[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            v[u] = i + u * RT < len ? static_cast<double>(Store<S>::ld(f + g.at(w.x, w.y, w.z)))
+                                    : 0.0;
+            w.step();
+        }
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            if (i + u * RT < len) {
+                a += v[u];
+                b = fma(v[u], v[u], b);
+                c = fmax(c, fabs(v[u]));
+            }
+        }
     }
     tree3(s0, s1, s2, a, b, c);
     if (threadIdx.x == 0) {
