@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/stencil.h"
 
@@ -163,6 +164,17 @@ template <typename S>
 __device__ __forceinline__ typename Store<S>::C plane_ld(const PlaneRef &p, uint32_t voff)
 {
     return BufLd<S>::ld(p.b, voff, p.soff);
+}
+
+// f(std::integral_constant<int, I>{}) for I = 0 .. N - 1, expanded at compile
+// time whatever the loop unroller's size limits (register arrays indexed by
+// I stay in registers).
+template <int N, int I = 0, typename F> __device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
 }
 
 // least common multiple, for the lengths of unrolled rounds over several

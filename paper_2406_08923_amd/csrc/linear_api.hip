@@ -318,6 +318,9 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
                     c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz, w});
                     if (sh[2] == 2 && p->lin.reff <= 3 && 64 * sh[0] * sh[1] <= 768)
                         c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz, w | STAR_PAIRS_BIT});
+                    if (sh[2] == 4 && p->lin.dtype != STENCIL_F64 && sh[0] == 1 &&
+                        64 * sh[1] <= 768)
+                        c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz, w | STAR_PAIRS_BIT});
                 }
         }
         // lane-exchange z march: (waves per workgroup, rows per lane)
@@ -725,13 +728,14 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
                 return fail(STENCIL_EINVAL, "the lane-exchange march runs one iteration per "
                                             "launch, without the cached or pair-layout flags");
             }
-            if ((c.p3 & STAR_PAIRS_BIT) &&
-                (tb != 2 || c.p1 != 2 || L.reff > 3 || 64 * (((c.p3 >> STAR_XW_SHIFT) & 15) ?
-                                                                 ((c.p3 >> STAR_XW_SHIFT) & 15) : 1) *
-                                                                 c.p0 > 768)) {
+            const int xwt = ((c.p3 >> STAR_XW_SHIFT) & 15) ? ((c.p3 >> STAR_XW_SHIFT) & 15) : 1;
+            const bool pair_ok = c.p1 == 2 && L.reff <= 3 && 64 * xwt * c.p0 <= 768;
+            const bool quad_ok = c.p1 == 4 && L.dtype != STENCIL_F64 && xwt == 1 && c.p0 * 64 <= 768;
+            if ((c.p3 & STAR_PAIRS_BIT) && (tb != 2 || !(pair_ok || quad_ok))) {
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "the pair layout needs two iterations per launch, two "
-                                            "rows per lane, radius <= 3 and at most 768 lanes");
+                                            "rows per lane, radius <= 3 and at most 768 lanes "
+                                            "(FP32/BF16: or four rows per lane, one wave wide)");
             }
         } else if (c.variant == STENCIL_VARIANT_BOX3D && (t[0] || t[1] || t[2] || t[3])) {
             if (t[0]) c.p0 = t[0];

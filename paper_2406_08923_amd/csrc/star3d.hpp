@@ -472,6 +472,7 @@ int launch_star3d_hwc_r(const S *in, S *out, const Geo &g,
 
 #include "star3d_t2.hpp"
 #include "star3d_t2p.hpp"
+#include "star3d_t2q.hpp"
 #include "star3d_dpp.hpp"
 
 namespace stn {
@@ -510,10 +511,15 @@ int launch_star3d_t2_t(const S *in, S *out, const Geo &g,
         if constexpr (NY == 2 && R <= 3 && 64 * XW * TY <= 768) {
             STAR_T2_LAUNCH(k_star3d_t2p, S, R, TY, XW);
             return check_launch("xcorr_star3d_t2 (pair layout)");
+        } else if constexpr (NY == 4 && sizeof(typename Store<S>::C) == 4 && XW == 1 &&
+                             64 * TY <= 768) {
+            STAR_T2_LAUNCH(k_star3d_t2q, S, R, TY);
+            return check_launch("xcorr_star3d_t2 (quad layout)");
         } else {
             return fail(STENCIL_EUNSUPPORTED,
                         "star3d (two iterations): the pair layout needs two rows per lane, "
-                        "radius <= 3 and at most 768 lanes");
+                        "radius <= 3 and at most 768 lanes (FP32/BF16: or four rows per lane "
+                        "in a 64-lane-wide tile)");
         }
     }
     // the per-plane resources only for the register-ring instances (the

@@ -334,6 +334,51 @@ def test_star_two_iterations_pair_layout_radii_random_taps(r, tile, dtype):
         assert_close(O.interior(got, r), O.interior(want, r), S.F64)
 
 
+QUAD_TILES = [(8, 4, 32, 0x12101), (8, 4, 8, 0x12105), (8, 4, 64, 0x12100)]
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("tile", QUAD_TILES)
+@pytest.mark.parametrize("dtype", [S.F32, S.BF16])
+def test_star_two_iterations_quad_layout_radii_random_taps(r, tile, dtype):
+    # quad-layout LDS planes (4-byte arithmetic, four rows per lane): every
+    # radius, asymmetric taps, a grid that is not a multiple of the tile (64
+    # lanes less 2r halo columns, 32 rows less 2r) in any axis
+    dims = (66, 29, 31)
+    g = rand_star(r, 23) * 0.15
+    for iters in (4, 5):  # two-iteration launches only / plus one single
+        got, plan, inner = run_star_iters(dims, r, g, dtype, tile, iters)
+        assert plan.tile[3] & (1 << 16) and plan.tile[1] == 4
+        ref, _, _ = run_star_iters(dims, r, g, dtype, (4, 2, 8, 0x221), iters)
+        assert np.array_equal(got, ref), (tile, iters)
+
+
+@pytest.mark.parametrize("dims,r", [((3, 3, 3), 3), ((5, 4, 7), 4), ((1, 1, 1), 1),
+                                    ((130, 7, 5), 2), ((56, 24, 9), 4), ((57, 25, 9), 4)])
+def test_star_two_iterations_quad_layout_tiny_and_edge_grids(dims, r):
+    # n < 2r, single cells, and exactly one tile (56 = 64 - 2r columns,
+    # 24 = 32 - 2r rows) and one past it
+    g = rand_star(r, 8) * 0.2
+    for iters in (2, 3):
+        got, _, _ = run_star_iters(dims, r, g, S.F32, (8, 4, 16, 0x12101), iters)
+        ref, _, _ = run_star_iters(dims, r, g, S.F32, (4, 2, 8, 0x221), iters)
+        assert np.array_equal(got, ref), (dims, iters)
+        assert np.array_equal(got, O.fill_periodic(got.copy(), r))
+
+
+def test_star_two_iterations_quad_layout_pitched_and_rejects():
+    dims, r = (70, 45, 37), 3
+    g = diffusion_star_exact(3, 3, 0.0815)
+    got, _, _ = run_star_iters(dims, r, g, S.F32, (8, 4, 16, 0x12101), 6, layout=(128, 32))
+    ref, _, _ = run_star_iters(dims, r, g, S.F32, ONE_TILE, 6)
+    assert np.array_equal(got, ref)
+    # FP64 (pairs only), several waves along x, one iteration per launch
+    for dtype, tile in ((S.F64, (8, 4, 16, 0x12101)), (S.F32, (4, 4, 16, 0x12201)),
+                        (S.F32, (8, 4, 16, 0x11101))):
+        with pytest.raises(S.StencilError):
+            S.LinearPlan((32, 32, 32), 3, g, dtype=dtype, variant=S.STAR3D, tile=tile)
+
+
 @pytest.mark.parametrize("dims,r", [((3, 3, 3), 3), ((5, 4, 7), 3), ((1, 1, 1), 1),
                                     ((130, 7, 5), 2)])
 @pytest.mark.parametrize("tile", [(8, 2, 32, 0x2101), (12, 2, 64, 0x2101), (12, 2, 64, 0x12101)])
