@@ -189,6 +189,12 @@ def star_run(torch, S, W, inputs, n, r, dtype, steps, warmup, tile=None, layout=
     return plan, g, total, total / max(1, nlaunch), (n_multi, n_single)
 
 
+def paper_ideal_ms(points):
+    """The paper's ideal time of one fused MHD substep (Sec. 5.4): the 8 FP64
+    fields read and written exactly once at peak HBM bandwidth."""
+    return 2 * 8 * 8 * points / (HBM_PEAK_GBS * 1e9) * 1e3
+
+
 def progress(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -360,6 +366,14 @@ def secondary(torch, S, W, inputs, args):
                                   "default_schedule": list(plan.schedule)}
                 comp[key]["tuned_ms"] = tms
                 del tp
+            if mname in ("mhd8", "mhd_full") and prec == S.PREC_F64:
+                # the paper's measure (Sec. 5.4): the final RK3 substep against
+                # the 8 fields read and written once at peak bandwidth
+                fin = timed(torch, lambda: plan.step(bufs["f_a"], bufs["f_b"], bufs["w"], 2, dt,
+                                                     w2=bufs["w2"], f64=bufs["f64"]), 10, warm=2)
+                d["final_substep"] = {"ms": fin, "paper_ideal_frac": paper_ideal_ms(pts) / fin}
+                comp[key]["final_substep_ms"] = fin
+                comp[key]["paper_ideal_frac"] = paper_ideal_ms(pts) / fin
             if mname == "mhd8" and prec == S.PREC_F64:
                 # FP64 diagnostics of the 8 fields (a7): sums, sums of squares,
                 # maxima; one read of each field (8 B per point and field)
@@ -375,6 +389,24 @@ def secondary(torch, S, W, inputs, args):
                                                 "hbm_frac": gb / (rms * 1e-3) / HBM_PEAK_GBS}
             del bufs, plan
         del f
+        # the same measure at the paper's own grid, 128^3
+        n2 = 128
+        f2, _ = inputs.fourier_fields((n2,) * 3, 1, nf=8, modes=8, kmax=8, amp=0.01)
+        for model, mname in ((S.MODEL_MHD8, "mhd8"), (S.MODEL_MHD_FULL, "mhd_full")):
+            plan = S.RkPlan(model, (n2,) * 3, S.PREC_F64,
+                            mhd=FULL_MHD if model == S.MODEL_MHD_FULL else None)
+            bufs = plan.alloc()
+            for k in range(8):
+                bufs["f_a"][k][3:n2 + 3, 3:n2 + 3, 3:n2 + 3] = torch.from_numpy(f2[k]).cuda()
+            dt2 = 0.1 * 2 * math.pi / n2
+            fin = timed(torch, lambda: plan.step(bufs["f_a"], bufs["f_b"], bufs["w"], 2, dt2,
+                                                 w2=bufs["w2"], f64=bufs["f64"]), 20, warm=3)
+            det["%s_128_f64_final_substep" % mname] = {
+                "ms": fin, "paper_ideal_frac": paper_ideal_ms(n2 ** 3) / fin}
+            comp["c2_%s_128_final" % mname] = {"ms": fin,
+                                                "paper_ideal_frac": paper_ideal_ms(n2 ** 3) / fin}
+            del bufs, plan
+        del f2
         torch.cuda.empty_cache()
     if want("precision"):
         if not args.no_precision_error:

@@ -303,11 +303,34 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
             bank.du[i][j] = U.d1[i][j];
     }
 
+    // The register (and, at the master policies' last stage, the first-stage
+    // register and the FP64 state) of the eight fields is read in batches of
+    // NB: a point reads and writes only its own cells, so the reads need not
+    // wait for the stores of earlier fields (one memory latency per batch
+    // instead of one per field). A batch of all eight is issued before phi,
+    // which hides its latency; the FP64 full model has no registers to spare
+    // for that and reads two batches of four after phi.
+    const int64_t p = g.at(x, y, z);
+    const bool last = MASTER && a.stage == 2;
+    constexpr int NB = (MODEL == MHD_FULL && sizeof(C) == 8) ? 4 : 8;
+    W wold[NB], w1v[NB];
+    double mst[NB];
+    auto read_regs = [&](int k0) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int k = k0 + j;
+            wold[j] = a.stage > 0 ? static_cast<const W *>(a.wrd[k])[p] : W(0);
+            w1v[j] = last ? static_cast<const W *>(a.w1[k])[p] : W(0);
+            mst[j] = last ? a.master[k][p] : 0.0;
+        }
+    };
+    if constexpr (NB == 8)
+        read_regs(0);
+
     // phi: the 8-field right-hand side
     C R[8];
     mhd_phi<MODEL, C>(bank, a.mhd, R);
     const C val[8] = {vl, bank.u[0], bank.u[1], bank.u[2], vs, bank.A[0], bank.A[1], bank.A[2]};
-    const int64_t p = g.at(x, y, z);
     auto io_of = [&](int k) {
         PointIO io;
         io.fout = a.fout[k];
@@ -329,12 +352,24 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
     if (sizeof(S) != 4 && images_simple(g)) {
         const PointImages im = point_images(g, x, y, z);
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            rk_update<S, W, C, MASTER, true>(io_of(k), g, p, x, y, z, R[k], val[k], &im);
+        for (int k0 = 0; k0 < 8; k0 += NB) {
+            if constexpr (NB < 8)
+                read_regs(k0);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                rk_update_pre<S, W, C, MASTER, true>(io_of(k0 + j), g, p, x, y, z, R[k0 + j],
+                                                     val[k0 + j], wold[j], w1v[j], mst[j], &im);
+        }
     } else {
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            rk_update<S, W, C, MASTER>(io_of(k), g, p, x, y, z, R[k], val[k]);
+        for (int k0 = 0; k0 < 8; k0 += NB) {
+            if constexpr (NB < 8)
+                read_regs(k0);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                rk_update_pre<S, W, C, MASTER>(io_of(k0 + j), g, p, x, y, z, R[k0 + j], val[k0 + j],
+                                               wold[j], w1v[j], mst[j]);
+        }
     }
 }
 
