@@ -681,8 +681,9 @@ def main():
     # per iteration each point's value is read once and written once
     alg_bytes = ipl * 2 * esize * points
     achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
-    kern_files = ("star3d.hpp", "star3d_t2.hpp", "star3d_t2p.hpp", "star3d_%s.hip" % args.dtype,
-                  "common.hpp", "linear_kernels.hpp", "linear_api.hip")
+    kern_files = ("star3d.hpp", "star3d_t2.hpp", "star3d_t2p.hpp", "star3d_t2q.hpp",
+                  "star3d_dpp.hpp", "star3d_%s.hip" % args.dtype, "common.hpp",
+                  "linear_kernels.hpp", "linear_api.hip")
     traffic = load_traffic("traffic_star3d_%d_%s.json" % (n, args.dtype), kern_files)
     traffic_gbs = traffic / (avg_launch_ms * 1e-3) / 1e9 if traffic else None
     copy_gbs = None if args.no_copy else copy_bandwidth(torch, S)
