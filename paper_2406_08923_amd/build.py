@@ -131,6 +131,14 @@ def build(verbose=False, jobs=None):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
+    # a kernel whose device code the host pass rejects without a message
+    # leaves its launch stub undefined: refuse such a library
+    r = subprocess.run(["nm", "-C", "--undefined-only", tmp], capture_output=True, text=True)
+    stubs = sorted({l.split("U", 1)[1].strip() for l in r.stdout.splitlines()
+                    if "__device_stub__" in l})
+    if r.returncode != 0 or stubs:
+        raise RuntimeError("kernels without a host launch stub (the host pass dropped them):\n  "
+                           + "\n  ".join(stubs or [r.stderr]))
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB, file=sys.stderr)

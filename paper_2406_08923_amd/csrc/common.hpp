@@ -100,6 +100,21 @@ __device__ __forceinline__ Buf make_buf(const void *base, uint64_t bytes)
                                                  static_cast<int>(n), BUF_DWORD3)};
 }
 
+// Buffer loads straight into LDS: lane l's SZ bytes (16 or 4) from the
+// buffer at byte offset voff land at lds + SZ * l, where lds is the same for
+// the whole wave. The size is a literal in each helper: the builtin accepts
+// no other form, and the host pass silently drops a kernel that passes one.
+__device__ __forceinline__ void buf_to_lds16(const Buf &b, void *lds, uint32_t voff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(b.r, (__attribute__((address_space(3))) void *)lds, 16,
+                                             voff, 0, 0, 0);
+}
+__device__ __forceinline__ void buf_to_lds4(const Buf &b, void *lds, uint32_t voff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(b.r, (__attribute__((address_space(3))) void *)lds, 4,
+                                             voff, 0, 0, 0);
+}
+
 // Buffer resource of one padded plane zp (0 .. nz + 2 rz - 1) of an array:
 // lane offsets within a plane stay far below 4 GiB, so kernels that address
 // the input plane by plane work for arrays of any size.

@@ -8,6 +8,8 @@
 // read; HBM/L2 see each field once per brick (times the halo overhead).
 #pragma once
 
+#include <type_traits>
+
 #include "mhd_phi.hpp"
 #include "rk_point.hpp"
 
@@ -174,7 +176,25 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
     k_rk_mhd8_lds(RkArgs a, int gx, int gy, int gz)
 {
     using B = Brick<BX, BY, BZ>;
-    __shared__ C tile[2][B::TN];
+    // Where the stored type is the arithmetic type (FP64, FP32 storage), a
+    // field's tile goes from HBM straight into LDS (buffer loads to LDS: each
+    // wave fills chunks of 64 x EPL consecutive tile cells, lane l the EPL
+    // cells at 64 EPL j + EPL l; a tile row has an even number of cells, so
+    // an FP64 pair never straddles rows), with no registers in between and no
+    // LDS stores. BF16 storage is widened on the way, through registers.
+    constexpr bool DMA = std::is_same<S, C>::value;
+    constexpr int EPL = DMA && sizeof(C) == 8 ? 2 : 1; // cells per lane and load
+    constexpr int CH = 64 * EPL;                        // cells per wave and load
+    constexpr int NCH = (B::TN + CH - 1) / CH;          // chunks per tile
+    constexpr int NW = B::NT / 64;                      // waves
+    constexpr int Q = (NCH + NW - 1) / NW;              // loads per lane and field
+    constexpr int TNP = DMA ? NCH * CH : B::TN;         // tile padded to whole chunks
+    static_assert(B::TX % 2 == 0 && B::NT % 64 == 0, "tile rows of even length, whole waves");
+    static_assert(!DMA || EPL * sizeof(C) == 16 || EPL * sizeof(C) == 4, "load size");
+    // two arrays, so the compiler's wait counting tells a load into one
+    // buffer from reads of the other
+    __shared__ C tile0[TNP];
+    __shared__ C tile1[TNP];
     // tensor form: staging of d_b v_b on the brick widened along the other two
     // axes (the largest of the three regions); the diagonal form needs none
     constexpr int G0 = BX * (BY + 6) * (BZ + 6), G1 = (BX + 6) * BY * (BZ + 6),
@@ -199,33 +219,51 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
     const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
     const bool live = x < g.nx && y < g.ny && z < g.nz;
 
-    // byte offsets (into the padded array) of this lane's tile cells; cells
-    // past the padded extent of a ragged brick are clamped onto it
-    uint32_t off[B::PER];
-#pragma unroll
-    for (int k = 0; k < B::PER; ++k) {
-        const int e = tid + k * B::NT;
-        if (e < B::TN) {
-            const int ex = e % B::TX, ey = (e / B::TX) % B::TY, ez = e / (B::TX * B::TY);
-            const int px = min(x0 - 3 + ex, g.nx + 2), py = min(y0 - 3 + ey, g.ny + 2),
-                      pz = min(z0 - 3 + ez, g.nz + 2);
-            off[k] = uint32_t(g.at(px, py, pz)) * es;
-        } else {
-            off[k] = 0;
-        }
-    }
+    // byte offsets (into the padded array) of tile cells; cells past the
+    // padded extent of a ragged brick are clamped onto it (they feed only
+    // points outside the grid; so does the second cell of a clamped pair)
+    auto cell_off = [&](int e) {
+        const int ex = e % B::TX, ey = (e / B::TX) % B::TY, ez = e / (B::TX * B::TY);
+        const int px = min(x0 - 3 + ex, g.nx + 2), py = min(y0 - 3 + ey, g.ny + 2),
+                  pz = min(z0 - 3 + ez, g.nz + 2);
+        return uint32_t(g.at(px, py, pz)) * es;
+    };
     const uint64_t bytes = uint64_t(padded_elems(g)) * es;
-    C reg[B::PER];
-    // stage field k's tile cells in registers / write them to LDS buffer buf
-#define RK_LOAD(k)                                                                           \
+    constexpr int NOFF = DMA ? Q : B::PER;
+    uint32_t off[NOFF];
+    const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
+#pragma unroll
+    for (int q = 0; q < NOFF; ++q) {
+        const int e = DMA ? EPL * ((wv + NW * q) * 64 + tid % 64) : tid + q * B::NT;
+        off[q] = e < B::TN ? cell_off(e) : 0u;
+    }
+    C reg[DMA ? 1 : B::PER];
+    // FETCH(k, dst): start loading field k's tile (into dst, or into
+    // registers); LAND(dst): write the registers to dst (register path)
+#define FETCH(k, dst)                                                                        \
     do {                                                                                     \
         const Buf fb = make_buf(a.fin[k], bytes);                                            \
-        _Pragma("unroll") for (int q = 0; q < B::PER; ++q) reg[q] = BufLd<S>::ld(fb, off[q], 0); \
+        if constexpr (DMA) {                                                                 \
+            _Pragma("unroll") for (int q = 0; q < Q; ++q) {                                  \
+                const int j = wv + NW * q;                                                   \
+                if (NW * (q + 1) <= NCH || j < NCH) { /* every wave has chunk q, or this one */ \
+                    if constexpr (EPL * sizeof(C) == 16)                                     \
+                        buf_to_lds16(fb, (dst) + j * CH, off[q]);                            \
+                    else                                                                     \
+                        buf_to_lds4(fb, (dst) + j * CH, off[q]);                             \
+                }                                                                            \
+            }                                                                                \
+        } else {                                                                             \
+            _Pragma("unroll") for (int q = 0; q < B::PER; ++q) reg[q] =                      \
+                BufLd<S>::ld(fb, off[q], 0);                                                 \
+        }                                                                                    \
     } while (0)
-#define RK_STORE(buf)                                                                        \
+#define LAND(dst)                                                                            \
     do {                                                                                     \
-        _Pragma("unroll") for (int q = 0; q < B::PER; ++q) if (tid + q * B::NT < B::TN)      \
-            tile[buf][tid + q * B::NT] = reg[q];                                             \
+        if constexpr (!DMA) {                                                                \
+            _Pragma("unroll") for (int q = 0; q < B::PER; ++q) if (tid + q * B::NT < B::TN)  \
+                (dst)[tid + q * B::NT] = reg[q];                                             \
+        }                                                                                    \
     } while (0)
 
     const C ids[3] = {C(a.inv_ds[0]), C(a.inv_ds[1]), C(a.inv_ds[2])};
@@ -234,20 +272,21 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
     C vl = 0, vs = 0, gl[3] = {}, gs[3] = {}, lapl = 0, laps = 0;
 
     // the streaming order A_x, A_y, A_z, u_x, u_y, u_z, lnrho, s; the loads
-    // of the next field are issued before the current one is differentiated
-    RK_LOAD(5);
-    RK_STORE(0);
+    // of the next field are issued before the current one is differentiated,
+    // into the buffer whose last reads the preceding barrier closed
+    FETCH(5, tile0);
+    LAND(tile0);
     __syncthreads();
-    RK_LOAD(6);
-    vec_component<C, BX, BY, BZ, MIXED>(tile[0], gbuf, tid, lx, ly, lz, 0, a.fd, ids, A);
-    RK_STORE(1);
+    FETCH(6, tile1);
+    vec_component<C, BX, BY, BZ, MIXED>(tile0, gbuf, tid, lx, ly, lz, 0, a.fd, ids, A);
+    LAND(tile1);
     __syncthreads();
-    RK_LOAD(7);
-    vec_component<C, BX, BY, BZ, MIXED>(tile[1], gbuf, tid, lx, ly, lz, 1, a.fd, ids, A);
-    RK_STORE(0);
+    FETCH(7, tile0);
+    vec_component<C, BX, BY, BZ, MIXED>(tile1, gbuf, tid, lx, ly, lz, 1, a.fd, ids, A);
+    LAND(tile0);
     __syncthreads();
-    RK_LOAD(1);
-    vec_component<C, BX, BY, BZ, MIXED>(tile[0], gbuf, tid, lx, ly, lz, 2, a.fd, ids, A);
+    FETCH(1, tile1);
+    vec_component<C, BX, BY, BZ, MIXED>(tile0, gbuf, tid, lx, ly, lz, 2, a.fd, ids, A);
     // magnetic field B = curl A, current j = grad(div A) - lap A: reduce the
     // A bank at once so its 21 values need not stay live
     C Bf[3] = {A.d1[1][2] - A.d1[2][1], A.d1[2][0] - A.d1[0][2], A.d1[0][1] - A.d1[1][0]};
@@ -258,27 +297,27 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
         pin(Bf[i]);
         pin(J[i]);
     }
-    RK_STORE(1);
+    LAND(tile1);
     __syncthreads();
-    RK_LOAD(2);
-    vec_component<C, BX, BY, BZ, MIXED>(tile[1], gbuf, tid, lx, ly, lz, 0, a.fd, ids, U);
-    RK_STORE(0);
+    FETCH(2, tile0);
+    vec_component<C, BX, BY, BZ, MIXED>(tile1, gbuf, tid, lx, ly, lz, 0, a.fd, ids, U);
+    LAND(tile0);
     __syncthreads();
-    RK_LOAD(3);
-    vec_component<C, BX, BY, BZ, MIXED>(tile[0], gbuf, tid, lx, ly, lz, 1, a.fd, ids, U);
-    RK_STORE(1);
+    FETCH(3, tile1);
+    vec_component<C, BX, BY, BZ, MIXED>(tile0, gbuf, tid, lx, ly, lz, 1, a.fd, ids, U);
+    LAND(tile1);
     __syncthreads();
-    RK_LOAD(0);
-    vec_component<C, BX, BY, BZ, MIXED>(tile[1], gbuf, tid, lx, ly, lz, 2, a.fd, ids, U);
-    RK_STORE(0);
+    FETCH(0, tile0);
+    vec_component<C, BX, BY, BZ, MIXED>(tile1, gbuf, tid, lx, ly, lz, 2, a.fd, ids, U);
+    LAND(tile0);
     __syncthreads();
-    RK_LOAD(4);
-    scalar_field<C, B::SY, B::SZ>(tile[0], c, a.fd, ids, vl, gl, lapl);
-    RK_STORE(1);
+    FETCH(4, tile1);
+    scalar_field<C, B::SY, B::SZ>(tile0, c, a.fd, ids, vl, gl, lapl);
+    LAND(tile1);
     __syncthreads();
-    scalar_field<C, B::SY, B::SZ>(tile[1], c, a.fd, ids, vs, gs, laps);
-#undef RK_LOAD
-#undef RK_STORE
+    scalar_field<C, B::SY, B::SZ>(tile1, c, a.fd, ids, vs, gs, laps);
+#undef FETCH
+#undef LAND
     if (!live)
         return;
 
