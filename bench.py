@@ -354,8 +354,8 @@ def secondary(torch, S, W, inputs, args):
                 "valu_roof": {"flops_per_point_substep": flops, "peak_tflops": peak,
                               "frac": 3 * pts / (ms * 1e-3) * flops / (peak * 1e12)}}
             key = ("c2_" if prec == S.PREC_F64 else "c3_") + "%s_256_%s" % (mname, name)
-            comp[key] = {"ms_step": ms, "pt_steps_s": d["point_steps_per_s"],
-                         "hbm_frac": d["hbm_frac"], "valu_frac": d["valu_roof"]["frac"]}
+            comp[key] = {"ms_step": ms, "hbm_frac": d["hbm_frac"],
+                         "valu_frac": d["valu_roof"]["frac"]}
             if mname in ("mhd8", "mhd_full") and prec in (S.PREC_F64, S.PREC_F32_MASTER64):
                 # the same step with the plan-time schedule search
                 tp = S.RkPlan(model, (nm, nm, nm), prec,
@@ -403,8 +403,9 @@ def secondary(torch, S, W, inputs, args):
                                                  w2=bufs["w2"], f64=bufs["f64"]), 20, warm=3)
             det["%s_128_f64_final_substep" % mname] = {
                 "ms": fin, "paper_ideal_frac": paper_ideal_ms(n2 ** 3) / fin}
-            comp["c2_%s_128_final" % mname] = {"ms": fin,
-                                                "paper_ideal_frac": paper_ideal_ms(n2 ** 3) / fin}
+            key = "c2_%s_256_f64" % mname
+            if key in comp:
+                comp[key]["final128_frac"] = paper_ideal_ms(n2 ** 3) / fin
             del bufs, plan
         del f2
         torch.cuda.empty_cache()
@@ -435,7 +436,6 @@ def secondary(torch, S, W, inputs, args):
                                     for d, v in sv["served"]["by_dtype"].items()},
                 "fifo_by_dtype": {d: [v["jobs"], v["p50_s"], v["p99_s"], v["point_steps_per_s"]]
                                   for d, v in sv["fifo_f64"]["by_dtype"].items()},
-                "served_tuned": {k: sv["served_tuned"][k] for k in keep},
                 "speedup": sv["speedup_point_steps_per_s"],
                 "p99_ratio_fifo_over_served": sv["p99_ratio_fifo_over_served"],
                 "err_vs_f64": sv["error_vs_fp64"],
