@@ -99,7 +99,7 @@ typedef struct stencil_desc {
      *             variant only: the temporal blocking the paper's discussion
      *             asks for; results are bitwise those of one-iteration
      *             launches), bit 16 (two iterations, two rows per lane,
-     *             r <= 3, at most 768 lanes) LDS planes stored y-fastest so
+     *             r <= 4, at most 768 lanes) LDS planes stored y-fastest so
      *             a lane's two rows are one 2-wide read, bit 17 (one
      *             iteration) lane-exchange z march: no LDS, x taps moved
      *             across the 64 lanes of a wave by DPP shifts (a wave yields

@@ -316,7 +316,7 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
                         continue;
                     const int w = STAR_FLAG_XCD | (sh[0] << STAR_XW_SHIFT) | (2 << STAR_T_SHIFT);
                     c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz, w});
-                    if (sh[2] == 2 && p->lin.reff <= 3 && 64 * sh[0] * sh[1] <= 768)
+                    if (sh[2] == 2 && p->lin.reff <= 4 && 64 * sh[0] * sh[1] <= 768)
                         c.push_back({STENCIL_VARIANT_STAR3D, sh[1], sh[2], lz, w | STAR_PAIRS_BIT});
                     if (sh[2] == 4 && p->lin.dtype != STENCIL_F64 && sh[0] == 1 &&
                         64 * sh[1] <= 768)
@@ -405,12 +405,14 @@ TuneChoice default_choice(const stencil_plan_s *p)
                 p->lin.g.ndim == 1 ? 1 : 4, 0, 0};
     }
     // periodic stars: two iterations per launch, the lane grids that measured
-    // fastest at 512^3 (64 x 24 for FP64, with pair-layout LDS planes up to
-    // r = 3; 64 x 32 with four rows per lane for the narrower types)
+    // fastest at 512^3 (64 x 24 with pair-layout LDS planes for FP64; 64 x 32
+    // with four rows per lane for the narrower types, 64 planes per workgroup
+    // from r = 3 on, 32 below)
     if (p->lin.is_star && p->lin.bc == STENCIL_BC_PERIODIC) {
         const bool f64 = p->lin.dtype == STENCIL_F64;
-        const int pairs = f64 && p->lin.reff <= 3 ? STAR_PAIRS_BIT : 0;
-        return {STENCIL_VARIANT_STAR3D, f64 ? 12 : 8, f64 ? 2 : 4, f64 ? 64 : 32,
+        const int pairs = f64 && p->lin.reff <= 4 ? STAR_PAIRS_BIT : 0;
+        const int lz = f64 || p->lin.reff >= 3 ? 64 : 32;
+        return {STENCIL_VARIANT_STAR3D, f64 ? 12 : 8, f64 ? 2 : 4, lz,
                 STAR_FLAG_XCD | (1 << STAR_XW_SHIFT) | (2 << STAR_T_SHIFT) | pairs};
     }
     if (p->lin.is_star)
@@ -729,12 +731,12 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
                                             "launch, without the cached or pair-layout flags");
             }
             const int xwt = ((c.p3 >> STAR_XW_SHIFT) & 15) ? ((c.p3 >> STAR_XW_SHIFT) & 15) : 1;
-            const bool pair_ok = c.p1 == 2 && L.reff <= 3 && 64 * xwt * c.p0 <= 768;
+            const bool pair_ok = c.p1 == 2 && L.reff <= 4 && 64 * xwt * c.p0 <= 768;
             const bool quad_ok = c.p1 == 4 && L.dtype != STENCIL_F64 && xwt == 1 && c.p0 * 64 <= 768;
             if ((c.p3 & STAR_PAIRS_BIT) && (tb != 2 || !(pair_ok || quad_ok))) {
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "the pair layout needs two iterations per launch, two "
-                                            "rows per lane, radius <= 3 and at most 768 lanes "
+                                            "rows per lane, radius <= 4 and at most 768 lanes "
                                             "(FP32/BF16: or four rows per lane, one wave wide)");
             }
         } else if (c.variant == STENCIL_VARIANT_BOX3D && (t[0] || t[1] || t[2] || t[3])) {

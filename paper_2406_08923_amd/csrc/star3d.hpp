@@ -508,7 +508,7 @@ int launch_star3d_t2_t(const S *in, S *out, const Geo &g,
                                dim3(SH::TXW, TY), 0, s, in, out, g, cf, lz, gx, gy, gz, flags); \
     } while (0)
     if (flags & STAR_FLAG_PAIRS) {
-        if constexpr (NY == 2 && R <= 3 && 64 * XW * TY <= 768) {
+        if constexpr (NY == 2 && R <= 4 && 64 * XW * TY <= 768) {
             STAR_T2_LAUNCH(k_star3d_t2p, S, R, TY, XW);
             return check_launch("xcorr_star3d_t2 (pair layout)");
         } else if constexpr (NY == 4 && sizeof(typename Store<S>::C) == 4 && XW == 1 &&
@@ -518,7 +518,7 @@ int launch_star3d_t2_t(const S *in, S *out, const Geo &g,
         } else {
             return fail(STENCIL_EUNSUPPORTED,
                         "star3d (two iterations): the pair layout needs two rows per lane, "
-                        "radius <= 3 and at most 768 lanes (FP32/BF16: or four rows per lane "
+                        "radius <= 4 and at most 768 lanes (FP32/BF16: or four rows per lane "
                         "in a 64-lane-wide tile)");
         }
     }

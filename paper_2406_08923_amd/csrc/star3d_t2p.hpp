@@ -58,9 +58,9 @@ __device__ __forceinline__ void star3d_t2p_segment(
     // worth of loads in flight per CU at 3.6 TB/s), so the FP64 launches
     // without images take three (0.366 against 0.396 ms per iteration at
     // 512^3); with image stores or 4-byte storage the longer unrolled round
-    // spills, so those keep two (one at r = 1, three at r = 2 and 4, where
-    // PF + 1 divides the ring).
-    constexpr int PF = R == 1 ? 1 : R == 3 ? (IMG || sizeof(S) != 8 ? 2 : 3) : 3;
+    // spills, so those keep two (one at r = 1 and r = 4, where the rings of
+    // nine-point columns leave no registers for more; three at r = 2).
+    constexpr int PF = R == 1 || R == 4 ? 1 : R == 3 ? (IMG || sizeof(S) != 8 ? 2 : 3) : 3;
     constexpr int NR = 2 * R + 1 + PF, NH = PF + 1;
     constexpr int U = lcm_int(NR, NH); // steps per unrolled round: whole turns of both rings
     constexpr int NP = (R + 1) / 2; // y-tap pairs on each side of the own pair

@@ -317,7 +317,7 @@ def test_star_two_iterations_radius_4_four_rows(dtype):
         assert np.array_equal(got, ref), iters
 
 
-@pytest.mark.parametrize("r", [1, 2, 3])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
 @pytest.mark.parametrize("tile", [(12, 2, 16, 0x12101), (8, 2, 16, 0x12105)])
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_star_two_iterations_pair_layout_radii_random_taps(r, tile, dtype):
@@ -424,10 +424,10 @@ def test_star_pair_layout_rejects_other_shapes():
                  (8, 2, 32, 0x12201)):
         with pytest.raises(S.StencilError):
             S.LinearPlan((32, 32, 32), 3, g3, variant=S.STAR3D, tile=tile)
-    # radius 4
-    g4 = rand_star(4, 5) * 0.1
+    # radius 5 (padding 5): beyond the star kernels
+    g5 = rand_star(5, 5) * 0.1
     with pytest.raises(S.StencilError):
-        S.LinearPlan((32, 32, 32), 4, g4, variant=S.STAR3D, tile=(8, 2, 32, 0x12101))
+        S.LinearPlan((32, 32, 32), 5, g5, variant=S.STAR3D, tile=(8, 2, 32, 0x12101))
 
 
 # ---------------------------------------------------------------------------
