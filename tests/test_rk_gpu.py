@@ -124,6 +124,23 @@ def test_mhd8_lds_and_cached_banks_agree_in_mixed_precision(prec):
         assert relerr(outs[1][k], outs[0][k]) <= tol, (prec, k)
 
 
+@pytest.mark.parametrize("n", [(3, 3, 3), (5, 4, 7), (17, 9, 33)])
+@pytest.mark.parametrize("block", [(32, 4, 4), (16, 8, 4)])
+@pytest.mark.parametrize("prec", [S.PREC_F32_MASTER64, S.PREC_BF16_MASTER64])
+def test_mhd8_lds_bricks_mixed_precision_on_tiny_and_ragged_grids(prec, block, n):
+    # FP32 storage fills its tiles with 4-byte buffer loads straight into LDS,
+    # BF16 through registers: bricks larger than the grid and ragged in every
+    # axis, against the cached bank (same arithmetic type)
+    ds = ds_of(n)
+    dt = 0.05 * min(ds)
+    f = mhd_fields(n, 5, kmax=1)
+    _, ref = run_policy(n, prec, f, 2, dt, nu=NU, eta=ETA, cs2=CS2, variant=S.RK_CACHED)
+    _, got = run_policy(n, prec, f, 2, dt, nu=NU, eta=ETA, cs2=CS2, variant=S.RK_LDS, block=block)
+    tol = 1e-4 if prec == S.PREC_BF16_MASTER64 else 1e-5
+    for k in range(8):
+        assert relerr(got[k], ref[k]) <= tol, (prec, block, n, k)
+
+
 def test_mhd8_three_steps_f64_run():
     n = (33, 26, 21)
     ds = ds_of(n)
