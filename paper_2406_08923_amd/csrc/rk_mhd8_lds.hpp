@@ -3,9 +3,10 @@
 // output points (one per lane) and streams the eight fields, one at a time,
 // through a double-buffered LDS tile of the brick plus its radius-3 halo
 // (Sec. 4.1's shared-memory strategy applied to the Eq. 8 bank). The next
-// field's tile is in flight in registers while the current one is
-// differentiated, so a field costs one barrier. Every derivative tap is an LDS
-// read; HBM/L2 see each field once per brick (times the halo overhead).
+// field's tile is in flight (straight into the other LDS buffer, or through
+// registers for BF16 storage) while the current one is differentiated, so a
+// field costs one barrier. Every derivative tap is an LDS read; HBM/L2 see
+// each field once per brick (times the halo overhead).
 #pragma once
 
 #include <type_traits>
