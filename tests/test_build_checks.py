@@ -3,7 +3,8 @@ schedule (no GPU needed).
 
 * Every kernel allowed to use scratch memory names GPU tests that exist, and
   (when a build report is present) every listed kernel is one the build made
-  that does use scratch.
+  that does use scratch; the built library defines every kernel launch stub
+  it references.
 * The register-ring march of the two-iteration star keeps the f0 window, the
   f1 window and the x/y halo planes in rings of registers addressed by
   compile-time slot numbers. A model of that schedule (slot formulas of the
@@ -11,10 +12,12 @@ schedule (no GPU needed).
   the plane it wants and that no load overwrites a slot still to be read, for
   radii 1-4 and the prefetch depths the kernel derives from them. The slot
   formulas do not involve the workgroup shape, so this covers every lane
-  count.
+  count. The same replay covers the pair-layout march (rounds of whole turns
+  of both rings) and the quad-layout march with their own prefetch depths.
 """
 import ast
 import json
+import math
 import os
 
 import numpy as np
@@ -72,6 +75,19 @@ def test_parse_resources_reads_hipcc_remarks():
     assert r["_Z3barPd"]["ScratchSize [bytes/lane]"] == "0"
 
 
+def test_library_has_no_undefined_launch_stubs():
+    # the host pass can drop a kernel whose device code it rejects without a
+    # message, leaving its launch stub undefined until the first launch
+    import shutil
+    import subprocess
+    lib = os.path.join(PKG, "libstencil.so")
+    if not os.path.exists(lib) or not shutil.which("nm"):
+        pytest.skip("library not built or nm missing")
+    r = subprocess.run(["nm", "-C", "--undefined-only", lib], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert [l for l in r.stdout.splitlines() if "__device_stub__" in l] == []
+
+
 # ---------------------------------------------------------------------------
 # register-ring schedule of the two-iteration star
 # ---------------------------------------------------------------------------
@@ -81,10 +97,12 @@ def ring_pf(R):
     return {1: 1, 2: 3, 3: 2, 4: 3}[R]
 
 
-def replay_ring_march(R, PF, z0, z1):
-    """Replay the ring march over one z chunk [z0, z1): returns a list of
-    problems (empty when every read finds its plane)."""
+def replay_ring_march(R, PF, z0, z1, U=None):
+    """Replay the ring march over one z chunk [z0, z1), unrolled in rounds
+    of U steps (default: the ring length): returns a list of problems (empty
+    when every read finds its plane)."""
     NR, NH = 2 * R + 1 + PF, PF + 1
+    U = U or NR
     zs, ze = z0 - R, z1 + R
     ring = [None] * NR       # f0 plane held by each slot
     r1 = [None] * NR         # f1 plane held by each slot
@@ -98,7 +116,7 @@ def replay_ring_march(R, PF, z0, z1):
     f1 = lambda q, k: (q - 1 + k + 2 * NR) % NR
     zb = zs
     while zb <= ze:
-        for q in range(NR):
+        for q in range(U):
             zA = zb + q
             if zA > ze:
                 break
@@ -124,7 +142,7 @@ def replay_ring_march(R, PF, z0, z1):
                 if ring[f0(q, k)] != zA + k:
                     bad.append(("f0 window", zA + k, ring[f0(q, k)]))
             r1[f0(q, 0)] = zA
-        zb += NR
+        zb += U
     return bad
 
 
@@ -134,6 +152,43 @@ def test_ring_schedule_reads_the_planes_it_wants(R, chunk):
     PF = ring_pf(R)
     assert (2 * R) % (PF + 1) == 0
     assert replay_ring_march(R, PF, *chunk) == []
+
+
+def pair_pf(R, img, es):
+    """Prefetch depth of the pair-layout march (FP64 without images: three
+    planes at r = 2 and 3; one at r = 1 and 4; two with images or 4-byte
+    storage at r = 3)."""
+    if R in (1, 4):
+        return 1
+    if R == 3:
+        return 2 if img or es != 8 else 3
+    return 3
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 4])
+@pytest.mark.parametrize("img,es", [(False, 8), (True, 8), (False, 4)])
+@pytest.mark.parametrize("chunk", [(0, 1), (0, 5), (64, 128), (3, 40), (10, 11 + 37)])
+def test_pair_layout_schedule_reads_the_planes_it_wants(R, img, es, chunk):
+    # the pair-layout march unrolls whole turns of both rings: lcm(NR, PF + 1)
+    PF = pair_pf(R, img, es)
+    NR, NH = 2 * R + 1 + PF, PF + 1
+    U = NR * NH // math.gcd(NR, NH)
+    assert replay_ring_march(R, PF, *chunk, U=U) == []
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 4])
+@pytest.mark.parametrize("chunk", [(0, 1), (0, 5), (64, 128), (3, 40), (10, 11 + 37)])
+def test_quad_layout_schedule_reads_the_planes_it_wants(R, chunk):
+    # the quad-layout march unrolls by the ring length; PF + 1 divides it
+    PF = 1 if R == 1 else 2 if R == 3 else 3
+    assert (2 * R + 1 + PF) % (PF + 1) == 0
+    assert replay_ring_march(R, PF, *chunk) == []
+
+
+def test_ring_schedule_model_catches_a_wrong_round_length():
+    # a round that is not a whole number of turns of the halo ring breaks the
+    # compile-time halo slots at r = 3 with three planes in flight
+    assert replay_ring_march(3, 3, 0, 40, U=10) != []
 
 
 def test_ring_schedule_model_catches_a_wrong_prefetch_depth():
