@@ -79,10 +79,12 @@ template <typename C> struct VecAcc {
 // Tensor form (MIX_TENSOR): the mixed derivatives d_a d_b v_b (a != b) are
 // taken separably: g = d_b v_b (unit spacing) is evaluated once per cell of
 // the brick widened by 3 along both other axes and staged in LDS (gb), then
-// d_a g is read from there: about 15 LDS accesses per point for the pair
-// instead of 72. The region writes and reads are separated by a barrier every
-// lane reaches. Diagonal form (MIX_DIAG): 12 tile reads per mixed
-// derivative, no staging and no barrier (gb unused).
+// d_a g is read from there (mixed_from_stage): about 15 LDS accesses per
+// point for the pair instead of 72. The caller reads the staged values after
+// the next barrier it passes anyway (the next field's), with the staging
+// buffers alternating between components, so the staging costs no barrier of
+// its own. Diagonal form (MIX_DIAG): 12 tile reads per mixed derivative,
+// taken here, no staging (gb unused).
 template <typename C, int BX, int BY, int BZ, int MIXED>
 __device__ __forceinline__ void vec_component(const C *t, C *gb, int tid, int lx, int ly, int lz,
                                               int b, const FdWeights &w, const C *ids,
@@ -129,7 +131,16 @@ __device__ __forceinline__ void vec_component(const C *t, C *gb, int tid, int lx
         gb[e] = C(w.w1[0]) * (t[ce + sb] - t[ce - sb]) + C(w.w1[1]) * (t[ce + 2 * sb] - t[ce - 2 * sb]) +
                 C(w.w1[2]) * (t[ce + 3 * sb] - t[ce - 3 * sb]);
     }
-    __syncthreads();
+}
+
+// Tensor form: the two mixed derivatives d_a d_b v_b (a != b) of component b
+// from its staged d_b v_b (a barrier separates the staging from this).
+template <typename C, int BX, int BY, int BZ>
+__device__ __forceinline__ void mixed_from_stage(const C *gb, int lx, int ly, int lz, int b,
+                                                 const FdWeights &w, const C *ids, VecAcc<C> &v)
+{
+    const int RX = b == 0 ? BX : BX + 6, RY = b == 1 ? BY : BY + 6;
+    const int ox = b == 0 ? 3 : 0, oy = b == 1 ? 3 : 0, oz = b == 2 ? 3 : 0; // tile offset
     // this lane's point in the region, and the region strides
     const int cg = (lx + 3 - ox) + RX * ((ly + 3 - oy) + RY * (lz + 3 - oz));
     const int rs[3] = {1, RX, RX * RY};
@@ -202,7 +213,8 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
                   G2 = (BX + 6) * (BY + 6) * BZ;
     constexpr int GT = G0 > G1 ? (G0 > G2 ? G0 : G2) : (G1 > G2 ? G1 : G2);
     constexpr int GN = MIXED == MIX_TENSOR ? GT : 1;
-    __shared__ C gbuf[GN];
+    __shared__ C gbuf0[GN];
+    __shared__ C gbuf1[GN];
     constexpr uint32_t es = sizeof(S);
     const Geo &g = a.g;
 
@@ -274,20 +286,34 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
 
     // the streaming order A_x, A_y, A_z, u_x, u_y, u_z, lnrho, s; the loads
     // of the next field are issued before the current one is differentiated,
-    // into the buffer whose last reads the preceding barrier closed
+    // into the buffer whose last reads the preceding barrier closed. Tensor
+    // form: component k stages into gbuf(k mod 2) and its mixed derivatives
+    // are read after the next barrier (MIXED_PREV), before component k + 1
+    // stages into the other buffer.
+    constexpr bool T = MIXED == MIX_TENSOR;
+#define MIXED_PREV(gb, b, V)                                                                 \
+    do {                                                                                     \
+        if constexpr (T)                                                                     \
+            mixed_from_stage<C, BX, BY, BZ>(gb, lx, ly, lz, b, a.fd, ids, V);                \
+    } while (0)
     FETCH(5, tile0);
     LAND(tile0);
     __syncthreads();
     FETCH(6, tile1);
-    vec_component<C, BX, BY, BZ, MIXED>(tile0, gbuf, tid, lx, ly, lz, 0, a.fd, ids, A);
+    vec_component<C, BX, BY, BZ, MIXED>(tile0, gbuf0, tid, lx, ly, lz, 0, a.fd, ids, A);
     LAND(tile1);
     __syncthreads();
+    MIXED_PREV(gbuf0, 0, A);
     FETCH(7, tile0);
-    vec_component<C, BX, BY, BZ, MIXED>(tile1, gbuf, tid, lx, ly, lz, 1, a.fd, ids, A);
+    vec_component<C, BX, BY, BZ, MIXED>(tile1, gbuf1, tid, lx, ly, lz, 1, a.fd, ids, A);
     LAND(tile0);
     __syncthreads();
+    MIXED_PREV(gbuf1, 1, A);
     FETCH(1, tile1);
-    vec_component<C, BX, BY, BZ, MIXED>(tile0, gbuf, tid, lx, ly, lz, 2, a.fd, ids, A);
+    vec_component<C, BX, BY, BZ, MIXED>(tile0, gbuf0, tid, lx, ly, lz, 2, a.fd, ids, A);
+    LAND(tile1);
+    __syncthreads();
+    MIXED_PREV(gbuf0, 2, A);
     // magnetic field B = curl A, current j = grad(div A) - lap A: reduce the
     // A bank at once so its 21 values need not stay live
     C Bf[3] = {A.d1[1][2] - A.d1[2][1], A.d1[2][0] - A.d1[0][2], A.d1[0][1] - A.d1[1][0]};
@@ -298,25 +324,27 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
         pin(Bf[i]);
         pin(J[i]);
     }
-    LAND(tile1);
-    __syncthreads();
     FETCH(2, tile0);
-    vec_component<C, BX, BY, BZ, MIXED>(tile1, gbuf, tid, lx, ly, lz, 0, a.fd, ids, U);
+    vec_component<C, BX, BY, BZ, MIXED>(tile1, gbuf1, tid, lx, ly, lz, 0, a.fd, ids, U);
     LAND(tile0);
     __syncthreads();
+    MIXED_PREV(gbuf1, 0, U);
     FETCH(3, tile1);
-    vec_component<C, BX, BY, BZ, MIXED>(tile0, gbuf, tid, lx, ly, lz, 1, a.fd, ids, U);
+    vec_component<C, BX, BY, BZ, MIXED>(tile0, gbuf0, tid, lx, ly, lz, 1, a.fd, ids, U);
     LAND(tile1);
     __syncthreads();
+    MIXED_PREV(gbuf0, 1, U);
     FETCH(0, tile0);
-    vec_component<C, BX, BY, BZ, MIXED>(tile1, gbuf, tid, lx, ly, lz, 2, a.fd, ids, U);
+    vec_component<C, BX, BY, BZ, MIXED>(tile1, gbuf1, tid, lx, ly, lz, 2, a.fd, ids, U);
     LAND(tile0);
     __syncthreads();
+    MIXED_PREV(gbuf1, 2, U);
     FETCH(4, tile1);
     scalar_field<C, B::SY, B::SZ>(tile0, c, a.fd, ids, vl, gl, lapl);
     LAND(tile1);
     __syncthreads();
     scalar_field<C, B::SY, B::SZ>(tile1, c, a.fd, ids, vs, gs, laps);
+#undef MIXED_PREV
 #undef FETCH
 #undef LAND
     if (!live)
