@@ -343,6 +343,31 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
     scalar_field<C, B::SY, B::SZ>(tile0, c, a.fd, ids, vl, gl, lapl);
     LAND(tile1);
     __syncthreads();
+    // The register (and, at the master policies' last stage, the first-stage
+    // register and the FP64 state) of the eight fields is read in batches of
+    // NB: a point reads and writes only its own cells, so the reads need not
+    // wait for the stores of earlier fields (one memory latency per batch
+    // instead of one per field). A batch of all eight is issued by the lanes
+    // inside the grid before the last field's derivatives, whose LDS work
+    // hides its latency; the FP64 full model has no registers to spare for
+    // that and reads two batches of four after phi.
+    const int64_t p = g.at(x, y, z);
+    const bool last = MASTER && a.stage == 2;
+    constexpr int NB = (MODEL == MHD_FULL && sizeof(C) == 8) ? 4 : 8;
+    W wold[NB], w1v[NB];
+    double mst[NB];
+    auto read_regs = [&](int k0) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int k = k0 + j;
+            wold[j] = a.stage > 0 ? static_cast<const W *>(a.wrd[k])[p] : W(0);
+            w1v[j] = last ? static_cast<const W *>(a.w1[k])[p] : W(0);
+            mst[j] = last ? a.master[k][p] : 0.0;
+        }
+    };
+    if constexpr (NB == 8)
+        if (live)
+            read_regs(0);
     scalar_field<C, B::SY, B::SZ>(tile1, c, a.fd, ids, vs, gs, laps);
 #undef MIXED_PREV
 #undef FETCH
@@ -371,29 +396,6 @@ __global__ void __launch_bounds__(BX *BY *BZ, (OCC > 0 ? OCC : 1))
             bank.du[i][j] = U.d1[i][j];
     }
 
-    // The register (and, at the master policies' last stage, the first-stage
-    // register and the FP64 state) of the eight fields is read in batches of
-    // NB: a point reads and writes only its own cells, so the reads need not
-    // wait for the stores of earlier fields (one memory latency per batch
-    // instead of one per field). A batch of all eight is issued before phi,
-    // which hides its latency; the FP64 full model has no registers to spare
-    // for that and reads two batches of four after phi.
-    const int64_t p = g.at(x, y, z);
-    const bool last = MASTER && a.stage == 2;
-    constexpr int NB = (MODEL == MHD_FULL && sizeof(C) == 8) ? 4 : 8;
-    W wold[NB], w1v[NB];
-    double mst[NB];
-    auto read_regs = [&](int k0) {
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int k = k0 + j;
-            wold[j] = a.stage > 0 ? static_cast<const W *>(a.wrd[k])[p] : W(0);
-            w1v[j] = last ? static_cast<const W *>(a.w1[k])[p] : W(0);
-            mst[j] = last ? a.master[k][p] : 0.0;
-        }
-    };
-    if constexpr (NB == 8)
-        read_regs(0);
 
     // phi: the 8-field right-hand side
     C R[8];
