@@ -314,6 +314,10 @@ def secondary(torch, S, W, inputs, args):
         comp["f3_box27_512"] = {"f64_ms": b["f64"]["ms_per_launch"], "f64_frac": b["f64"]["hbm_frac"],
                                 "f64_gather_ms": b["f64_gather"]["ms_per_launch"],
                                 "f32_ms": b["f32"]["ms_per_launch"]}
+        det["box_r2_r3_512"] = dense_box_r(torch, S, inputs, args.n)
+        b = det["box_r2_r3_512"]
+        comp["f3_box_r23_512"] = {k: [b[k]["ms_per_launch"], b[k]["valu_frac"]]
+                                  for k in ("r2_f64", "r3_f64", "r2_f32", "r2_f64_gather")}
     if want("mhd"):
         progress("fused 8-field steps")
         # fused 8-field RK3 step, 256^3
@@ -492,6 +496,41 @@ def dense_box(torch, S, inputs, n):
                      "hbm_frac": 2 * es * n ** 3 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "variant": p.variant, "tile": list(p.tile)}
         del a, b, p
+    return out
+
+
+def dense_box_r(torch, S, inputs, n, radii=(2, 3)):
+    """Dense boxes of radius 2 and 3 (all 125 / 343 taps nonzero, seeded
+    coefficients with sum |g| = 1) on the n^3 field, one periodic application
+    per launch (halo refresh included): the default BOX3D LDS march in FP64
+    and FP32 and, at radius 2, the gather kernel it replaces. (2R+1)^3
+    multiply-adds per point, so the bound is the vector FMA rate: valu_frac =
+    2 (2R+1)^3 n^3 flops per launch over the vector peak of the type."""
+    import numpy as np
+    dims = (n, n, n)
+    x = torch.from_numpy(inputs.uniform_field(dims, 1)).cuda()
+    out = {}
+    for r in radii:
+        K = 2 * r + 1
+        g = np.random.default_rng(r).uniform(0.2, 1.0, (K, K, K)) * \
+            np.random.default_rng(r + 10).choice([-1.0, 1.0], (K, K, K))
+        g /= np.abs(g).sum()
+        runs = [("f64", S.F64, S.VARIANT_AUTO)]
+        if r == 2:
+            runs += [("f32", S.F32, S.VARIANT_AUTO), ("f64_gather", S.F64, S.GENERIC)]
+        for name, dtype, variant in runs:
+            p = S.LinearPlan(dims, r, g, dtype=dtype, variant=variant)
+            a = p.empty(0.0)
+            p.padded(a)[r:n + r, r:n + r, r:n + r] = x.to(a.dtype)
+            b = p.empty(0.0)
+            p.halo(a)
+            ms = timed(torch, lambda: p.apply(a, b, 1, halo_valid=True), 5, warm=1)
+            peak = VALU_PEAK_TFLOPS["f64" if dtype == S.F64 else "f32"]
+            out["r%d_%s" % (r, name)] = {
+                "ms_per_launch": ms, "updates_per_s": n ** 3 / (ms * 1e-3),
+                "valu_frac": 2 * K ** 3 * n ** 3 / (ms * 1e-3) / 1e12 / peak,
+                "variant": p.variant, "tile": list(p.tile)}
+            del a, b, p
     return out
 
 

@@ -57,10 +57,13 @@ typedef enum { STENCIL_BC_PERIODIC = 0, STENCIL_BC_USER_HALO = 1 } stencil_bc;
  *            LDS, z taps from a per-lane register window marching along z.
  *  LINE1D  : 1-D stencils: block working set staged in LDS, several outputs
  *            per lane.
- *  BOX3D   : 3-D stencils with all 27 taps of the radius-1 box nonzero: z
- *            march reading each plane once, x neighbours moved across lanes
- *            (DPP), partial sums of the three output planes a plane feeds in
- *            registers. */
+ *  BOX3D   : 3-D stencils with all (2R+1)^3 taps of their radius-R box
+ *            nonzero, R = 1..4 (the multiply-add-bound regime of Sec. 5.2):
+ *            a z march reading each plane once that keeps in registers the
+ *            partial sums of the 2R + 1 output planes a plane feeds. R = 1:
+ *            x neighbours moved across lanes (DPP), taps in scalar
+ *            registers; R = 2..4: the halo'd plane staged in LDS, several
+ *            adjacent outputs per lane, taps read from LDS. */
 #define STENCIL_VARIANT_AUTO (-1)
 #define STENCIL_VARIANT_GENERIC 0
 #define STENCIL_VARIANT_STAR3D 1
@@ -114,10 +117,13 @@ typedef struct stencil_desc {
      *             (1,8,2) (1,16,1) (1,16,2) (1,12,2) (2,8,2) (1,8,4), the
      *             lane grid 64*width x lanes*rows yielding (64*width - 2r) x
      *             (lanes*rows - 2r) outputs per tile
-     *   BOX3D  : {waves per workgroup 4 or 8, rows per lane 1 or 2, z
-     *             planes per workgroup, flags: bit 0 XCD-aware order, bits
+     *   BOX3D  : R = 1: {waves per workgroup 4 or 8, rows per lane 1 or 2,
+     *             z planes per workgroup, flags: bit 0 XCD-aware order, bits
      *             4..7 planes in flight 1 or 3 (0 and 2 mean 1)}; a wave
-     *             yields 62 columns
+     *             yields 62 columns. R = 2..4: {waves per workgroup 4,
+     *             outputs per lane along x 4 or 8, z planes per workgroup,
+     *             flags: bit 0 XCD-aware order}; a wave yields 64 columns of
+     *             (outputs per lane) rows
      *   GENERIC: {block x, block y} (a multiple of 64 lanes, at most 1024)
      *   LINE1D : {outputs per lane: 1, 2, 4 or 8, iterations fused per
      *             launch T (0/1 = none; T > 1 periodic only: the block

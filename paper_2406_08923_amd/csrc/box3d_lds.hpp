@@ -1,0 +1,240 @@
+// box3d_lds.hpp -- dense 3-D box cross-correlation of radius R = 2 .. 4 (Eq. 3
+// with every tap of the (2R+1)^3 box nonzero: 125, 343 or 729 multiply-adds
+// per point), the regime where the taps, not HBM, bound the pass. The inputs
+// are served from LDS (the shared-memory strategy of Sec. 4.1).
+//
+// A workgroup owns a 64 x (TY*E) block of output columns over lz z planes and
+// marches z one input plane at a time: the halo'd input plane, (64 + 2R) x
+// (TY*E + 2R) cells, is staged in LDS, and the next plane's loads are in
+// flight in registers while the current one is used. Lane (lx, ly) of wave w
+// owns the E adjacent outputs x0 + E*lx .. x0 + E*lx + E - 1 of row
+// y0 + E*w + ly and keeps per output a register ring of 2R + 1 partial sums:
+// input plane p feeds output planes p - R .. p + R (with z tap p - z_out), so
+// per row offset dy a lane reads E + 2R inputs from LDS once and uses them for
+// (2R+1) x (2R+1) x E multiply-adds. After plane p the output plane p - R is
+// complete and stored, and the ring moves by one. The (2R+1)^2 coefficients
+// of one dy are read from LDS as wave-uniform vector loads (scalar registers
+// cannot hold 125 .. 729 taps next to the loop state). LDS rows are padded by
+// two cells after every E cells, so the vector reads of the lanes of a row
+// fall on distinct banks.
+//
+// Per output the taps are summed by input plane (z offset -R .. R), then by y
+// offset, then by x offset, a fixed order the FP64 tolerance covers. The
+// kernel stores the interior only: with (2R+1)^3 multiply-adds per point a
+// separate periodic halo pass costs far less than the image stores' registers
+// would inside the march.
+#pragma once
+
+#include "linear_kernels.hpp"
+
+namespace stn {
+
+template <typename C> struct LdsPair;
+template <> struct LdsPair<double> {
+    typedef double T __attribute__((ext_vector_type(2)));
+};
+template <> struct LdsPair<float> {
+    typedef float T __attribute__((ext_vector_type(2)));
+};
+
+// Lane grid and LDS layout. E outputs per lane along x, so a wave is
+// 64 / E lanes wide (64 columns) and E rows tall.
+template <int R, int E, int TY> struct BoxLdsShape {
+    static constexpr int K = 2 * R + 1;
+    static constexpr int NT = 64 * TY;
+    static constexpr int LX = 64 / E;
+    static constexpr int TX = 64, TYR = TY * E;              // outputs per plane
+    static constexpr int LW = TX + 2 * R, LH = TYR + 2 * R;  // staged cells
+    static constexpr int PW = (LW + E - 1) / E * (E + 2);    // padded row (cells)
+    static constexpr int PLANE = PW * LH;
+    static constexpr int NLD = (LW * LH + NT - 1) / NT;      // staged cells per lane
+    static constexpr bool LAST_FULL = LW * LH % NT == 0;
+    static constexpr int KP = K + 1;                         // coefficient row (even)
+    static constexpr int CB = K * KP;                        // coefficients of one dy
+    static __host__ __device__ constexpr int phys(int col) { return col + 2 * (col / E); }
+};
+
+template <typename S, int R, int E, int TY, bool BIG>
+__global__ void __launch_bounds__(64 * TY)
+    k_box3d_lds(const S *__restrict__ in, S *__restrict__ out, Geo g,
+                const typename Store<S>::C *__restrict__ cg, int lz, int gx, int gy, int gz,
+                int flags)
+{
+    using C = typename Store<S>::C;
+    using P2 = typename LdsPair<C>::T;
+    using SH = BoxLdsShape<R, E, TY>;
+    constexpr int K = SH::K, NT = SH::NT, NV = E + 2 * R;
+    constexpr uint32_t es = sizeof(S);
+    __shared__ __attribute__((aligned(16))) C plane[SH::PLANE];
+    __shared__ __attribute__((aligned(16))) C cl[K * SH::CB];
+
+    int lin = blockIdx.x;
+    const int total = gx * gy * gz;
+    if (flags & STAR_FLAG_XCD) lin = xcd_remap(lin, total);
+    const int bxi = lin % gx, byi = (lin / gx) % gy, bzi = lin / (gx * gy);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int lx = lane % SH::LX, ly = lane / SH::LX;
+    const int x0 = bxi * SH::TX, y0 = byi * SH::TYR;
+    const int z0 = bzi * lz, z1 = min(z0 + lz, g.nz);
+
+    // coefficients of y offset dy: cl[dy * CB + dz * KP + dx] = c[dz][dy][dx]
+    // (the dense box in z, y, x order); the pad cell of each row is zero
+    for (int i = tid; i < K * SH::CB; i += NT) {
+        const int dx = i % SH::KP, dz = (i / SH::KP) % K, dy = i / SH::CB;
+        cl[i] = dx < K ? cg[(dz * K + dy) * K + dx] : C(0);
+    }
+
+    // the cells this lane stages: byte offset within an input plane and LDS
+    // index (coordinates clamped into the padded array; clamped cells only
+    // feed outputs past the grid, which are not stored)
+    uint32_t goff[SH::NLD];
+    int ldst[SH::NLD];
+#pragma unroll
+    for (int q = 0; q < SH::NLD; ++q) {
+        const int t = min(tid + NT * q, SH::LW * SH::LH - 1);
+        const int row = t / SH::LW, col = t % SH::LW;
+        const int xs = min(x0 - R + col, g.nx + R - 1), ys = min(y0 - R + row, g.ny + R - 1);
+        goff[q] = uint32_t(xs + g.ox + g.sy * (ys + g.ry)) * es;
+        ldst[q] = row * SH::PW + SH::phys(col);
+    }
+    const bool last_ok = SH::LAST_FULL || tid + NT * (SH::NLD - 1) < SH::LW * SH::LH;
+    const PlaneSrc<S, BIG> src(in, g.sz, uint64_t(padded_elems(g)));
+    C stage[SH::NLD];
+    auto fetch = [&](int zin) {
+        const PlaneRef pb = src.plane(zin + g.rz);
+#pragma unroll
+        for (int q = 0; q < SH::NLD; ++q)
+            stage[q] = plane_ld<S>(pb, goff[q]);
+    };
+
+    C acc[K][E];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[k][e] = C(0);
+
+    const int zs = z0 - R, ze = z1 + R; // input planes zs .. ze - 1
+    const int row0 = wv * E + ly;       // LDS row of the lane's inputs at y offset -R
+    const int colp = lx * (E + 2);      // padded LDS column of its first input
+    const int y = y0 + row0, xo = x0 + lx * E;
+    fetch(zs);
+    for (int p = zs; p < ze; ++p) {
+        __syncthreads(); // every wave is done with plane p - 1
+#pragma unroll
+        for (int q = 0; q < SH::NLD; ++q)
+            if (q < SH::NLD - 1 || last_ok)
+                plane[ldst[q]] = stage[q];
+        __syncthreads();
+        if (p + 1 < ze)
+            fetch(p + 1);
+#pragma unroll 1
+        for (int dy = 0; dy < K; ++dy) {
+            const C *rp = plane + (row0 + dy) * SH::PW + colp;
+            C v[NV];
+            static_for<NV / 2>([&](auto jj) {
+                constexpr int j = 2 * jj;
+                const P2 t = *reinterpret_cast<const P2 *>(rp + SH::phys(j));
+                v[j] = t.x;
+                v[j + 1] = t.y;
+            });
+            const C *cb = cl + dy * SH::CB;
+            // slot k holds output plane p - R + k, whose z tap here is 2R - k;
+            // the coefficients of one z tap are loaded while the previous
+            // tap's multiply-adds run (a scheduling barrier per tap keeps
+            // the compiler from loading all (2R+1)^2 at once)
+            auto ldc = [&](int dz, C (&c)[SH::KP]) {
+                static_for<SH::KP / 2>([&](auto ii) {
+                    const P2 t = *reinterpret_cast<const P2 *>(cb + dz * SH::KP + 2 * ii);
+                    c[2 * ii] = t.x;
+                    c[2 * ii + 1] = t.y;
+                });
+            };
+            C cc[2][SH::KP];
+            ldc(2 * R, cc[0]);
+            static_for<K>([&](auto kk) {
+                constexpr int k = kk;
+                if constexpr (k + 1 < K)
+                    ldc(2 * R - k - 1, cc[(k + 1) & 1]);
+                static_for<K>([&](auto dx) {
+                    static_for<E>([&](auto e) {
+                        acc[k][e] = fma(cc[k & 1][dx], v[e + dx], acc[k][e]);
+                    });
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            });
+        }
+        const int zo = p - R; // complete
+        if (zo >= z0 && y < g.ny) {
+            S *o = out + g.at(xo, y, zo);
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (xo + e < g.nx)
+                    Store<S>::st(o + e, acc[0][e]);
+        }
+#pragma unroll
+        for (int k = 0; k + 1 < K; ++k)
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[k][e] = acc[k + 1][e];
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[K - 1][e] = C(0);
+    }
+}
+
+// Outputs per lane along x (E) and waves per workgroup (TY) that are built.
+#define BOX3D_LDS_SHAPES(X) X(4, 4) X(8, 4)
+
+template <typename S, int R, int E, int TY>
+int launch_box3d_lds_t(const S *in, S *out, const Geo &g, const typename Store<S>::C *cf, int lz,
+                       int flags, hipStream_t s)
+{
+    using SH = BoxLdsShape<R, E, TY>;
+    const int gx = (g.nx + SH::TX - 1) / SH::TX, gy = (g.ny + SH::TYR - 1) / SH::TYR,
+              gz = (g.nz + lz - 1) / lz;
+    const int64_t total = (int64_t)gx * gy * gz;
+    if (total > 0x7fffffff)
+        return fail(STENCIL_EUNSUPPORTED, "box3d (LDS): grid too large");
+    const bool big = uint64_t(padded_elems(g)) * sizeof(S) >= (uint64_t(1) << 32);
+    if (big)
+        hipLaunchKernelGGL((k_box3d_lds<S, R, E, TY, true>), dim3((unsigned)total), dim3(SH::NT),
+                           0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+    else
+        hipLaunchKernelGGL((k_box3d_lds<S, R, E, TY, false>), dim3((unsigned)total), dim3(SH::NT),
+                           0, s, in, out, g, cf, lz, gx, gy, gz, flags);
+    return check_launch("xcorr_box3d_lds");
+}
+
+template <typename S, int R>
+int launch_box3d_lds_r(const S *in, S *out, const Geo &g, const typename Store<S>::C *cf, int e,
+                       int ty, int lz, int flags, hipStream_t s)
+{
+#define BOX3D_LDS_CASE(E_, TY_)                                                              \
+    if (e == E_ && ty == TY_)                                                                \
+        return launch_box3d_lds_t<S, R, E_, TY_>(in, out, g, cf, lz, flags, s);
+    BOX3D_LDS_SHAPES(BOX3D_LDS_CASE)
+#undef BOX3D_LDS_CASE
+    return fail(STENCIL_EUNSUPPORTED, "box3d (LDS): %d outputs per lane with %d waves not built",
+                e, ty);
+}
+
+template <typename S>
+int launch_box3d_lds_impl(const S *in, S *out, const Geo &g, int R, const void *cf, int e, int ty,
+                          int lz, int flags, hipStream_t s)
+{
+    using C = typename Store<S>::C;
+    const C *c = static_cast<const C *>(cf);
+    if (g.ndim != 3 || R > g.r || cf == nullptr)
+        return fail(STENCIL_EINVAL, "box3d (LDS): needs a 3-D box within the padding and its "
+                                    "coefficients on the device");
+    if (lz < 1)
+        return fail(STENCIL_EINVAL, "box3d (LDS): z planes per workgroup must be >= 1");
+    switch (R) {
+    case 2: return launch_box3d_lds_r<S, 2>(in, out, g, c, e, ty, lz, flags, s);
+    case 3: return launch_box3d_lds_r<S, 3>(in, out, g, c, e, ty, lz, flags, s);
+    case 4: return launch_box3d_lds_r<S, 4>(in, out, g, c, e, ty, lz, flags, s);
+    default:
+        return fail(STENCIL_EUNSUPPORTED, "box3d (LDS): radius %d not built (2..4)", R);
+    }
+}
+
+} // namespace stn

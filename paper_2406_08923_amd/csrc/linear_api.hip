@@ -132,6 +132,15 @@ template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out
         return rc;
     }
     case STENCIL_VARIANT_BOX3D:
+        if (p->lin.reff >= 2) {
+            // radius 2..4: the LDS march writes the interior; the halo
+            // refresh follows on periodic plans
+            rc = launch_box3d_lds(in, out, p->lin.g, p->lin.reff, p->lin.d_taps, p->lin.ny,
+                                  p->lin.ty, p->lin.lz, p->lin.sflags & STAR_FLAG_XCD, s);
+            if (rc == STENCIL_OK && periodic)
+                rc = launch_halo<S>(out, p->lin.g, s);
+            return rc;
+        }
         return launch_box3d(in, out, p->lin.g, p->lin.box, p->lin.ty, p->lin.ny, p->lin.pf,
                             p->lin.lz, (p->lin.sflags & STAR_FLAG_XCD) | (periodic ? 0 : STAR_FLAG_NOFUSE),
                             s);
@@ -357,7 +366,11 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
             if (2 * g.r + 1 >= e - 1 && g.r >= 8)
                 c.push_back({STENCIL_VARIANT_LINE1D, e, 1, 1, 0});
     }
-    if (p->lin.is_dense3)
+    if (p->lin.is_dense3 && p->lin.reff >= 2)
+        for (int e : {4, 8})
+            for (int lz : {32, 64, 128})
+                c.push_back({STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD});
+    if (p->lin.is_dense3 && p->lin.reff == 1)
         for (int ty : {4, 8})
             for (int ny : {1, 2})
                 for (int lz : {8, 16, 32})
@@ -417,6 +430,8 @@ TuneChoice default_choice(const stencil_plan_s *p)
     }
     if (p->lin.is_star)
         return default_star1(p);
+    if (p->lin.is_dense3 && p->lin.reff >= 2)
+        return {STENCIL_VARIANT_BOX3D, 4, p->lin.reff <= 3 ? 8 : 4, 64, STAR_FLAG_XCD};
     if (p->lin.is_dense3)
         return {STENCIL_VARIANT_BOX3D, BOX3D_DEFAULT_TY, BOX3D_DEFAULT_NY, BOX3D_DEFAULT_LZ,
                 STAR_FLAG_XCD | (BOX3D_DEFAULT_PF << STAR_PF_SHIFT)};
@@ -609,8 +624,10 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
     L.op = d->op;
     L.is_star = star && reff >= 1 && reff <= STAR_MAX_R && L.op == STENCIL_OP_XCORR;
     L.is_box = nd == 3 && r >= 1 && r <= 3 && L.ntaps == K * K * K && L.op != STENCIL_OP_XCORR;
-    L.is_dense3 = nd == 3 && reff == 1 && L.ntaps == 27 && L.op == STENCIL_OP_XCORR;
-    if (L.is_dense3) {
+    L.is_dense3 = nd == 3 && reff >= 1 && reff <= BOX_LDS_MAX_R &&
+                  L.ntaps == (2 * reff + 1) * (2 * reff + 1) * (2 * reff + 1) &&
+                  L.op == STENCIL_OP_XCORR;
+    if (L.is_dense3 && reff == 1) {
         L.box.R = 1;
         for (int sz = -1; sz <= 1; ++sz)
             for (int sy = -1; sy <= 1; ++sy)
@@ -684,8 +701,8 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
     }
     if (d->variant == STENCIL_VARIANT_BOX3D && !L.is_dense3) {
         stencil_plan_destroy(p);
-        return fail(STENCIL_EUNSUPPORTED, "BOX3D needs a 3-D cross-correlation with all 27 taps "
-                                          "of the radius-1 box nonzero");
+        return fail(STENCIL_EUNSUPPORTED, "BOX3D needs a 3-D cross-correlation with all "
+                                          "(2R+1)^3 taps of a box of radius R = 1..4 nonzero");
     }
     if (d->variant == STENCIL_VARIANT_LINE1D && nd != 1) {
         stencil_plan_destroy(p);
@@ -747,6 +764,11 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
             if (c.p2 < 1) {
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "box3d z chunk must be >= 1");
+            }
+            if (L.reff >= 2 && (c.p0 != 4 || (c.p1 != 4 && c.p1 != 8))) {
+                stencil_plan_destroy(p);
+                return fail(STENCIL_EUNSUPPORTED, "box3d of radius 2..4: 4 waves per workgroup, "
+                                                  "4 or 8 outputs per lane");
             }
         } else if (c.variant == STENCIL_VARIANT_LINE1D) {
             if (t[0]) c.p0 = t[0];
@@ -825,7 +847,7 @@ stencil_status stencil_plan_tile(stencil_plan_t p, int tile[4])
         tile[0] = L.ty;
         tile[1] = L.ny;
         tile[2] = L.lz;
-        tile[3] = L.sflags | (L.pf << STAR_PF_SHIFT);
+        tile[3] = L.sflags | (L.reff >= 2 ? 0 : L.pf << STAR_PF_SHIFT);
     } else if (L.variant == STENCIL_VARIANT_LINE1D) {
         tile[0] = L.e1d;
         tile[1] = L.t1d;

@@ -102,6 +102,20 @@ BOX_DECL(float)
 BOX_DECL(bf16)
 #undef BOX_DECL
 
+// Dense 3-D box of radius R = 2 .. 4 (box3d_lds.hpp), one overload per
+// storage type (box3d_lds_*.hip): cf = the (2R+1)^3 coefficients on the device
+// in the arithmetic type, z, y, x order; e outputs per lane along x (4 or 8),
+// ty waves per workgroup (4), lz z planes per workgroup, flags:
+// STAR_FLAG_XCD. Writes the output interior only.
+#define BOXL_DECL(S)                                                                         \
+    int launch_box3d_lds(const S *in, S *out, const Geo &g, int R, const void *cf, int e,      \
+                         int ty, int lz, int flags, hipStream_t s);
+BOXL_DECL(double)
+BOXL_DECL(float)
+BOXL_DECL(bf16)
+#undef BOXL_DECL
+constexpr int BOX_LDS_MAX_R = 4;
+
 template <typename S>
 int launch_line1d(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs, bool fuse,
                   int e, hipStream_t s);

@@ -18,7 +18,8 @@ struct LinearPlan {
     bool is_star = false;
     int op = STENCIL_OP_XCORR; // window filters: STENCIL_OP_MAX / MIN / MEDIAN
     bool is_box = false;       // 3-D window covering the full (2r+1)^3 box
-    bool is_dense3 = false;    // 3-D cross-correlation with all 27 radius-1 box taps
+    bool is_dense3 = false;    // 3-D cross-correlation with all (2R+1)^3 taps of its
+                               // radius-R box nonzero, R = reff = 1..4
     StarCoefAny star{};
     BoxCoefAny box{};
     void *d_offs = nullptr;  // int32 tap offsets in the padded array
