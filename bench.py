@@ -255,7 +255,7 @@ def secondary(torch, S, W, inputs, args):
         err32 = star_f32_error(torch, S, W, inputs, n, r)
         d = det["star_%d_f32" % n]
         d["rel_err_vs_f64_100_iterations"] = err32
-        comp["c1_star512_f32"] = {"ups": d["updates_per_s"], "ms_it": d["ms_per_iteration"],
+        comp["c1_star512_f32"] = {"gups": d["updates_per_s"] / 1e9, "ms_it": d["ms_per_iteration"],
                                   "frac": d["hbm_frac"], "err_vs_f64_100it": err32}
         progress("radius-4 star")
         # the secondary star of the same workload: 25 points, radius 4, FP64
@@ -266,7 +266,7 @@ def secondary(torch, S, W, inputs, args):
             "iterations_per_launch": ipl,
             "hbm_frac": ipl * 16 * n ** 3 / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "avg_launch_ms": per, "tile": list(p4.tile)}
-        comp["c1_star512_f64_r4"] = {"ups": d["updates_per_s"], "ms_it": d["ms_per_iteration"],
+        comp["c1_star512_f64_r4"] = {"gups": d["updates_per_s"] / 1e9, "ms_it": d["ms_per_iteration"],
                                      "frac": d["hbm_frac"]}
         del p4
     if want("lines"):
@@ -295,7 +295,7 @@ def secondary(torch, S, W, inputs, args):
         d = det["line_2^20_f64_10iter"] = {"updates_per_s": N * 10 / (ms * 1e-3), "ms_per_call": ms,
                                            "us_per_iteration": ms * 100.0,
                                            "variant": p1.variant, "tile": list(p1.tile)}
-        comp["c0_line2^20_f64_10it"] = {"ups": d["updates_per_s"], "us_it": d["us_per_iteration"]}
+        comp["c0_line2^20_f64_10it"] = {"gups": d["updates_per_s"] / 1e9, "us_it": d["us_per_iteration"]}
         del a, b
     if want("lines"):
         progress("radius sweep")
@@ -430,19 +430,23 @@ def secondary(torch, S, W, inputs, args):
             progress("serving trace (%d jobs)" % args.serve_jobs)
             sv = serving(torch, args.serve_jobs, rates=rates, sweep_jobs=args.serve_sweep_jobs)
             det["serving"] = sv
-            keep = ("p50_s", "p99_s", "point_steps_per_s")
+            # throughput in 1e9 point-steps/s (keeps the result line short)
             comp["c4_serving"] = {
                 "jobs": args.serve_jobs, "rate_per_s": 200,
-                "served": {k: sv["served"][k] for k in keep},
-                "fifo_f64": {k: sv["fifo_f64"][k] for k in keep},
-                # per request dtype: [jobs, p50 s, p99 s, point-steps/s]
-                "served_by_dtype": {d: [v["jobs"], v["p50_s"], v["p99_s"], v["point_steps_per_s"]]
+                "served": {"p50_s": sv["served"]["p50_s"], "p99_s": sv["served"]["p99_s"],
+                           "gpts_s": sv["served"]["point_steps_per_s"] / 1e9},
+                "fifo_f64": {"p50_s": sv["fifo_f64"]["p50_s"], "p99_s": sv["fifo_f64"]["p99_s"],
+                             "gpts_s": sv["fifo_f64"]["point_steps_per_s"] / 1e9},
+                # per request dtype: [jobs, p50 s, p99 s, 1e9 point-steps/s]
+                "served_by_dtype": {d: [v["jobs"], v["p50_s"], v["p99_s"], v["point_steps_per_s"] / 1e9]
                                     for d, v in sv["served"]["by_dtype"].items()},
-                "fifo_by_dtype": {d: [v["jobs"], v["p50_s"], v["p99_s"], v["point_steps_per_s"]]
+                "fifo_by_dtype": {d: [v["jobs"], v["p50_s"], v["p99_s"], v["point_steps_per_s"] / 1e9]
                                   for d, v in sv["fifo_f64"]["by_dtype"].items()},
                 "speedup": sv["speedup_point_steps_per_s"],
                 "p99_ratio_fifo_over_served": sv["p99_ratio_fifo_over_served"],
-                "err_vs_f64": sv["error_vs_fp64"],
+                # max relative error of the f32 / f64 requests against FP64 runs
+                "err_vs_f64": {"f32": sv["error_vs_fp64"]["max_rel_err_f32_requests_vs_fp64"],
+                               "f64": sv["error_vs_fp64"]["max_rel_err_f64_requests_vs_fp64"]},
                 "sweep_p99_served_vs_fifo": {k: [v["served"]["p99_s"], v["fifo_f64"]["p99_s"]]
                                              for k, v in sv["rate_sweep"].items()}}
     return comp, det

@@ -12,11 +12,15 @@
 // input plane p feeds output planes p - R .. p + R (with z tap p - z_out), so
 // per row offset dy a lane reads E + 2R inputs from LDS once and uses them for
 // (2R+1) x (2R+1) x E multiply-adds. After plane p the output plane p - R is
-// complete and stored, and the ring moves by one. The (2R+1)^2 coefficients
-// of one dy are read from LDS as wave-uniform vector loads (scalar registers
-// cannot hold 125 .. 729 taps next to the loop state). LDS rows are padded by
-// two cells after every E cells, so the vector reads of the lanes of a row
-// fall on distinct banks.
+// complete and stored, and the ring moves by one. The coefficients are read
+// one z tap (2R + 1 values) at a time, the next tap's while the current one's
+// multiply-adds run: in FP64 through the scalar cache into scalar registers
+// (the multiply-adds take them as their scalar operand, and LDS serves only
+// the inputs), in FP32 from an LDS copy as wave-uniform vector loads (the
+// scalar loads measured slower there: they share a wait counter with the LDS
+// reads, and the shorter FP32 multiply-adds hide less of the wait). LDS rows
+// are padded by two cells after every E cells, so the vector reads of the
+// lanes of a row fall on distinct banks.
 //
 // Per output the taps are summed by input plane (z offset -R .. R), then by y
 // offset, then by x offset, a fixed order the FP64 tolerance covers. The
@@ -65,8 +69,9 @@ __global__ void __launch_bounds__(64 * TY)
     using SH = BoxLdsShape<R, E, TY>;
     constexpr int K = SH::K, NT = SH::NT, NV = E + 2 * R;
     constexpr uint32_t es = sizeof(S);
+    constexpr bool SCOEF = sizeof(C) == 8; // coefficients in scalar registers
     __shared__ __attribute__((aligned(16))) C plane[SH::PLANE];
-    __shared__ __attribute__((aligned(16))) C cl[K * SH::CB];
+    __shared__ __attribute__((aligned(16))) C cl[SCOEF ? 2 : K * SH::CB];
 
     int lin = blockIdx.x;
     const int total = gx * gy * gz;
@@ -80,10 +85,11 @@ __global__ void __launch_bounds__(64 * TY)
 
     // coefficients of y offset dy: cl[dy * CB + dz * KP + dx] = c[dz][dy][dx]
     // (the dense box in z, y, x order); the pad cell of each row is zero
-    for (int i = tid; i < K * SH::CB; i += NT) {
-        const int dx = i % SH::KP, dz = (i / SH::KP) % K, dy = i / SH::CB;
-        cl[i] = dx < K ? cg[(dz * K + dy) * K + dx] : C(0);
-    }
+    if constexpr (!SCOEF)
+        for (int i = tid; i < K * SH::CB; i += NT) {
+            const int dx = i % SH::KP, dz = (i / SH::KP) % K, dy = i / SH::CB;
+            cl[i] = dx < K ? cg[(dz * K + dy) * K + dx] : C(0);
+        }
 
     // the cells this lane stages: byte offset within an input plane and LDS
     // index (coordinates clamped into the padded array; clamped cells only
@@ -138,17 +144,22 @@ __global__ void __launch_bounds__(64 * TY)
                 v[j] = t.x;
                 v[j + 1] = t.y;
             });
-            const C *cb = cl + dy * SH::CB;
             // slot k holds output plane p - R + k, whose z tap here is 2R - k;
             // the coefficients of one z tap are loaded while the previous
             // tap's multiply-adds run (a scheduling barrier per tap keeps
             // the compiler from loading all (2R+1)^2 at once)
+            const C *cb = cl + dy * SH::CB; // LDS copy: c[dz][dy][dx] at dz KP + dx
+            const C *cq = cg + dy * K;      // device: c[dz][dy][dx] at dz K^2 + dx
             auto ldc = [&](int dz, C (&c)[SH::KP]) {
-                static_for<SH::KP / 2>([&](auto ii) {
-                    const P2 t = *reinterpret_cast<const P2 *>(cb + dz * SH::KP + 2 * ii);
-                    c[2 * ii] = t.x;
-                    c[2 * ii + 1] = t.y;
-                });
+                if constexpr (SCOEF) {
+                    static_for<K>([&](auto dx) { c[dx] = cq[dz * K * K + dx]; });
+                } else {
+                    static_for<SH::KP / 2>([&](auto ii) {
+                        const P2 t = *reinterpret_cast<const P2 *>(cb + dz * SH::KP + 2 * ii);
+                        c[2 * ii] = t.x;
+                        c[2 * ii + 1] = t.y;
+                    });
+                }
             };
             C cc[2][SH::KP];
             ldc(2 * R, cc[0]);

@@ -430,8 +430,20 @@ TuneChoice default_choice(const stencil_plan_s *p)
     }
     if (p->lin.is_star)
         return default_star1(p);
-    if (p->lin.is_dense3 && p->lin.reff >= 2)
-        return {STENCIL_VARIANT_BOX3D, 4, p->lin.reff <= 3 ? 8 : 4, 64, STAR_FLAG_XCD};
+    if (p->lin.is_dense3 && p->lin.reff >= 2) {
+        // dense boxes of radius 2..4: four outputs per lane (eight for FP32 at
+        // radius 4) and the deepest z chunk, up to 128 planes in FP64 and 64
+        // in FP32 below radius 4, that still gives 512 workgroups (two per
+        // compute unit): the fastest shapes at 512^3
+        const Geo &g = p->lin.g;
+        const bool f64 = p->lin.dtype == STENCIL_F64;
+        const int e = !f64 && p->lin.reff == 4 ? 8 : 4;
+        const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 4 * e - 1) / (4 * e));
+        int lz = f64 || p->lin.reff == 4 ? 128 : 64;
+        while (lz > 32 && cols * ((g.nz + lz - 1) / lz) < 512)
+            lz /= 2;
+        return {STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD};
+    }
     if (p->lin.is_dense3)
         return {STENCIL_VARIANT_BOX3D, BOX3D_DEFAULT_TY, BOX3D_DEFAULT_NY, BOX3D_DEFAULT_LZ,
                 STAR_FLAG_XCD | (BOX3D_DEFAULT_PF << STAR_PF_SHIFT)};

@@ -52,8 +52,8 @@ def test_dense_box_radius_2_to_4_matches_oracle(dtype, R, tile):
     plan = L.run_case(dims, R, dense_box(R, 50 + R), dtype,
                       S.BOX3D if tile else S.VARIANT_AUTO, tile=tile)
     assert plan.variant == S.BOX3D
-    if tile is None:
-        assert plan.tile == (4, 8 if R <= 3 else 4, 64, XCD)
+    if tile is None:  # small grid: the shallowest default z chunk
+        assert plan.tile == (4, 8 if dtype != S.F64 and R == 4 else 4, 32, XCD)
 
 
 @pytest.mark.parametrize("R", [2, 3, 4])
@@ -97,6 +97,15 @@ def test_dense_box_radius_2_to_4_user_halo_and_choice(R):
         S.LinearPlan(dims, R, g, variant=S.BOX3D, tile=(8, 4, 16, XCD))
     with pytest.raises(S.StencilError):
         S.LinearPlan(dims, R, g, variant=S.BOX3D, tile=(4, 2, 16, XCD))
+
+
+def test_dense_box_radius_2_to_4_default_shape_at_512():
+    # deepest z chunk that keeps 512 workgroups: 128 planes in FP64 at 512^3,
+    # 64 in FP32 below radius 4 (a plan only: no launch)
+    for R, dtype, want in ((2, S.F64, (4, 4, 128, XCD)), (3, S.F32, (4, 4, 64, XCD)),
+                           (4, S.F32, (4, 8, 128, XCD)), (3, S.F64, (4, 4, 128, XCD))):
+        assert S.LinearPlan((512, 512, 512), R, dense_box(R, 3), dtype=dtype).tile == want
+    assert S.LinearPlan((256, 256, 256), 3, dense_box(3, 3)).tile == (4, 4, 32, XCD)
 
 
 def test_dense_box_radius_5_stays_on_the_gather_kernel():

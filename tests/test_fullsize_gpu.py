@@ -264,16 +264,18 @@ def test_star_beyond_4_gib_default_plan_sampled_points():
     assert np.array_equal(got[:, :, :r], got[:, :, dims[0]:dims[0] + r])
 
 
-@pytest.mark.parametrize("kind", ["dense_box", "lane_exchange_star"])
+@pytest.mark.parametrize("kind", ["dense_box", "dense_box_r2", "lane_exchange_star"])
 def test_lane_exchange_kernels_beyond_4_gib_sampled_points(kind):
-    # the z marches without LDS address the input plane by plane above 4 GiB
-    # (a buffer resource per plane): one iteration of the dense 27-point box
-    # (default plan) and of the radius-3 star's lane-exchange march at
-    # 1024 x 1024 x 520 FP64, sampled points against the oracle
+    # the z marches address the input plane by plane above 4 GiB (a buffer
+    # resource per plane): one iteration of the dense 27-point box and of the
+    # dense radius-2 box (default plans: the lane-exchange and the LDS march)
+    # and of the radius-3 star's lane-exchange march at 1024 x 1024 x 520
+    # FP64, sampled points against the oracle
     dims = (1024, 1024, 520)
-    if kind == "dense_box":
-        r = 1
-        g = np.random.default_rng(7).uniform(0.2, 1.0, (3, 3, 3)) / 27
+    if kind.startswith("dense_box"):
+        r = 2 if kind == "dense_box_r2" else 1
+        k = 2 * r + 1
+        g = np.random.default_rng(7).uniform(0.2, 1.0, (k, k, k)) / k ** 3
         plan = S.LinearPlan(dims, r, g)
         assert plan.variant == S.BOX3D
     else:
