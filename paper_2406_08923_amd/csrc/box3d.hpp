@@ -1,10 +1,10 @@
 // box3d.hpp -- dense 3-D box cross-correlation (Eq. 3 with every tap of the
 // (2R+1)^3 box nonzero) as a z march with no LDS: the regime where the taps,
 // not HBM, set the cost ((2R+1)^3 multiply-adds per point). Built for R = 1
-// (27 taps, whose coefficients stay in scalar registers); at R = 2 and 3 the
-// 125 and 343 coefficients, with the fully unrolled tap loops the ring of
-// partial sums needs, do not fit the register files (the compiler spills to
-// scratch), so those boxes run the generic gather.
+// (27 taps, whose coefficients stay in scalar registers); at R = 2 .. 4 the
+// 125 .. 729 coefficients, with the fully unrolled tap loops this ring of
+// partial sums needs, do not fit the register files, so those boxes run the
+// LDS march of box3d_lds.hpp instead.
 //
 // A wave is one row of 64 consecutive columns: lane tx holds column
 // x0 - R + tx (the 2R edge lanes only feed their neighbours, so a wave yields

@@ -283,3 +283,115 @@ def test_box_partial_sum_ring_model_catches_a_wrong_clear():
     want = [sum(c[dz + 1] * fp[z + dz + 1] for dz in (-1, 0, 1)) for z in range(29)]
     got = replay_box_ring(f, c, 1, 0, 29, clear_shift=2)  # the slot of output p - 1
     assert not np.allclose([got[z] for z in range(29)], want)
+
+
+# ---------------------------------------------------------------------------
+# LDS march of the dense radius-2..4 boxes: every LDS and staging index it
+# forms stays inside its arrays, and the shifting ring of partial sums over
+# a staged plane gives the cross-correlation (the kernel's index arithmetic
+# replayed in Python on a small periodic grid; the expected values are the
+# oracle's)
+# ---------------------------------------------------------------------------
+
+def box_lds_shape(R, E, TY):
+    K = 2 * R + 1
+    LW, LH = 64 + 2 * R, TY * E + 2 * R
+    PW = (LW + E - 1) // E * (E + 2)
+    return dict(K=K, NT=64 * TY, LX=64 // E, TYR=TY * E, LW=LW, LH=LH, PW=PW,
+                PLANE=PW * LH, NLD=(LW * LH + 64 * TY - 1) // (64 * TY), KP=K + 1)
+
+
+def phys(col, E):
+    return col + 2 * (col // E)
+
+
+@pytest.mark.parametrize("R", [2, 3, 4])
+@pytest.mark.parametrize("E", [4, 8])
+def test_box_lds_indexes_stay_in_their_arrays(R, E):
+    sh = box_lds_shape(R, E, 4)
+    PLANE, PW, NT = sh["PLANE"], sh["PW"], sh["NT"]
+    # staged cells: each lane's LDS index (t clamped to the last cell) is in
+    # the plane, and the staged cells cover it exactly once
+    hits = np.zeros(PLANE, int)
+    for q in range(sh["NLD"]):
+        for tid in range(NT):
+            t = tid + NT * q
+            if t >= sh["LW"] * sh["LH"]:
+                continue
+            row, col = divmod(t, sh["LW"])
+            hits[row * PW + phys(col, E)] += 1
+    used = [r * PW + phys(c, E) for r in range(sh["LH"]) for c in range(sh["LW"])]
+    assert hits.max() == 1 and hits[used].min() == 1
+    # pair reads: aligned, inside the plane, and exactly the cells the lane's
+    # E outputs need (logical columns lx E .. lx E + E + 2R - 1)
+    for tid in range(NT):
+        lane, wv = tid % 64, tid // 64
+        lx, ly = lane % sh["LX"], lane // sh["LX"]
+        row0, colp = wv * E + ly, lx * (E + 2)
+        for dy in range(sh["K"]):
+            for j in range(0, E + 2 * R, 2):
+                a = (row0 + dy) * PW + colp + phys(j, E)
+                assert a % 2 == 0 and a + 1 < PLANE
+                assert a == (row0 + dy) * PW + phys(lx * E + j, E)
+                assert a + 1 == (row0 + dy) * PW + phys(lx * E + j + 1, E)
+    # coefficient pairs read up to the pad cell of each row of KP
+    assert (sh["KP"] // 2) * 2 == sh["KP"]
+
+
+def replay_box_lds(f, g, R, E, lz, dz_of_slot=lambda R, k: 2 * R - k):
+    """The kernel's march on a periodic n^3 grid, one lane grid of 64 x 4E
+    columns per tile: staged planes, a ring of 2R + 1 partial sums shifted
+    after each plane, stores of the completed plane."""
+    n = f.shape
+    K = 2 * R + 1
+    fp = np.pad(f, R, mode="wrap")  # padded[z + R, y + R, x + R]
+    out = np.full(n, np.nan)
+    TYR = 4 * E
+    for x0 in range(0, n[2], 64):
+        for y0 in range(0, n[1], TYR):
+            for z0 in range(0, n[0], lz):
+                z1 = min(z0 + lz, n[0])
+                acc = np.zeros((K, TYR, 64))
+                for p in range(z0 - R, z1 + R):
+                    # staged plane, columns x0 - R .., rows y0 - R .. (clamped
+                    # into the padded array as the kernel clamps)
+                    xs = np.minimum(np.arange(x0 - R, x0 + 64 + R), n[2] + R - 1) + R
+                    ys = np.minimum(np.arange(y0 - R, y0 + TYR + R), n[1] + R - 1) + R
+                    pl = fp[p + R][np.ix_(ys, xs)]
+                    for dy in range(K):
+                        rows = pl[dy:dy + TYR]
+                        for k in range(K):
+                            dz = dz_of_slot(R, k)
+                            for dx in range(K):
+                                acc[k] += g[dz, dy, dx] * rows[:, dx:dx + 64]
+                    zo = p - R
+                    if zo >= z0:
+                        ny, nx = min(TYR, n[1] - y0), min(64, n[2] - x0)
+                        out[zo, y0:y0 + ny, x0:x0 + nx] = acc[0][:ny, :nx]
+                    acc[:-1] = acc[1:].copy()
+                    acc[-1] = 0
+    return out
+
+
+@pytest.mark.parametrize("R,E,lz,dims", [(2, 4, 5, (11, 19, 70)), (3, 8, 4, (9, 40, 66)),
+                                         (4, 4, 16, (9, 17, 65))])
+def test_box_lds_ring_march_gives_the_correlation(R, E, lz, dims):
+    import oracle as O
+    rng = np.random.default_rng(R * 7 + E)
+    f = rng.uniform(-1, 1, dims)
+    K = 2 * R + 1
+    g = rng.uniform(-1, 1, (K, K, K))
+    a = O.pad_periodic(f, R)
+    want = O.interior(O.xcorr(a, R, g), R)
+    got = replay_box_lds(f, g, R, E, lz)
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
+
+
+def test_box_lds_ring_model_catches_a_wrong_z_tap():
+    import oracle as O
+    rng = np.random.default_rng(5)
+    f = rng.uniform(-1, 1, (7, 16, 64))
+    g = rng.uniform(-1, 1, (5, 5, 5))
+    want = O.interior(O.xcorr(O.pad_periodic(f, 2), 2, g), 2)
+    got = replay_box_lds(f, g, 2, 4, 4, dz_of_slot=lambda R, k: k)  # slot k read as tap k
+    assert not np.allclose(got, want, rtol=0, atol=1e-6)
