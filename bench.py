@@ -318,6 +318,9 @@ def secondary(torch, S, W, inputs, args):
         b = det["box_r2_r3_512"]
         comp["f3_box_r23_512"] = {k: [b[k]["ms_per_launch"], b[k]["valu_frac"]]
                                   for k in ("r2_f64", "r3_f64", "r2_f32", "r2_f64_gather")}
+        det["box2d_16384_f64"] = dense_box2d(torch, S, inputs)
+        b = det["box2d_16384_f64"]
+        comp["f3_box2d_16k_f64"] = {k: [b[k]["ms_per_launch"], b[k]["hbm_frac"]] for k in b}
     if want("mhd"):
         progress("fused 8-field steps")
         # fused 8-field RK3 step, 256^3
@@ -534,6 +537,34 @@ def dense_box_r(torch, S, inputs, n, radii=(2, 3)):
                 "ms_per_launch": ms, "updates_per_s": n ** 3 / (ms * 1e-3),
                 "valu_frac": 2 * K ** 3 * n ** 3 / (ms * 1e-3) / 1e12 / peak,
                 "variant": p.variant, "tile": list(p.tile)}
+            del a, b, p
+    return out
+
+
+def dense_box2d(torch, S, inputs, n=16384, radii=(2, 4)):
+    """Dense 2-D boxes of radius 2 and 4 (all 25 / 81 taps nonzero, seeded,
+    sum |g| = 1) on an n^2 FP64 field, one periodic application per launch
+    (halo refresh included): the default plan (the LDS march over one plane)
+    and, at radius 2, the gather kernel. 16 B per point of HBM traffic."""
+    import numpy as np
+    dims = (n, n)
+    x = torch.from_numpy(inputs.uniform_field(dims, 1)).cuda()
+    out = {}
+    for r in radii:
+        K = 2 * r + 1
+        g = np.random.default_rng(r).uniform(0.2, 1.0, (K, K))
+        g /= g.sum()
+        for name, variant in (("r%d" % r, S.VARIANT_AUTO),) + \
+                ((("r%d_gather" % r, S.GENERIC),) if r == 2 else ()):
+            p = S.LinearPlan(dims, r, g, variant=variant)
+            a = p.empty(0.0)
+            p.padded(a)[r:n + r, r:n + r] = x
+            b = p.empty(0.0)
+            p.halo(a)
+            ms = timed(torch, lambda: p.apply(a, b, 1, halo_valid=True), 5, warm=1)
+            out[name] = {"ms_per_launch": ms, "updates_per_s": n * n / (ms * 1e-3),
+                         "hbm_frac": 16 * n * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "variant": p.variant, "tile": list(p.tile)}
             del a, b, p
     return out
 

@@ -63,7 +63,9 @@ typedef enum { STENCIL_BC_PERIODIC = 0, STENCIL_BC_USER_HALO = 1 } stencil_bc;
  *            partial sums of the 2R + 1 output planes a plane feeds. R = 1:
  *            x neighbours moved across lanes (DPP), taps in scalar
  *            registers; R = 2..4: the halo'd plane staged in LDS, several
- *            adjacent outputs per lane, taps read from LDS. */
+ *            adjacent outputs per lane, taps read from LDS. Also 2-D
+ *            stencils with all (2R+1)^2 taps nonzero, R = 1..4, on arrays
+ *            below 4 GiB: the same LDS march over blocks of rows. */
 #define STENCIL_VARIANT_AUTO (-1)
 #define STENCIL_VARIANT_GENERIC 0
 #define STENCIL_VARIANT_STAR3D 1
@@ -120,7 +122,9 @@ typedef struct stencil_desc {
      *   BOX3D  : R = 1: {waves per workgroup 4 or 8, rows per lane 1 or 2,
      *             z planes per workgroup, flags: bit 0 XCD-aware order, bits
      *             4..7 planes in flight 1 or 3 (0 and 2 mean 1)}; a wave
-     *             yields 62 columns. R = 2..4: {waves per workgroup 4,
+     *             yields 62 columns. R = 2..4 (and 2-D boxes, where the third
+     *             entry counts blocks of 4 x (outputs per lane) rows per
+     *             workgroup): {waves per workgroup 4,
      *             outputs per lane along x 4 or 8, z planes per workgroup,
      *             flags: bit 0 XCD-aware order}; a wave yields 64 columns of
      *             (outputs per lane) rows

@@ -105,6 +105,16 @@ struct TuneChoice {
     int variant, p0, p1, p2, p3;
 };
 
+// Dense 2-D boxes (the LDS march over row blocks): outputs per lane. The
+// march addresses the array with 32-bit offsets, so it takes arrays below
+// 4 GiB; larger ones stay on the gather kernel.
+constexpr int BOX2D_DEFAULT_E = 8;
+
+bool box2d_fits(const stencil_plan_s *p)
+{
+    return uint64_t(padded_elems(p->lin.g)) * dtype_size(p->lin.dtype) < (uint64_t(1) << 32);
+}
+
 
 template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out, hipStream_t s)
 {
@@ -132,9 +142,9 @@ template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out
         return rc;
     }
     case STENCIL_VARIANT_BOX3D:
-        if (p->lin.reff >= 2) {
-            // radius 2..4: the LDS march writes the interior; the halo
-            // refresh follows on periodic plans
+        if (p->lin.reff >= 2 || p->lin.g.ndim == 2) {
+            // 3-D radius 2..4 and 2-D boxes: the LDS march writes the
+            // interior; the halo refresh follows on periodic plans
             rc = launch_box3d_lds(in, out, p->lin.g, p->lin.reff, p->lin.d_taps, p->lin.ny,
                                   p->lin.ty, p->lin.lz, p->lin.sflags & STAR_FLAG_XCD, s);
             if (rc == STENCIL_OK && periodic)
@@ -370,6 +380,10 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
         for (int e : {4, 8})
             for (int lz : {32, 64, 128})
                 c.push_back({STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD});
+    if (p->lin.is_dense2 && box2d_fits(p))
+        for (int e : {4, 8})
+            for (int lz : {1, 4, 16})
+                c.push_back({STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD});
     if (p->lin.is_dense3 && p->lin.reff == 1)
         for (int ty : {4, 8})
             for (int ny : {1, 2})
@@ -392,6 +406,7 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
 // FP32 (0.553 and 0.312 ms per launch, against 2.39 and 2.20 ms gathering).
 constexpr int BOX3D_DEFAULT_TY = 4, BOX3D_DEFAULT_NY = 2, BOX3D_DEFAULT_LZ = 8,
               BOX3D_DEFAULT_PF = 1;
+
 
 // One-iteration star shape that measured fastest at 512^3: 128 x 8 tiles,
 // 64 z planes per workgroup for FP64 and 32 for the narrower types.
@@ -430,6 +445,11 @@ TuneChoice default_choice(const stencil_plan_s *p)
     }
     if (p->lin.is_star)
         return default_star1(p);
+    if (p->lin.is_dense2 && box2d_fits(p))
+        // one block of rows per workgroup: with the outputs stored as whole
+        // rows, the fastest at 16384^2 up to radius 2 and within 2 % at 4
+        // (marching 16 blocks, which the search may still pick)
+        return {STENCIL_VARIANT_BOX3D, 4, BOX2D_DEFAULT_E, 1, STAR_FLAG_XCD};
     if (p->lin.is_dense3 && p->lin.reff >= 2) {
         // dense boxes of radius 2..4: four outputs per lane (eight for FP32 at
         // radius 4) and the deepest z chunk, up to 128 planes in FP64 and 64
@@ -639,6 +659,8 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
     L.is_dense3 = nd == 3 && reff >= 1 && reff <= BOX_LDS_MAX_R &&
                   L.ntaps == (2 * reff + 1) * (2 * reff + 1) * (2 * reff + 1) &&
                   L.op == STENCIL_OP_XCORR;
+    L.is_dense2 = nd == 2 && reff >= 1 && reff <= BOX_LDS_MAX_R &&
+                  L.ntaps == (2 * reff + 1) * (2 * reff + 1) && L.op == STENCIL_OP_XCORR;
     if (L.is_dense3 && reff == 1) {
         L.box.R = 1;
         for (int sz = -1; sz <= 1; ++sz)
@@ -711,10 +733,11 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
         stencil_plan_destroy(p);
         return fail(STENCIL_EUNSUPPORTED, "STAR3D needs a 3-D axis-aligned stencil of radius 1..4");
     }
-    if (d->variant == STENCIL_VARIANT_BOX3D && !L.is_dense3) {
+    if (d->variant == STENCIL_VARIANT_BOX3D && !L.is_dense3 && !(L.is_dense2 && box2d_fits(p))) {
         stencil_plan_destroy(p);
-        return fail(STENCIL_EUNSUPPORTED, "BOX3D needs a 3-D cross-correlation with all "
-                                          "(2R+1)^3 taps of a box of radius R = 1..4 nonzero");
+        return fail(STENCIL_EUNSUPPORTED, "BOX3D needs a 3-D (2-D, below 4 GiB) "
+                                          "cross-correlation with all (2R+1)^3 ((2R+1)^2) taps "
+                                          "of a box of radius R = 1..4 nonzero");
     }
     if (d->variant == STENCIL_VARIANT_LINE1D && nd != 1) {
         stencil_plan_destroy(p);
@@ -777,10 +800,10 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "box3d z chunk must be >= 1");
             }
-            if (L.reff >= 2 && (c.p0 != 4 || (c.p1 != 4 && c.p1 != 8))) {
+            if ((L.reff >= 2 || nd == 2) && (c.p0 != 4 || (c.p1 != 4 && c.p1 != 8))) {
                 stencil_plan_destroy(p);
-                return fail(STENCIL_EUNSUPPORTED, "box3d of radius 2..4: 4 waves per workgroup, "
-                                                  "4 or 8 outputs per lane");
+                return fail(STENCIL_EUNSUPPORTED, "2-D boxes and 3-D boxes of radius 2..4: 4 "
+                                                  "waves per workgroup, 4 or 8 outputs per lane");
             }
         } else if (c.variant == STENCIL_VARIANT_LINE1D) {
             if (t[0]) c.p0 = t[0];
@@ -859,7 +882,7 @@ stencil_status stencil_plan_tile(stencil_plan_t p, int tile[4])
         tile[0] = L.ty;
         tile[1] = L.ny;
         tile[2] = L.lz;
-        tile[3] = L.sflags | (L.reff >= 2 ? 0 : L.pf << STAR_PF_SHIFT);
+        tile[3] = L.sflags | (L.reff >= 2 || L.g.ndim == 2 ? 0 : L.pf << STAR_PF_SHIFT);
     } else if (L.variant == STENCIL_VARIANT_LINE1D) {
         tile[0] = L.e1d;
         tile[1] = L.t1d;

@@ -20,6 +20,7 @@ struct LinearPlan {
     bool is_box = false;       // 3-D window covering the full (2r+1)^3 box
     bool is_dense3 = false;    // 3-D cross-correlation with all (2R+1)^3 taps of its
                                // radius-R box nonzero, R = reff = 1..4
+    bool is_dense2 = false;    // the same for a 2-D cross-correlation ((2R+1)^2 taps)
     StarCoefAny star{};
     BoxCoefAny box{};
     void *d_offs = nullptr;  // int32 tap offsets in the padded array

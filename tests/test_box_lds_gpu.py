@@ -124,3 +124,69 @@ def test_dense_box_radius_2_to_4_autotune_candidates_match_the_oracle():
     for e in (4, 8):
         for lz in (32, 64, 128):
             L.run_case(dims, 3, g, S.F64, S.BOX3D, tile=(4, e, lz, XCD))
+
+
+# ---------------------------------------------------------------------------
+# dense 2-D boxes (radius 1..4): the same LDS march over one plane
+# ---------------------------------------------------------------------------
+
+def dense_box2(R, seed, r_pad=None):
+    r_pad = R if r_pad is None else r_pad
+    rng = np.random.default_rng(seed)
+    k, K = 2 * r_pad + 1, 2 * R + 1
+    taps = rng.uniform(0.2, 1.0, (K, K)) * rng.choice([-1.0, 1.0], (K, K))
+    g = np.zeros((k, k))
+    s = slice(r_pad - R, r_pad + R + 1)
+    g[s, s] = taps / np.abs(taps).sum()
+    return g
+
+
+@pytest.mark.parametrize("tile", [None, (4, 4, 1, XCD), (4, 8, 1, 0), (4, 4, 3, XCD), (4, 8, 16, 0)])
+@pytest.mark.parametrize("R", [1, 2, 3, 4])
+@pytest.mark.parametrize("dtype", L.DTYPES)
+def test_dense_2d_box_matches_oracle(dtype, R, tile):
+    # three tile columns of 64, ragged row blocks; a workgroup walks 1, 3 or
+    # 16 blocks of rows (more than the grid holds in the last case)
+    dims = (130, 77)
+    plan = L.run_case(dims, R, dense_box2(R, 20 + R), dtype,
+                      S.BOX3D if tile else S.VARIANT_AUTO, tile=tile)
+    assert plan.variant == S.BOX3D
+    if tile is None:
+        assert plan.tile == (4, 8, 1, XCD)
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 4])
+def test_dense_2d_box_tiny_edge_chained_and_wider_padding(R):
+    for dims in ((R, R), (64, R), (65, 2 * R + 1), (R, 70), (200, 33)):
+        for tile in ((4, 4, 1, XCD), (4, 8, 2, 0), (4, 4, 5, XCD)):
+            L.run_case(dims, R, dense_box2(R, 30 + R), S.F64, S.BOX3D, tile=tile)
+    L.run_case((70, 45), R, dense_box2(R, 31 + R), S.F64, S.VARIANT_AUTO, iters=3)
+    plan = L.run_case((66, 40), 6, dense_box2(R, 32 + R, r_pad=6), S.F64, S.VARIANT_AUTO)
+    assert plan.variant == S.BOX3D
+
+
+def test_dense_2d_box_user_halo_and_choice():
+    dims, R = (90, 41), 3
+    g = dense_box2(R, 40)
+    rng = np.random.default_rng(16)
+    a_host = rng.uniform(-1, 1, O.padded_shape(dims, R))
+    plan = S.LinearPlan(dims, R, g, bc=S.USER_HALO)
+    assert plan.variant == S.BOX3D
+    b = plan.empty(fill=123.0)
+    plan.apply(L.dev(a_host, S.F64), b, 1)
+    got = L.host(b)
+    L.assert_close(O.interior(got, R), O.interior(O.xcorr(a_host, R, g), R), S.F64)
+    mask = np.ones(got.shape, bool)
+    O.interior(mask, R)[...] = False
+    assert np.all(got[mask] == 123.0)
+    g2 = g.copy()
+    g2[0, R] = 0.0  # a star-free box with one tap missing: the gather kernel
+    assert S.LinearPlan(dims, R, g2).variant == S.GENERIC
+    assert S.LinearPlan(dims, 5, dense_box2(5, 41)).variant == S.GENERIC
+    # default: one block of 32 rows per workgroup
+    assert S.LinearPlan((16384, 16384), 2, dense_box2(2, 42)).tile == (4, 8, 1, XCD)
+    # 2-D arrays of 4 GiB or more stay on the gather kernel
+    big = S.LinearPlan((1 << 15, 1 << 14), 2, dense_box2(2, 43))
+    assert big.variant == S.GENERIC
+    with pytest.raises(S.StencilError):
+        S.LinearPlan((1 << 15, 1 << 14), 2, dense_box2(2, 43), variant=S.BOX3D)

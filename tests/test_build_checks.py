@@ -336,6 +336,8 @@ def test_box_lds_indexes_stay_in_their_arrays(R, E):
                 assert a + 1 == (row0 + dy) * PW + phys(lx * E + j + 1, E)
     # coefficient pairs read up to the pad cell of each row of KP
     assert (sh["KP"] // 2) * 2 == sh["KP"]
+    # a 2-D block's 64 x 4E outputs pass through the plane buffer
+    assert 64 * sh["TYR"] <= PLANE
 
 
 def replay_box_lds(f, g, R, E, lz, dz_of_slot=lambda R, k: 2 * R - k):
