@@ -425,7 +425,9 @@ def secondary(torch, S, W, inputs, args):
                 det["%s_mixed_precision_error_%d" % (mname, args.precision_n)] = res
                 comp["c3_err_%s_%d" % (mname, args.precision_n)] = {
                     "steps": res["steps"],
-                    **{k: [max(res[k][str(cp)]) for cp in res["steps"]]
+                    # max over the 8 fields, two significant digits (the
+                    # per-field values are in the detail output)
+                    **{k: [float("%.2g" % max(res[k][str(cp)])) for cp in res["steps"]]
                        for k in ("f32_master64", "bf16_master64", "f32_only", "bf16_only")}}
     if want("serving"):
         if args.serve_jobs > 0:
