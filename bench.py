@@ -486,16 +486,19 @@ def filters(torch, S, inputs, n):
 def dense_box(torch, S, inputs, n):
     """Dense 27-point box (every tap of the radius-1 box nonzero, seeded
     coefficients) on the n^3 field, one periodic application per launch: the
-    default BOX3D march in FP64 and FP32, and the gather kernel it replaces.
-    2 x storage bytes per point; 27 multiply-adds per point."""
+    default BOX3D march (LDS, outputs stored as whole rows) in FP64 and FP32,
+    the lane-exchange march (FP64) and the gather kernel. 2 x storage bytes
+    per point; 27 multiply-adds per point."""
     import numpy as np
     dims = (n, n, n)
     g = np.random.default_rng(1).uniform(0.2, 1.0, (3, 3, 3)) / 27
     x = torch.from_numpy(inputs.uniform_field(dims, 1)).cuda()
     out = {}
-    for name, dtype, es, variant in (("f64", S.F64, 8, S.VARIANT_AUTO), ("f32", S.F32, 4, S.VARIANT_AUTO),
-                                     ("f64_gather", S.F64, 8, S.GENERIC)):
-        p = S.LinearPlan(dims, 1, g, dtype=dtype, variant=variant)
+    for name, dtype, es, variant, tile in (
+            ("f64", S.F64, 8, S.VARIANT_AUTO, None), ("f32", S.F32, 4, S.VARIANT_AUTO, None),
+            ("f64_lane_exchange", S.F64, 8, S.BOX3D, (4, 2, 8, 1)),
+            ("f64_gather", S.F64, 8, S.GENERIC, None)):
+        p = S.LinearPlan(dims, 1, g, dtype=dtype, variant=variant, tile=tile)
         a = p.empty(0.0)
         p.padded(a)[1:n + 1, 1:n + 1, 1:n + 1] = x.to(a.dtype)
         b = p.empty(0.0)

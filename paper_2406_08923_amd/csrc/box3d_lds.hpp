@@ -77,6 +77,9 @@ __global__ void __launch_bounds__(64 * TY)
     constexpr int K = SH::K, KZ = SH::KZ, NT = SH::NT, NV = E + 2 * R;
     constexpr uint32_t es = sizeof(S);
     constexpr bool SCOEF = sizeof(C) == 8; // coefficients in scalar registers
+    // outputs stored as whole rows through LDS: where HBM, not the taps,
+    // bounds the pass (2-D boxes, the 27-point 3-D box)
+    constexpr bool ROWSTORE = RZ == 0 || R == 1;
     __shared__ __attribute__((aligned(16))) C plane[SH::PLANE];
     __shared__ __attribute__((aligned(16))) C cl[SCOEF ? 2 : K * SH::CB];
 
@@ -202,23 +205,26 @@ __global__ void __launch_bounds__(64 * TY)
             });
         }
         const int zo = p - RZ; // complete
-        if constexpr (RZ == 0) {
-            // 2-D: the block's outputs go out through LDS, so that each
-            // store instruction of a wave writes 64 consecutive cells of a
-            // row (a lane's E adjacent outputs would otherwise be E stores
-            // at a stride of E cells). The plane is free once every wave has
+        if constexpr (ROWSTORE) {
+            // the completed outputs go out through LDS, so that each store
+            // instruction of a wave writes 64 consecutive cells of a row (a
+            // lane's E adjacent outputs would otherwise be E stores at a
+            // stride of E cells). The plane is free once every wave has
             // summed it; the next landing waits at the loop head's barrier.
-            __syncthreads();
+            // (zo >= z0 is uniform over the workgroup.)
+            if (zo >= z0) {
+                __syncthreads();
 #pragma unroll
-            for (int e = 0; e < E; ++e)
-                plane[row0 * SH::TX + lx * E + e] = acc[0][e];
-            __syncthreads();
-            const int yb = zo * SH::TYR;
+                for (int e = 0; e < E; ++e)
+                    plane[row0 * SH::TX + lx * E + e] = acc[0][e];
+                __syncthreads();
+                const int yb = RZ == 0 ? zo * SH::TYR : y0;
 #pragma unroll
-            for (int i = tid; i < SH::TX * SH::TYR; i += NT) {
-                const int x = x0 + i % SH::TX, y = yb + i / SH::TX;
-                if (x < g.nx && y < g.ny)
-                    Store<S>::st(out + g.at(x, y, 0), plane[i]);
+                for (int i = tid; i < SH::TX * SH::TYR; i += NT) {
+                    const int x = x0 + i % SH::TX, y = yb + i / SH::TX;
+                    if (x < g.nx && y < g.ny)
+                        Store<S>::st(out + g.at(x, y, RZ == 0 ? 0 : zo), plane[i]);
+                }
             }
         } else {
             const int y = y0 + row0;
@@ -301,11 +307,12 @@ int launch_box3d_lds_impl(const S *in, S *out, const Geo &g, int R, const void *
         }
     }
     switch (R) {
+    case 1: return launch_box3d_lds_r<S, 1, 1>(in, out, g, c, e, ty, lz, flags, s);
     case 2: return launch_box3d_lds_r<S, 2, 2>(in, out, g, c, e, ty, lz, flags, s);
     case 3: return launch_box3d_lds_r<S, 3, 3>(in, out, g, c, e, ty, lz, flags, s);
     case 4: return launch_box3d_lds_r<S, 4, 4>(in, out, g, c, e, ty, lz, flags, s);
     default:
-        return fail(STENCIL_EUNSUPPORTED, "box (LDS): 3-D radius %d not built (2..4)", R);
+        return fail(STENCIL_EUNSUPPORTED, "box (LDS): 3-D radius %d not built (1..4)", R);
     }
 }
 

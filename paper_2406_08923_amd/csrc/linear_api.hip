@@ -110,6 +110,14 @@ struct TuneChoice {
 // 4 GiB; larger ones stay on the gather kernel.
 constexpr int BOX2D_DEFAULT_E = 8;
 
+// the dense box runs the LDS march (box3d_lds.hpp): every 2-D box and 3-D box
+// of radius 2..4; at radius 1 when the tile asks for 4 or 8 outputs per lane
+// (1 or 2 rows per lane select the lane-exchange march)
+bool box_lds(const LinearPlan &L)
+{
+    return L.reff >= 2 || L.g.ndim == 2 || L.ny >= 4;
+}
+
 bool box2d_fits(const stencil_plan_s *p)
 {
     return uint64_t(padded_elems(p->lin.g)) * dtype_size(p->lin.dtype) < (uint64_t(1) << 32);
@@ -142,9 +150,10 @@ template <typename S> int run_linear_once(stencil_plan_s *p, const S *in, S *out
         return rc;
     }
     case STENCIL_VARIANT_BOX3D:
-        if (p->lin.reff >= 2 || p->lin.g.ndim == 2) {
-            // 3-D radius 2..4 and 2-D boxes: the LDS march writes the
-            // interior; the halo refresh follows on periodic plans
+        if (box_lds(p->lin)) {
+            // 3-D radius 2..4, 2-D boxes, and the 27-point box with 4 or 8
+            // outputs per lane: the LDS march writes the interior; the halo
+            // refresh follows on periodic plans
             rc = launch_box3d_lds(in, out, p->lin.g, p->lin.reff, p->lin.d_taps, p->lin.ny,
                                   p->lin.ty, p->lin.lz, p->lin.sflags & STAR_FLAG_XCD, s);
             if (rc == STENCIL_OK && periodic)
@@ -385,6 +394,10 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
             for (int lz : {1, 4, 16})
                 c.push_back({STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD});
     if (p->lin.is_dense3 && p->lin.reff == 1)
+        for (int e : {4, 8})
+            for (int lz : {32, 64, 128})
+                c.push_back({STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD});
+    if (p->lin.is_dense3 && p->lin.reff == 1)
         for (int ty : {4, 8})
             for (int ny : {1, 2})
                 for (int lz : {8, 16, 32})
@@ -401,9 +414,10 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
     return c;
 }
 
-// Dense radius-1 box default shape (waves per workgroup, rows per lane, z
-// planes per workgroup, planes in flight): the fastest at 512^3 in FP64 and
-// FP32 (0.553 and 0.312 ms per launch, against 2.39 and 2.20 ms gathering).
+// Lane-exchange march shape for the dense radius-1 box (waves per workgroup,
+// rows per lane, z planes per workgroup, planes in flight): its fastest at
+// 512^3 (0.553 / 0.312 ms per launch in FP64 / FP32, against 2.39 / 2.20 ms
+// gathering); the LDS march is the default now, this one a search candidate.
 constexpr int BOX3D_DEFAULT_TY = 4, BOX3D_DEFAULT_NY = 2, BOX3D_DEFAULT_LZ = 8,
               BOX3D_DEFAULT_PF = 1;
 
@@ -450,23 +464,23 @@ TuneChoice default_choice(const stencil_plan_s *p)
         // rows, the fastest at 16384^2 up to radius 2 and within 2 % at 4
         // (marching 16 blocks, which the search may still pick)
         return {STENCIL_VARIANT_BOX3D, 4, BOX2D_DEFAULT_E, 1, STAR_FLAG_XCD};
-    if (p->lin.is_dense3 && p->lin.reff >= 2) {
-        // dense boxes of radius 2..4: four outputs per lane (eight for FP32 at
-        // radius 4) and the deepest z chunk, up to 128 planes in FP64 and 64
-        // in FP32 below radius 4, that still gives 512 workgroups (two per
-        // compute unit): the fastest shapes at 512^3
+    if (p->lin.is_dense3) {
+        // dense 3-D boxes run the LDS march: four outputs per lane (eight for
+        // FP64 at radius 1 and FP32 at radius 4) and the deepest z chunk, up
+        // to 128 planes (64 in FP32 at radius 2 and 3), that still gives 512
+        // workgroups (two per compute unit): the fastest shapes at 512^3. At
+        // radius 1 this beat the lane-exchange march by about 20 % (0.516
+        // against 0.649 ms in FP64, 0.250 against 0.313 in FP32).
         const Geo &g = p->lin.g;
         const bool f64 = p->lin.dtype == STENCIL_F64;
-        const int e = !f64 && p->lin.reff == 4 ? 8 : 4;
+        const int R = p->lin.reff;
+        const int e = (f64 && R == 1) || (!f64 && R == 4) ? 8 : 4;
         const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 4 * e - 1) / (4 * e));
-        int lz = f64 || p->lin.reff == 4 ? 128 : 64;
+        int lz = f64 || R == 1 || R == 4 ? 128 : 64;
         while (lz > 32 && cols * ((g.nz + lz - 1) / lz) < 512)
             lz /= 2;
         return {STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD};
     }
-    if (p->lin.is_dense3)
-        return {STENCIL_VARIANT_BOX3D, BOX3D_DEFAULT_TY, BOX3D_DEFAULT_NY, BOX3D_DEFAULT_LZ,
-                STAR_FLAG_XCD | (BOX3D_DEFAULT_PF << STAR_PF_SHIFT)};
     if (p->lin.g.ndim == 1)
         return {STENCIL_VARIANT_LINE1D, 4, 0, 0, 0};
     return {STENCIL_VARIANT_GENERIC, 64, 4, 0, 0};
@@ -800,7 +814,7 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "box3d z chunk must be >= 1");
             }
-            if ((L.reff >= 2 || nd == 2) && (c.p0 != 4 || (c.p1 != 4 && c.p1 != 8))) {
+            if ((L.reff >= 2 || nd == 2 || c.p1 >= 4) && (c.p0 != 4 || (c.p1 != 4 && c.p1 != 8))) {
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EUNSUPPORTED, "2-D boxes and 3-D boxes of radius 2..4: 4 "
                                                   "waves per workgroup, 4 or 8 outputs per lane");
@@ -882,7 +896,7 @@ stencil_status stencil_plan_tile(stencil_plan_t p, int tile[4])
         tile[0] = L.ty;
         tile[1] = L.ny;
         tile[2] = L.lz;
-        tile[3] = L.sflags | (L.reff >= 2 || L.g.ndim == 2 ? 0 : L.pf << STAR_PF_SHIFT);
+        tile[3] = L.sflags | (box_lds(L) ? 0 : L.pf << STAR_PF_SHIFT);
     } else if (L.variant == STENCIL_VARIANT_LINE1D) {
         tile[0] = L.e1d;
         tile[1] = L.t1d;

@@ -56,6 +56,17 @@ def test_dense_box_radius_2_to_4_matches_oracle(dtype, R, tile):
         assert plan.tile == (4, 8 if dtype != S.F64 and R == 4 else 4, 32, XCD)
 
 
+@pytest.mark.parametrize("tile", [(4, 4, 16, XCD), (4, 8, 5, 0), (4, 4, 128, XCD)])
+@pytest.mark.parametrize("dtype", L.DTYPES)
+def test_dense_27_point_box_on_the_lds_march_matches_oracle(dtype, tile):
+    # radius 1 with 4 or 8 outputs per lane: the LDS march (outputs stored as
+    # whole rows through LDS); 1 or 2 rows per lane keep the lane-exchange march
+    plan = L.run_case((130, 37, 29), 1, dense_box(1, 49), dtype, S.BOX3D, tile=tile)
+    assert plan.tile == tile
+    for dims in ((1, 1, 1), (64, 3, 2), (65, 33, 7)):
+        L.run_case(dims, 1, dense_box(1, 48), S.F64, S.BOX3D, tile=tile)
+
+
 @pytest.mark.parametrize("R", [2, 3, 4])
 def test_dense_box_radius_2_to_4_tiny_and_edge_grids(R):
     for dims in ((R, R, R), (64, R, R + 1), (65, 2 * R + 1, R), (R, 70, 9), (63, 33, 2 * R)):
@@ -106,6 +117,9 @@ def test_dense_box_radius_2_to_4_default_shape_at_512():
                            (4, S.F32, (4, 8, 128, XCD)), (3, S.F64, (4, 4, 128, XCD))):
         assert S.LinearPlan((512, 512, 512), R, dense_box(R, 3), dtype=dtype).tile == want
     assert S.LinearPlan((256, 256, 256), 3, dense_box(3, 3)).tile == (4, 4, 32, XCD)
+    # the 27-point box: eight outputs per lane in FP64, four in FP32
+    assert S.LinearPlan((512, 512, 512), 1, dense_box(1, 3)).tile == (4, 8, 128, XCD)
+    assert S.LinearPlan((512, 512, 512), 1, dense_box(1, 3), dtype=S.F32).tile == (4, 4, 128, XCD)
 
 
 def test_dense_box_radius_5_stays_on_the_gather_kernel():

@@ -276,7 +276,9 @@ def test_lane_exchange_kernels_beyond_4_gib_sampled_points(kind):
         r = 2 if kind == "dense_box_r2" else 1
         k = 2 * r + 1
         g = np.random.default_rng(7).uniform(0.2, 1.0, (k, k, k)) / k ** 3
-        plan = S.LinearPlan(dims, r, g)
+        # radius 1 on the lane-exchange march (an explicit tile: the default
+        # is the LDS march, which radius 2 covers here)
+        plan = S.LinearPlan(dims, r, g, variant=S.BOX3D, tile=(4, 2, 8, 1) if r == 1 else None)
         assert plan.variant == S.BOX3D
     else:
         r = 3
