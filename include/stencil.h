@@ -60,10 +60,10 @@ typedef enum { STENCIL_BC_PERIODIC = 0, STENCIL_BC_USER_HALO = 1 } stencil_bc;
  *  BOX3D   : 3-D stencils with all (2R+1)^3 taps of their radius-R box
  *            nonzero, R = 1..4 (the multiply-add-bound regime of Sec. 5.2):
  *            a z march reading each plane once that keeps in registers the
- *            partial sums of the 2R + 1 output planes a plane feeds. R = 1:
- *            x neighbours moved across lanes (DPP), taps in scalar
- *            registers; R = 2..4: the halo'd plane staged in LDS, several
- *            adjacent outputs per lane, taps read from LDS. Also 2-D
+ *            partial sums of the 2R + 1 output planes a plane feeds: the
+ *            halo'd plane staged in LDS, several adjacent outputs per lane
+ *            (the default, R = 1..4), or at R = 1 x neighbours moved across
+ *            lanes (DPP) with the taps in scalar registers. Also 2-D
  *            stencils with all (2R+1)^2 taps nonzero, R = 1..4, on arrays
  *            below 4 GiB: the same LDS march over blocks of rows. */
 #define STENCIL_VARIANT_AUTO (-1)
@@ -119,10 +119,11 @@ typedef struct stencil_desc {
      *             (1,8,2) (1,16,1) (1,16,2) (1,12,2) (2,8,2) (1,8,4), the
      *             lane grid 64*width x lanes*rows yielding (64*width - 2r) x
      *             (lanes*rows - 2r) outputs per tile
-     *   BOX3D  : R = 1: {waves per workgroup 4 or 8, rows per lane 1 or 2,
-     *             z planes per workgroup, flags: bit 0 XCD-aware order, bits
-     *             4..7 planes in flight 1 or 3 (0 and 2 mean 1)}; a wave
-     *             yields 62 columns. R = 2..4 (and 2-D boxes, where the third
+     *   BOX3D  : lane exchange (R = 1 only): {waves per workgroup 4 or 8,
+     *             rows per lane 1 or 2, z planes per workgroup, flags: bit 0
+     *             XCD-aware order, bits 4..7 planes in flight 1 or 3 (0 and 2
+     *             mean 1)}; a wave yields 62 columns. LDS march, R = 1..4
+     *             (and 2-D boxes, where the third
      *             entry counts blocks of 4 x (outputs per lane) rows per
      *             workgroup): {waves per workgroup 4,
      *             outputs per lane along x 4 or 8, z planes per workgroup,

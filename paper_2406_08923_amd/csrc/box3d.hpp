@@ -4,7 +4,8 @@
 // (27 taps, whose coefficients stay in scalar registers); at R = 2 .. 4 the
 // 125 .. 729 coefficients, with the fully unrolled tap loops this ring of
 // partial sums needs, do not fit the register files, so those boxes run the
-// LDS march of box3d_lds.hpp instead.
+// LDS march of box3d_lds.hpp instead, which is also the default at R = 1
+// (this march is chosen by tiles of 1 or 2 rows per lane).
 //
 // A wave is one row of 64 consecutive columns: lane tx holds column
 // x0 - R + tx (the 2R edge lanes only feed their neighbours, so a wave yields

@@ -1,7 +1,8 @@
-// box3d_lds.hpp -- dense 3-D box cross-correlation of radius R = 2 .. 4 (Eq. 3
-// with every tap of the (2R+1)^3 box nonzero: 125, 343 or 729 multiply-adds
-// per point), the regime where the taps, not HBM, bound the pass. The inputs
-// are served from LDS (the shared-memory strategy of Sec. 4.1).
+// box3d_lds.hpp -- dense 3-D box cross-correlation of radius R = 1 .. 4 (Eq. 3
+// with every tap of the (2R+1)^3 box nonzero: 27 .. 729 multiply-adds per
+// point; from radius 2 on the taps, not HBM, bound the pass), and dense 2-D
+// boxes. The inputs are served from LDS (the shared-memory strategy of
+// Sec. 4.1).
 //
 // A workgroup owns a 64 x (TY*E) block of output columns over lz z planes and
 // marches z one input plane at a time: the halo'd input plane, (64 + 2R) x
@@ -24,8 +25,9 @@
 //
 // A 2-D box (radius 1 .. 4) runs the same march with a ring of one partial
 // sum per output (RZ = 0): a workgroup walks lz row blocks of its 64-column
-// strip, staging block b + 1 while block b is summed, and writes each
-// block's outputs through LDS as whole rows.
+// strip, staging block b + 1 while block b is summed. It writes each block's
+// outputs through LDS as whole rows, and so does the 27-point 3-D box, where
+// HBM bounds the pass too.
 //
 // Per output the taps are summed by input plane (z offset -R .. R), then by y
 // offset, then by x offset, a fixed order the FP64 tolerance covers. The

@@ -469,8 +469,8 @@ TuneChoice default_choice(const stencil_plan_s *p)
         // FP64 at radius 1 and FP32 at radius 4) and the deepest z chunk, up
         // to 128 planes (64 in FP32 at radius 2 and 3), that still gives 512
         // workgroups (two per compute unit): the fastest shapes at 512^3. At
-        // radius 1 this beat the lane-exchange march by about 20 % (0.516
-        // against 0.649 ms in FP64, 0.250 against 0.313 in FP32).
+        // radius 1 this beat the lane-exchange march by 6-20 % in two
+        // sessions (FP64 0.516-0.540 against 0.577-0.649 ms).
         const Geo &g = p->lin.g;
         const bool f64 = p->lin.dtype == STENCIL_F64;
         const int R = p->lin.reff;
