@@ -397,3 +397,52 @@ def test_box_lds_ring_model_catches_a_wrong_z_tap():
     want = O.interior(O.xcorr(O.pad_periodic(f, 2), 2, g), 2)
     got = replay_box_lds(f, g, 2, 4, 4, dz_of_slot=lambda R, k: k)  # slot k read as tap k
     assert not np.allclose(got, want, rtol=0, atol=1e-6)
+
+
+def replay_box_lds_2d(f, g, R, E, lz):
+    """The 2-D form of the march (z radius 0): a workgroup walks lz blocks of
+    4E rows of its 64-column strip; each block's outputs are written by lane
+    (lx, ly) of wave w into an LDS tile at (E w + ly) * 64 + E lx + e and read
+    back as whole rows, cell i going to column x0 + i % 64, row yb + i // 64."""
+    ny, nx = f.shape
+    K = 2 * R + 1
+    TYR = 4 * E
+    fp = np.pad(f, R, mode="wrap")
+    out = np.full(f.shape, np.nan)
+    nby = (ny + TYR - 1) // TYR
+    for x0 in range(0, nx, 64):
+        for z0 in range(0, nby, lz):
+            for blk in range(z0, min(z0 + lz, nby)):
+                yb = blk * TYR
+                xs = np.minimum(np.arange(x0 - R, x0 + 64 + R), nx + R - 1) + R
+                ys = np.minimum(np.arange(yb - R, yb + TYR + R), ny + R - 1) + R
+                pl = fp[np.ix_(ys, xs)]
+                acc = np.zeros((TYR, 64))
+                for dy in range(K):
+                    for dx in range(K):
+                        acc += g[dy, dx] * pl[dy:dy + TYR, dx:dx + 64]
+                tile = np.full(64 * TYR, np.nan)
+                for w in range(4):
+                    for lane in range(64):
+                        lx, ly = lane % (64 // E), lane // (64 // E)
+                        row0 = w * E + ly
+                        for e in range(E):
+                            tile[row0 * 64 + lx * E + e] = acc[row0, lx * E + e]
+                for i in range(64 * TYR):
+                    x, y = x0 + i % 64, yb + i // 64
+                    if x < nx and y < ny:
+                        out[y, x] = tile[i]
+    return out
+
+
+@pytest.mark.parametrize("R,E,lz,dims", [(1, 8, 1, (77, 130)), (2, 4, 3, (40, 70)),
+                                         (4, 8, 16, (33, 65))])
+def test_box_lds_2d_row_march_gives_the_correlation(R, E, lz, dims):
+    import oracle as O
+    rng = np.random.default_rng(R * 11 + E)
+    f = rng.uniform(-1, 1, dims)
+    K = 2 * R + 1
+    g = rng.uniform(-1, 1, (K, K))
+    want = O.interior(O.xcorr(O.pad_periodic(f, R), R, g), R)
+    got = replay_box_lds_2d(f, g, R, E, lz)
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
