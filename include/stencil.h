@@ -58,13 +58,13 @@ typedef enum { STENCIL_BC_PERIODIC = 0, STENCIL_BC_USER_HALO = 1 } stencil_bc;
  *  LINE1D  : 1-D stencils: block working set staged in LDS, several outputs
  *            per lane.
  *  BOX3D   : 3-D stencils with all (2R+1)^3 taps of their radius-R box
- *            nonzero, R = 1..4 (the multiply-add-bound regime of Sec. 5.2):
+ *            nonzero, R = 1..8 (the multiply-add-bound regime of Sec. 5.2):
  *            a z march reading each plane once that keeps in registers the
  *            partial sums of the 2R + 1 output planes a plane feeds: the
  *            halo'd plane staged in LDS, several adjacent outputs per lane
- *            (the default, R = 1..4), or at R = 1 x neighbours moved across
+ *            (the default, R = 1..8), or at R = 1 x neighbours moved across
  *            lanes (DPP) with the taps in scalar registers. Also 2-D
- *            stencils with all (2R+1)^2 taps nonzero, R = 1..4, on arrays
+ *            stencils with all (2R+1)^2 taps nonzero, R = 1..8, on arrays
  *            below 4 GiB: the same LDS march over blocks of rows. */
 #define STENCIL_VARIANT_AUTO (-1)
 #define STENCIL_VARIANT_GENERIC 0
@@ -122,11 +122,12 @@ typedef struct stencil_desc {
      *   BOX3D  : lane exchange (R = 1 only): {waves per workgroup 4 or 8,
      *             rows per lane 1 or 2, z planes per workgroup, flags: bit 0
      *             XCD-aware order, bits 4..7 planes in flight 1 or 3 (0 and 2
-     *             mean 1)}; a wave yields 62 columns. LDS march, R = 1..4
+     *             mean 1)}; a wave yields 62 columns. LDS march, R = 1..8
      *             (and 2-D boxes, where the third
      *             entry counts blocks of 4 x (outputs per lane) rows per
      *             workgroup): {waves per workgroup 4,
-     *             outputs per lane along x 4 or 8, z planes per workgroup,
+     *             outputs per lane along x 4 or 8 (4 for 3-D R = 5..8), z
+     *             planes per workgroup,
      *             flags: bit 0 XCD-aware order}; a wave yields 64 columns of
      *             (outputs per lane) rows
      *   GENERIC: {block x, block y} (a multiple of 64 lanes, at most 1024)

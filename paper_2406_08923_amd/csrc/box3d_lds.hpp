@@ -1,7 +1,7 @@
-// box3d_lds.hpp -- dense 3-D box cross-correlation of radius R = 1 .. 4 (Eq. 3
-// with every tap of the (2R+1)^3 box nonzero: 27 .. 729 multiply-adds per
+// box3d_lds.hpp -- dense 3-D box cross-correlation of radius R = 1 .. 8 (Eq. 3
+// with every tap of the (2R+1)^3 box nonzero: 27 .. 4913 multiply-adds per
 // point; from radius 2 on the taps, not HBM, bound the pass), and dense 2-D
-// boxes. The inputs are served from LDS (the shared-memory strategy of
+// boxes of radius 1 .. 8. The inputs are served from LDS (the shared-memory strategy of
 // Sec. 4.1).
 //
 // A workgroup owns a 64 x (TY*E) block of output columns over lz z planes and
@@ -23,7 +23,7 @@
 // are padded by two cells after every E cells, so the vector reads of the
 // lanes of a row fall on distinct banks.
 //
-// A 2-D box (radius 1 .. 4) runs the same march with a ring of one partial
+// A 2-D box (radius 1 .. 8) runs the same march with a ring of one partial
 // sum per output (RZ = 0): a workgroup walks lz row blocks of its 64-column
 // strip, staging block b + 1 while block b is summed. It writes each block's
 // outputs through LDS as whole rows, and so does the 27-point 3-D box, where
@@ -276,9 +276,12 @@ template <typename S, int R, int RZ>
 int launch_box3d_lds_r(const S *in, S *out, const Geo &g, const typename Store<S>::C *cf, int e,
                        int ty, int lz, int flags, hipStream_t s)
 {
+// (3-D rings of 11 .. 17 sums at radius 5 .. 8 leave registers for 4 outputs
+// per lane only)
 #define BOX3D_LDS_CASE(E_, TY_)                                                              \
-    if (e == E_ && ty == TY_)                                                                \
-        return launch_box3d_lds_t<S, R, E_, TY_, RZ>(in, out, g, cf, lz, flags, s);
+    if constexpr (RZ < 5 || E_ == 4)                                                         \
+        if (e == E_ && ty == TY_)                                                            \
+            return launch_box3d_lds_t<S, R, E_, TY_, RZ>(in, out, g, cf, lz, flags, s);
     BOX3D_LDS_SHAPES(BOX3D_LDS_CASE)
 #undef BOX3D_LDS_CASE
     return fail(STENCIL_EUNSUPPORTED, "box3d (LDS): %d outputs per lane with %d waves not built",
@@ -304,8 +307,12 @@ int launch_box3d_lds_impl(const S *in, S *out, const Geo &g, int R, const void *
         case 2: return launch_box3d_lds_r<S, 2, 0>(in, out, g, c, e, ty, lz, flags, s);
         case 3: return launch_box3d_lds_r<S, 3, 0>(in, out, g, c, e, ty, lz, flags, s);
         case 4: return launch_box3d_lds_r<S, 4, 0>(in, out, g, c, e, ty, lz, flags, s);
+        case 5: return launch_box3d_lds_r<S, 5, 0>(in, out, g, c, e, ty, lz, flags, s);
+        case 6: return launch_box3d_lds_r<S, 6, 0>(in, out, g, c, e, ty, lz, flags, s);
+        case 7: return launch_box3d_lds_r<S, 7, 0>(in, out, g, c, e, ty, lz, flags, s);
+        case 8: return launch_box3d_lds_r<S, 8, 0>(in, out, g, c, e, ty, lz, flags, s);
         default:
-            return fail(STENCIL_EUNSUPPORTED, "box (LDS): 2-D radius %d not built (1..4)", R);
+            return fail(STENCIL_EUNSUPPORTED, "box (LDS): 2-D radius %d not built (1..8)", R);
         }
     }
     switch (R) {
@@ -313,8 +320,12 @@ int launch_box3d_lds_impl(const S *in, S *out, const Geo &g, int R, const void *
     case 2: return launch_box3d_lds_r<S, 2, 2>(in, out, g, c, e, ty, lz, flags, s);
     case 3: return launch_box3d_lds_r<S, 3, 3>(in, out, g, c, e, ty, lz, flags, s);
     case 4: return launch_box3d_lds_r<S, 4, 4>(in, out, g, c, e, ty, lz, flags, s);
+    case 5: return launch_box3d_lds_r<S, 5, 5>(in, out, g, c, e, ty, lz, flags, s);
+    case 6: return launch_box3d_lds_r<S, 6, 6>(in, out, g, c, e, ty, lz, flags, s);
+    case 7: return launch_box3d_lds_r<S, 7, 7>(in, out, g, c, e, ty, lz, flags, s);
+    case 8: return launch_box3d_lds_r<S, 8, 8>(in, out, g, c, e, ty, lz, flags, s);
     default:
-        return fail(STENCIL_EUNSUPPORTED, "box (LDS): 3-D radius %d not built (1..4)", R);
+        return fail(STENCIL_EUNSUPPORTED, "box (LDS): 3-D radius %d not built (1..8)", R);
     }
 }
 

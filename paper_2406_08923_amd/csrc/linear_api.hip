@@ -388,7 +388,8 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
     if (p->lin.is_dense3 && p->lin.reff >= 2)
         for (int e : {4, 8})
             for (int lz : {32, 64, 128})
-                c.push_back({STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD});
+                if (e == 4 || p->lin.reff <= 4)
+                    c.push_back({STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD});
     if (p->lin.is_dense2 && box2d_fits(p))
         for (int e : {4, 8})
             for (int lz : {1, 4, 16})
@@ -751,7 +752,7 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
         stencil_plan_destroy(p);
         return fail(STENCIL_EUNSUPPORTED, "BOX3D needs a 3-D (2-D, below 4 GiB) "
                                           "cross-correlation with all (2R+1)^3 ((2R+1)^2) taps "
-                                          "of a box of radius R = 1..4 nonzero");
+                                          "of a box of radius R = 1..8 nonzero");
     }
     if (d->variant == STENCIL_VARIANT_LINE1D && nd != 1) {
         stencil_plan_destroy(p);
@@ -814,10 +815,11 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "box3d z chunk must be >= 1");
             }
-            if ((L.reff >= 2 || nd == 2 || c.p1 >= 4) && (c.p0 != 4 || (c.p1 != 4 && c.p1 != 8))) {
+            if ((L.reff >= 2 || nd == 2 || c.p1 >= 4) &&
+                (c.p0 != 4 || (c.p1 != 4 && c.p1 != 8) || (nd == 3 && L.reff >= 5 && c.p1 != 4))) {
                 stencil_plan_destroy(p);
-                return fail(STENCIL_EUNSUPPORTED, "2-D boxes and 3-D boxes of radius 2..4: 4 "
-                                                  "waves per workgroup, 4 or 8 outputs per lane");
+                return fail(STENCIL_EUNSUPPORTED, "the LDS box march: 4 waves per workgroup, 4 "
+                                                  "or 8 outputs per lane (4 for 3-D radius 5..8)");
             }
         } else if (c.variant == STENCIL_VARIANT_LINE1D) {
             if (t[0]) c.p0 = t[0];

@@ -102,9 +102,10 @@ BOX_DECL(float)
 BOX_DECL(bf16)
 #undef BOX_DECL
 
-// Dense 3-D box of radius R = 2 .. 4 (box3d_lds.hpp), one overload per
-// storage type (box3d_lds_*.hip): cf = the (2R+1)^3 coefficients on the device
-// in the arithmetic type, z, y, x order; e outputs per lane along x (4 or 8),
+// Dense 3-D box of radius R = 1 .. 8, or 2-D box (box3d_lds.hpp), one overload
+// per storage type (box3d_lds_*.hip): cf = the (2R+1)^ndim coefficients on the
+// device in the arithmetic type, z, y, x order; e outputs per lane along x (4
+// or 8; 4 for 3-D boxes of radius 5 .. 8),
 // ty waves per workgroup (4), lz z planes per workgroup, flags:
 // STAR_FLAG_XCD. Writes the output interior only.
 #define BOXL_DECL(S)                                                                         \
@@ -114,7 +115,7 @@ BOXL_DECL(double)
 BOXL_DECL(float)
 BOXL_DECL(bf16)
 #undef BOXL_DECL
-constexpr int BOX_LDS_MAX_R = 4;
+constexpr int BOX_LDS_MAX_R = 8;
 
 template <typename S>
 int launch_line1d(const S *in, S *out, const Geo &g, const typename Store<S>::C *cs, bool fuse,

@@ -122,10 +122,17 @@ def test_dense_box_radius_2_to_4_default_shape_at_512():
     assert S.LinearPlan((512, 512, 512), 1, dense_box(1, 3), dtype=S.F32).tile == (4, 4, 128, XCD)
 
 
-def test_dense_box_radius_5_stays_on_the_gather_kernel():
-    dims = (24, 13, 11)
-    plan = L.run_case(dims, 5, dense_box(5, 80), S.F64, S.VARIANT_AUTO)
-    assert plan.variant == S.GENERIC
+@pytest.mark.parametrize("R", [5, 6, 7, 8])
+@pytest.mark.parametrize("dtype", [S.F64, S.F32])
+def test_dense_box_radius_5_to_8_matches_oracle(dtype, R):
+    # rings of 11 .. 17 partial sums, four outputs per lane; several z chunks
+    dims = (70, 21, 19)
+    for tile in (None, (4, 4, 7, 0)):
+        plan = L.run_case(dims, R, dense_box(R, 80 + R), dtype,
+                          S.BOX3D if tile else S.VARIANT_AUTO, tile=tile)
+        assert plan.variant == S.BOX3D
+    with pytest.raises(S.StencilError):  # eight outputs per lane are not built here
+        S.LinearPlan(dims, R, dense_box(R, 80 + R), variant=S.BOX3D, tile=(4, 8, 16, XCD))
 
 
 def test_dense_box_radius_2_to_4_autotune_candidates_match_the_oracle():
@@ -156,7 +163,7 @@ def dense_box2(R, seed, r_pad=None):
 
 
 @pytest.mark.parametrize("tile", [None, (4, 4, 1, XCD), (4, 8, 1, 0), (4, 4, 3, XCD), (4, 8, 16, 0)])
-@pytest.mark.parametrize("R", [1, 2, 3, 4])
+@pytest.mark.parametrize("R", [1, 2, 3, 4, 6, 8])
 @pytest.mark.parametrize("dtype", L.DTYPES)
 def test_dense_2d_box_matches_oracle(dtype, R, tile):
     # three tile columns of 64, ragged row blocks; a workgroup walks 1, 3 or
@@ -196,7 +203,7 @@ def test_dense_2d_box_user_halo_and_choice():
     g2 = g.copy()
     g2[0, R] = 0.0  # a star-free box with one tap missing: the gather kernel
     assert S.LinearPlan(dims, R, g2).variant == S.GENERIC
-    assert S.LinearPlan(dims, 5, dense_box2(5, 41)).variant == S.GENERIC
+    assert S.LinearPlan(dims, 8, dense_box2(8, 41)).variant == S.BOX3D
     # default: one block of 32 rows per workgroup
     assert S.LinearPlan((16384, 16384), 2, dense_box2(2, 42)).tile == (4, 8, 1, XCD)
     # 2-D arrays of 4 GiB or more stay on the gather kernel
