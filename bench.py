@@ -318,6 +318,7 @@ def secondary(torch, S, W, inputs, args):
         b = det["box_r2_r3_512"]
         comp["f3_box_r23_512"] = {k: [b[k]["ms_per_launch"], b[k]["valu_frac"]]
                                   for k in ("r2_f64", "r3_f64", "r2_f32", "r2_f64_gather")}
+        det["box_r5_r8_256"] = dense_box_r(torch, S, inputs, 256, radii=(5, 8), gather=True)
         det["box2d_16384_f64"] = dense_box2d(torch, S, inputs)
         b = det["box2d_16384_f64"]
         comp["f3_box2d_16k_f64"] = {k: [b[k]["ms_per_launch"], b[k]["hbm_frac"]] for k in b}
@@ -511,13 +512,15 @@ def dense_box(torch, S, inputs, n):
     return out
 
 
-def dense_box_r(torch, S, inputs, n, radii=(2, 3)):
+def dense_box_r(torch, S, inputs, n, radii=(2, 3), gather=False):
     """Dense boxes of radius 2 and 3 (all 125 / 343 taps nonzero, seeded
     coefficients with sum |g| = 1) on the n^3 field, one periodic application
     per launch (halo refresh included): the default BOX3D LDS march in FP64
     and FP32 and, at radius 2, the gather kernel it replaces. (2R+1)^3
     multiply-adds per point, so the bound is the vector FMA rate: valu_frac =
-    2 (2R+1)^3 n^3 flops per launch over the vector peak of the type."""
+    2 (2R+1)^3 n^3 flops per launch over the vector peak of the type. With
+    gather=True every radius also runs FP32 and the gather kernel (the
+    radius 5 and 8 boxes at 256^3)."""
     import numpy as np
     dims = (n, n, n)
     x = torch.from_numpy(inputs.uniform_field(dims, 1)).cuda()
@@ -528,7 +531,7 @@ def dense_box_r(torch, S, inputs, n, radii=(2, 3)):
             np.random.default_rng(r + 10).choice([-1.0, 1.0], (K, K, K))
         g /= np.abs(g).sum()
         runs = [("f64", S.F64, S.VARIANT_AUTO)]
-        if r == 2:
+        if r == 2 or gather:
             runs += [("f32", S.F32, S.VARIANT_AUTO), ("f64_gather", S.F64, S.GENERIC)]
         for name, dtype, variant in runs:
             p = S.LinearPlan(dims, r, g, dtype=dtype, variant=variant)
