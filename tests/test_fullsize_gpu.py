@@ -116,6 +116,31 @@ def test_star_512_default_plan_every_point(dtype):
 # 256^3 fused substep, every stage, every point
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("r", [1, 2])
+def test_dense_box_512_default_plan_every_point(r):
+    # the dense-box benchmark workloads: one periodic application of the
+    # 27-point and the radius-2 (125-point) box to the 512^3 FP64 field on
+    # the default plans (the LDS march), every interior and halo point
+    # against the oracle
+    dims, k = (512, 512, 512), 2 * r + 1
+    g = np.random.default_rng(r).uniform(0.2, 1.0, (k, k, k))
+    g /= g.sum()
+    plan = S.LinearPlan(dims, r, g)
+    assert plan.variant == S.BOX3D
+    pad = O.pad_periodic(inputs.uniform_field(dims, 1), r)
+    a = plan.empty(0.0)
+    plan.padded(a).copy_(torch.from_numpy(pad).cuda())
+    b = plan.empty(0.0)
+    res = plan.apply(a, b, 1)
+    got = host(plan.padded(res))
+    del a, b, res
+    ref = O.fill_periodic(O.xcorr(pad, r, g), r)
+    del pad
+    assert np.array_equal(got, O.fill_periodic(got.copy(), r))
+    err = relerr(got, ref)
+    assert err <= 1e-12, err
+
+
 @pytest.mark.parametrize("stage", [0, 1, 2])
 @pytest.mark.parametrize("model", [S.MODEL_MHD8, S.MODEL_MHD_FULL])
 def test_mhd_256_default_plan_every_point(model, stage):
