@@ -141,6 +141,26 @@ def test_dense_box_512_default_plan_every_point(r):
     assert err <= 1e-12, err
 
 
+def test_dense_2d_box_16384_default_plan_every_point():
+    # the 2-D dense-box benchmark workload: the radius-2 box on the 16384^2
+    # FP64 field, default plan (the LDS march over row blocks), every point
+    dims, r = (16384, 16384), 2
+    g = np.random.default_rng(r).uniform(0.2, 1.0, (5, 5))
+    g /= g.sum()
+    plan = S.LinearPlan(dims, r, g)
+    assert plan.variant == S.BOX3D
+    pad = O.pad_periodic(inputs.uniform_field(dims, 1), r)
+    a = plan.empty(0.0)
+    plan.padded(a).copy_(torch.from_numpy(pad).cuda())
+    b = plan.empty(0.0)
+    got = host(plan.padded(plan.apply(a, b, 1)))
+    del a, b
+    ref = O.fill_periodic(O.xcorr(pad, r, g), r)
+    del pad
+    assert np.array_equal(got, O.fill_periodic(got.copy(), r))
+    assert relerr(got, ref) <= 1e-12
+
+
 @pytest.mark.parametrize("stage", [0, 1, 2])
 @pytest.mark.parametrize("model", [S.MODEL_MHD8, S.MODEL_MHD_FULL])
 def test_mhd_256_default_plan_every_point(model, stage):
