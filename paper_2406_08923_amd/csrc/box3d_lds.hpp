@@ -1,8 +1,8 @@
 // box3d_lds.hpp -- dense 3-D box cross-correlation of radius R = 1 .. 8 (Eq. 3
 // with every tap of the (2R+1)^3 box nonzero: 27 .. 4913 multiply-adds per
 // point; from radius 2 on the taps, not HBM, bound the pass), and dense 2-D
-// boxes of radius 1 .. 8. The inputs are served from LDS (the shared-memory strategy of
-// Sec. 4.1).
+// boxes of radius 1 .. 8. The inputs are served from LDS (the shared-memory
+// strategy of Sec. 4.1).
 //
 // A workgroup owns a 64 x (TY*E) block of output columns over lz z planes and
 // marches z one input plane at a time: the halo'd input plane, (64 + 2R) x
@@ -12,7 +12,8 @@
 // y0 + E*w + ly and keeps per output a register ring of 2R + 1 partial sums:
 // input plane p feeds output planes p - R .. p + R (with z tap p - z_out), so
 // per row offset dy a lane reads E + 2R inputs from LDS once and uses them for
-// (2R+1) x (2R+1) x E multiply-adds. After plane p the output plane p - R is
+// (2R+1) x (2R+1) x E multiply-adds (E = 4 or 8; 4 from radius 5 on, where
+// the ring holds 11 .. 17 sums). After plane p the output plane p - R is
 // complete and stored, and the ring moves by one. The coefficients are read
 // one z tap (2R + 1 values) at a time, the next tap's while the current one's
 // multiply-adds run: in FP64 through the scalar cache into scalar registers
