@@ -62,8 +62,6 @@ template <int R, int E, int TY, int RZ = R> struct BoxLdsShape {
     static constexpr int PLANE = PW * LH;
     static constexpr int NLD = (LW * LH + NT - 1) / NT;      // staged cells per lane
     static constexpr bool LAST_FULL = LW * LH % NT == 0;
-    static constexpr int KP = K + 1;                         // coefficient row (even)
-    static constexpr int CB = KZ * KP;                       // coefficients of one dy
     static __host__ __device__ constexpr int phys(int col) { return col + 2 * (col / E); }
     static_assert(PLANE >= TX * TYR, "a 2-D block's outputs pass through the plane buffer");
 };
@@ -84,7 +82,11 @@ __global__ void __launch_bounds__(64 * TY)
     // bounds the pass (2-D boxes, the 27-point 3-D box)
     constexpr bool ROWSTORE = RZ == 0 || R == 1;
     __shared__ __attribute__((aligned(16))) C plane[SH::PLANE];
-    __shared__ __attribute__((aligned(16))) C cl[SCOEF ? 2 : K * SH::CB];
+    // LDS copy of the taps (FP32): rows of one z tap padded to four cells, so
+    // that one ds_read_b128 brings four taps
+    constexpr int KQ = (K + 3) / 4 * 4, CQ = KZ * KQ;
+    typedef C Q4 __attribute__((ext_vector_type(4)));
+    __shared__ __attribute__((aligned(16))) C cl[SCOEF ? 4 : K * CQ];
 
     int lin = blockIdx.x;
     const int total = gx * gy * gz;
@@ -102,11 +104,11 @@ __global__ void __launch_bounds__(64 * TY)
     const int y0 = RZ == 0 ? 0 : byi * SH::TYR;
     const int z0 = bzi * lz, z1 = min(z0 + lz, nzb);
 
-    // coefficients of y offset dy: cl[dy * CB + dz * KP + dx] = c[dz][dy][dx]
-    // (the dense box in z, y, x order); the pad cell of each row is zero
+    // coefficients of y offset dy: cl[dy * CQ + dz * KQ + dx] = c[dz][dy][dx]
+    // (the dense box in z, y, x order); the pad cells of each row are zero
     if constexpr (!SCOEF)
-        for (int i = tid; i < K * SH::CB; i += NT) {
-            const int dx = i % SH::KP, dz = (i / SH::KP) % KZ, dy = i / SH::CB;
+        for (int i = tid; i < K * CQ; i += NT) {
+            const int dx = i % KQ, dz = (i / KQ) % KZ, dy = i / CQ;
             cl[i] = dx < K ? cg[(dz * K + dy) * K + dx] : C(0);
         }
 
@@ -180,20 +182,22 @@ __global__ void __launch_bounds__(64 * TY)
             // the coefficients of one z tap are loaded while the previous
             // tap's multiply-adds run (a scheduling barrier per tap keeps
             // the compiler from loading all (2R+1)^2 at once)
-            const C *cb = cl + dy * SH::CB; // LDS copy: c[dz][dy][dx] at dz KP + dx
+            const C *cb = cl + dy * CQ;     // LDS copy: c[dz][dy][dx] at dz KQ + dx
             const C *cq = cg + dy * K;      // device: c[dz][dy][dx] at dz K^2 + dx
-            auto ldc = [&](int dz, C (&c)[SH::KP]) {
+            auto ldc = [&](int dz, C (&c)[KQ]) {
                 if constexpr (SCOEF) {
                     static_for<K>([&](auto dx) { c[dx] = cq[dz * K * K + dx]; });
                 } else {
-                    static_for<SH::KP / 2>([&](auto ii) {
-                        const P2 t = *reinterpret_cast<const P2 *>(cb + dz * SH::KP + 2 * ii);
-                        c[2 * ii] = t.x;
-                        c[2 * ii + 1] = t.y;
+                    static_for<KQ / 4>([&](auto ii) {
+                        const Q4 t = *reinterpret_cast<const Q4 *>(cb + dz * KQ + 4 * ii);
+                        c[4 * ii] = t.x;
+                        c[4 * ii + 1] = t.y;
+                        c[4 * ii + 2] = t.z;
+                        c[4 * ii + 3] = t.w;
                     });
                 }
             };
-            C cc[2][SH::KP];
+            C cc[2][KQ];
             ldc(2 * RZ, cc[0]);
             static_for<KZ>([&](auto kk) {
                 constexpr int k = kk;

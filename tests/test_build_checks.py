@@ -298,7 +298,7 @@ def box_lds_shape(R, E, TY):
     LW, LH = 64 + 2 * R, TY * E + 2 * R
     PW = (LW + E - 1) // E * (E + 2)
     return dict(K=K, NT=64 * TY, LX=64 // E, TYR=TY * E, LW=LW, LH=LH, PW=PW,
-                PLANE=PW * LH, NLD=(LW * LH + 64 * TY - 1) // (64 * TY), KP=K + 1)
+                PLANE=PW * LH, NLD=(LW * LH + 64 * TY - 1) // (64 * TY))
 
 
 def phys(col, E):
@@ -334,8 +334,9 @@ def test_box_lds_indexes_stay_in_their_arrays(R, E):
                 assert a % 2 == 0 and a + 1 < PLANE
                 assert a == (row0 + dy) * PW + phys(lx * E + j, E)
                 assert a + 1 == (row0 + dy) * PW + phys(lx * E + j + 1, E)
-    # coefficient pairs read up to the pad cell of each row of KP
-    assert (sh["KP"] // 2) * 2 == sh["KP"]
+    # FP32 tap rows padded to whole groups of four (one 16-byte read each)
+    KQ = (sh["K"] + 3) // 4 * 4
+    assert KQ % 4 == 0 and KQ >= sh["K"]
     # a 2-D block's 64 x 4E outputs pass through the plane buffer
     assert 64 * sh["TYR"] <= PLANE
 
