@@ -252,8 +252,9 @@ __global__ void __launch_bounds__(64 * TY)
     }
 }
 
-// Outputs per lane along x (E) and waves per workgroup (TY) that are built.
-#define BOX3D_LDS_SHAPES(X) X(4, 4) X(8, 4)
+// Outputs per lane along x (E) and waves per workgroup (TY) that are built
+// (8 waves only for the HBM-bound forms: 2-D boxes and the 27-point box).
+#define BOX3D_LDS_SHAPES(X) X(4, 4) X(8, 4) X(4, 8) X(8, 8)
 
 template <typename S, int R, int E, int TY, int RZ>
 int launch_box3d_lds_t(const S *in, S *out, const Geo &g, const typename Store<S>::C *cf, int lz,
@@ -284,7 +285,7 @@ int launch_box3d_lds_r(const S *in, S *out, const Geo &g, const typename Store<S
 // (3-D rings of 11 .. 17 sums at radius 5 .. 8 leave registers for 4 outputs
 // per lane only)
 #define BOX3D_LDS_CASE(E_, TY_)                                                              \
-    if constexpr (RZ < 5 || E_ == 4)                                                         \
+    if constexpr ((RZ < 5 || E_ == 4) && (TY_ == 4 || RZ == 0 || R == 1))                    \
         if (e == E_ && ty == TY_)                                                            \
             return launch_box3d_lds_t<S, R, E_, TY_, RZ>(in, out, g, cf, lz, flags, s);
     BOX3D_LDS_SHAPES(BOX3D_LDS_CASE)

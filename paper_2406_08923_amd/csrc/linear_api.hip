@@ -105,10 +105,11 @@ struct TuneChoice {
     int variant, p0, p1, p2, p3;
 };
 
-// Dense 2-D boxes (the LDS march over row blocks): outputs per lane. The
+// Dense 2-D boxes (the LDS march over row blocks, 8 waves per workgroup):
+// outputs per lane. The
 // march addresses the array with 32-bit offsets, so it takes arrays below
 // 4 GiB; larger ones stay on the gather kernel.
-constexpr int BOX2D_DEFAULT_E = 8;
+constexpr int BOX2D_DEFAULT_E = 4;
 
 // the dense box runs the LDS march (box3d_lds.hpp): every 2-D box and 3-D box
 // of radius 2..4; at radius 1 when the tile asks for 4 or 8 outputs per lane
@@ -391,13 +392,15 @@ std::vector<TuneChoice> candidates(const stencil_plan_s *p)
                 if (e == 4 || p->lin.reff <= 4)
                     c.push_back({STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD});
     if (p->lin.is_dense2 && box2d_fits(p))
-        for (int e : {4, 8})
-            for (int lz : {1, 4, 16})
-                c.push_back({STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD});
+        for (int ty : {4, 8})
+            for (int e : {4, 8})
+                for (int lz : {1, 4, 16})
+                    c.push_back({STENCIL_VARIANT_BOX3D, ty, e, lz, STAR_FLAG_XCD});
     if (p->lin.is_dense3 && p->lin.reff == 1)
-        for (int e : {4, 8})
-            for (int lz : {32, 64, 128})
-                c.push_back({STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD});
+        for (int ty : {4, 8})
+            for (int e : {4, 8})
+                for (int lz : {32, 64, 128})
+                    c.push_back({STENCIL_VARIANT_BOX3D, ty, e, lz, STAR_FLAG_XCD});
     if (p->lin.is_dense3 && p->lin.reff == 1)
         for (int ty : {4, 8})
             for (int ny : {1, 2})
@@ -461,26 +464,28 @@ TuneChoice default_choice(const stencil_plan_s *p)
     if (p->lin.is_star)
         return default_star1(p);
     if (p->lin.is_dense2 && box2d_fits(p))
-        // one block of rows per workgroup: with the outputs stored as whole
-        // rows, the fastest at 16384^2 up to radius 2 and within 2 % at 4
-        // (marching 16 blocks, which the search may still pick)
-        return {STENCIL_VARIANT_BOX3D, 4, BOX2D_DEFAULT_E, 1, STAR_FLAG_XCD};
+        // one block of 32 rows per workgroup of 8 waves with 4 outputs per
+        // lane: with the outputs stored as whole rows, the fastest at 16384^2
+        // at radius 2 and 4 (marching 16 blocks, which the search may still
+        // pick, was slower up to radius 2 and 2 % faster at radius 4)
+        return {STENCIL_VARIANT_BOX3D, 8, BOX2D_DEFAULT_E, 1, STAR_FLAG_XCD};
     if (p->lin.is_dense3) {
         // dense 3-D boxes run the LDS march: four outputs per lane (eight for
         // FP64 at radius 1 and FP32 at radius 4) and the deepest z chunk, up
-        // to 128 planes (64 in FP32 at radius 2 and 3), that still gives 512
-        // workgroups (two per compute unit): the fastest shapes at 512^3. At
-        // radius 1 this beat the lane-exchange march by 6-20 % in two
-        // sessions (FP64 0.516-0.540 against 0.577-0.649 ms).
+        // to 128 planes (64 in FP32 at radius 2 and 3), that still gives 2048
+        // waves (two per SIMD): the fastest shapes at 512^3. FP64 at radius
+        // 1 takes 8 waves (64 x 64 tiles): 0.468 ms against 0.537 with 4 and
+        // 0.577-0.649 on the lane-exchange march.
         const Geo &g = p->lin.g;
         const bool f64 = p->lin.dtype == STENCIL_F64;
         const int R = p->lin.reff;
         const int e = (f64 && R == 1) || (!f64 && R == 4) ? 8 : 4;
-        const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 4 * e - 1) / (4 * e));
+        const int ty = f64 && R == 1 ? 8 : 4; // 64 x 64 tiles: 13 % faster at 512^3
+        const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + ty * e - 1) / (ty * e));
         int lz = f64 || R == 1 || R == 4 ? 128 : 64;
-        while (lz > 32 && cols * ((g.nz + lz - 1) / lz) < 512)
+        while (lz > 32 && cols * ((g.nz + lz - 1) / lz) * ty < 2048) // waves
             lz /= 2;
-        return {STENCIL_VARIANT_BOX3D, 4, e, lz, STAR_FLAG_XCD};
+        return {STENCIL_VARIANT_BOX3D, ty, e, lz, STAR_FLAG_XCD};
     }
     if (p->lin.g.ndim == 1)
         return {STENCIL_VARIANT_LINE1D, 4, 0, 0, 0};
@@ -815,11 +820,14 @@ stencil_status stencil_plan(const stencil_desc *d, stencil_plan_t *out)
                 stencil_plan_destroy(p);
                 return fail(STENCIL_EINVAL, "box3d z chunk must be >= 1");
             }
+            const bool ty8 = c.p0 == 8 && (nd == 2 || L.reff == 1); // HBM-bound forms
             if ((L.reff >= 2 || nd == 2 || c.p1 >= 4) &&
-                (c.p0 != 4 || (c.p1 != 4 && c.p1 != 8) || (nd == 3 && L.reff >= 5 && c.p1 != 4))) {
+                ((c.p0 != 4 && !ty8) || (c.p1 != 4 && c.p1 != 8) ||
+                 (nd == 3 && L.reff >= 5 && c.p1 != 4))) {
                 stencil_plan_destroy(p);
-                return fail(STENCIL_EUNSUPPORTED, "the LDS box march: 4 waves per workgroup, 4 "
-                                                  "or 8 outputs per lane (4 for 3-D radius 5..8)");
+                return fail(STENCIL_EUNSUPPORTED, "the LDS box march: 4 waves per workgroup (8 "
+                                                  "for 2-D boxes and the 27-point box), 4 or 8 "
+                                                  "outputs per lane (4 for 3-D radius 5..8)");
             }
         } else if (c.variant == STENCIL_VARIANT_LINE1D) {
             if (t[0]) c.p0 = t[0];

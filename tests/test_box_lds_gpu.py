@@ -56,7 +56,8 @@ def test_dense_box_radius_2_to_4_matches_oracle(dtype, R, tile):
         assert plan.tile == (4, 8 if dtype != S.F64 and R == 4 else 4, 32, XCD)
 
 
-@pytest.mark.parametrize("tile", [(4, 4, 16, XCD), (4, 8, 5, 0), (4, 4, 128, XCD)])
+@pytest.mark.parametrize("tile", [(4, 4, 16, XCD), (4, 8, 5, 0), (4, 4, 128, XCD), (8, 8, 7, XCD),
+                                  (8, 4, 128, 0)])
 @pytest.mark.parametrize("dtype", L.DTYPES)
 def test_dense_27_point_box_on_the_lds_march_matches_oracle(dtype, tile):
     # radius 1 with 4 or 8 outputs per lane: the LDS march (outputs stored as
@@ -104,7 +105,7 @@ def test_dense_box_radius_2_to_4_user_halo_and_choice(R):
     assert S.LinearPlan(dims, R, g2).variant == S.GENERIC
     with pytest.raises(S.StencilError):
         S.LinearPlan(dims, R, g2, variant=S.BOX3D)
-    with pytest.raises(S.StencilError):  # tile outside the built shapes
+    with pytest.raises(S.StencilError):  # 8 waves: 2-D and 27-point boxes only
         S.LinearPlan(dims, R, g, variant=S.BOX3D, tile=(8, 4, 16, XCD))
     with pytest.raises(S.StencilError):
         S.LinearPlan(dims, R, g, variant=S.BOX3D, tile=(4, 2, 16, XCD))
@@ -118,7 +119,7 @@ def test_dense_box_radius_2_to_4_default_shape_at_512():
         assert S.LinearPlan((512, 512, 512), R, dense_box(R, 3), dtype=dtype).tile == want
     assert S.LinearPlan((256, 256, 256), 3, dense_box(3, 3)).tile == (4, 4, 32, XCD)
     # the 27-point box: eight outputs per lane in FP64, four in FP32
-    assert S.LinearPlan((512, 512, 512), 1, dense_box(1, 3)).tile == (4, 8, 128, XCD)
+    assert S.LinearPlan((512, 512, 512), 1, dense_box(1, 3)).tile == (8, 8, 128, XCD)
     assert S.LinearPlan((512, 512, 512), 1, dense_box(1, 3), dtype=S.F32).tile == (4, 4, 128, XCD)
 
 
@@ -162,7 +163,8 @@ def dense_box2(R, seed, r_pad=None):
     return g
 
 
-@pytest.mark.parametrize("tile", [None, (4, 4, 1, XCD), (4, 8, 1, 0), (4, 4, 3, XCD), (4, 8, 16, 0)])
+@pytest.mark.parametrize("tile", [None, (4, 4, 1, XCD), (4, 8, 1, 0), (4, 4, 3, XCD), (4, 8, 16, 0),
+                                  (8, 8, 2, XCD)])
 @pytest.mark.parametrize("R", [1, 2, 3, 4, 6, 8])
 @pytest.mark.parametrize("dtype", L.DTYPES)
 def test_dense_2d_box_matches_oracle(dtype, R, tile):
@@ -173,13 +175,13 @@ def test_dense_2d_box_matches_oracle(dtype, R, tile):
                       S.BOX3D if tile else S.VARIANT_AUTO, tile=tile)
     assert plan.variant == S.BOX3D
     if tile is None:
-        assert plan.tile == (4, 8, 1, XCD)
+        assert plan.tile == (8, 4, 1, XCD)
 
 
 @pytest.mark.parametrize("R", [1, 2, 3, 4])
 def test_dense_2d_box_tiny_edge_chained_and_wider_padding(R):
     for dims in ((R, R), (64, R), (65, 2 * R + 1), (R, 70), (200, 33)):
-        for tile in ((4, 4, 1, XCD), (4, 8, 2, 0), (4, 4, 5, XCD)):
+        for tile in ((4, 4, 1, XCD), (4, 8, 2, 0), (4, 4, 5, XCD), (8, 4, 1, XCD), (8, 8, 3, 0)):
             L.run_case(dims, R, dense_box2(R, 30 + R), S.F64, S.BOX3D, tile=tile)
     L.run_case((70, 45), R, dense_box2(R, 31 + R), S.F64, S.VARIANT_AUTO, iters=3)
     plan = L.run_case((66, 40), 6, dense_box2(R, 32 + R, r_pad=6), S.F64, S.VARIANT_AUTO)
@@ -205,7 +207,7 @@ def test_dense_2d_box_user_halo_and_choice():
     assert S.LinearPlan(dims, R, g2).variant == S.GENERIC
     assert S.LinearPlan(dims, 8, dense_box2(8, 41)).variant == S.BOX3D
     # default: one block of 32 rows per workgroup
-    assert S.LinearPlan((16384, 16384), 2, dense_box2(2, 42)).tile == (4, 8, 1, XCD)
+    assert S.LinearPlan((16384, 16384), 2, dense_box2(2, 42)).tile == (8, 4, 1, XCD)
     # 2-D arrays of 4 GiB or more stay on the gather kernel
     big = S.LinearPlan((1 << 15, 1 << 14), 2, dense_box2(2, 43))
     assert big.variant == S.GENERIC

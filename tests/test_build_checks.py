@@ -305,10 +305,10 @@ def phys(col, E):
     return col + 2 * (col // E)
 
 
-@pytest.mark.parametrize("R", [2, 3, 4])
+@pytest.mark.parametrize("R,TY", [(1, 4), (1, 8), (2, 4), (3, 4), (4, 4), (8, 4), (4, 8), (8, 8)])
 @pytest.mark.parametrize("E", [4, 8])
-def test_box_lds_indexes_stay_in_their_arrays(R, E):
-    sh = box_lds_shape(R, E, 4)
+def test_box_lds_indexes_stay_in_their_arrays(R, E, TY):
+    sh = box_lds_shape(R, E, TY)
     PLANE, PW, NT = sh["PLANE"], sh["PW"], sh["NT"]
     # staged cells: each lane's LDS index (t clamped to the last cell) is in
     # the plane, and the staged cells cover it exactly once

@@ -309,7 +309,8 @@ def test_star_beyond_4_gib_default_plan_sampled_points():
     assert np.array_equal(got[:, :, :r], got[:, :, dims[0]:dims[0] + r])
 
 
-@pytest.mark.parametrize("kind", ["dense_box", "dense_box_r2", "lane_exchange_star"])
+@pytest.mark.parametrize("kind", ["dense_box", "dense_box_lane_exchange", "dense_box_r2",
+                                  "lane_exchange_star"])
 def test_lane_exchange_kernels_beyond_4_gib_sampled_points(kind):
     # the z marches address the input plane by plane above 4 GiB (a buffer
     # resource per plane): one iteration of the dense 27-point box and of the
@@ -321,9 +322,10 @@ def test_lane_exchange_kernels_beyond_4_gib_sampled_points(kind):
         r = 2 if kind == "dense_box_r2" else 1
         k = 2 * r + 1
         g = np.random.default_rng(7).uniform(0.2, 1.0, (k, k, k)) / k ** 3
-        # radius 1 on the lane-exchange march (an explicit tile: the default
-        # is the LDS march, which radius 2 covers here)
-        plan = S.LinearPlan(dims, r, g, variant=S.BOX3D, tile=(4, 2, 8, 1) if r == 1 else None)
+        # default plans (the LDS march), and radius 1 on the lane-exchange
+        # march through an explicit tile
+        tile = (4, 2, 8, 1) if kind == "dense_box_lane_exchange" else None
+        plan = S.LinearPlan(dims, r, g, variant=S.BOX3D, tile=tile)
         assert plan.variant == S.BOX3D
     else:
         r = 3
